@@ -1,0 +1,166 @@
+"""Plain FP64 CPU oracle (test infrastructure only).
+
+Only ``tests/``, the smoke check and the benchmark's CPU-baseline leg import this package.
+The GPU library never imports it and shares no code with it.
+
+* ``apply``, ``apply_points``, ``thomas``, ``bicgstab`` wrap ``oracle.c`` (see its header for
+  the passages of the paper each follows).
+* ``dense_matrix`` / ``dense_solve`` assemble A as a dense matrix and solve it with LAPACK's
+  partial-pivot LU (the exact solution the Krylov iteration approaches; tiny grids only).
+* ``net`` holds the FP64 reference of the learned preconditioner's network.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_SRC = os.path.join(_HERE, "oracle.c")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile ``oracle.c`` into ``liboracle.so`` (gcc, -O2, no FMA contraction)."""
+    if force or not os.path.exists(LIB_PATH):
+        tmp = LIB_PATH + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
+                               "-Wall", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, LIB_PATH)
+    return LIB_PATH
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int), ("restarts", ctypes.c_int), ("status", ctypes.c_int),
+                ("half_step_exit", ctypes.c_int), ("rel_residual", ctypes.c_double),
+                ("true_rel_residual", ctypes.c_double)]
+
+
+@dataclass
+class SolveInfo:
+    iterations: int
+    restarts: int
+    status: int
+    half_step_exit: int
+    rel_residual: float
+    true_rel_residual: float
+    history: np.ndarray
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH) or os.path.getmtime(LIB_PATH) < os.path.getmtime(_SRC):
+            build()
+        lib = ctypes.CDLL(LIB_PATH)
+        dp = ctypes.POINTER(ctypes.c_double)
+        lib.orc_apply.argtypes = [ctypes.c_int] * 3 + [dp, dp, dp]
+        lib.orc_apply_points.argtypes = [ctypes.c_int] * 3 + [dp, dp, ctypes.POINTER(ctypes.c_long), ctypes.c_long, dp]
+        lib.orc_thomas.argtypes = [ctypes.c_int] * 3 + [dp, dp, dp]
+        lib.orc_dot.argtypes = [ctypes.c_long, dp, dp]
+        lib.orc_dot.restype = ctypes.c_double
+        lib.orc_bicgstab.argtypes = [ctypes.c_int] * 3 + [dp, dp, dp, ctypes.c_double, ctypes.c_int, ctypes.c_int,
+                                                          ctypes.c_int, dp, ctypes.c_int, ctypes.POINTER(_Info)]
+        lib.orc_bicgstab.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def _dp(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _check(coef: np.ndarray):
+    assert coef.dtype == np.float64 and coef.flags.c_contiguous and coef.ndim == 4 and coef.shape[0] == 7
+    return coef.shape[3], coef.shape[2], coef.shape[1]
+
+
+def _vec(v: np.ndarray, n: int) -> np.ndarray:
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    assert v.size == n
+    return v
+
+
+def apply(coef: np.ndarray, x: np.ndarray) -> np.ndarray:
+    """y = A x (plain row definition)."""
+    nlon, nlat, nlev = _check(coef)
+    x = _vec(x, nlon * nlat * nlev)
+    y = np.empty_like(x)
+    _load().orc_apply(nlon, nlat, nlev, _dp(coef), _dp(x), _dp(y))
+    return y
+
+
+def apply_points(coef: np.ndarray, x: np.ndarray, idx: np.ndarray) -> np.ndarray:
+    """(A x)[idx] computed one row at a time."""
+    nlon, nlat, nlev = _check(coef)
+    x = _vec(x, nlon * nlat * nlev)
+    idx = np.ascontiguousarray(idx, dtype=np.int64)
+    y = np.empty(idx.size)
+    _load().orc_apply_points(nlon, nlat, nlev, _dp(coef), _dp(x),
+                             idx.ctypes.data_as(ctypes.POINTER(ctypes.c_long)), idx.size, _dp(y))
+    return y
+
+
+def thomas(coef: np.ndarray, q: np.ndarray) -> np.ndarray:
+    """z = T^{-1} q, T = tridiag(-aD, C, -aU) per column."""
+    nlon, nlat, nlev = _check(coef)
+    q = _vec(q, nlon * nlat * nlev)
+    z = np.empty_like(q)
+    _load().orc_thomas(nlon, nlat, nlev, _dp(coef), _dp(q), _dp(z))
+    return z
+
+
+def dot(a: np.ndarray, b: np.ndarray) -> float:
+    a = np.ascontiguousarray(a, dtype=np.float64).ravel()
+    b = np.ascontiguousarray(b, dtype=np.float64).ravel()
+    return _load().orc_dot(a.size, _dp(a), _dp(b))
+
+
+def bicgstab(coef: np.ndarray, b: np.ndarray, x0: np.ndarray | None = None, tol: float = 1e-8,
+             maxit: int = 20000, restart_every: int = 0, precond: int = 1,
+             hist_cap: int | None = None) -> tuple[np.ndarray, SolveInfo]:
+    """Right-preconditioned BiCGStab; precond 1 = vertical tridiagonal, 0 = identity."""
+    nlon, nlat, nlev = _check(coef)
+    n = nlon * nlat * nlev
+    b = _vec(b, n)
+    x = np.zeros(n) if x0 is None else _vec(x0, n).copy()
+    cap = maxit if hist_cap is None else hist_cap
+    hist = np.full(max(cap, 1), np.nan)
+    info = _Info()
+    _load().orc_bicgstab(nlon, nlat, nlev, _dp(coef), _dp(b), _dp(x), tol, maxit, restart_every, precond,
+                         _dp(hist), cap, ctypes.byref(info))
+    h = hist[:min(info.iterations, cap)].copy()
+    return x, SolveInfo(info.iterations, info.restarts, info.status, info.half_step_exit, info.rel_residual,
+                        info.true_rel_residual, h)
+
+
+def dense_matrix(coef: np.ndarray) -> np.ndarray:
+    """Dense A assembled entry by entry from the coefficient arrays (tiny grids only).
+
+    Row c has C[c] on the diagonal and -a_d[c] in the column of neighbour d; couplings whose
+    neighbour lies across a pole, the bottom or the top are left out (they must be zero).
+    """
+    nlon, nlat, nlev = _check(coef)
+    n = nlon * nlat * nlev
+    assert n <= 4000, "dense assembly is for tiny grids"
+    A = np.zeros((n, n))
+    for k in range(nlev):
+        for j in range(nlat):
+            for i in range(nlon):
+                c = i + nlon * (j + nlat * k)
+                A[c, c] += coef[6, k, j, i]
+                nbrs = [(0, (i - 1) % nlon, j, k), (1, (i + 1) % nlon, j, k), (2, i, j - 1, k), (3, i, j + 1, k),
+                        (4, i, j, k - 1), (5, i, j, k + 1)]
+                for d, ii, jj, kk in nbrs:
+                    if 0 <= jj < nlat and 0 <= kk < nlev:
+                        A[c, ii + nlon * (jj + nlat * kk)] -= coef[d, k, j, i]
+    return A
+
+
+def dense_solve(coef: np.ndarray, b: np.ndarray) -> np.ndarray:
+    """Exact solution of A x = b by LAPACK partial-pivot LU (numpy.linalg.solve)."""
+    return np.linalg.solve(dense_matrix(coef), np.asarray(b, dtype=np.float64).ravel())
