@@ -1,0 +1,182 @@
+/*
+ * endgame.h — C ABI of the MI355X (gfx950) library that solves the Helmholtz
+ * pressure-correction system  A x = b  of the ENDGame dynamical core.
+ *
+ * Paper: C. M. Maynard and D. N. Walters, "Precision of the ENDGame: Mixed-precision
+ * arithmetic in the iterative solver of the Unified Model" (arXiv:1811.03852).
+ *
+ *   Sec. 1, Eq. 1        the linear system A x = b (x: pressure correction, b: forcing).
+ *   Sec. 2, Eq. 4        A is the Schur-complement Helmholtz matrix: 7-band, non-symmetric,
+ *                        variable coefficient, recomputed every time step.
+ *   Sec. 2, Eq. 5        right ("post-") preconditioned BiCGStab on the diagonally scaled
+ *                        system; the scaling is applied outside the solver (by the caller).
+ *   Sec. 2, Eq. 6-7      T, the vertical tridiagonal part of A, inverted per column with no
+ *                        vertical decomposition.
+ *   Sec. 3, Eq. 8-9      halting on R = ||b - A x_i|| / ||b|| < R_c.
+ *   Sec. 3, Eq. 10       32-bit arithmetic is adequate while R_c >> eps_32.
+ *   Sec. 4               64-bit global sums, breakdown of near-zero scalar weights, and a
+ *                        mandatory restart after a fixed number of iterations.
+ *
+ * General conventions
+ *   - Every array argument is a DEVICE pointer (for example torch.Tensor.data_ptr() of a
+ *     CUDA/HIP tensor) unless the comment says "host".  The caller owns every array it
+ *     passes; the library never frees caller memory and keeps no pointer to it after a call
+ *     returns.  The library owns the operator object and all its internal buffers.
+ *   - Grid layout of every field: idx = i + nlon * (j + nlat * k), i = longitude (fastest,
+ *     periodic), j = latitude (south to north), k = level (bottom to top).  n = nlon*nlat*nlev.
+ *   - All device work is ordered on the operator's stream (eg_set_stream; default: the null
+ *     stream).  Every call has completed on the device when it returns.
+ *   - Return values: >= 0 is a numerical outcome (enum eg_status), < 0 an error.  On error
+ *     eg_last_error() returns a message (thread-local).  No C++ exception crosses the ABI.
+ *   - An operator object must not be used from two threads at once.
+ */
+#ifndef ENDGAME_H
+#define ENDGAME_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct eg_operator eg_operator;
+
+/* Solver modes (argument `mode` of eg_solve). */
+enum eg_mode {
+    EG_FP64 = 0,            /* BiCGStab in FP64, T^{-1} preconditioner (Sec. 2)                  */
+    EG_FP32_IR = 1,         /* FP64 iterative refinement around an FP32 inner BiCGStab; FP64     */
+                            /* true residual, solution update and dot-product accumulation       */
+                            /* (Sec. 3-4: x kept in 64-bit, the rest 32-bit, 64-bit global sums) */
+    EG_FP32_IR_BF16 = 2,    /* as EG_FP32_IR, inner off-diagonal couplings stored as BF16        */
+    EG_FP32_IR_FP16 = 3,    /* as EG_FP32_IR, inner off-diagonal couplings stored as FP16        */
+    EG_LEARNED_FP64 = 4,    /* flexible BiCGStab in FP64 with the learned preconditioner         */
+    EG_LEARNED_FP32_IR = 5  /* FP64 refinement around flexible FP32 BiCGStab + learned precond.  */
+};
+
+/* Outcomes (>= 0) and errors (< 0). */
+enum eg_status {
+    EG_CONVERGED = 0,   /* true relative residual <= tol                                       */
+    EG_MAXIT = 1,       /* iteration limit reached; x holds the last iterate                  */
+    EG_BREAKDOWN = 2,   /* repeated breakdown without progress                                 */
+    EG_STALLED = 3,     /* true residual could not be driven below tol (precision floor)       */
+    EG_EINVAL = -1,     /* invalid argument or invalid operator                                */
+    EG_ENOMEM = -2,     /* device allocation failed                                            */
+    EG_EHIP = -3,       /* HIP runtime error                                                   */
+    EG_ENONFINITE = -4, /* NaN or Inf in the right-hand side or the initial guess              */
+    EG_ENOPC = -5       /* learned mode requested but no trained or loaded network exists      */
+};
+
+/* Precision selector of the building-block calls (eg_apply, eg_apply_precond). */
+enum eg_prec {
+    EG_PREC_FP64 = 0,   /* double vectors, FP64 couplings                                      */
+    EG_PREC_FP32 = 1,   /* float vectors, FP32 couplings                                       */
+    EG_PREC_BF16 = 2,   /* float vectors, BF16 off-diagonal couplings                          */
+    EG_PREC_FP16 = 3    /* float vectors, FP16 off-diagonal couplings                          */
+};
+
+typedef struct {
+    int iterations;            /* Krylov iterations (summed over refinement steps)            */
+    int outer_steps;           /* FP64 refinement steps (0 in EG_FP64 / EG_LEARNED_FP64)       */
+    int restarts;              /* breakdown, periodic and residual-gap restarts               */
+    int fallbacks;             /* learned modes: switches to the T^{-1} preconditioner         */
+    double true_rel_residual;  /* ||b - A x|| / ||b|| of the returned x, evaluated in FP64     */
+    double seconds;            /* wall time of the solve                                       */
+} eg_info;
+
+/*
+ * Build an operator from its seven coefficient arrays (Sec. 2, Eq. 4: A is the 7-band
+ * Helmholtz matrix; the library solves the matrix it is given, scaling included).
+ *   coeffs  device, double[7][nlev][nlat][nlon]; planes in the order W, E, S, N, D, U, C.
+ *           W/E couple point (i,j,k) to (i-1,j,k) / (i+1,j,k) (periodic in i), S/N to
+ *           (i,j-1,k) / (i,j+1,k), D/U to (i,j,k-1) / (i,j,k+1).  The six couplings are
+ *           magnitudes >= 0: the matrix entries are their negatives.  C is the diagonal.
+ *   Requirements (else EG_EINVAL, with the count of offending points in the message):
+ *           nlon >= 3, nlat >= 1, nlev >= 1; all values finite; couplings >= 0;
+ *           S = 0 on j = 0, N = 0 on j = nlat-1, D = 0 on k = 0, U = 0 on k = nlev-1;
+ *           margin m = C - (W+E+S+N+D+U) > 0 at every point (row diagonal dominance).
+ *   The library copies what it needs (the caller may free coeffs after return).  It keeps
+ *   FP64 couplings, the margin m and the tridiagonal's excess g = m + W + E + S + N; FP32
+ *   and 16-bit copies are built on first use of a mode that needs them.
+ *   *out receives the new operator (NULL on error).
+ */
+int eg_create_operator(const double *coeffs, int nlon, int nlat, int nlev, eg_operator **out);
+
+/*
+ * Solve A x = b to a true relative residual ||b - A x|| / ||b|| <= tol (Sec. 3, Eq. 8-9).
+ *   b       device, double[n], read only.
+ *   x       device, double[n]: initial guess in, solution out (untouched on error < 0).
+ *   tol     > 0.
+ *   maxit   > 0: limit on Krylov iterations (summed over refinement steps).
+ *   mode    enum eg_mode.
+ * Returns an eg_status; details of the solve via eg_get_info / eg_residual_history.
+ * b = 0 gives x = 0 and EG_CONVERGED.  NaN/Inf in b or x gives EG_ENONFINITE.
+ */
+int eg_solve(eg_operator *op, const double *b, double *x, double tol, int maxit, int mode);
+
+/* Statistics of the last eg_solve (host struct). */
+int eg_get_info(const eg_operator *op, eg_info *info);
+
+/*
+ * Residual history of the last eg_solve: host double buffer of capacity cap receives the
+ * recursive relative residual after each Krylov iteration (concatenated over refinement
+ * steps).  Returns the number of entries available (may exceed cap; only cap are written).
+ */
+int eg_residual_history(const eg_operator *op, double *host_buf, int cap);
+
+/* Order all later work of this operator on `hip_stream` (a hipStream_t; NULL = null stream). */
+int eg_set_stream(eg_operator *op, void *hip_stream);
+
+/*
+ * Solver options (defaults in brackets):
+ *   "eta"            inner relative tolerance of the FP32 refinement solves [1e-4]
+ *                    (Sec. 3, Eq. 10: keep the 32-bit target well above eps_32)
+ *   "restart_every"  mandatory restart period in iterations, 0 = off [0]
+ *                    (Sec. 4 uses 150 operationally)
+ *   "max_outer"      limit on refinement steps [30]
+ *   "poll"           iterations enqueued between host checks of the device flags [8]
+ *   "graph"          1 = replay batches of iterations as HIP graphs, 0 = plain launches [1]
+ *   "stall_window"   learned modes: iterations without a 2x gain that trigger fallback [20]
+ * Returns EG_EINVAL for an unknown key or out-of-range value.
+ */
+int eg_set_option(eg_operator *op, const char *key, double value);
+
+/* ---- building blocks (device pointers; used by the solver and exposed for tests) ---- */
+
+/*
+ * y = A x (Sec. 2, Eq. 4; 7-point stencil).  x, y: device arrays of n elements, double for
+ * EG_PREC_FP64 and float otherwise; x and y must not overlap.  Computed in the difference
+ * form y = m x + sum_d a_d (x - x_d), which equals the row definition C x - sum_d a_d x_d.
+ */
+int eg_apply(eg_operator *op, const void *x, void *y, int prec);
+
+/*
+ * z = T^{-1} q with T = tridiag(-D, C, -U) per column (Sec. 2, Eq. 6-7: the vertical
+ * tridiagonal that replaces the diagonal; factorised per horizontal point).  q, z: device
+ * arrays of n elements (double for EG_PREC_FP64, float otherwise); may not overlap.
+ */
+int eg_apply_precond(eg_operator *op, const void *q, void *z, int prec);
+
+/*
+ * r = b - A x in FP64 and *rel_host = ||r|| / ||b|| (host double; Sec. 3, Eq. 8-9).
+ * b, x, r: device double[n]; r may be NULL (only the norm is returned).
+ */
+int eg_residual(eg_operator *op, const double *b, const double *x, double *r, double *rel_host);
+
+/*
+ * *out_host = sum_i a_i b_i with every product and the sum in FP64 (Sec. 4: 64-bit global
+ * sums).  a, b: device arrays of n elements, double (prec = EG_PREC_FP64) or float (other).
+ * Fixed-order two-pass reduction: bitwise reproducible for a given n.
+ */
+int eg_dot(eg_operator *op, const void *a, const void *b, long n, int prec, double *out_host);
+
+/* Grid sizes of an operator (host ints; any pointer may be NULL). */
+int eg_get_shape(const eg_operator *op, int *nlon, int *nlat, int *nlev);
+
+/* Release the operator and all its device memory.  NULL is accepted. */
+void eg_destroy_operator(eg_operator *op);
+
+/* Message describing the last error of the calling thread ("" if none). */
+const char *eg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ENDGAME_H */

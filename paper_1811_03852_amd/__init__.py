@@ -1,0 +1,202 @@
+"""MI355X (gfx950) solver for the ENDGame Helmholtz pressure-correction system  A x = b.
+
+Thin ctypes binding over ``libendgame.so`` (the C ABI declared in ``include/endgame.h``).  It
+only marshals arguments: every step of the solve runs in the library's HIP kernels.  PyTorch
+supplies device memory and the stream (``torch.cuda.current_stream()``).  There is no CPU
+fallback: if the library is missing or no GPU is present, calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libendgame.so")
+
+# enum eg_mode
+FP64, FP32_IR, FP32_IR_BF16, FP32_IR_FP16, LEARNED_FP64, LEARNED_FP32_IR = range(6)
+MODE_NAMES = {FP64: "fp64", FP32_IR: "fp32_ir", FP32_IR_BF16: "fp32_ir_bf16", FP32_IR_FP16: "fp32_ir_fp16",
+              LEARNED_FP64: "learned_fp64", LEARNED_FP32_IR: "learned_fp32_ir"}
+# enum eg_prec
+PREC_FP64, PREC_FP32, PREC_BF16, PREC_FP16 = range(4)
+# enum eg_status
+CONVERGED, MAXIT, BREAKDOWN, STALLED = 0, 1, 2, 3
+EINVAL, ENOMEM, EHIP, ENONFINITE, ENOPC = -1, -2, -3, -4, -5
+
+EXPORTED = ["eg_create_operator", "eg_solve", "eg_get_info", "eg_residual_history", "eg_set_stream", "eg_set_option",
+            "eg_apply", "eg_apply_precond", "eg_residual", "eg_dot", "eg_get_shape", "eg_destroy_operator",
+            "eg_last_error"]
+
+
+class EndgameError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"endgame error {code}: {msg}")
+        self.code = code
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int), ("outer_steps", ctypes.c_int), ("restarts", ctypes.c_int),
+                ("fallbacks", ctypes.c_int), ("true_rel_residual", ctypes.c_double), ("seconds", ctypes.c_double)]
+
+
+@dataclass
+class SolveInfo:
+    status: int
+    iterations: int
+    outer_steps: int
+    restarts: int
+    fallbacks: int
+    true_rel_residual: float
+    seconds: float
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load ``libendgame.so`` (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_1811_03852_amd.build`")
+    lib = ctypes.CDLL(path)
+    vp, dp, ip = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)
+    sig = {
+        "eg_create_operator": ([vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(vp)], ctypes.c_int),
+        "eg_solve": ([vp, vp, vp, ctypes.c_double, ctypes.c_int, ctypes.c_int], ctypes.c_int),
+        "eg_get_info": ([vp, ctypes.POINTER(_Info)], ctypes.c_int),
+        "eg_residual_history": ([vp, dp, ctypes.c_int], ctypes.c_int),
+        "eg_set_stream": ([vp, vp], ctypes.c_int),
+        "eg_set_option": ([vp, ctypes.c_char_p, ctypes.c_double], ctypes.c_int),
+        "eg_apply": ([vp, vp, vp, ctypes.c_int], ctypes.c_int),
+        "eg_apply_precond": ([vp, vp, vp, ctypes.c_int], ctypes.c_int),
+        "eg_residual": ([vp, vp, vp, vp, dp], ctypes.c_int),
+        "eg_dot": ([vp, vp, vp, ctypes.c_long, ctypes.c_int, dp], ctypes.c_int),
+        "eg_get_shape": ([vp, ip, ip, ip], ctypes.c_int),
+        "eg_destroy_operator": ([vp], None),
+        "eg_last_error": ([], ctypes.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = lib
+    return lib
+
+
+def _check(rc: int) -> int:
+    if rc < 0:
+        raise EndgameError(rc, _lib.eg_last_error().decode())
+    return rc
+
+
+def _ptr(t) -> int:
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("expected a CUDA/HIP torch.Tensor")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return t.data_ptr()
+
+
+def _vec_dtype(prec: int):
+    import torch
+    return torch.float64 if prec == PREC_FP64 else torch.float32
+
+
+class Operator:
+    """A 7-point Helmholtz operator resident on the GPU.
+
+    ``coeffs``: CUDA float64 tensor of shape (7, nlev, nlat, nlon), planes W, E, S, N, D, U, C
+    (couplings as magnitudes; the matrix entries are their negatives; C is the diagonal).
+    """
+
+    def __init__(self, coeffs):
+        import torch
+        lib = load_library()
+        if coeffs.dtype != torch.float64 or coeffs.dim() != 4 or coeffs.shape[0] != 7:
+            raise ValueError("coeffs must be float64 of shape (7, nlev, nlat, nlon)")
+        _, nlev, nlat, nlon = (int(s) for s in coeffs.shape)
+        self.nlon, self.nlat, self.nlev = nlon, nlat, nlev
+        self.n = nlon * nlat * nlev
+        self.device = coeffs.device
+        h = ctypes.c_void_p()
+        self._sync_stream_ptr = None
+        _check(lib.eg_create_operator(_ptr(coeffs), nlon, nlat, nlev, ctypes.byref(h)))
+        self._h = h
+        self._bind_stream()
+
+    def _bind_stream(self):
+        import torch
+        s = torch.cuda.current_stream(self.device).cuda_stream
+        if s != self._sync_stream_ptr:
+            _check(_lib.eg_set_stream(self._h, ctypes.c_void_p(s)))
+            self._sync_stream_ptr = s
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.eg_destroy_operator(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def set_option(self, key: str, value: float):
+        _check(_lib.eg_set_option(self._h, key.encode(), float(value)))
+
+    def solve(self, b, x, tol: float = 1e-8, maxit: int = 20000, mode: int = FP64) -> SolveInfo:
+        """Solve in place: ``x`` holds the initial guess and receives the solution."""
+        self._bind_stream()
+        status = _check(_lib.eg_solve(self._h, _ptr(b), _ptr(x), float(tol), int(maxit), int(mode)))
+        info = _Info()
+        _check(_lib.eg_get_info(self._h, ctypes.byref(info)))
+        return SolveInfo(status, info.iterations, info.outer_steps, info.restarts, info.fallbacks,
+                         info.true_rel_residual, info.seconds)
+
+    def history(self):
+        import numpy as np
+        cnt = _check(_lib.eg_residual_history(self._h, None, 0))
+        buf = np.zeros(max(cnt, 1))
+        _lib.eg_residual_history(self._h, buf.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), cnt)
+        return buf[:cnt]
+
+    def apply(self, x, y=None, prec: int = PREC_FP64):
+        import torch
+        self._bind_stream()
+        if y is None:
+            y = torch.empty_like(x)
+        _check(_lib.eg_apply(self._h, _ptr(x), _ptr(y), int(prec)))
+        return y
+
+    def precond(self, q, z=None, prec: int = PREC_FP64):
+        import torch
+        self._bind_stream()
+        if z is None:
+            z = torch.empty_like(q)
+        _check(_lib.eg_apply_precond(self._h, _ptr(q), _ptr(z), int(prec)))
+        return z
+
+    def residual(self, b, x, r=None) -> float:
+        self._bind_stream()
+        rel = ctypes.c_double()
+        _check(_lib.eg_residual(self._h, _ptr(b), _ptr(x), None if r is None else _ptr(r), ctypes.byref(rel)))
+        return rel.value
+
+    def dot(self, a, b) -> float:
+        import torch
+        self._bind_stream()
+        prec = PREC_FP64 if a.dtype == torch.float64 else PREC_FP32
+        out = ctypes.c_double()
+        _check(_lib.eg_dot(self._h, _ptr(a), _ptr(b), a.numel(), prec, ctypes.byref(out)))
+        return out.value

@@ -1,0 +1,122 @@
+// Internal declarations of the endgame library (not part of the public ABI).
+//
+// Storage of an operator on the device (one set per precision, struct-of-arrays, each array
+// laid out like the grid, idx = i + nlon*(j + nlat*k)):
+//   a[6][n]  couplings W, E, S, N, D, U (magnitudes; matrix entries are their negatives)
+//   m[n]     margin  C - sum(a)  (> 0): the SpMV runs in the difference form
+//            y = m x + sum_d a_d (x - x_d), which never forms C x - sum a_d x_d and so keeps
+//            the small margin exact in FP32 and 16-bit storage
+//   g[n]     tridiagonal excess  m + W + E + S + N  (= C - D - U): the Thomas sweep runs in a
+//            form whose every intermediate is a sum of non-negative terms
+// 16-bit sets store a[] as BF16/FP16 bits scaled by a power of two per (direction, level,
+// latitude row) and keep m and g in FP32.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace eg {
+
+constexpr int kWG = 256;                 // threads per workgroup of the streaming kernels
+constexpr int kPartialCols = 4;          // doubles per partial row
+
+enum Prec { P64 = 0, P32 = 1, PBF16 = 2, PFP16 = 3 };
+
+// Device-resident state of one Krylov run.  Written only by the single-workgroup finalize
+// kernels (one thread), read by the streaming kernels at their start.
+struct alignas(64) Scalars {
+    double rho, rho_prev, alpha, omega, beta;
+    double rr;          // ||r||^2
+    double rhat2;       // ||rhat||^2
+    double nb2;         // ||b||^2 of the system this run solves
+    double thr2;        // tol^2 * ||b||^2
+    double ss;          // ||s||^2 of the current iteration
+    double last_rel;    // last recursive relative residual
+    double eps_bd;      // breakdown threshold (relative cosine)
+    double pn2;         // ||q||^2 of the vector fed to the learned preconditioner
+    double aux0;        // tolerance of this run (read by FIN_INIT)
+    double aux1;
+    int iter;           // iterations completed in this run
+    int maxit;
+    int done;           // 1: nothing more to do (status says why)
+    int status;         // 0 converged, 1 iteration limit, 2 breakdown, 4 periodic restart due
+    int fresh;          // 1: the next iteration restarts (rhat = r, p = r)
+    int was_fresh;      // the current iteration started fresh
+    int skip;           // sigma breakdown: rest of the current iteration is skipped
+    int half;           // converged at the half step of the current iteration
+    int wbd;            // omega breakdown in the current iteration
+    int restarts;
+    int restart_every;
+    int hist_base;      // first history slot of this run
+    int hist_cap;
+    int pad[3];
+};
+
+// Views of one precision set of the operator.
+template <typename Tc> struct CoefTraits;
+template <> struct CoefTraits<double> { using val = double; static constexpr bool quant = false; };
+template <> struct CoefTraits<float> { using val = float; static constexpr bool quant = false; };
+struct bf16_t { uint16_t bits; };
+struct fp16_t { uint16_t bits; };
+template <> struct CoefTraits<bf16_t> { using val = float; static constexpr bool quant = true; };
+template <> struct CoefTraits<fp16_t> { using val = float; static constexpr bool quant = true; };
+
+template <typename Tc> struct OpView {
+    using V = typename CoefTraits<Tc>::val;
+    const Tc *a;        // [6][n]
+    const V *m;         // [n]
+    const V *g;         // [n]
+    const float *qs;    // [6][nlev][nlat] power-of-two scales (16-bit sets only)
+    int nlon, nlat, nlev;
+    long P, n;
+};
+
+// flags a streaming kernel may be told to stop on
+constexpr int STOP_DONE = 1, STOP_SKIP = 2, STOP_HALF = 4;
+
+// ---- launchers (kernels.hip) ----
+// rows of the partial-sum buffer the kernels of a grid of this shape may write
+int partial_rows_needed(int nlon, int nlat, int nlev);
+// SpMV variants.  w is the dot partner; partials receive one row per workgroup.
+enum SpmvMode { SP_PLAIN = 0, SP_DOT2 = 1 };
+template <typename Tv, typename Tc>
+void launch_spmv(const OpView<Tc> &op, const Tv *x, Tv *y, const Tv *w, int mode, double *partials,
+                 int *nrows, const Scalars *sc, int stop_mask, hipStream_t s);
+// r = b - A x in FP64 with the result written as Tout; partials: ||r64||^2, ||b||^2, ||rout||^2
+template <typename Tout>
+void launch_residual(const OpView<double> &op, const double *b, const double *x, Tout *r, double *partials,
+                     int *nrows, hipStream_t s);
+
+enum ThomasMode { TH_PLAIN = 0, TH_P = 1, TH_S = 2 };
+template <typename Tv, typename Tc>
+void launch_thomas(const OpView<Tc> &op, const Tv *q, Tv *z, int mode, Tv *r, Tv *p, const Tv *v, Tv *rhat,
+                   Tv *scratch, double *partials, int *nrows, const Scalars *sc, hipStream_t s);
+
+template <typename Tv>
+void launch_update(long n, Tv *x, const Tv *ph, const Tv *sh, const Tv *s, const Tv *t, Tv *r, const Tv *rhat,
+                   double *partials, int *nrows, const Scalars *sc, hipStream_t stream);
+
+template <typename Ta, typename Tb>
+void launch_dot(long n, const Ta *a, const Tb *b, double *partials, int *nrows, hipStream_t s);
+
+// finalize kernels (one workgroup): reduce partials, update the scalar block
+enum FinStage { FIN_INIT = 0, FIN_END = 1, FIN_SIGMA = 2, FIN_S = 3, FIN_OMEGA = 4, FIN_SUM = 5, FIN_TRUE = 6 };
+// c_rr / c_nb: partial columns holding ||r||^2 and ||b||^2 (FIN_INIT, FIN_TRUE)
+void launch_finalize(int stage, const double *partials, int nrows, Scalars *sc, double *hist, double *out,
+                     int c_rr, int c_nb, hipStream_t s);
+
+template <typename T> void launch_fill(T *p, long n, T v, hipStream_t s);
+void launch_add_correction(long n, double *x, const float *d, hipStream_t s);
+void launch_copy_f64_to_f32(long n, const double *src, float *dst, hipStream_t s);
+
+// operator setup
+void launch_derive(const double *coeffs, int nlon, int nlat, int nlev, double *a64, double *m64, double *g64,
+                   int *bad, hipStream_t s);
+void launch_to_fp32(long n, const double *a64, const double *m64, const double *g64, float *a32, float *m32,
+                    float *g32, hipStream_t s);
+void launch_quantize(int kind, int nlon, int nlat, int nlev, const double *a64, const double *m64, uint16_t *aq,
+                     float *qs, float *gq, hipStream_t s);
+void launch_check_finite(long n, const double *v, int *bad, hipStream_t s);
+
+}  // namespace eg

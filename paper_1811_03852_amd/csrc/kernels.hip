@@ -1,0 +1,952 @@
+// HIP kernels (gfx950) of the BiCGStab hot path.
+//
+//   k_spmv      y = A x for the 7-point operator (Sec. 2, Eq. 4), fused with the FP64 partial
+//               sums of the two dot products the iteration needs next.  Memory-bound.
+//   k_thomas    z = T^{-1} q, T the vertical tridiagonal of A (Sec. 2, Eq. 6-7), one lane per
+//               column, levels walked in registers, fused with the vector update that forms q.
+//   k_update    x += alpha phat + omega shat; r = s - omega t; <rhat, r>, <r, r> partials.
+//   k_finalize  fixed-order FP64 sum of the per-workgroup partials (Sec. 4: 64-bit global
+//               sums) and the scalar recurrences of BiCGStab, in one workgroup.
+//
+// Every floating-point sum that leaves a workgroup is FP64 and is reduced in a fixed order, so
+// results are bitwise reproducible for a given grid.
+#include <algorithm>
+#include <cmath>
+
+#include "eg_internal.h"
+
+namespace eg {
+
+// ------------------------------------------------------------------------------------------
+// helpers
+// ------------------------------------------------------------------------------------------
+__device__ __forceinline__ float bf16_to_f(uint16_t b) { return __uint_as_float(static_cast<uint32_t>(b) << 16); }
+__device__ __forceinline__ float fp16_to_f(uint16_t b) { return static_cast<float>(__builtin_bit_cast(_Float16, b)); }
+
+template <typename Tc> struct Dec;
+template <> struct Dec<double> {
+    __device__ static __forceinline__ double get(const double *a, long i, float) { return a[i]; }
+};
+template <> struct Dec<float> {
+    __device__ static __forceinline__ float get(const float *a, long i, float) { return a[i]; }
+};
+template <> struct Dec<bf16_t> {
+    __device__ static __forceinline__ float get(const bf16_t *a, long i, float s) { return bf16_to_f(a[i].bits) * s; }
+};
+template <> struct Dec<fp16_t> {
+    __device__ static __forceinline__ float get(const fp16_t *a, long i, float s) { return fp16_to_f(a[i].bits) * s; }
+};
+
+__device__ __forceinline__ bool stopped(const Scalars *sc, int mask)
+{
+    if (!sc || !mask) return false;
+    int f = 0;
+    if (sc->done) f |= STOP_DONE;
+    if (sc->skip) f |= STOP_SKIP;
+    if (sc->half) f |= STOP_HALF;
+    return (f & mask) != 0;
+}
+
+// Sum NV doubles over the 256-thread workgroup in a fixed order; thread 0 writes `row`.
+template <int NV>
+__device__ __forceinline__ void block_sum_store(double (&v)[NV], double *row)
+{
+    __shared__ double sm[kWG / 64][NV];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+        for (int c = 0; c < NV; ++c) v[c] += __shfl_xor(v[c], off);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0)
+#pragma unroll
+        for (int c = 0; c < NV; ++c) sm[wv][c] = v[c];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int c = 0; c < NV; ++c) {
+            double s = sm[0][c];
+#pragma unroll
+            for (int w = 1; w < kWG / 64; ++w) s += sm[w][c];
+            row[c] = s;
+        }
+#pragma unroll
+        for (int c = NV; c < kPartialCols; ++c) row[c] = 0.0;
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// k_spmv: 7-point stencil, difference form  y = m x + sum_d a_d (x - x_d)
+//
+// Workgroup = 4 waves; wave w of tile (bx, by) owns longitudes bx*64 + lane and the R
+// consecutive latitude rows starting at (by*4 + w)*R, and walks levels k0..k1-1 of that
+// strip.  x is read once per point: the vertical neighbours come from a rolling register
+// window (x_{k-1}, x_k, x_{k+1}), the N/S neighbours from the same lane's other rows (two
+// halo rows per level are loaded), the E/W neighbours by cross-lane shuffles (edge lanes
+// load theirs, with the periodic wrap in longitude).
+//
+// Tiles are assigned XCD-aware: workgroups are dispatched round-robin over the 8 XCDs, so
+// workgroup b processes tile (b % 8) * per_xcd + b / 8 and each XCD walks one contiguous
+// range of tiles (lon-fastest order), keeping latitude-adjacent tiles in one L2.
+// ------------------------------------------------------------------------------------------
+enum { SPM_PLAIN = 0, SPM_DOT2 = 1, SPM_RESID = 2 };
+
+template <typename Tv, typename Tc, int R, int MODE, typename Tout>
+__global__ __launch_bounds__(kWG) void k_spmv(OpView<Tc> op, const Tv *__restrict__ x, Tout *__restrict__ y,
+                                              const Tv *__restrict__ w, double *__restrict__ partials,
+                                              const Scalars *__restrict__ sc, int stop_mask, int gx, int gy,
+                                              int kchunk, int ntiles, int per_xcd)
+{
+    if (stopped(sc, stop_mask)) return;
+    using V = typename CoefTraits<Tc>::val;
+    constexpr bool Q = CoefTraits<Tc>::quant;
+    constexpr int ND = (MODE == SPM_PLAIN) ? 0 : (MODE == SPM_DOT2 ? 2 : 3);
+
+    const int b = blockIdx.x;
+    const int t = (b & 7) * per_xcd + (b >> 3);
+    double acc[ND > 0 ? ND : 1];
+#pragma unroll
+    for (int c = 0; c < (ND > 0 ? ND : 1); ++c) acc[c] = 0.0;
+
+    if (t < ntiles) {
+        const int nlon = op.nlon, nlat = op.nlat, nlev = op.nlev;
+        const long P = op.P, n = op.n;
+        const int bx = t % gx;
+        const int rest = t / gx;
+        const int by = rest % gy;
+        const int bz = rest / gy;
+        const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+        const int i = bx * 64 + lane;
+        const bool iv = i < nlon;
+        const int ic = iv ? i : nlon - 1;
+        const int iw = (ic == 0) ? nlon - 1 : ic - 1;
+        const int ie = (ic == nlon - 1) ? 0 : ic + 1;
+        const bool needw = (lane == 0);
+        const bool neede = (lane == 63) || (ic == nlon - 1);
+        const int j0 = (by * 4 + wv) * R;
+        int jc[R];
+        bool jv[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            jv[r] = (j0 + r) < nlat;
+            jc[r] = jv[r] ? j0 + r : nlat - 1;
+        }
+        const int jsh = (j0 == 0) ? 0 : ((j0 - 1 < nlat) ? j0 - 1 : nlat - 1);   // south halo row
+        const int k0 = bz * kchunk;
+        const int k1 = (k0 + kchunk < nlev) ? k0 + kchunk : nlev;
+
+        Tv xp[R], xc[R], xn[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const long c = (long)k0 * P + (long)jc[r] * nlon + ic;
+            xc[r] = x[c];
+            xp[r] = (k0 > 0) ? x[c - P] : xc[r];
+        }
+        for (int k = k0; k < k1; ++k) {
+            const long base = (long)k * P;
+            const bool up = (k + 1) < nlev;
+#pragma unroll
+            for (int r = 0; r < R; ++r) xn[r] = up ? x[base + P + (long)jc[r] * nlon + ic] : xc[r];
+            const Tv hs = (j0 > 0) ? x[base + (long)jsh * nlon + ic] : xc[0];
+            const Tv hn = (j0 + R < nlat) ? x[base + (long)(j0 + R) * nlon + ic] : xc[R - 1];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const long rowb = base + (long)jc[r] * nlon;
+                const long c = rowb + ic;
+                const Tv xr = xc[r];
+                Tv xw = __shfl_up(xr, 1);
+                Tv xe = __shfl_down(xr, 1);
+                if (needw) xw = x[rowb + iw];
+                if (neede) xe = x[rowb + ie];
+                const Tv xs = (r == 0) ? hs : xc[r - 1];
+                const Tv xnn = (r == R - 1) ? hn : xc[r + 1];
+                float s0 = 1.f, s1 = 1.f, s2 = 1.f, s3 = 1.f, s4 = 1.f, s5 = 1.f;
+                if constexpr (Q) {
+                    const long qb = (long)k * nlat + jc[r];
+                    const long qd = (long)nlev * nlat;
+                    s0 = op.qs[qb];
+                    s1 = op.qs[qb + qd];
+                    s2 = op.qs[qb + 2 * qd];
+                    s3 = op.qs[qb + 3 * qd];
+                    s4 = op.qs[qb + 4 * qd];
+                    s5 = op.qs[qb + 5 * qd];
+                }
+                const V aW = Dec<Tc>::get(op.a, c, s0);
+                const V aE = Dec<Tc>::get(op.a, c + n, s1);
+                const V aS = Dec<Tc>::get(op.a, c + 2 * n, s2);
+                const V aN = Dec<Tc>::get(op.a, c + 3 * n, s3);
+                const V aD = Dec<Tc>::get(op.a, c + 4 * n, s4);
+                const V aU = Dec<Tc>::get(op.a, c + 5 * n, s5);
+                const V mm = op.m[c];
+                Tv yv = mm * xr;
+                yv += aW * (xr - xw);
+                yv += aE * (xr - xe);
+                yv += aS * (xr - xs);
+                yv += aN * (xr - xnn);
+                yv += aD * (xr - xp[r]);
+                yv += aU * (xr - xn[r]);
+                if (iv && jv[r]) {
+                    if constexpr (MODE == SPM_RESID) {
+                        const double bb = static_cast<double>(w[c]);
+                        const double rv = bb - static_cast<double>(yv);
+                        const Tout ro = static_cast<Tout>(rv);
+                        if (y) y[c] = ro;
+                        acc[0] += rv * rv;
+                        acc[1] += bb * bb;
+                        acc[2] += static_cast<double>(ro) * static_cast<double>(ro);
+                    } else {
+                        y[c] = static_cast<Tout>(yv);
+                        if constexpr (MODE == SPM_DOT2) {
+                            acc[0] += static_cast<double>(w[c]) * static_cast<double>(yv);
+                            acc[1] += static_cast<double>(yv) * static_cast<double>(yv);
+                        }
+                    }
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                xp[r] = xc[r];
+                xc[r] = xn[r];
+            }
+        }
+    }
+    if constexpr (ND > 0) block_sum_store<ND>(acc, partials + (long)b * kPartialCols);
+}
+
+struct SpmvGrid {
+    int gx, gy, gz, kchunk, ntiles, per_xcd, nblocks;
+};
+
+template <int R>
+static SpmvGrid spmv_grid(int nlon, int nlat, int nlev)
+{
+    SpmvGrid g;
+    g.gx = (nlon + 63) / 64;
+    g.gy = (nlat + 4 * R - 1) / (4 * R);
+    // split the level march when the horizontal tiling alone cannot fill the chip
+    const int tiles2d = g.gx * g.gy;
+    int chunks = 1;
+    while (tiles2d * chunks < 2048 && chunks < nlev) chunks *= 2;
+    if (chunks > nlev) chunks = nlev;
+    g.kchunk = (nlev + chunks - 1) / chunks;
+    g.gz = (nlev + g.kchunk - 1) / g.kchunk;
+    g.ntiles = tiles2d * g.gz;
+    g.per_xcd = (g.ntiles + 7) / 8;
+    g.nblocks = g.per_xcd * 8;
+    return g;
+}
+
+int partial_rows_needed(int nlon, int nlat, int nlev)
+{
+    const long P = (long)nlon * nlat;
+    long rows = spmv_grid<4>(nlon, nlat, nlev).nblocks;
+    rows = std::max(rows, (P + kWG - 1) / kWG);   // thomas(S): one row per workgroup of columns
+    rows = std::max(rows, 8192L);                 // elementwise kernels
+    return (int)rows;
+}
+
+template <typename Tv, typename Tc>
+int launch_spmv_impl(const OpView<Tc> &op, const Tv *x, Tv *y, const Tv *w, int mode, double *partials,
+                     const Scalars *sc, int stop_mask, hipStream_t s)
+{
+    constexpr int R = 4;
+    SpmvGrid g = spmv_grid<R>(op.nlon, op.nlat, op.nlev);
+    if (mode == SP_DOT2)
+        hipLaunchKernelGGL((k_spmv<Tv, Tc, R, SPM_DOT2, Tv>), dim3(g.nblocks), dim3(kWG), 0, s, op, x, y, w, partials,
+                           sc, stop_mask, g.gx, g.gy, g.kchunk, g.ntiles, g.per_xcd);
+    else
+        hipLaunchKernelGGL((k_spmv<Tv, Tc, R, SPM_PLAIN, Tv>), dim3(g.nblocks), dim3(kWG), 0, s, op, x, y, w,
+                           partials, sc, stop_mask, g.gx, g.gy, g.kchunk, g.ntiles, g.per_xcd);
+    return mode == SP_DOT2 ? g.nblocks : 0;
+}
+
+template <typename Tv, typename Tc>
+void launch_spmv(const OpView<Tc> &op, const Tv *x, Tv *y, const Tv *w, int mode, double *partials, int *nrows,
+                 const Scalars *sc, int stop_mask, hipStream_t s)
+{
+    int rows = launch_spmv_impl<Tv, Tc>(op, x, y, w, mode, partials, sc, stop_mask, s);
+    if (nrows) *nrows = rows;
+}
+
+template <typename Tout>
+void launch_residual(const OpView<double> &op, const double *b, const double *x, Tout *r, double *partials,
+                     int *nrows, hipStream_t s)
+{
+    constexpr int R = 4;
+    SpmvGrid g = spmv_grid<R>(op.nlon, op.nlat, op.nlev);
+    hipLaunchKernelGGL((k_spmv<double, double, R, SPM_RESID, Tout>), dim3(g.nblocks), dim3(kWG), 0, s, op, x, r, b,
+                       partials, nullptr, 0, g.gx, g.gy, g.kchunk, g.ntiles, g.per_xcd);
+    if (nrows) *nrows = g.nblocks;
+}
+
+// ------------------------------------------------------------------------------------------
+// k_thomas: per-column tridiagonal solve T z = q, T = tridiag(-aD, g + aD + aU, -aU).
+//
+// Elimination  z_k = y_k + c_k z_{k+1}  with den_k = C_k - aD_k c_{k-1}.  Written through the
+// excess e_k = den_k - aU_k, which obeys e_k = g_k + aD_k e_{k-1} / den_{k-1}: every quantity
+// is a sum of non-negative terms, so the sweep has no cancellation even where the horizontal
+// coupling (and hence g) is tiny next to the vertical one.
+//
+// One lane per column; lane -> column index col = j*nlon + i, so each level's load is a
+// contiguous run of the plane.  NL > 0: exactly NL levels, factors held in registers.  NL == 0:
+// any nlev, the forward sweep parks y_k in z and c_k in `scratch` and the backward sweep
+// re-reads them.
+//
+// Prologues: TH_PLAIN  q read from `q`;
+//            TH_P      q = r + beta (p - omega v), stored to p (on a restart q = r and rhat = r);
+//            TH_S      q = r - alpha v, stored to s (passed as `p`), ||q||^2 partial.
+// ------------------------------------------------------------------------------------------
+template <typename Tv, typename Tc, int NL, int MODE>
+__global__ __launch_bounds__(kWG) void k_thomas(OpView<Tc> op, const Tv *__restrict__ q, Tv *__restrict__ z,
+                                                const Tv *__restrict__ r, Tv *__restrict__ p,
+                                                const Tv *__restrict__ v, Tv *__restrict__ rhat,
+                                                Tv *__restrict__ scratch, double *__restrict__ partials,
+                                                const Scalars *__restrict__ sc, int stop_mask)
+{
+    if (stopped(sc, stop_mask)) return;
+    using V = typename CoefTraits<Tc>::val;
+    constexpr bool Q = CoefTraits<Tc>::quant;
+    const long P = op.P, n = op.n;
+    const int nlev = (NL > 0) ? NL : op.nlev;
+    const long col = (long)blockIdx.x * kWG + threadIdx.x;
+    const bool act = col < P;
+    const long cc = act ? col : P - 1;
+    const Tc *aDp = op.a + 4 * n;
+    const Tc *aUp = op.a + 5 * n;
+    long qrow = 0, qd = 0;
+    if constexpr (Q) {
+        qrow = cc / op.nlon;              // latitude row of this column
+        qd = (long)op.nlev * op.nlat;
+    }
+    Tv beta = 0, omega = 0, alpha = 0;
+    int fresh = 0;
+    if constexpr (MODE == TH_P) {
+        fresh = sc->fresh;
+        beta = static_cast<Tv>(sc->beta);
+        omega = static_cast<Tv>(sc->omega);
+    }
+    if constexpr (MODE == TH_S) alpha = static_cast<Tv>(sc->alpha);
+    double acc[1] = {0.0};
+
+    auto qval = [&](long c) -> Tv {
+        Tv qk;
+        if constexpr (MODE == TH_PLAIN) {
+            qk = q[c];
+        } else if constexpr (MODE == TH_P) {
+            const Tv rk = r[c];
+            if (fresh) {
+                qk = rk;
+                if (act) rhat[c] = rk;
+            } else {
+                qk = rk + beta * (p[c] - omega * v[c]);
+            }
+            if (act) p[c] = qk;
+        } else {
+            qk = r[c] - alpha * v[c];
+            if (act) {
+                p[c] = qk;
+                acc[0] += static_cast<double>(qk) * static_cast<double>(qk);
+            }
+        }
+        return qk;
+    };
+    auto coefs = [&](long c, int k, V &aD, V &aU, V &g) {
+        float sD = 1.f, sU = 1.f;
+        if constexpr (Q) {
+            sD = op.qs[4 * qd + (long)k * op.nlat + qrow];
+            sU = op.qs[5 * qd + (long)k * op.nlat + qrow];
+        }
+        aD = Dec<Tc>::get(aDp, c, sD);
+        aU = Dec<Tc>::get(aUp, c, sU);
+        g = op.g[c];
+    };
+
+    if constexpr (NL > 0) {
+        Tv cf[NL], yv[NL];
+        Tv ratio = 0, yprev = 0;
+#pragma unroll
+        for (int k = 0; k < NL; ++k) {
+            const long c = cc + (long)k * P;
+            const Tv qk = qval(c);
+            V aD, aU, g;
+            coefs(c, k, aD, aU, g);
+            const Tv e = g + aD * ratio;
+            const Tv den = e + aU;
+            const Tv inv = Tv(1) / den;
+            cf[k] = aU * inv;
+            yv[k] = (qk + aD * yprev) * inv;
+            ratio = e * inv;
+            yprev = yv[k];
+        }
+        Tv zz = 0;
+#pragma unroll
+        for (int k = NL - 1; k >= 0; --k) {
+            zz = yv[k] + cf[k] * zz;
+            if (act) z[cc + (long)k * P] = zz;
+        }
+    } else {
+        Tv ratio = 0, yprev = 0;
+        for (int k = 0; k < nlev; ++k) {
+            const long c = cc + (long)k * P;
+            const Tv qk = qval(c);
+            V aD, aU, g;
+            coefs(c, k, aD, aU, g);
+            const Tv e = g + aD * ratio;
+            const Tv den = e + aU;
+            const Tv inv = Tv(1) / den;
+            const Tv ck = aU * inv;
+            const Tv yk = (qk + aD * yprev) * inv;
+            ratio = e * inv;
+            yprev = yk;
+            if (act) {
+                z[c] = yk;
+                scratch[c] = ck;
+            }
+        }
+        Tv zz = 0;
+        for (int k = nlev - 1; k >= 0; --k) {
+            const long c = cc + (long)k * P;
+            if (act) {
+                zz = z[c] + scratch[c] * zz;
+                z[c] = zz;
+            }
+        }
+    }
+    if constexpr (MODE == TH_S) block_sum_store<1>(acc, partials + (long)blockIdx.x * kPartialCols);
+}
+
+template <typename Tv, typename Tc, int NL>
+static int thomas_dispatch_mode(const OpView<Tc> &op, const Tv *q, Tv *z, int mode, Tv *r, Tv *p, const Tv *v,
+                                Tv *rhat, Tv *scratch, double *partials, const Scalars *sc, hipStream_t s)
+{
+    const int nb = (int)((op.P + kWG - 1) / kWG);
+    switch (mode) {
+    case TH_P:
+        hipLaunchKernelGGL((k_thomas<Tv, Tc, NL, TH_P>), dim3(nb), dim3(kWG), 0, s, op, q, z, r, p, v, rhat, scratch,
+                           partials, sc, STOP_DONE);
+        return 0;
+    case TH_S:
+        hipLaunchKernelGGL((k_thomas<Tv, Tc, NL, TH_S>), dim3(nb), dim3(kWG), 0, s, op, q, z, r, p, v, rhat, scratch,
+                           partials, sc, STOP_DONE | STOP_SKIP);
+        return nb;
+    default:
+        hipLaunchKernelGGL((k_thomas<Tv, Tc, NL, TH_PLAIN>), dim3(nb), dim3(kWG), 0, s, op, q, z, r, p, v, rhat,
+                           scratch, partials, sc, 0);
+        return 0;
+    }
+}
+
+template <typename Tv, typename Tc>
+void launch_thomas(const OpView<Tc> &op, const Tv *q, Tv *z, int mode, Tv *r, Tv *p, const Tv *v, Tv *rhat,
+                   Tv *scratch, double *partials, int *nrows, const Scalars *sc, hipStream_t s)
+{
+    int rows;
+    // Register-resident sweeps for the level counts in use, as long as the factors of a
+    // column fit in registers without spilling (70 FP64 levels do not); any other case takes
+    // the generic path.
+    constexpr bool wide = sizeof(Tv) == 8;
+    if (op.nlev == 20)
+        rows = thomas_dispatch_mode<Tv, Tc, 20>(op, q, z, mode, r, p, v, rhat, scratch, partials, sc, s);
+    else if (op.nlev == 70 && !wide)
+        rows = thomas_dispatch_mode<Tv, Tc, (wide ? 0 : 70)>(op, q, z, mode, r, p, v, rhat, scratch, partials, sc, s);
+    else
+        rows = thomas_dispatch_mode<Tv, Tc, 0>(op, q, z, mode, r, p, v, rhat, scratch, partials, sc, s);
+    if (nrows) *nrows = rows;
+}
+
+// ------------------------------------------------------------------------------------------
+// k_update: end of a BiCGStab iteration.
+//   full step    x += alpha phat + omega shat; r = s - omega t; partials <rhat, r>, <r, r>
+//   half step    x += alpha phat                      (converged at s)
+//   omega = 0    x += alpha phat; r = s; partial <r, r>   (restart follows)
+// ------------------------------------------------------------------------------------------
+template <typename Tv>
+__global__ __launch_bounds__(kWG) void k_update(long n, Tv *__restrict__ x, const Tv *__restrict__ ph,
+                                                const Tv *__restrict__ sh, const Tv *__restrict__ s,
+                                                const Tv *__restrict__ t, Tv *__restrict__ r,
+                                                const Tv *__restrict__ rhat, double *__restrict__ partials,
+                                                const Scalars *__restrict__ sc)
+{
+    if (sc->done || sc->skip) return;
+    const Tv alpha = static_cast<Tv>(sc->alpha);
+    const Tv omega = static_cast<Tv>(sc->omega);
+    const int half = sc->half, wbd = sc->wbd;
+    double acc[2] = {0.0, 0.0};
+    const long stride = (long)gridDim.x * kWG;
+    for (long i = (long)blockIdx.x * kWG + threadIdx.x; i < n; i += stride) {
+        if (half) {
+            x[i] = x[i] + alpha * ph[i];
+        } else if (wbd) {
+            x[i] = x[i] + alpha * ph[i];
+            const Tv si = s[i];
+            r[i] = si;
+            acc[1] += static_cast<double>(si) * static_cast<double>(si);
+        } else {
+            x[i] = x[i] + alpha * ph[i] + omega * sh[i];
+            const Tv ri = s[i] - omega * t[i];
+            r[i] = ri;
+            acc[0] += static_cast<double>(rhat[i]) * static_cast<double>(ri);
+            acc[1] += static_cast<double>(ri) * static_cast<double>(ri);
+        }
+    }
+    block_sum_store<2>(acc, partials + (long)blockIdx.x * kPartialCols);
+}
+
+static int elementwise_blocks(long n)
+{
+    long nb = (n + kWG * 4 - 1) / (kWG * 4);
+    if (nb > 8192) nb = 8192;
+    if (nb < 1) nb = 1;
+    return (int)nb;
+}
+
+template <typename Tv>
+void launch_update(long n, Tv *x, const Tv *ph, const Tv *sh, const Tv *s, const Tv *t, Tv *r, const Tv *rhat,
+                   double *partials, int *nrows, const Scalars *sc, hipStream_t stream)
+{
+    const int nb = elementwise_blocks(n);
+    hipLaunchKernelGGL((k_update<Tv>), dim3(nb), dim3(kWG), 0, stream, n, x, ph, sh, s, t, r, rhat, partials, sc);
+    if (nrows) *nrows = nb;
+}
+
+// ------------------------------------------------------------------------------------------
+// generic dot product (products and sums in FP64)
+// ------------------------------------------------------------------------------------------
+template <typename Ta, typename Tb>
+__global__ __launch_bounds__(kWG) void k_dot(long n, const Ta *__restrict__ a, const Tb *__restrict__ b,
+                                             double *__restrict__ partials)
+{
+    double acc[1] = {0.0};
+    const long stride = (long)gridDim.x * kWG;
+    for (long i = (long)blockIdx.x * kWG + threadIdx.x; i < n; i += stride)
+        acc[0] += static_cast<double>(a[i]) * static_cast<double>(b[i]);
+    block_sum_store<1>(acc, partials + (long)blockIdx.x * kPartialCols);
+}
+
+template <typename Ta, typename Tb>
+void launch_dot(long n, const Ta *a, const Tb *b, double *partials, int *nrows, hipStream_t s)
+{
+    const int nb = elementwise_blocks(n);
+    hipLaunchKernelGGL((k_dot<Ta, Tb>), dim3(nb), dim3(kWG), 0, s, n, a, b, partials);
+    if (nrows) *nrows = nb;
+}
+
+// ------------------------------------------------------------------------------------------
+// k_finalize: one workgroup.  Fixed-order FP64 reduction of the partial rows, then the
+// scalar part of the iteration (thread 0).
+// ------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(kWG) void k_finalize(int stage, const double *__restrict__ partials, int nrows,
+                                                  Scalars *__restrict__ sc, double *__restrict__ hist,
+                                                  double *__restrict__ out, int c_rr, int c_nb)
+{
+    double a[kPartialCols];
+#pragma unroll
+    for (int c = 0; c < kPartialCols; ++c) a[c] = 0.0;
+    for (int r = threadIdx.x; r < nrows; r += kWG)
+#pragma unroll
+        for (int c = 0; c < kPartialCols; ++c) a[c] += partials[(long)r * kPartialCols + c];
+    __shared__ double tot[kPartialCols];
+    block_sum_store<kPartialCols>(a, tot);
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    const double s0 = tot[0], s1 = tot[1], s2 = tot[2], s3 = tot[3];
+
+    switch (stage) {
+    case FIN_SUM:
+        out[0] = s0;
+        out[1] = s1;
+        out[2] = s2;
+        out[3] = s3;
+        return;
+    case FIN_INIT: {
+        // start of a Krylov run: r = b - A x0 has just been formed
+        const double nb2 = tot[c_nb], rr = tot[c_rr];
+        sc->nb2 = nb2;
+        sc->thr2 = sc->aux0 * sc->aux0 * nb2;   // aux0 carries tol
+        sc->rr = rr;
+        sc->iter = 0;
+        sc->status = 0;
+        sc->skip = sc->half = sc->wbd = 0;
+        sc->restarts = 0;
+        sc->fresh = 1;
+        sc->was_fresh = 0;
+        sc->rho = rr;
+        sc->rhat2 = rr;
+        sc->rho_prev = sc->alpha = sc->omega = 1.0;
+        sc->beta = 0.0;
+        sc->last_rel = nb2 > 0.0 ? sqrt(rr / nb2) : 0.0;
+        sc->done = (nb2 == 0.0 || rr <= sc->thr2) ? 1 : 0;
+        if (out) {
+            out[0] = s0;
+            out[1] = s1;
+            out[2] = s2;
+            out[3] = s3;
+        }
+        return;
+    }
+    case FIN_TRUE:
+        // restart from a freshly computed true residual (periodic or residual-gap restart)
+        sc->rr = tot[c_rr];
+        sc->status = 0;
+        sc->skip = sc->half = sc->wbd = 0;
+        sc->fresh = 1;
+        sc->rho = sc->rr;
+        sc->rhat2 = sc->rr;
+        sc->last_rel = sqrt(sc->rr / sc->nb2);
+        sc->done = (sc->rr <= sc->thr2) ? 1 : 0;
+        sc->restarts += 1;
+        return;
+    default:
+        break;
+    }
+    if (sc->done) return;
+    switch (stage) {
+    case FIN_SIGMA: {
+        const int wf = sc->fresh;
+        sc->was_fresh = wf;
+        sc->fresh = 0;
+        const double sigma = s0, vv = s1;
+        if (!isfinite(sigma) || !isfinite(vv)) {   // poisoned iteration: stop
+            sc->done = 1;
+            sc->status = 2;
+            sc->iter += 1;
+            return;
+        }
+        if (fabs(sigma) <= sc->eps_bd * sqrt(sc->rhat2 * vv)) {
+            if (wf) {               // breakdown right after a restart: nothing left to try
+                sc->done = 1;
+                sc->status = 2;
+                sc->iter += 1;
+                return;
+            }
+            sc->skip = 1;
+            sc->restarts += 1;
+            return;
+        }
+        sc->alpha = sc->rho / sigma;
+        return;
+    }
+    case FIN_S:
+        if (sc->skip) return;
+        sc->ss = s0;
+        if (s0 <= sc->thr2) sc->half = 1;
+        return;
+    case FIN_OMEGA:
+        if (sc->skip || sc->half) return;
+        if (s1 == 0.0 || s0 == 0.0) {
+            sc->wbd = 1;
+            sc->restarts += 1;
+        } else {
+            sc->omega = s0 / s1;
+        }
+        return;
+    case FIN_END: {
+        const int it = sc->iter + 1;
+        sc->iter = it;
+        const int slot = sc->hist_base + it - 1;
+        if (sc->skip) {
+            sc->skip = 0;
+            sc->fresh = 1;
+            if (hist && slot < sc->hist_cap) hist[slot] = sc->last_rel;
+            if (it >= sc->maxit) {
+                sc->done = 1;
+                sc->status = 1;
+            }
+            return;
+        }
+        if (sc->half) {
+            sc->last_rel = sqrt(sc->ss / sc->nb2);
+            if (hist && slot < sc->hist_cap) hist[slot] = sc->last_rel;
+            sc->done = 1;
+            sc->status = 0;
+            return;
+        }
+        const double rr = s1;
+        sc->rr = rr;
+        sc->last_rel = sqrt(rr / sc->nb2);
+        if (hist && slot < sc->hist_cap) hist[slot] = sc->last_rel;
+        if (!isfinite(rr) || !isfinite(s0)) {
+            sc->done = 1;
+            sc->status = 2;
+            return;
+        }
+        if (sc->wbd) {
+            sc->wbd = 0;
+            sc->fresh = 1;
+        }
+        if (rr <= sc->thr2) {
+            sc->done = 1;
+            sc->status = 0;
+            return;
+        }
+        if (it >= sc->maxit) {
+            sc->done = 1;
+            sc->status = 1;
+            return;
+        }
+        if (sc->restart_every > 0 && it % sc->restart_every == 0) {
+            sc->done = 1;
+            sc->status = 4;
+            return;
+        }
+        if (sc->fresh) {
+            sc->rho = rr;
+            sc->rhat2 = rr;
+            sc->rho_prev = sc->alpha = sc->omega = 1.0;
+            sc->beta = 0.0;
+            return;
+        }
+        const double rhr = s0;
+        if (fabs(rhr) <= sc->eps_bd * sqrt(sc->rhat2 * rr)) {
+            sc->fresh = 1;
+            sc->restarts += 1;
+            sc->rho = rr;
+            sc->rhat2 = rr;
+            sc->rho_prev = sc->alpha = sc->omega = 1.0;
+            sc->beta = 0.0;
+            return;
+        }
+        sc->rho_prev = sc->rho;
+        sc->beta = (rhr / sc->rho) * (sc->alpha / sc->omega);
+        sc->rho = rhr;
+        return;
+    }
+    default:
+        return;
+    }
+}
+
+void launch_finalize(int stage, const double *partials, int nrows, Scalars *sc, double *hist, double *out,
+                     int c_rr, int c_nb, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kWG), 0, s, stage, partials, nrows, sc, hist, out, c_rr, c_nb);
+}
+
+// ------------------------------------------------------------------------------------------
+// small elementwise kernels
+// ------------------------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kWG) void k_fill(T *p, long n, T v)
+{
+    const long stride = (long)gridDim.x * kWG;
+    for (long i = (long)blockIdx.x * kWG + threadIdx.x; i < n; i += stride) p[i] = v;
+}
+
+template <typename T> void launch_fill(T *p, long n, T v, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_fill<T>), dim3(elementwise_blocks(n)), dim3(kWG), 0, s, p, n, v);
+}
+
+// x64 += d32 (the FP64 solution update of a refinement step)
+__global__ __launch_bounds__(kWG) void k_add_correction(long n, double *__restrict__ x, const float *__restrict__ d)
+{
+    const long stride = (long)gridDim.x * kWG;
+    for (long i = (long)blockIdx.x * kWG + threadIdx.x; i < n; i += stride) x[i] += static_cast<double>(d[i]);
+}
+
+void launch_add_correction(long n, double *x, const float *d, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_add_correction, dim3(elementwise_blocks(n)), dim3(kWG), 0, s, n, x, d);
+}
+
+__global__ __launch_bounds__(kWG) void k_check_finite(long n, const double *__restrict__ v, int *bad)
+{
+    int cnt = 0;
+    const long stride = (long)gridDim.x * kWG;
+    for (long i = (long)blockIdx.x * kWG + threadIdx.x; i < n; i += stride)
+        if (!isfinite(v[i])) ++cnt;
+    if (cnt) atomicAdd(bad, cnt);
+}
+
+void launch_check_finite(long n, const double *v, int *bad, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_check_finite, dim3(elementwise_blocks(n)), dim3(kWG), 0, s, n, v, bad);
+}
+
+// ------------------------------------------------------------------------------------------
+// operator setup
+// ------------------------------------------------------------------------------------------
+// Copy the couplings, derive m = C - (((((W+E)+S)+N)+D)+U) and g = m + (((W+E)+S)+N), and
+// count violations: bad[0] non-finite, bad[1] negative coupling, bad[2] coupling across a
+// pole / the bottom / the top, bad[3] non-positive margin.
+__global__ __launch_bounds__(kWG) void k_derive(const double *__restrict__ cf, int nlon, int nlat, int nlev,
+                                                double *__restrict__ a64, double *__restrict__ m64,
+                                                double *__restrict__ g64, int *__restrict__ bad)
+{
+    const long P = (long)nlon * nlat;
+    const long n = P * nlev;
+    int b0 = 0, b1 = 0, b2 = 0, b3 = 0;
+    const long stride = (long)gridDim.x * kWG;
+    for (long c = (long)blockIdx.x * kWG + threadIdx.x; c < n; c += stride) {
+        const int j = (int)((c / nlon) % nlat);
+        const int k = (int)(c / P);
+        double a[6];
+#pragma unroll
+        for (int d = 0; d < 6; ++d) {
+            a[d] = cf[d * n + c];
+            a64[d * n + c] = a[d];
+            if (!isfinite(a[d])) ++b0;
+            else if (a[d] < 0.0) ++b1;
+        }
+        const double C = cf[6 * n + c];
+        if (!isfinite(C)) ++b0;
+        if ((j == 0 && a[2] != 0.0) || (j == nlat - 1 && a[3] != 0.0) || (k == 0 && a[4] != 0.0) ||
+            (k == nlev - 1 && a[5] != 0.0))
+            ++b2;
+        const double hs = ((a[0] + a[1]) + a[2]) + a[3];
+        const double m = C - ((hs + a[4]) + a[5]);
+        if (!(m > 0.0)) ++b3;
+        m64[c] = m;
+        g64[c] = m + hs;
+    }
+    if (b0) atomicAdd(bad + 0, b0);
+    if (b1) atomicAdd(bad + 1, b1);
+    if (b2) atomicAdd(bad + 2, b2);
+    if (b3) atomicAdd(bad + 3, b3);
+}
+
+void launch_derive(const double *coeffs, int nlon, int nlat, int nlev, double *a64, double *m64, double *g64,
+                   int *bad, hipStream_t s)
+{
+    const long n = (long)nlon * nlat * nlev;
+    hipLaunchKernelGGL(k_derive, dim3(elementwise_blocks(n)), dim3(kWG), 0, s, coeffs, nlon, nlat, nlev, a64, m64,
+                       g64, bad);
+}
+
+__global__ __launch_bounds__(kWG) void k_to_fp32(long n, const double *__restrict__ a64,
+                                                 const double *__restrict__ m64, const double *__restrict__ g64,
+                                                 float *__restrict__ a32, float *__restrict__ m32,
+                                                 float *__restrict__ g32)
+{
+    const long stride = (long)gridDim.x * kWG;
+    for (long c = (long)blockIdx.x * kWG + threadIdx.x; c < n; c += stride) {
+#pragma unroll
+        for (int d = 0; d < 6; ++d) a32[d * n + c] = static_cast<float>(a64[d * n + c]);
+        m32[c] = static_cast<float>(m64[c]);
+        g32[c] = static_cast<float>(g64[c]);
+    }
+}
+
+void launch_to_fp32(long n, const double *a64, const double *m64, const double *g64, float *a32, float *m32,
+                    float *g32, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_to_fp32, dim3(elementwise_blocks(n)), dim3(kWG), 0, s, n, a64, m64, g64, a32, m32, g32);
+}
+
+// Round a non-negative double to p significant bits, ties to even, with exponents below emin
+// held at emin (gradual underflow).  Every step is exact except the single rint.
+__device__ double round_sig(double u, int p, int emin)
+{
+    if (u == 0.0) return 0.0;
+    int e;
+    (void)frexp(u, &e);         // u = f 2^e, f in [1/2, 1): leading bit has weight 2^(e-1)
+    int lead = e - 1;
+    if (lead < emin) lead = emin;
+    const double ulp = ldexp(1.0, lead - (p - 1));
+    return rint(u / ulp) * ulp;
+}
+
+// one wave per (direction, level, latitude row): power-of-two scale 2^ceil(log2 max a)
+__global__ __launch_bounds__(64) void k_qscale(int nlon, int nlat, int nlev, const double *__restrict__ a64,
+                                               float *__restrict__ qs)
+{
+    const long row = blockIdx.x;   // (d * nlev + k) * nlat + j
+    const int d = (int)(row / ((long)nlev * nlat));
+    const long kj = row % ((long)nlev * nlat);
+    const long n = (long)nlon * nlat * nlev;
+    const double *src = a64 + (long)d * n + kj * nlon;
+    double mx = 0.0;
+    for (int i = threadIdx.x; i < nlon; i += 64) mx = fmax(mx, src[i]);
+    for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off));
+    if (threadIdx.x == 0) {
+        float s = 1.f;
+        if (mx > 0.0) {
+            int e;
+            const double f = frexp(mx, &e);
+            s = ldexpf(1.f, (f == 0.5) ? e - 1 : e);
+        }
+        qs[row] = s;
+    }
+}
+
+// a_q = RNE(a / scale) in BF16 (kind 2) or FP16 (kind 3); g_q = m + sum of the decoded W,E,S,N
+__global__ __launch_bounds__(kWG) void k_quantize(int kind, int nlon, int nlat, int nlev,
+                                                  const double *__restrict__ a64, const double *__restrict__ m64,
+                                                  const float *__restrict__ qs, uint16_t *__restrict__ aq,
+                                                  float *__restrict__ gq)
+{
+    const long P = (long)nlon * nlat;
+    const long n = P * nlev;
+    const long stride = (long)gridDim.x * kWG;
+    for (long c = (long)blockIdx.x * kWG + threadIdx.x; c < n; c += stride) {
+        const long kj = c / nlon;   // k * nlat + j
+        double hs = 0.0;
+#pragma unroll
+        for (int d = 0; d < 6; ++d) {
+            const double s = qs[(long)d * nlev * nlat + kj];
+            const double u = a64[d * n + c] / s;
+            uint16_t bits;
+            double dq;
+            if (kind == PBF16) {
+                const double r = round_sig(u, 8, -126);
+                bits = static_cast<uint16_t>(__float_as_uint(static_cast<float>(r)) >> 16);
+                dq = static_cast<double>(bf16_to_f(bits)) * s;
+            } else {
+                const double r = round_sig(u, 11, -14);
+                const _Float16 h = static_cast<_Float16>(static_cast<float>(r));
+                bits = __builtin_bit_cast(uint16_t, h);
+                dq = static_cast<double>(fp16_to_f(bits)) * s;
+            }
+            aq[d * n + c] = bits;
+            if (d < 4) hs += dq;
+        }
+        gq[c] = static_cast<float>(m64[c] + hs);
+    }
+}
+
+void launch_quantize(int kind, int nlon, int nlat, int nlev, const double *a64, const double *m64, uint16_t *aq,
+                     float *qs, float *gq, hipStream_t s)
+{
+    const long rows = 6L * nlev * nlat;
+    hipLaunchKernelGGL(k_qscale, dim3((unsigned)rows), dim3(64), 0, s, nlon, nlat, nlev, a64, qs);
+    const long n = (long)nlon * nlat * nlev;
+    hipLaunchKernelGGL(k_quantize, dim3(elementwise_blocks(n)), dim3(kWG), 0, s, kind, nlon, nlat, nlev, a64, m64, qs,
+                       aq, gq);
+}
+
+// ------------------------------------------------------------------------------------------
+// explicit instantiations
+// ------------------------------------------------------------------------------------------
+template void launch_spmv<double, double>(const OpView<double> &, const double *, double *, const double *, int,
+                                          double *, int *, const Scalars *, int, hipStream_t);
+template void launch_spmv<float, float>(const OpView<float> &, const float *, float *, const float *, int, double *,
+                                        int *, const Scalars *, int, hipStream_t);
+template void launch_spmv<float, bf16_t>(const OpView<bf16_t> &, const float *, float *, const float *, int,
+                                         double *, int *, const Scalars *, int, hipStream_t);
+template void launch_spmv<float, fp16_t>(const OpView<fp16_t> &, const float *, float *, const float *, int,
+                                         double *, int *, const Scalars *, int, hipStream_t);
+template void launch_residual<double>(const OpView<double> &, const double *, const double *, double *, double *,
+                                      int *, hipStream_t);
+template void launch_residual<float>(const OpView<double> &, const double *, const double *, float *, double *,
+                                     int *, hipStream_t);
+template void launch_thomas<double, double>(const OpView<double> &, const double *, double *, int, double *,
+                                            double *, const double *, double *, double *, double *, int *,
+                                            const Scalars *, hipStream_t);
+template void launch_thomas<float, float>(const OpView<float> &, const float *, float *, int, float *, float *,
+                                          const float *, float *, float *, double *, int *, const Scalars *,
+                                          hipStream_t);
+template void launch_thomas<float, bf16_t>(const OpView<bf16_t> &, const float *, float *, int, float *, float *,
+                                           const float *, float *, float *, double *, int *, const Scalars *,
+                                           hipStream_t);
+template void launch_thomas<float, fp16_t>(const OpView<fp16_t> &, const float *, float *, int, float *, float *,
+                                           const float *, float *, float *, double *, int *, const Scalars *,
+                                           hipStream_t);
+template void launch_update<double>(long, double *, const double *, const double *, const double *, const double *,
+                                    double *, const double *, double *, int *, const Scalars *, hipStream_t);
+template void launch_update<float>(long, float *, const float *, const float *, const float *, const float *,
+                                   float *, const float *, double *, int *, const Scalars *, hipStream_t);
+template void launch_dot<double, double>(long, const double *, const double *, double *, int *, hipStream_t);
+template void launch_dot<float, float>(long, const float *, const float *, double *, int *, hipStream_t);
+template void launch_fill<double>(double *, long, double, hipStream_t);
+template void launch_fill<float>(float *, long, float, hipStream_t);
+
+}  // namespace eg

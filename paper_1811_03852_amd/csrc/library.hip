@@ -1,0 +1,635 @@
+// Host side of the endgame library: operator object, BiCGStab drivers and the C ABI.
+//
+// BiCGStab (Sec. 2, Eq. 5 of the paper: right-preconditioned, so the tracked residual is the
+// unpreconditioned b - A x that the halting test of Sec. 3, Eq. 8-9 measures) runs as a
+// device-driven state machine: the streaming kernels read alpha, beta, omega and the flags
+// from a device scalar block, single-workgroup finalize kernels reduce the FP64 partials and
+// advance the recurrences.  The host only enqueues batches of iterations and looks at the
+// flags between batches; kernels enqueued after convergence return at once, so the stopping
+// iteration is exact.
+//
+// One iteration (kernel order):
+//   thomas(P)  p = r + beta (p - omega v); phat = T^{-1} p
+//   spmv       v = A phat;  <rhat, v>, <v, v>               -> finalize(SIGMA): alpha
+//   thomas(S)  s = r - alpha v; shat = T^{-1} s; <s, s>    -> finalize(S): half-step exit?
+//   spmv       t = A shat;  <t, s>, <t, t>                  -> finalize(OMEGA): omega
+//   update     x += alpha phat + omega shat; r = s - omega t; <rhat, r>, <r, r>
+//                                                           -> finalize(END): rho, beta, stop?
+//
+// Mixed precision (Sec. 3-4 of the paper keep x in 64-bit, do the bulk in 32-bit and revert
+// the global sums to 64-bit): the refinement driver forms r = b - A x in FP64, rounds it to
+// FP32, solves A d = r with the FP32 machine above (FP64 dot accumulation) to a modest
+// relative tolerance eta, and updates x += d in FP64.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/endgame.h"
+#include "eg_internal.h"
+
+using namespace eg;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg)
+{
+    g_err = msg;
+    return code;
+}
+
+#define EG_HIP(call)                                                                                   \
+    do {                                                                                               \
+        hipError_t e_ = (call);                                                                        \
+        if (e_ != hipSuccess) return fail(EG_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+template <typename T> int dalloc(T **p, size_t count)
+{
+    *p = nullptr;
+    if (count == 0) count = 1;
+    hipError_t e = hipMalloc(reinterpret_cast<void **>(p), count * sizeof(T));
+    if (e != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return fail(EG_ENOMEM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed");
+    }
+    return 0;
+}
+
+template <typename T> void dfree(T *&p)
+{
+    if (p) (void)hipFree(p);
+    p = nullptr;
+}
+
+template <typename Tv> struct Work {
+    Tv *r = nullptr, *rh = nullptr, *p = nullptr, *ph = nullptr, *v = nullptr, *s = nullptr, *sh = nullptr,
+       *t = nullptr, *x = nullptr, *scr = nullptr;
+    bool ready = false;
+};
+
+}  // namespace
+
+struct eg_operator {
+    int nlon = 0, nlat = 0, nlev = 0;
+    long P = 0, n = 0;
+    hipStream_t stream = nullptr;
+
+    double *a64 = nullptr, *m64 = nullptr, *g64 = nullptr;
+    float *a32 = nullptr, *m32 = nullptr, *g32 = nullptr;
+    uint16_t *aq[2] = {nullptr, nullptr};
+    float *gq[2] = {nullptr, nullptr};
+    float *qs[2] = {nullptr, nullptr};
+
+    Work<double> w64;
+    Work<float> w32;
+
+    double *partials = nullptr;
+    Scalars *sc = nullptr;       // device
+    Scalars *h_sc = nullptr;     // pinned host mirror
+    double *d_out = nullptr;     // device, 4 doubles
+    double *h_out = nullptr;     // pinned host, 4 doubles
+    int *d_bad = nullptr;        // device, 4 ints
+    double *d_hist = nullptr;
+    int hist_cap = 0;
+
+    double eta = 1e-4;
+    int restart_every = 0;
+    int max_outer = 30;
+    int poll = 8;
+    int use_graph = 1;
+    int stall_window = 20;
+
+    eg_info info{};
+    std::vector<double> hist_host;
+    int hist_count = 0;
+
+    OpView<double> view64() const { return {a64, m64, g64, nullptr, nlon, nlat, nlev, P, n}; }
+    OpView<float> view32() const { return {a32, m32, g32, nullptr, nlon, nlat, nlev, P, n}; }
+    template <typename Tq> OpView<Tq> viewq(int slot) const
+    {
+        return {reinterpret_cast<const Tq *>(aq[slot]), m32, gq[slot], qs[slot], nlon, nlat, nlev, P, n};
+    }
+};
+
+namespace {
+
+int ensure_fp32(eg_operator *op)
+{
+    if (op->a32) return 0;
+    int rc;
+    if ((rc = dalloc(&op->a32, 6 * (size_t)op->n))) return rc;
+    if ((rc = dalloc(&op->m32, (size_t)op->n))) return rc;
+    if ((rc = dalloc(&op->g32, (size_t)op->n))) return rc;
+    launch_to_fp32(op->n, op->a64, op->m64, op->g64, op->a32, op->m32, op->g32, op->stream);
+    EG_HIP(hipGetLastError());
+    return 0;
+}
+
+int ensure_quant(eg_operator *op, int kind)
+{
+    const int slot = (kind == PBF16) ? 0 : 1;
+    int rc;
+    if ((rc = ensure_fp32(op))) return rc;   // m32 is shared with the FP32 set
+    if (op->aq[slot]) return 0;
+    if ((rc = dalloc(&op->aq[slot], 6 * (size_t)op->n))) return rc;
+    if ((rc = dalloc(&op->gq[slot], (size_t)op->n))) return rc;
+    if ((rc = dalloc(&op->qs[slot], 6 * (size_t)op->nlev * op->nlat))) return rc;
+    launch_quantize(kind, op->nlon, op->nlat, op->nlev, op->a64, op->m64, op->aq[slot], op->qs[slot], op->gq[slot],
+                    op->stream);
+    EG_HIP(hipGetLastError());
+    return 0;
+}
+
+template <typename Tv> int ensure_work(eg_operator *op, Work<Tv> &w)
+{
+    if (w.ready) return 0;
+    Tv **bufs[] = {&w.r, &w.rh, &w.p, &w.ph, &w.v, &w.s, &w.sh, &w.t, &w.x, &w.scr};
+    for (Tv **b : bufs) {
+        int rc = dalloc(b, (size_t)op->n);
+        if (rc) return rc;
+    }
+    w.ready = true;
+    return 0;
+}
+
+int ensure_hist(eg_operator *op, int cap)
+{
+    if (cap <= op->hist_cap) return 0;
+    dfree(op->d_hist);
+    int rc = dalloc(&op->d_hist, (size_t)cap);
+    if (rc) return rc;
+    op->hist_cap = cap;
+    return 0;
+}
+
+int sync_scalars(eg_operator *op)
+{
+    EG_HIP(hipMemcpyAsync(op->h_sc, op->sc, sizeof(Scalars), hipMemcpyDeviceToHost, op->stream));
+    EG_HIP(hipStreamSynchronize(op->stream));
+    return 0;
+}
+
+// Set the run parameters of the scalar block (host fields) before FIN_INIT.
+int put_run_params(eg_operator *op, double tol, int maxit, int hist_base, int restart_every)
+{
+    Scalars h{};
+    h.aux0 = tol;
+    h.maxit = maxit;
+    h.eps_bd = 2.220446049250313e-16;
+    h.hist_base = hist_base;
+    h.hist_cap = op->hist_cap;
+    h.restart_every = restart_every;
+    *op->h_sc = h;
+    EG_HIP(hipMemcpyAsync(op->sc, op->h_sc, sizeof(Scalars), hipMemcpyHostToDevice, op->stream));
+    return 0;
+}
+
+template <typename Tv, typename Tc>
+void enqueue_iteration(eg_operator *op, const OpView<Tc> &A, Work<Tv> &w)
+{
+    hipStream_t s = op->stream;
+    int nr = 0;
+    launch_thomas<Tv, Tc>(A, nullptr, w.ph, TH_P, w.r, w.p, w.v, w.rh, w.scr, op->partials, &nr, op->sc, s);
+    launch_spmv<Tv, Tc>(A, w.ph, w.v, w.rh, SP_DOT2, op->partials, &nr, op->sc, STOP_DONE, s);
+    launch_finalize(FIN_SIGMA, op->partials, nr, op->sc, op->d_hist, nullptr, 0, 0, s);
+    launch_thomas<Tv, Tc>(A, nullptr, w.sh, TH_S, w.r, w.s, w.v, nullptr, w.scr, op->partials, &nr, op->sc, s);
+    launch_finalize(FIN_S, op->partials, nr, op->sc, op->d_hist, nullptr, 0, 0, s);
+    launch_spmv<Tv, Tc>(A, w.sh, w.t, w.s, SP_DOT2, op->partials, &nr, op->sc, STOP_DONE | STOP_SKIP | STOP_HALF, s);
+    launch_finalize(FIN_OMEGA, op->partials, nr, op->sc, op->d_hist, nullptr, 0, 0, s);
+    launch_update<Tv>(op->n, w.x, w.ph, w.sh, w.s, w.t, w.r, w.rh, op->partials, &nr, op->sc, s);
+    launch_finalize(FIN_END, op->partials, nr, op->sc, op->d_hist, nullptr, 0, 0, s);
+}
+
+// Run Krylov iterations until the device says done.  Precondition: FIN_INIT (or FIN_TRUE) has
+// been enqueued for this run; w.r holds the residual and w.x the iterate.
+template <typename Tv, typename Tc> int krylov_run(eg_operator *op, const OpView<Tc> &A, Work<Tv> &w)
+{
+    int rc;
+    if ((rc = sync_scalars(op))) return rc;
+    int batch = std::max(1, op->poll);
+    while (!op->h_sc->done) {
+        for (int b = 0; b < batch; ++b) enqueue_iteration<Tv, Tc>(op, A, w);
+        EG_HIP(hipGetLastError());
+        if ((rc = sync_scalars(op))) return rc;
+    }
+    return 0;
+}
+
+double fetch_out(eg_operator *op, int idx)
+{
+    return op->h_out[idx];
+}
+
+// rr64 = ||b - A x||^2, bb = ||b||^2 into h_out[0..1]; r (may be null) receives b - A x.
+template <typename Tout> int true_residual(eg_operator *op, const double *b, const double *x, Tout *r, int *nrows)
+{
+    launch_residual<Tout>(op->view64(), b, x, r, op->partials, nrows, op->stream);
+    launch_finalize(FIN_SUM, op->partials, *nrows, op->sc, nullptr, op->d_out, 0, 0, op->stream);
+    EG_HIP(hipGetLastError());
+    EG_HIP(hipMemcpyAsync(op->h_out, op->d_out, 4 * sizeof(double), hipMemcpyDeviceToHost, op->stream));
+    EG_HIP(hipStreamSynchronize(op->stream));
+    return 0;
+}
+
+int check_vectors(eg_operator *op, const double *b, const double *x)
+{
+    EG_HIP(hipMemsetAsync(op->d_bad, 0, 4 * sizeof(int), op->stream));
+    launch_check_finite(op->n, b, op->d_bad, op->stream);
+    launch_check_finite(op->n, x, op->d_bad + 1, op->stream);
+    int h[4];
+    EG_HIP(hipMemcpyAsync(h, op->d_bad, 4 * sizeof(int), hipMemcpyDeviceToHost, op->stream));
+    EG_HIP(hipStreamSynchronize(op->stream));
+    if (h[0] || h[1])
+        return fail(EG_ENONFINITE, std::to_string(h[0]) + " non-finite values in b, " + std::to_string(h[1]) +
+                                       " in x");
+    return 0;
+}
+
+// ---- plain FP64 BiCGStab --------------------------------------------------------------------
+int solve_fp64(eg_operator *op, const double *b, double *x, double tol, int maxit)
+{
+    int rc;
+    if ((rc = ensure_work(op, op->w64))) return rc;
+    Work<double> &w = op->w64;
+    hipStream_t s = op->stream;
+    const OpView<double> A = op->view64();
+    EG_HIP(hipMemcpyAsync(w.x, x, op->n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    if ((rc = put_run_params(op, tol, maxit, 0, op->restart_every))) return rc;
+    int nr = 0;
+    launch_residual<double>(A, b, w.x, w.r, op->partials, &nr, s);
+    launch_finalize(FIN_INIT, op->partials, nr, op->sc, op->d_hist, nullptr, 0, 1, s);
+    EG_HIP(hipGetLastError());
+    if ((rc = sync_scalars(op))) return rc;
+    if (op->h_sc->nb2 == 0.0) {
+        launch_fill<double>(x, op->n, 0.0, s);
+        EG_HIP(hipStreamSynchronize(s));
+        op->info.true_rel_residual = 0.0;
+        return EG_CONVERGED;
+    }
+    int gap = 0, status = EG_CONVERGED;
+    for (;;) {
+        if ((rc = krylov_run<double, double>(op, A, w))) return rc;
+        const Scalars &h = *op->h_sc;
+        if (h.status == 4) {   // periodic restart: fresh true residual
+            launch_residual<double>(A, b, w.x, w.r, op->partials, &nr, s);
+            launch_finalize(FIN_TRUE, op->partials, nr, op->sc, nullptr, nullptr, 0, 1, s);
+            EG_HIP(hipGetLastError());
+            continue;
+        }
+        if (h.status == 1) { status = EG_MAXIT; break; }
+        if (h.status == 2) { status = EG_BREAKDOWN; break; }
+        // converged on the recursive residual: check the true one (residual-gap guard)
+        launch_residual<double>(A, b, w.x, w.r, op->partials, &nr, s);
+        launch_finalize(FIN_SUM, op->partials, nr, op->sc, nullptr, op->d_out, 0, 0, s);
+        EG_HIP(hipMemcpyAsync(op->h_out, op->d_out, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
+        EG_HIP(hipStreamSynchronize(s));
+        const double rel = std::sqrt(op->h_out[0] / op->h_out[1]);
+        if (rel <= tol) { status = EG_CONVERGED; break; }
+        if (gap >= 3 || h.iter >= h.maxit) { status = (h.iter >= h.maxit) ? EG_MAXIT : EG_STALLED; break; }
+        ++gap;
+        launch_finalize(FIN_TRUE, op->partials, nr, op->sc, nullptr, nullptr, 0, 1, s);
+        EG_HIP(hipGetLastError());
+    }
+    const Scalars &h = *op->h_sc;
+    op->info.iterations = h.iter;
+    op->info.restarts = h.restarts;
+    op->hist_count = h.iter;
+    EG_HIP(hipMemcpyAsync(x, w.x, op->n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    int n2;
+    if ((rc = true_residual<double>(op, b, x, static_cast<double *>(nullptr), &n2))) return rc;
+    op->info.true_rel_residual = std::sqrt(op->h_out[0] / op->h_out[1]);
+    return status;
+}
+
+// ---- FP64 refinement around an FP32 inner BiCGStab ------------------------------------------
+template <typename Tc>
+int solve_ir(eg_operator *op, const OpView<Tc> &A32, const double *b, double *x, double tol, int maxit)
+{
+    int rc;
+    if ((rc = ensure_work(op, op->w32))) return rc;
+    Work<float> &w = op->w32;
+    hipStream_t s = op->stream;
+    int total = 0, outer = 0, status = EG_MAXIT, stalls = 0, restarts = 0;
+    double rel_prev = INFINITY;
+    for (;;) {
+        int nr = 0;
+        launch_residual<float>(op->view64(), b, x, w.r, op->partials, &nr, s);
+        launch_finalize(FIN_SUM, op->partials, nr, op->sc, nullptr, op->d_out, 0, 0, s);
+        EG_HIP(hipMemcpyAsync(op->h_out, op->d_out, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
+        EG_HIP(hipStreamSynchronize(s));
+        const double rr = op->h_out[0], bb = op->h_out[1];
+        if (bb == 0.0) {
+            launch_fill<double>(x, op->n, 0.0, s);
+            EG_HIP(hipStreamSynchronize(s));
+            op->info.true_rel_residual = 0.0;
+            status = EG_CONVERGED;
+            break;
+        }
+        const double rel = std::sqrt(rr / bb);
+        op->info.true_rel_residual = rel;
+        if (rel <= tol) { status = EG_CONVERGED; break; }
+        if (total >= maxit) { status = EG_MAXIT; break; }
+        if (outer >= op->max_outer) { status = EG_STALLED; break; }
+        if (rel > 0.5 * rel_prev) {
+            if (++stalls >= 2) { status = EG_STALLED; break; }
+        } else {
+            stalls = 0;
+        }
+        rel_prev = rel;
+        // inner solve  A32 d = r32  to relative tolerance eta (no tighter than this step needs)
+        const double eta = std::max(op->eta, 0.25 * tol / rel);
+        if ((rc = put_run_params(op, eta, maxit - total, total, op->restart_every))) return rc;
+        launch_finalize(FIN_INIT, op->partials, nr, op->sc, op->d_hist, nullptr, 2, 2, s);
+        launch_fill<float>(w.x, op->n, 0.0f, s);
+        EG_HIP(hipGetLastError());
+        if ((rc = krylov_run<float, Tc>(op, A32, w))) return rc;
+        total += op->h_sc->iter;
+        restarts += op->h_sc->restarts;
+        launch_add_correction(op->n, x, w.x, s);
+        EG_HIP(hipGetLastError());
+        ++outer;
+    }
+    op->info.iterations = total;
+    op->info.outer_steps = outer;
+    op->info.restarts = restarts;
+    op->hist_count = total;
+    return status;
+}
+
+}  // namespace
+
+// =============================================================================================
+// C ABI
+// =============================================================================================
+extern "C" {
+
+const char *eg_last_error(void) { return g_err.c_str(); }
+
+void eg_destroy_operator(eg_operator *op)
+{
+    if (!op) return;
+    (void)hipStreamSynchronize(op->stream);
+    dfree(op->a64); dfree(op->m64); dfree(op->g64);
+    dfree(op->a32); dfree(op->m32); dfree(op->g32);
+    for (int i = 0; i < 2; ++i) { dfree(op->aq[i]); dfree(op->gq[i]); dfree(op->qs[i]); }
+    for (Work<double> *w : {&op->w64}) {
+        dfree(w->r); dfree(w->rh); dfree(w->p); dfree(w->ph); dfree(w->v); dfree(w->s); dfree(w->sh);
+        dfree(w->t); dfree(w->x); dfree(w->scr);
+    }
+    for (Work<float> *w : {&op->w32}) {
+        dfree(w->r); dfree(w->rh); dfree(w->p); dfree(w->ph); dfree(w->v); dfree(w->s); dfree(w->sh);
+        dfree(w->t); dfree(w->x); dfree(w->scr);
+    }
+    dfree(op->partials); dfree(op->sc); dfree(op->d_out); dfree(op->d_bad); dfree(op->d_hist);
+    if (op->h_sc) (void)hipHostFree(op->h_sc);
+    if (op->h_out) (void)hipHostFree(op->h_out);
+    delete op;
+}
+
+int eg_create_operator(const double *coeffs, int nlon, int nlat, int nlev, eg_operator **out)
+{
+    if (!out) return fail(EG_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!coeffs) return fail(EG_EINVAL, "coeffs is NULL");
+    if (nlon < 3 || nlat < 1 || nlev < 1) return fail(EG_EINVAL, "need nlon >= 3, nlat >= 1, nlev >= 1");
+    const long P = (long)nlon * nlat;
+    const long n = P * nlev;
+    if (n > (1L << 40)) return fail(EG_EINVAL, "grid too large");
+    eg_operator *op = new eg_operator();
+    op->nlon = nlon; op->nlat = nlat; op->nlev = nlev; op->P = P; op->n = n;
+    int rc = 0;
+    auto bail = [&](int code) { eg_destroy_operator(op); return code; };
+    if ((rc = dalloc(&op->a64, 6 * (size_t)n)) || (rc = dalloc(&op->m64, (size_t)n)) ||
+        (rc = dalloc(&op->g64, (size_t)n)) ||
+        (rc = dalloc(&op->partials, (size_t)partial_rows_needed(nlon, nlat, nlev) * kPartialCols)) ||
+        (rc = dalloc(&op->sc, 1)) || (rc = dalloc(&op->d_out, 4)) || (rc = dalloc(&op->d_bad, 4)))
+        return bail(rc);
+    if (hipHostMalloc(reinterpret_cast<void **>(&op->h_sc), sizeof(Scalars)) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void **>(&op->h_out), 4 * sizeof(double)) != hipSuccess)
+        return bail(fail(EG_ENOMEM, "hipHostMalloc failed"));
+    if ((rc = ensure_hist(op, 4096))) return bail(rc);
+    int bad[4] = {0, 0, 0, 0};
+    if (hipMemsetAsync(op->d_bad, 0, 4 * sizeof(int), op->stream) != hipSuccess) return bail(fail(EG_EHIP, "memset"));
+    launch_derive(coeffs, nlon, nlat, nlev, op->a64, op->m64, op->g64, op->d_bad, op->stream);
+    if (hipGetLastError() != hipSuccess ||
+        hipMemcpyAsync(bad, op->d_bad, sizeof(bad), hipMemcpyDeviceToHost, op->stream) != hipSuccess ||
+        hipStreamSynchronize(op->stream) != hipSuccess)
+        return bail(fail(EG_EHIP, "operator setup kernel failed"));
+    if (bad[0] || bad[1] || bad[2] || bad[3]) {
+        std::string m = "invalid operator: " + std::to_string(bad[0]) + " non-finite, " + std::to_string(bad[1]) +
+                        " negative couplings, " + std::to_string(bad[2]) + " couplings across a boundary, " +
+                        std::to_string(bad[3]) + " rows without a positive margin C - sum(a)";
+        return bail(fail(EG_EINVAL, m));
+    }
+    *out = op;
+    return 0;
+}
+
+int eg_set_stream(eg_operator *op, void *hip_stream)
+{
+    if (!op) return fail(EG_EINVAL, "op is NULL");
+    op->stream = static_cast<hipStream_t>(hip_stream);
+    return 0;
+}
+
+int eg_set_option(eg_operator *op, const char *key, double value)
+{
+    if (!op || !key) return fail(EG_EINVAL, "NULL argument");
+    const std::string k(key);
+    if (k == "eta") {
+        if (!(value > 0.0 && value < 1.0)) return fail(EG_EINVAL, "eta must be in (0, 1)");
+        op->eta = value;
+    } else if (k == "restart_every") {
+        if (value < 0) return fail(EG_EINVAL, "restart_every must be >= 0");
+        op->restart_every = (int)value;
+    } else if (k == "max_outer") {
+        if (value < 1) return fail(EG_EINVAL, "max_outer must be >= 1");
+        op->max_outer = (int)value;
+    } else if (k == "poll") {
+        if (value < 1 || value > 4096) return fail(EG_EINVAL, "poll must be in [1, 4096]");
+        op->poll = (int)value;
+    } else if (k == "graph") {
+        op->use_graph = value != 0.0;
+    } else if (k == "stall_window") {
+        if (value < 1) return fail(EG_EINVAL, "stall_window must be >= 1");
+        op->stall_window = (int)value;
+    } else {
+        return fail(EG_EINVAL, "unknown option '" + k + "'");
+    }
+    return 0;
+}
+
+int eg_get_shape(const eg_operator *op, int *nlon, int *nlat, int *nlev)
+{
+    if (!op) return fail(EG_EINVAL, "op is NULL");
+    if (nlon) *nlon = op->nlon;
+    if (nlat) *nlat = op->nlat;
+    if (nlev) *nlev = op->nlev;
+    return 0;
+}
+
+int eg_solve(eg_operator *op, const double *b, double *x, double tol, int maxit, int mode)
+{
+    if (!op || !b || !x) return fail(EG_EINVAL, "NULL argument");
+    if (!(tol > 0.0) || maxit < 1) return fail(EG_EINVAL, "need tol > 0 and maxit >= 1");
+    if (mode < EG_FP64 || mode > EG_LEARNED_FP32_IR) return fail(EG_EINVAL, "unknown mode");
+    if (mode >= EG_LEARNED_FP64) return fail(EG_ENOPC, "no learned preconditioner has been trained or loaded");
+    const auto t0 = std::chrono::steady_clock::now();
+    op->info = eg_info{};
+    op->hist_count = 0;
+    int rc;
+    if ((rc = check_vectors(op, b, x))) return rc;
+    if ((rc = ensure_hist(op, std::min(maxit, 1 << 22)))) return rc;
+    int status;
+    switch (mode) {
+    case EG_FP64:
+        status = solve_fp64(op, b, x, tol, maxit);
+        break;
+    case EG_FP32_IR:
+        if ((rc = ensure_fp32(op))) return rc;
+        status = solve_ir<float>(op, op->view32(), b, x, tol, maxit);
+        break;
+    case EG_FP32_IR_BF16:
+        if ((rc = ensure_quant(op, PBF16))) return rc;
+        status = solve_ir<bf16_t>(op, op->viewq<bf16_t>(0), b, x, tol, maxit);
+        break;
+    default:
+        if ((rc = ensure_quant(op, PFP16))) return rc;
+        status = solve_ir<fp16_t>(op, op->viewq<fp16_t>(1), b, x, tol, maxit);
+        break;
+    }
+    if (status < 0) return status;
+    // history to the host
+    const int cnt = std::min(op->hist_count, op->hist_cap);
+    op->hist_host.assign(cnt, 0.0);
+    if (cnt > 0) {
+        EG_HIP(hipMemcpyAsync(op->hist_host.data(), op->d_hist, cnt * sizeof(double), hipMemcpyDeviceToHost,
+                              op->stream));
+        EG_HIP(hipStreamSynchronize(op->stream));
+    }
+    op->info.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return status;
+}
+
+int eg_get_info(const eg_operator *op, eg_info *info)
+{
+    if (!op || !info) return fail(EG_EINVAL, "NULL argument");
+    *info = op->info;
+    return 0;
+}
+
+int eg_residual_history(const eg_operator *op, double *host_buf, int cap)
+{
+    if (!op) return fail(EG_EINVAL, "op is NULL");
+    const int cnt = (int)op->hist_host.size();
+    if (host_buf && cap > 0) std::memcpy(host_buf, op->hist_host.data(), std::min(cap, cnt) * sizeof(double));
+    return cnt;
+}
+
+int eg_apply(eg_operator *op, const void *x, void *y, int prec)
+{
+    if (!op || !x || !y) return fail(EG_EINVAL, "NULL argument");
+    int rc;
+    switch (prec) {
+    case EG_PREC_FP64:
+        launch_spmv<double, double>(op->view64(), static_cast<const double *>(x), static_cast<double *>(y), nullptr,
+                                    SP_PLAIN, op->partials, nullptr, nullptr, 0, op->stream);
+        break;
+    case EG_PREC_FP32:
+        if ((rc = ensure_fp32(op))) return rc;
+        launch_spmv<float, float>(op->view32(), static_cast<const float *>(x), static_cast<float *>(y), nullptr,
+                                  SP_PLAIN, op->partials, nullptr, nullptr, 0, op->stream);
+        break;
+    case EG_PREC_BF16:
+        if ((rc = ensure_quant(op, PBF16))) return rc;
+        launch_spmv<float, bf16_t>(op->viewq<bf16_t>(0), static_cast<const float *>(x), static_cast<float *>(y),
+                                   nullptr, SP_PLAIN, op->partials, nullptr, nullptr, 0, op->stream);
+        break;
+    case EG_PREC_FP16:
+        if ((rc = ensure_quant(op, PFP16))) return rc;
+        launch_spmv<float, fp16_t>(op->viewq<fp16_t>(1), static_cast<const float *>(x), static_cast<float *>(y),
+                                   nullptr, SP_PLAIN, op->partials, nullptr, nullptr, 0, op->stream);
+        break;
+    default:
+        return fail(EG_EINVAL, "unknown precision");
+    }
+    EG_HIP(hipGetLastError());
+    EG_HIP(hipStreamSynchronize(op->stream));
+    return 0;
+}
+
+int eg_apply_precond(eg_operator *op, const void *q, void *z, int prec)
+{
+    if (!op || !q || !z) return fail(EG_EINVAL, "NULL argument");
+    int rc;
+    if (prec == EG_PREC_FP64) {
+        if ((rc = ensure_work(op, op->w64))) return rc;
+        launch_thomas<double, double>(op->view64(), static_cast<const double *>(q), static_cast<double *>(z), TH_PLAIN,
+                                      nullptr, nullptr, nullptr, nullptr, op->w64.scr, op->partials, nullptr, nullptr,
+                                      op->stream);
+    } else {
+        if ((rc = ensure_work(op, op->w32))) return rc;
+        const float *qf = static_cast<const float *>(q);
+        float *zf = static_cast<float *>(z);
+        switch (prec) {
+        case EG_PREC_FP32:
+            if ((rc = ensure_fp32(op))) return rc;
+            launch_thomas<float, float>(op->view32(), qf, zf, TH_PLAIN, nullptr, nullptr, nullptr, nullptr,
+                                        op->w32.scr, op->partials, nullptr, nullptr, op->stream);
+            break;
+        case EG_PREC_BF16:
+            if ((rc = ensure_quant(op, PBF16))) return rc;
+            launch_thomas<float, bf16_t>(op->viewq<bf16_t>(0), qf, zf, TH_PLAIN, nullptr, nullptr, nullptr, nullptr,
+                                         op->w32.scr, op->partials, nullptr, nullptr, op->stream);
+            break;
+        case EG_PREC_FP16:
+            if ((rc = ensure_quant(op, PFP16))) return rc;
+            launch_thomas<float, fp16_t>(op->viewq<fp16_t>(1), qf, zf, TH_PLAIN, nullptr, nullptr, nullptr, nullptr,
+                                         op->w32.scr, op->partials, nullptr, nullptr, op->stream);
+            break;
+        default:
+            return fail(EG_EINVAL, "unknown precision");
+        }
+    }
+    EG_HIP(hipGetLastError());
+    EG_HIP(hipStreamSynchronize(op->stream));
+    return 0;
+}
+
+int eg_residual(eg_operator *op, const double *b, const double *x, double *r, double *rel_host)
+{
+    if (!op || !b || !x) return fail(EG_EINVAL, "NULL argument");
+    int nr, rc;
+    if ((rc = true_residual<double>(op, b, x, r, &nr))) return rc;
+    if (rel_host) *rel_host = op->h_out[1] > 0.0 ? std::sqrt(op->h_out[0] / op->h_out[1]) : 0.0;
+    return 0;
+}
+
+int eg_dot(eg_operator *op, const void *a, const void *b, long n, int prec, double *out_host)
+{
+    if (!op || !a || !b || !out_host || n < 0) return fail(EG_EINVAL, "bad argument");
+    int nr = 0;
+    if (prec == EG_PREC_FP64)
+        launch_dot<double, double>(n, static_cast<const double *>(a), static_cast<const double *>(b), op->partials, &nr,
+                                   op->stream);
+    else
+        launch_dot<float, float>(n, static_cast<const float *>(a), static_cast<const float *>(b), op->partials, &nr,
+                                 op->stream);
+    launch_finalize(FIN_SUM, op->partials, nr, op->sc, nullptr, op->d_out, 0, 0, op->stream);
+    EG_HIP(hipGetLastError());
+    EG_HIP(hipMemcpyAsync(op->h_out, op->d_out, 4 * sizeof(double), hipMemcpyDeviceToHost, op->stream));
+    EG_HIP(hipStreamSynchronize(op->stream));
+    *out_host = op->h_out[0];
+    return 0;
+}
+
+}  // extern "C"

@@ -1,0 +1,178 @@
+"""Solver parity: the HIP BiCGStab against the CPU oracle, in every precision mode, plus special
+cases, failure paths and determinism."""
+import numpy as np
+import pytest
+
+import synth
+from tests.helpers import dev, host
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def eg():
+    import torch
+    import paper_1811_03852_amd as eg
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    eg.load_library()
+    return eg
+
+
+@pytest.fixture(scope="module")
+def c1(oracle_mod):
+    """The small configuration and its oracle solution at tol 1e-12."""
+    p = synth.CONFIGS["c1"]
+    coef = synth.make_coeffs(p)
+    b = synth.make_rhs(p).ravel()
+    x_ref, info = oracle_mod.bicgstab(coef, b, tol=1e-12)
+    assert info.status == 0
+    return p, coef, b, x_ref, info
+
+
+def _true_rel(oracle_mod, coef, b, x):
+    return np.linalg.norm(b - oracle_mod.apply(coef, x)) / np.linalg.norm(b)
+
+
+def test_fp64_parity_tight_tolerance(eg, oracle_mod, c1):
+    """Both solvers at tol 1e-12: the GPU x matches the oracle x to 1e-10 relative L2."""
+    import torch
+    p, coef, b, x_ref, info_ref = c1
+    with eg.Operator(dev(coef)) as op:
+        x = torch.zeros(p.n, dtype=torch.float64, device="cuda")
+        info = op.solve(dev(b), x, tol=1e-12, maxit=5000, mode=eg.FP64)
+        xh = host(x)
+        assert info.status == eg.CONVERGED
+        assert _true_rel(oracle_mod, coef, b, xh) <= 1e-12
+        err = np.linalg.norm(xh - x_ref) / np.linalg.norm(x_ref)
+        assert err <= 1e-10, err
+        # the two iterations follow the same recurrences: counts agree closely
+        assert abs(info.iterations - info_ref.iterations) <= max(3, info_ref.iterations // 10)
+        hist = op.history()
+        assert len(hist) == info.iterations and hist[-1] <= 1e-12
+
+
+@pytest.mark.parametrize("p", [synth.Problem(67, 13, 9, seed=1), synth.Problem(130, 37, 5, seed=2),
+                               synth.Problem(40, 30, 24, seed=5, shift=1e-6, bands=True, ratio=synth._c5_ratio()),
+                               synth.Problem(64, 16, 70, seed=4)],
+                         ids=lambda p: f"{p.nlon}x{p.nlat}x{p.nlev}")
+def test_fp64_parity_shapes(eg, oracle_mod, p):
+    import torch
+    coef = synth.make_coeffs(p)
+    b = synth.make_rhs(p).ravel()
+    tol = 1e-12 if p.shift >= 1e-3 else 1e-10
+    x_ref, info_ref = oracle_mod.bicgstab(coef, b, tol=tol)
+    with eg.Operator(dev(coef)) as op:
+        x = torch.zeros(p.n, dtype=torch.float64, device="cuda")
+        info = op.solve(dev(b), x, tol=tol, maxit=20000, mode=eg.FP64)
+        assert info.status == eg.CONVERGED
+        xh = host(x)
+        assert _true_rel(oracle_mod, coef, b, xh) <= tol
+        err = np.linalg.norm(xh - x_ref) / np.linalg.norm(x_ref)
+        assert err <= (1e-10 if p.shift >= 1e-3 else 1e-7), err
+
+
+@pytest.mark.parametrize("mode_name", ["FP64", "FP32_IR", "FP32_IR_BF16", "FP32_IR_FP16"])
+def test_modes_reach_1e8_true_residual(eg, oracle_mod, c1, mode_name):
+    """Every precision mode reaches ||b - A x|| / ||b|| <= 1e-8, checked by the oracle's FP64
+    product on the returned x; the error against the FP64 oracle solution is reported."""
+    import torch
+    p, coef, b, x_ref, _ = c1
+    with eg.Operator(dev(coef)) as op:
+        x = torch.zeros(p.n, dtype=torch.float64, device="cuda")
+        info = op.solve(dev(b), x, tol=1e-8, maxit=20000, mode=getattr(eg, mode_name))
+        xh = host(x)
+        assert info.status == eg.CONVERGED, info
+        rel = _true_rel(oracle_mod, coef, b, xh)
+        assert rel <= 1e-8 and abs(rel - info.true_rel_residual) <= 1e-10
+        err = np.linalg.norm(xh - x_ref) / np.linalg.norm(x_ref)
+        print(f"{mode_name}: iterations {info.iterations} outer {info.outer_steps} true R {rel:.3e} "
+              f"error vs oracle {err:.3e}")
+        assert err <= 1e-5
+        if mode_name != "FP64":
+            assert info.outer_steps >= 1
+
+
+def test_refinement_outer_residuals_fall_by_eta(eg, oracle_mod, c1):
+    """Each FP64 refinement step reduces the true residual by at least 10x."""
+    import torch
+    p, coef, b, _, _ = c1
+    with eg.Operator(dev(coef)) as op:
+        op.set_option("eta", 1e-3)
+        x = torch.zeros(p.n, dtype=torch.float64, device="cuda")
+        rels = []
+        for k in range(1, 4):
+            op.set_option("max_outer", k)
+            x.zero_()
+            info = op.solve(dev(b), x, tol=1e-14, maxit=20000, mode=eg.FP32_IR)
+            rels.append(_true_rel(oracle_mod, coef, b, host(x)))
+        assert rels[1] <= 0.1 * rels[0] and rels[2] <= 0.1 * rels[1], rels
+
+
+def test_special_cases(eg, oracle_mod, c1):
+    import torch
+    p, coef, b, x_ref, _ = c1
+    with eg.Operator(dev(coef)) as op:
+        # b = 0 -> x = 0
+        x = torch.randn(p.n, dtype=torch.float64, device="cuda")
+        info = op.solve(torch.zeros(p.n, dtype=torch.float64, device="cuda"), x, 1e-8, 100, eg.FP64)
+        assert info.status == eg.CONVERGED and not torch.any(x)
+        # start at the solution -> no iteration
+        x = dev(x_ref)
+        info = op.solve(dev(b), x, 1e-8, 100, eg.FP64)
+        assert info.status == eg.CONVERGED and info.iterations == 0
+        # iteration limit
+        x = torch.zeros(p.n, dtype=torch.float64, device="cuda")
+        info = op.solve(dev(b), x, 1e-8, 5, eg.FP64)
+        assert info.status == eg.MAXIT and info.iterations == 5
+        # non-finite input
+        bad = dev(b)
+        bad[17] = float("nan")
+        with pytest.raises(eg.EndgameError) as ei:
+            op.solve(bad, torch.zeros_like(bad), 1e-8, 100, eg.FP64)
+        assert ei.value.code == eg.ENONFINITE
+        with pytest.raises(eg.EndgameError) as ei:
+            op.solve(dev(b), torch.zeros_like(bad), 1e-8, 100, eg.LEARNED_FP64)
+        assert ei.value.code == eg.ENOPC
+        with pytest.raises(eg.EndgameError):
+            op.solve(dev(b), torch.zeros_like(bad), -1.0, 100, eg.FP64)
+
+
+def test_decoupled_columns_converge_in_one_half_step(eg, oracle_mod):
+    import torch
+    p = synth.Problem(70, 20, 11, seed=8)
+    coef = synth.make_coeffs(p)
+    coef[:4] = 0.0
+    b = synth.make_rhs(p).ravel()
+    with eg.Operator(dev(coef)) as op:
+        x = torch.zeros(p.n, dtype=torch.float64, device="cuda")
+        info = op.solve(dev(b), x, 1e-12, 100, eg.FP64)
+        assert info.status == eg.CONVERGED and info.iterations == 1
+        ref = oracle_mod.thomas(coef, b)
+        assert np.max(np.abs(host(x) - ref)) <= 1e-13 * np.abs(ref).max()
+
+
+def test_periodic_restart(eg, oracle_mod, c1):
+    import torch
+    p, coef, b, x_ref, _ = c1
+    with eg.Operator(dev(coef)) as op:
+        op.set_option("restart_every", 20)
+        x = torch.zeros(p.n, dtype=torch.float64, device="cuda")
+        info = op.solve(dev(b), x, 1e-9, 20000, eg.FP64)
+        assert info.status == eg.CONVERGED and info.restarts >= (info.iterations - 1) // 20
+        assert _true_rel(oracle_mod, coef, b, host(x)) <= 1e-9
+        _, oi = oracle_mod.bicgstab(coef, b, tol=1e-9, restart_every=20)
+        assert abs(oi.iterations - info.iterations) <= max(3, oi.iterations // 10)
+
+
+def test_bitwise_deterministic(eg, c1):
+    import torch
+    p, coef, b, _, _ = c1
+    with eg.Operator(dev(coef)) as op:
+        outs = []
+        for _ in range(2):
+            for mode in (eg.FP64, eg.FP32_IR_BF16):
+                x = torch.zeros(p.n, dtype=torch.float64, device="cuda")
+                op.solve(dev(b), x, 1e-8, 20000, mode)
+                outs.append((host(x), op.history()))
+        for a, b2 in zip(outs[:2], outs[2:]):
+            assert np.array_equal(a[0], b2[0]) and np.array_equal(a[1], b2[1])
