@@ -93,8 +93,8 @@ typedef struct {
  *           S = 0 on j = 0, N = 0 on j = nlat-1, D = 0 on k = 0, U = 0 on k = nlev-1;
  *           margin m = C - (W+E+S+N+D+U) > 0 at every point (row diagonal dominance).
  *   The library copies what it needs (the caller may free coeffs after return).  It keeps
- *   FP64 couplings, the margin m and the tridiagonal's excess g = m + W + E + S + N; FP32
- *   and 16-bit copies are built on first use of a mode that needs them.
+ *   FP64 couplings, the margin m and the LU factors of the vertical tridiagonal; FP32 and
+ *   16-bit copies are built on first use of a mode that needs them.
  *   *out receives the new operator (NULL on error).
  */
 int eg_create_operator(const double *coeffs, int nlon, int nlat, int nlev, eg_operator **out);
@@ -134,6 +134,7 @@ int eg_set_stream(eg_operator *op, void *hip_stream);
  *   "poll"           iterations enqueued between host checks of the device flags [8]
  *   "graph"          1 = replay batches of iterations as HIP graphs, 0 = plain launches [1]
  *   "stall_window"   learned modes: iterations without a 2x gain that trigger fallback [20]
+ *   "profile"        1 = time every streaming kernel launch (see eg_kernel_stats) [0]
  * Returns EG_EINVAL for an unknown key or out-of-range value.
  */
 int eg_set_option(eg_operator *op, const char *key, double value);
@@ -149,8 +150,10 @@ int eg_apply(eg_operator *op, const void *x, void *y, int prec);
 
 /*
  * z = T^{-1} q with T = tridiag(-D, C, -U) per column (Sec. 2, Eq. 6-7: the vertical
- * tridiagonal that replaces the diagonal; factorised per horizontal point).  q, z: device
- * arrays of n elements (double for EG_PREC_FP64, float otherwise); may not overlap.
+ * tridiagonal that replaces the diagonal; its LU factors are precomputed per horizontal point
+ * when the operator is built).  q, z: device arrays of n elements (double for EG_PREC_FP64,
+ * float otherwise); may not overlap.  FP64 uses the FP64 factors; every other precision uses
+ * their FP32 rounding (the 16-bit modes store only the couplings of A in 16 bits).
  */
 int eg_apply_precond(eg_operator *op, const void *q, void *z, int prec);
 
@@ -166,6 +169,28 @@ int eg_residual(eg_operator *op, const double *b, const double *x, double *r, do
  * Fixed-order two-pass reduction: bitwise reproducible for a given n.
  */
 int eg_dot(eg_operator *op, const void *a, const void *b, long n, int prec, double *out_host);
+
+/*
+ * Kernel timing (tracing).  With the option "profile" set to 1, every streaming kernel launch
+ * of eg_solve that does work is bracketed by HIP events on the operator's stream and its
+ * device time is accumulated per (kernel, precision); the host then checks the device flags
+ * after every iteration so no launch is wasted.
+ *   kernel    enum eg_kernel;  prec  enum eg_prec of the vectors/couplings the launch used.
+ *   launches  host long (may be NULL): number of timed launches.
+ *   total_ms  host double (may be NULL): summed device time in milliseconds.
+ * eg_reset_kernel_stats clears all counters.
+ */
+enum eg_kernel {
+    EG_K_THOMAS_P = 0,   /* p = r + beta (p - omega v); phat = T^{-1} p                     */
+    EG_K_SPMV_V = 1,     /* v = A phat with <rhat, v>, <v, v>                               */
+    EG_K_THOMAS_S = 2,   /* s = r - alpha v; shat = T^{-1} s with <s, s>                    */
+    EG_K_SPMV_T = 3,     /* t = A shat with <t, s>, <t, t>                                  */
+    EG_K_UPDATE = 4,     /* x += alpha phat + omega shat; r = s - omega t with dots         */
+    EG_K_RESIDUAL = 5,   /* FP64 true residual r = b - A x (refinement steps)               */
+    EG_K_COUNT = 8
+};
+int eg_kernel_stats(const eg_operator *op, int kernel, int prec, long *launches, double *total_ms);
+int eg_reset_kernel_stats(eg_operator *op);
 
 /* Grid sizes of an operator (host ints; any pointer may be NULL). */
 int eg_get_shape(const eg_operator *op, int *nlon, int *nlat, int *nlev);

@@ -26,7 +26,9 @@ EINVAL, ENOMEM, EHIP, ENONFINITE, ENOPC = -1, -2, -3, -4, -5
 
 EXPORTED = ["eg_create_operator", "eg_solve", "eg_get_info", "eg_residual_history", "eg_set_stream", "eg_set_option",
             "eg_apply", "eg_apply_precond", "eg_residual", "eg_dot", "eg_get_shape", "eg_destroy_operator",
-            "eg_last_error"]
+            "eg_last_error", "eg_kernel_stats", "eg_reset_kernel_stats"]
+# enum eg_kernel
+K_THOMAS_P, K_SPMV_V, K_THOMAS_S, K_SPMV_T, K_UPDATE, K_RESIDUAL = range(6)
 
 
 class EndgameError(RuntimeError):
@@ -77,6 +79,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "eg_get_shape": ([vp, ip, ip, ip], ctypes.c_int),
         "eg_destroy_operator": ([vp], None),
         "eg_last_error": ([], ctypes.c_char_p),
+        "eg_kernel_stats": ([vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_long), dp], ctypes.c_int),
+        "eg_reset_kernel_stats": ([vp], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -192,6 +196,16 @@ class Operator:
         rel = ctypes.c_double()
         _check(_lib.eg_residual(self._h, _ptr(b), _ptr(x), None if r is None else _ptr(r), ctypes.byref(rel)))
         return rel.value
+
+    def kernel_stats(self, kernel: int, prec: int) -> tuple[int, float]:
+        """(timed launches, total device ms) of one kernel class; needs set_option("profile", 1)."""
+        cnt = ctypes.c_long()
+        ms = ctypes.c_double()
+        _check(_lib.eg_kernel_stats(self._h, int(kernel), int(prec), ctypes.byref(cnt), ctypes.byref(ms)))
+        return cnt.value, ms.value
+
+    def reset_kernel_stats(self):
+        _check(_lib.eg_reset_kernel_stats(self._h))
 
     def dot(self, a, b) -> float:
         import torch

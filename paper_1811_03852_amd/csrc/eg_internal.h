@@ -6,10 +6,9 @@
 //   m[n]     margin  C - sum(a)  (> 0): the SpMV runs in the difference form
 //            y = m x + sum_d a_d (x - x_d), which never forms C x - sum a_d x_d and so keeps
 //            the small margin exact in FP32 and 16-bit storage
-//   g[n]     tridiagonal excess  m + W + E + S + N  (= C - D - U): the Thomas sweep runs in a
-//            form whose every intermediate is a sum of non-negative terms
+//   f[3][n]  LU factors (l, inv, c) of the vertical tridiagonal T, computed once in FP64
 // 16-bit sets store a[] as BF16/FP16 bits scaled by a power of two per (direction, level,
-// latitude row) and keep m and g in FP32.
+// latitude row) and share m and the FP32 factors with the FP32 set.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -50,7 +49,8 @@ struct alignas(64) Scalars {
     int restart_every;
     int hist_base;      // first history slot of this run
     int hist_cap;
-    int pad[3];
+    int work_mask;      // streaming kernels of the last iteration that did work (bit = eg_kernel)
+    int pad[2];
 };
 
 // Views of one precision set of the operator.
@@ -62,14 +62,22 @@ struct fp16_t { uint16_t bits; };
 template <> struct CoefTraits<bf16_t> { using val = float; static constexpr bool quant = true; };
 template <> struct CoefTraits<fp16_t> { using val = float; static constexpr bool quant = true; };
 
+constexpr int kQsStride = 8;   // floats per (level, latitude row) record of 16-bit scales
+
 template <typename Tc> struct OpView {
     using V = typename CoefTraits<Tc>::val;
     const Tc *a;        // [6][n]
     const V *m;         // [n]
-    const V *g;         // [n]
-    const float *qs;    // [6][nlev][nlat] power-of-two scales (16-bit sets only)
+    const float *qs;    // [nlev][nlat][kQsStride] power-of-two scales (16-bit sets only)
     int nlon, nlat, nlev;
     long P, n;
+};
+
+// Factors of the vertical tridiagonal: f[3][n] = (l, inv, c), see k_tri_factor.
+template <typename Tv> struct TriView {
+    const Tv *f;
+    long P, n;
+    int nlev;
 };
 
 // flags a streaming kernel may be told to stop on
@@ -89,9 +97,11 @@ void launch_residual(const OpView<double> &op, const double *b, const double *x,
                      int *nrows, hipStream_t s);
 
 enum ThomasMode { TH_PLAIN = 0, TH_P = 1, TH_S = 2 };
-template <typename Tv, typename Tc>
-void launch_thomas(const OpView<Tc> &op, const Tv *q, Tv *z, int mode, Tv *r, Tv *p, const Tv *v, Tv *rhat,
-                   Tv *scratch, double *partials, int *nrows, const Scalars *sc, hipStream_t s);
+template <typename Tv>
+void launch_thomas(const TriView<Tv> &tv, const Tv *q, Tv *z, int mode, const Tv *r, Tv *p, const Tv *v, Tv *rhat,
+                   double *partials, int *nrows, const Scalars *sc, hipStream_t s);
+template <typename Tf>
+void launch_tri_factor(const double *a64, const double *m64, int nlon, int nlat, int nlev, Tf *f, hipStream_t s);
 
 template <typename Tv>
 void launch_update(long n, Tv *x, const Tv *ph, const Tv *sh, const Tv *s, const Tv *t, Tv *r, const Tv *rhat,
@@ -108,15 +118,13 @@ void launch_finalize(int stage, const double *partials, int nrows, Scalars *sc, 
 
 template <typename T> void launch_fill(T *p, long n, T v, hipStream_t s);
 void launch_add_correction(long n, double *x, const float *d, hipStream_t s);
-void launch_copy_f64_to_f32(long n, const double *src, float *dst, hipStream_t s);
 
 // operator setup
-void launch_derive(const double *coeffs, int nlon, int nlat, int nlev, double *a64, double *m64, double *g64,
-                   int *bad, hipStream_t s);
-void launch_to_fp32(long n, const double *a64, const double *m64, const double *g64, float *a32, float *m32,
-                    float *g32, hipStream_t s);
-void launch_quantize(int kind, int nlon, int nlat, int nlev, const double *a64, const double *m64, uint16_t *aq,
-                     float *qs, float *gq, hipStream_t s);
+void launch_derive(const double *coeffs, int nlon, int nlat, int nlev, double *a64, double *m64, int *bad,
+                   hipStream_t s);
+void launch_to_fp32(long n, const double *a64, const double *m64, float *a32, float *m32, hipStream_t s);
+void launch_quantize(int kind, int nlon, int nlat, int nlev, const double *a64, uint16_t *aq, float *qs,
+                     hipStream_t s);
 void launch_check_finite(long n, const double *v, int *bad, hipStream_t s);
 
 }  // namespace eg

@@ -12,6 +12,7 @@
 // results are bitwise reproducible for a given grid.
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 
 #include "eg_internal.h"
 
@@ -114,7 +115,8 @@ __global__ __launch_bounds__(kWG) void k_spmv(OpView<Tc> op, const Tv *__restric
         const int rest = t / gx;
         const int by = rest % gy;
         const int bz = rest / gy;
-        const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+        const int lane = threadIdx.x & 63;
+        const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
         const int i = bx * 64 + lane;
         const bool iv = i < nlon;
         const int ic = iv ? i : nlon - 1;
@@ -161,14 +163,15 @@ __global__ __launch_bounds__(kWG) void k_spmv(OpView<Tc> op, const Tv *__restric
                 const Tv xnn = (r == R - 1) ? hn : xc[r + 1];
                 float s0 = 1.f, s1 = 1.f, s2 = 1.f, s3 = 1.f, s4 = 1.f, s5 = 1.f;
                 if constexpr (Q) {
-                    const long qb = (long)k * nlat + jc[r];
-                    const long qd = (long)nlev * nlat;
-                    s0 = op.qs[qb];
-                    s1 = op.qs[qb + qd];
-                    s2 = op.qs[qb + 2 * qd];
-                    s3 = op.qs[qb + 3 * qd];
-                    s4 = op.qs[qb + 4 * qd];
-                    s5 = op.qs[qb + 5 * qd];
+                    // the row's six scales: one wave-uniform 32-byte record
+                    const float4 *qr = reinterpret_cast<const float4 *>(op.qs + ((long)k * nlat + jc[r]) * kQsStride);
+                    const float4 q0 = qr[0], q1 = qr[1];
+                    s0 = q0.x;
+                    s1 = q0.y;
+                    s2 = q0.z;
+                    s3 = q0.w;
+                    s4 = q1.x;
+                    s5 = q1.y;
                 }
                 const V aW = Dec<Tc>::get(op.a, c, s0);
                 const V aE = Dec<Tc>::get(op.a, c + n, s1);
@@ -235,10 +238,12 @@ static SpmvGrid spmv_grid(int nlon, int nlat, int nlev)
     return g;
 }
 
+constexpr int kSpmvRows = 2;   // latitude rows per thread
+
 int partial_rows_needed(int nlon, int nlat, int nlev)
 {
     const long P = (long)nlon * nlat;
-    long rows = spmv_grid<4>(nlon, nlat, nlev).nblocks;
+    long rows = spmv_grid<kSpmvRows>(nlon, nlat, nlev).nblocks;
     rows = std::max(rows, (P + kWG - 1) / kWG);   // thomas(S): one row per workgroup of columns
     rows = std::max(rows, 8192L);                 // elementwise kernels
     return (int)rows;
@@ -248,7 +253,7 @@ template <typename Tv, typename Tc>
 int launch_spmv_impl(const OpView<Tc> &op, const Tv *x, Tv *y, const Tv *w, int mode, double *partials,
                      const Scalars *sc, int stop_mask, hipStream_t s)
 {
-    constexpr int R = 4;
+    constexpr int R = kSpmvRows;
     SpmvGrid g = spmv_grid<R>(op.nlon, op.nlat, op.nlev);
     if (mode == SP_DOT2)
         hipLaunchKernelGGL((k_spmv<Tv, Tc, R, SPM_DOT2, Tv>), dim3(g.nblocks), dim3(kWG), 0, s, op, x, y, w, partials,
@@ -271,7 +276,7 @@ template <typename Tout>
 void launch_residual(const OpView<double> &op, const double *b, const double *x, Tout *r, double *partials,
                      int *nrows, hipStream_t s)
 {
-    constexpr int R = 4;
+    constexpr int R = kSpmvRows;
     SpmvGrid g = spmv_grid<R>(op.nlon, op.nlat, op.nlev);
     hipLaunchKernelGGL((k_spmv<double, double, R, SPM_RESID, Tout>), dim3(g.nblocks), dim3(kWG), 0, s, op, x, r, b,
                        partials, nullptr, 0, g.gx, g.gy, g.kchunk, g.ntiles, g.per_xcd);
@@ -279,44 +284,75 @@ void launch_residual(const OpView<double> &op, const double *b, const double *x,
 }
 
 // ------------------------------------------------------------------------------------------
-// k_thomas: per-column tridiagonal solve T z = q, T = tridiag(-aD, g + aD + aU, -aU).
+// Thomas factors of T = tridiag(-aD, C, -aU), computed once per operator (the paper notes the
+// LU factorisation of T can be precomputed per horizontal point).  With
+//   den_k = C_k - aD_k aU_{k-1} / den_{k-1},  inv_k = 1 / den_k,
+//   l_k = aD_k inv_{k-1}  (l_0 = 0),          c_k = aU_k inv_k,
+// the solve is  w_k = q_k + l_k w_{k-1}  (forward)  and  z_k = inv_k w_k + c_k z_{k+1}  (back).
+// den_k is evaluated through the excess e_k = den_k - aU_k = g_k + aD_k e_{k-1} / den_{k-1},
+// g = m + W + E + S + N, in FP64: every term is non-negative, so no cancellation occurs even
+// where the horizontal coupling is tiny next to the vertical one.  f[3][n] = (l, inv, c).
+// ------------------------------------------------------------------------------------------
+template <typename Tf>
+__global__ __launch_bounds__(kWG) void k_tri_factor(const double *__restrict__ a64, const double *__restrict__ m64,
+                                                    int nlon, int nlat, int nlev, Tf *__restrict__ f)
+{
+    const long P = (long)nlon * nlat;
+    const long n = P * nlev;
+    const long col = (long)blockIdx.x * kWG + threadIdx.x;
+    if (col >= P) return;
+    double ratio = 0.0, inv_prev = 0.0;
+    for (int k = 0; k < nlev; ++k) {
+        const long c = col + (long)k * P;
+        const double g = m64[c] + (((a64[c] + a64[n + c]) + a64[2 * n + c]) + a64[3 * n + c]);
+        const double aD = a64[4 * n + c], aU = a64[5 * n + c];
+        const double e = g + aD * ratio;
+        const double den = e + aU;
+        const double inv = 1.0 / den;
+        f[c] = static_cast<Tf>(aD * inv_prev);
+        f[n + c] = static_cast<Tf>(inv);
+        f[2 * n + c] = static_cast<Tf>(aU * inv);
+        ratio = e * inv;
+        inv_prev = inv;
+    }
+}
+
+template <typename Tf>
+void launch_tri_factor(const double *a64, const double *m64, int nlon, int nlat, int nlev, Tf *f, hipStream_t s)
+{
+    const long P = (long)nlon * nlat;
+    hipLaunchKernelGGL((k_tri_factor<Tf>), dim3((unsigned)((P + kWG - 1) / kWG)), dim3(kWG), 0, s, a64, m64, nlon,
+                       nlat, nlev, f);
+}
+
+// ------------------------------------------------------------------------------------------
+// k_thomas: z = T^{-1} q per column from the precomputed factors.
 //
-// Elimination  z_k = y_k + c_k z_{k+1}  with den_k = C_k - aD_k c_{k-1}.  Written through the
-// excess e_k = den_k - aU_k, which obeys e_k = g_k + aD_k e_{k-1} / den_{k-1}: every quantity
-// is a sum of non-negative terms, so the sweep has no cancellation even where the horizontal
-// coupling (and hence g) is tiny next to the vertical one.
-//
-// One lane per column; lane -> column index col = j*nlon + i, so each level's load is a
-// contiguous run of the plane.  NL > 0: exactly NL levels, factors held in registers.  NL == 0:
-// any nlev, the forward sweep parks y_k in z and c_k in `scratch` and the backward sweep
-// re-reads them.
+// One lane per column; lane -> column col = j*nlon + i, so each level's load is a contiguous
+// run of the plane.  NL > 0: exactly NL levels, the forward values w_k held in registers.
+// NL == 0: any nlev, w_k parked in z between the sweeps.
 //
 // Prologues: TH_PLAIN  q read from `q`;
 //            TH_P      q = r + beta (p - omega v), stored to p (on a restart q = r and rhat = r);
 //            TH_S      q = r - alpha v, stored to s (passed as `p`), ||q||^2 partial.
 // ------------------------------------------------------------------------------------------
-template <typename Tv, typename Tc, int NL, int MODE>
-__global__ __launch_bounds__(kWG) void k_thomas(OpView<Tc> op, const Tv *__restrict__ q, Tv *__restrict__ z,
+template <typename Tv, int NL, int MODE, int PF = 8>
+__global__ __launch_bounds__(kWG) void k_thomas(TriView<Tv> tv, const Tv *__restrict__ q, Tv *__restrict__ z,
                                                 const Tv *__restrict__ r, Tv *__restrict__ p,
                                                 const Tv *__restrict__ v, Tv *__restrict__ rhat,
-                                                Tv *__restrict__ scratch, double *__restrict__ partials,
-                                                const Scalars *__restrict__ sc, int stop_mask)
+                                                double *__restrict__ partials, const Scalars *__restrict__ sc,
+                                                int stop_mask)
 {
     if (stopped(sc, stop_mask)) return;
-    using V = typename CoefTraits<Tc>::val;
-    constexpr bool Q = CoefTraits<Tc>::quant;
-    const long P = op.P, n = op.n;
-    const int nlev = (NL > 0) ? NL : op.nlev;
+    const long P = tv.P, n = tv.n;
+    const int nlev = (NL > 0) ? NL : tv.nlev;
     const long col = (long)blockIdx.x * kWG + threadIdx.x;
     const bool act = col < P;
-    const long cc = act ? col : P - 1;
-    const Tc *aDp = op.a + 4 * n;
-    const Tc *aUp = op.a + 5 * n;
-    long qrow = 0, qd = 0;
-    if constexpr (Q) {
-        qrow = cc / op.nlon;              // latitude row of this column
-        qd = (long)op.nlev * op.nlat;
-    }
+    // 32-bit lane offset within a level plane; per-level bases below are wave-uniform
+    const unsigned cu = static_cast<unsigned>(act ? col : P - 1);
+    const Tv *lf = tv.f;
+    const Tv *invf = tv.f + n;
+    const Tv *cf = tv.f + 2 * n;
     Tv beta = 0, omega = 0, alpha = 0;
     int fresh = 0;
     if constexpr (MODE == TH_P) {
@@ -326,130 +362,179 @@ __global__ __launch_bounds__(kWG) void k_thomas(OpView<Tc> op, const Tv *__restr
     }
     if constexpr (MODE == TH_S) alpha = static_cast<Tv>(sc->alpha);
     double acc[1] = {0.0};
-
-    auto qval = [&](long c) -> Tv {
-        Tv qk;
-        if constexpr (MODE == TH_PLAIN) {
-            qk = q[c];
-        } else if constexpr (MODE == TH_P) {
-            const Tv rk = r[c];
-            if (fresh) {
-                qk = rk;
-                if (act) rhat[c] = rk;
-            } else {
-                qk = rk + beta * (p[c] - omega * v[c]);
-            }
-            if (act) p[c] = qk;
-        } else {
-            qk = r[c] - alpha * v[c];
-            if (act) {
-                p[c] = qk;
-                acc[0] += static_cast<double>(qk) * static_cast<double>(qk);
-            }
-        }
-        return qk;
-    };
-    auto coefs = [&](long c, int k, V &aD, V &aU, V &g) {
-        float sD = 1.f, sU = 1.f;
-        if constexpr (Q) {
-            sD = op.qs[4 * qd + (long)k * op.nlat + qrow];
-            sU = op.qs[5 * qd + (long)k * op.nlat + qrow];
-        }
-        aD = Dec<Tc>::get(aDp, c, sD);
-        aU = Dec<Tc>::get(aUp, c, sU);
-        g = op.g[c];
-    };
+    auto lv = [&](auto *base, int k) { return base + (size_t)k * (size_t)P; };
 
     if constexpr (NL > 0) {
-        Tv cf[NL], yv[NL];
-        Tv ratio = 0, yprev = 0;
+        // Register path (the launcher guarantees P % kWG == 0, so every lane owns a column,
+        // and n * sizeof(Tv) < 2^32, so level offsets fit 32-bit byte offsets from the
+        // wave-uniform array bases).  Software pipeline: the loads of level k + PF are issued
+        // while level k is computed, into a ring of PF register slots; the scheduling fences
+        // stop the compiler from hoisting all levels' loads (which would exhaust registers).
+        const uint32_t step = static_cast<uint32_t>(P * sizeof(Tv));
+        const uint32_t bo0 = cu * static_cast<uint32_t>(sizeof(Tv));
+        auto ld = [](const Tv *base, uint32_t bo) {
+            return *reinterpret_cast<const Tv *>(reinterpret_cast<const char *>(base) + bo);
+        };
+        auto st = [](Tv *base, uint32_t bo, Tv val) {
+            *reinterpret_cast<Tv *>(reinterpret_cast<char *>(base) + bo) = val;
+        };
+        Tv w[NL];
+        auto sweep = [&](auto fresh_c) {
+            constexpr bool F = decltype(fresh_c)::value;
+            Tv b0[PF], b1[PF], b2[PF], bl[PF];
+            uint32_t bl_off = bo0;   // next level to load
+            auto issue = [&](int sl) {
+                if constexpr (MODE == TH_PLAIN) {
+                    b0[sl] = ld(q, bl_off);
+                } else if constexpr (MODE == TH_P) {
+                    b0[sl] = ld(r, bl_off);
+                    if constexpr (!F) {
+                        b1[sl] = ld(p, bl_off);
+                        b2[sl] = ld(v, bl_off);
+                    }
+                } else {
+                    b0[sl] = ld(r, bl_off);
+                    b2[sl] = ld(v, bl_off);
+                }
+                bl[sl] = ld(lf, bl_off);
+                bl_off += step;
+            };
 #pragma unroll
-        for (int k = 0; k < NL; ++k) {
-            const long c = cc + (long)k * P;
-            const Tv qk = qval(c);
-            V aD, aU, g;
-            coefs(c, k, aD, aU, g);
-            const Tv e = g + aD * ratio;
-            const Tv den = e + aU;
-            const Tv inv = Tv(1) / den;
-            cf[k] = aU * inv;
-            yv[k] = (qk + aD * yprev) * inv;
-            ratio = e * inv;
-            yprev = yv[k];
+            for (int k = 0; k < PF && k < NL; ++k) issue(k);
+            uint32_t bo = bo0;
+            Tv wprev = 0;
+            double ss = 0.0;
+#pragma unroll
+            for (int k = 0; k < NL; ++k) {
+                const int sl = k % PF;
+                Tv qk;
+                if constexpr (MODE == TH_PLAIN) {
+                    qk = b0[sl];
+                } else if constexpr (MODE == TH_P) {
+                    if constexpr (F) {
+                        qk = b0[sl];
+                        st(rhat, bo, qk);
+                    } else {
+                        qk = b0[sl] + beta * (b1[sl] - omega * b2[sl]);
+                    }
+                    st(p, bo, qk);
+                } else {
+                    qk = b0[sl] - alpha * b2[sl];
+                    st(p, bo, qk);
+                    ss = fma(static_cast<double>(qk), static_cast<double>(qk), ss);
+                    // empty asm: pins the accumulation to this level (otherwise the compiler
+                    // sinks all the FP64 products to the end and keeps NL values live)
+                    asm volatile("" : "+v"(ss));
+                }
+                w[k] = qk + bl[sl] * wprev;
+                wprev = w[k];
+                bo += step;
+                if (k + PF < NL) issue(sl);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            if constexpr (MODE == TH_S) acc[0] = ss;
+        };
+        if (MODE == TH_P && fresh)
+            sweep(std::integral_constant<bool, true>{});
+        else
+            sweep(std::integral_constant<bool, false>{});
+        Tv bi[PF], bc[PF];
+        uint32_t bl_off = bo0 + static_cast<uint32_t>(NL - 1) * step;
+#pragma unroll
+        for (int j = 0; j < PF && j < NL; ++j) {
+            bi[j] = ld(invf, bl_off);
+            bc[j] = ld(cf, bl_off);
+            bl_off -= step;
         }
+        uint32_t bo = bo0 + static_cast<uint32_t>(NL - 1) * step;
         Tv zz = 0;
 #pragma unroll
         for (int k = NL - 1; k >= 0; --k) {
-            zz = yv[k] + cf[k] * zz;
-            if (act) z[cc + (long)k * P] = zz;
+            const int sl = (NL - 1 - k) % PF;
+            zz = bi[sl] * w[k] + bc[sl] * zz;
+            st(z, bo, zz);
+            bo -= step;
+            if (k - PF >= 0) {
+                bi[sl] = ld(invf, bl_off);
+                bc[sl] = ld(cf, bl_off);
+                bl_off -= step;
+            }
+            __builtin_amdgcn_sched_barrier(0);
         }
     } else {
-        Tv ratio = 0, yprev = 0;
+        Tv wprev = 0;
         for (int k = 0; k < nlev; ++k) {
-            const long c = cc + (long)k * P;
-            const Tv qk = qval(c);
-            V aD, aU, g;
-            coefs(c, k, aD, aU, g);
-            const Tv e = g + aD * ratio;
-            const Tv den = e + aU;
-            const Tv inv = Tv(1) / den;
-            const Tv ck = aU * inv;
-            const Tv yk = (qk + aD * yprev) * inv;
-            ratio = e * inv;
-            yprev = yk;
-            if (act) {
-                z[c] = yk;
-                scratch[c] = ck;
+            Tv qk;
+            if constexpr (MODE == TH_PLAIN) {
+                qk = lv(q, k)[cu];
+            } else if constexpr (MODE == TH_P) {
+                const Tv rk = lv(r, k)[cu];
+                if (fresh) {
+                    qk = rk;
+                    if (act) lv(rhat, k)[cu] = rk;
+                } else {
+                    qk = rk + beta * (lv(p, k)[cu] - omega * lv(v, k)[cu]);
+                }
+                if (act) lv(p, k)[cu] = qk;
+            } else {
+                qk = lv(r, k)[cu] - alpha * lv(v, k)[cu];
+                if (act) {
+                    lv(p, k)[cu] = qk;
+                    acc[0] += static_cast<double>(qk) * static_cast<double>(qk);
+                }
             }
+            wprev = qk + lv(lf, k)[cu] * wprev;
+            if (act) lv(z, k)[cu] = wprev;
         }
-        Tv zz = 0;
-        for (int k = nlev - 1; k >= 0; --k) {
-            const long c = cc + (long)k * P;
-            if (act) {
-                zz = z[c] + scratch[c] * zz;
-                z[c] = zz;
+        if (act) {
+            Tv zz = 0;
+            for (int k = nlev - 1; k >= 0; --k) {
+                zz = lv(invf, k)[cu] * lv(z, k)[cu] + lv(cf, k)[cu] * zz;
+                lv(z, k)[cu] = zz;
             }
         }
     }
     if constexpr (MODE == TH_S) block_sum_store<1>(acc, partials + (long)blockIdx.x * kPartialCols);
 }
 
-template <typename Tv, typename Tc, int NL>
-static int thomas_dispatch_mode(const OpView<Tc> &op, const Tv *q, Tv *z, int mode, Tv *r, Tv *p, const Tv *v,
-                                Tv *rhat, Tv *scratch, double *partials, const Scalars *sc, hipStream_t s)
+template <typename Tv, int NL>
+static int thomas_dispatch_mode(const TriView<Tv> &tv, const Tv *q, Tv *z, int mode, const Tv *r, Tv *p,
+                                const Tv *v, Tv *rhat, double *partials, const Scalars *sc, hipStream_t s)
 {
-    const int nb = (int)((op.P + kWG - 1) / kWG);
+    const int nb = (int)((tv.P + kWG - 1) / kWG);
     switch (mode) {
     case TH_P:
-        hipLaunchKernelGGL((k_thomas<Tv, Tc, NL, TH_P>), dim3(nb), dim3(kWG), 0, s, op, q, z, r, p, v, rhat, scratch,
-                           partials, sc, STOP_DONE);
+        hipLaunchKernelGGL((k_thomas<Tv, NL, TH_P>), dim3(nb), dim3(kWG), 0, s, tv, q, z, r, p, v, rhat, partials, sc,
+                           STOP_DONE);
         return 0;
     case TH_S:
-        hipLaunchKernelGGL((k_thomas<Tv, Tc, NL, TH_S>), dim3(nb), dim3(kWG), 0, s, op, q, z, r, p, v, rhat, scratch,
-                           partials, sc, STOP_DONE | STOP_SKIP);
+        hipLaunchKernelGGL((k_thomas<Tv, NL, TH_S>), dim3(nb), dim3(kWG), 0, s, tv, q, z, r, p, v, rhat, partials, sc,
+                           STOP_DONE | STOP_SKIP);
         return nb;
     default:
-        hipLaunchKernelGGL((k_thomas<Tv, Tc, NL, TH_PLAIN>), dim3(nb), dim3(kWG), 0, s, op, q, z, r, p, v, rhat,
-                           scratch, partials, sc, 0);
+        hipLaunchKernelGGL((k_thomas<Tv, NL, TH_PLAIN>), dim3(nb), dim3(kWG), 0, s, tv, q, z, r, p, v, rhat, partials,
+                           sc, 0);
         return 0;
     }
 }
 
-template <typename Tv, typename Tc>
-void launch_thomas(const OpView<Tc> &op, const Tv *q, Tv *z, int mode, Tv *r, Tv *p, const Tv *v, Tv *rhat,
-                   Tv *scratch, double *partials, int *nrows, const Scalars *sc, hipStream_t s)
+template <typename Tv>
+void launch_thomas(const TriView<Tv> &tv, const Tv *q, Tv *z, int mode, const Tv *r, Tv *p, const Tv *v, Tv *rhat,
+                   double *partials, int *nrows, const Scalars *sc, hipStream_t s)
 {
     int rows;
-    // Register-resident sweeps for the level counts in use, as long as the factors of a
-    // column fit in registers without spilling (70 FP64 levels do not); any other case takes
-    // the generic path.
-    constexpr bool wide = sizeof(Tv) == 8;
-    if (op.nlev == 20)
-        rows = thomas_dispatch_mode<Tv, Tc, 20>(op, q, z, mode, r, p, v, rhat, scratch, partials, sc, s);
-    else if (op.nlev == 70 && !wide)
-        rows = thomas_dispatch_mode<Tv, Tc, (wide ? 0 : 70)>(op, q, z, mode, r, p, v, rhat, scratch, partials, sc, s);
+    // Register-resident forward values for the level counts in use, on grids whose columns
+    // fill whole workgroups and whose arrays are addressable with 32-bit byte offsets; any
+    // other grid takes the generic path.
+    const bool reg = (tv.P % kWG == 0) && ((unsigned long)tv.n * sizeof(Tv) < (1ul << 32));
+    if (reg && tv.nlev == 20)
+        rows = thomas_dispatch_mode<Tv, 20>(tv, q, z, mode, r, p, v, rhat, partials, sc, s);
+    else if (reg && tv.nlev == 70)
+        rows = thomas_dispatch_mode<Tv, 70>(tv, q, z, mode, r, p, v, rhat, partials, sc, s);
+    else if (reg && tv.nlev == 140 && sizeof(Tv) == 4)
+        rows = thomas_dispatch_mode<Tv, (sizeof(Tv) == 4 ? 140 : 0)>(tv, q, z, mode, r, p, v, rhat, partials, sc, s);
     else
-        rows = thomas_dispatch_mode<Tv, Tc, 0>(op, q, z, mode, r, p, v, rhat, scratch, partials, sc, s);
+        rows = thomas_dispatch_mode<Tv, 0>(tv, q, z, mode, r, p, v, rhat, partials, sc, s);
     if (nrows) *nrows = rows;
 }
 
@@ -458,7 +543,31 @@ void launch_thomas(const OpView<Tc> &op, const Tv *q, Tv *z, int mode, Tv *r, Tv
 //   full step    x += alpha phat + omega shat; r = s - omega t; partials <rhat, r>, <r, r>
 //   half step    x += alpha phat                      (converged at s)
 //   omega = 0    x += alpha phat; r = s; partial <r, r>   (restart follows)
+// 16-byte vector accesses (double2 / float4); the n % VEC tail is done by workgroup 0.
 // ------------------------------------------------------------------------------------------
+template <typename T> struct alignas(16) Pack {
+    static constexpr int N = 16 / sizeof(T);
+    T v[N];
+};
+
+template <typename Tv>
+__device__ __forceinline__ void update_one(int mode, Tv alpha, Tv omega, Tv &x, Tv ph, Tv sh, Tv s, Tv t, Tv &r,
+                                           Tv rh, double (&acc)[2])
+{
+    if (mode == 1) {
+        x = x + alpha * ph;
+    } else if (mode == 2) {
+        x = x + alpha * ph;
+        r = s;
+        acc[1] += static_cast<double>(s) * static_cast<double>(s);
+    } else {
+        x = x + alpha * ph + omega * sh;
+        r = s - omega * t;
+        acc[0] += static_cast<double>(rh) * static_cast<double>(r);
+        acc[1] += static_cast<double>(r) * static_cast<double>(r);
+    }
+}
+
 template <typename Tv>
 __global__ __launch_bounds__(kWG) void k_update(long n, Tv *__restrict__ x, const Tv *__restrict__ ph,
                                                 const Tv *__restrict__ sh, const Tv *__restrict__ s,
@@ -469,25 +578,38 @@ __global__ __launch_bounds__(kWG) void k_update(long n, Tv *__restrict__ x, cons
     if (sc->done || sc->skip) return;
     const Tv alpha = static_cast<Tv>(sc->alpha);
     const Tv omega = static_cast<Tv>(sc->omega);
-    const int half = sc->half, wbd = sc->wbd;
+    const int mode = sc->half ? 1 : (sc->wbd ? 2 : 0);
+    using PK = Pack<Tv>;
+    constexpr int V = PK::N;
     double acc[2] = {0.0, 0.0};
+    const long nv = n / V;
     const long stride = (long)gridDim.x * kWG;
-    for (long i = (long)blockIdx.x * kWG + threadIdx.x; i < n; i += stride) {
-        if (half) {
-            x[i] = x[i] + alpha * ph[i];
-        } else if (wbd) {
-            x[i] = x[i] + alpha * ph[i];
-            const Tv si = s[i];
-            r[i] = si;
-            acc[1] += static_cast<double>(si) * static_cast<double>(si);
-        } else {
-            x[i] = x[i] + alpha * ph[i] + omega * sh[i];
-            const Tv ri = s[i] - omega * t[i];
-            r[i] = ri;
-            acc[0] += static_cast<double>(rhat[i]) * static_cast<double>(ri);
-            acc[1] += static_cast<double>(ri) * static_cast<double>(ri);
+    for (long i = (long)blockIdx.x * kWG + threadIdx.x; i < nv; i += stride) {
+        PK xv = reinterpret_cast<const PK *>(x)[i];
+        const PK pv = reinterpret_cast<const PK *>(ph)[i];
+        PK sv{}, hv{}, tv{}, rv{}, qv{};
+        if (mode != 1) sv = reinterpret_cast<const PK *>(s)[i];
+        if (mode == 0) {
+            hv = reinterpret_cast<const PK *>(sh)[i];
+            tv = reinterpret_cast<const PK *>(t)[i];
+            qv = reinterpret_cast<const PK *>(rhat)[i];
         }
+#pragma unroll
+        for (int e = 0; e < V; ++e)
+            update_one<Tv>(mode, alpha, omega, xv.v[e], pv.v[e], hv.v[e], sv.v[e], tv.v[e], rv.v[e], qv.v[e], acc);
+        reinterpret_cast<PK *>(x)[i] = xv;
+        if (mode != 1) reinterpret_cast<PK *>(r)[i] = rv;
     }
+    if (blockIdx.x == 0)
+        for (long i = nv * V + threadIdx.x; i < n; i += kWG) {
+            Tv xi = x[i], ri = 0;
+            const Tv si = (mode != 1) ? s[i] : Tv(0);
+            const Tv hi = (mode == 0) ? sh[i] : Tv(0), ti = (mode == 0) ? t[i] : Tv(0);
+            const Tv qi = (mode == 0) ? rhat[i] : Tv(0);
+            update_one<Tv>(mode, alpha, omega, xi, ph[i], hi, si, ti, ri, qi, acc);
+            x[i] = xi;
+            if (mode != 1) r[i] = ri;
+        }
     block_sum_store<2>(acc, partials + (long)blockIdx.x * kPartialCols);
 }
 
@@ -605,6 +727,7 @@ __global__ __launch_bounds__(kWG) void k_finalize(int stage, const double *__res
         sc->was_fresh = wf;
         sc->fresh = 0;
         const double sigma = s0, vv = s1;
+        sc->work_mask = 0x3;   // thomas(P) and spmv(v) ran; the rest only if alpha is set
         if (!isfinite(sigma) || !isfinite(vv)) {   // poisoned iteration: stop
             sc->done = 1;
             sc->status = 2;
@@ -643,6 +766,7 @@ __global__ __launch_bounds__(kWG) void k_finalize(int stage, const double *__res
         const int it = sc->iter + 1;
         sc->iter = it;
         const int slot = sc->hist_base + it - 1;
+        sc->work_mask = sc->skip ? 0x3 : (sc->half ? 0x17 : 0x1f);
         if (sc->skip) {
             sc->skip = 0;
             sc->fresh = 1;
@@ -765,12 +889,11 @@ void launch_check_finite(long n, const double *v, int *bad, hipStream_t s)
 // ------------------------------------------------------------------------------------------
 // operator setup
 // ------------------------------------------------------------------------------------------
-// Copy the couplings, derive m = C - (((((W+E)+S)+N)+D)+U) and g = m + (((W+E)+S)+N), and
-// count violations: bad[0] non-finite, bad[1] negative coupling, bad[2] coupling across a
+// Copy the couplings, derive the margin m = C - (((((W+E)+S)+N)+D)+U), and count violations: bad[0] non-finite, bad[1] negative coupling, bad[2] coupling across a
 // pole / the bottom / the top, bad[3] non-positive margin.
 __global__ __launch_bounds__(kWG) void k_derive(const double *__restrict__ cf, int nlon, int nlat, int nlev,
                                                 double *__restrict__ a64, double *__restrict__ m64,
-                                                double *__restrict__ g64, int *__restrict__ bad)
+                                                int *__restrict__ bad)
 {
     const long P = (long)nlon * nlat;
     const long n = P * nlev;
@@ -796,7 +919,6 @@ __global__ __launch_bounds__(kWG) void k_derive(const double *__restrict__ cf, i
         const double m = C - ((hs + a[4]) + a[5]);
         if (!(m > 0.0)) ++b3;
         m64[c] = m;
-        g64[c] = m + hs;
     }
     if (b0) atomicAdd(bad + 0, b0);
     if (b1) atomicAdd(bad + 1, b1);
@@ -804,32 +926,29 @@ __global__ __launch_bounds__(kWG) void k_derive(const double *__restrict__ cf, i
     if (b3) atomicAdd(bad + 3, b3);
 }
 
-void launch_derive(const double *coeffs, int nlon, int nlat, int nlev, double *a64, double *m64, double *g64,
-                   int *bad, hipStream_t s)
+void launch_derive(const double *coeffs, int nlon, int nlat, int nlev, double *a64, double *m64, int *bad,
+                   hipStream_t s)
 {
     const long n = (long)nlon * nlat * nlev;
     hipLaunchKernelGGL(k_derive, dim3(elementwise_blocks(n)), dim3(kWG), 0, s, coeffs, nlon, nlat, nlev, a64, m64,
-                       g64, bad);
+                       bad);
 }
 
 __global__ __launch_bounds__(kWG) void k_to_fp32(long n, const double *__restrict__ a64,
-                                                 const double *__restrict__ m64, const double *__restrict__ g64,
-                                                 float *__restrict__ a32, float *__restrict__ m32,
-                                                 float *__restrict__ g32)
+                                                 const double *__restrict__ m64, float *__restrict__ a32,
+                                                 float *__restrict__ m32)
 {
     const long stride = (long)gridDim.x * kWG;
     for (long c = (long)blockIdx.x * kWG + threadIdx.x; c < n; c += stride) {
 #pragma unroll
         for (int d = 0; d < 6; ++d) a32[d * n + c] = static_cast<float>(a64[d * n + c]);
         m32[c] = static_cast<float>(m64[c]);
-        g32[c] = static_cast<float>(g64[c]);
     }
 }
 
-void launch_to_fp32(long n, const double *a64, const double *m64, const double *g64, float *a32, float *m32,
-                    float *g32, hipStream_t s)
+void launch_to_fp32(long n, const double *a64, const double *m64, float *a32, float *m32, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_to_fp32, dim3(elementwise_blocks(n)), dim3(kWG), 0, s, n, a64, m64, g64, a32, m32, g32);
+    hipLaunchKernelGGL(k_to_fp32, dim3(elementwise_blocks(n)), dim3(kWG), 0, s, n, a64, m64, a32, m32);
 }
 
 // Round a non-negative double to p significant bits, ties to even, with exponents below emin
@@ -845,7 +964,8 @@ __device__ double round_sig(double u, int p, int emin)
     return rint(u / ulp) * ulp;
 }
 
-// one wave per (direction, level, latitude row): power-of-two scale 2^ceil(log2 max a)
+// One wave per (direction, level, latitude row): power-of-two scale 2^ceil(log2 max a), stored
+// at qs[(k * nlat + j) * 8 + d] so that one row's six scales are one 32-byte record.
 __global__ __launch_bounds__(64) void k_qscale(int nlon, int nlat, int nlev, const double *__restrict__ a64,
                                                float *__restrict__ qs)
 {
@@ -864,53 +984,48 @@ __global__ __launch_bounds__(64) void k_qscale(int nlon, int nlat, int nlev, con
             const double f = frexp(mx, &e);
             s = ldexpf(1.f, (f == 0.5) ? e - 1 : e);
         }
-        qs[row] = s;
+        qs[kj * kQsStride + d] = s;
+        if (d == 0)
+            for (int pad = 6; pad < kQsStride; ++pad) qs[kj * kQsStride + pad] = 1.f;
     }
 }
 
-// a_q = RNE(a / scale) in BF16 (kind 2) or FP16 (kind 3); g_q = m + sum of the decoded W,E,S,N
+// a_q = RNE(a / scale) in BF16 (kind 2) or FP16 (kind 3)
 __global__ __launch_bounds__(kWG) void k_quantize(int kind, int nlon, int nlat, int nlev,
-                                                  const double *__restrict__ a64, const double *__restrict__ m64,
-                                                  const float *__restrict__ qs, uint16_t *__restrict__ aq,
-                                                  float *__restrict__ gq)
+                                                  const double *__restrict__ a64, const float *__restrict__ qs,
+                                                  uint16_t *__restrict__ aq)
 {
     const long P = (long)nlon * nlat;
     const long n = P * nlev;
     const long stride = (long)gridDim.x * kWG;
     for (long c = (long)blockIdx.x * kWG + threadIdx.x; c < n; c += stride) {
         const long kj = c / nlon;   // k * nlat + j
-        double hs = 0.0;
 #pragma unroll
         for (int d = 0; d < 6; ++d) {
-            const double s = qs[(long)d * nlev * nlat + kj];
+            const double s = qs[kj * kQsStride + d];
             const double u = a64[d * n + c] / s;
             uint16_t bits;
-            double dq;
             if (kind == PBF16) {
                 const double r = round_sig(u, 8, -126);
                 bits = static_cast<uint16_t>(__float_as_uint(static_cast<float>(r)) >> 16);
-                dq = static_cast<double>(bf16_to_f(bits)) * s;
             } else {
                 const double r = round_sig(u, 11, -14);
                 const _Float16 h = static_cast<_Float16>(static_cast<float>(r));
                 bits = __builtin_bit_cast(uint16_t, h);
-                dq = static_cast<double>(fp16_to_f(bits)) * s;
             }
             aq[d * n + c] = bits;
-            if (d < 4) hs += dq;
         }
-        gq[c] = static_cast<float>(m64[c] + hs);
     }
 }
 
-void launch_quantize(int kind, int nlon, int nlat, int nlev, const double *a64, const double *m64, uint16_t *aq,
-                     float *qs, float *gq, hipStream_t s)
+void launch_quantize(int kind, int nlon, int nlat, int nlev, const double *a64, uint16_t *aq, float *qs,
+                     hipStream_t s)
 {
     const long rows = 6L * nlev * nlat;
     hipLaunchKernelGGL(k_qscale, dim3((unsigned)rows), dim3(64), 0, s, nlon, nlat, nlev, a64, qs);
     const long n = (long)nlon * nlat * nlev;
-    hipLaunchKernelGGL(k_quantize, dim3(elementwise_blocks(n)), dim3(kWG), 0, s, kind, nlon, nlat, nlev, a64, m64, qs,
-                       aq, gq);
+    hipLaunchKernelGGL(k_quantize, dim3(elementwise_blocks(n)), dim3(kWG), 0, s, kind, nlon, nlat, nlev, a64, qs,
+                       aq);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -928,18 +1043,12 @@ template void launch_residual<double>(const OpView<double> &, const double *, co
                                       int *, hipStream_t);
 template void launch_residual<float>(const OpView<double> &, const double *, const double *, float *, double *,
                                      int *, hipStream_t);
-template void launch_thomas<double, double>(const OpView<double> &, const double *, double *, int, double *,
-                                            double *, const double *, double *, double *, double *, int *,
-                                            const Scalars *, hipStream_t);
-template void launch_thomas<float, float>(const OpView<float> &, const float *, float *, int, float *, float *,
-                                          const float *, float *, float *, double *, int *, const Scalars *,
-                                          hipStream_t);
-template void launch_thomas<float, bf16_t>(const OpView<bf16_t> &, const float *, float *, int, float *, float *,
-                                           const float *, float *, float *, double *, int *, const Scalars *,
-                                           hipStream_t);
-template void launch_thomas<float, fp16_t>(const OpView<fp16_t> &, const float *, float *, int, float *, float *,
-                                           const float *, float *, float *, double *, int *, const Scalars *,
-                                           hipStream_t);
+template void launch_thomas<double>(const TriView<double> &, const double *, double *, int, const double *,
+                                    double *, const double *, double *, double *, int *, const Scalars *, hipStream_t);
+template void launch_thomas<float>(const TriView<float> &, const float *, float *, int, const float *, float *,
+                                   const float *, float *, double *, int *, const Scalars *, hipStream_t);
+template void launch_tri_factor<double>(const double *, const double *, int, int, int, double *, hipStream_t);
+template void launch_tri_factor<float>(const double *, const double *, int, int, int, float *, hipStream_t);
 template void launch_update<double>(long, double *, const double *, const double *, const double *, const double *,
                                     double *, const double *, double *, int *, const Scalars *, hipStream_t);
 template void launch_update<float>(long, float *, const float *, const float *, const float *, const float *,

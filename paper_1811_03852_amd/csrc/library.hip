@@ -28,6 +28,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/endgame.h"
@@ -72,7 +73,7 @@ template <typename T> void dfree(T *&p)
 
 template <typename Tv> struct Work {
     Tv *r = nullptr, *rh = nullptr, *p = nullptr, *ph = nullptr, *v = nullptr, *s = nullptr, *sh = nullptr,
-       *t = nullptr, *x = nullptr, *scr = nullptr;
+       *t = nullptr, *x = nullptr;
     bool ready = false;
 };
 
@@ -83,10 +84,9 @@ struct eg_operator {
     long P = 0, n = 0;
     hipStream_t stream = nullptr;
 
-    double *a64 = nullptr, *m64 = nullptr, *g64 = nullptr;
-    float *a32 = nullptr, *m32 = nullptr, *g32 = nullptr;
+    double *a64 = nullptr, *m64 = nullptr, *tri64 = nullptr;
+    float *a32 = nullptr, *m32 = nullptr, *tri32 = nullptr;
     uint16_t *aq[2] = {nullptr, nullptr};
-    float *gq[2] = {nullptr, nullptr};
     float *qs[2] = {nullptr, nullptr};
 
     Work<double> w64;
@@ -107,16 +107,31 @@ struct eg_operator {
     int poll = 8;
     int use_graph = 1;
     int stall_window = 20;
+    int profile = 0;
+
+    // kernel timing: events around the streaming kernels of one iteration + the residual
+    hipEvent_t ev[12] = {};
+    bool ev_ready = false;
+    double kms[EG_K_COUNT][4] = {};
+    long kcnt[EG_K_COUNT][4] = {};
 
     eg_info info{};
     std::vector<double> hist_host;
     int hist_count = 0;
 
-    OpView<double> view64() const { return {a64, m64, g64, nullptr, nlon, nlat, nlev, P, n}; }
-    OpView<float> view32() const { return {a32, m32, g32, nullptr, nlon, nlat, nlev, P, n}; }
+    OpView<double> view64() const { return {a64, m64, nullptr, nlon, nlat, nlev, P, n}; }
+    OpView<float> view32() const { return {a32, m32, nullptr, nlon, nlat, nlev, P, n}; }
     template <typename Tq> OpView<Tq> viewq(int slot) const
     {
-        return {reinterpret_cast<const Tq *>(aq[slot]), m32, gq[slot], qs[slot], nlon, nlat, nlev, P, n};
+        return {reinterpret_cast<const Tq *>(aq[slot]), m32, qs[slot], nlon, nlat, nlev, P, n};
+    }
+    TriView<double> tri_view64() const { return {tri64, P, n, nlev}; }
+    TriView<float> tri_view32() const { return {tri32, P, n, nlev}; }
+    // the Thomas factors a precision uses: FP64, or FP32 for every lower-precision set
+    template <typename Tv> TriView<Tv> tri_view() const
+    {
+        if constexpr (std::is_same_v<Tv, double>) return tri_view64();
+        else return tri_view32();
     }
 };
 
@@ -128,8 +143,9 @@ int ensure_fp32(eg_operator *op)
     int rc;
     if ((rc = dalloc(&op->a32, 6 * (size_t)op->n))) return rc;
     if ((rc = dalloc(&op->m32, (size_t)op->n))) return rc;
-    if ((rc = dalloc(&op->g32, (size_t)op->n))) return rc;
-    launch_to_fp32(op->n, op->a64, op->m64, op->g64, op->a32, op->m32, op->g32, op->stream);
+    if ((rc = dalloc(&op->tri32, 3 * (size_t)op->n))) return rc;
+    launch_to_fp32(op->n, op->a64, op->m64, op->a32, op->m32, op->stream);
+    launch_tri_factor<float>(op->a64, op->m64, op->nlon, op->nlat, op->nlev, op->tri32, op->stream);
     EG_HIP(hipGetLastError());
     return 0;
 }
@@ -138,13 +154,11 @@ int ensure_quant(eg_operator *op, int kind)
 {
     const int slot = (kind == PBF16) ? 0 : 1;
     int rc;
-    if ((rc = ensure_fp32(op))) return rc;   // m32 is shared with the FP32 set
+    if ((rc = ensure_fp32(op))) return rc;   // m32 and the FP32 factors are shared with the FP32 set
     if (op->aq[slot]) return 0;
     if ((rc = dalloc(&op->aq[slot], 6 * (size_t)op->n))) return rc;
-    if ((rc = dalloc(&op->gq[slot], (size_t)op->n))) return rc;
-    if ((rc = dalloc(&op->qs[slot], 6 * (size_t)op->nlev * op->nlat))) return rc;
-    launch_quantize(kind, op->nlon, op->nlat, op->nlev, op->a64, op->m64, op->aq[slot], op->qs[slot], op->gq[slot],
-                    op->stream);
+    if ((rc = dalloc(&op->qs[slot], (size_t)kQsStride * op->nlev * op->nlat))) return rc;
+    launch_quantize(kind, op->nlon, op->nlat, op->nlev, op->a64, op->aq[slot], op->qs[slot], op->stream);
     EG_HIP(hipGetLastError());
     return 0;
 }
@@ -152,7 +166,7 @@ int ensure_quant(eg_operator *op, int kind)
 template <typename Tv> int ensure_work(eg_operator *op, Work<Tv> &w)
 {
     if (w.ready) return 0;
-    Tv **bufs[] = {&w.r, &w.rh, &w.p, &w.ph, &w.v, &w.s, &w.sh, &w.t, &w.x, &w.scr};
+    Tv **bufs[] = {&w.r, &w.rh, &w.p, &w.ph, &w.v, &w.s, &w.sh, &w.t, &w.x};
     for (Tv **b : bufs) {
         int rc = dalloc(b, (size_t)op->n);
         if (rc) return rc;
@@ -193,19 +207,60 @@ int put_run_params(eg_operator *op, double tol, int maxit, int hist_base, int re
     return 0;
 }
 
+template <typename Tc> constexpr int prec_of()
+{
+    if constexpr (std::is_same_v<Tc, double>) return EG_PREC_FP64;
+    else if constexpr (std::is_same_v<Tc, float>) return EG_PREC_FP32;
+    else if constexpr (std::is_same_v<Tc, bf16_t>) return EG_PREC_BF16;
+    else return EG_PREC_FP16;
+}
+
+int ensure_events(eg_operator *op)
+{
+    if (op->ev_ready) return 0;
+    for (hipEvent_t &e : op->ev) EG_HIP(hipEventCreate(&e));
+    op->ev_ready = true;
+    return 0;
+}
+
+// Accumulate the device time between event pair k (events 2k, 2k+1) into kernel `kind`.
+int add_kernel_time(eg_operator *op, int k, int kind, int prec)
+{
+    float ms = 0.f;
+    EG_HIP(hipEventElapsedTime(&ms, op->ev[2 * k], op->ev[2 * k + 1]));
+    op->kms[kind][prec] += ms;
+    op->kcnt[kind][prec] += 1;
+    return 0;
+}
+
+// ev (may be null): 10 events recorded around the five streaming kernels.
 template <typename Tv, typename Tc>
-void enqueue_iteration(eg_operator *op, const OpView<Tc> &A, Work<Tv> &w)
+void enqueue_iteration(eg_operator *op, const OpView<Tc> &A, Work<Tv> &w, hipEvent_t *ev)
 {
     hipStream_t s = op->stream;
+    const TriView<Tv> T = op->tri_view<Tv>();
     int nr = 0;
-    launch_thomas<Tv, Tc>(A, nullptr, w.ph, TH_P, w.r, w.p, w.v, w.rh, w.scr, op->partials, &nr, op->sc, s);
+    auto mark = [&](int i) {
+        if (ev) (void)hipEventRecord(ev[i], s);
+    };
+    mark(0);
+    launch_thomas<Tv>(T, nullptr, w.ph, TH_P, w.r, w.p, w.v, w.rh, op->partials, &nr, op->sc, s);
+    mark(1);
+    mark(2);
     launch_spmv<Tv, Tc>(A, w.ph, w.v, w.rh, SP_DOT2, op->partials, &nr, op->sc, STOP_DONE, s);
+    mark(3);
     launch_finalize(FIN_SIGMA, op->partials, nr, op->sc, op->d_hist, nullptr, 0, 0, s);
-    launch_thomas<Tv, Tc>(A, nullptr, w.sh, TH_S, w.r, w.s, w.v, nullptr, w.scr, op->partials, &nr, op->sc, s);
+    mark(4);
+    launch_thomas<Tv>(T, nullptr, w.sh, TH_S, w.r, w.s, w.v, nullptr, op->partials, &nr, op->sc, s);
+    mark(5);
     launch_finalize(FIN_S, op->partials, nr, op->sc, op->d_hist, nullptr, 0, 0, s);
+    mark(6);
     launch_spmv<Tv, Tc>(A, w.sh, w.t, w.s, SP_DOT2, op->partials, &nr, op->sc, STOP_DONE | STOP_SKIP | STOP_HALF, s);
+    mark(7);
     launch_finalize(FIN_OMEGA, op->partials, nr, op->sc, op->d_hist, nullptr, 0, 0, s);
+    mark(8);
     launch_update<Tv>(op->n, w.x, w.ph, w.sh, w.s, w.t, w.r, w.rh, op->partials, &nr, op->sc, s);
+    mark(9);
     launch_finalize(FIN_END, op->partials, nr, op->sc, op->d_hist, nullptr, 0, 0, s);
 }
 
@@ -215,9 +270,24 @@ template <typename Tv, typename Tc> int krylov_run(eg_operator *op, const OpView
 {
     int rc;
     if ((rc = sync_scalars(op))) return rc;
+    if (op->profile) {
+        // one iteration per check; time the streaming kernels that did work
+        if ((rc = ensure_events(op))) return rc;
+        constexpr int prec = prec_of<Tc>();
+        while (!op->h_sc->done) {
+            enqueue_iteration<Tv, Tc>(op, A, w, op->ev);
+            EG_HIP(hipGetLastError());
+            if ((rc = sync_scalars(op))) return rc;
+            const int mask = op->h_sc->work_mask;
+            for (int k = 0; k < 5; ++k)
+                if (mask & (1 << k))
+                    if ((rc = add_kernel_time(op, k, k, prec))) return rc;
+        }
+        return 0;
+    }
     int batch = std::max(1, op->poll);
     while (!op->h_sc->done) {
-        for (int b = 0; b < batch; ++b) enqueue_iteration<Tv, Tc>(op, A, w);
+        for (int b = 0; b < batch; ++b) enqueue_iteration<Tv, Tc>(op, A, w, nullptr);
         EG_HIP(hipGetLastError());
         if ((rc = sync_scalars(op))) return rc;
     }
@@ -322,10 +392,16 @@ int solve_ir(eg_operator *op, const OpView<Tc> &A32, const double *b, double *x,
     double rel_prev = INFINITY;
     for (;;) {
         int nr = 0;
+        if (op->profile) {
+            if ((rc = ensure_events(op))) return rc;
+            EG_HIP(hipEventRecord(op->ev[10], s));
+        }
         launch_residual<float>(op->view64(), b, x, w.r, op->partials, &nr, s);
+        if (op->profile) EG_HIP(hipEventRecord(op->ev[11], s));
         launch_finalize(FIN_SUM, op->partials, nr, op->sc, nullptr, op->d_out, 0, 0, s);
         EG_HIP(hipMemcpyAsync(op->h_out, op->d_out, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
         EG_HIP(hipStreamSynchronize(s));
+        if (op->profile && (rc = add_kernel_time(op, 5, EG_K_RESIDUAL, EG_PREC_FP64))) return rc;
         const double rr = op->h_out[0], bb = op->h_out[1];
         if (bb == 0.0) {
             launch_fill<double>(x, op->n, 0.0, s);
@@ -378,17 +454,19 @@ void eg_destroy_operator(eg_operator *op)
 {
     if (!op) return;
     (void)hipStreamSynchronize(op->stream);
-    dfree(op->a64); dfree(op->m64); dfree(op->g64);
-    dfree(op->a32); dfree(op->m32); dfree(op->g32);
-    for (int i = 0; i < 2; ++i) { dfree(op->aq[i]); dfree(op->gq[i]); dfree(op->qs[i]); }
+    dfree(op->a64); dfree(op->m64); dfree(op->tri64);
+    dfree(op->a32); dfree(op->m32); dfree(op->tri32);
+    for (int i = 0; i < 2; ++i) { dfree(op->aq[i]); dfree(op->qs[i]); }
     for (Work<double> *w : {&op->w64}) {
         dfree(w->r); dfree(w->rh); dfree(w->p); dfree(w->ph); dfree(w->v); dfree(w->s); dfree(w->sh);
-        dfree(w->t); dfree(w->x); dfree(w->scr);
+        dfree(w->t); dfree(w->x);
     }
     for (Work<float> *w : {&op->w32}) {
         dfree(w->r); dfree(w->rh); dfree(w->p); dfree(w->ph); dfree(w->v); dfree(w->s); dfree(w->sh);
-        dfree(w->t); dfree(w->x); dfree(w->scr);
+        dfree(w->t); dfree(w->x);
     }
+    if (op->ev_ready)
+        for (hipEvent_t e : op->ev) (void)hipEventDestroy(e);
     dfree(op->partials); dfree(op->sc); dfree(op->d_out); dfree(op->d_bad); dfree(op->d_hist);
     if (op->h_sc) (void)hipHostFree(op->h_sc);
     if (op->h_out) (void)hipHostFree(op->h_out);
@@ -409,7 +487,7 @@ int eg_create_operator(const double *coeffs, int nlon, int nlat, int nlev, eg_op
     int rc = 0;
     auto bail = [&](int code) { eg_destroy_operator(op); return code; };
     if ((rc = dalloc(&op->a64, 6 * (size_t)n)) || (rc = dalloc(&op->m64, (size_t)n)) ||
-        (rc = dalloc(&op->g64, (size_t)n)) ||
+        (rc = dalloc(&op->tri64, 3 * (size_t)n)) ||
         (rc = dalloc(&op->partials, (size_t)partial_rows_needed(nlon, nlat, nlev) * kPartialCols)) ||
         (rc = dalloc(&op->sc, 1)) || (rc = dalloc(&op->d_out, 4)) || (rc = dalloc(&op->d_bad, 4)))
         return bail(rc);
@@ -419,7 +497,7 @@ int eg_create_operator(const double *coeffs, int nlon, int nlat, int nlev, eg_op
     if ((rc = ensure_hist(op, 4096))) return bail(rc);
     int bad[4] = {0, 0, 0, 0};
     if (hipMemsetAsync(op->d_bad, 0, 4 * sizeof(int), op->stream) != hipSuccess) return bail(fail(EG_EHIP, "memset"));
-    launch_derive(coeffs, nlon, nlat, nlev, op->a64, op->m64, op->g64, op->d_bad, op->stream);
+    launch_derive(coeffs, nlon, nlat, nlev, op->a64, op->m64, op->d_bad, op->stream);
     if (hipGetLastError() != hipSuccess ||
         hipMemcpyAsync(bad, op->d_bad, sizeof(bad), hipMemcpyDeviceToHost, op->stream) != hipSuccess ||
         hipStreamSynchronize(op->stream) != hipSuccess)
@@ -430,6 +508,9 @@ int eg_create_operator(const double *coeffs, int nlon, int nlat, int nlev, eg_op
                         std::to_string(bad[3]) + " rows without a positive margin C - sum(a)";
         return bail(fail(EG_EINVAL, m));
     }
+    launch_tri_factor<double>(op->a64, op->m64, nlon, nlat, nlev, op->tri64, op->stream);
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(op->stream) != hipSuccess)
+        return bail(fail(EG_EHIP, "tridiagonal factorisation failed"));
     *out = op;
     return 0;
 }
@@ -459,6 +540,8 @@ int eg_set_option(eg_operator *op, const char *key, double value)
         op->poll = (int)value;
     } else if (k == "graph") {
         op->use_graph = value != 0.0;
+    } else if (k == "profile") {
+        op->profile = value != 0.0;
     } else if (k == "stall_window") {
         if (value < 1) return fail(EG_EINVAL, "stall_window must be >= 1");
         op->stall_window = (int)value;
@@ -520,6 +603,23 @@ int eg_solve(eg_operator *op, const double *b, double *x, double tol, int maxit,
     return status;
 }
 
+int eg_kernel_stats(const eg_operator *op, int kernel, int prec, long *launches, double *total_ms)
+{
+    if (!op) return fail(EG_EINVAL, "op is NULL");
+    if (kernel < 0 || kernel >= EG_K_COUNT || prec < 0 || prec > 3) return fail(EG_EINVAL, "bad kernel or prec");
+    if (launches) *launches = op->kcnt[kernel][prec];
+    if (total_ms) *total_ms = op->kms[kernel][prec];
+    return 0;
+}
+
+int eg_reset_kernel_stats(eg_operator *op)
+{
+    if (!op) return fail(EG_EINVAL, "op is NULL");
+    std::memset(op->kms, 0, sizeof(op->kms));
+    std::memset(op->kcnt, 0, sizeof(op->kcnt));
+    return 0;
+}
+
 int eg_get_info(const eg_operator *op, eg_info *info)
 {
     if (!op || !info) return fail(EG_EINVAL, "NULL argument");
@@ -570,35 +670,16 @@ int eg_apply(eg_operator *op, const void *x, void *y, int prec)
 int eg_apply_precond(eg_operator *op, const void *q, void *z, int prec)
 {
     if (!op || !q || !z) return fail(EG_EINVAL, "NULL argument");
+    if (prec < EG_PREC_FP64 || prec > EG_PREC_FP16) return fail(EG_EINVAL, "unknown precision");
     int rc;
     if (prec == EG_PREC_FP64) {
-        if ((rc = ensure_work(op, op->w64))) return rc;
-        launch_thomas<double, double>(op->view64(), static_cast<const double *>(q), static_cast<double *>(z), TH_PLAIN,
-                                      nullptr, nullptr, nullptr, nullptr, op->w64.scr, op->partials, nullptr, nullptr,
-                                      op->stream);
+        launch_thomas<double>(op->tri_view64(), static_cast<const double *>(q), static_cast<double *>(z), TH_PLAIN,
+                              nullptr, nullptr, nullptr, nullptr, op->partials, nullptr, nullptr, op->stream);
     } else {
-        if ((rc = ensure_work(op, op->w32))) return rc;
-        const float *qf = static_cast<const float *>(q);
-        float *zf = static_cast<float *>(z);
-        switch (prec) {
-        case EG_PREC_FP32:
-            if ((rc = ensure_fp32(op))) return rc;
-            launch_thomas<float, float>(op->view32(), qf, zf, TH_PLAIN, nullptr, nullptr, nullptr, nullptr,
-                                        op->w32.scr, op->partials, nullptr, nullptr, op->stream);
-            break;
-        case EG_PREC_BF16:
-            if ((rc = ensure_quant(op, PBF16))) return rc;
-            launch_thomas<float, bf16_t>(op->viewq<bf16_t>(0), qf, zf, TH_PLAIN, nullptr, nullptr, nullptr, nullptr,
-                                         op->w32.scr, op->partials, nullptr, nullptr, op->stream);
-            break;
-        case EG_PREC_FP16:
-            if ((rc = ensure_quant(op, PFP16))) return rc;
-            launch_thomas<float, fp16_t>(op->viewq<fp16_t>(1), qf, zf, TH_PLAIN, nullptr, nullptr, nullptr, nullptr,
-                                         op->w32.scr, op->partials, nullptr, nullptr, op->stream);
-            break;
-        default:
-            return fail(EG_EINVAL, "unknown precision");
-        }
+        // every lower-precision set uses the FP32 rounding of the FP64 factors
+        if ((rc = ensure_fp32(op))) return rc;
+        launch_thomas<float>(op->tri_view32(), static_cast<const float *>(q), static_cast<float *>(z), TH_PLAIN,
+                             nullptr, nullptr, nullptr, nullptr, op->partials, nullptr, nullptr, op->stream);
     }
     EG_HIP(hipGetLastError());
     EG_HIP(hipStreamSynchronize(op->stream));

@@ -105,14 +105,16 @@ def test_thomas_fp64_matches_oracle(eg, oracle_mod, p):
     op.close()
 
 
-@pytest.mark.parametrize("prec_name,kind", [("PREC_FP32", None), ("PREC_BF16", "bf16"), ("PREC_FP16", "fp16")])
-@pytest.mark.parametrize("p", [SHAPES[0], SHAPES[1], SHAPES[4]], ids=lambda p: f"{p.nlon}x{p.nlat}x{p.nlev}")
-def test_thomas_low_precision_backward_error(eg, oracle_mod, p, prec_name, kind):
+@pytest.mark.parametrize("prec_name", ["PREC_FP32", "PREC_BF16", "PREC_FP16"])
+@pytest.mark.parametrize("p", [SHAPES[0], SHAPES[1], SHAPES[4], SHAPES[5]], ids=lambda p: f"{p.nlon}x{p.nlat}x{p.nlev}")
+def test_thomas_low_precision_backward_error(eg, oracle_mod, p, prec_name):
+    """Every FP32-vector precision applies the FP64 T's LU factors rounded to FP32: a
+    componentwise backward error of order nlev eps32 against the FP64 T (for an M-matrix
+    tridiagonal |L||U| = |T|, so factor rounding stays within the same bound)."""
     coef, op = _op(eg, p)
-    cref = coef if kind is None else quantized_coeffs(coef, kind)
     q32 = np.random.default_rng(p.seed + 500).standard_normal(p.n).astype(np.float32)
     z = host(op.precond(dev(q32), prec=getattr(eg, prec_name))).astype(np.float64)
-    res, scale = _tridiag_backward_bound(oracle_mod, cref, z, q32.astype(np.float64), EPS32)
+    res, scale = _tridiag_backward_bound(oracle_mod, coef, z, q32.astype(np.float64), EPS32)
     assert np.all(res <= 16 * p.nlev * EPS32 * scale)
     op.close()
 
