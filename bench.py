@@ -25,8 +25,8 @@ PEAK_HBM_GBS = 8000.0
 # must touch once), by kernel and precision (fp64, fp32, bf16, fp16).
 BYTES_PER_POINT = {
     "spmv": {0: 80, 1: 40, 2: 28, 3: 28},       # 6 couplings + margin + x + dot partner + y
-    "thomas_p": {0: 64, 1: 32, 2: 28, 3: 28},   # D, U, g + r, p, v in + p, phat out
-    "thomas_s": {0: 56, 1: 28, 2: 24, 3: 24},   # D, U, g + r, v in + s, shat out
+    "thomas_p": {0: 64, 1: 32, 2: 32, 3: 32},   # 3 LU factors + r, p, v in + p, phat out
+    "thomas_s": {0: 56, 1: 28, 2: 28, 3: 28},   # 3 LU factors + r, v in + s, shat out (16-bit modes use FP32 factors)
     "update": {0: 64, 1: 32, 2: 32, 3: 32},     # x, phat, shat, s, t, rhat in + x, r out
     "residual": {0: 76},                        # 6 couplings + margin + x + b (FP64) + r (FP32)
 }
