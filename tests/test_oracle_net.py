@@ -1,0 +1,90 @@
+"""Pins for the FP64 reference of the learned preconditioner (oracle/net.py)."""
+import numpy as np
+
+import oracle
+import synth
+from oracle import net
+
+
+def _small():
+    p = synth.Problem(8, 6, 7, seed=3)
+    coef = synth.make_coeffs(p)
+    rng = np.random.default_rng(1)
+    r = rng.standard_normal(p.n)
+    e = rng.standard_normal(p.n)
+    th = net.init_theta(5)
+    d = net.unpack(th)
+    d["W4"] = rng.standard_normal(d["W4"].shape) * 0.3
+    d["b1"] = rng.standard_normal(32) * 0.1
+    d["b3"] = rng.standard_normal(32) * 0.1
+    d["b4"] = np.array([0.05])
+    return p, coef, r, e, net.pack(d)
+
+
+def test_parameter_count():
+    assert net.N_PARAMS == 15233
+
+
+def test_gradient_matches_central_differences():
+    """Plain FP64 network: the hand-written backward pass agrees with central differences."""
+    p, coef, r, e, th = _small()
+    L, g = net.loss_and_grad(th, coef, r, e, bf16_round=False)
+    rng = np.random.default_rng(7)
+    # a sample of parameters from every tensor
+    offs, o = [], 0
+    for _, shape in net.SHAPES:
+        size = int(np.prod(shape))
+        offs.extend(o + rng.choice(size, size=min(size, 12), replace=False))
+        o += size
+    h = 1e-6
+    fd = []
+    for i in offs:
+        tp = th.copy()
+        tp[i] += h
+        tm = th.copy()
+        tm[i] -= h
+        fd.append((net.loss(tp, coef, r, e, False) - net.loss(tm, coef, r, e, False)) / (2 * h))
+    fd = np.array(fd)
+    ga = g[offs]
+    assert np.linalg.norm(fd - ga) <= 1e-6 * np.linalg.norm(ga), (np.linalg.norm(fd - ga), np.linalg.norm(ga))
+
+
+def test_transposed_thomas_is_the_adjoint():
+    p = synth.Problem(9, 5, 11, seed=2, shift=1e-6, bands=True)
+    coef = synth.make_coeffs(p)
+    rng = np.random.default_rng(3)
+    a = rng.standard_normal(p.n)
+    b = rng.standard_normal(p.n)
+    lhs = np.dot(oracle.thomas(coef, a), b)
+    rhs = np.dot(a, net.thomas_transpose(coef, b))
+    assert abs(lhs - rhs) <= 1e-9 * (abs(lhs) + 1.0) * np.linalg.norm(a) * np.linalg.norm(b)
+
+
+def test_zero_last_layer_is_plain_tridiagonal():
+    p, coef, r, _, _ = _small()
+    th = net.init_theta(11)
+    assert np.array_equal(net.apply(th, coef, r), oracle.thomas(coef, r))
+
+
+def test_lon_translation_equivariance():
+    """Rolling the right-hand side and the operator in longitude rolls the correction."""
+    p, coef, r, _, th = _small()
+    d1, _ = net.forward(th, coef, r, bf16_round=False)
+    s = 3
+    coef_r = np.roll(coef, s, axis=3)
+    r_r = np.roll(r.reshape(p.shape), s, axis=2).ravel()
+    d2, _ = net.forward(th, coef_r, r_r, bf16_round=False)
+    assert np.allclose(np.roll(d1.reshape(p.shape), s, axis=2).ravel(), d2, rtol=1e-12, atol=1e-12)
+
+
+def test_bf16_rounding():
+    x = np.array([1.0, 1.00390625, 1.005859375, 3.0e-3, -2.5, 0.0, 1.0 + 2 ** -8])
+    y = net.bf16(x)
+    assert y[0] == 1.0 and y[1] == 1.0   # 1 + 2^-8 is a tie between 1 and 1 + 2^-7: rounds to even
+    assert y[2] == 1.0078125               # above the tie: rounds up
+    assert y[5] == 0.0 and y[4] == -2.5
+    # agrees with torch's float32 -> bfloat16 conversion on float32-exact inputs
+    import torch
+    v = np.random.default_rng(0).standard_normal(1000).astype(np.float32)
+    t = torch.from_numpy(v).to(torch.bfloat16).to(torch.float64).numpy()
+    assert np.array_equal(net.bf16(v.astype(np.float64)), t)
