@@ -61,7 +61,7 @@ enum eg_status {
     EG_ENOMEM = -2,     /* device allocation failed                                            */
     EG_EHIP = -3,       /* HIP runtime error                                                   */
     EG_ENONFINITE = -4, /* NaN or Inf in the right-hand side or the initial guess              */
-    EG_ENOPC = -5       /* learned mode requested but no trained or loaded network exists      */
+    EG_ENOPC = -5       /* learned mode requested but no network is attached to the operator  */
 };
 
 /* Precision selector of the building-block calls (eg_apply, eg_apply_precond). */
@@ -191,6 +191,61 @@ enum eg_kernel {
 };
 int eg_kernel_stats(const eg_operator *op, int kernel, int prec, long *launches, double *total_ms);
 int eg_reset_kernel_stats(eg_operator *op);
+
+/* ---- learned right preconditioner ----
+ *
+ * The paper's preconditioner keeps the exact vertical tridiagonal solve (Sec. 2, Eq. 6-7).  The
+ * learned form keeps it too and adds a correction from a small network in residual space:
+ *     M(q) = T^{-1} (q + rho * delta(q)),   rho = rms(q),
+ * delta from the input channels [q/rho, T^{-1}q / rms(T^{-1}q), D+U, W+E+S+N] through
+ * conv1d over levels (4->32, 5 taps), ReLU, 3x3 horizontal mixing (32->32), ReLU, conv1d
+ * (32->32, 5 taps), ReLU, conv1d (32->1, 5 taps).  15,233 parameters (flat FP32 vector,
+ * order W1[5][32][4] b1[32] W2[9][32][32] b2[32] W3[5][32][32] b3[32] W4[5][32] b4; vertical
+ * tap t couples level k+t-2, horizontal tap t couples (i + t%3 - 1, j + t/3 - 1), longitude
+ * periodic, latitudes and levels zero-padded).  Inference and training run in BF16 on the
+ * matrix cores with FP32 accumulation.  M is nonlinear, so the learned modes run flexible
+ * BiCGStab (x is updated with exactly the preconditioned vectors that were multiplied by A),
+ * and fall back to T^{-1} alone when the residual stalls (no halving of the best residual in
+ * "stall_window" iterations, a residual 1e3 times the best, or a breakdown).
+ */
+typedef struct eg_net eg_net;
+
+/* New network with He-normal weights from `seed` (splitmix64 + Box-Muller), zero biases and
+ * a zero output layer, so that M = T^{-1} exactly until it is trained. */
+int eg_net_create(unsigned long long seed, eg_net **out);
+void eg_net_destroy(eg_net *net);                                   /* NULL-safe */
+/* host float[count]; count must equal 15233.  Resets the optimiser state. */
+int eg_net_set_weights(eg_net *net, const float *host, long count);
+/* copies the weights to host float[cap] if cap >= 15233; returns 15233 */
+int eg_net_get_weights(const eg_net *net, float *host, long cap);
+/* Use `net` (not owned; must outlive its use; NULL detaches) in the EG_LEARNED_* modes. */
+int eg_attach_learned_pc(eg_operator *op, eg_net *net);
+
+/* z = M(q) in FP32 on the FP32 copy of the operator; q, z device float[n]; delta (may be
+ * NULL) device float[n] receives the network output. */
+int eg_net_apply(eg_operator *op, eg_net *net, const float *q, float *z, float *delta);
+
+/* Loss ||M(r) - e||^2 / ||e||^2 of one (residual, error) pair (device float[n] each) and its
+ * gradient with respect to the parameters (host double, host float[15233]; either may be NULL). */
+int eg_net_loss_grad(eg_operator *op, eg_net *net, const float *r, const float *e, double *loss_host,
+                     float *grad_host);
+
+/* Harvest training pairs from the solver itself: solve A x* = b in FP64 as tightly as FP64
+ * allows, then run FP64 BiCGStab from x0 = 0 and after iteration i (i = 1..nsnap) store
+ * r_i = b - A x_i and e_i = x* - x_i as float.  b: device double[n]; r_out, e_out: device
+ * float[nsnap][n].  Returns the number of pairs stored (fewer if the solve converged first). */
+int eg_harvest(eg_operator *op, const double *b, int nsnap, float *r_out, float *e_out);
+
+/* Train with Adam (lr; beta 0.9 / 0.999) on pairs r, e (device float[npairs][n]); pair i
+ * belongs to operator ops[pair_op[i]] (host arrays; every operator must have the same grid).
+ * Each epoch visits the pairs in a seeded random order in batches of `batch` (mean loss).
+ * loss_hist (host double[epochs], may be NULL) receives each epoch's mean training loss.
+ * All work is ordered on ops[0]'s stream. */
+int eg_net_train(eg_net *net, eg_operator *const *ops, int nops, const float *r, const float *e, const int *pair_op,
+                 int npairs, int epochs, int batch, double lr, unsigned long long seed, double *loss_hist);
+/* Mean loss of the pairs (no training). */
+int eg_net_eval(eg_net *net, eg_operator *const *ops, int nops, const float *r, const float *e, const int *pair_op,
+                int npairs, double *mean_loss);
 
 /* Grid sizes of an operator (host ints; any pointer may be NULL). */
 int eg_get_shape(const eg_operator *op, int *nlon, int *nlat, int *nlev);

@@ -26,7 +26,10 @@ EINVAL, ENOMEM, EHIP, ENONFINITE, ENOPC = -1, -2, -3, -4, -5
 
 EXPORTED = ["eg_create_operator", "eg_solve", "eg_get_info", "eg_residual_history", "eg_set_stream", "eg_set_option",
             "eg_apply", "eg_apply_precond", "eg_residual", "eg_dot", "eg_get_shape", "eg_destroy_operator",
-            "eg_last_error", "eg_kernel_stats", "eg_reset_kernel_stats"]
+            "eg_last_error", "eg_kernel_stats", "eg_reset_kernel_stats", "eg_net_create", "eg_net_destroy",
+            "eg_net_set_weights", "eg_net_get_weights", "eg_attach_learned_pc", "eg_net_apply", "eg_net_loss_grad",
+            "eg_harvest", "eg_net_train", "eg_net_eval"]
+N_NET_PARAMS = 15233
 # enum eg_kernel
 K_THOMAS_P, K_SPMV_V, K_THOMAS_S, K_SPMV_T, K_UPDATE, K_RESIDUAL = range(6)
 
@@ -81,6 +84,17 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "eg_last_error": ([], ctypes.c_char_p),
         "eg_kernel_stats": ([vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_long), dp], ctypes.c_int),
         "eg_reset_kernel_stats": ([vp], ctypes.c_int),
+        "eg_net_create": ([ctypes.c_ulonglong, ctypes.POINTER(vp)], ctypes.c_int),
+        "eg_net_destroy": ([vp], None),
+        "eg_net_set_weights": ([vp, vp, ctypes.c_long], ctypes.c_int),
+        "eg_net_get_weights": ([vp, vp, ctypes.c_long], ctypes.c_int),
+        "eg_attach_learned_pc": ([vp, vp], ctypes.c_int),
+        "eg_net_apply": ([vp, vp, vp, vp, vp], ctypes.c_int),
+        "eg_net_loss_grad": ([vp, vp, vp, vp, dp, vp], ctypes.c_int),
+        "eg_harvest": ([vp, vp, ctypes.c_int, vp, vp], ctypes.c_int),
+        "eg_net_train": ([vp, vp, ctypes.c_int, vp, vp, vp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                          ctypes.c_double, ctypes.c_ulonglong, dp], ctypes.c_int),
+        "eg_net_eval": ([vp, vp, ctypes.c_int, vp, vp, vp, ctypes.c_int, dp], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -207,10 +221,99 @@ class Operator:
     def reset_kernel_stats(self):
         _check(_lib.eg_reset_kernel_stats(self._h))
 
+    def attach(self, net: "Net | None"):
+        """Use ``net`` in the LEARNED modes (None detaches)."""
+        _check(_lib.eg_attach_learned_pc(self._h, None if net is None else net._h))
+        self._net = net
+
+    def harvest(self, b, nsnap: int):
+        """(r, e) float tensors of shape (count, n) from the solver's own FP64 iterates."""
+        import torch
+        self._bind_stream()
+        r = torch.empty((nsnap, self.n), dtype=torch.float32, device=b.device)
+        e = torch.empty_like(r)
+        cnt = _check(_lib.eg_harvest(self._h, _ptr(b), int(nsnap), _ptr(r), _ptr(e)))
+        return r[:cnt].contiguous(), e[:cnt].contiguous()
+
     def dot(self, a, b) -> float:
         import torch
         self._bind_stream()
         prec = PREC_FP64 if a.dtype == torch.float64 else PREC_FP32
         out = ctypes.c_double()
         _check(_lib.eg_dot(self._h, _ptr(a), _ptr(b), a.numel(), prec, ctypes.byref(out)))
+        return out.value
+
+
+class Net:
+    """The learned preconditioner's network (weights on the GPU)."""
+
+    def __init__(self, seed: int = 0):
+        lib = load_library()
+        h = ctypes.c_void_p()
+        _check(lib.eg_net_create(int(seed), ctypes.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.eg_net_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def get_weights(self):
+        import numpy as np
+        w = np.zeros(N_NET_PARAMS, dtype=np.float32)
+        _check(_lib.eg_net_get_weights(self._h, w.ctypes.data_as(ctypes.c_void_p), w.size))
+        return w
+
+    def set_weights(self, w):
+        import numpy as np
+        w = np.ascontiguousarray(w, dtype=np.float32)
+        _check(_lib.eg_net_set_weights(self._h, w.ctypes.data_as(ctypes.c_void_p), w.size))
+
+    def apply(self, op: Operator, q, delta=None):
+        """M(q) in FP32 (q: float tensor of n); returns z (and fills ``delta`` if given)."""
+        import torch
+        op._bind_stream()
+        z = torch.empty_like(q)
+        _check(_lib.eg_net_apply(op._h, self._h, _ptr(q), _ptr(z), None if delta is None else _ptr(delta)))
+        return z
+
+    def loss_grad(self, op: Operator, r, e):
+        import numpy as np
+        op._bind_stream()
+        loss = ctypes.c_double()
+        g = np.zeros(N_NET_PARAMS, dtype=np.float32)
+        _check(_lib.eg_net_loss_grad(op._h, self._h, _ptr(r), _ptr(e), ctypes.byref(loss),
+                                     g.ctypes.data_as(ctypes.c_void_p)))
+        return loss.value, g
+
+    @staticmethod
+    def _pairs(ops, pair_op):
+        import numpy as np
+        arr = (ctypes.c_void_p * len(ops))(*[o._h.value for o in ops])
+        po = np.ascontiguousarray(pair_op, dtype=np.int32)
+        return arr, po
+
+    def train(self, ops, r, e, pair_op, epochs: int, batch: int = 16, lr: float = 1e-3, seed: int = 0):
+        """Adam training; returns the per-epoch mean training loss (numpy array)."""
+        import numpy as np
+        ops[0]._bind_stream()
+        arr, po = self._pairs(ops, pair_op)
+        hist = np.zeros(max(epochs, 1))
+        _check(_lib.eg_net_train(self._h, arr, len(ops), _ptr(r), _ptr(e), po.ctypes.data_as(ctypes.c_void_p),
+                                 po.size, int(epochs), int(batch), float(lr), int(seed),
+                                 hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return hist[:epochs]
+
+    def eval(self, ops, r, e, pair_op) -> float:
+        ops[0]._bind_stream()
+        arr, po = self._pairs(ops, pair_op)
+        out = ctypes.c_double()
+        _check(_lib.eg_net_eval(self._h, arr, len(ops), _ptr(r), _ptr(e), po.ctypes.data_as(ctypes.c_void_p),
+                                po.size, ctypes.byref(out)))
         return out.value

@@ -33,9 +33,10 @@ struct alignas(64) Scalars {
     double ss;          // ||s||^2 of the current iteration
     double last_rel;    // last recursive relative residual
     double eps_bd;      // breakdown threshold (relative cosine)
-    double pn2;         // ||q||^2 of the vector fed to the learned preconditioner
     double aux0;        // tolerance of this run (read by FIN_INIT)
-    double aux1;
+    double net_q2;      // learned preconditioner: ||q||^2 of its input
+    double net_z2;      //   ||T^{-1} q||^2
+    double net_ee;      //   ||e||^2 of the training target
     int iter;           // iterations completed in this run
     int maxit;
     int done;           // 1: nothing more to do (status says why)
@@ -97,9 +98,10 @@ void launch_residual(const OpView<double> &op, const double *b, const double *x,
                      int *nrows, hipStream_t s);
 
 enum ThomasMode { TH_PLAIN = 0, TH_P = 1, TH_S = 2 };
+// stop_mask: flags that make a TH_PLAIN launch return at once (TH_P / TH_S use their own)
 template <typename Tv>
 void launch_thomas(const TriView<Tv> &tv, const Tv *q, Tv *z, int mode, const Tv *r, Tv *p, const Tv *v, Tv *rhat,
-                   double *partials, int *nrows, const Scalars *sc, hipStream_t s);
+                   double *partials, int *nrows, const Scalars *sc, hipStream_t s, int stop_mask = 0);
 template <typename Tf>
 void launch_tri_factor(const double *a64, const double *m64, int nlon, int nlat, int nlev, Tf *f, hipStream_t s);
 
@@ -109,15 +111,21 @@ void launch_update(long n, Tv *x, const Tv *ph, const Tv *sh, const Tv *s, const
 
 template <typename Ta, typename Tb>
 void launch_dot(long n, const Ta *a, const Tb *b, double *partials, int *nrows, hipStream_t s);
+// partial columns 0 and 1: <a, b> and <c, d> (FP64 products and sums)
+template <typename T>
+void launch_dot2(long n, const T *a, const T *b, const T *c, const T *d, double *partials, int *nrows,
+                 const Scalars *sc, int stop_mask, hipStream_t s);
 
 // finalize kernels (one workgroup): reduce partials, update the scalar block
-enum FinStage { FIN_INIT = 0, FIN_END = 1, FIN_SIGMA = 2, FIN_S = 3, FIN_OMEGA = 4, FIN_SUM = 5, FIN_TRUE = 6 };
+enum FinStage { FIN_INIT = 0, FIN_END = 1, FIN_SIGMA = 2, FIN_S = 3, FIN_OMEGA = 4, FIN_SUM = 5, FIN_TRUE = 6,
+                FIN_NET = 7, FIN_LOSS = 8 };
 // c_rr / c_nb: partial columns holding ||r||^2 and ||b||^2 (FIN_INIT, FIN_TRUE)
 void launch_finalize(int stage, const double *partials, int nrows, Scalars *sc, double *hist, double *out,
                      int c_rr, int c_nb, hipStream_t s);
 
 template <typename T> void launch_fill(T *p, long n, T v, hipStream_t s);
 void launch_add_correction(long n, double *x, const float *d, hipStream_t s);
+void launch_sub_to_f32(long n, const double *a, const double *b, float *out, hipStream_t s);
 
 // operator setup
 void launch_derive(const double *coeffs, int nlon, int nlat, int nlev, double *a64, double *m64, int *bad,
@@ -126,5 +134,48 @@ void launch_to_fp32(long n, const double *a64, const double *m64, float *a32, fl
 void launch_quantize(int kind, int nlon, int nlat, int nlev, const double *a64, uint16_t *aq, float *qs,
                      hipStream_t s);
 void launch_check_finite(long n, const double *v, int *bad, hipStream_t s);
+
+// ---- learned preconditioner (net.hip) ----
+// flat parameter vector: W1[5][32][4] b1[32] W2[9][32][32] b2[32] W3[5][32][32] b3[32] W4[5][32] b4
+constexpr int kNetParams = 15233;
+constexpr int kNetOffW1 = 0, kNetOffB1 = 640, kNetOffW2 = 672, kNetOffB2 = 9888, kNetOffW3 = 9920,
+              kNetOffB3 = 15040, kNetOffW4 = 15072, kNetOffB4 = 15232;
+constexpr int kNetPartRows = 512;   // rows of per-wave partial weight gradients
+
+struct NetGeo {
+    int nlon, nlat, nlev;
+    long P, n;
+};
+
+// device state of one network: FP32 master weights, gradient, Adam moments, and the BF16
+// copies the MFMA kernels read (w1f [co][tap*4+ci] padded to 32, w2f/w3f [tap][co][ci],
+// w2b/w3b [tap][ci][co] for the transposed convolutions, w4 as BF16-rounded floats)
+struct NetDev {
+    float *theta, *grad, *adam_m, *adam_v, *part;
+    uint16_t *w1f, *w2f, *w3f, *w2b, *w3b;
+    float *w4;
+};
+
+// activations of one application: x0 [n][4], a1..a3 [n][32] (BF16); d1, d2 [n][32] BF16
+// gradient buffers (training only)
+struct NetActs {
+    uint16_t *x0, *a1, *a2, *a3, *d1, *d2;
+};
+
+template <typename Tv, typename Tc>
+void launch_net_features(const NetGeo &g, const Tv *q, const Tv *z0, const Tc *a, uint16_t *x0, const Scalars *sc,
+                         int stop_mask, hipStream_t s);
+void launch_net_forward_layers(const NetGeo &g, const NetDev &d, const NetActs &act, const Scalars *sc, int stop_mask,
+                               hipStream_t s);
+template <typename Tv>
+void launch_net_out(const NetGeo &g, const NetDev &d, const NetActs &act, const Tv *q, Tv *qout, float *delta,
+                    const Scalars *sc, int stop_mask, hipStream_t s);
+void launch_thomas_t(const TriView<float> &tv, const float *y, float *z, hipStream_t s);
+void launch_net_gseed(long n, const float *m, const float *e, float *g, const Scalars *sc, hipStream_t s);
+void launch_net_diff(long n, const float *m, const float *e, float *out, hipStream_t s);
+void launch_net_backward(const NetGeo &g, const NetDev &d, const NetActs &act, const float *u, const Scalars *sc,
+                         float scale, int accumulate, hipStream_t s);
+void launch_net_refresh(const NetDev &d, hipStream_t s);
+void launch_net_adam(const NetDev &d, float lr, int step, hipStream_t s);
 
 }  // namespace eg

@@ -537,7 +537,8 @@ __global__ __launch_bounds__(kWG) void k_thomas(TriView<Tv> tv, const Tv *__rest
 
 template <typename Tv, int NL>
 static int thomas_dispatch_mode(const TriView<Tv> &tv, const Tv *q, Tv *z, int mode, const Tv *r, Tv *p,
-                                const Tv *v, Tv *rhat, double *partials, const Scalars *sc, hipStream_t s)
+                                const Tv *v, Tv *rhat, double *partials, const Scalars *sc, hipStream_t s,
+                                int stop_mask)
 {
     const int nb = (int)((tv.P + kWG - 1) / kWG);
     switch (mode) {
@@ -551,14 +552,14 @@ static int thomas_dispatch_mode(const TriView<Tv> &tv, const Tv *q, Tv *z, int m
         return nb;
     default:
         hipLaunchKernelGGL((k_thomas<Tv, NL, TH_PLAIN>), dim3(nb), dim3(kWG), 0, s, tv, q, z, r, p, v, rhat, partials,
-                           sc, 0);
+                           sc, stop_mask);
         return 0;
     }
 }
 
 template <typename Tv>
 void launch_thomas(const TriView<Tv> &tv, const Tv *q, Tv *z, int mode, const Tv *r, Tv *p, const Tv *v, Tv *rhat,
-                   double *partials, int *nrows, const Scalars *sc, hipStream_t s)
+                   double *partials, int *nrows, const Scalars *sc, hipStream_t s, int stop_mask)
 {
     int rows;
     // Register-resident forward values for the level counts in use, on grids whose columns
@@ -566,13 +567,13 @@ void launch_thomas(const TriView<Tv> &tv, const Tv *q, Tv *z, int mode, const Tv
     // other grid takes the generic path.
     const bool reg = (tv.P % kWG == 0) && ((unsigned long)tv.n * sizeof(Tv) < (1ul << 32));
     if (reg && tv.nlev == 20)
-        rows = thomas_dispatch_mode<Tv, 20>(tv, q, z, mode, r, p, v, rhat, partials, sc, s);
+        rows = thomas_dispatch_mode<Tv, 20>(tv, q, z, mode, r, p, v, rhat, partials, sc, s, stop_mask);
     else if (reg && tv.nlev == 70)
-        rows = thomas_dispatch_mode<Tv, 70>(tv, q, z, mode, r, p, v, rhat, partials, sc, s);
+        rows = thomas_dispatch_mode<Tv, 70>(tv, q, z, mode, r, p, v, rhat, partials, sc, s, stop_mask);
     else if (reg && tv.nlev == 140 && sizeof(Tv) == 4)
-        rows = thomas_dispatch_mode<Tv, (sizeof(Tv) == 4 ? 140 : 0)>(tv, q, z, mode, r, p, v, rhat, partials, sc, s);
+        rows = thomas_dispatch_mode<Tv, (sizeof(Tv) == 4 ? 140 : 0)>(tv, q, z, mode, r, p, v, rhat, partials, sc, s, stop_mask);
     else
-        rows = thomas_dispatch_mode<Tv, 0>(tv, q, z, mode, r, p, v, rhat, partials, sc, s);
+        rows = thomas_dispatch_mode<Tv, 0>(tv, q, z, mode, r, p, v, rhat, partials, sc, s, stop_mask);
     if (nrows) *nrows = rows;
 }
 
@@ -710,6 +711,31 @@ void launch_dot(long n, const Ta *a, const Tb *b, double *partials, int *nrows, 
     if (nrows) *nrows = nb;
 }
 
+template <typename T>
+__global__ __launch_bounds__(kWG) void k_dot2(long n, const T *__restrict__ a, const T *__restrict__ b,
+                                              const T *__restrict__ c, const T *__restrict__ d,
+                                              double *__restrict__ partials, const Scalars *__restrict__ sc,
+                                              int stop_mask)
+{
+    if (stopped(sc, stop_mask)) return;
+    double acc[2] = {0.0, 0.0};
+    const long stride = (long)gridDim.x * kWG;
+    for (long i = (long)blockIdx.x * kWG + threadIdx.x; i < n; i += stride) {
+        acc[0] += static_cast<double>(a[i]) * static_cast<double>(b[i]);
+        acc[1] += static_cast<double>(c[i]) * static_cast<double>(d[i]);
+    }
+    block_sum_store<2>(acc, partials + (long)blockIdx.x * kPartialCols);
+}
+
+template <typename T>
+void launch_dot2(long n, const T *a, const T *b, const T *c, const T *d, double *partials, int *nrows,
+                 const Scalars *sc, int stop_mask, hipStream_t s)
+{
+    const int nb = elementwise_blocks(n);
+    hipLaunchKernelGGL((k_dot2<T>), dim3(nb), dim3(kWG), 0, s, n, a, b, c, d, partials, sc, stop_mask);
+    if (nrows) *nrows = nb;
+}
+
 // ------------------------------------------------------------------------------------------
 // k_finalize: one workgroup.  Fixed-order FP64 reduction of the partial rows, then the
 // scalar part of the iteration (thread 0).
@@ -763,6 +789,16 @@ __global__ __launch_bounds__(kWG) void k_finalize(int stage, const double *__res
         }
         return;
     }
+    case FIN_NET:
+        // norms of the learned preconditioner's input and of its tridiagonal solve
+        sc->net_q2 = s0;
+        sc->net_z2 = s1;
+        return;
+    case FIN_LOSS:
+        // training loss ||m - e||^2 / ||e||^2 of one pair, kept for the gradient seed
+        sc->net_ee = s1;
+        if (out) out[0] = s1 > 0.0 ? s0 / s1 : 0.0;
+        return;
     case FIN_TRUE:
         // restart from a freshly computed true residual (periodic or residual-gap restart)
         sc->rr = tot[c_rr];
@@ -928,6 +964,19 @@ __global__ __launch_bounds__(kWG) void k_add_correction(long n, double *__restri
 void launch_add_correction(long n, double *x, const float *d, hipStream_t s)
 {
     hipLaunchKernelGGL(k_add_correction, dim3(elementwise_blocks(n)), dim3(kWG), 0, s, n, x, d);
+}
+
+// out = float(a - b)   (harvest: error of an iterate against the reference solution)
+__global__ __launch_bounds__(kWG) void k_sub_to_f32(long n, const double *__restrict__ a, const double *__restrict__ b,
+                                                    float *__restrict__ out)
+{
+    const long stride = (long)gridDim.x * kWG;
+    for (long i = (long)blockIdx.x * kWG + threadIdx.x; i < n; i += stride) out[i] = static_cast<float>(a[i] - b[i]);
+}
+
+void launch_sub_to_f32(long n, const double *a, const double *b, float *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_sub_to_f32, dim3(elementwise_blocks(n)), dim3(kWG), 0, s, n, a, b, out);
 }
 
 __global__ __launch_bounds__(kWG) void k_check_finite(long n, const double *__restrict__ v, int *bad)
@@ -1102,9 +1151,10 @@ template void launch_residual<double>(const OpView<double> &, const double *, co
 template void launch_residual<float>(const OpView<double> &, const double *, const double *, float *, double *,
                                      int *, hipStream_t);
 template void launch_thomas<double>(const TriView<double> &, const double *, double *, int, const double *,
-                                    double *, const double *, double *, double *, int *, const Scalars *, hipStream_t);
+                                    double *, const double *, double *, double *, int *, const Scalars *, hipStream_t,
+                                    int);
 template void launch_thomas<float>(const TriView<float> &, const float *, float *, int, const float *, float *,
-                                   const float *, float *, double *, int *, const Scalars *, hipStream_t);
+                                   const float *, float *, double *, int *, const Scalars *, hipStream_t, int);
 template void launch_tri_factor<double>(const double *, const double *, int, int, int, double *, hipStream_t);
 template void launch_tri_factor<float>(const double *, const double *, int, int, int, float *, hipStream_t);
 template void launch_update<double>(long, double *, const double *, const double *, const double *, const double *,
@@ -1113,6 +1163,10 @@ template void launch_update<float>(long, float *, const float *, const float *, 
                                    float *, const float *, double *, int *, const Scalars *, hipStream_t);
 template void launch_dot<double, double>(long, const double *, const double *, double *, int *, hipStream_t);
 template void launch_dot<float, float>(long, const float *, const float *, double *, int *, hipStream_t);
+template void launch_dot2<double>(long, const double *, const double *, const double *, const double *, double *,
+                                  int *, const Scalars *, int, hipStream_t);
+template void launch_dot2<float>(long, const float *, const float *, const float *, const float *, double *, int *,
+                                 const Scalars *, int, hipStream_t);
 template void launch_fill<double>(double *, long, double, hipStream_t);
 template void launch_fill<float>(float *, long, float, hipStream_t);
 

@@ -74,10 +74,25 @@ template <typename T> void dfree(T *&p)
 template <typename Tv> struct Work {
     Tv *r = nullptr, *rh = nullptr, *p = nullptr, *ph = nullptr, *v = nullptr, *s = nullptr, *sh = nullptr,
        *t = nullptr, *x = nullptr;
+    Tv *qp = nullptr;   // learned modes: q + rho * delta before the final tridiagonal solve
     bool ready = false;
 };
 
 }  // namespace
+
+// The learned preconditioner's network: weights, optimiser state, activation and training
+// buffers (grown to the largest grid used).
+struct eg_net {
+    NetDev d{};
+    NetActs act{};
+    long act_cap = 0;
+    bool act_train = false;
+    float *t_z0 = nullptr, *t_qp = nullptr, *t_m = nullptr, *t_diff = nullptr, *t_g = nullptr, *t_u = nullptr;
+    long t_cap = 0;
+    double *d_loss = nullptr;   // per-pair losses of the current pass
+    long loss_cap = 0;
+    int step = 0;               // Adam steps taken
+};
 
 struct eg_operator {
     int nlon = 0, nlat = 0, nlev = 0;
@@ -118,6 +133,8 @@ struct eg_operator {
     eg_info info{};
     std::vector<double> hist_host;
     int hist_count = 0;
+    eg_net *net = nullptr;      // learned preconditioner attached to this operator (not owned)
+    double *harvest_x = nullptr;
 
     OpView<double> view64() const { return {a64, m64, nullptr, nlon, nlat, nlev, P, n}; }
     OpView<float> view32() const { return {a32, m32, nullptr, nlon, nlat, nlev, P, n}; }
@@ -294,6 +311,122 @@ template <typename Tv, typename Tc> int krylov_run(eg_operator *op, const OpView
     return 0;
 }
 
+// ---- learned preconditioner ---------------------------------------------------------------
+int ensure_acts(eg_net *net, long n, bool train)
+{
+    if (n <= net->act_cap && (!train || net->act_train)) return 0;
+    const long cap = std::max(n, net->act_cap);
+    NetActs &a = net->act;
+    dfree(a.x0); dfree(a.a1); dfree(a.a2); dfree(a.a3); dfree(a.d1); dfree(a.d2);
+    net->act_cap = 0;
+    int rc;
+    if ((rc = dalloc(&a.x0, 4 * (size_t)cap)) || (rc = dalloc(&a.a1, 32 * (size_t)cap)) ||
+        (rc = dalloc(&a.a2, 32 * (size_t)cap)) || (rc = dalloc(&a.a3, 32 * (size_t)cap)))
+        return rc;
+    if (train || net->act_train) {
+        if ((rc = dalloc(&a.d1, 32 * (size_t)cap)) || (rc = dalloc(&a.d2, 32 * (size_t)cap))) return rc;
+        net->act_train = true;
+    }
+    net->act_cap = cap;
+    return 0;
+}
+
+int ensure_train_tmp(eg_net *net, long n)
+{
+    if (n <= net->t_cap) return 0;
+    float **bufs[] = {&net->t_z0, &net->t_qp, &net->t_m, &net->t_diff, &net->t_g, &net->t_u};
+    for (float **b : bufs) {
+        dfree(*b);
+        int rc = dalloc(b, (size_t)n);
+        if (rc) return rc;
+    }
+    net->t_cap = n;
+    return 0;
+}
+
+template <typename Tv> int ensure_qp(eg_operator *op, Work<Tv> &w)
+{
+    return w.qp ? 0 : dalloc(&w.qp, (size_t)op->n);
+}
+
+NetGeo geo_of(const eg_operator *op) { return {op->nlon, op->nlat, op->nlev, op->P, op->n}; }
+
+// z (holding T^{-1} q on entry) <- M(q) = T^{-1} (q + rho delta(q)).  Tc: coefficient set the
+// input channels are read from.
+template <typename Tv, typename Tc>
+void enqueue_net_stage(eg_operator *op, eg_net *net, const Tc *coef, const Tv *q, Tv *z, Tv *qp, float *delta,
+                       int stop_mask)
+{
+    hipStream_t s = op->stream;
+    const NetGeo g = geo_of(op);
+    int nr = 0;
+    launch_dot2<Tv>(op->n, q, q, z, z, op->partials, &nr, op->sc, stop_mask, s);
+    launch_finalize(FIN_NET, op->partials, nr, op->sc, nullptr, nullptr, 0, 0, s);
+    launch_net_features<Tv, Tc>(g, q, z, coef, net->act.x0, op->sc, stop_mask, s);
+    launch_net_forward_layers(g, net->d, net->act, op->sc, stop_mask, s);
+    launch_net_out<Tv>(g, net->d, net->act, q, qp, delta, op->sc, stop_mask, s);
+    launch_thomas<Tv>(op->tri_view<Tv>(), qp, z, TH_PLAIN, nullptr, nullptr, nullptr, nullptr, op->partials, nullptr,
+                      op->sc, s, stop_mask);
+}
+
+// One flexible BiCGStab iteration with the learned preconditioner: the recurrences are those
+// of the plain iteration; x is updated with exactly the phat, shat that were multiplied by A.
+template <typename Tv, typename Tc>
+void enqueue_iteration_learned(eg_operator *op, const OpView<Tc> &A, Work<Tv> &w, eg_net *net, const Tc *coef)
+{
+    hipStream_t s = op->stream;
+    const TriView<Tv> T = op->tri_view<Tv>();
+    int nr = 0;
+    launch_thomas<Tv>(T, nullptr, w.ph, TH_P, w.r, w.p, w.v, w.rh, op->partials, &nr, op->sc, s);
+    enqueue_net_stage<Tv, Tc>(op, net, coef, w.p, w.ph, w.qp, nullptr, STOP_DONE);
+    launch_spmv<Tv, Tc>(A, w.ph, w.v, w.rh, SP_DOT2, op->partials, &nr, op->sc, STOP_DONE, s);
+    launch_finalize(FIN_SIGMA, op->partials, nr, op->sc, op->d_hist, nullptr, 0, 0, s);
+    launch_thomas<Tv>(T, nullptr, w.sh, TH_S, w.r, w.s, w.v, nullptr, op->partials, &nr, op->sc, s);
+    launch_finalize(FIN_S, op->partials, nr, op->sc, op->d_hist, nullptr, 0, 0, s);
+    enqueue_net_stage<Tv, Tc>(op, net, coef, w.s, w.sh, w.qp, nullptr, STOP_DONE | STOP_SKIP | STOP_HALF);
+    launch_spmv<Tv, Tc>(A, w.sh, w.t, w.s, SP_DOT2, op->partials, &nr, op->sc, STOP_DONE | STOP_SKIP | STOP_HALF, s);
+    launch_finalize(FIN_OMEGA, op->partials, nr, op->sc, op->d_hist, nullptr, 0, 0, s);
+    launch_update<Tv>(op->n, w.x, w.ph, w.sh, w.s, w.t, w.r, w.rh, op->partials, &nr, op->sc, s);
+    launch_finalize(FIN_END, op->partials, nr, op->sc, op->d_hist, nullptr, 0, 0, s);
+}
+
+// Krylov run with the learned preconditioner, checked after every iteration.  Stall rule:
+// the best residual has not halved within stall_window iterations, or the residual exceeds
+// 1e3 times the best, or the iteration broke down.  On a stall *fallback is set and the run
+// returns with the device state mid-run; the caller continues with T^{-1} alone.
+template <typename Tv, typename Tc>
+int krylov_run_learned(eg_operator *op, const OpView<Tc> &A, Work<Tv> &w, eg_net *net, const Tc *coef,
+                       int *fallback)
+{
+    *fallback = 0;
+    int rc;
+    if ((rc = sync_scalars(op))) return rc;
+    double best = op->h_sc->last_rel, anchor = best;
+    int anchor_it = op->h_sc->iter;
+    while (!op->h_sc->done) {
+        enqueue_iteration_learned<Tv, Tc>(op, A, w, net, coef);
+        EG_HIP(hipGetLastError());
+        if ((rc = sync_scalars(op))) return rc;
+        const Scalars &h = *op->h_sc;
+        if (h.done && h.status == 2) {   // breakdown: hand over to the plain preconditioner
+            *fallback = 1;
+            return 0;
+        }
+        if (h.done) break;
+        const double R = h.last_rel;
+        best = std::min(best, R);
+        if (R <= 0.5 * anchor) {
+            anchor = R;
+            anchor_it = h.iter;
+        }
+        if (h.iter - anchor_it >= op->stall_window || R > 1e3 * best || !std::isfinite(R)) {
+            *fallback = 1;
+            return 0;
+        }
+    }
+    return 0;
+}
+
 double fetch_out(eg_operator *op, int idx)
 {
     return op->h_out[idx];
@@ -325,10 +458,11 @@ int check_vectors(eg_operator *op, const double *b, const double *x)
 }
 
 // ---- plain FP64 BiCGStab --------------------------------------------------------------------
-int solve_fp64(eg_operator *op, const double *b, double *x, double tol, int maxit)
+int solve_fp64(eg_operator *op, const double *b, double *x, double tol, int maxit, eg_net *net = nullptr)
 {
     int rc;
     if ((rc = ensure_work(op, op->w64))) return rc;
+    if (net && ((rc = ensure_qp(op, op->w64)) || (rc = ensure_acts(net, op->n, false)))) return rc;
     Work<double> &w = op->w64;
     hipStream_t s = op->stream;
     const OpView<double> A = op->view64();
@@ -346,8 +480,23 @@ int solve_fp64(eg_operator *op, const double *b, double *x, double tol, int maxi
         return EG_CONVERGED;
     }
     int gap = 0, status = EG_CONVERGED;
+    bool use_net = net != nullptr;
     for (;;) {
-        if ((rc = krylov_run<double, double>(op, A, w))) return rc;
+        if (use_net) {
+            int fb = 0;
+            if ((rc = krylov_run_learned<double, double>(op, A, w, net, op->a64, &fb))) return rc;
+            if (fb) {   // stall: continue with T^{-1}, restarted from the true residual
+                use_net = false;
+                op->info.fallbacks += 1;
+                if (op->h_sc->iter >= op->h_sc->maxit) { status = EG_MAXIT; break; }
+                launch_residual<double>(A, b, w.x, w.r, op->partials, &nr, s);
+                launch_finalize(FIN_TRUE, op->partials, nr, op->sc, nullptr, nullptr, 0, 1, s);
+                EG_HIP(hipGetLastError());
+                continue;
+            }
+        } else if ((rc = krylov_run<double, double>(op, A, w))) {
+            return rc;
+        }
         const Scalars &h = *op->h_sc;
         if (h.status == 4) {   // periodic restart: fresh true residual
             launch_residual<double>(A, b, w.x, w.r, op->partials, &nr, s);
@@ -382,10 +531,13 @@ int solve_fp64(eg_operator *op, const double *b, double *x, double tol, int maxi
 
 // ---- FP64 refinement around an FP32 inner BiCGStab ------------------------------------------
 template <typename Tc>
-int solve_ir(eg_operator *op, const OpView<Tc> &A32, const double *b, double *x, double tol, int maxit)
+int solve_ir(eg_operator *op, const OpView<Tc> &A32, const double *b, double *x, double tol, int maxit,
+             eg_net *net = nullptr)
 {
     int rc;
     if ((rc = ensure_work(op, op->w32))) return rc;
+    if (net && ((rc = ensure_qp(op, op->w32)) || (rc = ensure_acts(net, op->n, false)))) return rc;
+    bool use_net = net != nullptr;
     Work<float> &w = op->w32;
     hipStream_t s = op->stream;
     int total = 0, outer = 0, status = EG_MAXIT, stalls = 0, restarts = 0;
@@ -416,7 +568,7 @@ int solve_ir(eg_operator *op, const OpView<Tc> &A32, const double *b, double *x,
         if (total >= maxit) { status = EG_MAXIT; break; }
         if (outer >= op->max_outer) { status = EG_STALLED; break; }
         if (rel > 0.5 * rel_prev) {
-            if (++stalls >= 2) { status = EG_STALLED; break; }
+            if (++stalls >= (net ? 3 : 2)) { status = EG_STALLED; break; }
         } else {
             stalls = 0;
         }
@@ -427,7 +579,20 @@ int solve_ir(eg_operator *op, const OpView<Tc> &A32, const double *b, double *x,
         launch_finalize(FIN_INIT, op->partials, nr, op->sc, op->d_hist, nullptr, 2, 2, s);
         launch_fill<float>(w.x, op->n, 0.0f, s);
         EG_HIP(hipGetLastError());
-        if ((rc = krylov_run<float, Tc>(op, A32, w))) return rc;
+        if constexpr (std::is_same_v<Tc, float>) {
+            if (use_net) {
+                int fb = 0;
+                if ((rc = krylov_run_learned<float, float>(op, A32, w, net, op->a32, &fb))) return rc;
+                if (fb) {   // stall: this refinement step ends here, the next ones use T^{-1}
+                    use_net = false;
+                    op->info.fallbacks += 1;
+                }
+            } else if ((rc = krylov_run<float, Tc>(op, A32, w))) {
+                return rc;
+            }
+        } else if ((rc = krylov_run<float, Tc>(op, A32, w))) {
+            return rc;
+        }
         total += op->h_sc->iter;
         restarts += op->h_sc->restarts;
         launch_add_correction(op->n, x, w.x, s);
@@ -439,6 +604,79 @@ int solve_ir(eg_operator *op, const OpView<Tc> &A32, const double *b, double *x,
     op->info.restarts = restarts;
     op->hist_count = total;
     return status;
+}
+
+// ---- network training pieces ---------------------------------------------------------------
+uint64_t splitmix64(uint64_t &s)
+{
+    uint64_t z = (s += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+double uniform01(uint64_t &s) { return ((splitmix64(s) >> 11) + 0.5) * (1.0 / 9007199254740992.0); }
+
+double std_normal(uint64_t &s)   // Box-Muller
+{
+    const double u1 = uniform01(s), u2 = uniform01(s);
+    return std::sqrt(-2.0 * std::log(u1)) * std::cos(6.283185307179586 * u2);
+}
+
+// One training pair on the first operator's stream: forward, loss ||M(r) - e||^2 / ||e||^2
+// into *loss_slot (device), and (if backward) the parameter gradient scaled by `scale` into
+// net->d.grad (added to it when accumulate is set).
+int net_pair_pass(eg_net *net, eg_operator *op, const float *r, const float *e, bool backward, float scale,
+                  int accumulate, double *loss_slot, hipStream_t s)
+{
+    int rc;
+    if ((rc = ensure_fp32(op)) || (rc = ensure_acts(net, op->n, backward)) || (rc = ensure_train_tmp(net, op->n)))
+        return rc;
+    const long n = op->n;
+    const NetGeo g = geo_of(op);
+    const TriView<float> T = op->tri_view32();
+    int nr = 0;
+    launch_thomas<float>(T, r, net->t_z0, TH_PLAIN, nullptr, nullptr, nullptr, nullptr, op->partials, nullptr, nullptr,
+                         s);
+    launch_dot2<float>(n, r, r, net->t_z0, net->t_z0, op->partials, &nr, nullptr, 0, s);
+    launch_finalize(FIN_NET, op->partials, nr, op->sc, nullptr, nullptr, 0, 0, s);
+    launch_net_features<float, float>(g, r, net->t_z0, op->a32, net->act.x0, op->sc, 0, s);
+    launch_net_forward_layers(g, net->d, net->act, op->sc, 0, s);
+    launch_net_out<float>(g, net->d, net->act, r, net->t_qp, nullptr, op->sc, 0, s);
+    launch_thomas<float>(T, net->t_qp, net->t_m, TH_PLAIN, nullptr, nullptr, nullptr, nullptr, op->partials, nullptr,
+                         nullptr, s);
+    launch_net_diff(n, net->t_m, e, net->t_diff, s);
+    launch_dot2<float>(n, net->t_diff, net->t_diff, e, e, op->partials, &nr, nullptr, 0, s);
+    launch_finalize(FIN_LOSS, op->partials, nr, op->sc, nullptr, loss_slot, 0, 0, s);
+    if (backward) {
+        launch_net_gseed(n, net->t_m, e, net->t_g, op->sc, s);
+        launch_thomas_t(T, net->t_g, net->t_u, s);
+        launch_net_backward(g, net->d, net->act, net->t_u, op->sc, scale, accumulate, s);
+    }
+    EG_HIP(hipGetLastError());
+    return 0;
+}
+
+int ensure_loss(eg_net *net, long npairs)
+{
+    if (npairs <= net->loss_cap) return 0;
+    dfree(net->d_loss);
+    int rc = dalloc(&net->d_loss, (size_t)npairs);
+    if (rc) return rc;
+    net->loss_cap = npairs;
+    return 0;
+}
+
+int check_pairs(eg_operator *const *ops, int nops, const float *r, const float *e, const int *pair_op, int npairs)
+{
+    if (!ops || nops < 1 || !r || !e || !pair_op || npairs < 1) return fail(EG_EINVAL, "bad training arguments");
+    for (int i = 0; i < nops; ++i) {
+        if (!ops[i]) return fail(EG_EINVAL, "NULL operator in the list");
+        if (ops[i]->n != ops[0]->n) return fail(EG_EINVAL, "all training operators must have the same grid");
+    }
+    for (int i = 0; i < npairs; ++i)
+        if (pair_op[i] < 0 || pair_op[i] >= nops) return fail(EG_EINVAL, "pair_op index out of range");
+    return 0;
 }
 
 }  // namespace
@@ -457,6 +695,9 @@ void eg_destroy_operator(eg_operator *op)
     dfree(op->a64); dfree(op->m64); dfree(op->tri64);
     dfree(op->a32); dfree(op->m32); dfree(op->tri32);
     for (int i = 0; i < 2; ++i) { dfree(op->aq[i]); dfree(op->qs[i]); }
+    dfree(op->harvest_x);
+    dfree(op->w64.qp);
+    dfree(op->w32.qp);
     for (Work<double> *w : {&op->w64}) {
         dfree(w->r); dfree(w->rh); dfree(w->p); dfree(w->ph); dfree(w->v); dfree(w->s); dfree(w->sh);
         dfree(w->t); dfree(w->x);
@@ -565,7 +806,8 @@ int eg_solve(eg_operator *op, const double *b, double *x, double tol, int maxit,
     if (!op || !b || !x) return fail(EG_EINVAL, "NULL argument");
     if (!(tol > 0.0) || maxit < 1) return fail(EG_EINVAL, "need tol > 0 and maxit >= 1");
     if (mode < EG_FP64 || mode > EG_LEARNED_FP32_IR) return fail(EG_EINVAL, "unknown mode");
-    if (mode >= EG_LEARNED_FP64) return fail(EG_ENOPC, "no learned preconditioner has been trained or loaded");
+    if (mode >= EG_LEARNED_FP64 && !op->net)
+        return fail(EG_ENOPC, "no learned preconditioner is attached to this operator (eg_attach_learned_pc)");
     const auto t0 = std::chrono::steady_clock::now();
     op->info = eg_info{};
     op->hist_count = 0;
@@ -585,9 +827,16 @@ int eg_solve(eg_operator *op, const double *b, double *x, double tol, int maxit,
         if ((rc = ensure_quant(op, PBF16))) return rc;
         status = solve_ir<bf16_t>(op, op->viewq<bf16_t>(0), b, x, tol, maxit);
         break;
-    default:
+    case EG_FP32_IR_FP16:
         if ((rc = ensure_quant(op, PFP16))) return rc;
         status = solve_ir<fp16_t>(op, op->viewq<fp16_t>(1), b, x, tol, maxit);
+        break;
+    case EG_LEARNED_FP64:
+        status = solve_fp64(op, b, x, tol, maxit, op->net);
+        break;
+    default:
+        if ((rc = ensure_fp32(op))) return rc;
+        status = solve_ir<float>(op, op->view32(), b, x, tol, maxit, op->net);
         break;
     }
     if (status < 0) return status;
@@ -710,6 +959,208 @@ int eg_dot(eg_operator *op, const void *a, const void *b, long n, int prec, doub
     EG_HIP(hipMemcpyAsync(op->h_out, op->d_out, 4 * sizeof(double), hipMemcpyDeviceToHost, op->stream));
     EG_HIP(hipStreamSynchronize(op->stream));
     *out_host = op->h_out[0];
+    return 0;
+}
+
+// ---------------------------------------------------------------------------------------------
+// learned preconditioner
+// ---------------------------------------------------------------------------------------------
+void eg_net_destroy(eg_net *net)
+{
+    if (!net) return;
+    (void)hipDeviceSynchronize();
+    NetDev &d = net->d;
+    dfree(d.theta); dfree(d.grad); dfree(d.adam_m); dfree(d.adam_v); dfree(d.part);
+    dfree(d.w1f); dfree(d.w2f); dfree(d.w3f); dfree(d.w2b); dfree(d.w3b); dfree(d.w4);
+    NetActs &a = net->act;
+    dfree(a.x0); dfree(a.a1); dfree(a.a2); dfree(a.a3); dfree(a.d1); dfree(a.d2);
+    dfree(net->t_z0); dfree(net->t_qp); dfree(net->t_m); dfree(net->t_diff); dfree(net->t_g); dfree(net->t_u);
+    dfree(net->d_loss);
+    delete net;
+}
+
+int eg_net_set_weights(eg_net *net, const float *host, long count)
+{
+    if (!net || !host) return fail(EG_EINVAL, "NULL argument");
+    if (count != kNetParams) return fail(EG_EINVAL, "expected " + std::to_string(kNetParams) + " weights");
+    EG_HIP(hipMemcpy(net->d.theta, host, kNetParams * sizeof(float), hipMemcpyHostToDevice));
+    EG_HIP(hipMemset(net->d.adam_m, 0, kNetParams * sizeof(float)));
+    EG_HIP(hipMemset(net->d.adam_v, 0, kNetParams * sizeof(float)));
+    net->step = 0;
+    launch_net_refresh(net->d, nullptr);
+    EG_HIP(hipGetLastError());
+    EG_HIP(hipDeviceSynchronize());
+    return 0;
+}
+
+int eg_net_get_weights(const eg_net *net, float *host, long cap)
+{
+    if (!net) return fail(EG_EINVAL, "NULL net");
+    if (host && cap >= kNetParams) {
+        EG_HIP(hipDeviceSynchronize());
+        EG_HIP(hipMemcpy(host, net->d.theta, kNetParams * sizeof(float), hipMemcpyDeviceToHost));
+    }
+    return kNetParams;
+}
+
+int eg_net_create(unsigned long long seed, eg_net **out)
+{
+    if (!out) return fail(EG_EINVAL, "out is NULL");
+    *out = nullptr;
+    eg_net *net = new eg_net();
+    NetDev &d = net->d;
+    int rc;
+    if ((rc = dalloc(&d.theta, kNetParams)) || (rc = dalloc(&d.grad, kNetParams)) ||
+        (rc = dalloc(&d.adam_m, kNetParams)) || (rc = dalloc(&d.adam_v, kNetParams)) ||
+        (rc = dalloc(&d.part, (size_t)kNetPartRows * kNetParams)) || (rc = dalloc(&d.w1f, 32 * 32)) ||
+        (rc = dalloc(&d.w2f, 9 * 1024)) || (rc = dalloc(&d.w3f, 5 * 1024)) || (rc = dalloc(&d.w2b, 9 * 1024)) ||
+        (rc = dalloc(&d.w3b, 5 * 1024)) || (rc = dalloc(&d.w4, 160))) {
+        eg_net_destroy(net);
+        return rc;
+    }
+    if (hipMemset(d.w1f, 0, 32 * 32 * sizeof(uint16_t)) != hipSuccess) {
+        eg_net_destroy(net);
+        return fail(EG_EHIP, "memset");
+    }
+    // He-normal weights (splitmix64 + Box-Muller), zero biases, zero output layer: M = T^{-1}
+    std::vector<float> th(kNetParams, 0.f);
+    uint64_t st = seed;
+    auto fill = [&](int lo, int hi, double sd) {
+        for (int i = lo; i < hi; ++i) th[i] = static_cast<float>(sd * std_normal(st));
+    };
+    fill(kNetOffW1, kNetOffB1, std::sqrt(2.0 / 20.0));
+    fill(kNetOffW2, kNetOffB2, std::sqrt(2.0 / 288.0));
+    fill(kNetOffW3, kNetOffB3, std::sqrt(2.0 / 160.0));
+    if ((rc = eg_net_set_weights(net, th.data(), kNetParams))) {
+        eg_net_destroy(net);
+        return rc;
+    }
+    *out = net;
+    return 0;
+}
+
+int eg_attach_learned_pc(eg_operator *op, eg_net *net)
+{
+    if (!op) return fail(EG_EINVAL, "op is NULL");
+    op->net = net;
+    return 0;
+}
+
+int eg_net_apply(eg_operator *op, eg_net *net, const float *q, float *z, float *delta)
+{
+    if (!op || !net || !q || !z) return fail(EG_EINVAL, "NULL argument");
+    int rc;
+    if ((rc = ensure_fp32(op)) || (rc = ensure_acts(net, op->n, false)) || (rc = ensure_train_tmp(net, op->n)))
+        return rc;
+    hipStream_t s = op->stream;
+    launch_thomas<float>(op->tri_view32(), q, z, TH_PLAIN, nullptr, nullptr, nullptr, nullptr, op->partials, nullptr,
+                         nullptr, s);
+    enqueue_net_stage<float, float>(op, net, op->a32, q, z, net->t_qp, delta, 0);
+    EG_HIP(hipGetLastError());
+    EG_HIP(hipStreamSynchronize(s));
+    return 0;
+}
+
+int eg_net_loss_grad(eg_operator *op, eg_net *net, const float *r, const float *e, double *loss_host,
+                     float *grad_host)
+{
+    if (!op || !net || !r || !e) return fail(EG_EINVAL, "NULL argument");
+    int rc;
+    if ((rc = ensure_loss(net, 1))) return rc;
+    if ((rc = net_pair_pass(net, op, r, e, true, 1.f, 0, net->d_loss, op->stream))) return rc;
+    EG_HIP(hipStreamSynchronize(op->stream));
+    if (loss_host) EG_HIP(hipMemcpy(loss_host, net->d_loss, sizeof(double), hipMemcpyDeviceToHost));
+    if (grad_host) EG_HIP(hipMemcpy(grad_host, net->d.grad, kNetParams * sizeof(float), hipMemcpyDeviceToHost));
+    return 0;
+}
+
+int eg_harvest(eg_operator *op, const double *b, int nsnap, float *r_out, float *e_out)
+{
+    if (!op || !b || !r_out || !e_out || nsnap < 1) return fail(EG_EINVAL, "bad argument");
+    int rc;
+    if ((rc = check_vectors(op, b, b))) return rc;
+    if (!op->harvest_x && (rc = dalloc(&op->harvest_x, (size_t)op->n))) return rc;
+    if ((rc = ensure_hist(op, 20000))) return rc;
+    hipStream_t s = op->stream;
+    // reference solution (as tight as FP64 allows)
+    launch_fill<double>(op->harvest_x, op->n, 0.0, s);
+    const int st = solve_fp64(op, b, op->harvest_x, 1e-12, 20000);
+    if (st < 0) return st;
+    // iterates of a fresh solve from x0 = 0, one snapshot after every iteration
+    Work<double> &w = op->w64;
+    const OpView<double> A = op->view64();
+    launch_fill<double>(w.x, op->n, 0.0, s);
+    if ((rc = put_run_params(op, 1e-300, nsnap, 0, 0))) return rc;
+    int nr = 0;
+    launch_residual<double>(A, b, w.x, w.r, op->partials, &nr, s);
+    launch_finalize(FIN_INIT, op->partials, nr, op->sc, op->d_hist, nullptr, 0, 1, s);
+    int count = 0;
+    for (int i = 0; i < nsnap; ++i) {
+        if ((rc = sync_scalars(op))) return rc;
+        if (op->h_sc->done) break;
+        enqueue_iteration<double, double>(op, A, w, nullptr);
+        launch_residual<float>(A, b, w.x, r_out + (size_t)i * op->n, op->partials, &nr, s);
+        launch_sub_to_f32(op->n, op->harvest_x, w.x, e_out + (size_t)i * op->n, s);
+        EG_HIP(hipGetLastError());
+        ++count;
+    }
+    EG_HIP(hipStreamSynchronize(s));
+    return count;
+}
+
+int eg_net_train(eg_net *net, eg_operator *const *ops, int nops, const float *r, const float *e, const int *pair_op,
+                 int npairs, int epochs, int batch, double lr, unsigned long long seed, double *loss_hist)
+{
+    if (!net || epochs < 0 || batch < 1 || !(lr > 0.0)) return fail(EG_EINVAL, "bad training arguments");
+    int rc;
+    if ((rc = check_pairs(ops, nops, r, e, pair_op, npairs)) || (rc = ensure_loss(net, npairs))) return rc;
+    hipStream_t s = ops[0]->stream;
+    const size_t n = (size_t)ops[0]->n;
+    std::vector<int> order(npairs);
+    std::vector<double> losses(npairs);
+    for (int ep = 0; ep < epochs; ++ep) {
+        for (int i = 0; i < npairs; ++i) order[i] = i;
+        uint64_t st = seed * 1000003ull + (uint64_t)ep;
+        for (int i = npairs - 1; i > 0; --i) std::swap(order[i], order[splitmix64(st) % (uint64_t)(i + 1)]);
+        for (int b0 = 0; b0 < npairs; b0 += batch) {
+            const int b1 = std::min(npairs, b0 + batch);
+            const float scale = 1.f / (float)(b1 - b0);
+            for (int k = b0; k < b1; ++k) {
+                const int pi = order[k];
+                if ((rc = net_pair_pass(net, ops[pair_op[pi]], r + (size_t)pi * n, e + (size_t)pi * n, true, scale,
+                                        k > b0, net->d_loss + k, s)))
+                    return rc;
+            }
+            net->step += 1;
+            launch_net_adam(net->d, (float)lr, net->step, s);
+            EG_HIP(hipGetLastError());
+        }
+        EG_HIP(hipMemcpyAsync(losses.data(), net->d_loss, npairs * sizeof(double), hipMemcpyDeviceToHost, s));
+        EG_HIP(hipStreamSynchronize(s));
+        double m = 0.0;
+        for (double v : losses) m += v;
+        if (loss_hist) loss_hist[ep] = m / npairs;
+    }
+    return 0;
+}
+
+int eg_net_eval(eg_net *net, eg_operator *const *ops, int nops, const float *r, const float *e, const int *pair_op,
+                int npairs, double *mean_loss)
+{
+    if (!net || !mean_loss) return fail(EG_EINVAL, "NULL argument");
+    int rc;
+    if ((rc = check_pairs(ops, nops, r, e, pair_op, npairs)) || (rc = ensure_loss(net, npairs))) return rc;
+    hipStream_t s = ops[0]->stream;
+    const size_t n = (size_t)ops[0]->n;
+    for (int i = 0; i < npairs; ++i)
+        if ((rc = net_pair_pass(net, ops[pair_op[i]], r + i * n, e + i * n, false, 1.f, 0, net->d_loss + i, s)))
+            return rc;
+    std::vector<double> losses(npairs);
+    EG_HIP(hipMemcpyAsync(losses.data(), net->d_loss, npairs * sizeof(double), hipMemcpyDeviceToHost, s));
+    EG_HIP(hipStreamSynchronize(s));
+    double m = 0.0;
+    for (double v : losses) m += v;
+    *mean_loss = m / npairs;
     return 0;
 }
 

@@ -1,0 +1,660 @@
+// Learned right preconditioner: network kernels (gfx950, BF16 MFMA with FP32 accumulation).
+//
+//   M(q) = T^{-1} (q + rho * delta(q)),   rho = rms(q)
+//
+// delta is produced per grid point from four input channels
+//   x0 = [ q / rho,  T^{-1}q / rms(T^{-1}q),  D + U,  W + E + S + N ]
+// by conv1d over levels (4 -> 32, 5 taps) -> ReLU -> 3x3 horizontal mixing (32 -> 32) -> ReLU
+// -> conv1d (32 -> 32, 5 taps) -> ReLU -> conv1d (32 -> 1, 5 taps).  The exact tridiagonal
+// solve of the paper's preconditioner (Sec. 2, Eq. 6-7) is kept on both sides; the network
+// only adds a correction in residual space, and with its last layer zero M is exactly T^{-1}.
+//
+// Layouts: activations are [position][32] BF16 (64 bytes per grid point; position = the grid
+// index i + nlon (j + nlat k)); x0 is [position][4] BF16.  Each conv layer is a GEMM whose
+// K dimension is (tap, input channel): one 16x16x32 MFMA per (tap, 16-wide output tile) over a
+// tile of 16 positions.  MFMA operand layout (verified on gfx950): lane l supplies row l % 16
+// and K elements 8 (l / 16) .. 8 (l / 16) + 7 of A (and column l % 16 of B); the result lane
+// l holds column l % 16 of rows 4 (l / 16) .. 4 (l / 16) + 3.
+#include <cmath>
+
+#include "eg_internal.h"
+
+namespace eg {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+namespace {
+
+__device__ __forceinline__ uint16_t f2bf(float f) { return __builtin_bit_cast(uint16_t, static_cast<__bf16>(f)); }
+__device__ __forceinline__ float bf2f(uint16_t u) { return __uint_as_float(static_cast<uint32_t>(u) << 16); }
+
+__device__ __forceinline__ bf16x8 ld8(const uint16_t *row)
+{
+    return __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(row));
+}
+
+__device__ __forceinline__ bf16x8 zero8() { return __builtin_bit_cast(bf16x8, make_uint4(0, 0, 0, 0)); }
+
+__device__ __forceinline__ f32x4 mfma(bf16x8 a, bf16x8 b, f32x4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+struct Pos {
+    int i, j, k;
+};
+
+__device__ __forceinline__ Pos decompose(const NetGeo &g, long p)
+{
+    Pos r;
+    r.i = (int)(p % g.nlon);
+    const long q = p / g.nlon;
+    r.j = (int)(q % g.nlat);
+    r.k = (int)(q / g.nlat);
+    return r;
+}
+
+// neighbour of position p for a vertical tap offset dk (-1 if outside the column)
+__device__ __forceinline__ long nb_v(const NetGeo &g, long p, const Pos &x, int dk)
+{
+    const int k2 = x.k + dk;
+    return (k2 < 0 || k2 >= g.nlev) ? -1 : p + (long)dk * g.P;
+}
+
+// neighbour for a horizontal offset (di, dj): periodic in longitude, -1 across a pole
+__device__ __forceinline__ long nb_h(const NetGeo &g, long p, const Pos &x, int di, int dj)
+{
+    const int j2 = x.j + dj;
+    if (j2 < 0 || j2 >= g.nlat) return -1;
+    int i2 = x.i + di;
+    if (i2 < 0) i2 += g.nlon;
+    else if (i2 >= g.nlon) i2 -= g.nlon;
+    return p + (i2 - x.i) + (long)dj * g.nlon;
+}
+
+// layer geometry: L1 and L3 are vertical (5 taps, offset t - 2), L2 is horizontal (9 taps)
+template <int L> struct LayerGeo {
+    static constexpr int T = (L == 2) ? 9 : 5;
+    __device__ static __forceinline__ long nb(const NetGeo &g, long p, const Pos &x, int t, bool mirror)
+    {
+        const int s = mirror ? -1 : 1;
+        if constexpr (L == 2) return nb_h(g, p, x, s * (t % 3 - 1), s * (t / 3 - 1));
+        else return nb_v(g, p, x, s * (t - 2));
+    }
+};
+
+__device__ __forceinline__ bool stop_now(const Scalars *sc, int mask)
+{
+    if (!sc || !mask) return false;
+    return ((mask & STOP_DONE) && sc->done) || ((mask & STOP_SKIP) && sc->skip) || ((mask & STOP_HALF) && sc->half);
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------------------------------
+// input channels
+// ------------------------------------------------------------------------------------------
+template <typename Tv, typename Tc>
+__global__ __launch_bounds__(256) void k_net_features(NetGeo g, const Tv *__restrict__ q, const Tv *__restrict__ z0,
+                                                      const Tc *__restrict__ a, uint16_t *__restrict__ x0,
+                                                      const Scalars *__restrict__ sc, int stop_mask)
+{
+    if (stop_now(sc, stop_mask)) return;
+    const double inv_rho = 1.0 / sqrt(sc->net_q2 / (double)g.n);
+    const double inv_rhoz = sc->net_z2 > 0.0 ? 1.0 / sqrt(sc->net_z2 / (double)g.n) : 0.0;
+    const long stride = (long)gridDim.x * 256;
+    for (long p = (long)blockIdx.x * 256 + threadIdx.x; p < g.n; p += stride) {
+        const float c0 = static_cast<float>(static_cast<double>(q[p]) * inv_rho);
+        const float c1 = static_cast<float>(static_cast<double>(z0[p]) * inv_rhoz);
+        const float c2 = static_cast<float>(a[4 * g.n + p]) + static_cast<float>(a[5 * g.n + p]);
+        const float c3 = (static_cast<float>(a[p]) + static_cast<float>(a[g.n + p])) +
+                         (static_cast<float>(a[2 * g.n + p]) + static_cast<float>(a[3 * g.n + p]));
+        uint2 v;
+        v.x = static_cast<uint32_t>(f2bf(c0)) | (static_cast<uint32_t>(f2bf(c1)) << 16);
+        v.y = static_cast<uint32_t>(f2bf(c2)) | (static_cast<uint32_t>(f2bf(c3)) << 16);
+        reinterpret_cast<uint2 *>(x0)[p] = v;
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// conv layer, forward:  out[p][co] = ReLU(bias[co] + sum_{t, ci} W[t][co][ci] in[nb(p, t)][ci])
+// One wave per tile of 16 positions (waves stride over tiles); the layer's weights stay in
+// registers for the whole launch.
+// ------------------------------------------------------------------------------------------
+template <int L>
+__global__ __launch_bounds__(256) void k_conv_fwd(NetGeo g, const uint16_t *__restrict__ in,
+                                                  const uint16_t *__restrict__ wf, const float *__restrict__ bias,
+                                                  uint16_t *__restrict__ out, const Scalars *__restrict__ sc,
+                                                  int stop_mask)
+{
+    if (stop_now(sc, stop_mask)) return;
+    constexpr int T = LayerGeo<L>::T;
+    constexpr int NCH = (L == 1) ? 1 : T;   // K chunks of 32
+    const int lane = threadIdx.x & 63, m = lane & 15, grp = lane >> 4;
+    bf16x8 wb[NCH][2];
+#pragma unroll
+    for (int c = 0; c < NCH; ++c)
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt) wb[c][nt] = ld8(wf + (long)c * 1024 + (16 * nt + m) * 32 + 8 * grp);
+    const float bias0 = bias[m], bias1 = bias[16 + m];
+    const long ntiles = (g.n + 15) / 16;
+    const long nw = (long)gridDim.x * 4;
+    for (long tile = (long)blockIdx.x * 4 + (threadIdx.x >> 6); tile < ntiles; tile += nw) {
+        const long p = tile * 16 + m;
+        const bool pv = p < g.n;
+        const long pc = pv ? p : g.n - 1;
+        const Pos x = decompose(g, pc);
+        f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+        if constexpr (L == 1) {
+            // K = (tap, channel): lane group grp holds taps 2 grp and 2 grp + 1 (4 channels each)
+            uint2 h[2];
+#pragma unroll
+            for (int hh = 0; hh < 2; ++hh) {
+                const int t = 2 * grp + hh;
+                h[hh] = make_uint2(0, 0);
+                if (t < 5) {
+                    const long q = nb_v(g, pc, x, t - 2);
+                    if (pv && q >= 0) h[hh] = reinterpret_cast<const uint2 *>(in)[q];
+                }
+            }
+            const bf16x8 a = __builtin_bit_cast(bf16x8, make_uint4(h[0].x, h[0].y, h[1].x, h[1].y));
+            acc0 = mfma(a, wb[0][0], acc0);
+            acc1 = mfma(a, wb[0][1], acc1);
+        } else {
+#pragma unroll
+            for (int t = 0; t < T; ++t) {
+                const long q = LayerGeo<L>::nb(g, pc, x, t, false);
+                const bf16x8 a = (pv && q >= 0) ? ld8(in + q * 32 + 8 * grp) : zero8();
+                acc0 = mfma(a, wb[t][0], acc0);
+                acc1 = mfma(a, wb[t][1], acc1);
+            }
+        }
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) {
+            const long q = tile * 16 + 4 * grp + jj;
+            if (q < g.n) {
+                out[q * 32 + m] = f2bf(fmaxf(acc0[jj] + bias0, 0.f));
+                out[q * 32 + 16 + m] = f2bf(fmaxf(acc1[jj] + bias1, 0.f));
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// conv layer, backward data:  din[p][ci] = [aprev[p][ci] > 0] sum_{t, co} W[t][co][ci] dout[nb(p, -t)][co]
+// (the transposed convolution, masked by the derivative of the ReLU that produced aprev)
+// ------------------------------------------------------------------------------------------
+template <int L>
+__global__ __launch_bounds__(256) void k_conv_bwd(NetGeo g, const uint16_t *__restrict__ dout,
+                                                  const uint16_t *__restrict__ wt, const uint16_t *__restrict__ aprev,
+                                                  uint16_t *__restrict__ din)
+{
+    constexpr int T = LayerGeo<L>::T;
+    const int lane = threadIdx.x & 63, m = lane & 15, grp = lane >> 4;
+    bf16x8 wb[T][2];
+#pragma unroll
+    for (int t = 0; t < T; ++t)
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt) wb[t][nt] = ld8(wt + (long)t * 1024 + (16 * nt + m) * 32 + 8 * grp);
+    const long ntiles = (g.n + 15) / 16;
+    const long nw = (long)gridDim.x * 4;
+    for (long tile = (long)blockIdx.x * 4 + (threadIdx.x >> 6); tile < ntiles; tile += nw) {
+        const long p = tile * 16 + m;
+        const bool pv = p < g.n;
+        const long pc = pv ? p : g.n - 1;
+        const Pos x = decompose(g, pc);
+        f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int t = 0; t < T; ++t) {
+            const long q = LayerGeo<L>::nb(g, pc, x, t, true);
+            const bf16x8 a = (pv && q >= 0) ? ld8(dout + q * 32 + 8 * grp) : zero8();
+            acc0 = mfma(a, wb[t][0], acc0);
+            acc1 = mfma(a, wb[t][1], acc1);
+        }
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) {
+            const long q = tile * 16 + 4 * grp + jj;
+            if (q < g.n) {
+                const float m0 = bf2f(aprev[q * 32 + m]) > 0.f ? 1.f : 0.f;
+                const float m1 = bf2f(aprev[q * 32 + 16 + m]) > 0.f ? 1.f : 0.f;
+                din[q * 32 + m] = f2bf(acc0[jj] * m0);
+                din[q * 32 + 16 + m] = f2bf(acc1[jj] * m1);
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// conv layer, weight gradient (per-wave partial sums; rows reduced later in a fixed order):
+//   dW[t][co][ci] = sum_p dout[p][co] in[nb(p, t)][ci],   db[co] = sum_p dout[p][co]
+// MFMA with M = co, N = ci (for layer 1: N = (tap, channel)), K = 32 positions per chunk.
+// ------------------------------------------------------------------------------------------
+template <int L>
+__global__ __launch_bounds__(256) void k_conv_dw(NetGeo g, const uint16_t *__restrict__ dout,
+                                                 const uint16_t *__restrict__ in, float *__restrict__ part)
+{
+    constexpr int T = LayerGeo<L>::T;
+    constexpr int NG = (L == 1) ? 1 : T;
+    const int lane = threadIdx.x & 63, m = lane & 15, grp = lane >> 4;
+    const long row = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const long nrows = (long)gridDim.x * 4;
+    f32x4 acc[NG][2][2];
+#pragma unroll
+    for (int a = 0; a < NG; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int c = 0; c < 2; ++c) acc[a][b][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+    float bsum[2] = {0.f, 0.f};
+    const long nchunks = (g.n + 31) / 32;
+    for (long ch = row; ch < nchunks; ch += nrows) {
+        const long p0 = ch * 32 + 8 * grp;
+        long pos[8];
+        Pos xs[8];
+        bool ok[8];
+#pragma unroll
+        for (int jj = 0; jj < 8; ++jj) {
+            pos[jj] = p0 + jj;
+            ok[jj] = pos[jj] < g.n;
+            xs[jj] = decompose(g, ok[jj] ? pos[jj] : 0);
+        }
+        bf16x8 a[2];
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt) {
+#pragma unroll
+            for (int jj = 0; jj < 8; ++jj) {
+                const uint16_t v = ok[jj] ? dout[pos[jj] * 32 + 16 * mt + m] : (uint16_t)0;
+                a[mt][jj] = __builtin_bit_cast(__bf16, v);
+                bsum[mt] += bf2f(v);
+            }
+        }
+#pragma unroll
+        for (int G = 0; G < NG; ++G) {
+#pragma unroll
+            for (int nt = 0; nt < 2; ++nt) {
+                bf16x8 b;
+#pragma unroll
+                for (int jj = 0; jj < 8; ++jj) {
+                    uint16_t v = 0;
+                    if constexpr (L == 1) {
+                        const int kk = 16 * nt + m;   // (tap, channel) = (kk / 4, kk % 4)
+                        if (kk < 20 && ok[jj]) {
+                            const long q = nb_v(g, pos[jj], xs[jj], kk / 4 - 2);
+                            if (q >= 0) v = in[q * 4 + (kk & 3)];
+                        }
+                    } else {
+                        if (ok[jj]) {
+                            const long q = LayerGeo<L>::nb(g, pos[jj], xs[jj], G, false);
+                            if (q >= 0) v = in[q * 32 + 16 * nt + m];
+                        }
+                    }
+                    b[jj] = __builtin_bit_cast(__bf16, v);
+                }
+#pragma unroll
+                for (int mt = 0; mt < 2; ++mt) acc[G][mt][nt] = mfma(a[mt], b, acc[G][mt][nt]);
+            }
+        }
+    }
+    float *dst = part + row * kNetParams;
+    // result lane l: co = 16 mt + 4 grp + jj, N index = 16 nt + m
+#pragma unroll
+    for (int G = 0; G < NG; ++G)
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+            for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+                for (int jj = 0; jj < 4; ++jj) {
+                    const int co = 16 * mt + 4 * grp + jj;
+                    const int nn = 16 * nt + m;
+                    if constexpr (L == 1) {
+                        if (nn < 20) dst[kNetOffW1 + (nn / 4) * 128 + co * 4 + (nn & 3)] = acc[G][mt][nt][jj];
+                    } else {
+                        const int off = (L == 2) ? kNetOffW2 : kNetOffW3;
+                        dst[off + G * 1024 + co * 32 + nn] = acc[G][mt][nt][jj];
+                    }
+                }
+    // bias: sum over the four lane groups holding the same output channel
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt) {
+        float s = bsum[mt];
+        s += __shfl_xor(s, 16);
+        s += __shfl_xor(s, 32);
+        if (grp == 0) {
+            const int off = (L == 1) ? kNetOffB1 : ((L == 2) ? kNetOffB2 : kNetOffB3);
+            dst[off + 16 * mt + m] = s;
+        }
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// output layer (32 -> 1, 5 vertical taps) fused with  q' = q + rho * delta
+// ------------------------------------------------------------------------------------------
+template <typename Tv>
+__global__ __launch_bounds__(256) void k_net_out(NetGeo g, const uint16_t *__restrict__ a3,
+                                                 const float *__restrict__ w4, const float *__restrict__ theta,
+                                                 const Tv *__restrict__ q, Tv *__restrict__ qout,
+                                                 float *__restrict__ delta, const Scalars *__restrict__ sc,
+                                                 int stop_mask)
+{
+    if (stop_now(sc, stop_mask)) return;
+    __shared__ float w[160];
+    if (threadIdx.x < 160) w[threadIdx.x] = w4[threadIdx.x];
+    __syncthreads();
+    const float b4 = theta[kNetOffB4];
+    const double rho = sqrt(sc->net_q2 / (double)g.n);
+    const long stride = (long)gridDim.x * 256;
+    for (long p = (long)blockIdx.x * 256 + threadIdx.x; p < g.n; p += stride) {
+        const Pos x = decompose(g, p);
+        float d = b4;
+#pragma unroll
+        for (int t = 0; t < 5; ++t) {
+            const long nb = nb_v(g, p, x, t - 2);
+            if (nb < 0) continue;
+            const uint4 *row = reinterpret_cast<const uint4 *>(a3 + nb * 32);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const uint4 u = row[v];
+                const uint32_t wd[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+                for (int h = 0; h < 4; ++h) {
+                    const int c = 8 * v + 2 * h;
+                    d += w[t * 32 + c] * __uint_as_float(wd[h] << 16);
+                    d += w[t * 32 + c + 1] * __uint_as_float(wd[h] & 0xffff0000u);
+                }
+            }
+        }
+        if (delta) delta[p] = d;
+        qout[p] = static_cast<Tv>(static_cast<double>(q[p]) + rho * static_cast<double>(d));
+    }
+}
+
+// Backward of the output layer:  dδ = rho u;  dh3[p][c] = [a3 > 0] sum_t W4[t][c] dδ[p - (t - 2) P]
+__global__ __launch_bounds__(256) void k_net_out_bwd(NetGeo g, const float *__restrict__ u,
+                                                     const uint16_t *__restrict__ a3, const float *__restrict__ w4,
+                                                     uint16_t *__restrict__ dh3, const Scalars *__restrict__ sc)
+{
+    __shared__ float w[160];
+    if (threadIdx.x < 160) w[threadIdx.x] = w4[threadIdx.x];
+    __syncthreads();
+    const float rho = static_cast<float>(sqrt(sc->net_q2 / (double)g.n));
+    const long stride = (long)gridDim.x * 256;
+    for (long p = (long)blockIdx.x * 256 + threadIdx.x; p < g.n; p += stride) {
+        const Pos x = decompose(g, p);
+        float dd[5];
+#pragma unroll
+        for (int t = 0; t < 5; ++t) {
+            const long nb = nb_v(g, p, x, -(t - 2));
+            dd[t] = nb < 0 ? 0.f : rho * u[nb];
+        }
+        const uint4 *row = reinterpret_cast<const uint4 *>(a3 + p * 32);
+        uint4 *orow = reinterpret_cast<uint4 *>(dh3 + p * 32);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const uint4 ain = row[v];
+            const uint32_t wd[4] = {ain.x, ain.y, ain.z, ain.w};
+            uint32_t od[4];
+#pragma unroll
+            for (int h = 0; h < 4; ++h) {
+                float o[2];
+#pragma unroll
+                for (int e = 0; e < 2; ++e) {
+                    const int c = 8 * v + 2 * h + e;
+                    float s = 0.f;
+#pragma unroll
+                    for (int t = 0; t < 5; ++t) s += w[t * 32 + c] * dd[t];
+                    const float av = e ? __uint_as_float(wd[h] & 0xffff0000u) : __uint_as_float(wd[h] << 16);
+                    o[e] = av > 0.f ? s : 0.f;
+                }
+                od[h] = static_cast<uint32_t>(f2bf(o[0])) | (static_cast<uint32_t>(f2bf(o[1])) << 16);
+            }
+            orow[v] = make_uint4(od[0], od[1], od[2], od[3]);
+        }
+    }
+}
+
+// Output-layer weight gradient: dW4[t][c] = sum_p dδ[p] a3[p + (t - 2) P][c], db4 = sum dδ.
+// Workgroup = 32 channels x 8 position streams; one partial row per workgroup.
+__global__ __launch_bounds__(256) void k_net_out_dw(NetGeo g, const float *__restrict__ u,
+                                                    const uint16_t *__restrict__ a3, float *__restrict__ part,
+                                                    const Scalars *__restrict__ sc)
+{
+    const float rho = static_cast<float>(sqrt(sc->net_q2 / (double)g.n));
+    const int c = threadIdx.x & 31, s = threadIdx.x >> 5;
+    float acc[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+    float bacc = 0.f;
+    const long stride = (long)gridDim.x * 8;
+    for (long p = (long)blockIdx.x * 8 + s; p < g.n; p += stride) {
+        const Pos x = decompose(g, p);
+        const float dd = rho * u[p];
+        if (c == 0) bacc += dd;
+#pragma unroll
+        for (int t = 0; t < 5; ++t) {
+            const long nb = nb_v(g, p, x, t - 2);
+            if (nb >= 0) acc[t] += dd * bf2f(a3[nb * 32 + c]);
+        }
+    }
+    __shared__ float red[8][161];
+#pragma unroll
+    for (int t = 0; t < 5; ++t) red[s][t * 32 + c] = acc[t];
+    if (c == 0) red[s][160] = bacc;
+    __syncthreads();
+    if (threadIdx.x <= 160) {
+        float v = 0.f;
+        for (int r = 0; r < 8; ++r) v += red[r][threadIdx.x];
+        float *dst = part + (long)blockIdx.x * kNetParams;
+        if (threadIdx.x < 160) dst[kNetOffW4 + threadIdx.x] = v;
+        else dst[kNetOffB4] = v;
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// loss pieces:  g = 2 (m - e) / ||e||^2
+// ------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_net_gseed(long n, const float *__restrict__ m, const float *__restrict__ e,
+                                                   float *__restrict__ gout, const Scalars *__restrict__ sc)
+{
+    const float s = static_cast<float>(2.0 / sc->net_ee);
+    const long stride = (long)gridDim.x * 256;
+    for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) gout[i] = s * (m[i] - e[i]);
+}
+
+// diff = m - e (for the loss numerator)
+__global__ __launch_bounds__(256) void k_net_diff(long n, const float *__restrict__ m, const float *__restrict__ e,
+                                                  float *__restrict__ out)
+{
+    const long stride = (long)gridDim.x * 256;
+    for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) out[i] = m[i] - e[i];
+}
+
+// ------------------------------------------------------------------------------------------
+// z = T^{-T} y per column from the LU factors (l, inv, c) of T = L U:
+//   U^T u = y :  ~u_k = y_k + c_{k-1} ~u_{k-1},  u_k = inv_k ~u_k
+//   L^T z = u :  z_k = u_k + l_{k+1} z_{k+1}
+// ------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_thomas_t(TriView<float> tv, const float *__restrict__ y,
+                                                  float *__restrict__ z)
+{
+    const long col = (long)blockIdx.x * 256 + threadIdx.x;
+    if (col >= tv.P) return;
+    const long P = tv.P, n = tv.n;
+    const float *lf = tv.f, *invf = tv.f + n, *cf = tv.f + 2 * n;
+    float ut = 0.f, cprev = 0.f;
+    for (int k = 0; k < tv.nlev; ++k) {
+        const long c = col + (long)k * P;
+        ut = y[c] + cprev * ut;
+        z[c] = invf[c] * ut;
+        cprev = cf[c];
+    }
+    float zz = 0.f, lnext = 0.f;
+    for (int k = tv.nlev - 1; k >= 0; --k) {
+        const long c = col + (long)k * P;
+        zz = z[c] + lnext * zz;
+        z[c] = zz;
+        lnext = lf[c];
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// parameters: gradient reduction, Adam, BF16 copies
+// ------------------------------------------------------------------------------------------
+// grad[i] = (accumulate ? grad[i] : 0) + scale * sum over the launch's partial rows of part[row][i]
+// (rows summed in order: deterministic).  Only parameters in [lo, hi) are touched.
+__global__ __launch_bounds__(256) void k_net_reduce(const float *__restrict__ part, int rows, int lo, int hi,
+                                                    float scale, int accumulate, float *__restrict__ grad)
+{
+    const int i = lo + blockIdx.x * 256 + threadIdx.x;
+    if (i >= hi) return;
+    float s = 0.f;
+    for (int r = 0; r < rows; ++r) s += part[(long)r * kNetParams + i];
+    grad[i] = (accumulate ? grad[i] : 0.f) + scale * s;
+}
+
+__device__ void refresh_one(const NetDev &d, int i, float v)
+{
+    const uint16_t b = f2bf(v);
+    if (i < kNetOffB1) {                    // W1[t][co][ci] -> w1f[co][t*4 + ci]
+        const int t = i / 128, co = (i % 128) / 4, ci = i % 4;
+        d.w1f[co * 32 + t * 4 + ci] = b;
+    } else if (i >= kNetOffW2 && i < kNetOffB2) {
+        const int r = i - kNetOffW2, t = r / 1024, co = (r % 1024) / 32, ci = r % 32;
+        d.w2f[t * 1024 + co * 32 + ci] = b;
+        d.w2b[t * 1024 + ci * 32 + co] = b;
+    } else if (i >= kNetOffW3 && i < kNetOffB3) {
+        const int r = i - kNetOffW3, t = r / 1024, co = (r % 1024) / 32, ci = r % 32;
+        d.w3f[t * 1024 + co * 32 + ci] = b;
+        d.w3b[t * 1024 + ci * 32 + co] = b;
+    } else if (i >= kNetOffW4 && i < kNetOffB4) {
+        d.w4[i - kNetOffW4] = bf2f(b);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_net_refresh(NetDev d)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < kNetParams) refresh_one(d, i, d.theta[i]);
+}
+
+__global__ __launch_bounds__(256) void k_net_adam(NetDev d, float lr, float b1, float b2, float eps, float c1,
+                                                  float c2)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= kNetParams) return;
+    const float gr = d.grad[i];
+    const float m = b1 * d.adam_m[i] + (1.f - b1) * gr;
+    const float v = b2 * d.adam_v[i] + (1.f - b2) * gr * gr;
+    d.adam_m[i] = m;
+    d.adam_v[i] = v;
+    const float th = d.theta[i] - lr * (m * c1) / (sqrtf(v * c2) + eps);
+    d.theta[i] = th;
+    refresh_one(d, i, th);
+}
+
+// ------------------------------------------------------------------------------------------
+// launchers
+// ------------------------------------------------------------------------------------------
+static int net_blocks(long n, long per_block, long cap)
+{
+    long b = (n + per_block - 1) / per_block;
+    if (b > cap) b = cap;
+    return (int)(b < 1 ? 1 : b);
+}
+
+template <typename Tv, typename Tc>
+void launch_net_features(const NetGeo &g, const Tv *q, const Tv *z0, const Tc *a, uint16_t *x0, const Scalars *sc,
+                         int stop_mask, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_net_features<Tv, Tc>), dim3(net_blocks(g.n, 1024, 8192)), dim3(256), 0, s, g, q, z0, a, x0,
+                       sc, stop_mask);
+}
+
+void launch_net_forward_layers(const NetGeo &g, const NetDev &d, const NetActs &act, const Scalars *sc, int stop_mask,
+                               hipStream_t s)
+{
+    const int nb = net_blocks((g.n + 15) / 16, 4 * 8, 4096);
+    hipLaunchKernelGGL((k_conv_fwd<1>), dim3(nb), dim3(256), 0, s, g, act.x0, d.w1f, d.theta + kNetOffB1, act.a1, sc,
+                       stop_mask);
+    hipLaunchKernelGGL((k_conv_fwd<2>), dim3(nb), dim3(256), 0, s, g, act.a1, d.w2f, d.theta + kNetOffB2, act.a2, sc,
+                       stop_mask);
+    hipLaunchKernelGGL((k_conv_fwd<3>), dim3(nb), dim3(256), 0, s, g, act.a2, d.w3f, d.theta + kNetOffB3, act.a3, sc,
+                       stop_mask);
+}
+
+template <typename Tv>
+void launch_net_out(const NetGeo &g, const NetDev &d, const NetActs &act, const Tv *q, Tv *qout, float *delta,
+                    const Scalars *sc, int stop_mask, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_net_out<Tv>), dim3(net_blocks(g.n, 1024, 8192)), dim3(256), 0, s, g, act.a3, d.w4, d.theta,
+                       q, qout, delta, sc, stop_mask);
+}
+
+void launch_thomas_t(const TriView<float> &tv, const float *y, float *z, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_thomas_t, dim3((unsigned)((tv.P + 255) / 256)), dim3(256), 0, s, tv, y, z);
+}
+
+void launch_net_gseed(long n, const float *m, const float *e, float *g, const Scalars *sc, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_net_gseed, dim3(net_blocks(n, 1024, 8192)), dim3(256), 0, s, n, m, e, g, sc);
+}
+
+void launch_net_diff(long n, const float *m, const float *e, float *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_net_diff, dim3(net_blocks(n, 1024, 8192)), dim3(256), 0, s, n, m, e, out);
+}
+
+// Backward through the network for one pair; partial weight gradients accumulate into grad.
+void launch_net_backward(const NetGeo &g, const NetDev &d, const NetActs &act, const float *u, const Scalars *sc,
+                         float scale, int accumulate, hipStream_t s)
+{
+    const int rows = kNetPartRows;
+    // output layer
+    hipLaunchKernelGGL(k_net_out_bwd, dim3(net_blocks(g.n, 1024, 8192)), dim3(256), 0, s, g, u, act.a3, d.w4, act.d1,
+                       sc);
+    hipLaunchKernelGGL(k_net_out_dw, dim3(rows), dim3(256), 0, s, g, u, act.a3, d.part, sc);
+    hipLaunchKernelGGL(k_net_reduce, dim3((kNetParams - kNetOffW4 + 255) / 256), dim3(256), 0, s, d.part, rows,
+                       kNetOffW4, kNetParams, scale, accumulate, d.grad);
+    const int nb = net_blocks((g.n + 15) / 16, 4 * 8, 4096);
+    const int rb = rows / 4;   // dw kernels: one partial row per wave
+    // layer 3: dW3 from (dh3, a2); dh2 = bwd(dh3) masked by a2
+    hipLaunchKernelGGL((k_conv_dw<3>), dim3(rb), dim3(256), 0, s, g, act.d1, act.a2, d.part);
+    hipLaunchKernelGGL(k_net_reduce, dim3((kNetOffW4 - kNetOffW3 + 255) / 256), dim3(256), 0, s, d.part, rows,
+                       kNetOffW3, kNetOffW4, scale, accumulate, d.grad);
+    hipLaunchKernelGGL((k_conv_bwd<3>), dim3(nb), dim3(256), 0, s, g, act.d1, d.w3b, act.a2, act.d2);
+    // layer 2: dW2 from (dh2, a1); dh1 = bwd(dh2) masked by a1
+    hipLaunchKernelGGL((k_conv_dw<2>), dim3(rb), dim3(256), 0, s, g, act.d2, act.a1, d.part);
+    hipLaunchKernelGGL(k_net_reduce, dim3((kNetOffW3 - kNetOffW2 + 255) / 256), dim3(256), 0, s, d.part, rows,
+                       kNetOffW2, kNetOffW3, scale, accumulate, d.grad);
+    hipLaunchKernelGGL((k_conv_bwd<2>), dim3(nb), dim3(256), 0, s, g, act.d2, d.w2b, act.a1, act.d1);
+    // layer 1: dW1 from (dh1, x0)
+    hipLaunchKernelGGL((k_conv_dw<1>), dim3(rb), dim3(256), 0, s, g, act.d1, act.x0, d.part);
+    hipLaunchKernelGGL(k_net_reduce, dim3((kNetOffW2 - kNetOffW1 + 255) / 256), dim3(256), 0, s, d.part, rows,
+                       kNetOffW1, kNetOffW2, scale, accumulate, d.grad);
+}
+
+void launch_net_refresh(const NetDev &d, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_net_refresh, dim3((kNetParams + 255) / 256), dim3(256), 0, s, d);
+}
+
+void launch_net_adam(const NetDev &d, float lr, int step, hipStream_t s)
+{
+    const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+    const float c1 = 1.f / (1.f - powf(b1, (float)step));
+    const float c2 = 1.f / (1.f - powf(b2, (float)step));
+    hipLaunchKernelGGL(k_net_adam, dim3((kNetParams + 255) / 256), dim3(256), 0, s, d, lr, b1, b2, eps, c1, c2);
+}
+
+template void launch_net_features<double, double>(const NetGeo &, const double *, const double *, const double *,
+                                                  uint16_t *, const Scalars *, int, hipStream_t);
+template void launch_net_features<float, double>(const NetGeo &, const float *, const float *, const double *,
+                                                 uint16_t *, const Scalars *, int, hipStream_t);
+template void launch_net_features<float, float>(const NetGeo &, const float *, const float *, const float *,
+                                                uint16_t *, const Scalars *, int, hipStream_t);
+template void launch_net_out<double>(const NetGeo &, const NetDev &, const NetActs &, const double *, double *,
+                                     float *, const Scalars *, int, hipStream_t);
+template void launch_net_out<float>(const NetGeo &, const NetDev &, const NetActs &, const float *, float *, float *,
+                                    const Scalars *, int, hipStream_t);
+
+}  // namespace eg

@@ -1,0 +1,200 @@
+"""Learned preconditioner on the GPU: network parity with the FP64 oracle (forward and
+gradients), harvest, training, flexible BiCGStab and the stall fallback."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import net as onet
+from tests.helpers import dev, host
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def eg():
+    import torch
+    import paper_1811_03852_amd as eg
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    eg.load_library()
+    return eg
+
+
+def _theta(seed, w4_scale=0.3):
+    rng = np.random.default_rng(seed)
+    d = onet.unpack(onet.init_theta(seed))
+    d["W4"] = rng.standard_normal(d["W4"].shape) * w4_scale
+    d["b1"] = rng.standard_normal(32) * 0.1
+    d["b2"] = rng.standard_normal(32) * 0.1
+    d["b3"] = rng.standard_normal(32) * 0.1
+    d["b4"] = np.array([0.02])
+    # the GPU keeps FP32 master weights: the oracle sees the same FP32 values
+    return onet.pack(d).astype(np.float32).astype(np.float64)
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.mark.parametrize("p", [synth.Problem(24, 12, 9, seed=2), synth.Problem(37, 9, 20, seed=3)],
+                         ids=lambda p: f"{p.nlon}x{p.nlat}x{p.nlev}")
+def test_forward_matches_oracle(eg, p):
+    import torch
+    coef = synth.make_coeffs(p)
+    th = _theta(4)
+    net = eg.Net(0)
+    net.set_weights(th.astype(np.float32))
+    q = np.random.default_rng(5).standard_normal(p.n).astype(np.float32)
+    with eg.Operator(dev(coef)) as op:
+        delta = torch.empty(p.n, dtype=torch.float32, device="cuda")
+        z = host(net.apply(op, dev(q), delta)).astype(np.float64)
+    d_ref, _ = onet.forward(th, coef, q.astype(np.float64), bf16_round=True)
+    z_ref = onet.apply(th, coef, q.astype(np.float64), bf16_round=True)
+    e_d, e_z = _rel(host(delta).astype(np.float64), d_ref), _rel(z, z_ref)
+    print(f"forward parity: delta rel L2 {e_d:.2e}, M(q) rel L2 {e_z:.2e}")
+    assert e_d <= 1e-2 and e_z <= 1e-3
+    net.close()
+
+
+def test_gradients_match_oracle(eg):
+    p = synth.Problem(24, 12, 9, seed=6)
+    coef = synth.make_coeffs(p)
+    th = _theta(7)
+    net = eg.Net(0)
+    net.set_weights(th.astype(np.float32))
+    rng = np.random.default_rng(8)
+    r = rng.standard_normal(p.n).astype(np.float32)
+    e = rng.standard_normal(p.n).astype(np.float32)
+    with eg.Operator(dev(coef)) as op:
+        L, g = net.loss_grad(op, dev(r), dev(e))
+    L_ref, g_ref = onet.loss_and_grad(th, coef, r.astype(np.float64), e.astype(np.float64), bf16_round=True)
+    assert abs(L - L_ref) <= 1e-3 * abs(L_ref)
+    G, Gr = onet.unpack(g.astype(np.float64)), onet.unpack(g_ref)
+    worst = 0.0
+    for name, _ in onet.SHAPES:
+        err = _rel(G[name].ravel(), Gr[name].ravel())
+        print(f"grad {name}: rel L2 {err:.2e}")
+        worst = max(worst, err)
+    assert worst <= 2e-2
+    net.close()
+
+
+def test_zero_output_layer_reproduces_plain_solver_bitwise(eg):
+    """Untrained net (zero output layer): delta = 0 exactly, so flexible BiCGStab with the
+    learned M follows the tridiagonal-preconditioned trajectory bit for bit."""
+    import torch
+    p = synth.CONFIGS["c1"]
+    coef = synth.make_coeffs(p)
+    b = dev(synth.make_rhs(p).ravel())
+    net = eg.Net(3)
+    with eg.Operator(dev(coef)) as op:
+        op.attach(net)
+        for plain, learned in ((eg.FP64, eg.LEARNED_FP64), (eg.FP32_IR, eg.LEARNED_FP32_IR)):
+            x1 = torch.zeros(p.n, dtype=torch.float64, device="cuda")
+            i1 = op.solve(b, x1, 1e-8, 5000, plain)
+            h1 = op.history()
+            x2 = torch.zeros_like(x1)
+            i2 = op.solve(b, x2, 1e-8, 5000, learned)
+            h2 = op.history()
+            assert i1.status == i2.status == eg.CONVERGED
+            assert torch.equal(x1, x2) and np.array_equal(h1, h2) and i2.fallbacks == 0
+    net.close()
+
+
+def test_harvest_pairs(eg, oracle_mod):
+    p = synth.Problem(48, 24, 10, seed=9)
+    coef = synth.make_coeffs(p)
+    b = synth.make_rhs(p).ravel()
+    with eg.Operator(dev(coef)) as op:
+        r, e = op.harvest(dev(b), 12)
+    assert r.shape[0] == 12
+    rh, eh = host(r).astype(np.float64), host(e).astype(np.float64)
+    for i in (0, 5, 11):
+        # r_i = b - A x_i and e_i = x* - x_i with A x* = b  =>  r_i = A e_i (up to FP32 rounding)
+        Ae = oracle_mod.apply(coef, eh[i])
+        assert _rel(Ae, rh[i]) <= 1e-4
+    # the iterates converge: errors shrink
+    assert np.linalg.norm(eh[11]) < 0.1 * np.linalg.norm(eh[0])
+
+
+@pytest.fixture(scope="module")
+def trained(eg):
+    """A network trained on pairs harvested from four small operators of the generator's family."""
+    import torch
+    ops, rs, es, owner = [], [], [], []
+    for s in range(4):
+        p = synth.Problem(48, 24, 10, seed=1000 + s)
+        op = eg.Operator(dev(synth.make_coeffs(p)))
+        b = synth.make_rhs(p, seed=2000 + s).ravel()
+        r, e = op.harvest(dev(b), 12)
+        ops.append(op)
+        rs.append(r)
+        es.append(e)
+        owner += [s] * r.shape[0]
+    r = torch.cat(rs).contiguous()
+    e = torch.cat(es).contiguous()
+    net = eg.Net(11)
+    loss0 = net.eval(ops, r, e, owner)
+    hist = net.train(ops, r, e, owner, epochs=12, batch=8, lr=2e-3, seed=1)
+    yield dict(net=net, ops=ops, r=r, e=e, owner=owner, loss0=loss0, hist=hist)
+    for op in ops:
+        op.close()
+    net.close()
+
+
+def test_training_reduces_loss(trained):
+    h = trained["hist"]
+    print(f"loss untrained {trained['loss0']:.4f}, per epoch {np.round(h, 4)}")
+    assert trained["loss0"] == pytest.approx(h[0], rel=0.5)
+    assert h[-1] < 0.9 * trained["loss0"]
+
+
+def test_training_is_deterministic(eg, trained):
+    ops, r, e, owner = trained["ops"], trained["r"], trained["e"], trained["owner"]
+    w = []
+    for _ in range(2):
+        net = eg.Net(11)
+        net.train(ops, r, e, owner, epochs=2, batch=8, lr=2e-3, seed=1)
+        w.append(net.get_weights())
+        net.close()
+    assert np.array_equal(w[0], w[1])
+
+
+@pytest.mark.parametrize("mode_name", ["LEARNED_FP64", "LEARNED_FP32_IR"])
+def test_learned_modes_reach_1e8(eg, oracle_mod, trained, mode_name):
+    import torch
+    p = synth.Problem(48, 24, 10, seed=1007)
+    coef = synth.make_coeffs(p)
+    b = synth.make_rhs(p, seed=2007).ravel()
+    x_ref, _ = oracle_mod.bicgstab(coef, b, tol=1e-12)
+    with eg.Operator(dev(coef)) as op:
+        op.attach(trained["net"])
+        x = torch.zeros(p.n, dtype=torch.float64, device="cuda")
+        info = op.solve(dev(b), x, 1e-8, 5000, getattr(eg, mode_name))
+        xp = torch.zeros_like(x)
+        plain = op.solve(dev(b), xp, 1e-8, 5000, eg.FP64)
+    xh = host(x)
+    rel = np.linalg.norm(b - oracle_mod.apply(coef, xh)) / np.linalg.norm(b)
+    err = np.linalg.norm(xh - x_ref) / np.linalg.norm(x_ref)
+    print(f"{mode_name}: iterations {info.iterations} (plain FP64 {plain.iterations}), fallbacks {info.fallbacks}, "
+          f"true R {rel:.2e}, error vs oracle {err:.2e}")
+    assert info.status == eg.CONVERGED and rel <= 1e-8 and err <= 1e-5
+
+
+def test_stall_triggers_fallback_and_still_converges(eg, oracle_mod):
+    """A network with large random output weights is a poor preconditioner: the stall rule
+    switches to T^{-1} and the solve still reaches the tolerance."""
+    import torch
+    p = synth.Problem(48, 24, 10, seed=21)
+    coef = synth.make_coeffs(p)
+    b = synth.make_rhs(p).ravel()
+    net = eg.Net(0)
+    net.set_weights(_theta(13, w4_scale=30.0).astype(np.float32))
+    with eg.Operator(dev(coef)) as op:
+        op.attach(net)
+        op.set_option("stall_window", 5)
+        for mode in (eg.LEARNED_FP64, eg.LEARNED_FP32_IR):
+            x = torch.zeros(p.n, dtype=torch.float64, device="cuda")
+            info = op.solve(dev(b), x, 1e-8, 5000, mode)
+            rel = np.linalg.norm(b - oracle_mod.apply(coef, host(x))) / np.linalg.norm(b)
+            assert info.fallbacks >= 1 and info.status == eg.CONVERGED and rel <= 1e-8, info
+    net.close()
