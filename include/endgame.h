@@ -134,7 +134,11 @@ int eg_set_stream(eg_operator *op, void *hip_stream);
  *   "poll"           iterations enqueued between host checks of the device flags [8]
  *   "graph"          1 = replay batches of iterations as HIP graphs, 0 = plain launches [1]
  *   "stall_window"   learned modes: iterations without a 2x gain that trigger fallback [20]
+ *                    (FGMRES: at least one restart cycle, max(stall_window, gmres_m))
  *   "profile"        1 = time every streaming kernel launch (see eg_kernel_stats) [0]
+ *   "method"         Krylov method of the plain modes: 0 BiCGStab, 1 restarted FGMRES [0]
+ *   "learned_method" Krylov method of the learned modes: 0 flexible BiCGStab, 1 FGMRES [1]
+ *   "gmres_m"        FGMRES restart length, 1..64 [30]
  * Returns EG_EINVAL for an unknown key or out-of-range value.
  */
 int eg_set_option(eg_operator *op, const char *key, double value);
@@ -225,16 +229,32 @@ int eg_attach_learned_pc(eg_operator *op, eg_net *net);
  * NULL) device float[n] receives the network output. */
 int eg_net_apply(eg_operator *op, eg_net *net, const float *q, float *z, float *delta);
 
-/* Loss ||M(r) - e||^2 / ||e||^2 of one (residual, error) pair (device float[n] each) and its
- * gradient with respect to the parameters (host double, host float[15233]; either may be NULL). */
+/* Training loss of a (residual, error) pair, A e = r:
+ *   kind 1 (default)  ||A M(r) - r||^2 / ||r||^2   (residual space: what the Krylov method sees)
+ *   kind 0            ||M(r) - e||^2 / ||e||^2     (error space)
+ * Returns EG_EINVAL for another kind. */
+int eg_net_set_loss(eg_net *net, int kind);
+
+/* Loss of one (residual, error) pair (device float[n] each) and its gradient with respect to
+ * the parameters (host double, host float[15233]; either may be NULL). */
 int eg_net_loss_grad(eg_operator *op, eg_net *net, const float *r, const float *e, double *loss_host,
                      float *grad_host);
 
 /* Harvest training pairs from the solver itself: solve A x* = b in FP64 as tightly as FP64
- * allows, then run FP64 BiCGStab from x0 = 0 and after iteration i (i = 1..nsnap) store
- * r_i = b - A x_i and e_i = x* - x_i as float.  b: device double[n]; r_out, e_out: device
- * float[nsnap][n].  Returns the number of pairs stored (fewer if the solve converged first). */
+ * allows, then run FP64 BiCGStab from x0 = 0 and store r_i = b - A x_i and e_i = x* - x_i as
+ * float for the iterates i = 0 .. nsnap-1 (i = 0 is x0 = 0: r_0 = b, e_0 = x*).
+ * b: device double[n]; r_out, e_out: device float[nsnap][n].  Returns the number of pairs
+ * stored (fewer if the solve converged first). */
 int eg_harvest(eg_operator *op, const double *b, int nsnap, float *r_out, float *e_out);
+
+/* Training pairs from the Krylov basis the preconditioner is applied to: one FGMRES(nvec) cycle
+ * with M = T^{-1} from x0 = 0 on b (restarted flexible GMRES, Saad 1993; the paper's solver
+ * family of Sec. 2 with its tridiagonal preconditioner of Eq. 7) stores its orthonormal basis
+ * v_0 = b/||b||, v_1, ..., v_{nvec-1} in r_out (float), and, if e_out is not NULL, the errors
+ * e_j = A^{-1} v_j from FP64 BiCGStab solves to a relative residual of 1e-10.
+ * b: device double[n]; r_out, e_out: device float[nvec][n]; 1 <= nvec <= 64.  Returns the
+ * number of pairs stored (fewer if the Krylov space became invariant first). */
+int eg_harvest_krylov(eg_operator *op, const double *b, int nvec, float *r_out, float *e_out);
 
 /* Train with Adam (lr; beta 0.9 / 0.999) on pairs r, e (device float[npairs][n]); pair i
  * belongs to operator ops[pair_op[i]] (host arrays; every operator must have the same grid).

@@ -137,24 +137,52 @@ def apply(theta: np.ndarray, coef: np.ndarray, q: np.ndarray, bf16_round: bool =
     return oracle.thomas(coef, np.asarray(q, dtype=np.float64).ravel() + c["rho"] * delta)
 
 
-def loss(theta, coef, r, e, bf16_round=True) -> float:
+def transpose_coeffs(coef: np.ndarray) -> np.ndarray:
+    """Coefficients of A^T as a 7-point operator: row c of A^T holds the couplings of the
+    neighbours' rows to c (W'(i) = E(i-1), E'(i) = W(i+1), S'(j) = N(j-1), N'(j) = S(j+1),
+    D'(k) = U(k-1), U'(k) = D(k+1)); the diagonal is unchanged."""
+    ct = np.zeros_like(coef)
+    ct[0] = np.roll(coef[1], 1, axis=2)
+    ct[1] = np.roll(coef[0], -1, axis=2)
+    ct[2, :, 1:] = coef[3, :, :-1]
+    ct[3, :, :-1] = coef[2, :, 1:]
+    ct[4, 1:] = coef[5, :-1]
+    ct[5, :-1] = coef[4, 1:]
+    ct[6] = coef[6]
+    return ct
+
+
+LOSS_ERROR, LOSS_RESIDUAL = 0, 1
+
+
+def loss(theta, coef, r, e, bf16_round=True, kind=LOSS_ERROR) -> float:
+    """kind 0: ||M(r) - e||^2 / ||e||^2;  kind 1: ||A M(r) - r||^2 / ||r||^2 (A e = r)."""
     m = apply(theta, coef, r, bf16_round)
+    if kind == LOSS_RESIDUAL:
+        r = np.asarray(r, dtype=np.float64).ravel()
+        return float(np.sum((oracle.apply(coef, m) - r) ** 2) / np.sum(r * r))
     e = np.asarray(e, dtype=np.float64).ravel()
     return float(np.sum((m - e) ** 2) / np.sum(e * e))
 
 
-def loss_and_grad(theta, coef, r, e, bf16_round: bool = True):
-    """Loss ||M(r) - e||^2 / ||e||^2 and its gradient with respect to theta (chain rule by
-    hand: through T^{-1} by T^{-T}, through each layer by the transposed convolution)."""
+def loss_and_grad(theta, coef, r, e, bf16_round: bool = True, kind: int = LOSS_ERROR):
+    """Loss (see ``loss``) and its gradient with respect to theta (chain rule by hand: through
+    A by A^T, through T^{-1} by T^{-T}, through each layer by the transposed convolution)."""
     r = np.asarray(r, dtype=np.float64).ravel()
     e = np.asarray(e, dtype=np.float64).ravel()
     delta, c = forward(theta, coef, r, bf16_round)
     rho, rnd = c["rho"], c["rnd"]
     W1, W2, W3, W4 = c["W"]
     m = oracle.thomas(coef, r + rho * delta)
-    ee = np.sum(e * e)
-    L = float(np.sum((m - e) ** 2) / ee)
-    g_m = 2.0 * (m - e) / ee
+    if kind == LOSS_RESIDUAL:
+        d = oracle.apply(coef, m) - r
+        rr = np.sum(r * r)
+        L = float(np.sum(d * d) / rr)
+        g_m = oracle.apply(transpose_coeffs(coef), 2.0 * d / rr)
+    else:
+        ee = np.sum(e * e)
+        L = float(np.sum((m - e) ** 2) / ee)
+        g_m = 2.0 * (m - e) / ee
     g_delta = (rho * thomas_transpose(coef, g_m)).reshape(c["a3"].shape[:3])
     G = {}
     # layer 4: delta = sum_t shift_v(a3, t) . W4[t] + b4

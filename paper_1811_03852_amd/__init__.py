@@ -28,7 +28,7 @@ EXPORTED = ["eg_create_operator", "eg_solve", "eg_get_info", "eg_residual_histor
             "eg_apply", "eg_apply_precond", "eg_residual", "eg_dot", "eg_get_shape", "eg_destroy_operator",
             "eg_last_error", "eg_kernel_stats", "eg_reset_kernel_stats", "eg_net_create", "eg_net_destroy",
             "eg_net_set_weights", "eg_net_get_weights", "eg_attach_learned_pc", "eg_net_apply", "eg_net_loss_grad",
-            "eg_harvest", "eg_net_train", "eg_net_eval"]
+            "eg_harvest", "eg_harvest_krylov", "eg_net_train", "eg_net_eval", "eg_net_set_loss"]
 N_NET_PARAMS = 15233
 # enum eg_kernel
 K_THOMAS_P, K_SPMV_V, K_THOMAS_S, K_SPMV_T, K_UPDATE, K_RESIDUAL = range(6)
@@ -92,9 +92,11 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "eg_net_apply": ([vp, vp, vp, vp, vp], ctypes.c_int),
         "eg_net_loss_grad": ([vp, vp, vp, vp, dp, vp], ctypes.c_int),
         "eg_harvest": ([vp, vp, ctypes.c_int, vp, vp], ctypes.c_int),
+        "eg_harvest_krylov": ([vp, vp, ctypes.c_int, vp, vp], ctypes.c_int),
         "eg_net_train": ([vp, vp, ctypes.c_int, vp, vp, vp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                           ctypes.c_double, ctypes.c_ulonglong, dp], ctypes.c_int),
         "eg_net_eval": ([vp, vp, ctypes.c_int, vp, vp, vp, ctypes.c_int, dp], ctypes.c_int),
+        "eg_net_set_loss": ([vp, ctypes.c_int], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -235,6 +237,16 @@ class Operator:
         cnt = _check(_lib.eg_harvest(self._h, _ptr(b), int(nsnap), _ptr(r), _ptr(e)))
         return r[:cnt].contiguous(), e[:cnt].contiguous()
 
+    def harvest_krylov(self, b, nvec: int, errors: bool = True):
+        """(r, e) float tensors of shape (count, n): the FGMRES basis vectors of b and A^{-1} of
+        each (e is None when ``errors`` is False)."""
+        import torch
+        self._bind_stream()
+        r = torch.empty((nvec, self.n), dtype=torch.float32, device=b.device)
+        e = torch.empty_like(r) if errors else None
+        cnt = _check(_lib.eg_harvest_krylov(self._h, _ptr(b), int(nvec), _ptr(r), _ptr(e) if errors else None))
+        return r[:cnt].contiguous(), (e[:cnt].contiguous() if errors else None)
+
     def dot(self, a, b) -> float:
         import torch
         self._bind_stream()
@@ -263,6 +275,11 @@ class Net:
             self.close()
         except Exception:
             pass
+
+    LOSS_ERROR, LOSS_RESIDUAL = 0, 1
+
+    def set_loss(self, kind: int):
+        _check(_lib.eg_net_set_loss(self._h, int(kind)))
 
     def get_weights(self):
         import numpy as np

@@ -116,6 +116,16 @@ template <typename T>
 void launch_dot2(long n, const T *a, const T *b, const T *c, const T *d, double *partials, int *nrows,
                  const Scalars *sc, int stop_mask, hipStream_t s);
 
+// FGMRES: blocked classical Gram-Schmidt over basis vectors V + i * n (kMBlk per pass).
+// launch_mdot writes <w, v_{i0+c}> to out[i0 + c]; part must hold elementwise rows x kMBlk.
+constexpr int kMBlk = 8;
+template <typename Tv>
+int launch_mdot(long n, const Tv *w, const Tv *V, int i0, int nb, double *part, double *out, hipStream_t s);
+template <typename Tv>
+int launch_maxpy(long n, Tv *w, const Tv *V, int i0, int nb, const double *h, double sign, int want_norm,
+                 double *part, hipStream_t s);
+template <typename Tv> void launch_vscale(long n, const Tv *x, Tv *y, const double *d, hipStream_t s);
+
 // finalize kernels (one workgroup): reduce partials, update the scalar block
 enum FinStage { FIN_INIT = 0, FIN_END = 1, FIN_SIGMA = 2, FIN_S = 3, FIN_OMEGA = 4, FIN_SUM = 5, FIN_TRUE = 6,
                 FIN_NET = 7, FIN_LOSS = 8 };
@@ -126,6 +136,7 @@ void launch_finalize(int stage, const double *partials, int nrows, Scalars *sc, 
 template <typename T> void launch_fill(T *p, long n, T v, hipStream_t s);
 void launch_add_correction(long n, double *x, const float *d, hipStream_t s);
 void launch_sub_to_f32(long n, const double *a, const double *b, float *out, hipStream_t s);
+void launch_cast_f32(long n, const double *a, float *out, hipStream_t s);
 
 // operator setup
 void launch_derive(const double *coeffs, int nlon, int nlat, int nlev, double *a64, double *m64, int *bad,
@@ -171,6 +182,7 @@ template <typename Tv>
 void launch_net_out(const NetGeo &g, const NetDev &d, const NetActs &act, const Tv *q, Tv *qout, float *delta,
                     const Scalars *sc, int stop_mask, hipStream_t s);
 void launch_thomas_t(const TriView<float> &tv, const float *y, float *z, hipStream_t s);
+void launch_spmv_t(const NetGeo &g, const float *a, const float *m, const float *x, float *y, hipStream_t s);
 void launch_net_gseed(long n, const float *m, const float *e, float *g, const Scalars *sc, hipStream_t s);
 void launch_net_diff(long n, const float *m, const float *e, float *out, hipStream_t s);
 void launch_net_backward(const NetGeo &g, const NetDev &d, const NetActs &act, const float *u, const Scalars *sc,

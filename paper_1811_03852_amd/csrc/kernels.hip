@@ -737,6 +737,119 @@ void launch_dot2(long n, const T *a, const T *b, const T *c, const T *d, double 
 }
 
 // ------------------------------------------------------------------------------------------
+// Blocked Gram-Schmidt pieces for FGMRES: up to kMBlk basis vectors per pass (the basis is
+// one array, vector i at V + i * n).
+//   k_mdot   partials of <w, v_{i0+c}>, c < nb          (kMBlk columns per workgroup row)
+//   k_maxpy  w -= sum_c h[i0+c] v_{i0+c} (sign -1) or x += sum_c h[i0+c] v_{i0+c} (sign +1);
+//            with want_norm the partial of ||w||^2 after the update goes to column 0
+// ------------------------------------------------------------------------------------------
+template <typename Tv>
+__global__ __launch_bounds__(kWG) void k_mdot(long n, const Tv *__restrict__ w, const Tv *__restrict__ V, int i0,
+                                              int nb, double *__restrict__ part)
+{
+    double acc[kMBlk];
+#pragma unroll
+    for (int c = 0; c < kMBlk; ++c) acc[c] = 0.0;
+    const long stride = (long)gridDim.x * kWG;
+    for (long i = (long)blockIdx.x * kWG + threadIdx.x; i < n; i += stride) {
+        const double wi = static_cast<double>(w[i]);
+#pragma unroll
+        for (int c = 0; c < kMBlk; ++c)
+            if (c < nb) acc[c] += wi * static_cast<double>(V[(size_t)(i0 + c) * n + i]);
+    }
+    // fixed-order workgroup sum, kMBlk columns
+    __shared__ double sm[kWG / 64][kMBlk];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+        for (int c = 0; c < kMBlk; ++c) acc[c] += __shfl_xor(acc[c], off);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0)
+#pragma unroll
+        for (int c = 0; c < kMBlk; ++c) sm[wv][c] = acc[c];
+    __syncthreads();
+    if (threadIdx.x < kMBlk) {
+        double s = sm[0][threadIdx.x];
+        for (int w2 = 1; w2 < kWG / 64; ++w2) s += sm[w2][threadIdx.x];
+        part[(long)blockIdx.x * kMBlk + threadIdx.x] = s;
+    }
+}
+
+template <typename Tv>
+__global__ __launch_bounds__(kWG) void k_maxpy(long n, Tv *__restrict__ w, const Tv *__restrict__ V, int i0, int nb,
+                                               const double *__restrict__ h, double sign, int want_norm,
+                                               double *__restrict__ part)
+{
+    Tv hc[kMBlk];
+#pragma unroll
+    for (int c = 0; c < kMBlk; ++c) hc[c] = (c < nb) ? static_cast<Tv>(sign * h[i0 + c]) : Tv(0);
+    double acc[1] = {0.0};
+    const long stride = (long)gridDim.x * kWG;
+    for (long i = (long)blockIdx.x * kWG + threadIdx.x; i < n; i += stride) {
+        Tv wi = w[i];
+#pragma unroll
+        for (int c = 0; c < kMBlk; ++c)
+            if (c < nb) wi += hc[c] * V[(size_t)(i0 + c) * n + i];
+        w[i] = wi;
+        acc[0] += static_cast<double>(wi) * static_cast<double>(wi);
+    }
+    if (want_norm) block_sum_store<1>(acc, part + (long)blockIdx.x * kPartialCols);
+}
+
+// out[c] = sum over rows of part[row][c], c < ncols (one workgroup; thread t sums the rows
+// r = t / kMBlk (mod kWG / kMBlk) of column t % kMBlk, then the groups are added in order)
+__global__ __launch_bounds__(kWG) void k_msum(const double *__restrict__ part, int rows, int ncols,
+                                              double *__restrict__ out)
+{
+    constexpr int kGroups = kWG / kMBlk;
+    __shared__ double sm[kWG];
+    const int c = threadIdx.x % kMBlk, g = threadIdx.x / kMBlk;
+    double s = 0.0;
+    if (c < ncols)
+        for (int r = g; r < rows; r += kGroups) s += part[(long)r * kMBlk + c];
+    sm[threadIdx.x] = s;
+    __syncthreads();
+    if (threadIdx.x < ncols) {
+        double t = 0.0;
+        for (int q = 0; q < kGroups; ++q) t += sm[q * kMBlk + threadIdx.x];
+        out[threadIdx.x] = t;
+    }
+}
+
+// y = x * (1 / d[0])  (normalise the next Arnoldi vector by a device scalar)
+template <typename Tv>
+__global__ __launch_bounds__(kWG) void k_vscale(long n, const Tv *__restrict__ x, Tv *__restrict__ y,
+                                                const double *__restrict__ d)
+{
+    const Tv s = static_cast<Tv>(1.0 / d[0]);
+    const long stride = (long)gridDim.x * kWG;
+    for (long i = (long)blockIdx.x * kWG + threadIdx.x; i < n; i += stride) y[i] = x[i] * s;
+}
+
+template <typename Tv>
+int launch_mdot(long n, const Tv *w, const Tv *V, int i0, int nb, double *part, double *out, hipStream_t s)
+{
+    const int rows = elementwise_blocks(n);
+    hipLaunchKernelGGL((k_mdot<Tv>), dim3(rows), dim3(kWG), 0, s, n, w, V, i0, nb, part);
+    hipLaunchKernelGGL(k_msum, dim3(1), dim3(kWG), 0, s, part, rows, nb, out + i0);
+    return rows;
+}
+
+template <typename Tv>
+int launch_maxpy(long n, Tv *w, const Tv *V, int i0, int nb, const double *h, double sign, int want_norm,
+                 double *part, hipStream_t s)
+{
+    const int rows = elementwise_blocks(n);
+    hipLaunchKernelGGL((k_maxpy<Tv>), dim3(rows), dim3(kWG), 0, s, n, w, V, i0, nb, h, sign, want_norm, part);
+    return rows;
+}
+
+template <typename Tv> void launch_vscale(long n, const Tv *x, Tv *y, const double *d, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_vscale<Tv>), dim3(elementwise_blocks(n)), dim3(kWG), 0, s, n, x, y, d);
+}
+
+// ------------------------------------------------------------------------------------------
 // k_finalize: one workgroup.  Fixed-order FP64 reduction of the partial rows, then the
 // scalar part of the iteration (thread 0).
 // ------------------------------------------------------------------------------------------
@@ -979,6 +1092,17 @@ void launch_sub_to_f32(long n, const double *a, const double *b, float *out, hip
     hipLaunchKernelGGL(k_sub_to_f32, dim3(elementwise_blocks(n)), dim3(kWG), 0, s, n, a, b, out);
 }
 
+__global__ __launch_bounds__(kWG) void k_cast_f32(long n, const double *__restrict__ a, float *__restrict__ out)
+{
+    const long stride = (long)gridDim.x * kWG;
+    for (long i = (long)blockIdx.x * kWG + threadIdx.x; i < n; i += stride) out[i] = static_cast<float>(a[i]);
+}
+
+void launch_cast_f32(long n, const double *a, float *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_cast_f32, dim3(elementwise_blocks(n)), dim3(kWG), 0, s, n, a, out);
+}
+
 __global__ __launch_bounds__(kWG) void k_check_finite(long n, const double *__restrict__ v, int *bad)
 {
     int cnt = 0;
@@ -1167,6 +1291,14 @@ template void launch_dot2<double>(long, const double *, const double *, const do
                                   int *, const Scalars *, int, hipStream_t);
 template void launch_dot2<float>(long, const float *, const float *, const float *, const float *, double *, int *,
                                  const Scalars *, int, hipStream_t);
+template int launch_mdot<double>(long, const double *, const double *, int, int, double *, double *, hipStream_t);
+template int launch_mdot<float>(long, const float *, const float *, int, int, double *, double *, hipStream_t);
+template int launch_maxpy<double>(long, double *, const double *, int, int, const double *, double, int, double *,
+                                  hipStream_t);
+template int launch_maxpy<float>(long, float *, const float *, int, int, const double *, double, int, double *,
+                                 hipStream_t);
+template void launch_vscale<double>(long, const double *, double *, const double *, hipStream_t);
+template void launch_vscale<float>(long, const float *, float *, const double *, hipStream_t);
 template void launch_fill<double>(double *, long, double, hipStream_t);
 template void launch_fill<float>(float *, long, float, hipStream_t);
 

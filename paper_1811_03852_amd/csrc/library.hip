@@ -71,6 +71,13 @@ template <typename T> void dfree(T *&p)
     p = nullptr;
 }
 
+constexpr int kMaxGmres = 64;   // largest FGMRES restart length
+
+template <typename Tv> struct Fgm {   // FGMRES basis storage of one precision
+    Tv *V = nullptr, *Z = nullptr, *W = nullptr, *R = nullptr, *tmp = nullptr;
+    int m = 0;
+};
+
 template <typename Tv> struct Work {
     Tv *r = nullptr, *rh = nullptr, *p = nullptr, *ph = nullptr, *v = nullptr, *s = nullptr, *sh = nullptr,
        *t = nullptr, *x = nullptr;
@@ -92,6 +99,7 @@ struct eg_net {
     double *d_loss = nullptr;   // per-pair losses of the current pass
     long loss_cap = 0;
     int step = 0;               // Adam steps taken
+    int loss_kind = 1;          // 0: ||M(r) - e||^2 / ||e||^2,  1: ||A M(r) - r||^2 / ||r||^2
 };
 
 struct eg_operator {
@@ -135,6 +143,20 @@ struct eg_operator {
     int hist_count = 0;
     eg_net *net = nullptr;      // learned preconditioner attached to this operator (not owned)
     double *harvest_x = nullptr;
+    int method = 0;             // plain modes: 0 BiCGStab, 1 FGMRES
+    int learned_method = 1;     // learned modes: 0 flexible BiCGStab, 1 FGMRES
+    int gm_m = 30;              // FGMRES restart length
+    Fgm<double> f64;
+    Fgm<float> f32;
+    double *d_h = nullptr;      // FGMRES: Gram-Schmidt coefficients (two passes) / solution weights
+    double *mpart = nullptr;    // FGMRES: partial sums of the blocked dot products
+    double *h_h = nullptr;      // pinned host mirror of d_h
+    std::vector<double> hist_pending;   // history written on the host (FGMRES)
+    template <typename Tv> Fgm<Tv> &fgm()
+    {
+        if constexpr (std::is_same_v<Tv, double>) return f64;
+        else return f32;
+    }
 
     OpView<double> view64() const { return {a64, m64, nullptr, nlon, nlat, nlev, P, n}; }
     OpView<float> view32() const { return {a32, m32, nullptr, nlon, nlat, nlev, P, n}; }
@@ -427,6 +449,155 @@ int krylov_run_learned(eg_operator *op, const OpView<Tc> &A, Work<Tv> &w, eg_net
     return 0;
 }
 
+// ---- FGMRES ------------------------------------------------------------------------------
+template <typename Tv> int ensure_fgm(eg_operator *op)
+{
+    Fgm<Tv> &F = op->fgm<Tv>();
+    int rc;
+    if (!op->d_h) {
+        if ((rc = dalloc(&op->d_h, 4 * (kMaxGmres + 2)))) return rc;
+        if ((rc = dalloc(&op->mpart, (size_t)8192 * kMBlk))) return rc;
+        if (hipHostMalloc(reinterpret_cast<void **>(&op->h_h), 4 * (kMaxGmres + 2) * sizeof(double)) != hipSuccess)
+            return fail(EG_ENOMEM, "hipHostMalloc failed");
+    }
+    if (F.m == op->gm_m && F.V) return 0;
+    dfree(F.V); dfree(F.Z); dfree(F.W); dfree(F.R); dfree(F.tmp);
+    F.m = 0;
+    const size_t n = (size_t)op->n, m = (size_t)op->gm_m;
+    if ((rc = dalloc(&F.V, (m + 1) * n)) || (rc = dalloc(&F.Z, m * n)) || (rc = dalloc(&F.W, n)) ||
+        (rc = dalloc(&F.R, n)) || (rc = dalloc(&F.tmp, n)))
+        return rc;
+    F.m = op->gm_m;
+    return 0;
+}
+
+// Right-preconditioned restarted FGMRES(m) for A d = rhs (Saad's flexible variant: the
+// preconditioned vectors z_j are kept, so M may change between applications, e.g. the learned
+// M).  On entry F.R holds rhs - A d; resid() must recompute it from the current d.  Classical
+// Gram-Schmidt with one reorthogonalisation pass; FP64 dot products.  Histories are relative
+// to nb.  Stops at |g| / nb <= tol (then checked against the recomputed residual) or maxit.
+// With a network the stall rule of the flexible BiCGStab applies to the residual estimates,
+// over at least one restart cycle: when the best residual has not halved within
+// max(stall_window, m) steps the cycle ends there and the iteration continues with T^{-1}.
+template <typename Tv, typename Tc, typename ResidFn>
+int fgmres(eg_operator *op, const OpView<Tc> &A, Tv *d, double nb, double tol, int maxit, eg_net *net,
+           const Tc *coef, ResidFn resid, int *iters, int *status, int *fallbacks)
+{
+    int rc;
+    if ((rc = ensure_fgm<Tv>(op))) return rc;
+    Fgm<Tv> &F = op->fgm<Tv>();
+    hipStream_t s = op->stream;
+    const long n = op->n;
+    const int m = F.m;
+    const TriView<Tv> T = op->tri_view<Tv>();
+    bool use_net = net != nullptr;
+    Tv *qp = nullptr;
+    if (use_net) qp = F.tmp;
+    std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
+    auto Hij = [&](int i, int j) -> double & { return H[(size_t)i * m + j]; };
+    int it = 0, anchor_it = 0;
+    *status = 1;
+    double anchor = INFINITY;
+    bool stalled = false;
+    for (;;) {
+        // beta = ||R||
+        int nr = 0;
+        launch_dot<Tv, Tv>(n, F.R, F.R, op->partials, &nr, s);
+        launch_finalize(FIN_SUM, op->partials, nr, op->sc, nullptr, op->d_out, 0, 0, s);
+        EG_HIP(hipMemcpyAsync(op->h_out, op->d_out, sizeof(double), hipMemcpyDeviceToHost, s));
+        EG_HIP(hipStreamSynchronize(s));
+        const double beta = std::sqrt(op->h_out[0]);
+        if (beta / nb <= tol || beta == 0.0) { *status = 0; break; }
+        if (it >= maxit) break;
+        if (!std::isfinite(beta)) { *status = 2; break; }
+        if (stalled) {
+            use_net = false;
+            *fallbacks += 1;
+            stalled = false;
+        }
+        if (beta / nb <= 0.5 * anchor) {
+            anchor = beta / nb;
+            anchor_it = it;
+        }
+        // v0 = R / beta
+        op->h_h[0] = beta;
+        EG_HIP(hipMemcpyAsync(op->d_h + 2 * (kMaxGmres + 1), op->h_h, sizeof(double), hipMemcpyHostToDevice, s));
+        launch_vscale<Tv>(n, F.R, F.V, op->d_h + 2 * (kMaxGmres + 1), s);
+        std::fill(g.begin(), g.end(), 0.0);
+        g[0] = beta;
+        int jend = -1;
+        for (int j = 0; j < m; ++j) {
+            Tv *Vj = F.V + (size_t)j * n, *Zj = F.Z + (size_t)j * n;
+            launch_thomas<Tv>(T, Vj, Zj, TH_PLAIN, nullptr, nullptr, nullptr, nullptr, op->partials, nullptr, nullptr, s);
+            if constexpr (std::is_same_v<Tc, float> || std::is_same_v<Tc, double>)
+                if (use_net) enqueue_net_stage<Tv, Tc>(op, net, coef, Vj, Zj, qp, nullptr, 0);
+            launch_spmv<Tv, Tc>(A, Zj, F.W, nullptr, SP_PLAIN, op->partials, nullptr, nullptr, 0, s);
+            for (int pass = 0; pass < 2; ++pass) {
+                double *hp = op->d_h + pass * (kMaxGmres + 1);
+                for (int i0 = 0; i0 <= j; i0 += kMBlk)
+                    launch_mdot<Tv>(n, F.W, F.V, i0, std::min(kMBlk, j + 1 - i0), op->mpart, hp, s);
+                for (int i0 = 0; i0 <= j; i0 += kMBlk) {
+                    const bool last = (pass == 1) && (i0 + kMBlk > j);
+                    nr = launch_maxpy<Tv>(n, F.W, F.V, i0, std::min(kMBlk, j + 1 - i0), hp, -1.0, last, op->partials, s);
+                }
+            }
+            launch_finalize(FIN_SUM, op->partials, nr, op->sc, nullptr, op->d_out, 0, 0, s);
+            EG_HIP(hipMemcpyAsync(op->h_h, op->d_h, 2 * (kMaxGmres + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
+            EG_HIP(hipMemcpyAsync(op->h_out, op->d_out, sizeof(double), hipMemcpyDeviceToHost, s));
+            EG_HIP(hipGetLastError());
+            EG_HIP(hipStreamSynchronize(s));
+            for (int i = 0; i <= j; ++i) Hij(i, j) = op->h_h[i] + op->h_h[kMaxGmres + 1 + i];
+            const double hn = std::sqrt(op->h_out[0]);
+            Hij(j + 1, j) = hn;
+            // v_{j+1} = w / h_{j+1,j}
+            if (hn > 0.0) {
+                op->h_h[0] = hn;
+                EG_HIP(hipMemcpyAsync(op->d_h + 2 * (kMaxGmres + 1), op->h_h, sizeof(double), hipMemcpyHostToDevice,
+                                      s));
+                launch_vscale<Tv>(n, F.W, F.V + (size_t)(j + 1) * n, op->d_h + 2 * (kMaxGmres + 1), s);
+            }
+            // Givens rotations: apply the previous ones to column j, then annihilate H(j+1, j)
+            for (int i = 0; i < j; ++i) {
+                const double a = Hij(i, j), b = Hij(i + 1, j);
+                Hij(i, j) = cs[i] * a + sn[i] * b;
+                Hij(i + 1, j) = -sn[i] * a + cs[i] * b;
+            }
+            const double a = Hij(j, j), b = Hij(j + 1, j);
+            const double rr = std::hypot(a, b);
+            cs[j] = rr > 0.0 ? a / rr : 1.0;
+            sn[j] = rr > 0.0 ? b / rr : 0.0;
+            Hij(j, j) = rr;
+            Hij(j + 1, j) = 0.0;
+            g[j + 1] = -sn[j] * g[j];
+            g[j] = cs[j] * g[j];
+            ++it;
+            const double R = std::fabs(g[j + 1]) / nb;
+            op->hist_pending.push_back(R);
+            jend = j;
+            if (R <= 0.5 * anchor) {
+                anchor = R;
+                anchor_it = it;
+            }
+            if (use_net && (it - anchor_it >= std::max(op->stall_window, m) || !std::isfinite(R))) stalled = true;
+            if (R <= tol || it >= maxit || hn == 0.0 || !std::isfinite(hn) || stalled) break;
+        }
+        // y = H^{-1} g (upper triangular), d += Z y
+        for (int i = jend; i >= 0; --i) {
+            double t = g[i];
+            for (int k = i + 1; k <= jend; ++k) t -= Hij(i, k) * y[k];
+            y[i] = Hij(i, i) != 0.0 ? t / Hij(i, i) : 0.0;
+        }
+        for (int i = 0; i <= jend; ++i) op->h_h[i] = y[i];
+        EG_HIP(hipMemcpyAsync(op->d_h, op->h_h, (jend + 1) * sizeof(double), hipMemcpyHostToDevice, s));
+        for (int i0 = 0; i0 <= jend; i0 += kMBlk)
+            launch_maxpy<Tv>(n, d, F.Z, i0, std::min(kMBlk, jend + 1 - i0), op->d_h, 1.0, 0, op->partials, s);
+        resid();
+        EG_HIP(hipGetLastError());
+    }
+    *iters = it;
+    return 0;
+}
+
 double fetch_out(eg_operator *op, int idx)
 {
     return op->h_out[idx];
@@ -478,6 +649,26 @@ int solve_fp64(eg_operator *op, const double *b, double *x, double tol, int maxi
         EG_HIP(hipStreamSynchronize(s));
         op->info.true_rel_residual = 0.0;
         return EG_CONVERGED;
+    }
+    if ((net ? op->learned_method : op->method) == 1) {
+        // restarted FGMRES(m); every cycle ends on the FP64 true residual
+        Fgm<double> *F = nullptr;
+        if ((rc = ensure_fgm<double>(op))) return rc;
+        F = &op->f64;
+        const double nb = std::sqrt(op->h_sc->nb2);
+        launch_residual<double>(A, b, w.x, F->R, op->partials, &nr, s);
+        auto resid = [&]() { launch_residual<double>(A, b, w.x, F->R, op->partials, &nr, s); };
+        int its = 0, st = 1, fb = 0;
+        if ((rc = fgmres<double, double>(op, A, w.x, nb, tol, maxit, net, op->a64, resid, &its, &st, &fb))) return rc;
+        op->info.iterations = its;
+        op->info.fallbacks += fb;
+        op->hist_count = its;
+        EG_HIP(hipMemcpyAsync(x, w.x, op->n * sizeof(double), hipMemcpyDeviceToDevice, s));
+        int n2;
+        if ((rc = true_residual<double>(op, b, x, static_cast<double *>(nullptr), &n2))) return rc;
+        op->info.true_rel_residual = std::sqrt(op->h_out[0] / op->h_out[1]);
+        if (op->info.true_rel_residual <= tol) return EG_CONVERGED;
+        return st == 2 ? EG_BREAKDOWN : (its >= maxit ? EG_MAXIT : EG_STALLED);
     }
     int gap = 0, status = EG_CONVERGED;
     bool use_net = net != nullptr;
@@ -579,6 +770,32 @@ int solve_ir(eg_operator *op, const OpView<Tc> &A32, const double *b, double *x,
         launch_finalize(FIN_INIT, op->partials, nr, op->sc, op->d_hist, nullptr, 2, 2, s);
         launch_fill<float>(w.x, op->n, 0.0f, s);
         EG_HIP(hipGetLastError());
+        if ((net ? op->learned_method : op->method) == 1) {
+            // inner FGMRES on A32 d = r32 (F.R = r32 - A32 d, recomputed after every cycle)
+            if ((rc = ensure_fgm<float>(op))) return rc;
+            Fgm<float> &F = op->f32;
+            EG_HIP(hipMemcpyAsync(F.R, w.r, op->n * sizeof(float), hipMemcpyDeviceToDevice, s));
+            const double nb_in = std::sqrt(op->h_out[2]);
+            auto resid = [&]() {
+                launch_spmv<float, Tc>(A32, w.x, F.tmp, nullptr, SP_PLAIN, op->partials, nullptr, nullptr, 0, s);
+                launch_net_diff(op->n, w.r, F.tmp, F.R, s);
+            };
+            int its = 0, st = 1, fb = 0;
+            const Tc *coef = nullptr;
+            if constexpr (std::is_same_v<Tc, float>) coef = op->a32;
+            if ((rc = fgmres<float, Tc>(op, A32, w.x, nb_in, eta, maxit - total, use_net ? net : nullptr, coef, resid,
+                                        &its, &st, &fb)))
+                return rc;
+            if (fb) {
+                use_net = false;
+                op->info.fallbacks += fb;
+            }
+            total += its;
+            launch_add_correction(op->n, x, w.x, s);
+            EG_HIP(hipGetLastError());
+            ++outer;
+            continue;
+        }
         if constexpr (std::is_same_v<Tc, float>) {
             if (use_net) {
                 int fb = 0;
@@ -645,13 +862,29 @@ int net_pair_pass(eg_net *net, eg_operator *op, const float *r, const float *e, 
     launch_net_out<float>(g, net->d, net->act, r, net->t_qp, nullptr, op->sc, 0, s);
     launch_thomas<float>(T, net->t_qp, net->t_m, TH_PLAIN, nullptr, nullptr, nullptr, nullptr, op->partials, nullptr,
                          nullptr, s);
-    launch_net_diff(n, net->t_m, e, net->t_diff, s);
-    launch_dot2<float>(n, net->t_diff, net->t_diff, e, e, op->partials, &nr, nullptr, 0, s);
-    launch_finalize(FIN_LOSS, op->partials, nr, op->sc, nullptr, loss_slot, 0, 0, s);
-    if (backward) {
-        launch_net_gseed(n, net->t_m, e, net->t_g, op->sc, s);
-        launch_thomas_t(T, net->t_g, net->t_u, s);
-        launch_net_backward(g, net->d, net->act, net->t_u, op->sc, scale, accumulate, s);
+    if (net->loss_kind == 1) {
+        // residual space: d = A m - r, loss ||d||^2 / ||r||^2, dL/dm = A^T (2 d / ||r||^2)
+        launch_spmv<float, float>(op->view32(), net->t_m, net->t_g, nullptr, SP_PLAIN, op->partials, nullptr, nullptr,
+                                  0, s);
+        launch_net_diff(n, net->t_g, r, net->t_diff, s);
+        launch_dot2<float>(n, net->t_diff, net->t_diff, r, r, op->partials, &nr, nullptr, 0, s);
+        launch_finalize(FIN_LOSS, op->partials, nr, op->sc, nullptr, loss_slot, 0, 0, s);
+        if (backward) {
+            launch_net_gseed(n, net->t_g, r, net->t_g, op->sc, s);
+            launch_spmv_t(g, op->a32, op->m32, net->t_g, net->t_z0, s);
+            launch_thomas_t(T, net->t_z0, net->t_u, s);
+            launch_net_backward(g, net->d, net->act, net->t_u, op->sc, scale, accumulate, s);
+        }
+    } else {
+        // error space: loss ||m - e||^2 / ||e||^2, dL/dm = 2 (m - e) / ||e||^2
+        launch_net_diff(n, net->t_m, e, net->t_diff, s);
+        launch_dot2<float>(n, net->t_diff, net->t_diff, e, e, op->partials, &nr, nullptr, 0, s);
+        launch_finalize(FIN_LOSS, op->partials, nr, op->sc, nullptr, loss_slot, 0, 0, s);
+        if (backward) {
+            launch_net_gseed(n, net->t_m, e, net->t_g, op->sc, s);
+            launch_thomas_t(T, net->t_g, net->t_u, s);
+            launch_net_backward(g, net->d, net->act, net->t_u, op->sc, scale, accumulate, s);
+        }
     }
     EG_HIP(hipGetLastError());
     return 0;
@@ -696,6 +929,10 @@ void eg_destroy_operator(eg_operator *op)
     dfree(op->a32); dfree(op->m32); dfree(op->tri32);
     for (int i = 0; i < 2; ++i) { dfree(op->aq[i]); dfree(op->qs[i]); }
     dfree(op->harvest_x);
+    for (Fgm<double> *F : {&op->f64}) { dfree(F->V); dfree(F->Z); dfree(F->W); dfree(F->R); dfree(F->tmp); }
+    for (Fgm<float> *F : {&op->f32}) { dfree(F->V); dfree(F->Z); dfree(F->W); dfree(F->R); dfree(F->tmp); }
+    dfree(op->d_h); dfree(op->mpart);
+    if (op->h_h) (void)hipHostFree(op->h_h);
     dfree(op->w64.qp);
     dfree(op->w32.qp);
     for (Work<double> *w : {&op->w64}) {
@@ -781,6 +1018,15 @@ int eg_set_option(eg_operator *op, const char *key, double value)
         op->poll = (int)value;
     } else if (k == "graph") {
         op->use_graph = value != 0.0;
+    } else if (k == "method") {
+        if (value != 0.0 && value != 1.0) return fail(EG_EINVAL, "method must be 0 (BiCGStab) or 1 (FGMRES)");
+        op->method = (int)value;
+    } else if (k == "learned_method") {
+        if (value != 0.0 && value != 1.0) return fail(EG_EINVAL, "learned_method must be 0 or 1");
+        op->learned_method = (int)value;
+    } else if (k == "gmres_m") {
+        if (value < 1 || value > kMaxGmres) return fail(EG_EINVAL, "gmres_m must be in [1, 64]");
+        op->gm_m = (int)value;
     } else if (k == "profile") {
         op->profile = value != 0.0;
     } else if (k == "stall_window") {
@@ -811,6 +1057,7 @@ int eg_solve(eg_operator *op, const double *b, double *x, double tol, int maxit,
     const auto t0 = std::chrono::steady_clock::now();
     op->info = eg_info{};
     op->hist_count = 0;
+    op->hist_pending.clear();
     int rc;
     if ((rc = check_vectors(op, b, x))) return rc;
     if ((rc = ensure_hist(op, std::min(maxit, 1 << 22)))) return rc;
@@ -841,6 +1088,11 @@ int eg_solve(eg_operator *op, const double *b, double *x, double tol, int maxit,
     }
     if (status < 0) return status;
     // history to the host
+    if (!op->hist_pending.empty()) {
+        op->hist_host = op->hist_pending;
+        op->info.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        return status;
+    }
     const int cnt = std::min(op->hist_count, op->hist_cap);
     op->hist_host.assign(cnt, 0.0);
     if (cnt > 0) {
@@ -1039,6 +1291,13 @@ int eg_net_create(unsigned long long seed, eg_net **out)
     return 0;
 }
 
+int eg_net_set_loss(eg_net *net, int kind)
+{
+    if (!net || (kind != 0 && kind != 1)) return fail(EG_EINVAL, "loss kind must be 0 or 1");
+    net->loss_kind = kind;
+    return 0;
+}
+
 int eg_attach_learned_pc(eg_operator *op, eg_net *net)
 {
     if (!op) return fail(EG_EINVAL, "op is NULL");
@@ -1090,15 +1349,17 @@ int eg_harvest(eg_operator *op, const double *b, int nsnap, float *r_out, float 
     Work<double> &w = op->w64;
     const OpView<double> A = op->view64();
     launch_fill<double>(w.x, op->n, 0.0, s);
-    if ((rc = put_run_params(op, 1e-300, nsnap, 0, 0))) return rc;
+    if ((rc = put_run_params(op, 1e-300, std::max(nsnap - 1, 1), 0, 0))) return rc;
     int nr = 0;
     launch_residual<double>(A, b, w.x, w.r, op->partials, &nr, s);
     launch_finalize(FIN_INIT, op->partials, nr, op->sc, op->d_hist, nullptr, 0, 1, s);
     int count = 0;
     for (int i = 0; i < nsnap; ++i) {
-        if ((rc = sync_scalars(op))) return rc;
-        if (op->h_sc->done) break;
-        enqueue_iteration<double, double>(op, A, w, nullptr);
+        if (i > 0) {   // snapshot 0 is the initial guess x0 = 0 (r_0 = b, e_0 = x*)
+            if ((rc = sync_scalars(op))) return rc;
+            if (op->h_sc->done) break;
+            enqueue_iteration<double, double>(op, A, w, nullptr);
+        }
         launch_residual<float>(A, b, w.x, r_out + (size_t)i * op->n, op->partials, &nr, s);
         launch_sub_to_f32(op->n, op->harvest_x, w.x, e_out + (size_t)i * op->n, s);
         EG_HIP(hipGetLastError());
@@ -1106,6 +1367,52 @@ int eg_harvest(eg_operator *op, const double *b, int nsnap, float *r_out, float 
     }
     EG_HIP(hipStreamSynchronize(s));
     return count;
+}
+
+int eg_harvest_krylov(eg_operator *op, const double *b, int nvec, float *r_out, float *e_out)
+{
+    if (!op || !b || !r_out || nvec < 1 || nvec > kMaxGmres) return fail(EG_EINVAL, "bad argument");
+    int rc;
+    if ((rc = check_vectors(op, b, b))) return rc;
+    if ((rc = ensure_work(op, op->w64))) return rc;
+    if (!op->harvest_x && (rc = dalloc(&op->harvest_x, (size_t)op->n))) return rc;
+    if ((rc = ensure_hist(op, 20000))) return rc;
+    // one FGMRES(nvec) cycle with M = T^{-1} from x0 = 0; its basis v_0 .. v_{nvec-1} are the
+    // vectors the preconditioner is applied to
+    struct Restore {
+        eg_operator *op;
+        int m, method;
+        ~Restore() { op->gm_m = m; op->method = method; op->hist_pending.clear(); }
+    } restore{op, op->gm_m, op->method};
+    op->gm_m = nvec;
+    if ((rc = ensure_fgm<double>(op))) return rc;
+    Fgm<double> &F = op->f64;
+    Work<double> &w = op->w64;
+    hipStream_t s = op->stream;
+    const OpView<double> A = op->view64();
+    const long n = op->n;
+    launch_fill<double>(w.x, n, 0.0, s);
+    EG_HIP(hipMemcpyAsync(F.R, b, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    int nr = 0;
+    auto resid = [&]() { launch_residual<double>(A, b, w.x, F.R, op->partials, &nr, s); };
+    int its = 0, st = 1, fb = 0;
+    if ((rc = fgmres<double, double>(op, A, w.x, 1.0, 0.0, nvec, nullptr, op->a64, resid, &its, &st, &fb)))
+        return rc;
+    // errors e_j = A^{-1} v_j from tight FP64 BiCGStab solves (the basis is not touched by them)
+    op->method = 0;
+    for (int j = 0; j < its; ++j) {
+        const double *vj = F.V + (size_t)j * n;
+        launch_cast_f32(n, vj, r_out + (size_t)j * n, s);
+        EG_HIP(hipGetLastError());
+        if (!e_out) continue;
+        launch_fill<double>(op->harvest_x, n, 0.0, s);
+        const int sst = solve_fp64(op, vj, op->harvest_x, 1e-10, 20000);
+        if (sst < 0) return sst;
+        launch_cast_f32(n, op->harvest_x, e_out + (size_t)j * n, s);
+        EG_HIP(hipGetLastError());
+    }
+    EG_HIP(hipStreamSynchronize(s));
+    return its;
 }
 
 int eg_net_train(eg_net *net, eg_operator *const *ops, int nops, const float *r, const float *e, const int *pair_op,

@@ -90,6 +90,13 @@ __device__ __forceinline__ bool stop_now(const Scalars *sc, int mask)
     return ((mask & STOP_DONE) && sc->done) || ((mask & STOP_SKIP) && sc->skip) || ((mask & STOP_HALF) && sc->half);
 }
 
+int net_blocks(long n, long per_block, long cap)
+{
+    long b = (n + per_block - 1) / per_block;
+    if (b > cap) b = cap;
+    return (int)(b < 1 ? 1 : b);
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------------------------------
@@ -497,6 +504,40 @@ __global__ __launch_bounds__(256) void k_thomas_t(TriView<float> tv, const float
 }
 
 // ------------------------------------------------------------------------------------------
+// y = A^T x in FP32 (gradient of the residual-space loss):
+//   (A^T x)_c = C_c x_c - W(c+1) x(c+1) - E(c-1) x(c-1) - S(j+1) x(j+1) - N(j-1) x(j-1)
+//               - D(k+1) x(k+1) - U(k-1) x(k-1),   C = m + sum of the six couplings
+// (longitude periodic; terms across a pole, the bottom or the top are absent)
+// ------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_spmv_t(NetGeo g, const float *__restrict__ a, const float *__restrict__ mg,
+                                                const float *__restrict__ x, float *__restrict__ y)
+{
+    const long n = g.n;
+    const long stride = (long)gridDim.x * 256;
+    for (long c = (long)blockIdx.x * 256 + threadIdx.x; c < n; c += stride) {
+        const Pos p = decompose(g, c);
+        const long cw = c - p.i + (p.i == 0 ? g.nlon - 1 : p.i - 1);
+        const long ce = c - p.i + (p.i == g.nlon - 1 ? 0 : p.i + 1);
+        float diag = mg[c];
+#pragma unroll
+        for (int d = 0; d < 6; ++d) diag += a[d * n + c];
+        float s = diag * x[c];
+        s -= a[ce] * x[ce];              // row c+1 couples to c through its W coupling
+        s -= a[n + cw] * x[cw];          // row c-1 through its E coupling
+        if (p.j < g.nlat - 1) s -= a[2 * n + c + g.nlon] * x[c + g.nlon];
+        if (p.j > 0) s -= a[3 * n + c - g.nlon] * x[c - g.nlon];
+        if (p.k < g.nlev - 1) s -= a[4 * n + c + g.P] * x[c + g.P];
+        if (p.k > 0) s -= a[5 * n + c - g.P] * x[c - g.P];
+        y[c] = s;
+    }
+}
+
+void launch_spmv_t(const NetGeo &g, const float *a, const float *m, const float *x, float *y, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_spmv_t, dim3(net_blocks(g.n, 1024, 8192)), dim3(256), 0, s, g, a, m, x, y);
+}
+
+// ------------------------------------------------------------------------------------------
 // parameters: gradient reduction, Adam, BF16 copies
 // ------------------------------------------------------------------------------------------
 // grad[i] = (accumulate ? grad[i] : 0) + scale * sum over the launch's partial rows of part[row][i]
@@ -554,13 +595,6 @@ __global__ __launch_bounds__(256) void k_net_adam(NetDev d, float lr, float b1, 
 // ------------------------------------------------------------------------------------------
 // launchers
 // ------------------------------------------------------------------------------------------
-static int net_blocks(long n, long per_block, long cap)
-{
-    long b = (n + per_block - 1) / per_block;
-    if (b > cap) b = cap;
-    return (int)(b < 1 ? 1 : b);
-}
-
 template <typename Tv, typename Tc>
 void launch_net_features(const NetGeo &g, const Tv *q, const Tv *z0, const Tc *a, uint16_t *x0, const Scalars *sc,
                          int stop_mask, hipStream_t s)

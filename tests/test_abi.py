@@ -44,6 +44,8 @@ def test_argument_errors_without_device_work(lib):
     assert lib.eg_create_operator(ctypes.c_void_p(8), 10, 0, 10, ctypes.byref(h)) == -1
     assert lib.eg_solve(None, None, None, 1e-8, 10, 0) == -1
     assert lib.eg_set_option(None, b"eta", 1e-4) == -1
+    assert lib.eg_harvest_krylov(None, None, 5, None, None) == -1
+    assert lib.eg_harvest(None, None, 5, None, None) == -1
     lib.eg_destroy_operator(None)
 
 

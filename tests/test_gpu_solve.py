@@ -176,3 +176,53 @@ def test_bitwise_deterministic(eg, c1):
                 outs.append((host(x), op.history()))
         for a, b2 in zip(outs[:2], outs[2:]):
             assert np.array_equal(a[0], b2[0]) and np.array_equal(a[1], b2[1])
+
+
+def test_fgmres_fp64_matches_oracle(eg, oracle_mod, c1):
+    """Restarted FGMRES(30) with T^{-1}: the same residual history as the FP64 oracle FGMRES
+    (the same method; the GPU orthogonalises by classical Gram-Schmidt applied twice, the oracle
+    by modified Gram-Schmidt, equal in exact arithmetic) and the same solution."""
+    import torch
+    from oracle import krylov
+    p, coef, b, x_ref, _ = c1
+    x_o, info_o = krylov.fgmres(coef, b, tol=1e-10, m=30, maxit=3000)
+    assert info_o.status == 0
+    with eg.Operator(dev(coef)) as op:
+        op.set_option("method", 1)
+        op.set_option("gmres_m", 30)
+        x = torch.zeros(p.n, dtype=torch.float64, device="cuda")
+        info = op.solve(dev(b), x, 1e-10, 3000, eg.FP64)
+        h = op.history()
+    xh = host(x)
+    rel = _true_rel(oracle_mod, coef, b, xh)
+    k = min(len(h), len(info_o.history), 60)
+    hdiff = np.max(np.abs(h[:k] - info_o.history[:k]) / info_o.history[:k])
+    print(f"FGMRES: GPU {info.iterations} its, oracle {info_o.iterations}; history rel diff (first {k}) "
+          f"{hdiff:.1e}; true R {rel:.2e}")
+    assert info.status == eg.CONVERGED and rel <= 1e-10
+    assert abs(info.iterations - info_o.iterations) <= 2 and len(h) == info.iterations
+    assert hdiff <= 1e-6
+    assert np.linalg.norm(xh - x_o) <= 1e-7 * np.linalg.norm(x_o)
+
+
+@pytest.mark.parametrize("mode_name", ["FP32_IR", "FP32_IR_BF16"])
+def test_fgmres_refinement_modes_reach_1e8(eg, oracle_mod, c1, mode_name):
+    import torch
+    p, coef, b, x_ref, _ = c1
+    with eg.Operator(dev(coef)) as op:
+        op.set_option("method", 1)
+        x = torch.zeros(p.n, dtype=torch.float64, device="cuda")
+        info = op.solve(dev(b), x, 1e-8, 5000, getattr(eg, mode_name))
+    xh = host(x)
+    rel = _true_rel(oracle_mod, coef, b, xh)
+    print(f"FGMRES {mode_name}: {info.iterations} its, {info.outer_steps} outer, true R {rel:.2e}")
+    assert info.status == eg.CONVERGED and rel <= 1e-8 and info.outer_steps >= 2
+    assert np.linalg.norm(xh - x_ref) <= 1e-5 * np.linalg.norm(x_ref)
+
+
+def test_fgmres_options_are_checked(eg, c1):
+    p, coef, b, _, _ = c1
+    with eg.Operator(dev(coef)) as op:
+        for key, bad in (("method", 2), ("learned_method", -1), ("gmres_m", 0), ("gmres_m", 65)):
+            with pytest.raises(eg.EndgameError):
+                op.set_option(key, bad)

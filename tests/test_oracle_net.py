@@ -1,5 +1,6 @@
 """Pins for the FP64 reference of the learned preconditioner (oracle/net.py)."""
 import numpy as np
+import pytest
 
 import oracle
 import synth
@@ -25,10 +26,11 @@ def test_parameter_count():
     assert net.N_PARAMS == 15233
 
 
-def test_gradient_matches_central_differences():
+@pytest.mark.parametrize("kind", [net.LOSS_ERROR, net.LOSS_RESIDUAL])
+def test_gradient_matches_central_differences(kind):
     """Plain FP64 network: the hand-written backward pass agrees with central differences."""
     p, coef, r, e, th = _small()
-    L, g = net.loss_and_grad(th, coef, r, e, bf16_round=False)
+    L, g = net.loss_and_grad(th, coef, r, e, bf16_round=False, kind=kind)
     rng = np.random.default_rng(7)
     # a sample of parameters from every tensor
     offs, o = [], 0
@@ -43,7 +45,7 @@ def test_gradient_matches_central_differences():
         tp[i] += h
         tm = th.copy()
         tm[i] -= h
-        fd.append((net.loss(tp, coef, r, e, False) - net.loss(tm, coef, r, e, False)) / (2 * h))
+        fd.append((net.loss(tp, coef, r, e, False, kind) - net.loss(tm, coef, r, e, False, kind)) / (2 * h))
     fd = np.array(fd)
     ga = g[offs]
     assert np.linalg.norm(fd - ga) <= 1e-6 * np.linalg.norm(ga), (np.linalg.norm(fd - ga), np.linalg.norm(ga))
@@ -88,3 +90,18 @@ def test_bf16_rounding():
     v = np.random.default_rng(0).standard_normal(1000).astype(np.float32)
     t = torch.from_numpy(v).to(torch.bfloat16).to(torch.float64).numpy()
     assert np.array_equal(net.bf16(v.astype(np.float64)), t)
+
+
+def test_transpose_coefficients_give_the_adjoint():
+    """<A x, y> = <x, A^T y> with A^T applied as a 7-point operator (non-symmetric operator,
+    periodic longitude, pole and top/bottom rows)."""
+    p = synth.Problem(9, 6, 5, seed=12)
+    coef = synth.make_coeffs(p)
+    rng = np.random.default_rng(4)
+    x = rng.standard_normal(p.n)
+    y = rng.standard_normal(p.n)
+    lhs = np.dot(oracle.apply(coef, x), y)
+    rhs = np.dot(x, oracle.apply(net.transpose_coeffs(coef), y))
+    assert abs(lhs - rhs) <= 1e-12 * np.linalg.norm(x) * np.linalg.norm(y) * 10
+    A = oracle.dense_matrix(coef)
+    assert np.allclose(oracle.dense_matrix(net.transpose_coeffs(coef)), A.T, rtol=0, atol=1e-15)
