@@ -132,7 +132,6 @@ int eg_set_stream(eg_operator *op, void *hip_stream);
  *                    (Sec. 4 uses 150 operationally)
  *   "max_outer"      limit on refinement steps [30]
  *   "poll"           iterations enqueued between host checks of the device flags [8]
- *   "graph"          1 = replay batches of iterations as HIP graphs, 0 = plain launches [1]
  *   "stall_window"   learned modes: iterations without a 2x gain that trigger fallback [20]
  *                    (FGMRES: at least one restart cycle, max(stall_window, gmres_m))
  *   "profile"        1 = time every streaming kernel launch (see eg_kernel_stats) [0]

@@ -128,7 +128,6 @@ struct eg_operator {
     int restart_every = 0;
     int max_outer = 30;
     int poll = 8;
-    int use_graph = 1;
     int stall_window = 20;
     int profile = 0;
 
@@ -1016,8 +1015,6 @@ int eg_set_option(eg_operator *op, const char *key, double value)
     } else if (k == "poll") {
         if (value < 1 || value > 4096) return fail(EG_EINVAL, "poll must be in [1, 4096]");
         op->poll = (int)value;
-    } else if (k == "graph") {
-        op->use_graph = value != 0.0;
     } else if (k == "method") {
         if (value != 0.0 && value != 1.0) return fail(EG_EINVAL, "method must be 0 (BiCGStab) or 1 (FGMRES)");
         op->method = (int)value;
