@@ -1,0 +1,147 @@
+"""Parity at the benchmark's full sizes, in the launch configuration bench.py times.
+
+2560x1920x70 (344M unknowns): SpMV and Thomas outputs on sampled rows and columns against the
+oracle computed one row / one column at a time; every solver mode's true residual recomputed
+by the oracle's full FP64 matrix-vector product on the host; the modes' solutions against each
+other.  640x480x70 with a manufactured solution: forward error against x*.
+"""
+import numpy as np
+import pytest
+
+import synth
+from tests.helpers import host
+
+pytestmark = pytest.mark.gpu
+
+EPS64 = 2.0 ** -53
+EPS32 = 2.0 ** -24
+
+
+@pytest.fixture(scope="module")
+def eg():
+    import torch
+    import paper_1811_03852_amd as eg
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    eg.load_library()
+    return eg
+
+
+@pytest.fixture(scope="module")
+def c3(eg):
+    import torch
+    p = synth.CONFIGS["c3"]
+    coef = synth.make_coeffs(p, threads=16)
+    b = synth.make_rhs(p).ravel()
+    print(f"[fullsize] 2560x1920x70 generated", flush=True)
+    op = eg.Operator(torch.from_numpy(coef).cuda())
+    torch.cuda.synchronize()
+    yield p, coef, b, op
+    op.close()
+
+
+def _sample_points(p, rng, count):
+    """Random rows plus every corner of the grid (poles, lon wrap, bottom and top levels)."""
+    idx = rng.integers(0, p.n, count)
+    corners = [i + p.nlon * (j + p.nlat * k) for i in (0, 1, p.nlon - 1) for j in (0, 1, p.nlat - 1)
+               for k in (0, 1, p.nlev - 1)]
+    return np.unique(np.concatenate([idx, corners]))
+
+
+def _columns(coef, cols):
+    """The sampled columns as an nlev x 1 x ncols sub-problem (the tridiagonal solve is
+    column-local: only D, U and C enter it)."""
+    nlat, nlon = coef.shape[2:]
+    j, i = cols // nlon, cols % nlon
+    return np.ascontiguousarray(coef[:, :, j, i][:, :, None, :])
+
+
+def test_spmv_sampled_rows(eg, oracle_mod, c3):
+    import torch
+    p, coef, _, op = c3
+    rng = np.random.default_rng(31)
+    x = rng.standard_normal(p.n)
+    idx = _sample_points(p, rng, 20000)
+    ref = oracle_mod.apply_points(coef, x, idx)
+    cflat = coef[6].reshape(-1)[idx]
+    scale = 2.0 * cflat * np.max(np.abs(x))        # >= C|x_p| + sum a |x_d| (a >= 0, sum a <= C)
+    xd = torch.from_numpy(x).cuda()
+    y = host(op.apply(xd))[idx]
+    assert np.all(np.abs(y - ref) <= 32 * EPS64 * scale)
+    x32 = xd.float()
+    ref32 = oracle_mod.apply_points(coef, x32.double().cpu().numpy(), idx)
+    for prec, rel in ((eg.PREC_FP32, 0.0), (eg.PREC_BF16, 2.0 ** -8), (eg.PREC_FP16, 2.0 ** -11)):
+        y = host(op.apply(x32, prec=prec)).astype(np.float64)[idx]
+        err = np.abs(y - ref32)
+        print(f"SpMV prec {prec}: max |y - oracle| / scale = {np.max(err / scale):.2e}")
+        assert np.all(err <= (rel + 32 * EPS32) * scale)
+
+
+def test_thomas_sampled_columns(eg, oracle_mod, c3):
+    import torch
+    p, coef, _, op = c3
+    rng = np.random.default_rng(32)
+    P = p.nlon * p.nlat
+    cols = np.unique(np.concatenate([rng.integers(0, P, 3000), [0, p.nlon - 1, P - p.nlon, P - 1]]))
+    sub = _columns(coef, cols)
+    q = rng.standard_normal(p.n)
+    qd = torch.from_numpy(q).cuda()
+    dec = sub.copy()
+    dec[:4] = 0.0
+    neg = dec.copy()
+    neg[4:6] = -neg[4:6]
+    for prec, eps, qv in ((eg.PREC_FP64, EPS64, qd), (eg.PREC_FP32, EPS32, qd.float())):
+        z = host(op.precond(qv, prec=prec)).astype(np.float64).reshape(p.nlev, P)[:, cols].ravel()
+        qin = host(qv).astype(np.float64).reshape(p.nlev, P)[:, cols].ravel()
+        # componentwise backward error of a stable tridiagonal solve: |T z - q| <= c nlev eps |T||z|
+        res = np.abs(oracle_mod.apply(dec, z) - qin)
+        scl = oracle_mod.apply(neg, np.abs(z))
+        assert np.all(res <= 16 * p.nlev * eps * scl)
+        ref = oracle_mod.thomas(sub, qin)
+        print(f"Thomas prec {prec}: max rel diff to oracle {np.max(np.abs(z - ref)) / np.max(np.abs(ref)):.2e}")
+        if prec == eg.PREC_FP64:
+            # forward agreement per column within cond(T) (diagonal dominance bounds ||T^{-1}||)
+            tmin = (sub[6] - sub[4] - sub[5]).reshape(p.nlev, -1).min(axis=0)
+            kappa = 2 * sub[6].reshape(p.nlev, -1).max(axis=0) / tmin
+            err = np.abs(z - ref).reshape(p.nlev, -1).max(axis=0)
+            assert np.all(err <= 32 * p.nlev * EPS64 * kappa * np.abs(ref).reshape(p.nlev, -1).max(axis=0))
+
+
+def test_all_modes_reach_1e8_true_residual(eg, oracle_mod, c3):
+    import torch
+    p, coef, b, op = c3
+    bd = torch.from_numpy(b).cuda()
+    nb = np.linalg.norm(b)
+    sols = {}
+    for name in ("FP64", "FP32_IR", "FP32_IR_BF16"):
+        x = torch.zeros(p.n, dtype=torch.float64, device="cuda")
+        print(f"[fullsize] solving {name}", flush=True)
+        info = op.solve(bd, x, 1e-8, 20000, getattr(eg, name))
+        xh = host(x)
+        rel = np.linalg.norm(b - oracle_mod.apply(coef, xh)) / nb
+        print(f"{name}: status {info.status}, {info.iterations} its, {info.outer_steps} outer, {info.seconds:.2f} s, "
+              f"true R (oracle) {rel:.3e}, library {info.true_rel_residual:.3e}")
+        assert info.status == eg.CONVERGED and rel <= 1e-8 * (1 + 1e-6)
+        assert abs(rel - info.true_rel_residual) <= 1e-6 * rel
+        sols[name] = xh
+    ref = sols["FP64"]
+    for name in ("FP32_IR", "FP32_IR_BF16"):
+        d = np.linalg.norm(sols[name] - ref) / np.linalg.norm(ref)
+        print(f"{name} vs FP64: rel L2 {d:.2e}")
+        assert d <= 1e-4   # two solutions with R <= 1e-8 each, cond(A) ~ 1e3 at shift 1e-3
+
+
+def test_manufactured_solution_640x480x70(eg, oracle_mod):
+    import torch
+    p = synth.CONFIGS["c2"]
+    coef = synth.make_coeffs(p, threads=16)
+    xs = synth.make_xstar(p).ravel()
+    b = oracle_mod.apply(coef, xs)
+    with eg.Operator(torch.from_numpy(coef).cuda()) as op:
+        for name in ("FP64", "FP32_IR"):
+            x = torch.zeros(p.n, dtype=torch.float64, device="cuda")
+            info = op.solve(torch.from_numpy(b).cuda(), x, 1e-8, 20000, getattr(eg, name))
+            xh = host(x)
+            rel = np.linalg.norm(b - oracle_mod.apply(coef, xh)) / np.linalg.norm(b)
+            fwd = np.linalg.norm(xh - xs) / np.linalg.norm(xs)
+            print(f"640x480x70 {name}: {info.iterations} its, true R {rel:.2e}, forward error {fwd:.2e}")
+            assert info.status == eg.CONVERGED and rel <= 1e-8 * (1 + 1e-6) and fwd <= 1e-5
