@@ -5,7 +5,11 @@ the HBM roofline fraction of the dominant kernel and the CPU oracle as a reporte
 
 A step solves A x = b once in every listed mode (x0 = 0).  Inputs (operator and right-hand
 side) are generated on the host from the seeded recipe, copied to HBM and the operator is built
-before the timed region.  One JSON line is printed on stdout.
+before the timed region.  Learned modes first train the network (untimed, reported): FGMRES
+bases harvested from small operators of the same recipe, Adam on the residual-space loss.
+After the timed steps, the learned preconditioner is compared with the tridiagonal one on its
+own workload (640x480x70 by default), each with FGMRES(30) in FP32 with FP64 refinement, beside
+BiCGStab.  One JSON line is printed on stdout.
 """
 from __future__ import annotations
 
@@ -35,6 +39,13 @@ KERNEL_SYMBOL = {"spmv": "k_spmv", "thomas_p": "k_thomas", "thomas_s": "k_thomas
                  "residual": "k_spmv"}
 PREC_NAME = {0: "fp64", 1: "fp32", 2: "bf16", 3: "fp16"}
 
+# HBM bytes per launch measured with rocprofv3 FETCH_SIZE and WRITE_SIZE on the 2560x1920x70
+# grid (`python bench.py --traffic-probe` under `rocprofv3 --pmc`), scaled by the same counters
+# on a device copy of known size (FETCH_SIZE x 2, WRITE_SIZE x 1).  Valid while the kernels
+# are unchanged since that measurement; see profiles/hbm_traffic_2560x1920x70.txt.
+MEASURED_TRAFFIC = {("c3", "spmv_fp64"): 28.73e9, ("c3", "spmv_fp32"): 14.67e9, ("c3", "thomas_p_fp64"): 22.02e9,
+                    ("c3", "thomas_s_fp64"): 19.27e9, ("c3", "update_fp64"): 22.02e9}
+
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
@@ -52,7 +63,7 @@ def generate_on_device(p, torch):
     return coef, b
 
 
-def cpu_baseline(n_target: int, iterations: int, sample_iters: int = 6):
+def cpu_baseline(n_target: int, iterations: int, sample_iters: int = 20):
     """Single-thread oracle BiCGStab on a 640x480x70 grid of the same recipe for a fixed number
     of iterations; scaled per point and iteration to the benchmark grid."""
     import numpy as np
@@ -81,6 +92,74 @@ def cpu_baseline(n_target: int, iterations: int, sample_iters: int = 6):
     }
 
 
+def train_network(eg, torch, shape, nops, nvec, epochs, seed=1):
+    """Harvest FGMRES bases from `nops` operators of the recipe at `shape` and train a network."""
+    import numpy as np
+
+    import synth
+    t0 = time.perf_counter()
+    ops, rs, owner = [], [], []
+    for s in range(nops):
+        p = synth.Problem(*shape, seed=1000 + s)
+        op = eg.Operator(torch.from_numpy(synth.make_coeffs(p, threads=16)).cuda())
+        r, _ = op.harvest_krylov(torch.from_numpy(synth.make_rhs(p, seed=2000 + s).ravel()).cuda(), nvec,
+                                 errors=False)
+        ops.append(op)
+        rs.append(r)
+        owner += [s] * r.shape[0]
+    r = torch.cat(rs).contiguous()
+    del rs
+    torch.cuda.synchronize()
+    t_harvest = time.perf_counter() - t0
+    net = eg.Net(11)
+    loss0 = net.eval(ops, r, r, owner)
+    t0 = time.perf_counter()
+    hist = net.train(ops, r, r, owner, epochs=epochs, batch=16, lr=2e-3, seed=seed)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    for op in ops:
+        op.close()
+    info = {"shape": list(shape), "operators": nops, "vectors_per_operator": nvec, "pairs": int(r.shape[0]),
+            "epochs": epochs, "loss": "||A M(r) - r||^2 / ||r||^2", "loss_untrained": round(loss0, 4),
+            "loss_last_epoch": round(float(hist[-1]), 4), "harvest_seconds": round(t_harvest, 2),
+            "train_seconds": round(t_train, 2)}
+    del r
+    torch.cuda.empty_cache()
+    return net, info
+
+
+def learned_comparison(eg, torch, net, cfg_name, tol):
+    """FGMRES(30) with T^-1 vs with the learned M (both FP32 inner + FP64 refinement), and
+    BiCGStab, on one workload; one warm-up solve each, then one timed solve."""
+    import synth
+    p = synth.CONFIGS[cfg_name]
+    coef, b = generate_on_device(p, torch)
+    op = eg.Operator(coef)
+    del coef
+    torch.cuda.empty_cache()
+    op.attach(net)
+    out = {"workload": f"{cfg_name}: {p.nlon}x{p.nlat}x{p.nlev}, b ~ N(0,1), tol {tol}"}
+    x = torch.zeros(p.n, dtype=torch.float64, device="cuda")
+    for name, mode, method in (("fgmres_tri_fp32_ir", eg.FP32_IR, 1), ("fgmres_learned_fp32_ir", eg.LEARNED_FP32_IR, 1),
+                               ("bicgstab_tri_fp32_ir", eg.FP32_IR, 0), ("fgmres_tri_fp64", eg.FP64, 1),
+                               ("fgmres_learned_fp64", eg.LEARNED_FP64, 1)):
+        op.set_option("method", method)
+        op.set_option("learned_method", method)
+        x.zero_()
+        op.solve(b, x, tol, 20000, mode)
+        x.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        info = op.solve(b, x, tol, 20000, mode)
+        torch.cuda.synchronize()
+        out[name] = {"seconds": round(time.perf_counter() - t0, 4), "iterations": info.iterations,
+                     "outer_steps": info.outer_steps, "fallbacks": info.fallbacks, "status": info.status,
+                     "true_rel_residual": info.true_rel_residual}
+        log(f"learned comparison {name}: {out[name]}")
+    op.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -90,6 +169,13 @@ def main():
     ap.add_argument("--modes", default="fp64,fp32_ir,fp32_ir_bf16")
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--learned-config", default="c4", help="workload of the learned-preconditioner comparison ('' skips it)")
+    ap.add_argument("--train-shape", default="160x120x70")
+    ap.add_argument("--train-ops", type=int, default=16)
+    ap.add_argument("--train-vecs", type=int, default=20)
+    ap.add_argument("--train-epochs", type=int, default=20)
+    ap.add_argument("--traffic-probe", action="store_true",
+                    help="run four iterations of each mode and a device copy of known size (for counter runs) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU decomposition "
@@ -104,8 +190,41 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     p = synth.CONFIGS[args.config]
+    if args.traffic_probe:
+        coef, b = generate_on_device(p, torch)
+        op = eg.Operator(coef)
+        del coef
+        x = torch.zeros(p.n, dtype=torch.float64, device="cuda")
+        for m in (eg.FP64, eg.FP32_IR, eg.FP32_IR_BF16):
+            x.zero_()
+            op.solve(b, x, args.tol, 4, m)
+        for _ in range(3):
+            x.copy_(b)
+        torch.cuda.synchronize()
+        op.close()
+        del x, b
+        torch.cuda.empty_cache()
+        # three network applications on the learned preconditioner's workload
+        p4 = synth.CONFIGS[args.learned_config or "c4"]
+        coef, _ = generate_on_device(p4, torch)
+        op = eg.Operator(coef)
+        del coef
+        net = eg.Net(11)
+        q = torch.randn(p4.n, dtype=torch.float32, device="cuda", generator=torch.Generator("cuda").manual_seed(5))
+        for _ in range(3):
+            net.apply(op, q)
+        torch.cuda.synchronize()
+        print(json.dumps({"traffic_probe": args.config, "copy_bytes_read": p.n * 8, "copy_bytes_written": p.n * 8,
+                          "net_workload": args.learned_config or "c4"}))
+        return
     name2mode = {v: k for k, v in eg.MODE_NAMES.items()}
     modes = [name2mode[m] for m in args.modes.split(",") if m]
+
+    net, training = None, None
+    if args.learned_config or any(m in (eg.LEARNED_FP64, eg.LEARNED_FP32_IR) for m in modes):
+        shape = tuple(int(v) for v in args.train_shape.split("x"))
+        net, training = train_network(eg, torch, shape, args.train_ops, args.train_vecs, args.train_epochs)
+        log(f"trained the network: {training}")
 
     t0 = time.perf_counter()
     coef, b = generate_on_device(p, torch)
@@ -134,6 +253,8 @@ def main():
             t_setup_low[PREC_NAME[prec]] = time.perf_counter() - t0
     del scratch, out
 
+    if net is not None:
+        op.attach(net)
     x = torch.zeros(p.n, dtype=torch.float64, device="cuda")
     for _ in range(args.warmup):
         for m in modes:
@@ -181,8 +302,10 @@ def main():
                 "gbs": round(bytes_launch / (avg_ms * 1e-3) / 1e9, 1)}
     dom_name = max(kernels, key=lambda k: kernels[k]["total_ms"])
     dom = kernels[dom_name]
+    traffic = MEASURED_TRAFFIC.get((args.config, dom_name))
     roofline = {"bound": "hbm", "kernel": dom_name, "achieved": dom["gbs"], "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": round(dom["gbs"] / PEAK_HBM_GBS, 4), "traffic": None,
+                "frac": round(dom["gbs"] / PEAK_HBM_GBS, 4), "traffic": traffic,
+                "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                 "bytes_per_launch": dom["bytes_per_launch"], "avg_ms": dom["avg_ms"]}
 
     modes_out = {}
@@ -191,6 +314,14 @@ def main():
                         "outer_steps": d["outer_steps"], "status": d["status"],
                         "true_rel_residual": d["true_rel_residual"]}
     fp64_iters = per_mode.get("fp64", {}).get("iterations")
+    op.close()
+    del x, b
+    torch.cuda.empty_cache()
+
+    learned = None
+    if args.learned_config:
+        learned = learned_comparison(eg, torch, net, args.learned_config, args.tol)
+        learned["training"] = training
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -198,7 +329,8 @@ def main():
         cpu = cpu_baseline(p.n, fp64_iters or 1)
 
     dtypes = sorted({{eg.FP64: "f64", eg.FP32_IR: "f64+f32", eg.FP32_IR_BF16: "f64+f32+bf16",
-                      eg.FP32_IR_FP16: "f64+f32+f16"}[m] for m in modes})
+                      eg.FP32_IR_FP16: "f64+f32+f16", eg.LEARNED_FP64: "f64+bf16mfma",
+                      eg.LEARNED_FP32_IR: "f64+f32+bf16mfma"}[m] for m in modes})
     result = {
         "metric": "time-to-solve at ||r||/||b||<=1e-8, FP64 vs mixed vs learned-PC; HBM GB/s",
         "value": round(ms_per_step / 1000.0, 4),
@@ -221,9 +353,9 @@ def main():
         "roofline": roofline,
         "kernels": kernels,
         "cpu_baseline": cpu,
+        "learned": learned,
     }
     print(json.dumps(result), flush=True)
-    op.close()
 
 
 if __name__ == "__main__":

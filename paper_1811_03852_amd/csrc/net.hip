@@ -36,6 +36,14 @@ __device__ __forceinline__ bf16x8 ld8(const uint16_t *row)
 
 __device__ __forceinline__ bf16x8 zero8() { return __builtin_bit_cast(bf16x8, make_uint4(0, 0, 0, 0)); }
 
+// v if keep, else zero, without a branch (loads stay unconditional, so the compiler can count
+// them and wait only for the ones a multiply needs)
+__device__ __forceinline__ bf16x8 keep8(bf16x8 v, bool keep)
+{
+    const uint4 u = __builtin_bit_cast(uint4, v);
+    return __builtin_bit_cast(bf16x8, make_uint4(keep ? u.x : 0u, keep ? u.y : 0u, keep ? u.z : 0u, keep ? u.w : 0u));
+}
+
 __device__ __forceinline__ f32x4 mfma(bf16x8 a, bf16x8 b, f32x4 c)
 {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
@@ -125,65 +133,196 @@ __global__ __launch_bounds__(256) void k_net_features(NetGeo g, const Tv *__rest
 }
 
 // ------------------------------------------------------------------------------------------
+// Column-marching forward layers.  A wave owns a tile of positions of the level plane (16 for
+// the MFMA layers, 64 for the output layer) and walks a chunk of levels upwards, so every
+// activation row is read from HBM once per layer: the vertical taps come from a rolling
+// register window, the horizontal neighbours of the 3x3 layer from rows the waves of the
+// neighbouring tiles read at the same time, and the neighbour offsets in the plane are
+// computed once per wave.  Work units (tile, level chunk) are numbered tile-fastest and
+// mapped XCD-aware like the SpMV tiles.
+// ------------------------------------------------------------------------------------------
+struct ColGrid {
+    int tiles, kchunk, per_xcd, blocks;
+    long units;
+};
+
+static ColGrid col_grid(const NetGeo &g, int tile_pos)
+{
+    ColGrid c;
+    c.tiles = (int)((g.P + tile_pos - 1) / tile_pos);
+    int chunks = 1;
+    while ((long)c.tiles * chunks < 8192 && chunks < g.nlev) chunks *= 2;
+    if (chunks > g.nlev) chunks = g.nlev;
+    c.kchunk = (g.nlev + chunks - 1) / chunks;
+    const int nchunks = (g.nlev + c.kchunk - 1) / c.kchunk;
+    c.units = (long)c.tiles * nchunks;
+    const long wgs = (c.units + 3) / 4;
+    c.per_xcd = (int)((wgs + 7) / 8);
+    c.blocks = c.per_xcd * 8;
+    return c;
+}
+
+__device__ __forceinline__ long col_unit(int per_xcd)
+{
+    const int b = blockIdx.x;
+    return ((long)(b & 7) * per_xcd + (b >> 3)) * 4 + (threadIdx.x >> 6);
+}
+
+// four consecutive output channels of one position: bias, ReLU, BF16, one 8-byte store
+__device__ __forceinline__ void store4(uint16_t *dst, f32x4 acc, const float *b)
+{
+    uint2 v;
+    v.x = static_cast<uint32_t>(f2bf(fmaxf(acc[0] + b[0], 0.f))) |
+          (static_cast<uint32_t>(f2bf(fmaxf(acc[1] + b[1], 0.f))) << 16);
+    v.y = static_cast<uint32_t>(f2bf(fmaxf(acc[2] + b[2], 0.f))) |
+          (static_cast<uint32_t>(f2bf(fmaxf(acc[3] + b[3], 0.f))) << 16);
+    *reinterpret_cast<uint2 *>(dst) = v;
+}
+
+// ------------------------------------------------------------------------------------------
 // conv layer, forward:  out[p][co] = ReLU(bias[co] + sum_{t, ci} W[t][co][ci] in[nb(p, t)][ci])
-// One wave per tile of 16 positions (waves stride over tiles); the layer's weights stay in
-// registers for the whole launch.
+// The MFMA computes D[co][position] = W[co][K] In[position][K]^T (K = input channels, or
+// (tap, channel) for layer 1): lane l ends with output channels 16 nt + 4 (l / 16) .. + 3 of
+// position l % 16.  The layer's weights stay in registers for the whole launch.
 // ------------------------------------------------------------------------------------------
 template <int L>
 __global__ __launch_bounds__(256) void k_conv_fwd(NetGeo g, const uint16_t *__restrict__ in,
                                                   const uint16_t *__restrict__ wf, const float *__restrict__ bias,
                                                   uint16_t *__restrict__ out, const Scalars *__restrict__ sc,
-                                                  int stop_mask)
+                                                  int stop_mask, int tiles, int kchunk, long units, int per_xcd)
 {
     if (stop_now(sc, stop_mask)) return;
     constexpr int T = LayerGeo<L>::T;
     constexpr int NCH = (L == 1) ? 1 : T;   // K chunks of 32
     const int lane = threadIdx.x & 63, m = lane & 15, grp = lane >> 4;
-    bf16x8 wb[NCH][2];
-#pragma unroll
-    for (int c = 0; c < NCH; ++c)
-#pragma unroll
-        for (int nt = 0; nt < 2; ++nt) wb[c][nt] = ld8(wf + (long)c * 1024 + (16 * nt + m) * 32 + 8 * grp);
-    const float bias0 = bias[m], bias1 = bias[16 + m];
-    const long ntiles = (g.n + 15) / 16;
-    const long nw = (long)gridDim.x * 4;
-    for (long tile = (long)blockIdx.x * 4 + (threadIdx.x >> 6); tile < ntiles; tile += nw) {
-        const long p = tile * 16 + m;
-        const bool pv = p < g.n;
-        const long pc = pv ? p : g.n - 1;
-        const Pos x = decompose(g, pc);
-        f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
-        if constexpr (L == 1) {
-            // K = (tap, channel): lane group grp holds taps 2 grp and 2 grp + 1 (4 channels each)
-            uint2 h[2];
-#pragma unroll
-            for (int hh = 0; hh < 2; ++hh) {
-                const int t = 2 * grp + hh;
-                h[hh] = make_uint2(0, 0);
-                if (t < 5) {
-                    const long q = nb_v(g, pc, x, t - 2);
-                    if (pv && q >= 0) h[hh] = reinterpret_cast<const uint2 *>(in)[q];
-                }
-            }
-            const bf16x8 a = __builtin_bit_cast(bf16x8, make_uint4(h[0].x, h[0].y, h[1].x, h[1].y));
-            acc0 = mfma(a, wb[0][0], acc0);
-            acc1 = mfma(a, wb[0][1], acc1);
-        } else {
-#pragma unroll
-            for (int t = 0; t < T; ++t) {
-                const long q = LayerGeo<L>::nb(g, pc, x, t, false);
-                const bf16x8 a = (pv && q >= 0) ? ld8(in + q * 32 + 8 * grp) : zero8();
-                acc0 = mfma(a, wb[t][0], acc0);
-                acc1 = mfma(a, wb[t][1], acc1);
-            }
+    // the 3x3 layer keeps its weights (18 KB) in LDS, in each lane's operand order, to leave
+    // registers for the next level's loads; the vertical layers keep theirs in registers
+    constexpr int NW = (L == 2) ? 18 * 64 : 1;
+    __shared__ uint4 wsh[NW];
+    if constexpr (L == 2) {
+        for (int e = threadIdx.x; e < 18 * 64; e += 256) {
+            const int tn = e / 64, l = e % 64;   // tn = 2 t + nt
+            wsh[e] = *reinterpret_cast<const uint4 *>(wf + (long)(tn / 2) * 1024 + (16 * (tn % 2) + (l & 15)) * 32 +
+                                                      8 * (l >> 4));
         }
+        __syncthreads();
+    }
+    const long unit = col_unit(per_xcd);
+    if (unit >= units) return;
+    bf16x8 wa[(L == 2) ? 1 : NCH][2];
+    if constexpr (L != 2) {
 #pragma unroll
-        for (int jj = 0; jj < 4; ++jj) {
-            const long q = tile * 16 + 4 * grp + jj;
-            if (q < g.n) {
-                out[q * 32 + m] = f2bf(fmaxf(acc0[jj] + bias0, 0.f));
-                out[q * 32 + 16 + m] = f2bf(fmaxf(acc1[jj] + bias1, 0.f));
+        for (int c = 0; c < NCH; ++c)
+#pragma unroll
+            for (int nt = 0; nt < 2; ++nt) wa[c][nt] = ld8(wf + (long)c * 1024 + (16 * nt + m) * 32 + 8 * grp);
+    }
+    float bs[2][4];
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) bs[nt][jj] = bias[16 * nt + 4 * grp + jj];
+    const int tile = (int)(unit % tiles);
+    const int k0 = (int)(unit / tiles) * kchunk;
+    const int k1 = min(g.nlev, k0 + kchunk);
+    const long p2 = (long)tile * 16 + m;
+    const bool pv = p2 < g.P;
+    const long p2s = pv ? p2 : g.P - 1;   // an in-bounds address for the lanes past the plane
+    auto emit = [&](int k, f32x4 acc0, f32x4 acc1) {
+        if (!pv) return;
+        uint16_t *dst = out + ((long)k * g.P + p2) * 32 + 4 * grp;
+        store4(dst, acc0, bs[0]);
+        store4(dst + 16, acc1, bs[1]);
+    };
+    if constexpr (L == 2) {
+        // the nine horizontal neighbours in the level plane (periodic in longitude, none
+        // across a pole), as offsets from p2; bit t of ok marks a neighbour that exists
+        const int i = (int)(p2s % g.nlon), j = (int)(p2s / g.nlon);
+        int off[9];
+        int ok = 0;
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
+            const int di = t % 3 - 1, dj = t / 3 - 1;
+            int i2 = i + di;
+            if (i2 < 0) i2 += g.nlon;
+            else if (i2 >= g.nlon) i2 -= g.nlon;
+            const bool in_plane = j + dj >= 0 && j + dj < g.nlat;
+            off[t] = in_plane ? (i2 - i) + dj * g.nlon : 0;   // missing neighbours read p2 itself, masked below
+            if (pv && in_plane) ok |= 1 << t;
+        }
+        // the next level's nine operands are loaded while the current level is multiplied
+        auto load9 = [&](int k, bf16x8 *a) {
+            const uint16_t *base = in + ((long)k * g.P + p2s) * 32 + 8 * grp;
+#pragma unroll
+            for (int t = 0; t < 9; ++t) a[t] = ld8(base + (long)off[t] * 32);
+        };
+        bf16x8 cur[9], nxt[9];
+        load9(k0, cur);
+        for (int k = k0; k < k1; ++k) {
+            // weights are re-read from LDS every level rather than held in 72 registers
+            asm volatile("" ::: "memory");
+            load9(min(k + 1, k1 - 1), nxt);   // the last level re-reads itself (in bounds, unused)
+#pragma unroll
+            for (int t = 0; t < 9; ++t) cur[t] = keep8(cur[t], (ok >> t) & 1);
+            f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int t = 0; t < 9; ++t) {
+                acc0 = mfma(__builtin_bit_cast(bf16x8, wsh[(2 * t) * 64 + lane]), cur[t], acc0);
+                acc1 = mfma(__builtin_bit_cast(bf16x8, wsh[(2 * t + 1) * 64 + lane]), cur[t], acc1);
             }
+            emit(k, acc0, acc1);
+#pragma unroll
+            for (int t = 0; t < 9; ++t) cur[t] = nxt[t];
+        }
+    } else if constexpr (L == 3) {
+        auto row = [&](int kk) -> bf16x8 {
+            const int kc = min(max(kk, 0), g.nlev - 1);
+            return keep8(ld8(in + ((long)kc * g.P + p2s) * 32 + 8 * grp), pv && kk >= 0 && kk < g.nlev);
+        };
+        bf16x8 w0 = row(k0 - 2), w1 = row(k0 - 1), w2 = row(k0), w3 = row(k0 + 1), w4 = row(k0 + 2);
+        for (int k = k0; k < k1; ++k) {
+            const bf16x8 nx = row(k + 3);   // one level ahead
+            f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+            acc0 = mfma(wa[0][0], w0, acc0);
+            acc1 = mfma(wa[0][1], w0, acc1);
+            acc0 = mfma(wa[1][0], w1, acc0);
+            acc1 = mfma(wa[1][1], w1, acc1);
+            acc0 = mfma(wa[2][0], w2, acc0);
+            acc1 = mfma(wa[2][1], w2, acc1);
+            acc0 = mfma(wa[3][0], w3, acc0);
+            acc1 = mfma(wa[3][1], w3, acc1);
+            acc0 = mfma(wa[4][0], w4, acc0);
+            acc1 = mfma(wa[4][1], w4, acc1);
+            emit(k, acc0, acc1);
+            w0 = w1;
+            w1 = w2;
+            w2 = w3;
+            w3 = w4;
+            w4 = nx;
+        }
+    } else {
+        // layer 1: K = (tap, channel); lane group grp holds taps 2 grp and 2 grp + 1
+        auto row = [&](int kk) -> uint2 {
+            const int kc = min(max(kk, 0), g.nlev - 1);
+            const uint2 v = reinterpret_cast<const uint2 *>(in)[(long)kc * g.P + p2s];
+            const bool keep = pv && kk >= 0 && kk < g.nlev;
+            return make_uint2(keep ? v.x : 0u, keep ? v.y : 0u);
+        };
+        uint2 x0 = row(k0 - 2), x1 = row(k0 - 1), x2 = row(k0), x3 = row(k0 + 1), x4 = row(k0 + 2);
+        const uint2 zz = make_uint2(0, 0);
+        for (int k = k0; k < k1; ++k) {
+            const uint2 nx = row(k + 3);
+            const uint2 lo = grp == 0 ? x0 : (grp == 1 ? x2 : (grp == 2 ? x4 : zz));
+            const uint2 hi = grp == 0 ? x1 : (grp == 1 ? x3 : zz);
+            const bf16x8 a = __builtin_bit_cast(bf16x8, make_uint4(lo.x, lo.y, hi.x, hi.y));
+            f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+            acc0 = mfma(wa[0][0], a, acc0);
+            acc1 = mfma(wa[0][1], a, acc1);
+            emit(k, acc0, acc1);
+            x0 = x1;
+            x1 = x2;
+            x2 = x3;
+            x3 = x4;
+            x4 = nx;
         }
     }
 }
@@ -337,29 +476,38 @@ __global__ __launch_bounds__(256) void k_conv_dw(NetGeo g, const uint16_t *__res
 
 // ------------------------------------------------------------------------------------------
 // output layer (32 -> 1, 5 vertical taps) fused with  q' = q + rho * delta
+// One lane per position of the level plane, marching up a chunk of levels: each input row
+// a3[kk] is read once and its five tap sums s_t = sum_c W4[t][c] a3[kk][c] are added to the
+// pending outputs of levels kk + 2 - t; level kk - 2 is complete after input kk.
 // ------------------------------------------------------------------------------------------
 template <typename Tv>
 __global__ __launch_bounds__(256) void k_net_out(NetGeo g, const uint16_t *__restrict__ a3,
                                                  const float *__restrict__ w4, const float *__restrict__ theta,
                                                  const Tv *__restrict__ q, Tv *__restrict__ qout,
                                                  float *__restrict__ delta, const Scalars *__restrict__ sc,
-                                                 int stop_mask)
+                                                 int stop_mask, int tiles, int kchunk, long units, int per_xcd)
 {
     if (stop_now(sc, stop_mask)) return;
     __shared__ float w[160];
     if (threadIdx.x < 160) w[threadIdx.x] = w4[threadIdx.x];
     __syncthreads();
+    const long unit = col_unit(per_xcd);
+    if (unit >= units) return;
     const float b4 = theta[kNetOffB4];
     const double rho = sqrt(sc->net_q2 / (double)g.n);
-    const long stride = (long)gridDim.x * 256;
-    for (long p = (long)blockIdx.x * 256 + threadIdx.x; p < g.n; p += stride) {
-        const Pos x = decompose(g, p);
-        float d = b4;
-#pragma unroll
-        for (int t = 0; t < 5; ++t) {
-            const long nb = nb_v(g, p, x, t - 2);
-            if (nb < 0) continue;
-            const uint4 *row = reinterpret_cast<const uint4 *>(a3 + nb * 32);
+    const int tile = (int)(unit % tiles);
+    const int k0 = (int)(unit / tiles) * kchunk;
+    const int k1 = min(g.nlev, k0 + kchunk);
+    const long p2 = (long)tile * 64 + (threadIdx.x & 63);
+    if (p2 >= g.P) return;
+    // r[d] accumulates the output of level kk - 2 + d
+    float r[5] = {b4, b4, b4, b4, b4};
+    for (int kk = k0 - 2; kk < k1 + 2; ++kk) {
+        // keeps the weights in LDS (read as broadcasts every level) instead of 160 registers
+        asm volatile("" ::: "memory");
+        if (kk >= 0 && kk < g.nlev) {
+            const uint4 *row = reinterpret_cast<const uint4 *>(a3 + ((long)kk * g.P + p2) * 32);
+            float s[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const uint4 u = row[v];
@@ -367,13 +515,25 @@ __global__ __launch_bounds__(256) void k_net_out(NetGeo g, const uint16_t *__res
 #pragma unroll
                 for (int h = 0; h < 4; ++h) {
                     const int c = 8 * v + 2 * h;
-                    d += w[t * 32 + c] * __uint_as_float(wd[h] << 16);
-                    d += w[t * 32 + c + 1] * __uint_as_float(wd[h] & 0xffff0000u);
+                    const float lo = __uint_as_float(wd[h] << 16), hi = __uint_as_float(wd[h] & 0xffff0000u);
+#pragma unroll
+                    for (int t = 0; t < 5; ++t) s[t] += w[t * 32 + c] * lo + w[t * 32 + c + 1] * hi;
                 }
             }
+#pragma unroll
+            for (int d = 0; d < 5; ++d) r[d] += s[4 - d];
         }
-        if (delta) delta[p] = d;
-        qout[p] = static_cast<Tv>(static_cast<double>(q[p]) + rho * static_cast<double>(d));
+        const int k = kk - 2;
+        if (k >= k0 && k < k1) {
+            const long p = (long)k * g.P + p2;
+            if (delta) delta[p] = r[0];
+            qout[p] = static_cast<Tv>(static_cast<double>(q[p]) + rho * static_cast<double>(r[0]));
+        }
+        r[0] = r[1];
+        r[1] = r[2];
+        r[2] = r[3];
+        r[3] = r[4];
+        r[4] = b4;
     }
 }
 
@@ -606,21 +766,22 @@ void launch_net_features(const NetGeo &g, const Tv *q, const Tv *z0, const Tc *a
 void launch_net_forward_layers(const NetGeo &g, const NetDev &d, const NetActs &act, const Scalars *sc, int stop_mask,
                                hipStream_t s)
 {
-    const int nb = net_blocks((g.n + 15) / 16, 4 * 8, 4096);
-    hipLaunchKernelGGL((k_conv_fwd<1>), dim3(nb), dim3(256), 0, s, g, act.x0, d.w1f, d.theta + kNetOffB1, act.a1, sc,
-                       stop_mask);
-    hipLaunchKernelGGL((k_conv_fwd<2>), dim3(nb), dim3(256), 0, s, g, act.a1, d.w2f, d.theta + kNetOffB2, act.a2, sc,
-                       stop_mask);
-    hipLaunchKernelGGL((k_conv_fwd<3>), dim3(nb), dim3(256), 0, s, g, act.a2, d.w3f, d.theta + kNetOffB3, act.a3, sc,
-                       stop_mask);
+    const ColGrid c = col_grid(g, 16);
+    hipLaunchKernelGGL((k_conv_fwd<1>), dim3(c.blocks), dim3(256), 0, s, g, act.x0, d.w1f, d.theta + kNetOffB1, act.a1,
+                       sc, stop_mask, c.tiles, c.kchunk, c.units, c.per_xcd);
+    hipLaunchKernelGGL((k_conv_fwd<2>), dim3(c.blocks), dim3(256), 0, s, g, act.a1, d.w2f, d.theta + kNetOffB2, act.a2,
+                       sc, stop_mask, c.tiles, c.kchunk, c.units, c.per_xcd);
+    hipLaunchKernelGGL((k_conv_fwd<3>), dim3(c.blocks), dim3(256), 0, s, g, act.a2, d.w3f, d.theta + kNetOffB3, act.a3,
+                       sc, stop_mask, c.tiles, c.kchunk, c.units, c.per_xcd);
 }
 
 template <typename Tv>
 void launch_net_out(const NetGeo &g, const NetDev &d, const NetActs &act, const Tv *q, Tv *qout, float *delta,
                     const Scalars *sc, int stop_mask, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_net_out<Tv>), dim3(net_blocks(g.n, 1024, 8192)), dim3(256), 0, s, g, act.a3, d.w4, d.theta,
-                       q, qout, delta, sc, stop_mask);
+    const ColGrid c = col_grid(g, 64);
+    hipLaunchKernelGGL((k_net_out<Tv>), dim3(c.blocks), dim3(256), 0, s, g, act.a3, d.w4, d.theta, q, qout, delta, sc,
+                       stop_mask, c.tiles, c.kchunk, c.units, c.per_xcd);
 }
 
 void launch_thomas_t(const TriView<float> &tv, const float *y, float *z, hipStream_t s)
