@@ -186,7 +186,8 @@ void launch_spmv_t(const NetGeo &g, const float *a, const float *m, const float 
 void launch_net_gseed(long n, const float *m, const float *e, float *g, const Scalars *sc, hipStream_t s);
 void launch_net_diff(long n, const float *m, const float *e, float *out, hipStream_t s);
 void launch_net_backward(const NetGeo &g, const NetDev &d, const NetActs &act, const float *u, const Scalars *sc,
-                         float scale, int accumulate, hipStream_t s);
+                         int first, hipStream_t s);
+void launch_net_grad(const NetDev &d, float scale, hipStream_t s);
 void launch_net_refresh(const NetDev &d, hipStream_t s);
 void launch_net_adam(const NetDev &d, float lr, int step, hipStream_t s);
 

@@ -829,7 +829,9 @@ __global__ __launch_bounds__(kWG) void k_vscale(long n, const Tv *__restrict__ x
 template <typename Tv>
 int launch_mdot(long n, const Tv *w, const Tv *V, int i0, int nb, double *part, double *out, hipStream_t s)
 {
-    const int rows = elementwise_blocks(n);
+    // at most 2048 partial rows (8 workgroups per CU): enough to stream at full rate, few
+    // enough for the single-workgroup column sums that follow
+    const int rows = std::min(elementwise_blocks(n), 2048);
     hipLaunchKernelGGL((k_mdot<Tv>), dim3(rows), dim3(kWG), 0, s, n, w, V, i0, nb, part);
     hipLaunchKernelGGL(k_msum, dim3(1), dim3(kWG), 0, s, part, rows, nb, out + i0);
     return rows;

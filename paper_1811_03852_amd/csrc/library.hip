@@ -839,11 +839,11 @@ double std_normal(uint64_t &s)   // Box-Muller
     return std::sqrt(-2.0 * std::log(u1)) * std::cos(6.283185307179586 * u2);
 }
 
-// One training pair on the first operator's stream: forward, loss ||M(r) - e||^2 / ||e||^2
-// into *loss_slot (device), and (if backward) the parameter gradient scaled by `scale` into
-// net->d.grad (added to it when accumulate is set).
-int net_pair_pass(eg_net *net, eg_operator *op, const float *r, const float *e, bool backward, float scale,
-                  int accumulate, double *loss_slot, hipStream_t s)
+// One training pair on the given stream: forward, the loss into *loss_slot (device), and (if
+// backward) this pair's per-row partial weight gradients, written into net->d.part for the
+// first pair of a batch and added for the others (launch_net_grad sums them into d.grad).
+int net_pair_pass(eg_net *net, eg_operator *op, const float *r, const float *e, bool backward, int first,
+                  double *loss_slot, hipStream_t s)
 {
     int rc;
     if ((rc = ensure_fp32(op)) || (rc = ensure_acts(net, op->n, backward)) || (rc = ensure_train_tmp(net, op->n)))
@@ -872,7 +872,7 @@ int net_pair_pass(eg_net *net, eg_operator *op, const float *r, const float *e, 
             launch_net_gseed(n, net->t_g, r, net->t_g, op->sc, s);
             launch_spmv_t(g, op->a32, op->m32, net->t_g, net->t_z0, s);
             launch_thomas_t(T, net->t_z0, net->t_u, s);
-            launch_net_backward(g, net->d, net->act, net->t_u, op->sc, scale, accumulate, s);
+            launch_net_backward(g, net->d, net->act, net->t_u, op->sc, first, s);
         }
     } else {
         // error space: loss ||m - e||^2 / ||e||^2, dL/dm = 2 (m - e) / ||e||^2
@@ -882,7 +882,7 @@ int net_pair_pass(eg_net *net, eg_operator *op, const float *r, const float *e, 
         if (backward) {
             launch_net_gseed(n, net->t_m, e, net->t_g, op->sc, s);
             launch_thomas_t(T, net->t_g, net->t_u, s);
-            launch_net_backward(g, net->d, net->act, net->t_u, op->sc, scale, accumulate, s);
+            launch_net_backward(g, net->d, net->act, net->t_u, op->sc, first, s);
         }
     }
     EG_HIP(hipGetLastError());
@@ -1323,7 +1323,9 @@ int eg_net_loss_grad(eg_operator *op, eg_net *net, const float *r, const float *
     if (!op || !net || !r || !e) return fail(EG_EINVAL, "NULL argument");
     int rc;
     if ((rc = ensure_loss(net, 1))) return rc;
-    if ((rc = net_pair_pass(net, op, r, e, true, 1.f, 0, net->d_loss, op->stream))) return rc;
+    if ((rc = net_pair_pass(net, op, r, e, true, 1, net->d_loss, op->stream))) return rc;
+    launch_net_grad(net->d, 1.f, op->stream);
+    EG_HIP(hipGetLastError());
     EG_HIP(hipStreamSynchronize(op->stream));
     if (loss_host) EG_HIP(hipMemcpy(loss_host, net->d_loss, sizeof(double), hipMemcpyDeviceToHost));
     if (grad_host) EG_HIP(hipMemcpy(grad_host, net->d.grad, kNetParams * sizeof(float), hipMemcpyDeviceToHost));
@@ -1431,10 +1433,11 @@ int eg_net_train(eg_net *net, eg_operator *const *ops, int nops, const float *r,
             const float scale = 1.f / (float)(b1 - b0);
             for (int k = b0; k < b1; ++k) {
                 const int pi = order[k];
-                if ((rc = net_pair_pass(net, ops[pair_op[pi]], r + (size_t)pi * n, e + (size_t)pi * n, true, scale,
-                                        k > b0, net->d_loss + k, s)))
+                if ((rc = net_pair_pass(net, ops[pair_op[pi]], r + (size_t)pi * n, e + (size_t)pi * n, true, k == b0,
+                                        net->d_loss + k, s)))
                     return rc;
             }
+            launch_net_grad(net->d, scale, s);
             net->step += 1;
             launch_net_adam(net->d, (float)lr, net->step, s);
             EG_HIP(hipGetLastError());
@@ -1457,7 +1460,7 @@ int eg_net_eval(eg_net *net, eg_operator *const *ops, int nops, const float *r, 
     hipStream_t s = ops[0]->stream;
     const size_t n = (size_t)ops[0]->n;
     for (int i = 0; i < npairs; ++i)
-        if ((rc = net_pair_pass(net, ops[pair_op[i]], r + i * n, e + i * n, false, 1.f, 0, net->d_loss + i, s)))
+        if ((rc = net_pair_pass(net, ops[pair_op[i]], r + i * n, e + i * n, false, 1, net->d_loss + i, s)))
             return rc;
     std::vector<double> losses(npairs);
     EG_HIP(hipMemcpyAsync(losses.data(), net->d_loss, npairs * sizeof(double), hipMemcpyDeviceToHost, s));

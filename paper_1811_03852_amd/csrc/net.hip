@@ -378,7 +378,7 @@ __global__ __launch_bounds__(256) void k_conv_bwd(NetGeo g, const uint16_t *__re
 // ------------------------------------------------------------------------------------------
 template <int L>
 __global__ __launch_bounds__(256) void k_conv_dw(NetGeo g, const uint16_t *__restrict__ dout,
-                                                 const uint16_t *__restrict__ in, float *__restrict__ part)
+                                                 const uint16_t *__restrict__ in, float *__restrict__ part, int add)
 {
     constexpr int T = LayerGeo<L>::T;
     constexpr int NG = (L == 1) ? 1 : T;
@@ -455,10 +455,14 @@ __global__ __launch_bounds__(256) void k_conv_dw(NetGeo g, const uint16_t *__res
                     const int co = 16 * mt + 4 * grp + jj;
                     const int nn = 16 * nt + m;
                     if constexpr (L == 1) {
-                        if (nn < 20) dst[kNetOffW1 + (nn / 4) * 128 + co * 4 + (nn & 3)] = acc[G][mt][nt][jj];
+                        if (nn < 20) {
+                            float &o = dst[kNetOffW1 + (nn / 4) * 128 + co * 4 + (nn & 3)];
+                            o = add ? o + acc[G][mt][nt][jj] : acc[G][mt][nt][jj];
+                        }
                     } else {
                         const int off = (L == 2) ? kNetOffW2 : kNetOffW3;
-                        dst[off + G * 1024 + co * 32 + nn] = acc[G][mt][nt][jj];
+                        float &o = dst[off + G * 1024 + co * 32 + nn];
+                        o = add ? o + acc[G][mt][nt][jj] : acc[G][mt][nt][jj];
                     }
                 }
     // bias: sum over the four lane groups holding the same output channel
@@ -469,7 +473,8 @@ __global__ __launch_bounds__(256) void k_conv_dw(NetGeo g, const uint16_t *__res
         s += __shfl_xor(s, 32);
         if (grp == 0) {
             const int off = (L == 1) ? kNetOffB1 : ((L == 2) ? kNetOffB2 : kNetOffB3);
-            dst[off + 16 * mt + m] = s;
+            float &o = dst[off + 16 * mt + m];
+            o = add ? o + s : s;
         }
     }
 }
@@ -585,7 +590,7 @@ __global__ __launch_bounds__(256) void k_net_out_bwd(NetGeo g, const float *__re
 // Workgroup = 32 channels x 8 position streams; one partial row per workgroup.
 __global__ __launch_bounds__(256) void k_net_out_dw(NetGeo g, const float *__restrict__ u,
                                                     const uint16_t *__restrict__ a3, float *__restrict__ part,
-                                                    const Scalars *__restrict__ sc)
+                                                    const Scalars *__restrict__ sc, int add)
 {
     const float rho = static_cast<float>(sqrt(sc->net_q2 / (double)g.n));
     const int c = threadIdx.x & 31, s = threadIdx.x >> 5;
@@ -611,8 +616,8 @@ __global__ __launch_bounds__(256) void k_net_out_dw(NetGeo g, const float *__res
         float v = 0.f;
         for (int r = 0; r < 8; ++r) v += red[r][threadIdx.x];
         float *dst = part + (long)blockIdx.x * kNetParams;
-        if (threadIdx.x < 160) dst[kNetOffW4 + threadIdx.x] = v;
-        else dst[kNetOffB4] = v;
+        float &o = (threadIdx.x < 160) ? dst[kNetOffW4 + threadIdx.x] : dst[kNetOffB4];
+        o = add ? o + v : v;
     }
 }
 
@@ -700,16 +705,20 @@ void launch_spmv_t(const NetGeo &g, const float *a, const float *m, const float 
 // ------------------------------------------------------------------------------------------
 // parameters: gradient reduction, Adam, BF16 copies
 // ------------------------------------------------------------------------------------------
-// grad[i] = (accumulate ? grad[i] : 0) + scale * sum over the launch's partial rows of part[row][i]
-// (rows summed in order: deterministic).  Only parameters in [lo, hi) are touched.
-__global__ __launch_bounds__(256) void k_net_reduce(const float *__restrict__ part, int rows, int lo, int hi,
-                                                    float scale, int accumulate, float *__restrict__ grad)
+// grad[i] = scale * sum over the partial rows of part[row][i]: eight interleaved running sums
+// (rows r = 8 q + c go to sum c) combined in a fixed tree, so the result is deterministic.
+__global__ __launch_bounds__(256) void k_net_reduce(const float *__restrict__ part, int rows, float scale,
+                                                    float *__restrict__ grad)
 {
-    const int i = lo + blockIdx.x * 256 + threadIdx.x;
-    if (i >= hi) return;
-    float s = 0.f;
-    for (int r = 0; r < rows; ++r) s += part[(long)r * kNetParams + i];
-    grad[i] = (accumulate ? grad[i] : 0.f) + scale * s;
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= kNetParams) return;
+    float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    int r = 0;
+    for (; r + 8 <= rows; r += 8)
+#pragma unroll
+        for (int c = 0; c < 8; ++c) s[c] += part[(long)(r + c) * kNetParams + i];
+    for (; r < rows; ++r) s[0] += part[(long)r * kNetParams + i];
+    grad[i] = scale * (((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7])));
 }
 
 __device__ void refresh_one(const NetDev &d, int i, float v)
@@ -799,33 +808,34 @@ void launch_net_diff(long n, const float *m, const float *e, float *out, hipStre
     hipLaunchKernelGGL(k_net_diff, dim3(net_blocks(n, 1024, 8192)), dim3(256), 0, s, n, m, e, out);
 }
 
-// Backward through the network for one pair; partial weight gradients accumulate into grad.
+// Backward through the network for one pair: per-row partial weight gradients are written
+// (first pair of a batch) or added (later pairs) into d.part; launch_net_grad then sums the
+// rows once per batch.
 void launch_net_backward(const NetGeo &g, const NetDev &d, const NetActs &act, const float *u, const Scalars *sc,
-                         float scale, int accumulate, hipStream_t s)
+                         int first, hipStream_t s)
 {
     const int rows = kNetPartRows;
+    const int add = first ? 0 : 1;
     // output layer
     hipLaunchKernelGGL(k_net_out_bwd, dim3(net_blocks(g.n, 1024, 8192)), dim3(256), 0, s, g, u, act.a3, d.w4, act.d1,
                        sc);
-    hipLaunchKernelGGL(k_net_out_dw, dim3(rows), dim3(256), 0, s, g, u, act.a3, d.part, sc);
-    hipLaunchKernelGGL(k_net_reduce, dim3((kNetParams - kNetOffW4 + 255) / 256), dim3(256), 0, s, d.part, rows,
-                       kNetOffW4, kNetParams, scale, accumulate, d.grad);
+    hipLaunchKernelGGL(k_net_out_dw, dim3(rows), dim3(256), 0, s, g, u, act.a3, d.part, sc, add);
     const int nb = net_blocks((g.n + 15) / 16, 4 * 8, 4096);
     const int rb = rows / 4;   // dw kernels: one partial row per wave
     // layer 3: dW3 from (dh3, a2); dh2 = bwd(dh3) masked by a2
-    hipLaunchKernelGGL((k_conv_dw<3>), dim3(rb), dim3(256), 0, s, g, act.d1, act.a2, d.part);
-    hipLaunchKernelGGL(k_net_reduce, dim3((kNetOffW4 - kNetOffW3 + 255) / 256), dim3(256), 0, s, d.part, rows,
-                       kNetOffW3, kNetOffW4, scale, accumulate, d.grad);
+    hipLaunchKernelGGL((k_conv_dw<3>), dim3(rb), dim3(256), 0, s, g, act.d1, act.a2, d.part, add);
     hipLaunchKernelGGL((k_conv_bwd<3>), dim3(nb), dim3(256), 0, s, g, act.d1, d.w3b, act.a2, act.d2);
     // layer 2: dW2 from (dh2, a1); dh1 = bwd(dh2) masked by a1
-    hipLaunchKernelGGL((k_conv_dw<2>), dim3(rb), dim3(256), 0, s, g, act.d2, act.a1, d.part);
-    hipLaunchKernelGGL(k_net_reduce, dim3((kNetOffW3 - kNetOffW2 + 255) / 256), dim3(256), 0, s, d.part, rows,
-                       kNetOffW2, kNetOffW3, scale, accumulate, d.grad);
+    hipLaunchKernelGGL((k_conv_dw<2>), dim3(rb), dim3(256), 0, s, g, act.d2, act.a1, d.part, add);
     hipLaunchKernelGGL((k_conv_bwd<2>), dim3(nb), dim3(256), 0, s, g, act.d2, d.w2b, act.a1, act.d1);
     // layer 1: dW1 from (dh1, x0)
-    hipLaunchKernelGGL((k_conv_dw<1>), dim3(rb), dim3(256), 0, s, g, act.d1, act.x0, d.part);
-    hipLaunchKernelGGL(k_net_reduce, dim3((kNetOffW2 - kNetOffW1 + 255) / 256), dim3(256), 0, s, d.part, rows,
-                       kNetOffW1, kNetOffW2, scale, accumulate, d.grad);
+    hipLaunchKernelGGL((k_conv_dw<1>), dim3(rb), dim3(256), 0, s, g, act.d1, act.x0, d.part, add);
+}
+
+void launch_net_grad(const NetDev &d, float scale, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_net_reduce, dim3((kNetParams + 255) / 256), dim3(256), 0, s, d.part, kNetPartRows, scale,
+                       d.grad);
 }
 
 void launch_net_refresh(const NetDev &d, hipStream_t s)
