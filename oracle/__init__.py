@@ -3,8 +3,8 @@
 Only ``tests/``, the smoke check and the benchmark's CPU-baseline leg import this package.
 The GPU library never imports it and shares no code with it.
 
-* ``apply``, ``apply_points``, ``thomas``, ``bicgstab`` wrap ``oracle.c`` (see its header for
-  the passages of the paper each follows).
+* ``apply``, ``apply_points``, ``thomas``, ``rbsor``, ``bicgstab`` wrap ``oracle.c`` (see its
+  header for the passages of the paper each follows).
 * ``dense_matrix`` / ``dense_solve`` assemble A as a dense matrix and solve it with LAPACK's
   partial-pivot LU (the exact solution the Krylov iteration approaches; tiny grids only).
 * ``net`` holds the FP64 reference of the learned preconditioner's network.
@@ -66,6 +66,11 @@ def _load():
         lib.orc_bicgstab.argtypes = [ctypes.c_int] * 3 + [dp, dp, dp, ctypes.c_double, ctypes.c_int, ctypes.c_int,
                                                           ctypes.c_int, dp, ctypes.c_int, ctypes.POINTER(_Info)]
         lib.orc_bicgstab.restype = ctypes.c_int
+        lib.orc_rbsor.argtypes = [ctypes.c_int] * 3 + [dp, dp, dp, ctypes.c_int, ctypes.c_double]
+        lib.orc_bicgstab_sor.argtypes = [ctypes.c_int] * 3 + [dp, dp, dp, ctypes.c_double, ctypes.c_int, ctypes.c_int,
+                                                             ctypes.c_int, ctypes.c_double, dp, ctypes.c_int,
+                                                             ctypes.POINTER(_Info)]
+        lib.orc_bicgstab_sor.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -120,10 +125,22 @@ def dot(a: np.ndarray, b: np.ndarray) -> float:
     return _load().orc_dot(a.size, _dp(a), _dp(b))
 
 
+def rbsor(coef: np.ndarray, q: np.ndarray, sweeps: int = 3, omega: float = 1.5, half_sweeps: int | None = None):
+    """Red-black vertical-line SOR applied to q from x0 = 0 (the tri_sor preconditioner of
+    Sec. 2, Eq. 7, with red-black column order); ``half_sweeps`` overrides 2 * sweeps."""
+    nlon, nlat, nlev = _check(coef)
+    q = _vec(q, nlon * nlat * nlev)
+    z = np.empty_like(q)
+    nh = 2 * sweeps if half_sweeps is None else half_sweeps
+    _load().orc_rbsor(nlon, nlat, nlev, _dp(coef), _dp(q), _dp(z), int(nh), float(omega))
+    return z
+
+
 def bicgstab(coef: np.ndarray, b: np.ndarray, x0: np.ndarray | None = None, tol: float = 1e-8,
              maxit: int = 20000, restart_every: int = 0, precond: int = 1,
-             hist_cap: int | None = None) -> tuple[np.ndarray, SolveInfo]:
-    """Right-preconditioned BiCGStab; precond 1 = vertical tridiagonal, 0 = identity."""
+             hist_cap: int | None = None, sor_sweeps: int = 3, sor_omega: float = 1.5) -> tuple[np.ndarray, SolveInfo]:
+    """Right-preconditioned BiCGStab; precond 1 = vertical tridiagonal, 0 = identity,
+    2 = red-black line SOR with ``sor_sweeps`` sweeps and relaxation ``sor_omega``."""
     nlon, nlat, nlev = _check(coef)
     n = nlon * nlat * nlev
     b = _vec(b, n)
@@ -131,8 +148,12 @@ def bicgstab(coef: np.ndarray, b: np.ndarray, x0: np.ndarray | None = None, tol:
     cap = maxit if hist_cap is None else hist_cap
     hist = np.full(max(cap, 1), np.nan)
     info = _Info()
-    _load().orc_bicgstab(nlon, nlat, nlev, _dp(coef), _dp(b), _dp(x), tol, maxit, restart_every, precond,
-                         _dp(hist), cap, ctypes.byref(info))
+    if precond == 2:
+        _load().orc_bicgstab_sor(nlon, nlat, nlev, _dp(coef), _dp(b), _dp(x), tol, maxit, restart_every,
+                                 int(sor_sweeps), float(sor_omega), _dp(hist), cap, ctypes.byref(info))
+    else:
+        _load().orc_bicgstab(nlon, nlat, nlev, _dp(coef), _dp(b), _dp(x), tol, maxit, restart_every, precond,
+                             _dp(hist), cap, ctypes.byref(info))
     h = hist[:min(info.iterations, cap)].copy()
     return x, SolveInfo(info.iterations, info.restarts, info.status, info.half_step_exit, info.rel_residual,
                         info.true_rel_residual, h)

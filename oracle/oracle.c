@@ -15,6 +15,9 @@
  *   orc_thomas     Sec. 2, Eq. 6-7 and the text after them: T is the vertical tridiagonal
  *                  part of A, inverted per horizontal point with no vertical decomposition.
  *                  Plain LU (Thomas) without pivoting.
+ *   orc_rbsor      Sec. 2, Eq. 6-7: the tri_sor preconditioner (a few over-relaxed sweeps of
+ *                  vertical-line Gauss-Seidel in which T takes the place of the diagonal),
+ *                  with the columns visited in red-black order instead of lexicographically.
  *   orc_bicgstab   Sec. 2 (post-conditioned BiCGStab, Eq. 5; van der Vorst's method with the
  *                  preconditioner applied on the right) and Sec. 3 (halting on
  *                  R = ||r_i|| / ||b|| of the unpreconditioned residual, Eq. 8-9), with the
@@ -134,6 +137,73 @@ void orc_thomas(int nlon, int nlat, int nlev, const double *coef, const double *
     free(yy);
 }
 
+/*
+ * Red-black vertical-line SOR (Sec. 2, Eq. 6-7).  The paper writes the scaled operator as
+ * T + L + U (T the vertical tridiagonal part, L and U the couplings to columns visited before
+ * and after a column) and applies a few sweeps of
+ *     (T + omega L) x_n = (1 - omega) T x_{n-1} + omega (r - U x_{n-1}),   x_0 = 0.
+ * Solved column by column this is: x_c <- (1 - omega) x_c + omega T_c^{-1} (r_c + sum of the
+ * horizontal couplings times the newest neighbour values).  Here the columns are visited in
+ * red-black order (red: i + j even, then black), so "before" means "of the other colour and
+ * already updated in this sweep".  Within one colour all columns use the values at the start
+ * of the half-sweep (with even nlon no column has a neighbour of its own colour).
+ * nhalf = number of half-sweeps (two per sweep: red, then black).  z receives x.
+ */
+void orc_rbsor(int nlon, int nlat, int nlev, const double *coef, const double *q, double *z, int nhalf,
+               double omega)
+{
+    const long P = (long)nlon * nlat;
+    const long n = P * nlev;
+    const double *aW = coef + ORC_W * n, *aE = coef + ORC_E * n, *aS = coef + ORC_S * n, *aN = coef + ORC_N * n;
+    const double *aD = coef + ORC_D * n, *aU = coef + ORC_U * n, *C = coef + ORC_C * n;
+    double *old = (double *)malloc(sizeof(double) * (size_t)n);
+    double *rhs = (double *)malloc(sizeof(double) * (size_t)nlev);
+    double *cp = (double *)malloc(sizeof(double) * (size_t)nlev);
+    double *yy = (double *)malloc(sizeof(double) * (size_t)nlev);
+    double *col = (double *)malloc(sizeof(double) * (size_t)nlev);
+    for (long c = 0; c < n; ++c) z[c] = 0.0;
+    for (int h = 0; h < nhalf; ++h) {
+        const int colour = h % 2;
+        memcpy(old, z, sizeof(double) * (size_t)n);
+        for (int j = 0; j < nlat; ++j)
+            for (int i = 0; i < nlon; ++i) {
+                if ((i + j) % 2 != colour) continue;
+                const int iw = (i == 0) ? nlon - 1 : i - 1;
+                const int ie = (i == nlon - 1) ? 0 : i + 1;
+                for (int k = 0; k < nlev; ++k) {
+                    const long c = i + (long)nlon * (j + (long)nlat * k);
+                    double acc = q[c];
+                    acc = acc + aW[c] * old[c - i + iw];
+                    acc = acc + aE[c] * old[c - i + ie];
+                    if (j > 0) acc = acc + aS[c] * old[c - nlon];
+                    if (j < nlat - 1) acc = acc + aN[c] * old[c + nlon];
+                    rhs[k] = acc;
+                }
+                /* T_c y = rhs, plain Thomas as in orc_thomas */
+                const long c0 = i + (long)nlon * j;
+                cp[0] = -aU[c0] / C[c0];
+                yy[0] = rhs[0] / C[c0];
+                for (int k = 1; k < nlev; ++k) {
+                    const long c = c0 + k * P;
+                    const double den = C[c] - (-aD[c]) * cp[k - 1];
+                    cp[k] = -aU[c] / den;
+                    yy[k] = (rhs[k] - (-aD[c]) * yy[k - 1]) / den;
+                }
+                col[nlev - 1] = yy[nlev - 1];
+                for (int k = nlev - 2; k >= 0; --k) col[k] = yy[k] - cp[k] * col[k + 1];
+                for (int k = 0; k < nlev; ++k) {
+                    const long c = c0 + k * P;
+                    z[c] = (1.0 - omega) * old[c] + omega * col[k];
+                }
+            }
+    }
+    free(old);
+    free(rhs);
+    free(cp);
+    free(yy);
+    free(col);
+}
+
 double orc_dot(long n, const double *a, const double *b)
 {
     double s = 0.0;
@@ -143,12 +213,18 @@ double orc_dot(long n, const double *a, const double *b)
 
 static double nrm2(long n, const double *a) { return sqrt(orc_dot(n, a, a)); }
 
-/* precond: 0 = identity, 1 = vertical tridiagonal (T^{-1}) */
+/* preconditioner choice of orc_bicgstab_pc: 0 = identity, 1 = vertical tridiagonal (T^{-1}),
+ * 2 = red-black line SOR (orc_rbsor) with sor_sweeps sweeps and relaxation sor_omega */
+static int g_sor_sweeps = 3;
+static double g_sor_omega = 1.5;
+
 static void apply_m(int precond, int nlon, int nlat, int nlev, const double *coef,
                     const double *q, double *z, long n)
 {
     if (precond == 1)
         orc_thomas(nlon, nlat, nlev, coef, q, z);
+    else if (precond == 2)
+        orc_rbsor(nlon, nlat, nlev, coef, q, z, 2 * g_sor_sweeps, g_sor_omega);
     else
         memcpy(z, q, sizeof(double) * (size_t)n);
 }
@@ -319,4 +395,17 @@ done:
     info->iterations = it;
     free(r); free(rh); free(p); free(ph); free(v); free(s); free(sh); free(t);
     return info->status;
+}
+
+/* orc_bicgstab with the red-black line SOR preconditioner's parameters (precond = 2). */
+int orc_bicgstab_sor(int nlon, int nlat, int nlev, const double *coef, const double *b, double *x,
+                     double tol, int maxit, int restart_every, int sweeps, double omega, double *hist,
+                     int hist_cap, orc_info *info)
+{
+    g_sor_sweeps = sweeps;
+    g_sor_omega = omega;
+    const int st = orc_bicgstab(nlon, nlat, nlev, coef, b, x, tol, maxit, restart_every, 2, hist, hist_cap, info);
+    g_sor_sweeps = 3;
+    g_sor_omega = 1.5;
+    return st;
 }
