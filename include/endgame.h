@@ -135,6 +135,12 @@ int eg_set_stream(eg_operator *op, void *hip_stream);
  *   "stall_window"   learned modes: iterations without a 2x gain that trigger fallback [20]
  *                    (FGMRES: at least one restart cycle, max(stall_window, gmres_m))
  *   "profile"        1 = time every streaming kernel launch (see eg_kernel_stats) [0]
+ *   "precond"        preconditioner of the plain modes: 0 the vertical tridiagonal solve
+ *                    T^{-1}, 1 red-black vertical-line SOR (the tri_sor of Sec. 2, Eq. 7, with
+ *                    the columns in red-black order; needs an even nlon) [0].  The learned modes
+ *                    and the harvests always build on T^{-1}.
+ *   "sor_sweeps"     sweeps of the line SOR, 1..16 [3]
+ *   "sor_omega"      its relaxation factor, 0 < omega < 2 [1.5]
  *   "method"         Krylov method of the plain modes: 0 BiCGStab, 1 restarted FGMRES [0]
  *   "learned_method" Krylov method of the learned modes: 0 flexible BiCGStab, 1 FGMRES [1]
  *   "gmres_m"        FGMRES restart length, 1..64 [30]
@@ -152,11 +158,15 @@ int eg_set_option(eg_operator *op, const char *key, double value);
 int eg_apply(eg_operator *op, const void *x, void *y, int prec);
 
 /*
- * z = T^{-1} q with T = tridiag(-D, C, -U) per column (Sec. 2, Eq. 6-7: the vertical
- * tridiagonal that replaces the diagonal; its LU factors are precomputed per horizontal point
- * when the operator is built).  q, z: device arrays of n elements (double for EG_PREC_FP64,
- * float otherwise); may not overlap.  FP64 uses the FP64 factors; every other precision uses
- * their FP32 rounding (the 16-bit modes store only the couplings of A in 16 bits).
+ * z = M q with the operator's preconditioner.  Default: M = T^{-1}, T = tridiag(-D, C, -U) per
+ * column (Sec. 2, Eq. 6-7: the vertical tridiagonal that replaces the diagonal; its LU factors
+ * are precomputed per horizontal point when the operator is built).  With the option
+ * "precond" = 1, M is the red-black vertical-line SOR from x = 0: each sweep updates the
+ * columns with i + j even, then the others, by x_c <- (1 - omega) x_c + omega T_c^{-1}(q_c +
+ * sum of the horizontal couplings times the neighbours' newest values).  q, z: device arrays
+ * of n elements (double for EG_PREC_FP64, float otherwise); may not overlap.  FP64 uses the
+ * FP64 factors and couplings; every other precision uses the FP32 rounding of the FP64 factors
+ * and that precision's couplings.
  */
 int eg_apply_precond(eg_operator *op, const void *q, void *z, int prec);
 
@@ -190,6 +200,8 @@ enum eg_kernel {
     EG_K_SPMV_T = 3,     /* t = A shat with <t, s>, <t, t>                                  */
     EG_K_UPDATE = 4,     /* x += alpha phat + omega shat; r = s - omega t with dots         */
     EG_K_RESIDUAL = 5,   /* FP64 true residual r = b - A x (refinement steps)               */
+    EG_K_SOR_P = 6,      /* red-black line SOR half-sweeps on p (option "precond" = 1)      */
+    EG_K_SOR_S = 7,      /* red-black line SOR half-sweeps on s                             */
     EG_K_COUNT = 8
 };
 int eg_kernel_stats(const eg_operator *op, int kernel, int prec, long *launches, double *total_ms);

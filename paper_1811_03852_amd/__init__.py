@@ -31,7 +31,7 @@ EXPORTED = ["eg_create_operator", "eg_solve", "eg_get_info", "eg_residual_histor
             "eg_harvest", "eg_harvest_krylov", "eg_net_train", "eg_net_eval", "eg_net_set_loss"]
 N_NET_PARAMS = 15233
 # enum eg_kernel
-K_THOMAS_P, K_SPMV_V, K_THOMAS_S, K_SPMV_T, K_UPDATE, K_RESIDUAL = range(6)
+K_THOMAS_P, K_SPMV_V, K_THOMAS_S, K_SPMV_T, K_UPDATE, K_RESIDUAL, K_SOR_P, K_SOR_S = range(8)
 
 
 class EndgameError(RuntimeError):

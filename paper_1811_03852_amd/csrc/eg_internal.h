@@ -102,6 +102,11 @@ enum ThomasMode { TH_PLAIN = 0, TH_P = 1, TH_S = 2 };
 template <typename Tv>
 void launch_thomas(const TriView<Tv> &tv, const Tv *q, Tv *z, int mode, const Tv *r, Tv *p, const Tv *v, Tv *rhat,
                    double *partials, int *nrows, const Scalars *sc, hipStream_t s, int stop_mask = 0);
+// Red-black vertical-line SOR applied to q, `sweeps` sweeps with relaxation omega; x must hold
+// T^{-1} q on entry and receives the result; wsc is an n-vector of scratch.  nlon must be even.
+template <typename Tv, typename Tc>
+void launch_sor(const OpView<Tc> &op, const TriView<Tv> &tv, const Tv *q, Tv *x, Tv *wsc, int sweeps, double omega,
+                const Scalars *sc, int stop_mask, hipStream_t s);
 template <typename Tf>
 void launch_tri_factor(const double *a64, const double *m64, int nlon, int nlat, int nlev, Tf *f, hipStream_t s);
 

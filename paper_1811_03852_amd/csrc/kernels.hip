@@ -1262,6 +1262,108 @@ void launch_quantize(int kind, int nlon, int nlat, int nlev, const double *a64, 
 }
 
 // ------------------------------------------------------------------------------------------
+// Red-black vertical-line SOR (Sec. 2, Eq. 6-7, the tri_sor preconditioner with the columns
+// visited in red-black order; red: i + j even).  A sweep updates every column of one colour,
+// then every column of the other, each by
+//     x_c <- (1 - omega) x_c + omega T_c^{-1} (q_c + sum of its horizontal couplings times x)
+// With nlon even every horizontal neighbour has the other colour, so the columns of one colour
+// are independent: one lane per column, the rhs gathered level by level on the way up, w_k of
+// the Thomas forward sweep parked in a scratch vector, the blend done on the way down.
+//
+// The first half-sweep from x = 0 is omega T^{-1} q on the red columns; the caller has already
+// computed T^{-1} q for every column (the tridiagonal kernel it fuses with the BiCGStab axpy),
+// so the chain starts at the first black half-sweep and reads the red values with the factor
+// omega applied on the fly (nb_scale), and the next red half-sweep reads its own old value the
+// same way (own_scale).  With a single sweep the red values are scaled at the end.
+// ------------------------------------------------------------------------------------------
+template <typename Tv, typename Tc>
+__global__ __launch_bounds__(kWG) void k_sor_half(OpView<Tc> op, TriView<Tv> tv, const Tv *__restrict__ q,
+                                                  Tv *__restrict__ x, Tv *__restrict__ wsc, int colour, Tv omega,
+                                                  Tv nb_scale, Tv own_scale, const Scalars *__restrict__ sc,
+                                                  int stop_mask)
+{
+    if (stopped(sc, stop_mask)) return;
+    using V = typename CoefTraits<Tc>::val;
+    constexpr bool Q = CoefTraits<Tc>::quant;
+    const int nlon = op.nlon, nlat = op.nlat, nlev = op.nlev;
+    const int half = nlon / 2;
+    const long P = op.P, n = op.n;
+    const long c2 = (long)blockIdx.x * kWG + threadIdx.x;
+    if (c2 >= P / 2) return;
+    const int j = (int)(c2 / half);
+    const int i = 2 * (int)(c2 % half) + ((j + colour) & 1);
+    const int iw = (i == 0) ? nlon - 1 : i - 1;
+    const int ie = (i == nlon - 1) ? 0 : i + 1;
+    const long col = (long)j * nlon + i;
+    const Tv *lf = tv.f, *invf = tv.f + n, *cf = tv.f + 2 * n;
+    // forward: rhs_k = q_k + nb_scale * sum_d a_d x_d,  w_k = rhs_k + l_k w_{k-1}
+    Tv wprev = 0;
+    for (int k = 0; k < nlev; ++k) {
+        const long c = col + (long)k * P;
+        float s0 = 1.f, s1 = 1.f, s2 = 1.f, s3 = 1.f;
+        if constexpr (Q) {
+            const float *qr = op.qs + ((size_t)k * nlat + j) * kQsStride;
+            s0 = qr[0];
+            s1 = qr[1];
+            s2 = qr[2];
+            s3 = qr[3];
+        }
+        const Tc *arow = op.a + (c - i);
+        const V aW = DecB<Tc>::get(arow, i, s0);
+        const V aE = DecB<Tc>::get(arow + n, i, s1);
+        Tv h = aW * x[c - i + iw] + aE * x[c - i + ie];
+        if (j > 0) h += static_cast<Tv>(DecB<Tc>::get(arow + 2 * n, i, s2)) * x[c - nlon];
+        if (j < nlat - 1) h += static_cast<Tv>(DecB<Tc>::get(arow + 3 * n, i, s3)) * x[c + nlon];
+        const Tv w = (q[c] + nb_scale * h) + lf[c] * wprev;
+        wsc[c] = w;
+        wprev = w;
+    }
+    // backward: y_k = inv_k w_k + c_k y_{k+1};  x_k <- (1 - omega) own_scale x_k + omega y_k
+    Tv ynext = 0;
+    const Tv keep = (Tv(1) - omega) * own_scale;
+    for (int k = nlev - 1; k >= 0; --k) {
+        const long c = col + (long)k * P;
+        const Tv y = invf[c] * wsc[c] + cf[c] * ynext;
+        const Tv old = (own_scale == Tv(0)) ? Tv(0) : x[c];
+        x[c] = keep * old + omega * y;
+        ynext = y;
+    }
+}
+
+// x <- factor * x on the columns of one colour (all levels)
+template <typename Tv>
+__global__ __launch_bounds__(kWG) void k_sor_scale(long P, long n, int nlon, Tv *__restrict__ x, int colour,
+                                                   Tv factor, const Scalars *__restrict__ sc, int stop_mask)
+{
+    if (stopped(sc, stop_mask)) return;
+    const long stride = (long)gridDim.x * kWG;
+    for (long c = (long)blockIdx.x * kWG + threadIdx.x; c < n; c += stride) {
+        const long pc = c % P;
+        const int i = (int)(pc % nlon), j = (int)(pc / nlon);
+        if (((i + j) & 1) == colour) x[c] *= factor;
+    }
+}
+
+template <typename Tv, typename Tc>
+void launch_sor(const OpView<Tc> &op, const TriView<Tv> &tv, const Tv *q, Tv *x, Tv *wsc, int sweeps, double omega,
+                const Scalars *sc, int stop_mask, hipStream_t s)
+{
+    const long half_cols = op.P / 2;
+    const unsigned blocks = (unsigned)((half_cols + kWG - 1) / kWG);
+    const Tv w = static_cast<Tv>(omega);
+    for (int h = 1; h < 2 * sweeps; ++h) {
+        const int colour = (h & 1) ? 1 : 0;                       // odd: black, even: red
+        const Tv nb_scale = (h == 1) ? w : Tv(1);                 // red still holds T^{-1} q
+        const Tv own_scale = (h == 1) ? Tv(0) : (h == 2 ? w : Tv(1));
+        hipLaunchKernelGGL((k_sor_half<Tv, Tc>), dim3(blocks), dim3(kWG), 0, s, op, tv, q, x, wsc, colour, w,
+                           nb_scale, own_scale, sc, stop_mask);
+    }
+    if (sweeps == 1)
+        hipLaunchKernelGGL((k_sor_scale<Tv>), dim3(elementwise_blocks(op.n)), dim3(kWG), 0, s, op.P, op.n, op.nlon, x,
+                           0, w, sc, stop_mask);
+}
+
+// ------------------------------------------------------------------------------------------
 // explicit instantiations
 // ------------------------------------------------------------------------------------------
 template void launch_spmv<double, double>(const OpView<double> &, const double *, double *, const double *, int,
@@ -1301,6 +1403,14 @@ template int launch_maxpy<float>(long, float *, const float *, int, int, const d
                                  hipStream_t);
 template void launch_vscale<double>(long, const double *, double *, const double *, hipStream_t);
 template void launch_vscale<float>(long, const float *, float *, const double *, hipStream_t);
+template void launch_sor<double, double>(const OpView<double> &, const TriView<double> &, const double *, double *,
+                                         double *, int, double, const Scalars *, int, hipStream_t);
+template void launch_sor<float, float>(const OpView<float> &, const TriView<float> &, const float *, float *, float *,
+                                       int, double, const Scalars *, int, hipStream_t);
+template void launch_sor<float, bf16_t>(const OpView<bf16_t> &, const TriView<float> &, const float *, float *,
+                                        float *, int, double, const Scalars *, int, hipStream_t);
+template void launch_sor<float, fp16_t>(const OpView<fp16_t> &, const TriView<float> &, const float *, float *,
+                                        float *, int, double, const Scalars *, int, hipStream_t);
 template void launch_fill<double>(double *, long, double, hipStream_t);
 template void launch_fill<float>(float *, long, float, hipStream_t);
 

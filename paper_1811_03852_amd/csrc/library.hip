@@ -129,10 +129,15 @@ struct eg_operator {
     int max_outer = 30;
     int poll = 8;
     int stall_window = 20;
+    int precond = 0;            // plain modes: 0 T^{-1}, 1 red-black vertical-line SOR
+    int sor_sweeps = 3;
+    double sor_omega = 1.5;
+    bool sor_on = false;        // SOR active in the current solve (plain modes with precond 1)
+    double *sor_scratch = nullptr;   // n doubles, for eg_apply_precond
     int profile = 0;
 
     // kernel timing: events around the streaming kernels of one iteration + the residual
-    hipEvent_t ev[12] = {};
+    hipEvent_t ev[16] = {};
     bool ev_ready = false;
     double kms[EG_K_COUNT][4] = {};
     long kcnt[EG_K_COUNT][4] = {};
@@ -284,6 +289,11 @@ void enqueue_iteration(eg_operator *op, const OpView<Tc> &A, Work<Tv> &w, hipEve
     mark(0);
     launch_thomas<Tv>(T, nullptr, w.ph, TH_P, w.r, w.p, w.v, w.rh, op->partials, &nr, op->sc, s);
     mark(1);
+    if (op->sor_on) {   // t is free until the second product of the iteration
+        mark(12);
+        launch_sor<Tv, Tc>(A, T, w.p, w.ph, w.t, op->sor_sweeps, op->sor_omega, op->sc, STOP_DONE, s);
+        mark(13);
+    }
     mark(2);
     launch_spmv<Tv, Tc>(A, w.ph, w.v, w.rh, SP_DOT2, op->partials, &nr, op->sc, STOP_DONE, s);
     mark(3);
@@ -292,6 +302,12 @@ void enqueue_iteration(eg_operator *op, const OpView<Tc> &A, Work<Tv> &w, hipEve
     launch_thomas<Tv>(T, nullptr, w.sh, TH_S, w.r, w.s, w.v, nullptr, op->partials, &nr, op->sc, s);
     mark(5);
     launch_finalize(FIN_S, op->partials, nr, op->sc, op->d_hist, nullptr, 0, 0, s);
+    if (op->sor_on) {
+        mark(14);
+        launch_sor<Tv, Tc>(A, T, w.s, w.sh, w.t, op->sor_sweeps, op->sor_omega, op->sc,
+                           STOP_DONE | STOP_SKIP | STOP_HALF, s);
+        mark(15);
+    }
     mark(6);
     launch_spmv<Tv, Tc>(A, w.sh, w.t, w.s, SP_DOT2, op->partials, &nr, op->sc, STOP_DONE | STOP_SKIP | STOP_HALF, s);
     mark(7);
@@ -320,6 +336,10 @@ template <typename Tv, typename Tc> int krylov_run(eg_operator *op, const OpView
             for (int k = 0; k < 5; ++k)
                 if (mask & (1 << k))
                     if ((rc = add_kernel_time(op, k, k, prec))) return rc;
+            if (op->sor_on) {
+                if ((mask & 1) && (rc = add_kernel_time(op, 6, EG_K_SOR_P, prec))) return rc;
+                if ((mask & 4) && (rc = add_kernel_time(op, 7, EG_K_SOR_S, prec))) return rc;
+            }
         }
         return 0;
     }
@@ -528,6 +548,8 @@ int fgmres(eg_operator *op, const OpView<Tc> &A, Tv *d, double nb, double tol, i
         for (int j = 0; j < m; ++j) {
             Tv *Vj = F.V + (size_t)j * n, *Zj = F.Z + (size_t)j * n;
             launch_thomas<Tv>(T, Vj, Zj, TH_PLAIN, nullptr, nullptr, nullptr, nullptr, op->partials, nullptr, nullptr, s);
+            if (op->sor_on && !use_net)
+                launch_sor<Tv, Tc>(A, T, Vj, Zj, F.tmp, op->sor_sweeps, op->sor_omega, nullptr, 0, s);
             if constexpr (std::is_same_v<Tc, float> || std::is_same_v<Tc, double>)
                 if (use_net) enqueue_net_stage<Tv, Tc>(op, net, coef, Vj, Zj, qp, nullptr, 0);
             launch_spmv<Tv, Tc>(A, Zj, F.W, nullptr, SP_PLAIN, op->partials, nullptr, nullptr, 0, s);
@@ -930,7 +952,7 @@ void eg_destroy_operator(eg_operator *op)
     dfree(op->harvest_x);
     for (Fgm<double> *F : {&op->f64}) { dfree(F->V); dfree(F->Z); dfree(F->W); dfree(F->R); dfree(F->tmp); }
     for (Fgm<float> *F : {&op->f32}) { dfree(F->V); dfree(F->Z); dfree(F->W); dfree(F->R); dfree(F->tmp); }
-    dfree(op->d_h); dfree(op->mpart);
+    dfree(op->d_h); dfree(op->mpart); dfree(op->sor_scratch);
     if (op->h_h) (void)hipHostFree(op->h_h);
     dfree(op->w64.qp);
     dfree(op->w32.qp);
@@ -1015,6 +1037,16 @@ int eg_set_option(eg_operator *op, const char *key, double value)
     } else if (k == "poll") {
         if (value < 1 || value > 4096) return fail(EG_EINVAL, "poll must be in [1, 4096]");
         op->poll = (int)value;
+    } else if (k == "precond") {
+        if (value != 0.0 && value != 1.0) return fail(EG_EINVAL, "precond must be 0 (T^-1) or 1 (red-black line SOR)");
+        if (value == 1.0 && op->nlon % 2 != 0) return fail(EG_EINVAL, "the red-black line SOR needs an even nlon");
+        op->precond = (int)value;
+    } else if (k == "sor_sweeps") {
+        if (value < 1 || value > 16 || value != std::floor(value)) return fail(EG_EINVAL, "sor_sweeps must be in 1..16");
+        op->sor_sweeps = (int)value;
+    } else if (k == "sor_omega") {
+        if (!(value > 0.0 && value < 2.0)) return fail(EG_EINVAL, "sor_omega must be in (0, 2)");
+        op->sor_omega = value;
     } else if (k == "method") {
         if (value != 0.0 && value != 1.0) return fail(EG_EINVAL, "method must be 0 (BiCGStab) or 1 (FGMRES)");
         op->method = (int)value;
@@ -1055,6 +1087,7 @@ int eg_solve(eg_operator *op, const double *b, double *x, double tol, int maxit,
     op->info = eg_info{};
     op->hist_count = 0;
     op->hist_pending.clear();
+    op->sor_on = (op->precond == 1) && mode < EG_LEARNED_FP64;
     int rc;
     if ((rc = check_vectors(op, b, x))) return rc;
     if ((rc = ensure_hist(op, std::min(maxit, 1 << 22)))) return rc;
@@ -1083,6 +1116,7 @@ int eg_solve(eg_operator *op, const double *b, double *x, double tol, int maxit,
         status = solve_ir<float>(op, op->view32(), b, x, tol, maxit, op->net);
         break;
     }
+    op->sor_on = false;
     if (status < 0) return status;
     // history to the host
     if (!op->hist_pending.empty()) {
@@ -1170,14 +1204,37 @@ int eg_apply_precond(eg_operator *op, const void *q, void *z, int prec)
     if (!op || !q || !z) return fail(EG_EINVAL, "NULL argument");
     if (prec < EG_PREC_FP64 || prec > EG_PREC_FP16) return fail(EG_EINVAL, "unknown precision");
     int rc;
+    const bool sor = op->precond == 1;
+    if (sor && !op->sor_scratch && (rc = dalloc(&op->sor_scratch, (size_t)op->n))) return rc;
     if (prec == EG_PREC_FP64) {
         launch_thomas<double>(op->tri_view64(), static_cast<const double *>(q), static_cast<double *>(z), TH_PLAIN,
                               nullptr, nullptr, nullptr, nullptr, op->partials, nullptr, nullptr, op->stream);
+        if (sor)
+            launch_sor<double, double>(op->view64(), op->tri_view64(), static_cast<const double *>(q),
+                                       static_cast<double *>(z), op->sor_scratch, op->sor_sweeps, op->sor_omega,
+                                       nullptr, 0, op->stream);
     } else {
         // every lower-precision set uses the FP32 rounding of the FP64 factors
         if ((rc = ensure_fp32(op))) return rc;
-        launch_thomas<float>(op->tri_view32(), static_cast<const float *>(q), static_cast<float *>(z), TH_PLAIN,
-                             nullptr, nullptr, nullptr, nullptr, op->partials, nullptr, nullptr, op->stream);
+        const float *qf = static_cast<const float *>(q);
+        float *zf = static_cast<float *>(z), *wf = reinterpret_cast<float *>(op->sor_scratch);
+        launch_thomas<float>(op->tri_view32(), qf, zf, TH_PLAIN, nullptr, nullptr, nullptr, nullptr, op->partials,
+                             nullptr, nullptr, op->stream);
+        if (sor) {
+            const TriView<float> T = op->tri_view32();
+            if (prec == EG_PREC_FP32) {
+                launch_sor<float, float>(op->view32(), T, qf, zf, wf, op->sor_sweeps, op->sor_omega, nullptr, 0,
+                                         op->stream);
+            } else if (prec == EG_PREC_BF16) {
+                if ((rc = ensure_quant(op, PBF16))) return rc;
+                launch_sor<float, bf16_t>(op->viewq<bf16_t>(0), T, qf, zf, wf, op->sor_sweeps, op->sor_omega, nullptr,
+                                          0, op->stream);
+            } else {
+                if ((rc = ensure_quant(op, PFP16))) return rc;
+                launch_sor<float, fp16_t>(op->viewq<fp16_t>(1), T, qf, zf, wf, op->sor_sweeps, op->sor_omega, nullptr,
+                                          0, op->stream);
+            }
+        }
     }
     EG_HIP(hipGetLastError());
     EG_HIP(hipStreamSynchronize(op->stream));
@@ -1336,6 +1393,7 @@ int eg_harvest(eg_operator *op, const double *b, int nsnap, float *r_out, float 
 {
     if (!op || !b || !r_out || !e_out || nsnap < 1) return fail(EG_EINVAL, "bad argument");
     int rc;
+    op->sor_on = false;   // the harvests use the tridiagonal preconditioner
     if ((rc = check_vectors(op, b, b))) return rc;
     if (!op->harvest_x && (rc = dalloc(&op->harvest_x, (size_t)op->n))) return rc;
     if ((rc = ensure_hist(op, 20000))) return rc;
@@ -1372,6 +1430,7 @@ int eg_harvest_krylov(eg_operator *op, const double *b, int nvec, float *r_out, 
 {
     if (!op || !b || !r_out || nvec < 1 || nvec > kMaxGmres) return fail(EG_EINVAL, "bad argument");
     int rc;
+    op->sor_on = false;   // the harvests use the tridiagonal preconditioner
     if ((rc = check_vectors(op, b, b))) return rc;
     if ((rc = ensure_work(op, op->w64))) return rc;
     if (!op->harvest_x && (rc = dalloc(&op->harvest_x, (size_t)op->n))) return rc;
