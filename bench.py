@@ -3,7 +3,8 @@ the HBM roofline fraction of the dominant kernel and the CPU oracle as a reporte
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--config c3] [--modes fp64,fp32_ir,...]
 
-A step solves A x = b once in every listed mode (x0 = 0).  Inputs (operator and right-hand
+A step solves A x = b once in every listed mode (x0 = 0); a "_sor" suffix selects the red-black
+vertical-line SOR preconditioner (three sweeps, omega 1.5) instead of the tridiagonal solve.  Inputs (operator and right-hand
 side) are generated on the host from the seeded recipe, copied to HBM and the operator is built
 before the timed region.  Learned modes first train the network (untimed, reported): FGMRES
 bases harvested from small operators of the same recipe, Adam on the residual-space loss.
@@ -34,9 +35,15 @@ BYTES_PER_POINT = {
     "update": {0: 64, 1: 32, 2: 32, 3: 32},     # x, phat, shat, s, t, rhat in + x, r out
     "residual": {0: 76},                        # 6 couplings + margin + x + b (FP64) + r (FP32)
 }
-KERNEL_IDS = {"thomas_p": [0], "spmv": [1, 3], "thomas_s": [2], "update": [4], "residual": [5]}
+# Red-black line SOR: algorithmic bytes of one half-sweep per grid point (half the columns
+# update: rhs q, own x in and out, the three LU factors, four horizontal couplings and the
+# parked forward-sweep value (write + read); the other half's x is read once as neighbours),
+# times 2 * sweeps - 1 half-sweeps per application (the first red half-sweep is the
+# tridiagonal solve before it).
+SOR_HALF_BYTES = {0: 52, 1: 26, 2: 22, 3: 22}
+KERNEL_IDS = {"thomas_p": [0], "spmv": [1, 3], "thomas_s": [2], "update": [4], "residual": [5], "sor": [6, 7]}
 KERNEL_SYMBOL = {"spmv": "k_spmv", "thomas_p": "k_thomas", "thomas_s": "k_thomas", "update": "k_update",
-                 "residual": "k_spmv"}
+                 "residual": "k_spmv", "sor": "k_sor_half"}
 PREC_NAME = {0: "fp64", 1: "fp32", 2: "bf16", 3: "fp16"}
 
 # HBM bytes per launch measured with rocprofv3 FETCH_SIZE and WRITE_SIZE on the 2560x1920x70
@@ -169,7 +176,7 @@ def main():
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="c3")
-    ap.add_argument("--modes", default="fp64,fp32_ir,fp32_ir_bf16")
+    ap.add_argument("--modes", default="fp64,fp32_ir,fp32_ir_bf16,fp64_sor,fp32_ir_sor,fp32_ir_bf16_sor")
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--learned-config", default="c4", help="workload of the learned-preconditioner comparison ('' skips it)")
@@ -221,7 +228,14 @@ def main():
                           "net_workload": args.learned_config or "c4"}))
         return
     name2mode = {v: k for k, v in eg.MODE_NAMES.items()}
-    modes = [name2mode[m] for m in args.modes.split(",") if m]
+    # a "_sor" suffix runs the mode with the red-black line SOR preconditioner (option precond 1)
+    runs = []
+    for m in args.modes.split(","):
+        if not m:
+            continue
+        sor = m.endswith("_sor")
+        runs.append((m, name2mode[m[:-4] if sor else m], sor))
+    modes = [mode for _, mode, _ in runs]
 
     net, training = None, None
     if args.learned_config or any(m in (eg.LEARNED_FP64, eg.LEARNED_FP32_IR) for m in modes):
@@ -260,25 +274,27 @@ def main():
         op.attach(net)
     x = torch.zeros(p.n, dtype=torch.float64, device="cuda")
     for _ in range(args.warmup):
-        for m in modes:
+        for name, m, sor in runs:
+            op.set_option("precond", 1 if sor else 0)
             x.zero_()
             info = op.solve(b, x, args.tol, 20000, m)
-            log(f"warmup {eg.MODE_NAMES[m]}: {info}")
+            log(f"warmup {name}: {info}")
 
     op.set_option("profile", 1)
     op.reset_kernel_stats()
-    per_mode = {eg.MODE_NAMES[m]: {"seconds": [], "iterations": None, "outer_steps": None, "status": None,
-                                   "true_rel_residual": None} for m in modes}
+    per_mode = {name: {"seconds": [], "iterations": None, "outer_steps": None, "status": None,
+                       "true_rel_residual": None} for name, _, _ in runs}
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     for _ in range(args.steps):
-        for m in modes:
+        for name, m, sor in runs:
+            op.set_option("precond", 1 if sor else 0)
             x.zero_()
             torch.cuda.synchronize()
             ts = time.perf_counter()
             info = op.solve(b, x, args.tol, 20000, m)
             torch.cuda.synchronize()
-            d = per_mode[eg.MODE_NAMES[m]]
+            d = per_mode[name]
             d["seconds"].append(time.perf_counter() - ts)
             d.update(iterations=info.iterations, outer_steps=info.outer_steps, status=info.status,
                      true_rel_residual=info.true_rel_residual)
@@ -295,9 +311,10 @@ def main():
                 c, t = op.kernel_stats(kid, prec)
                 cnt += c
                 ms += t
-            if cnt == 0 or prec not in BYTES_PER_POINT[kname]:
+            if cnt == 0 or (kname != "sor" and prec not in BYTES_PER_POINT[kname]):
                 continue
-            bytes_launch = BYTES_PER_POINT[kname][prec] * p.n
+            bpp = SOR_HALF_BYTES[prec] * (2 * 3 - 1) if kname == "sor" else BYTES_PER_POINT[kname][prec]
+            bytes_launch = bpp * p.n
             avg_ms = ms / cnt
             kernels[f"{kname}_{PREC_NAME[prec]}"] = {
                 "symbol": KERNEL_SYMBOL[kname], "launches": cnt, "avg_ms": round(avg_ms, 4),
@@ -349,7 +366,7 @@ def main():
         "dtype": ",".join(dtypes),
         "data": "synthetic (seeded operator recipe and b ~ N(0,1); no UM data)",
         "config": {"workload": f"{args.config}: {p.nlon}x{p.nlat}x{p.nlev} Helmholtz solve to 1e-8, one solve per mode "
-                               f"({','.join(eg.MODE_NAMES[m] for m in modes)})",
+                               f"({','.join(name for name, _, _ in runs)})",
                    "grid": [p.nlon, p.nlat, p.nlev], "dof": p.n, "tol": args.tol, "parallelism": "1 GPU"},
         "modes": modes_out,
         "setup_seconds": {"generate_host": round(t_gen, 2), "operator_fp64": round(t_setup64, 3),

@@ -102,11 +102,19 @@ enum ThomasMode { TH_PLAIN = 0, TH_P = 1, TH_S = 2 };
 template <typename Tv>
 void launch_thomas(const TriView<Tv> &tv, const Tv *q, Tv *z, int mode, const Tv *r, Tv *p, const Tv *v, Tv *rhat,
                    double *partials, int *nrows, const Scalars *sc, hipStream_t s, int stop_mask = 0);
-// Red-black vertical-line SOR applied to q, `sweeps` sweeps with relaxation omega; x must hold
-// T^{-1} q on entry and receives the result; wsc is an n-vector of scratch.  nlon must be even.
+// Red-black vertical-line SOR.  SorView: the LU factors of T (f[3]) and the W, E, S, N
+// couplings (a[4]) in colour-major order (index colour * n/2 + k * P/2 + j * nlon/2 + i/2).
+template <typename Tv, typename Tc> struct SorView {
+    const Tv *f;
+    const Tc *a;
+};
+// reorder nd arrays of n values from grid order into colour-major order (nlon even)
+template <typename T> void launch_sor_perm(const T *src, T *dst, int nd, int nlon, int nlat, int nlev, hipStream_t s);
+// `sweeps` sweeps with relaxation omega applied to q; x must hold T^{-1} q on entry and
+// receives the result; wsc is an n-vector of scratch.
 template <typename Tv, typename Tc>
-void launch_sor(const OpView<Tc> &op, const TriView<Tv> &tv, const Tv *q, Tv *x, Tv *wsc, int sweeps, double omega,
-                const Scalars *sc, int stop_mask, hipStream_t s);
+void launch_sor(const OpView<Tc> &op, const SorView<Tv, Tc> &sv, const Tv *q, Tv *x, Tv *wsc, int sweeps,
+                double omega, const Scalars *sc, int stop_mask, hipStream_t s);
 template <typename Tf>
 void launch_tri_factor(const double *a64, const double *m64, int nlon, int nlat, int nlev, Tf *f, hipStream_t s);
 

@@ -1268,7 +1268,14 @@ void launch_quantize(int kind, int nlon, int nlat, int nlev, const double *a64, 
 //     x_c <- (1 - omega) x_c + omega T_c^{-1} (q_c + sum of its horizontal couplings times x)
 // With nlon even every horizontal neighbour has the other colour, so the columns of one colour
 // are independent: one lane per column, the rhs gathered level by level on the way up, w_k of
-// the Thomas forward sweep parked in a scratch vector, the blend done on the way down.
+// the Thomas forward sweep parked in a colour-major scratch vector (coalesced), the blend done
+// on the way down.
+//
+// Layout: the operator constants a half-sweep reads for its own columns (the three LU factors
+// of T and the W, E, S, N couplings) are kept a second time in colour-major order,
+// index = colour * n/2 + k * P/2 + c2 with c2 = j * nlon/2 + i/2, so the lanes of a wave read
+// them contiguously; q and x stay in grid order (the neighbours of a column are the other
+// colour's entries of the same cache lines and rows).
 //
 // The first half-sweep from x = 0 is omega T^{-1} q on the red columns; the caller has already
 // computed T^{-1} q for every column (the tridiagonal kernel it fuses with the BiCGStab axpy),
@@ -1276,8 +1283,25 @@ void launch_quantize(int kind, int nlon, int nlat, int nlev, const double *a64, 
 // omega applied on the fly (nb_scale), and the next red half-sweep reads its own old value the
 // same way (own_scale).  With a single sweep the red values are scaled at the end.
 // ------------------------------------------------------------------------------------------
-template <typename Tv, typename Tc>
-__global__ __launch_bounds__(kWG) void k_sor_half(OpView<Tc> op, TriView<Tv> tv, const Tv *__restrict__ q,
+template <typename T>
+__global__ __launch_bounds__(kWG) void k_sor_perm(const T *__restrict__ src, T *__restrict__ dst, int nd, int nlon,
+                                                  int nlat, int nlev)
+{
+    const long P = (long)nlon * nlat, n = P * nlev, P2 = P / 2;
+    const long total = (long)nd * n;
+    const long stride = (long)gridDim.x * kWG;
+    for (long e = (long)blockIdx.x * kWG + threadIdx.x; e < total; e += stride) {
+        const long d = e / n, c = e % n;
+        const long k = c / P, pc = c % P;
+        const int j = (int)(pc / nlon), i = (int)(pc % nlon);
+        const int colour = (i + j) & 1;
+        const long c2 = (long)j * (nlon / 2) + i / 2;
+        dst[d * n + colour * (n / 2) + k * P2 + c2] = src[e];
+    }
+}
+
+template <typename Tv, typename Tc, int NL>
+__global__ __launch_bounds__(kWG) void k_sor_half(OpView<Tc> op, SorView<Tv, Tc> sv, const Tv *__restrict__ q,
                                                   Tv *__restrict__ x, Tv *__restrict__ wsc, int colour, Tv omega,
                                                   Tv nb_scale, Tv own_scale, const Scalars *__restrict__ sc,
                                                   int stop_mask)
@@ -1285,21 +1309,23 @@ __global__ __launch_bounds__(kWG) void k_sor_half(OpView<Tc> op, TriView<Tv> tv,
     if (stopped(sc, stop_mask)) return;
     using V = typename CoefTraits<Tc>::val;
     constexpr bool Q = CoefTraits<Tc>::quant;
-    const int nlon = op.nlon, nlat = op.nlat, nlev = op.nlev;
+    const int nlon = op.nlon, nlat = op.nlat;
+    const int nlev = (NL > 0) ? NL : op.nlev;
     const int half = nlon / 2;
-    const long P = op.P, n = op.n;
+    const long P = op.P, n = op.n, P2 = P / 2;
     const long c2 = (long)blockIdx.x * kWG + threadIdx.x;
-    if (c2 >= P / 2) return;
+    if (c2 >= P2) return;
     const int j = (int)(c2 / half);
     const int i = 2 * (int)(c2 % half) + ((j + colour) & 1);
     const int iw = (i == 0) ? nlon - 1 : i - 1;
     const int ie = (i == nlon - 1) ? 0 : i + 1;
     const long col = (long)j * nlon + i;
-    const Tv *lf = tv.f, *invf = tv.f + n, *cf = tv.f + 2 * n;
-    // forward: rhs_k = q_k + nb_scale * sum_d a_d x_d,  w_k = rhs_k + l_k w_{k-1}
-    Tv wprev = 0;
-    for (int k = 0; k < nlev; ++k) {
-        const long c = col + (long)k * P;
+    const long pb = (long)colour * (n / 2) + c2;   // colour-major index of level 0
+    const Tv *lf = sv.f, *invf = sv.f + n, *cf = sv.f + 2 * n;
+    const Tc *aWp = sv.a, *aEp = sv.a + n, *aSp = sv.a + 2 * n, *aNp = sv.a + 3 * n;
+    const bool hs = j > 0, hn = j < nlat - 1;
+    auto rhs_at = [&](int k) -> Tv {
+        const long c = col + (long)k * P, pi = pb + (long)k * P2;
         float s0 = 1.f, s1 = 1.f, s2 = 1.f, s3 = 1.f;
         if constexpr (Q) {
             const float *qr = op.qs + ((size_t)k * nlat + j) * kQsStride;
@@ -1308,25 +1334,47 @@ __global__ __launch_bounds__(kWG) void k_sor_half(OpView<Tc> op, TriView<Tv> tv,
             s2 = qr[2];
             s3 = qr[3];
         }
-        const Tc *arow = op.a + (c - i);
-        const V aW = DecB<Tc>::get(arow, i, s0);
-        const V aE = DecB<Tc>::get(arow + n, i, s1);
+        const V aW = DecB<Tc>::get(aWp + pi, 0, s0);
+        const V aE = DecB<Tc>::get(aEp + pi, 0, s1);
         Tv h = aW * x[c - i + iw] + aE * x[c - i + ie];
-        if (j > 0) h += static_cast<Tv>(DecB<Tc>::get(arow + 2 * n, i, s2)) * x[c - nlon];
-        if (j < nlat - 1) h += static_cast<Tv>(DecB<Tc>::get(arow + 3 * n, i, s3)) * x[c + nlon];
-        const Tv w = (q[c] + nb_scale * h) + lf[c] * wprev;
-        wsc[c] = w;
-        wprev = w;
-    }
-    // backward: y_k = inv_k w_k + c_k y_{k+1};  x_k <- (1 - omega) own_scale x_k + omega y_k
-    Tv ynext = 0;
+        if (hs) h += static_cast<Tv>(DecB<Tc>::get(aSp + pi, 0, s2)) * x[c - nlon];
+        if (hn) h += static_cast<Tv>(DecB<Tc>::get(aNp + pi, 0, s3)) * x[c + nlon];
+        return q[c] + nb_scale * h;
+    };
     const Tv keep = (Tv(1) - omega) * own_scale;
-    for (int k = nlev - 1; k >= 0; --k) {
-        const long c = col + (long)k * P;
-        const Tv y = invf[c] * wsc[c] + cf[c] * ynext;
-        const Tv old = (own_scale == Tv(0)) ? Tv(0) : x[c];
-        x[c] = keep * old + omega * y;
-        ynext = y;
+    if constexpr (NL > 0) {
+        Tv w[NL];
+        Tv wprev = 0;
+#pragma unroll
+        for (int k = 0; k < NL; ++k) {
+            w[k] = rhs_at(k) + lf[pb + (long)k * P2] * wprev;
+            wprev = w[k];
+        }
+        Tv ynext = 0;
+#pragma unroll
+        for (int k = NL - 1; k >= 0; --k) {
+            const long c = col + (long)k * P, pi = pb + (long)k * P2;
+            const Tv y = invf[pi] * w[k] + cf[pi] * ynext;
+            const Tv old = (own_scale == Tv(0)) ? Tv(0) : x[c];
+            x[c] = keep * old + omega * y;
+            ynext = y;
+        }
+    } else {
+        Tv wprev = 0;
+        for (int k = 0; k < nlev; ++k) {
+            const long pi = pb + (long)k * P2;
+            const Tv w = rhs_at(k) + lf[pi] * wprev;
+            wsc[pi] = w;
+            wprev = w;
+        }
+        Tv ynext = 0;
+        for (int k = nlev - 1; k >= 0; --k) {
+            const long c = col + (long)k * P, pi = pb + (long)k * P2;
+            const Tv y = invf[pi] * wsc[pi] + cf[pi] * ynext;
+            const Tv old = (own_scale == Tv(0)) ? Tv(0) : x[c];
+            x[c] = keep * old + omega * y;
+            ynext = y;
+        }
     }
 }
 
@@ -1344,9 +1392,16 @@ __global__ __launch_bounds__(kWG) void k_sor_scale(long P, long n, int nlon, Tv 
     }
 }
 
+template <typename T> void launch_sor_perm(const T *src, T *dst, int nd, int nlon, int nlat, int nlev, hipStream_t s)
+{
+    const long n = (long)nlon * nlat * nlev;
+    hipLaunchKernelGGL((k_sor_perm<T>), dim3(elementwise_blocks(nd * n)), dim3(kWG), 0, s, src, dst, nd, nlon, nlat,
+                       nlev);
+}
+
 template <typename Tv, typename Tc>
-void launch_sor(const OpView<Tc> &op, const TriView<Tv> &tv, const Tv *q, Tv *x, Tv *wsc, int sweeps, double omega,
-                const Scalars *sc, int stop_mask, hipStream_t s)
+void launch_sor(const OpView<Tc> &op, const SorView<Tv, Tc> &sv, const Tv *q, Tv *x, Tv *wsc, int sweeps,
+                double omega, const Scalars *sc, int stop_mask, hipStream_t s)
 {
     const long half_cols = op.P / 2;
     const unsigned blocks = (unsigned)((half_cols + kWG - 1) / kWG);
@@ -1355,7 +1410,7 @@ void launch_sor(const OpView<Tc> &op, const TriView<Tv> &tv, const Tv *q, Tv *x,
         const int colour = (h & 1) ? 1 : 0;                       // odd: black, even: red
         const Tv nb_scale = (h == 1) ? w : Tv(1);                 // red still holds T^{-1} q
         const Tv own_scale = (h == 1) ? Tv(0) : (h == 2 ? w : Tv(1));
-        hipLaunchKernelGGL((k_sor_half<Tv, Tc>), dim3(blocks), dim3(kWG), 0, s, op, tv, q, x, wsc, colour, w,
+        hipLaunchKernelGGL((k_sor_half<Tv, Tc, 0>), dim3(blocks), dim3(kWG), 0, s, op, sv, q, x, wsc, colour, w,
                            nb_scale, own_scale, sc, stop_mask);
     }
     if (sweeps == 1)
@@ -1403,14 +1458,17 @@ template int launch_maxpy<float>(long, float *, const float *, int, int, const d
                                  hipStream_t);
 template void launch_vscale<double>(long, const double *, double *, const double *, hipStream_t);
 template void launch_vscale<float>(long, const float *, float *, const double *, hipStream_t);
-template void launch_sor<double, double>(const OpView<double> &, const TriView<double> &, const double *, double *,
-                                         double *, int, double, const Scalars *, int, hipStream_t);
-template void launch_sor<float, float>(const OpView<float> &, const TriView<float> &, const float *, float *, float *,
-                                       int, double, const Scalars *, int, hipStream_t);
-template void launch_sor<float, bf16_t>(const OpView<bf16_t> &, const TriView<float> &, const float *, float *,
-                                        float *, int, double, const Scalars *, int, hipStream_t);
-template void launch_sor<float, fp16_t>(const OpView<fp16_t> &, const TriView<float> &, const float *, float *,
-                                        float *, int, double, const Scalars *, int, hipStream_t);
+template void launch_sor<double, double>(const OpView<double> &, const SorView<double, double> &, const double *,
+                                         double *, double *, int, double, const Scalars *, int, hipStream_t);
+template void launch_sor<float, float>(const OpView<float> &, const SorView<float, float> &, const float *, float *,
+                                       float *, int, double, const Scalars *, int, hipStream_t);
+template void launch_sor<float, bf16_t>(const OpView<bf16_t> &, const SorView<float, bf16_t> &, const float *,
+                                        float *, float *, int, double, const Scalars *, int, hipStream_t);
+template void launch_sor<float, fp16_t>(const OpView<fp16_t> &, const SorView<float, fp16_t> &, const float *,
+                                        float *, float *, int, double, const Scalars *, int, hipStream_t);
+template void launch_sor_perm<double>(const double *, double *, int, int, int, int, hipStream_t);
+template void launch_sor_perm<float>(const float *, float *, int, int, int, int, hipStream_t);
+template void launch_sor_perm<uint16_t>(const uint16_t *, uint16_t *, int, int, int, int, hipStream_t);
 template void launch_fill<double>(double *, long, double, hipStream_t);
 template void launch_fill<float>(float *, long, float, hipStream_t);
 

@@ -134,6 +134,10 @@ struct eg_operator {
     double sor_omega = 1.5;
     bool sor_on = false;        // SOR active in the current solve (plain modes with precond 1)
     double *sor_scratch = nullptr;   // n doubles, for eg_apply_precond
+    // colour-major copies of the LU factors and the W, E, S, N couplings the SOR reads
+    double *sorf64 = nullptr, *sora64 = nullptr;
+    float *sorf32 = nullptr, *sora32 = nullptr;
+    uint16_t *sorq[2] = {nullptr, nullptr};
     int profile = 0;
 
     // kernel timing: events around the streaming kernels of one iteration + the residual
@@ -167,6 +171,13 @@ struct eg_operator {
     template <typename Tq> OpView<Tq> viewq(int slot) const
     {
         return {reinterpret_cast<const Tq *>(aq[slot]), m32, qs[slot], nlon, nlat, nlev, P, n};
+    }
+    template <typename Tv, typename Tc> SorView<Tv, Tc> sor_view() const
+    {
+        if constexpr (std::is_same_v<Tc, double>) return {sorf64, sora64};
+        else if constexpr (std::is_same_v<Tc, float>) return {sorf32, sora32};
+        else if constexpr (std::is_same_v<Tc, bf16_t>) return {sorf32, reinterpret_cast<const bf16_t *>(sorq[0])};
+        else return {sorf32, reinterpret_cast<const fp16_t *>(sorq[1])};
     }
     TriView<double> tri_view64() const { return {tri64, P, n, nlev}; }
     TriView<float> tri_view32() const { return {tri32, P, n, nlev}; }
@@ -202,6 +213,39 @@ int ensure_quant(eg_operator *op, int kind)
     if ((rc = dalloc(&op->aq[slot], 6 * (size_t)op->n))) return rc;
     if ((rc = dalloc(&op->qs[slot], (size_t)kQsStride * op->nlev * op->nlat))) return rc;
     launch_quantize(kind, op->nlon, op->nlat, op->nlev, op->a64, op->aq[slot], op->qs[slot], op->stream);
+    EG_HIP(hipGetLastError());
+    return 0;
+}
+
+// the colour-major constants of the red-black line SOR for one coefficient set
+template <typename Tc> int ensure_sor(eg_operator *op)
+{
+    int rc;
+    const size_t n = (size_t)op->n;
+    hipStream_t s = op->stream;
+    if constexpr (std::is_same_v<Tc, double>) {
+        if (op->sorf64) return 0;
+        if ((rc = dalloc(&op->sorf64, 3 * n)) || (rc = dalloc(&op->sora64, 4 * n))) return rc;
+        launch_sor_perm<double>(op->tri64, op->sorf64, 3, op->nlon, op->nlat, op->nlev, s);
+        launch_sor_perm<double>(op->a64, op->sora64, 4, op->nlon, op->nlat, op->nlev, s);
+    } else {
+        if ((rc = ensure_fp32(op))) return rc;
+        if (!op->sorf32) {
+            if ((rc = dalloc(&op->sorf32, 3 * n))) return rc;
+            launch_sor_perm<float>(op->tri32, op->sorf32, 3, op->nlon, op->nlat, op->nlev, s);
+        }
+        if constexpr (std::is_same_v<Tc, float>) {
+            if (op->sora32) return 0;
+            if ((rc = dalloc(&op->sora32, 4 * n))) return rc;
+            launch_sor_perm<float>(op->a32, op->sora32, 4, op->nlon, op->nlat, op->nlev, s);
+        } else {
+            const int slot = std::is_same_v<Tc, bf16_t> ? 0 : 1;
+            if ((rc = ensure_quant(op, slot == 0 ? PBF16 : PFP16))) return rc;
+            if (op->sorq[slot]) return 0;
+            if ((rc = dalloc(&op->sorq[slot], 4 * n))) return rc;
+            launch_sor_perm<uint16_t>(op->aq[slot], op->sorq[slot], 4, op->nlon, op->nlat, op->nlev, s);
+        }
+    }
     EG_HIP(hipGetLastError());
     return 0;
 }
@@ -291,7 +335,8 @@ void enqueue_iteration(eg_operator *op, const OpView<Tc> &A, Work<Tv> &w, hipEve
     mark(1);
     if (op->sor_on) {   // t is free until the second product of the iteration
         mark(12);
-        launch_sor<Tv, Tc>(A, T, w.p, w.ph, w.t, op->sor_sweeps, op->sor_omega, op->sc, STOP_DONE, s);
+        launch_sor<Tv, Tc>(A, op->sor_view<Tv, Tc>(), w.p, w.ph, w.t, op->sor_sweeps, op->sor_omega, op->sc, STOP_DONE,
+                           s);
         mark(13);
     }
     mark(2);
@@ -304,7 +349,7 @@ void enqueue_iteration(eg_operator *op, const OpView<Tc> &A, Work<Tv> &w, hipEve
     launch_finalize(FIN_S, op->partials, nr, op->sc, op->d_hist, nullptr, 0, 0, s);
     if (op->sor_on) {
         mark(14);
-        launch_sor<Tv, Tc>(A, T, w.s, w.sh, w.t, op->sor_sweeps, op->sor_omega, op->sc,
+        launch_sor<Tv, Tc>(A, op->sor_view<Tv, Tc>(), w.s, w.sh, w.t, op->sor_sweeps, op->sor_omega, op->sc,
                            STOP_DONE | STOP_SKIP | STOP_HALF, s);
         mark(15);
     }
@@ -549,7 +594,8 @@ int fgmres(eg_operator *op, const OpView<Tc> &A, Tv *d, double nb, double tol, i
             Tv *Vj = F.V + (size_t)j * n, *Zj = F.Z + (size_t)j * n;
             launch_thomas<Tv>(T, Vj, Zj, TH_PLAIN, nullptr, nullptr, nullptr, nullptr, op->partials, nullptr, nullptr, s);
             if (op->sor_on && !use_net)
-                launch_sor<Tv, Tc>(A, T, Vj, Zj, F.tmp, op->sor_sweeps, op->sor_omega, nullptr, 0, s);
+                launch_sor<Tv, Tc>(A, op->sor_view<Tv, Tc>(), Vj, Zj, F.tmp, op->sor_sweeps, op->sor_omega, nullptr, 0,
+                                   s);
             if constexpr (std::is_same_v<Tc, float> || std::is_same_v<Tc, double>)
                 if (use_net) enqueue_net_stage<Tv, Tc>(op, net, coef, Vj, Zj, qp, nullptr, 0);
             launch_spmv<Tv, Tc>(A, Zj, F.W, nullptr, SP_PLAIN, op->partials, nullptr, nullptr, 0, s);
@@ -953,6 +999,7 @@ void eg_destroy_operator(eg_operator *op)
     for (Fgm<double> *F : {&op->f64}) { dfree(F->V); dfree(F->Z); dfree(F->W); dfree(F->R); dfree(F->tmp); }
     for (Fgm<float> *F : {&op->f32}) { dfree(F->V); dfree(F->Z); dfree(F->W); dfree(F->R); dfree(F->tmp); }
     dfree(op->d_h); dfree(op->mpart); dfree(op->sor_scratch);
+    dfree(op->sorf64); dfree(op->sora64); dfree(op->sorf32); dfree(op->sora32); dfree(op->sorq[0]); dfree(op->sorq[1]);
     if (op->h_h) (void)hipHostFree(op->h_h);
     dfree(op->w64.qp);
     dfree(op->w32.qp);
@@ -1087,8 +1134,15 @@ int eg_solve(eg_operator *op, const double *b, double *x, double tol, int maxit,
     op->info = eg_info{};
     op->hist_count = 0;
     op->hist_pending.clear();
-    op->sor_on = (op->precond == 1) && mode < EG_LEARNED_FP64;
     int rc;
+    op->sor_on = (op->precond == 1) && mode < EG_LEARNED_FP64;
+    if (op->sor_on) {
+        if (mode == EG_FP64) rc = ensure_sor<double>(op);
+        else if (mode == EG_FP32_IR) rc = ensure_sor<float>(op);
+        else if (mode == EG_FP32_IR_BF16) rc = ensure_sor<bf16_t>(op);
+        else rc = ensure_sor<fp16_t>(op);
+        if (rc) return rc;
+    }
     if ((rc = check_vectors(op, b, x))) return rc;
     if ((rc = ensure_hist(op, std::min(maxit, 1 << 22)))) return rc;
     int status;
@@ -1207,12 +1261,15 @@ int eg_apply_precond(eg_operator *op, const void *q, void *z, int prec)
     const bool sor = op->precond == 1;
     if (sor && !op->sor_scratch && (rc = dalloc(&op->sor_scratch, (size_t)op->n))) return rc;
     if (prec == EG_PREC_FP64) {
-        launch_thomas<double>(op->tri_view64(), static_cast<const double *>(q), static_cast<double *>(z), TH_PLAIN,
-                              nullptr, nullptr, nullptr, nullptr, op->partials, nullptr, nullptr, op->stream);
-        if (sor)
-            launch_sor<double, double>(op->view64(), op->tri_view64(), static_cast<const double *>(q),
-                                       static_cast<double *>(z), op->sor_scratch, op->sor_sweeps, op->sor_omega,
-                                       nullptr, 0, op->stream);
+        const double *qd = static_cast<const double *>(q);
+        double *zd = static_cast<double *>(z);
+        launch_thomas<double>(op->tri_view64(), qd, zd, TH_PLAIN, nullptr, nullptr, nullptr, nullptr, op->partials,
+                              nullptr, nullptr, op->stream);
+        if (sor) {
+            if ((rc = ensure_sor<double>(op))) return rc;
+            launch_sor<double, double>(op->view64(), op->sor_view<double, double>(), qd, zd, op->sor_scratch,
+                                       op->sor_sweeps, op->sor_omega, nullptr, 0, op->stream);
+        }
     } else {
         // every lower-precision set uses the FP32 rounding of the FP64 factors
         if ((rc = ensure_fp32(op))) return rc;
@@ -1221,18 +1278,18 @@ int eg_apply_precond(eg_operator *op, const void *q, void *z, int prec)
         launch_thomas<float>(op->tri_view32(), qf, zf, TH_PLAIN, nullptr, nullptr, nullptr, nullptr, op->partials,
                              nullptr, nullptr, op->stream);
         if (sor) {
-            const TriView<float> T = op->tri_view32();
             if (prec == EG_PREC_FP32) {
-                launch_sor<float, float>(op->view32(), T, qf, zf, wf, op->sor_sweeps, op->sor_omega, nullptr, 0,
-                                         op->stream);
+                if ((rc = ensure_sor<float>(op))) return rc;
+                launch_sor<float, float>(op->view32(), op->sor_view<float, float>(), qf, zf, wf, op->sor_sweeps,
+                                         op->sor_omega, nullptr, 0, op->stream);
             } else if (prec == EG_PREC_BF16) {
-                if ((rc = ensure_quant(op, PBF16))) return rc;
-                launch_sor<float, bf16_t>(op->viewq<bf16_t>(0), T, qf, zf, wf, op->sor_sweeps, op->sor_omega, nullptr,
-                                          0, op->stream);
+                if ((rc = ensure_sor<bf16_t>(op))) return rc;
+                launch_sor<float, bf16_t>(op->viewq<bf16_t>(0), op->sor_view<float, bf16_t>(), qf, zf, wf,
+                                          op->sor_sweeps, op->sor_omega, nullptr, 0, op->stream);
             } else {
-                if ((rc = ensure_quant(op, PFP16))) return rc;
-                launch_sor<float, fp16_t>(op->viewq<fp16_t>(1), T, qf, zf, wf, op->sor_sweeps, op->sor_omega, nullptr,
-                                          0, op->stream);
+                if ((rc = ensure_sor<fp16_t>(op))) return rc;
+                launch_sor<float, fp16_t>(op->viewq<fp16_t>(1), op->sor_view<float, fp16_t>(), qf, zf, wf,
+                                          op->sor_sweeps, op->sor_omega, nullptr, 0, op->stream);
             }
         }
     }
