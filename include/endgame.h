@@ -48,7 +48,11 @@ enum eg_mode {
     EG_FP32_IR_BF16 = 2,    /* as EG_FP32_IR, inner off-diagonal couplings stored as BF16        */
     EG_FP32_IR_FP16 = 3,    /* as EG_FP32_IR, inner off-diagonal couplings stored as FP16        */
     EG_LEARNED_FP64 = 4,    /* flexible BiCGStab in FP64 with the learned preconditioner         */
-    EG_LEARNED_FP32_IR = 5  /* FP64 refinement around flexible FP32 BiCGStab + learned precond.  */
+    EG_LEARNED_FP32_IR = 5, /* FP64 refinement around flexible FP32 BiCGStab + learned precond.  */
+    EG_FP32_MP = 6          /* the paper's mixed-precision BiCGStab (Sec. 3-4): FP32 vectors and
+                               coefficients, FP64 solution updated every iteration, FP64 global
+                               sums, restart every restart_every iterations (150 if 0); no
+                               refinement, so it stalls below about 1e-6 (EG_STALLED)            */
 };
 
 /* Outcomes (>= 0) and errors (< 0). */

@@ -15,9 +15,9 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libendgame.so")
 
 # enum eg_mode
-FP64, FP32_IR, FP32_IR_BF16, FP32_IR_FP16, LEARNED_FP64, LEARNED_FP32_IR = range(6)
+FP64, FP32_IR, FP32_IR_BF16, FP32_IR_FP16, LEARNED_FP64, LEARNED_FP32_IR, FP32_MP = range(7)
 MODE_NAMES = {FP64: "fp64", FP32_IR: "fp32_ir", FP32_IR_BF16: "fp32_ir_bf16", FP32_IR_FP16: "fp32_ir_fp16",
-              LEARNED_FP64: "learned_fp64", LEARNED_FP32_IR: "learned_fp32_ir"}
+              LEARNED_FP64: "learned_fp64", LEARNED_FP32_IR: "learned_fp32_ir", FP32_MP: "fp32_mp"}
 # enum eg_prec
 PREC_FP64, PREC_FP32, PREC_BF16, PREC_FP16 = range(4)
 # enum eg_status

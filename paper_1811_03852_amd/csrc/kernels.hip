@@ -672,12 +672,54 @@ __global__ __launch_bounds__(kWG) void k_update(long n, Tv *__restrict__ x, cons
     block_sum_store<2>(acc, partials + (long)blockIdx.x * kPartialCols);
 }
 
+// The paper's mixed-precision update (Sec. 3 and Sec. 4): the solution stays FP64 and is
+// updated every iteration from the FP32 search directions with the FP64 scalars; the
+// residual recurrence stays FP32.  Same modes as k_update (full step, half step, half step
+// after a t = 0 breakdown).
+__global__ __launch_bounds__(kWG) void k_update_mp(long n, double *__restrict__ x, const float *__restrict__ ph,
+                                                   const float *__restrict__ sh, const float *__restrict__ s,
+                                                   const float *__restrict__ t, float *__restrict__ r,
+                                                   const float *__restrict__ rhat, double *__restrict__ partials,
+                                                   const Scalars *__restrict__ sc)
+{
+    if (sc->done || sc->skip) return;
+    const double alpha = sc->alpha, omega = sc->omega;
+    const float omega32 = static_cast<float>(omega);
+    const int mode = sc->half ? 1 : (sc->wbd ? 2 : 0);
+    double acc[2] = {0.0, 0.0};
+    const long stride = (long)gridDim.x * kWG;
+    for (long i = (long)blockIdx.x * kWG + threadIdx.x; i < n; i += stride) {
+        double xi = x[i] + alpha * static_cast<double>(ph[i]);
+        if (mode == 2) {
+            const float si = s[i];
+            r[i] = si;
+            acc[1] += static_cast<double>(si) * static_cast<double>(si);
+        } else if (mode == 0) {
+            xi += omega * static_cast<double>(sh[i]);
+            const float ri = s[i] - omega32 * t[i];
+            r[i] = ri;
+            acc[0] += static_cast<double>(rhat[i]) * static_cast<double>(ri);
+            acc[1] += static_cast<double>(ri) * static_cast<double>(ri);
+        }
+        x[i] = xi;
+    }
+    block_sum_store<2>(acc, partials + (long)blockIdx.x * kPartialCols);
+}
+
 static int elementwise_blocks(long n)
 {
     long nb = (n + kWG * 4 - 1) / (kWG * 4);
     if (nb > 8192) nb = 8192;
     if (nb < 1) nb = 1;
     return (int)nb;
+}
+
+void launch_update_mp(long n, double *x, const float *ph, const float *sh, const float *s, const float *t, float *r,
+                      const float *rhat, double *partials, int *nrows, const Scalars *sc, hipStream_t stream)
+{
+    const int nb = elementwise_blocks(n);
+    hipLaunchKernelGGL(k_update_mp, dim3(nb), dim3(kWG), 0, stream, n, x, ph, sh, s, t, r, rhat, partials, sc);
+    if (nrows) *nrows = nb;
 }
 
 template <typename Tv>

@@ -134,6 +134,8 @@ struct eg_operator {
     double sor_omega = 1.5;
     bool sor_on = false;        // SOR active in the current solve (plain modes with precond 1)
     double *sor_scratch = nullptr;   // n doubles, for eg_apply_precond
+    double *mp_x = nullptr;     // EG_FP32_MP: the FP64 solution the FP32 iteration updates
+    bool mp_active = false;
     // colour-major copies of the LU factors and the W, E, S, N couplings the SOR reads
     double *sorf64 = nullptr, *sora64 = nullptr;
     float *sorf32 = nullptr, *sora32 = nullptr;
@@ -358,7 +360,14 @@ void enqueue_iteration(eg_operator *op, const OpView<Tc> &A, Work<Tv> &w, hipEve
     mark(7);
     launch_finalize(FIN_OMEGA, op->partials, nr, op->sc, op->d_hist, nullptr, 0, 0, s);
     mark(8);
-    launch_update<Tv>(op->n, w.x, w.ph, w.sh, w.s, w.t, w.r, w.rh, op->partials, &nr, op->sc, s);
+    if constexpr (std::is_same_v<Tv, float>) {
+        if (op->mp_active)
+            launch_update_mp(op->n, op->mp_x, w.ph, w.sh, w.s, w.t, w.r, w.rh, op->partials, &nr, op->sc, s);
+        else
+            launch_update<Tv>(op->n, w.x, w.ph, w.sh, w.s, w.t, w.r, w.rh, op->partials, &nr, op->sc, s);
+    } else {
+        launch_update<Tv>(op->n, w.x, w.ph, w.sh, w.s, w.t, w.r, w.rh, op->partials, &nr, op->sc, s);
+    }
     mark(9);
     launch_finalize(FIN_END, op->partials, nr, op->sc, op->d_hist, nullptr, 0, 0, s);
 }
@@ -890,6 +899,74 @@ int solve_ir(eg_operator *op, const OpView<Tc> &A32, const double *b, double *x,
     return status;
 }
 
+// ---- the paper's mixed-precision BiCGStab (Sec. 3 and Sec. 4) ------------------------------
+// FP32 vectors, coefficients and preconditioner; the solution x in FP64, updated every
+// iteration; FP64 global sums; a restart from the true residual every restart_every
+// iterations (150, the paper's value, when the option is 0).  No refinement: one Krylov run on
+// A x = b, halted on the recursive residual and then checked against the FP64 true residual
+// (up to three residual-gap restarts, then EG_STALLED: the FP32 recurrence has hit its floor).
+int solve_mp(eg_operator *op, const double *b, double *x, double tol, int maxit)
+{
+    int rc;
+    if ((rc = ensure_fp32(op)) || (rc = ensure_work(op, op->w32))) return rc;
+    if (!op->mp_x && (rc = dalloc(&op->mp_x, (size_t)op->n))) return rc;
+    Work<float> &w = op->w32;
+    hipStream_t s = op->stream;
+    const OpView<double> A64 = op->view64();
+    const OpView<float> A32 = op->view32();
+    EG_HIP(hipMemcpyAsync(op->mp_x, x, op->n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    if ((rc = put_run_params(op, tol, maxit, 0, op->restart_every > 0 ? op->restart_every : 150))) return rc;
+    int nr = 0;
+    // r = b - A x in FP64, stored in FP32; partials ||r64||^2, ||b||^2, ||r32||^2
+    launch_residual<float>(A64, b, op->mp_x, w.r, op->partials, &nr, s);
+    launch_finalize(FIN_INIT, op->partials, nr, op->sc, op->d_hist, nullptr, 2, 1, s);
+    EG_HIP(hipGetLastError());
+    if ((rc = sync_scalars(op))) return rc;
+    if (op->h_sc->nb2 == 0.0) {
+        launch_fill<double>(x, op->n, 0.0, s);
+        EG_HIP(hipStreamSynchronize(s));
+        op->info.true_rel_residual = 0.0;
+        return EG_CONVERGED;
+    }
+    struct Guard {
+        eg_operator *op;
+        ~Guard() { op->mp_active = false; }
+    } guard{op};
+    op->mp_active = true;
+    int gap = 0, status = EG_CONVERGED;
+    for (;;) {
+        if ((rc = krylov_run<float, float>(op, A32, w))) return rc;
+        const Scalars &h = *op->h_sc;
+        if (h.status == 4) {   // periodic restart from the true residual
+            launch_residual<float>(A64, b, op->mp_x, w.r, op->partials, &nr, s);
+            launch_finalize(FIN_TRUE, op->partials, nr, op->sc, nullptr, nullptr, 2, 1, s);
+            EG_HIP(hipGetLastError());
+            continue;
+        }
+        if (h.status == 1) { status = EG_MAXIT; break; }
+        if (h.status == 2) { status = EG_BREAKDOWN; break; }
+        launch_residual<float>(A64, b, op->mp_x, w.r, op->partials, &nr, s);
+        launch_finalize(FIN_SUM, op->partials, nr, op->sc, nullptr, op->d_out, 0, 0, s);
+        EG_HIP(hipMemcpyAsync(op->h_out, op->d_out, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
+        EG_HIP(hipStreamSynchronize(s));
+        const double rel = std::sqrt(op->h_out[0] / op->h_out[1]);
+        if (rel <= tol) { status = EG_CONVERGED; break; }
+        if (gap >= 3 || h.iter >= h.maxit) { status = (h.iter >= h.maxit) ? EG_MAXIT : EG_STALLED; break; }
+        ++gap;
+        launch_finalize(FIN_TRUE, op->partials, nr, op->sc, nullptr, nullptr, 2, 1, s);
+        EG_HIP(hipGetLastError());
+    }
+    const Scalars &h = *op->h_sc;
+    op->info.iterations = h.iter;
+    op->info.restarts = h.restarts;
+    op->hist_count = h.iter;
+    EG_HIP(hipMemcpyAsync(x, op->mp_x, op->n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    int n2;
+    if ((rc = true_residual<double>(op, b, x, static_cast<double *>(nullptr), &n2))) return rc;
+    op->info.true_rel_residual = std::sqrt(op->h_out[0] / op->h_out[1]);
+    return status;
+}
+
 // ---- network training pieces ---------------------------------------------------------------
 uint64_t splitmix64(uint64_t &s)
 {
@@ -998,7 +1075,7 @@ void eg_destroy_operator(eg_operator *op)
     dfree(op->harvest_x);
     for (Fgm<double> *F : {&op->f64}) { dfree(F->V); dfree(F->Z); dfree(F->W); dfree(F->R); dfree(F->tmp); }
     for (Fgm<float> *F : {&op->f32}) { dfree(F->V); dfree(F->Z); dfree(F->W); dfree(F->R); dfree(F->tmp); }
-    dfree(op->d_h); dfree(op->mpart); dfree(op->sor_scratch);
+    dfree(op->d_h); dfree(op->mpart); dfree(op->sor_scratch); dfree(op->mp_x);
     dfree(op->sorf64); dfree(op->sora64); dfree(op->sorf32); dfree(op->sora32); dfree(op->sorq[0]); dfree(op->sorq[1]);
     if (op->h_h) (void)hipHostFree(op->h_h);
     dfree(op->w64.qp);
@@ -1127,18 +1204,19 @@ int eg_solve(eg_operator *op, const double *b, double *x, double tol, int maxit,
 {
     if (!op || !b || !x) return fail(EG_EINVAL, "NULL argument");
     if (!(tol > 0.0) || maxit < 1) return fail(EG_EINVAL, "need tol > 0 and maxit >= 1");
-    if (mode < EG_FP64 || mode > EG_LEARNED_FP32_IR) return fail(EG_EINVAL, "unknown mode");
-    if (mode >= EG_LEARNED_FP64 && !op->net)
+    if (mode < EG_FP64 || mode > EG_FP32_MP) return fail(EG_EINVAL, "unknown mode");
+    const bool learned = (mode == EG_LEARNED_FP64 || mode == EG_LEARNED_FP32_IR);
+    if (learned && !op->net)
         return fail(EG_ENOPC, "no learned preconditioner is attached to this operator (eg_attach_learned_pc)");
     const auto t0 = std::chrono::steady_clock::now();
     op->info = eg_info{};
     op->hist_count = 0;
     op->hist_pending.clear();
     int rc;
-    op->sor_on = (op->precond == 1) && mode < EG_LEARNED_FP64;
+    op->sor_on = (op->precond == 1) && !learned;
     if (op->sor_on) {
         if (mode == EG_FP64) rc = ensure_sor<double>(op);
-        else if (mode == EG_FP32_IR) rc = ensure_sor<float>(op);
+        else if (mode == EG_FP32_IR || mode == EG_FP32_MP) rc = ensure_sor<float>(op);
         else if (mode == EG_FP32_IR_BF16) rc = ensure_sor<bf16_t>(op);
         else rc = ensure_sor<fp16_t>(op);
         if (rc) return rc;
@@ -1164,6 +1242,9 @@ int eg_solve(eg_operator *op, const double *b, double *x, double tol, int maxit,
         break;
     case EG_LEARNED_FP64:
         status = solve_fp64(op, b, x, tol, maxit, op->net);
+        break;
+    case EG_FP32_MP:
+        status = solve_mp(op, b, x, tol, maxit);
         break;
     default:
         if ((rc = ensure_fp32(op))) return rc;

@@ -226,3 +226,38 @@ def test_fgmres_options_are_checked(eg, c1):
         for key, bad in (("method", 2), ("learned_method", -1), ("gmres_m", 0), ("gmres_m", 65)):
             with pytest.raises(eg.EndgameError):
                 op.set_option(key, bad)
+
+
+@pytest.mark.parametrize("tol", [1e-4, 1e-6])
+def test_paper_mixed_precision_mode(eg, oracle_mod, c1, tol):
+    """The paper's MP BiCGStab (FP32 vectors, FP64 solution and sums, no refinement) at the
+    tolerances the paper uses: converges with about the FP64 iteration count."""
+    import torch
+    p, coef, b, x_ref, _ = c1
+    with eg.Operator(dev(coef)) as op:
+        x = torch.zeros(p.n, dtype=torch.float64, device="cuda")
+        info = op.solve(dev(b), x, tol, 5000, eg.FP32_MP)
+        i64 = op.solve(dev(b), torch.zeros_like(x), tol, 5000, eg.FP64)
+    xh = host(x)
+    rel = _true_rel(oracle_mod, coef, b, xh)
+    err = np.linalg.norm(xh - x_ref) / np.linalg.norm(x_ref)
+    print(f"MP tol {tol:g}: {info.iterations} its (FP64 {i64.iterations}), true R {rel:.2e}, error {err:.2e}")
+    assert info.status == eg.CONVERGED and rel <= tol and info.outer_steps == 0
+    assert abs(info.iterations - i64.iterations) <= max(3, i64.iterations // 5)
+    assert err <= 1e4 * tol
+
+
+def test_paper_mixed_precision_restarts_every_150(eg, oracle_mod):
+    """Shift 1e-6 needs a few hundred iterations: the mode restarts from the true residual
+    every 150 iterations and still converges."""
+    import torch
+    p = synth.Problem(96, 72, 20, seed=5, shift=1e-6)
+    coef = synth.make_coeffs(p)
+    b = synth.make_rhs(p).ravel()
+    with eg.Operator(dev(coef)) as op:
+        x = torch.zeros(p.n, dtype=torch.float64, device="cuda")
+        info = op.solve(dev(b), x, 1e-5, 5000, eg.FP32_MP)
+    rel = _true_rel(oracle_mod, coef, b, host(x))
+    print(f"MP shift 1e-6: {info.iterations} its, {info.restarts} restarts, true R {rel:.2e}")
+    assert info.status == eg.CONVERGED and rel <= 1e-5
+    assert info.iterations > 150 and info.restarts >= info.iterations // 150
