@@ -170,6 +170,45 @@ def learned_comparison(eg, torch, net, cfg_name, tol):
     return out
 
 
+def paper_study(eg, torch, op, b):
+    """The paper's own measurement on its grid (Table 1, Sec. 4): BiCGStab with tri_sor in FP64
+    (DP) and in the paper's mixed precision (MP: FP32 vectors and coefficients, FP64 solution
+    and global sums, restart every 150 iterations), to R = 1e-3 and 1e-4, and the iteration
+    counts of both as the tolerance tightens (the question of Fig. 1 and Fig. 3)."""
+    op.set_option("profile", 0)
+    op.set_option("precond", 1)
+    op.set_option("sor_sweeps", 3)
+    op.set_option("sor_omega", 1.5)
+    x = torch.zeros_like(b)
+    sweep = {}
+    for tol in (1e-3, 1e-4, 1e-5, 1e-6, 1e-7, 1e-8):
+        row = {}
+        for name, mode in (("dp", eg.FP64), ("mp", eg.FP32_MP)):
+            x.zero_()
+            op.solve(b, x, tol, 2000, mode)
+            x.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            info = op.solve(b, x, tol, 2000, mode)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            row[name] = {"seconds": round(dt, 4), "iterations": info.iterations, "status": info.status,
+                         "true_rel_residual": info.true_rel_residual,
+                         "ms_per_iteration": round(1e3 * dt / max(info.iterations, 1), 3)}
+        sweep[f"{tol:g}"] = row
+        log(f"paper study tol {tol:g}: {row}")
+    op.set_option("precond", 0)
+    table1 = {}
+    for tol in ("0.001", "0.0001"):
+        r = sweep[tol]
+        table1[tol] = {"dp_seconds": r["dp"]["seconds"], "mp_seconds": r["mp"]["seconds"],
+                       "dp_iterations": r["dp"]["iterations"], "mp_iterations": r["mp"]["iterations"],
+                       "mp_over_dp_per_iteration": round(r["mp"]["ms_per_iteration"] / r["dp"]["ms_per_iteration"], 3),
+                       "paper_mp_over_dp_per_iteration": {"0.001": 0.585, "0.0001": 0.573}[tol]}
+    return {"preconditioner": "tri_sor as red-black line SOR, 3 sweeps, omega 1.5", "table1": table1,
+            "tolerance_sweep": sweep}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -184,6 +223,7 @@ def main():
     ap.add_argument("--train-ops", type=int, default=16)
     ap.add_argument("--train-vecs", type=int, default=20)
     ap.add_argument("--train-epochs", type=int, default=20)
+    ap.add_argument("--no-paper-study", action="store_true", help="skip the DP vs MP comparison of the paper's Table 1")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="run four iterations of each mode and a device copy of known size (for counter runs) and exit")
     args = ap.parse_args()
@@ -335,6 +375,7 @@ def main():
                         "outer_steps": d["outer_steps"], "status": d["status"],
                         "true_rel_residual": d["true_rel_residual"]}
     fp64_iters = per_mode.get("fp64", {}).get("iterations")
+    paper = None if args.no_paper_study else paper_study(eg, torch, op, b)
     op.close()
     del x, b
     torch.cuda.empty_cache()
@@ -375,6 +416,7 @@ def main():
         "kernels": kernels,
         "cpu_baseline": cpu,
         "learned": learned,
+        "paper_study": paper,
     }
     print(json.dumps(result), flush=True)
 
