@@ -248,6 +248,11 @@ def main():
         for m in (eg.FP64, eg.FP32_IR, eg.FP32_IR_BF16):
             x.zero_()
             op.solve(b, x, args.tol, 4, m)
+        op.set_option("precond", 1)   # the line-SOR half-sweeps
+        for m in (eg.FP64, eg.FP32_IR):
+            x.zero_()
+            op.solve(b, x, args.tol, 2, m)
+        op.set_option("precond", 0)
         for _ in range(3):
             x.copy_(b)
         torch.cuda.synchronize()

@@ -1346,7 +1346,7 @@ template <typename Tv, typename Tc, int NL>
 __global__ __launch_bounds__(kWG) void k_sor_half(OpView<Tc> op, SorView<Tv, Tc> sv, const Tv *__restrict__ q,
                                                   Tv *__restrict__ x, Tv *__restrict__ wsc, int colour, Tv omega,
                                                   Tv nb_scale, Tv own_scale, const Scalars *__restrict__ sc,
-                                                  int stop_mask)
+                                                  int stop_mask, int per_xcd)
 {
     if (stopped(sc, stop_mask)) return;
     using V = typename CoefTraits<Tc>::val;
@@ -1355,7 +1355,11 @@ __global__ __launch_bounds__(kWG) void k_sor_half(OpView<Tc> op, SorView<Tv, Tc>
     const int nlev = (NL > 0) ? NL : op.nlev;
     const int half = nlon / 2;
     const long P = op.P, n = op.n, P2 = P / 2;
-    const long c2 = (long)blockIdx.x * kWG + threadIdx.x;
+    // XCD-aware: workgroups go round-robin over the 8 XCDs, so workgroup b takes the logical
+    // block (b % 8) * per_xcd + b / 8 and each XCD walks a contiguous band of latitude rows,
+    // whose north and south neighbour rows its own L2 then holds
+    const long lb = (long)(blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+    const long c2 = lb * kWG + threadIdx.x;
     if (c2 >= P2) return;
     const int j = (int)(c2 / half);
     const int i = 2 * (int)(c2 % half) + ((j + colour) & 1);
@@ -1446,14 +1450,16 @@ void launch_sor(const OpView<Tc> &op, const SorView<Tv, Tc> &sv, const Tv *q, Tv
                 double omega, const Scalars *sc, int stop_mask, hipStream_t s)
 {
     const long half_cols = op.P / 2;
-    const unsigned blocks = (unsigned)((half_cols + kWG - 1) / kWG);
+    const long lblocks = (half_cols + kWG - 1) / kWG;
+    const int per_xcd = (int)((lblocks + 7) / 8);
+    const unsigned blocks = (unsigned)(per_xcd * 8);
     const Tv w = static_cast<Tv>(omega);
     for (int h = 1; h < 2 * sweeps; ++h) {
         const int colour = (h & 1) ? 1 : 0;                       // odd: black, even: red
         const Tv nb_scale = (h == 1) ? w : Tv(1);                 // red still holds T^{-1} q
         const Tv own_scale = (h == 1) ? Tv(0) : (h == 2 ? w : Tv(1));
         hipLaunchKernelGGL((k_sor_half<Tv, Tc, 0>), dim3(blocks), dim3(kWG), 0, s, op, sv, q, x, wsc, colour, w,
-                           nb_scale, own_scale, sc, stop_mask);
+                           nb_scale, own_scale, sc, stop_mask, per_xcd);
     }
     if (sweeps == 1)
         hipLaunchKernelGGL((k_sor_scale<Tv>), dim3(elementwise_blocks(op.n)), dim3(kWG), 0, s, op.P, op.n, op.nlon, x,
