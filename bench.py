@@ -50,11 +50,13 @@ PREC_NAME = {0: "fp64", 1: "fp32", 2: "bf16", 3: "fp16"}
 # grid (`python bench.py --traffic-probe` under `rocprofv3 --pmc`), scaled by the same counters
 # on a device copy of known size (FETCH_SIZE x 2, WRITE_SIZE x 1).  Valid while the kernels
 # are unchanged since that measurement; see profiles/hbm_traffic_2560x1920x70.txt.
-MEASURED_TRAFFIC = {("c3", "spmv_fp64"): 28.73e9, ("c3", "spmv_fp32"): 14.67e9, ("c3", "spmv_bf16"): 9.83e9,
+MEASURED_TRAFFIC = {("c3", "spmv_fp64"): 28.74e9, ("c3", "spmv_fp32"): 14.65e9, ("c3", "spmv_bf16"): 9.82e9,
                     ("c3", "thomas_p_fp64"): 22.02e9, ("c3", "thomas_s_fp64"): 19.27e9, ("c3", "update_fp64"): 22.02e9,
                     ("c3", "thomas_p_fp32"): 11.01e9, ("c3", "thomas_s_fp32"): 9.63e9, ("c3", "update_fp32"): 11.01e9,
                     ("c3", "thomas_p_bf16"): 11.01e9, ("c3", "thomas_s_bf16"): 9.63e9, ("c3", "update_bf16"): 11.01e9,
-                    ("c3", "residual_fp64"): 27.34e9}
+                    ("c3", "residual_fp64"): 27.29e9,
+                    # one SOR application = five half-sweeps
+                    ("c3", "sor_fp64"): 5 * 27.02e9, ("c3", "sor_fp32"): 5 * 11.85e9}
 
 
 def log(*a):
