@@ -371,111 +371,242 @@ __global__ __launch_bounds__(256) void k_conv_bwd(NetGeo g, const uint16_t *__re
     }
 }
 
+
 // ------------------------------------------------------------------------------------------
-// conv layer, weight gradient (per-wave partial sums; rows reduced later in a fixed order):
+// Weight gradient of the 32 -> 32 layers through LDS (layers 2 and 3):
 //   dW[t][co][ci] = sum_p dout[p][co] in[nb(p, t)][ci],   db[co] = sum_p dout[p][co]
-// MFMA with M = co, N = ci (for layer 1: N = (tap, channel)), K = 32 positions per chunk.
+// One workgroup (one partial row) walks chunks of 32 consecutive positions.  The chunk's dout
+// tile and, per tap, the neighbours' input tile are loaded with 32-byte vector loads and
+// written to LDS transposed ([channel][position]), so each MFMA operand (8 consecutive
+// positions of one channel) is a single 16-byte LDS read; K = 32 positions per MFMA.  Wave w
+// owns taps w, w + 4, w + 8 (its accumulators: 16 floats per tap).
 // ------------------------------------------------------------------------------------------
 template <int L>
-__global__ __launch_bounds__(256) void k_conv_dw(NetGeo g, const uint16_t *__restrict__ dout,
-                                                 const uint16_t *__restrict__ in, float *__restrict__ part, int add)
+__global__ __launch_bounds__(256) void k_conv_dw_lds(NetGeo g, const uint16_t *__restrict__ dout,
+                                                     const uint16_t *__restrict__ in, float *__restrict__ part,
+                                                     int add)
 {
+    static_assert(L == 2 || L == 3, "32 -> 32 layers only");
     constexpr int T = LayerGeo<L>::T;
-    constexpr int NG = (L == 1) ? 1 : T;
-    const int lane = threadIdx.x & 63, m = lane & 15, grp = lane >> 4;
-    const long row = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
-    const long nrows = (long)gridDim.x * 4;
-    f32x4 acc[NG][2][2];
+    constexpr int TW = (T + 3) / 4;   // taps per wave
+    constexpr int PITCH = 40;         // bf16 per LDS row (80 bytes: 16-byte aligned rows)
+    __shared__ __align__(16) uint16_t dT[32 * PITCH];
+    __shared__ __align__(16) uint16_t iT[4][32 * PITCH];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, m = lane & 15, grp = lane >> 4;
+    const int lp = lane >> 1, lh = lane & 1;   // loader lane: position lp, channels 16 lh .. 16 lh + 15
+    f32x4 acc[TW][2][2];
 #pragma unroll
-    for (int a = 0; a < NG; ++a)
+    for (int a = 0; a < TW; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b)
 #pragma unroll
             for (int c = 0; c < 2; ++c) acc[a][b][c] = f32x4{0.f, 0.f, 0.f, 0.f};
-    float bsum[2] = {0.f, 0.f};
+    float bsum[16];
+#pragma unroll
+    for (int c = 0; c < 16; ++c) bsum[c] = 0.f;
+    // write 16 channels of one position into a transposed tile
+    auto put = [&](uint16_t *tile, uint4 u0, uint4 u1) {
+        const uint32_t w[8] = {u0.x, u0.y, u0.z, u0.w, u1.x, u1.y, u1.z, u1.w};
+#pragma unroll
+        for (int h = 0; h < 8; ++h) {
+            tile[(16 * lh + 2 * h) * PITCH + lp] = static_cast<uint16_t>(w[h] & 0xffffu);
+            tile[(16 * lh + 2 * h + 1) * PITCH + lp] = static_cast<uint16_t>(w[h] >> 16);
+        }
+    };
     const long nchunks = (g.n + 31) / 32;
-    for (long ch = row; ch < nchunks; ch += nrows) {
-        const long p0 = ch * 32 + 8 * grp;
-        long pos[8];
-        Pos xs[8];
-        bool ok[8];
-#pragma unroll
-        for (int jj = 0; jj < 8; ++jj) {
-            pos[jj] = p0 + jj;
-            ok[jj] = pos[jj] < g.n;
-            xs[jj] = decompose(g, ok[jj] ? pos[jj] : 0);
-        }
-        bf16x8 a[2];
-#pragma unroll
-        for (int mt = 0; mt < 2; ++mt) {
-#pragma unroll
-            for (int jj = 0; jj < 8; ++jj) {
-                const uint16_t v = ok[jj] ? dout[pos[jj] * 32 + 16 * mt + m] : (uint16_t)0;
-                a[mt][jj] = __builtin_bit_cast(__bf16, v);
-                bsum[mt] += bf2f(v);
+    for (long ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
+        const long p = ch * 32 + lp;
+        const bool pv = p < g.n;
+        const long pc = pv ? p : g.n - 1;
+        __syncthreads();   // the previous chunk's tiles are no longer read
+        if (wv == 0) {
+            uint4 u0 = make_uint4(0, 0, 0, 0), u1 = u0;
+            if (pv) {
+                const uint4 *src = reinterpret_cast<const uint4 *>(dout + pc * 32 + 16 * lh);
+                u0 = src[0];
+                u1 = src[1];
             }
-        }
+            const uint32_t w[8] = {u0.x, u0.y, u0.z, u0.w, u1.x, u1.y, u1.z, u1.w};
 #pragma unroll
-        for (int G = 0; G < NG; ++G) {
-#pragma unroll
-            for (int nt = 0; nt < 2; ++nt) {
-                bf16x8 b;
-#pragma unroll
-                for (int jj = 0; jj < 8; ++jj) {
-                    uint16_t v = 0;
-                    if constexpr (L == 1) {
-                        const int kk = 16 * nt + m;   // (tap, channel) = (kk / 4, kk % 4)
-                        if (kk < 20 && ok[jj]) {
-                            const long q = nb_v(g, pos[jj], xs[jj], kk / 4 - 2);
-                            if (q >= 0) v = in[q * 4 + (kk & 3)];
-                        }
-                    } else {
-                        if (ok[jj]) {
-                            const long q = LayerGeo<L>::nb(g, pos[jj], xs[jj], G, false);
-                            if (q >= 0) v = in[q * 32 + 16 * nt + m];
-                        }
-                    }
-                    b[jj] = __builtin_bit_cast(__bf16, v);
-                }
-#pragma unroll
-                for (int mt = 0; mt < 2; ++mt) acc[G][mt][nt] = mfma(a[mt], b, acc[G][mt][nt]);
+            for (int h = 0; h < 8; ++h) {
+                bsum[2 * h] += bf2f(static_cast<uint16_t>(w[h] & 0xffffu));
+                bsum[2 * h + 1] += bf2f(static_cast<uint16_t>(w[h] >> 16));
             }
+            put(dT, u0, u1);
+        }
+        __syncthreads();
+        const Pos x = decompose(g, pc);
+        // every wave runs TW rounds (a wave with fewer taps idles in its last round) so that
+        // all of them meet the workgroup barriers
+#pragma unroll
+        for (int a = 0; a < TW; ++a) {
+            const int t = wv + 4 * a;
+            const bool tv = t < T;
+            const long q = tv ? LayerGeo<L>::nb(g, pc, x, t, false) : -1;
+            uint4 u0 = make_uint4(0, 0, 0, 0), u1 = u0;
+            if (pv && q >= 0) {
+                const uint4 *src = reinterpret_cast<const uint4 *>(in + q * 32 + 16 * lh);
+                u0 = src[0];
+                u1 = src[1];
+            }
+            if (a > 0) __syncthreads();   // the previous round's tile has been read
+            put(iT[wv], u0, u1);
+            __syncthreads();
+            if (!tv) continue;
+            bf16x8 A[2], B[2];
+#pragma unroll
+            for (int mt = 0; mt < 2; ++mt)
+                A[mt] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(dT + (16 * mt + m) * PITCH + 8 * grp));
+#pragma unroll
+            for (int nt = 0; nt < 2; ++nt)
+                B[nt] = __builtin_bit_cast(bf16x8,
+                                           *reinterpret_cast<const uint4 *>(iT[wv] + (16 * nt + m) * PITCH + 8 * grp));
+#pragma unroll
+            for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+                for (int nt = 0; nt < 2; ++nt) acc[a][mt][nt] = mfma(A[mt], B[nt], acc[a][mt][nt]);
         }
     }
-    float *dst = part + row * kNetParams;
-    // result lane l: co = 16 mt + 4 grp + jj, N index = 16 nt + m
+    float *dst = part + (long)blockIdx.x * kNetParams;
+    const int off = (L == 2) ? kNetOffW2 : kNetOffW3;
+    // result lane l: co = 16 mt + 4 grp + jj, ci = 16 nt + m
 #pragma unroll
-    for (int G = 0; G < NG; ++G)
+    for (int a = 0; a < TW; ++a) {
+        const int t = wv + 4 * a;
+        if (t >= T) break;
 #pragma unroll
         for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
             for (int nt = 0; nt < 2; ++nt)
 #pragma unroll
                 for (int jj = 0; jj < 4; ++jj) {
-                    const int co = 16 * mt + 4 * grp + jj;
-                    const int nn = 16 * nt + m;
-                    if constexpr (L == 1) {
-                        if (nn < 20) {
-                            float &o = dst[kNetOffW1 + (nn / 4) * 128 + co * 4 + (nn & 3)];
-                            o = add ? o + acc[G][mt][nt][jj] : acc[G][mt][nt][jj];
-                        }
-                    } else {
-                        const int off = (L == 2) ? kNetOffW2 : kNetOffW3;
-                        float &o = dst[off + G * 1024 + co * 32 + nn];
-                        o = add ? o + acc[G][mt][nt][jj] : acc[G][mt][nt][jj];
-                    }
+                    float &o = dst[off + t * 1024 + (16 * mt + 4 * grp + jj) * 32 + 16 * nt + m];
+                    o = add ? o + acc[a][mt][nt][jj] : acc[a][mt][nt][jj];
                 }
-    // bias: sum over the four lane groups holding the same output channel
+    }
+    if (wv == 0) {
+        // bias: lanes with the same lh hold the same channels for different positions
 #pragma unroll
-    for (int mt = 0; mt < 2; ++mt) {
-        float s = bsum[mt];
-        s += __shfl_xor(s, 16);
-        s += __shfl_xor(s, 32);
-        if (grp == 0) {
-            const int off = (L == 1) ? kNetOffB1 : ((L == 2) ? kNetOffB2 : kNetOffB3);
-            float &o = dst[off + 16 * mt + m];
-            o = add ? o + s : s;
+        for (int c = 0; c < 16; ++c) {
+            float v = bsum[c];
+            v += __shfl_xor(v, 2);
+            v += __shfl_xor(v, 4);
+            v += __shfl_xor(v, 8);
+            v += __shfl_xor(v, 16);
+            v += __shfl_xor(v, 32);
+            if (lane < 2 && lane == lh) {
+                float &o = dst[((L == 2) ? kNetOffB2 : kNetOffB3) + 16 * lh + c];
+                o = add ? o + v : v;
+            }
         }
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// Weight gradients of the two layers with few weights, as column marches on the vector ALU.
+// A workgroup is 8 streams of 32 lanes (lane = channel); a stream takes whole columns of the
+// level plane and walks their levels, so every activation row is read once (64 contiguous
+// bytes per stream) and the few values of the other factor come from a rolling window of
+// five levels (a broadcast load per level).  The 8 streams' sums are added in a fixed order in
+// LDS and written as the workgroup's partial row.
+//   output layer: dW4[t][c] = sum_p drho(p) a3[p + (t-2) P][c], db4 = sum_p drho(p), drho = rho u
+//   layer 1:      dW1[t][co][ci] = sum_p dh1[p][co] x0[p + (t-2) P][ci], db1[co] = sum_p dh1[p][co]
+// ------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_net_out_dw_col(NetGeo g, const float *__restrict__ u,
+                                                        const uint16_t *__restrict__ a3, float *__restrict__ part,
+                                                        const Scalars *__restrict__ sc, int add)
+{
+    const float rho = static_cast<float>(sqrt(sc->net_q2 / (double)g.n));
+    const int c = threadIdx.x & 31, st = threadIdx.x >> 5;
+    const long nst = (long)gridDim.x * 8;
+    float acc[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+    float bacc = 0.f;
+    auto dr = [&](long col, int k) -> float { return (k >= 0 && k < g.nlev) ? rho * u[col + (long)k * g.P] : 0.f; };
+    for (long col = (long)blockIdx.x * 8 + st; col < g.P; col += nst) {
+        // d[t] = drho at level kk + 2 - t
+        float d0 = dr(col, 2), d1 = dr(col, 1), d2 = dr(col, 0), d3 = 0.f, d4 = 0.f;
+        for (int kk = 0; kk < g.nlev; ++kk) {
+            const float a = bf2f(a3[(col + (long)kk * g.P) * 32 + c]);
+            acc[0] += d0 * a;
+            acc[1] += d1 * a;
+            acc[2] += d2 * a;
+            acc[3] += d3 * a;
+            acc[4] += d4 * a;
+            bacc += d2;
+            d4 = d3;
+            d3 = d2;
+            d2 = d1;
+            d1 = d0;
+            d0 = dr(col, kk + 3);
+        }
+    }
+    __shared__ float red[8][161];
+#pragma unroll
+    for (int t = 0; t < 5; ++t) red[st][t * 32 + c] = acc[t];
+    if (c == 0) red[st][160] = bacc;
+    __syncthreads();
+    if (threadIdx.x <= 160) {
+        float v = 0.f;
+        for (int r = 0; r < 8; ++r) v += red[r][threadIdx.x];
+        float *dst = part + (long)blockIdx.x * kNetParams;
+        float &o = (threadIdx.x < 160) ? dst[kNetOffW4 + threadIdx.x] : dst[kNetOffB4];
+        o = add ? o + v : v;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_conv_dw1_col(NetGeo g, const uint16_t *__restrict__ dout,
+                                                      const uint16_t *__restrict__ x0, float *__restrict__ part,
+                                                      int add)
+{
+    const int co = threadIdx.x & 31, st = threadIdx.x >> 5;
+    const long nst = (long)gridDim.x * 8;
+    float acc[5][4];
+#pragma unroll
+    for (int t = 0; t < 5; ++t)
+#pragma unroll
+        for (int ci = 0; ci < 4; ++ci) acc[t][ci] = 0.f;
+    float bacc = 0.f;
+    auto xin = [&](long col, int k) -> uint2 {
+        return (k >= 0 && k < g.nlev) ? reinterpret_cast<const uint2 *>(x0)[col + (long)k * g.P] : make_uint2(0, 0);
+    };
+    auto ch = [](uint2 v, int ci) -> float {
+        const uint32_t w = (ci < 2) ? v.x : v.y;
+        return bf2f(static_cast<uint16_t>((ci & 1) ? (w >> 16) : (w & 0xffffu)));
+    };
+    for (long col = (long)blockIdx.x * 8 + st; col < g.P; col += nst) {
+        // w[t] = x0 at level k + t - 2
+        uint2 w0 = xin(col, -2), w1 = xin(col, -1), w2 = xin(col, 0), w3 = xin(col, 1), w4 = xin(col, 2);
+        for (int k = 0; k < g.nlev; ++k) {
+            const float dv = bf2f(dout[(col + (long)k * g.P) * 32 + co]);
+            bacc += dv;
+#pragma unroll
+            for (int ci = 0; ci < 4; ++ci) {
+                acc[0][ci] += dv * ch(w0, ci);
+                acc[1][ci] += dv * ch(w1, ci);
+                acc[2][ci] += dv * ch(w2, ci);
+                acc[3][ci] += dv * ch(w3, ci);
+                acc[4][ci] += dv * ch(w4, ci);
+            }
+            w0 = w1;
+            w1 = w2;
+            w2 = w3;
+            w3 = w4;
+            w4 = xin(col, k + 3);
+        }
+    }
+    __shared__ float red[8][5 * 128 + 32];
+#pragma unroll
+    for (int t = 0; t < 5; ++t)
+#pragma unroll
+        for (int ci = 0; ci < 4; ++ci) red[st][t * 128 + co * 4 + ci] = acc[t][ci];
+    red[st][640 + co] = bacc;
+    __syncthreads();
+    float *dst = part + (long)blockIdx.x * kNetParams;
+    for (int e = threadIdx.x; e < 672; e += 256) {
+        float v = 0.f;
+        for (int r = 0; r < 8; ++r) v += red[r][e];
+        float &o = (e < 640) ? dst[kNetOffW1 + e] : dst[kNetOffB1 + (e - 640)];
+        o = add ? o + v : v;
     }
 }
 
@@ -586,40 +717,6 @@ __global__ __launch_bounds__(256) void k_net_out_bwd(NetGeo g, const float *__re
     }
 }
 
-// Output-layer weight gradient: dW4[t][c] = sum_p dδ[p] a3[p + (t - 2) P][c], db4 = sum dδ.
-// Workgroup = 32 channels x 8 position streams; one partial row per workgroup.
-__global__ __launch_bounds__(256) void k_net_out_dw(NetGeo g, const float *__restrict__ u,
-                                                    const uint16_t *__restrict__ a3, float *__restrict__ part,
-                                                    const Scalars *__restrict__ sc, int add)
-{
-    const float rho = static_cast<float>(sqrt(sc->net_q2 / (double)g.n));
-    const int c = threadIdx.x & 31, s = threadIdx.x >> 5;
-    float acc[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
-    float bacc = 0.f;
-    const long stride = (long)gridDim.x * 8;
-    for (long p = (long)blockIdx.x * 8 + s; p < g.n; p += stride) {
-        const Pos x = decompose(g, p);
-        const float dd = rho * u[p];
-        if (c == 0) bacc += dd;
-#pragma unroll
-        for (int t = 0; t < 5; ++t) {
-            const long nb = nb_v(g, p, x, t - 2);
-            if (nb >= 0) acc[t] += dd * bf2f(a3[nb * 32 + c]);
-        }
-    }
-    __shared__ float red[8][161];
-#pragma unroll
-    for (int t = 0; t < 5; ++t) red[s][t * 32 + c] = acc[t];
-    if (c == 0) red[s][160] = bacc;
-    __syncthreads();
-    if (threadIdx.x <= 160) {
-        float v = 0.f;
-        for (int r = 0; r < 8; ++r) v += red[r][threadIdx.x];
-        float *dst = part + (long)blockIdx.x * kNetParams;
-        float &o = (threadIdx.x < 160) ? dst[kNetOffW4 + threadIdx.x] : dst[kNetOffB4];
-        o = add ? o + v : v;
-    }
-}
 
 // ------------------------------------------------------------------------------------------
 // loss pieces:  g = 2 (m - e) / ||e||^2
@@ -819,17 +916,16 @@ void launch_net_backward(const NetGeo &g, const NetDev &d, const NetActs &act, c
     // output layer
     hipLaunchKernelGGL(k_net_out_bwd, dim3(net_blocks(g.n, 1024, 8192)), dim3(256), 0, s, g, u, act.a3, d.w4, act.d1,
                        sc);
-    hipLaunchKernelGGL(k_net_out_dw, dim3(rows), dim3(256), 0, s, g, u, act.a3, d.part, sc, add);
+    hipLaunchKernelGGL(k_net_out_dw_col, dim3(rows), dim3(256), 0, s, g, u, act.a3, d.part, sc, add);
     const int nb = net_blocks((g.n + 15) / 16, 4 * 8, 4096);
-    const int rb = rows / 4;   // dw kernels: one partial row per wave
     // layer 3: dW3 from (dh3, a2); dh2 = bwd(dh3) masked by a2
-    hipLaunchKernelGGL((k_conv_dw<3>), dim3(rb), dim3(256), 0, s, g, act.d1, act.a2, d.part, add);
+    hipLaunchKernelGGL((k_conv_dw_lds<3>), dim3(rows), dim3(256), 0, s, g, act.d1, act.a2, d.part, add);
     hipLaunchKernelGGL((k_conv_bwd<3>), dim3(nb), dim3(256), 0, s, g, act.d1, d.w3b, act.a2, act.d2);
     // layer 2: dW2 from (dh2, a1); dh1 = bwd(dh2) masked by a1
-    hipLaunchKernelGGL((k_conv_dw<2>), dim3(rb), dim3(256), 0, s, g, act.d2, act.a1, d.part, add);
+    hipLaunchKernelGGL((k_conv_dw_lds<2>), dim3(rows), dim3(256), 0, s, g, act.d2, act.a1, d.part, add);
     hipLaunchKernelGGL((k_conv_bwd<2>), dim3(nb), dim3(256), 0, s, g, act.d2, d.w2b, act.a1, act.d1);
     // layer 1: dW1 from (dh1, x0)
-    hipLaunchKernelGGL((k_conv_dw<1>), dim3(rb), dim3(256), 0, s, g, act.d1, act.x0, d.part, add);
+    hipLaunchKernelGGL(k_conv_dw1_col, dim3(rows), dim3(256), 0, s, g, act.d1, act.x0, d.part, add);
 }
 
 void launch_net_grad(const NetDev &d, float scale, hipStream_t s)
