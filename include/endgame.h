@@ -45,6 +45,9 @@ enum eg_mode {
     EG_FP32_IR = 1,         /* FP64 iterative refinement around an FP32 inner BiCGStab; FP64     */
                             /* true residual, solution update and dot-product accumulation       */
                             /* (Sec. 3-4: x kept in 64-bit, the rest 32-bit, 64-bit global sums) */
+                            /* A refinement step that does not reduce the true residual is       */
+                            /* undone, and so is the refinement when it stagnates: the solve     */
+                            /* then continues from x with the EG_FP64 solver (info.fallbacks).   */
     EG_FP32_IR_BF16 = 2,    /* as EG_FP32_IR, inner off-diagonal couplings stored as BF16        */
     EG_FP32_IR_FP16 = 3,    /* as EG_FP32_IR, inner off-diagonal couplings stored as FP16        */
     EG_LEARNED_FP64 = 4,    /* flexible BiCGStab in FP64 with the learned preconditioner         */
@@ -80,7 +83,8 @@ typedef struct {
     int iterations;            /* Krylov iterations (summed over refinement steps)            */
     int outer_steps;           /* FP64 refinement steps (0 in EG_FP64 / EG_LEARNED_FP64)       */
     int restarts;              /* breakdown, periodic and residual-gap restarts               */
-    int fallbacks;             /* learned modes: switches to the T^{-1} preconditioner         */
+    int fallbacks;             /* learned modes: switches to the T^{-1} preconditioner;       */
+                               /* refinement modes: +1 when the FP64 solver took over          */
     double true_rel_residual;  /* ||b - A x|| / ||b|| of the returned x, evaluated in FP64     */
     double seconds;            /* wall time of the solve                                       */
 } eg_info;

@@ -135,6 +135,7 @@ struct eg_operator {
     bool sor_on = false;        // SOR active in the current solve (plain modes with precond 1)
     double *sor_scratch = nullptr;   // n doubles, for eg_apply_precond
     double *mp_x = nullptr;     // EG_FP32_MP: the FP64 solution the FP32 iteration updates
+    double *ir_backup = nullptr;   // refinement: x before the last correction
     bool mp_active = false;
     // colour-major copies of the LU factors and the W, E, S, N couplings the SOR reads
     double *sorf64 = nullptr, *sora64 = nullptr;
@@ -807,8 +808,10 @@ int solve_ir(eg_operator *op, const OpView<Tc> &A32, const double *b, double *x,
     bool use_net = net != nullptr;
     Work<float> &w = op->w32;
     hipStream_t s = op->stream;
+    if (!op->ir_backup && (rc = dalloc(&op->ir_backup, (size_t)op->n))) return rc;
     int total = 0, outer = 0, status = EG_MAXIT, stalls = 0, restarts = 0;
     double rel_prev = INFINITY;
+    bool fallback = false;
     for (;;) {
         int nr = 0;
         if (op->profile) {
@@ -832,10 +835,18 @@ int solve_ir(eg_operator *op, const OpView<Tc> &A32, const double *b, double *x,
         const double rel = std::sqrt(rr / bb);
         op->info.true_rel_residual = rel;
         if (rel <= tol) { status = EG_CONVERGED; break; }
+        if (outer > 0 && !(rel < rel_prev)) {
+            // the last correction made the residual no smaller (the FP32 inner solve failed,
+            // e.g. on a near-singular operator): undo it and finish in FP64
+            EG_HIP(hipMemcpyAsync(x, op->ir_backup, op->n * sizeof(double), hipMemcpyDeviceToDevice, s));
+            op->info.true_rel_residual = rel_prev;
+            fallback = true;
+            break;
+        }
         if (total >= maxit) { status = EG_MAXIT; break; }
-        if (outer >= op->max_outer) { status = EG_STALLED; break; }
+        if (outer >= op->max_outer) { status = EG_STALLED; break; }   // the caller's cap on refinement steps
         if (rel > 0.5 * rel_prev) {
-            if (++stalls >= (net ? 3 : 2)) { status = EG_STALLED; break; }
+            if (++stalls >= (net ? 3 : 2)) { fallback = true; break; }
         } else {
             stalls = 0;
         }
@@ -867,6 +878,7 @@ int solve_ir(eg_operator *op, const OpView<Tc> &A32, const double *b, double *x,
                 op->info.fallbacks += fb;
             }
             total += its;
+            EG_HIP(hipMemcpyAsync(op->ir_backup, x, op->n * sizeof(double), hipMemcpyDeviceToDevice, s));
             launch_add_correction(op->n, x, w.x, s);
             EG_HIP(hipGetLastError());
             ++outer;
@@ -888,6 +900,7 @@ int solve_ir(eg_operator *op, const OpView<Tc> &A32, const double *b, double *x,
         }
         total += op->h_sc->iter;
         restarts += op->h_sc->restarts;
+        EG_HIP(hipMemcpyAsync(op->ir_backup, x, op->n * sizeof(double), hipMemcpyDeviceToDevice, s));
         launch_add_correction(op->n, x, w.x, s);
         EG_HIP(hipGetLastError());
         ++outer;
@@ -896,6 +909,18 @@ int solve_ir(eg_operator *op, const OpView<Tc> &A32, const double *b, double *x,
     op->info.outer_steps = outer;
     op->info.restarts = restarts;
     op->hist_count = total;
+    if (fallback) {
+        // the FP32 refinement cannot go further: continue from x with the FP64 solver (the
+        // history then holds the FP64 solve's residuals)
+        const eg_info before = op->info;
+        if (op->sor_on && (rc = ensure_sor<double>(op))) return rc;
+        status = solve_fp64(op, b, x, tol, std::max(1, maxit - total));
+        if (status < 0) return status;
+        op->info.iterations += before.iterations;
+        op->info.outer_steps = before.outer_steps;
+        op->info.restarts += before.restarts;
+        op->info.fallbacks = before.fallbacks + 1;
+    }
     return status;
 }
 
@@ -1075,7 +1100,7 @@ void eg_destroy_operator(eg_operator *op)
     dfree(op->harvest_x);
     for (Fgm<double> *F : {&op->f64}) { dfree(F->V); dfree(F->Z); dfree(F->W); dfree(F->R); dfree(F->tmp); }
     for (Fgm<float> *F : {&op->f32}) { dfree(F->V); dfree(F->Z); dfree(F->W); dfree(F->R); dfree(F->tmp); }
-    dfree(op->d_h); dfree(op->mpart); dfree(op->sor_scratch); dfree(op->mp_x);
+    dfree(op->d_h); dfree(op->mpart); dfree(op->sor_scratch); dfree(op->mp_x); dfree(op->ir_backup);
     dfree(op->sorf64); dfree(op->sora64); dfree(op->sorf32); dfree(op->sora32); dfree(op->sorq[0]); dfree(op->sorq[1]);
     if (op->h_h) (void)hipHostFree(op->h_h);
     dfree(op->w64.qp);

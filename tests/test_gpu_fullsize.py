@@ -145,3 +145,67 @@ def test_manufactured_solution_640x480x70(eg, oracle_mod):
             fwd = np.linalg.norm(xh - xs) / np.linalg.norm(xs)
             print(f"640x480x70 {name}: {info.iterations} its, true R {rel:.2e}, forward error {fwd:.2e}")
             assert info.status == eg.CONVERGED and rel <= 1e-8 * (1 + 1e-6) and fwd <= 1e-5
+
+
+def test_stress_case_1280x960x140(eg, oracle_mod):
+    """Coefficient contrast 1e4 in vertical bands, shift 1e-6 (near-singular), 140 levels: FP64,
+    FP32 inner + FP64 refinement and the line-SOR variant reach 1e-8 (true residual by the
+    oracle's FP64 product on the host); the refinement solution agrees with the FP64 one within
+    the conditioning of the problem."""
+    import torch
+    p = synth.CONFIGS["c5"]
+    coef = synth.make_coeffs(p, threads=16)
+    b = synth.make_rhs(p).ravel()
+    print("[fullsize] 1280x960x140 generated", flush=True)
+    nb = np.linalg.norm(b)
+    sols = {}
+    with eg.Operator(torch.from_numpy(coef).cuda()) as op:
+        bd = torch.from_numpy(b).cuda()
+        for name, mode, pc in (("FP64", eg.FP64, 0), ("FP32_IR", eg.FP32_IR, 0), ("FP32_IR+SOR", eg.FP32_IR, 1)):
+            op.set_option("precond", pc)
+            x = torch.zeros(p.n, dtype=torch.float64, device="cuda")
+            print(f"[fullsize] 1280x960x140 {name}", flush=True)
+            info = op.solve(bd, x, 1e-8, 20000, mode)
+            xh = host(x)
+            rel = np.linalg.norm(b - oracle_mod.apply(coef, xh)) / nb
+            print(f"1280x960x140 {name}: status {info.status}, {info.iterations} its, {info.outer_steps} outer, "
+                  f"{info.fallbacks} fallbacks to FP64, {info.seconds:.2f} s, true R {rel:.2e}")
+            assert info.status == eg.CONVERGED and rel <= 1e-8 * (1 + 1e-6)
+            sols[name] = xh
+    ref = sols["FP64"]
+    for name in ("FP32_IR", "FP32_IR+SOR"):
+        d = np.linalg.norm(sols[name] - ref) / np.linalg.norm(ref)
+        print(f"{name} vs FP64: rel L2 {d:.2e}")
+        assert d <= 1e-1   # shift 1e-6: cond(A) ~ 1e6, two solutions with R <= 1e-8 each
+
+
+def test_learned_preconditioner_640x480x70(eg, oracle_mod):
+    """A network trained in seconds on small operators of the recipe, attached to the
+    640x480x70 operator: FGMRES with the learned preconditioner reaches 1e-8 in FP64 and in
+    FP32 with FP64 refinement (true residual by the oracle)."""
+    import torch
+    ops, rs, owner = [], [], []
+    for s in range(8):
+        q = synth.Problem(96, 72, 20, seed=1000 + s)
+        op = eg.Operator(torch.from_numpy(synth.make_coeffs(q)).cuda())
+        r, _ = op.harvest_krylov(torch.from_numpy(synth.make_rhs(q, seed=2000 + s).ravel()).cuda(), 20, errors=False)
+        ops.append(op)
+        rs.append(r)
+        owner += [s] * r.shape[0]
+    r = torch.cat(rs).contiguous()
+    net = eg.Net(11)
+    net.train(ops, r, r, owner, epochs=10, batch=16, lr=2e-3, seed=1)
+    for op in ops:
+        op.close()
+    p = synth.CONFIGS["c4"]
+    coef = synth.make_coeffs(p, threads=16)
+    b = synth.make_rhs(p).ravel()
+    with eg.Operator(torch.from_numpy(coef).cuda()) as op:
+        op.attach(net)
+        for mode in (eg.LEARNED_FP64, eg.LEARNED_FP32_IR):
+            x = torch.zeros(p.n, dtype=torch.float64, device="cuda")
+            info = op.solve(torch.from_numpy(b).cuda(), x, 1e-8, 5000, mode)
+            rel = np.linalg.norm(b - oracle_mod.apply(coef, host(x))) / np.linalg.norm(b)
+            print(f"640x480x70 {eg.MODE_NAMES[mode]}: {info.iterations} its, fallbacks {info.fallbacks}, true R {rel:.2e}")
+            assert info.status == eg.CONVERGED and rel <= 1e-8 * (1 + 1e-6)
+    net.close()
