@@ -3,7 +3,7 @@
 Only ``tests/``, the smoke check and the benchmark's CPU-baseline leg import this package.
 The GPU library never imports it and shares no code with it.
 
-* ``apply``, ``apply_points``, ``thomas``, ``rbsor``, ``bicgstab`` wrap ``oracle.c`` (see its
+* ``apply``, ``apply_points``, ``thomas``, ``rbsor``, ``lexsor``, ``bicgstab`` wrap ``oracle.c`` (see its
   header for the passages of the paper each follows).
 * ``dense_matrix`` / ``dense_solve`` assemble A as a dense matrix and solve it with LAPACK's
   partial-pivot LU (the exact solution the Krylov iteration approaches; tiny grids only).
@@ -67,9 +67,10 @@ def _load():
                                                           ctypes.c_int, dp, ctypes.c_int, ctypes.POINTER(_Info)]
         lib.orc_bicgstab.restype = ctypes.c_int
         lib.orc_rbsor.argtypes = [ctypes.c_int] * 3 + [dp, dp, dp, ctypes.c_int, ctypes.c_double]
+        lib.orc_lexsor.argtypes = [ctypes.c_int] * 3 + [dp, dp, dp, ctypes.c_int, ctypes.c_double]
         lib.orc_bicgstab_sor.argtypes = [ctypes.c_int] * 3 + [dp, dp, dp, ctypes.c_double, ctypes.c_int, ctypes.c_int,
-                                                             ctypes.c_int, ctypes.c_double, dp, ctypes.c_int,
-                                                             ctypes.POINTER(_Info)]
+                                                             ctypes.c_int, ctypes.c_int, ctypes.c_double, dp,
+                                                             ctypes.c_int, ctypes.POINTER(_Info)]
         lib.orc_bicgstab_sor.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -136,11 +137,21 @@ def rbsor(coef: np.ndarray, q: np.ndarray, sweeps: int = 3, omega: float = 1.5, 
     return z
 
 
+def lexsor(coef: np.ndarray, q: np.ndarray, sweeps: int = 3, omega: float = 1.5):
+    """The same line SOR in lexicographic column order (the paper's serial order)."""
+    nlon, nlat, nlev = _check(coef)
+    q = _vec(q, nlon * nlat * nlev)
+    z = np.empty_like(q)
+    _load().orc_lexsor(nlon, nlat, nlev, _dp(coef), _dp(q), _dp(z), int(sweeps), float(omega))
+    return z
+
+
 def bicgstab(coef: np.ndarray, b: np.ndarray, x0: np.ndarray | None = None, tol: float = 1e-8,
              maxit: int = 20000, restart_every: int = 0, precond: int = 1,
              hist_cap: int | None = None, sor_sweeps: int = 3, sor_omega: float = 1.5) -> tuple[np.ndarray, SolveInfo]:
     """Right-preconditioned BiCGStab; precond 1 = vertical tridiagonal, 0 = identity,
-    2 = red-black line SOR with ``sor_sweeps`` sweeps and relaxation ``sor_omega``."""
+    2 = red-black line SOR, 3 = lexicographic line SOR, with ``sor_sweeps`` sweeps and
+    relaxation ``sor_omega``."""
     nlon, nlat, nlev = _check(coef)
     n = nlon * nlat * nlev
     b = _vec(b, n)
@@ -148,8 +159,8 @@ def bicgstab(coef: np.ndarray, b: np.ndarray, x0: np.ndarray | None = None, tol:
     cap = maxit if hist_cap is None else hist_cap
     hist = np.full(max(cap, 1), np.nan)
     info = _Info()
-    if precond == 2:
-        _load().orc_bicgstab_sor(nlon, nlat, nlev, _dp(coef), _dp(b), _dp(x), tol, maxit, restart_every,
+    if precond in (2, 3):
+        _load().orc_bicgstab_sor(nlon, nlat, nlev, _dp(coef), _dp(b), _dp(x), tol, maxit, restart_every, precond,
                                  int(sor_sweeps), float(sor_omega), _dp(hist), cap, ctypes.byref(info))
     else:
         _load().orc_bicgstab(nlon, nlat, nlev, _dp(coef), _dp(b), _dp(x), tol, maxit, restart_every, precond,

@@ -18,6 +18,7 @@
  *   orc_rbsor      Sec. 2, Eq. 6-7: the tri_sor preconditioner (a few over-relaxed sweeps of
  *                  vertical-line Gauss-Seidel in which T takes the place of the diagonal),
  *                  with the columns visited in red-black order instead of lexicographically.
+ *   orc_lexsor     the same sweeps in lexicographic column order (the paper's serial order).
  *   orc_bicgstab   Sec. 2 (post-conditioned BiCGStab, Eq. 5; van der Vorst's method with the
  *                  preconditioner applied on the right) and Sec. 3 (halting on
  *                  R = ||r_i|| / ||b|| of the unpreconditioned residual, Eq. 8-9), with the
@@ -204,6 +205,60 @@ void orc_rbsor(int nlon, int nlat, int nlev, const double *coef, const double *q
     free(col);
 }
 
+/*
+ * The same SOR in the serial order of the paper's CPU code (Sec. 2, Eq. 7): columns visited
+ * lexicographically (i fastest, then j), each using the newest values of all its neighbours
+ * (x_c <- (1 - omega) x_c + omega T_c^{-1}(q_c + sum_nb a_nb x_nb)); nsweeps sweeps from x = 0.
+ * Kept for comparing the orderings; the GPU builds the red-black one.
+ */
+void orc_lexsor(int nlon, int nlat, int nlev, const double *coef, const double *q, double *z, int nsweeps,
+                double omega)
+{
+    const long P = (long)nlon * nlat;
+    const long n = P * nlev;
+    const double *aW = coef + ORC_W * n, *aE = coef + ORC_E * n, *aS = coef + ORC_S * n, *aN = coef + ORC_N * n;
+    const double *aD = coef + ORC_D * n, *aU = coef + ORC_U * n, *C = coef + ORC_C * n;
+    double *rhs = (double *)malloc(sizeof(double) * (size_t)nlev);
+    double *cp = (double *)malloc(sizeof(double) * (size_t)nlev);
+    double *yy = (double *)malloc(sizeof(double) * (size_t)nlev);
+    for (long c = 0; c < n; ++c) z[c] = 0.0;
+    for (int sw = 0; sw < nsweeps; ++sw)
+        for (int j = 0; j < nlat; ++j)
+            for (int i = 0; i < nlon; ++i) {
+                const int iw = (i == 0) ? nlon - 1 : i - 1;
+                const int ie = (i == nlon - 1) ? 0 : i + 1;
+                for (int k = 0; k < nlev; ++k) {
+                    const long c = i + (long)nlon * (j + (long)nlat * k);
+                    double acc = q[c];
+                    acc = acc + aW[c] * z[c - i + iw];
+                    acc = acc + aE[c] * z[c - i + ie];
+                    if (j > 0) acc = acc + aS[c] * z[c - nlon];
+                    if (j < nlat - 1) acc = acc + aN[c] * z[c + nlon];
+                    rhs[k] = acc;
+                }
+                const long c0 = i + (long)nlon * j;
+                cp[0] = -aU[c0] / C[c0];
+                yy[0] = rhs[0] / C[c0];
+                for (int k = 1; k < nlev; ++k) {
+                    const long c = c0 + k * P;
+                    const double den = C[c] - (-aD[c]) * cp[k - 1];
+                    cp[k] = -aU[c] / den;
+                    yy[k] = (rhs[k] - (-aD[c]) * yy[k - 1]) / den;
+                }
+                double znext = yy[nlev - 1];
+                z[c0 + (long)(nlev - 1) * P] = (1.0 - omega) * z[c0 + (long)(nlev - 1) * P] + omega * znext;
+                for (int k = nlev - 2; k >= 0; --k) {
+                    const double y = yy[k] - cp[k] * znext;
+                    const long c = c0 + k * P;
+                    z[c] = (1.0 - omega) * z[c] + omega * y;
+                    znext = y;
+                }
+            }
+    free(rhs);
+    free(cp);
+    free(yy);
+}
+
 double orc_dot(long n, const double *a, const double *b)
 {
     double s = 0.0;
@@ -213,8 +268,9 @@ double orc_dot(long n, const double *a, const double *b)
 
 static double nrm2(long n, const double *a) { return sqrt(orc_dot(n, a, a)); }
 
-/* preconditioner choice of orc_bicgstab_pc: 0 = identity, 1 = vertical tridiagonal (T^{-1}),
- * 2 = red-black line SOR (orc_rbsor) with sor_sweeps sweeps and relaxation sor_omega */
+/* preconditioner choice of orc_bicgstab: 0 = identity, 1 = vertical tridiagonal (T^{-1}),
+ * 2 = red-black line SOR (orc_rbsor), 3 = lexicographic line SOR (orc_lexsor), both with
+ * sor_sweeps sweeps and relaxation sor_omega (orc_bicgstab_sor) */
 static int g_sor_sweeps = 3;
 static double g_sor_omega = 1.5;
 
@@ -225,6 +281,8 @@ static void apply_m(int precond, int nlon, int nlat, int nlev, const double *coe
         orc_thomas(nlon, nlat, nlev, coef, q, z);
     else if (precond == 2)
         orc_rbsor(nlon, nlat, nlev, coef, q, z, 2 * g_sor_sweeps, g_sor_omega);
+    else if (precond == 3)
+        orc_lexsor(nlon, nlat, nlev, coef, q, z, g_sor_sweeps, g_sor_omega);
     else
         memcpy(z, q, sizeof(double) * (size_t)n);
 }
@@ -397,14 +455,16 @@ done:
     return info->status;
 }
 
-/* orc_bicgstab with the red-black line SOR preconditioner's parameters (precond = 2). */
+/* orc_bicgstab with a line-SOR preconditioner (precond 2 red-black, 3 lexicographic) and its
+ * parameters. */
 int orc_bicgstab_sor(int nlon, int nlat, int nlev, const double *coef, const double *b, double *x,
-                     double tol, int maxit, int restart_every, int sweeps, double omega, double *hist,
-                     int hist_cap, orc_info *info)
+                     double tol, int maxit, int restart_every, int precond, int sweeps, double omega,
+                     double *hist, int hist_cap, orc_info *info)
 {
     g_sor_sweeps = sweeps;
     g_sor_omega = omega;
-    const int st = orc_bicgstab(nlon, nlat, nlev, coef, b, x, tol, maxit, restart_every, 2, hist, hist_cap, info);
+    const int st = orc_bicgstab(nlon, nlat, nlev, coef, b, x, tol, maxit, restart_every, precond, hist, hist_cap,
+                                info);
     g_sor_sweeps = 3;
     g_sor_omega = 1.5;
     return st;
