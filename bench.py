@@ -32,6 +32,10 @@ BYTES_PER_POINT = {
     "spmv": {0: 80, 1: 40, 2: 28, 3: 28},       # 6 couplings + margin + x + dot partner + y
     "thomas_p": {0: 64, 1: 32, 2: 32, 3: 32},   # 3 LU factors + r, p, v in + p, phat out
     "thomas_s": {0: 56, 1: 28, 2: 28, 3: 28},   # 3 LU factors + r, v in + s, shat out (16-bit modes use FP32 factors)
+    # line-SOR modes: the same with the result written in colour-major order and q once more
+    # (its colour-major copy for the half-sweeps)
+    "thomas_p_cm": {0: 72, 1: 36, 2: 36, 3: 36},
+    "thomas_s_cm": {0: 64, 1: 32, 2: 32, 3: 32},
     "update": {0: 64, 1: 32, 2: 32, 3: 32},     # x, phat, shat, s, t, rhat in + x, r out
     "residual": {0: 76},                        # 6 couplings + margin + x + b (FP64) + r (FP32)
 }
@@ -39,24 +43,29 @@ BYTES_PER_POINT = {
 # update: rhs q, own x in and out, the three LU factors, four horizontal couplings and the
 # parked forward-sweep value (write + read); the other half's x is read once as neighbours),
 # times 2 * sweeps - 1 half-sweeps per application (the first red half-sweep is the
-# tridiagonal solve before it).
+# tridiagonal solve before it).  The first half-sweep reads no old x of its own and the last
+# writes the other colour's values in grid order as well: over an application these balance,
+# so 52 B (FP64) per half-sweep holds on average.
 SOR_HALF_BYTES = {0: 52, 1: 26, 2: 22, 3: 22}
 KERNEL_IDS = {"thomas_p": [0], "spmv": [1, 3], "thomas_s": [2], "update": [4], "residual": [5], "sor": [6, 7]}
 KERNEL_SYMBOL = {"spmv": "k_spmv", "thomas_p": "k_thomas", "thomas_s": "k_thomas", "update": "k_update",
-                 "residual": "k_spmv", "sor": "k_sor_half"}
+                 "residual": "k_spmv", "sor": "k_sor_half", "thomas_p_cm": "k_thomas", "thomas_s_cm": "k_thomas"}
 PREC_NAME = {0: "fp64", 1: "fp32", 2: "bf16", 3: "fp16"}
 
 # HBM bytes per launch measured with rocprofv3 FETCH_SIZE and WRITE_SIZE on the 2560x1920x70
 # grid (`python bench.py --traffic-probe` under `rocprofv3 --pmc`), scaled by the same counters
 # on a device copy of known size (FETCH_SIZE x 2, WRITE_SIZE x 1).  Valid while the kernels
 # are unchanged since that measurement; see profiles/hbm_traffic_2560x1920x70.txt.
-MEASURED_TRAFFIC = {("c3", "spmv_fp64"): 28.74e9, ("c3", "spmv_fp32"): 14.65e9, ("c3", "spmv_bf16"): 9.82e9,
+MEASURED_TRAFFIC = {("c3", "spmv_fp64"): 28.74e9, ("c3", "spmv_fp32"): 14.67e9, ("c3", "spmv_bf16"): 9.82e9,
                     ("c3", "thomas_p_fp64"): 22.02e9, ("c3", "thomas_s_fp64"): 19.27e9, ("c3", "update_fp64"): 22.02e9,
                     ("c3", "thomas_p_fp32"): 11.01e9, ("c3", "thomas_s_fp32"): 9.63e9, ("c3", "update_fp32"): 11.01e9,
                     ("c3", "thomas_p_bf16"): 11.01e9, ("c3", "thomas_s_bf16"): 9.63e9, ("c3", "update_bf16"): 11.01e9,
-                    ("c3", "residual_fp64"): 27.29e9,
-                    # one SOR application = five half-sweeps
-                    ("c3", "sor_fp64"): 5 * 27.02e9, ("c3", "sor_fp32"): 5 * 11.85e9}
+                    ("c3", "residual_fp64"): 27.35e9,
+                    ("c3", "thomas_p_cm_fp64"): 24.78e9, ("c3", "thomas_s_cm_fp64"): 22.02e9,
+                    ("c3", "thomas_p_cm_fp32"): 12.39e9, ("c3", "thomas_s_cm_fp32"): 11.01e9,
+                    ("c3", "thomas_p_cm_bf16"): 12.39e9, ("c3", "thomas_s_cm_bf16"): 11.01e9,
+                    # one line-SOR application = five half-sweeps
+                    ("c3", "sor_fp64"): 95.94e9, ("c3", "sor_fp32"): 46.45e9, ("c3", "sor_bf16"): 39.57e9}
 
 
 def log(*a):
@@ -251,7 +260,7 @@ def main():
             x.zero_()
             op.solve(b, x, args.tol, 4, m)
         op.set_option("precond", 1)   # the line-SOR half-sweeps
-        for m in (eg.FP64, eg.FP32_IR):
+        for m in (eg.FP64, eg.FP32_IR, eg.FP32_IR_BF16):
             x.zero_()
             op.solve(b, x, args.tol, 2, m)
         op.set_option("precond", 0)
@@ -329,6 +338,22 @@ def main():
 
     op.set_option("profile", 1)
     op.reset_kernel_stats()
+    stats = {}   # (kernel name, precision) -> [launches, total ms]
+
+    def collect(sor):
+        # the library's HIP-event times of the last solve; in the line-SOR modes the
+        # tridiagonal kernels also write the colour-major copies (listed as *_cm)
+        for kname, ids in KERNEL_IDS.items():
+            key = f"{kname}_cm" if sor and kname in ("thomas_p", "thomas_s") else kname
+            for prec in range(4):
+                for kid in ids:
+                    c, t = op.kernel_stats(kid, prec)
+                    if c:
+                        e = stats.setdefault((key, prec), [0, 0.0])
+                        e[0] += c
+                        e[1] += t
+        op.reset_kernel_stats()
+
     per_mode = {name: {"seconds": [], "iterations": None, "outer_steps": None, "status": None,
                        "true_rel_residual": None} for name, _, _ in runs}
     torch.cuda.synchronize()
@@ -343,6 +368,7 @@ def main():
             torch.cuda.synchronize()
             d = per_mode[name]
             d["seconds"].append(time.perf_counter() - ts)
+            collect(sor)
             d.update(iterations=info.iterations, outer_steps=info.outer_steps, status=info.status,
                      true_rel_residual=info.true_rel_residual)
     torch.cuda.synchronize()
@@ -351,23 +377,18 @@ def main():
 
     # per-kernel achieved bandwidth from the library's HIP-event timing over the timed region
     kernels = {}
-    for kname, ids in KERNEL_IDS.items():
-        for prec in range(4):
-            cnt, ms = 0, 0.0
-            for kid in ids:
-                c, t = op.kernel_stats(kid, prec)
-                cnt += c
-                ms += t
-            if cnt == 0 or (kname != "sor" and prec not in BYTES_PER_POINT[kname]):
-                continue
-            bpp = SOR_HALF_BYTES[prec] * (2 * 3 - 1) if kname == "sor" else BYTES_PER_POINT[kname][prec]
-            bytes_launch = bpp * p.n
-            avg_ms = ms / cnt
-            kernels[f"{kname}_{PREC_NAME[prec]}"] = {
-                "symbol": KERNEL_SYMBOL[kname], "launches": cnt, "avg_ms": round(avg_ms, 4),
-                "total_ms": round(ms, 2), "bytes_per_launch": bytes_launch,
-                "gbs": round(bytes_launch / (avg_ms * 1e-3) / 1e9, 1),
-                "measured_bytes_per_launch": MEASURED_TRAFFIC.get((args.config, f"{kname}_{PREC_NAME[prec]}"))}
+    order = list(KERNEL_SYMBOL)
+    for (kname, prec), (cnt, ms) in sorted(stats.items(), key=lambda kv: (order.index(kv[0][0]), kv[0][1])):
+        if kname != "sor" and prec not in BYTES_PER_POINT[kname]:
+            continue
+        bpp = SOR_HALF_BYTES[prec] * (2 * 3 - 1) if kname == "sor" else BYTES_PER_POINT[kname][prec]
+        bytes_launch = bpp * p.n
+        avg_ms = ms / cnt
+        kernels[f"{kname}_{PREC_NAME[prec]}"] = {
+            "symbol": KERNEL_SYMBOL[kname], "launches": cnt, "avg_ms": round(avg_ms, 4),
+            "total_ms": round(ms, 2), "bytes_per_launch": bytes_launch,
+            "gbs": round(bytes_launch / (avg_ms * 1e-3) / 1e9, 1),
+            "measured_bytes_per_launch": MEASURED_TRAFFIC.get((args.config, f"{kname}_{PREC_NAME[prec]}"))}
     dom_name = max(kernels, key=lambda k: kernels[k]["total_ms"])
     dom = kernels[dom_name]
     traffic = MEASURED_TRAFFIC.get((args.config, dom_name))

@@ -102,6 +102,12 @@ enum ThomasMode { TH_PLAIN = 0, TH_P = 1, TH_S = 2 };
 template <typename Tv>
 void launch_thomas(const TriView<Tv> &tv, const Tv *q, Tv *z, int mode, const Tv *r, Tv *p, const Tv *v, Tv *rhat,
                    double *partials, int *nrows, const Scalars *sc, hipStream_t s, int stop_mask = 0);
+// The same with the result zcm = T^{-1} q, and q itself (qcm), written in the colour-major
+// order of the line-SOR kernels (nlon even): the start of a line-SOR application.
+template <typename Tv>
+void launch_thomas_cm(const TriView<Tv> &tv, int nlon, const Tv *q, Tv *zcm, Tv *qcm, int mode, const Tv *r, Tv *p,
+                      const Tv *v, Tv *rhat, double *partials, int *nrows, const Scalars *sc, hipStream_t s,
+                      int stop_mask = 0);
 // Red-black vertical-line SOR.  SorView: the LU factors of T (f[3]) and the W, E, S, N
 // couplings (a[4]) in colour-major order (index colour * n/2 + k * P/2 + j * nlon/2 + i/2).
 template <typename Tv, typename Tc> struct SorView {
@@ -110,11 +116,12 @@ template <typename Tv, typename Tc> struct SorView {
 };
 // reorder nd arrays of n values from grid order into colour-major order (nlon even)
 template <typename T> void launch_sor_perm(const T *src, T *dst, int nd, int nlon, int nlat, int nlev, hipStream_t s);
-// `sweeps` sweeps with relaxation omega applied to q; x must hold T^{-1} q on entry and
-// receives the result; wsc is an n-vector of scratch.
+// `sweeps` sweeps with relaxation omega applied to q.  qcm: q in colour-major order; xcm: T^{-1} q
+// in colour-major order on entry (launch_thomas_cm writes both), overwritten; wsc: n/2 values of
+// scratch; xout: the result in grid order.
 template <typename Tv, typename Tc>
-void launch_sor(const OpView<Tc> &op, const SorView<Tv, Tc> &sv, const Tv *q, Tv *x, Tv *wsc, int sweeps,
-                double omega, const Scalars *sc, int stop_mask, hipStream_t s);
+void launch_sor(const OpView<Tc> &op, const SorView<Tv, Tc> &sv, const Tv *qcm, Tv *xcm, Tv *wsc, Tv *xout,
+                int sweeps, double omega, const Scalars *sc, int stop_mask, hipStream_t s);
 template <typename Tf>
 void launch_tri_factor(const double *a64, const double *m64, int nlon, int nlat, int nlev, Tf *f, hipStream_t s);
 

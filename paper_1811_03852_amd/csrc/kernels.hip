@@ -377,13 +377,16 @@ void launch_tri_factor(const double *a64, const double *m64, int nlon, int nlat,
 // Prologues: TH_PLAIN  q read from `q`;
 //            TH_P      q = r + beta (p - omega v), stored to p (on a restart q = r and rhat = r);
 //            TH_S      q = r - alpha v, stored to s (passed as `p`), ||q||^2 partial.
+// CM: z is written in the colour-major order of the line-SOR kernels (index
+// colour * n/2 + k * P/2 + j * nlon/2 + i/2, colour = (i + j) & 1, nlon even) and q is also
+// stored there, to qcm: the start of a line-SOR application (both in one pass).
 // ------------------------------------------------------------------------------------------
-template <typename Tv, int NL, int MODE, int PF = 8>
+template <typename Tv, int NL, int MODE, bool CM, int PF = 8>
 __global__ __launch_bounds__(kWG) void k_thomas(TriView<Tv> tv, const Tv *__restrict__ q, Tv *__restrict__ z,
                                                 const Tv *__restrict__ r, Tv *__restrict__ p,
                                                 const Tv *__restrict__ v, Tv *__restrict__ rhat,
                                                 double *__restrict__ partials, const Scalars *__restrict__ sc,
-                                                int stop_mask)
+                                                int stop_mask, Tv *__restrict__ qcm, int nlon)
 {
     if (stopped(sc, stop_mask)) return;
     const long P = tv.P, n = tv.n;
@@ -392,6 +395,13 @@ __global__ __launch_bounds__(kWG) void k_thomas(TriView<Tv> tv, const Tv *__rest
     const bool act = col < P;
     // 32-bit lane offset within a level plane; per-level bases below are wave-uniform
     const unsigned cu = static_cast<unsigned>(act ? col : P - 1);
+    // colour-major element index of this column's level 0 (CM only) and the level stride
+    long cm0 = 0;
+    if constexpr (CM) {
+        const int i = (int)(cu % (unsigned)nlon), j = (int)(cu / (unsigned)nlon);
+        cm0 = (long)((i + j) & 1) * (n / 2) + (long)j * (nlon / 2) + i / 2;
+    }
+    const long P2 = P / 2;
     const Tv *lf = tv.f;
     const Tv *invf = tv.f + n;
     const Tv *cf = tv.f + 2 * n;
@@ -414,6 +424,8 @@ __global__ __launch_bounds__(kWG) void k_thomas(TriView<Tv> tv, const Tv *__rest
         // stop the compiler from hoisting all levels' loads (which would exhaust registers).
         const uint32_t step = static_cast<uint32_t>(P * sizeof(Tv));
         const uint32_t bo0 = cu * static_cast<uint32_t>(sizeof(Tv));
+        const uint32_t cstep = static_cast<uint32_t>(P2 * sizeof(Tv));
+        const uint32_t cbo0 = static_cast<uint32_t>(cm0 * (long)sizeof(Tv));
         auto ld = [](const Tv *base, uint32_t bo) { return ldn(base, bo); };
         auto st = [](Tv *base, uint32_t bo, Tv val) { stn(base, bo, val); };
         Tv w[NL];
@@ -440,6 +452,7 @@ __global__ __launch_bounds__(kWG) void k_thomas(TriView<Tv> tv, const Tv *__rest
 #pragma unroll
             for (int k = 0; k < PF && k < NL; ++k) issue(k);
             uint32_t bo = bo0;
+            uint32_t cbo = cbo0;
             Tv wprev = 0;
             double ss = 0.0;
 #pragma unroll
@@ -464,6 +477,10 @@ __global__ __launch_bounds__(kWG) void k_thomas(TriView<Tv> tv, const Tv *__rest
                     // sinks all the FP64 products to the end and keeps NL values live)
                     asm volatile("" : "+v"(ss));
                 }
+                if constexpr (CM) {
+                    st(qcm, cbo, qk);
+                    cbo += cstep;
+                }
                 w[k] = qk + bl[sl] * wprev;
                 wprev = w[k];
                 bo += step;
@@ -484,14 +501,14 @@ __global__ __launch_bounds__(kWG) void k_thomas(TriView<Tv> tv, const Tv *__rest
             bc[j] = ld(cf, bl_off);
             bl_off -= step;
         }
-        uint32_t bo = bo0 + static_cast<uint32_t>(NL - 1) * step;
+        uint32_t bo = CM ? cbo0 + static_cast<uint32_t>(NL - 1) * cstep : bo0 + static_cast<uint32_t>(NL - 1) * step;
         Tv zz = 0;
 #pragma unroll
         for (int k = NL - 1; k >= 0; --k) {
             const int sl = (NL - 1 - k) % PF;
             zz = bi[sl] * w[k] + bc[sl] * zz;
             st(z, bo, zz);
-            bo -= step;
+            bo -= CM ? cstep : step;
             if (k - PF >= 0) {
                 bi[sl] = ld(invf, bl_off);
                 bc[sl] = ld(cf, bl_off);
@@ -500,6 +517,8 @@ __global__ __launch_bounds__(kWG) void k_thomas(TriView<Tv> tv, const Tv *__rest
             __builtin_amdgcn_sched_barrier(0);
         }
     } else {
+        // z index of level k (the forward values are parked there between the sweeps)
+        auto zi = [&](int k) -> long { return CM ? cm0 + (long)k * P2 : (long)cu + (long)k * P; };
         Tv wprev = 0;
         for (int k = 0; k < nlev; ++k) {
             Tv qk;
@@ -521,59 +540,77 @@ __global__ __launch_bounds__(kWG) void k_thomas(TriView<Tv> tv, const Tv *__rest
                     acc[0] += static_cast<double>(qk) * static_cast<double>(qk);
                 }
             }
+            if constexpr (CM)
+                if (act) qcm[cm0 + (long)k * P2] = qk;
             wprev = qk + lv(lf, k)[cu] * wprev;
-            if (act) lv(z, k)[cu] = wprev;
+            if (act) z[zi(k)] = wprev;
         }
         if (act) {
             Tv zz = 0;
             for (int k = nlev - 1; k >= 0; --k) {
-                zz = lv(invf, k)[cu] * lv(z, k)[cu] + lv(cf, k)[cu] * zz;
-                lv(z, k)[cu] = zz;
+                zz = lv(invf, k)[cu] * z[zi(k)] + lv(cf, k)[cu] * zz;
+                z[zi(k)] = zz;
             }
         }
     }
     if constexpr (MODE == TH_S) block_sum_store<1>(acc, partials + (long)blockIdx.x * kPartialCols);
 }
 
-template <typename Tv, int NL>
+template <typename Tv, int NL, bool CM>
 static int thomas_dispatch_mode(const TriView<Tv> &tv, const Tv *q, Tv *z, int mode, const Tv *r, Tv *p,
                                 const Tv *v, Tv *rhat, double *partials, const Scalars *sc, hipStream_t s,
-                                int stop_mask)
+                                int stop_mask, Tv *qcm, int nlon)
 {
     const int nb = (int)((tv.P + kWG - 1) / kWG);
     switch (mode) {
     case TH_P:
-        hipLaunchKernelGGL((k_thomas<Tv, NL, TH_P>), dim3(nb), dim3(kWG), 0, s, tv, q, z, r, p, v, rhat, partials, sc,
-                           STOP_DONE);
+        hipLaunchKernelGGL((k_thomas<Tv, NL, TH_P, CM>), dim3(nb), dim3(kWG), 0, s, tv, q, z, r, p, v, rhat, partials,
+                           sc, STOP_DONE, qcm, nlon);
         return 0;
     case TH_S:
-        hipLaunchKernelGGL((k_thomas<Tv, NL, TH_S>), dim3(nb), dim3(kWG), 0, s, tv, q, z, r, p, v, rhat, partials, sc,
-                           STOP_DONE | STOP_SKIP);
+        hipLaunchKernelGGL((k_thomas<Tv, NL, TH_S, CM>), dim3(nb), dim3(kWG), 0, s, tv, q, z, r, p, v, rhat, partials,
+                           sc, STOP_DONE | STOP_SKIP, qcm, nlon);
         return nb;
     default:
-        hipLaunchKernelGGL((k_thomas<Tv, NL, TH_PLAIN>), dim3(nb), dim3(kWG), 0, s, tv, q, z, r, p, v, rhat, partials,
-                           sc, stop_mask);
+        hipLaunchKernelGGL((k_thomas<Tv, NL, TH_PLAIN, CM>), dim3(nb), dim3(kWG), 0, s, tv, q, z, r, p, v, rhat,
+                           partials, sc, stop_mask, qcm, nlon);
         return 0;
     }
+}
+
+template <typename Tv, bool CM>
+static int thomas_dispatch(const TriView<Tv> &tv, const Tv *q, Tv *z, int mode, const Tv *r, Tv *p, const Tv *v,
+                           Tv *rhat, double *partials, const Scalars *sc, hipStream_t s, int stop_mask, Tv *qcm,
+                           int nlon)
+{
+    // Register-resident forward values for the level counts in use, on grids whose columns
+    // fill whole workgroups and whose arrays are addressable with 32-bit byte offsets; any
+    // other grid takes the generic path.
+    const bool reg = (tv.P % kWG == 0) && ((unsigned long)tv.n * sizeof(Tv) < (1ul << 32));
+    if (reg && tv.nlev == 20)
+        return thomas_dispatch_mode<Tv, 20, CM>(tv, q, z, mode, r, p, v, rhat, partials, sc, s, stop_mask, qcm, nlon);
+    if (reg && tv.nlev == 70)
+        return thomas_dispatch_mode<Tv, 70, CM>(tv, q, z, mode, r, p, v, rhat, partials, sc, s, stop_mask, qcm, nlon);
+    if (reg && tv.nlev == 140 && sizeof(Tv) == 4)
+        return thomas_dispatch_mode<Tv, (sizeof(Tv) == 4 ? 140 : 0), CM>(tv, q, z, mode, r, p, v, rhat, partials, sc,
+                                                                          s, stop_mask, qcm, nlon);
+    return thomas_dispatch_mode<Tv, 0, CM>(tv, q, z, mode, r, p, v, rhat, partials, sc, s, stop_mask, qcm, nlon);
 }
 
 template <typename Tv>
 void launch_thomas(const TriView<Tv> &tv, const Tv *q, Tv *z, int mode, const Tv *r, Tv *p, const Tv *v, Tv *rhat,
                    double *partials, int *nrows, const Scalars *sc, hipStream_t s, int stop_mask)
 {
-    int rows;
-    // Register-resident forward values for the level counts in use, on grids whose columns
-    // fill whole workgroups and whose arrays are addressable with 32-bit byte offsets; any
-    // other grid takes the generic path.
-    const bool reg = (tv.P % kWG == 0) && ((unsigned long)tv.n * sizeof(Tv) < (1ul << 32));
-    if (reg && tv.nlev == 20)
-        rows = thomas_dispatch_mode<Tv, 20>(tv, q, z, mode, r, p, v, rhat, partials, sc, s, stop_mask);
-    else if (reg && tv.nlev == 70)
-        rows = thomas_dispatch_mode<Tv, 70>(tv, q, z, mode, r, p, v, rhat, partials, sc, s, stop_mask);
-    else if (reg && tv.nlev == 140 && sizeof(Tv) == 4)
-        rows = thomas_dispatch_mode<Tv, (sizeof(Tv) == 4 ? 140 : 0)>(tv, q, z, mode, r, p, v, rhat, partials, sc, s, stop_mask);
-    else
-        rows = thomas_dispatch_mode<Tv, 0>(tv, q, z, mode, r, p, v, rhat, partials, sc, s, stop_mask);
+    const int rows = thomas_dispatch<Tv, false>(tv, q, z, mode, r, p, v, rhat, partials, sc, s, stop_mask, nullptr, 0);
+    if (nrows) *nrows = rows;
+}
+
+template <typename Tv>
+void launch_thomas_cm(const TriView<Tv> &tv, int nlon, const Tv *q, Tv *zcm, Tv *qcm, int mode, const Tv *r, Tv *p,
+                      const Tv *v, Tv *rhat, double *partials, int *nrows, const Scalars *sc, hipStream_t s,
+                      int stop_mask)
+{
+    const int rows = thomas_dispatch<Tv, true>(tv, q, zcm, mode, r, p, v, rhat, partials, sc, s, stop_mask, qcm, nlon);
     if (nrows) *nrows = rows;
 }
 
@@ -1310,20 +1347,22 @@ void launch_quantize(int kind, int nlon, int nlat, int nlev, const double *a64, 
 //     x_c <- (1 - omega) x_c + omega T_c^{-1} (q_c + sum of its horizontal couplings times x)
 // With nlon even every horizontal neighbour has the other colour, so the columns of one colour
 // are independent: one lane per column, the rhs gathered level by level on the way up, w_k of
-// the Thomas forward sweep parked in a colour-major scratch vector (coalesced), the blend done
-// on the way down.
+// the Thomas forward sweep parked in a scratch vector, the blend done on the way down.
 //
-// Layout: the operator constants a half-sweep reads for its own columns (the three LU factors
-// of T and the W, E, S, N couplings) are kept a second time in colour-major order,
-// index = colour * n/2 + k * P/2 + c2 with c2 = j * nlon/2 + i/2, so the lanes of a wave read
-// them contiguously; q and x stay in grid order (the neighbours of a column are the other
-// colour's entries of the same cache lines and rows).
+// Layout: everything a half-sweep touches is in colour-major order,
+// index = colour * n/2 + k * P/2 + c2 with c2 = j * nlon/2 + i/2: the operator constants (the
+// three LU factors of T and the W, E, S, N couplings, a second copy made once), q and x.  The
+// lanes of a wave hold 64 consecutive columns of one colour in a latitude row, so every access
+// is unit-stride: own constants, q and x at c2, the other colour's west/east neighbours at
+// c2 - 1 + par and c2 + par (par = parity of i; with the periodic wrap in longitude) and its
+// south/north neighbours at c2 -/+ nlon/2.  The tridiagonal kernel writes T^{-1} q and q in this
+// order (k_thomas with CM); the last half-sweep writes the result in grid order, each lane the
+// pair of grid columns 2m, 2m + 1 of its row (its own column and the other colour's partner).
 //
-// The first half-sweep from x = 0 is omega T^{-1} q on the red columns; the caller has already
-// computed T^{-1} q for every column (the tridiagonal kernel it fuses with the BiCGStab axpy),
-// so the chain starts at the first black half-sweep and reads the red values with the factor
-// omega applied on the fly (nb_scale), and the next red half-sweep reads its own old value the
-// same way (own_scale).  With a single sweep the red values are scaled at the end.
+// The first half-sweep from x = 0 is omega T^{-1} q on the red columns; the tridiagonal kernel
+// has already computed T^{-1} q for every column, so the chain starts at the first black
+// half-sweep and reads the red values with the factor omega applied on the fly (nb_scale),
+// and the next red half-sweep reads its own old value the same way (own_scale).
 // ------------------------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(kWG) void k_sor_perm(const T *__restrict__ src, T *__restrict__ dst, int nd, int nlon,
@@ -1342,36 +1381,38 @@ __global__ __launch_bounds__(kWG) void k_sor_perm(const T *__restrict__ src, T *
     }
 }
 
-template <typename Tv, typename Tc, int NL>
-__global__ __launch_bounds__(kWG) void k_sor_half(OpView<Tc> op, SorView<Tv, Tc> sv, const Tv *__restrict__ q,
-                                                  Tv *__restrict__ x, Tv *__restrict__ wsc, int colour, Tv omega,
-                                                  Tv nb_scale, Tv own_scale, const Scalars *__restrict__ sc,
-                                                  int stop_mask, int per_xcd)
+template <typename Tv, typename Tc, bool LAST>
+__global__ __launch_bounds__(kWG) void k_sor_half(OpView<Tc> op, SorView<Tv, Tc> sv, const Tv *__restrict__ qcm,
+                                                  Tv *__restrict__ xcm, Tv *__restrict__ wsc, Tv *__restrict__ xout,
+                                                  int colour, Tv omega, Tv nb_scale, Tv own_scale,
+                                                  const Scalars *__restrict__ sc, int stop_mask, int per_xcd)
 {
     if (stopped(sc, stop_mask)) return;
     using V = typename CoefTraits<Tc>::val;
     constexpr bool Q = CoefTraits<Tc>::quant;
-    const int nlon = op.nlon, nlat = op.nlat;
-    const int nlev = (NL > 0) ? NL : op.nlev;
-    const int half = nlon / 2;
-    const long P = op.P, n = op.n, P2 = P / 2;
+    const int nlat = op.nlat, nlev = op.nlev;
+    const int half = op.nlon / 2;
+    const long P = op.P, n = op.n, P2 = P / 2, n2 = n / 2;
     // XCD-aware: workgroups go round-robin over the 8 XCDs, so workgroup b takes the logical
     // block (b % 8) * per_xcd + b / 8 and each XCD walks a contiguous band of latitude rows,
     // whose north and south neighbour rows its own L2 then holds
     const long lb = (long)(blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
     const long c2 = lb * kWG + threadIdx.x;
     if (c2 >= P2) return;
-    const int j = (int)(c2 / half);
-    const int i = 2 * (int)(c2 % half) + ((j + colour) & 1);
-    const int iw = (i == 0) ? nlon - 1 : i - 1;
-    const int ie = (i == nlon - 1) ? 0 : i + 1;
-    const long col = (long)j * nlon + i;
-    const long pb = (long)colour * (n / 2) + c2;   // colour-major index of level 0
+    const int j = (int)(c2 / half), m = (int)(c2 % half);
+    const int par = (j + colour) & 1;   // own grid column i = 2m + par
+    // the other colour's west / east neighbours in this row (periodic in longitude)
+    const long cw = (long)j * half + (par ? m : (m == 0 ? half - 1 : m - 1));
+    const long ce = (long)j * half + (par ? (m == half - 1 ? 0 : m + 1) : m);
+    const long own = (long)colour * n2 + c2;
+    const Tv *oth = xcm + (long)(1 - colour) * n2;
+    const bool hs = j > 0, hn = j < nlat - 1;
     const Tv *lf = sv.f, *invf = sv.f + n, *cf = sv.f + 2 * n;
     const Tc *aWp = sv.a, *aEp = sv.a + n, *aSp = sv.a + 2 * n, *aNp = sv.a + 3 * n;
-    const bool hs = j > 0, hn = j < nlat - 1;
-    auto rhs_at = [&](int k) -> Tv {
-        const long c = col + (long)k * P, pi = pb + (long)k * P2;
+    Tv wprev = 0;
+    for (int k = 0; k < nlev; ++k) {
+        const long pi = own + (long)k * P2;
+        const Tv *ok = oth + (long)k * P2;
         float s0 = 1.f, s1 = 1.f, s2 = 1.f, s3 = 1.f;
         if constexpr (Q) {
             const float *qr = op.qs + ((size_t)k * nlat + j) * kQsStride;
@@ -1382,59 +1423,32 @@ __global__ __launch_bounds__(kWG) void k_sor_half(OpView<Tc> op, SorView<Tv, Tc>
         }
         const V aW = DecB<Tc>::get(aWp + pi, 0, s0);
         const V aE = DecB<Tc>::get(aEp + pi, 0, s1);
-        Tv h = aW * x[c - i + iw] + aE * x[c - i + ie];
-        if (hs) h += static_cast<Tv>(DecB<Tc>::get(aSp + pi, 0, s2)) * x[c - nlon];
-        if (hn) h += static_cast<Tv>(DecB<Tc>::get(aNp + pi, 0, s3)) * x[c + nlon];
-        return q[c] + nb_scale * h;
-    };
-    const Tv keep = (Tv(1) - omega) * own_scale;
-    if constexpr (NL > 0) {
-        Tv w[NL];
-        Tv wprev = 0;
-#pragma unroll
-        for (int k = 0; k < NL; ++k) {
-            w[k] = rhs_at(k) + lf[pb + (long)k * P2] * wprev;
-            wprev = w[k];
-        }
-        Tv ynext = 0;
-#pragma unroll
-        for (int k = NL - 1; k >= 0; --k) {
-            const long c = col + (long)k * P, pi = pb + (long)k * P2;
-            const Tv y = invf[pi] * w[k] + cf[pi] * ynext;
-            const Tv old = (own_scale == Tv(0)) ? Tv(0) : x[c];
-            x[c] = keep * old + omega * y;
-            ynext = y;
-        }
-    } else {
-        Tv wprev = 0;
-        for (int k = 0; k < nlev; ++k) {
-            const long pi = pb + (long)k * P2;
-            const Tv w = rhs_at(k) + lf[pi] * wprev;
-            wsc[pi] = w;
-            wprev = w;
-        }
-        Tv ynext = 0;
-        for (int k = nlev - 1; k >= 0; --k) {
-            const long c = col + (long)k * P, pi = pb + (long)k * P2;
-            const Tv y = invf[pi] * wsc[pi] + cf[pi] * ynext;
-            const Tv old = (own_scale == Tv(0)) ? Tv(0) : x[c];
-            x[c] = keep * old + omega * y;
-            ynext = y;
-        }
+        Tv h = aW * ok[cw] + aE * ok[ce];
+        if (hs) h += static_cast<Tv>(DecB<Tc>::get(aSp + pi, 0, s2)) * ok[c2 - half];
+        if (hn) h += static_cast<Tv>(DecB<Tc>::get(aNp + pi, 0, s3)) * ok[c2 + half];
+        const Tv rhs = __builtin_nontemporal_load(qcm + pi) + nb_scale * h;
+        const Tv w = rhs + __builtin_nontemporal_load(lf + pi) * wprev;
+        __builtin_nontemporal_store(w, wsc + c2 + (long)k * P2);
+        wprev = w;
     }
-}
-
-// x <- factor * x on the columns of one colour (all levels)
-template <typename Tv>
-__global__ __launch_bounds__(kWG) void k_sor_scale(long P, long n, int nlon, Tv *__restrict__ x, int colour,
-                                                   Tv factor, const Scalars *__restrict__ sc, int stop_mask)
-{
-    if (stopped(sc, stop_mask)) return;
-    const long stride = (long)gridDim.x * kWG;
-    for (long c = (long)blockIdx.x * kWG + threadIdx.x; c < n; c += stride) {
-        const long pc = c % P;
-        const int i = (int)(pc % nlon), j = (int)(pc / nlon);
-        if (((i + j) & 1) == colour) x[c] *= factor;
+    const Tv keep = (Tv(1) - omega) * own_scale;
+    Tv ynext = 0;
+    for (int k = nlev - 1; k >= 0; --k) {
+        const long pi = own + (long)k * P2;
+        const Tv y = __builtin_nontemporal_load(invf + pi) * __builtin_nontemporal_load(wsc + c2 + (long)k * P2) +
+                     __builtin_nontemporal_load(cf + pi) * ynext;
+        const Tv old = (own_scale == Tv(0)) ? Tv(0) : xcm[pi];
+        const Tv val = keep * old + omega * y;
+        if constexpr (LAST) {
+            // grid columns 2m and 2m + 1 of row j: this column (2m + par) and its partner of
+            // the other colour, which has the same c2; the wave writes whole cache lines
+            Tv *o = xout + (long)k * P + 2 * c2;
+            __builtin_nontemporal_store(val, o + par);
+            __builtin_nontemporal_store(nb_scale * oth[(long)k * P2 + c2], o + (1 - par));
+        } else {
+            xcm[pi] = val;
+        }
+        ynext = y;
     }
 }
 
@@ -1446,24 +1460,26 @@ template <typename T> void launch_sor_perm(const T *src, T *dst, int nd, int nlo
 }
 
 template <typename Tv, typename Tc>
-void launch_sor(const OpView<Tc> &op, const SorView<Tv, Tc> &sv, const Tv *q, Tv *x, Tv *wsc, int sweeps,
-                double omega, const Scalars *sc, int stop_mask, hipStream_t s)
+void launch_sor(const OpView<Tc> &op, const SorView<Tv, Tc> &sv, const Tv *qcm, Tv *xcm, Tv *wsc, Tv *xout,
+                int sweeps, double omega, const Scalars *sc, int stop_mask, hipStream_t s)
 {
     const long half_cols = op.P / 2;
     const long lblocks = (half_cols + kWG - 1) / kWG;
     const int per_xcd = (int)((lblocks + 7) / 8);
     const unsigned blocks = (unsigned)(per_xcd * 8);
     const Tv w = static_cast<Tv>(omega);
-    for (int h = 1; h < 2 * sweeps; ++h) {
+    const int last = 2 * sweeps - 1;
+    for (int h = 1; h <= last; ++h) {
         const int colour = (h & 1) ? 1 : 0;                       // odd: black, even: red
         const Tv nb_scale = (h == 1) ? w : Tv(1);                 // red still holds T^{-1} q
         const Tv own_scale = (h == 1) ? Tv(0) : (h == 2 ? w : Tv(1));
-        hipLaunchKernelGGL((k_sor_half<Tv, Tc, 0>), dim3(blocks), dim3(kWG), 0, s, op, sv, q, x, wsc, colour, w,
-                           nb_scale, own_scale, sc, stop_mask, per_xcd);
+        if (h == last)
+            hipLaunchKernelGGL((k_sor_half<Tv, Tc, true>), dim3(blocks), dim3(kWG), 0, s, op, sv, qcm, xcm, wsc, xout,
+                               colour, w, nb_scale, own_scale, sc, stop_mask, per_xcd);
+        else
+            hipLaunchKernelGGL((k_sor_half<Tv, Tc, false>), dim3(blocks), dim3(kWG), 0, s, op, sv, qcm, xcm, wsc,
+                               xout, colour, w, nb_scale, own_scale, sc, stop_mask, per_xcd);
     }
-    if (sweeps == 1)
-        hipLaunchKernelGGL((k_sor_scale<Tv>), dim3(elementwise_blocks(op.n)), dim3(kWG), 0, s, op.P, op.n, op.nlon, x,
-                           0, w, sc, stop_mask);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -1486,6 +1502,12 @@ template void launch_thomas<double>(const TriView<double> &, const double *, dou
                                     int);
 template void launch_thomas<float>(const TriView<float> &, const float *, float *, int, const float *, float *,
                                    const float *, float *, double *, int *, const Scalars *, hipStream_t, int);
+template void launch_thomas_cm<double>(const TriView<double> &, int, const double *, double *, double *, int,
+                                       const double *, double *, const double *, double *, double *, int *,
+                                       const Scalars *, hipStream_t, int);
+template void launch_thomas_cm<float>(const TriView<float> &, int, const float *, float *, float *, int,
+                                      const float *, float *, const float *, float *, double *, int *,
+                                      const Scalars *, hipStream_t, int);
 template void launch_tri_factor<double>(const double *, const double *, int, int, int, double *, hipStream_t);
 template void launch_tri_factor<float>(const double *, const double *, int, int, int, float *, hipStream_t);
 template void launch_update<double>(long, double *, const double *, const double *, const double *, const double *,
@@ -1507,13 +1529,13 @@ template int launch_maxpy<float>(long, float *, const float *, int, int, const d
 template void launch_vscale<double>(long, const double *, double *, const double *, hipStream_t);
 template void launch_vscale<float>(long, const float *, float *, const double *, hipStream_t);
 template void launch_sor<double, double>(const OpView<double> &, const SorView<double, double> &, const double *,
-                                         double *, double *, int, double, const Scalars *, int, hipStream_t);
+                                         double *, double *, double *, int, double, const Scalars *, int, hipStream_t);
 template void launch_sor<float, float>(const OpView<float> &, const SorView<float, float> &, const float *, float *,
-                                       float *, int, double, const Scalars *, int, hipStream_t);
+                                       float *, float *, int, double, const Scalars *, int, hipStream_t);
 template void launch_sor<float, bf16_t>(const OpView<bf16_t> &, const SorView<float, bf16_t> &, const float *,
-                                        float *, float *, int, double, const Scalars *, int, hipStream_t);
+                                        float *, float *, float *, int, double, const Scalars *, int, hipStream_t);
 template void launch_sor<float, fp16_t>(const OpView<fp16_t> &, const SorView<float, fp16_t> &, const float *,
-                                        float *, float *, int, double, const Scalars *, int, hipStream_t);
+                                        float *, float *, float *, int, double, const Scalars *, int, hipStream_t);
 template void launch_sor_perm<double>(const double *, double *, int, int, int, int, hipStream_t);
 template void launch_sor_perm<float>(const float *, float *, int, int, int, int, hipStream_t);
 template void launch_sor_perm<uint16_t>(const uint16_t *, uint16_t *, int, int, int, int, hipStream_t);

@@ -133,7 +133,9 @@ struct eg_operator {
     int sor_sweeps = 3;
     double sor_omega = 1.5;
     bool sor_on = false;        // SOR active in the current solve (plain modes with precond 1)
-    double *sor_scratch = nullptr;   // n doubles, for eg_apply_precond
+    // line-SOR work vectors in colour-major order: x (n), q (n) and the parked forward
+    // values (n/2), room for FP64 (5n/2 doubles)
+    double *sor_ws = nullptr;
     double *mp_x = nullptr;     // EG_FP32_MP: the FP64 solution the FP32 iteration updates
     double *ir_backup = nullptr;   // refinement: x before the last correction
     bool mp_active = false;
@@ -175,6 +177,9 @@ struct eg_operator {
     {
         return {reinterpret_cast<const Tq *>(aq[slot]), m32, qs[slot], nlon, nlat, nlev, P, n};
     }
+    template <typename Tv> Tv *sor_x() const { return reinterpret_cast<Tv *>(sor_ws); }
+    template <typename Tv> Tv *sor_q() const { return reinterpret_cast<Tv *>(sor_ws) + n; }
+    template <typename Tv> Tv *sor_w() const { return reinterpret_cast<Tv *>(sor_ws) + 2 * n; }
     template <typename Tv, typename Tc> SorView<Tv, Tc> sor_view() const
     {
         if constexpr (std::is_same_v<Tc, double>) return {sorf64, sora64};
@@ -226,6 +231,7 @@ template <typename Tc> int ensure_sor(eg_operator *op)
     int rc;
     const size_t n = (size_t)op->n;
     hipStream_t s = op->stream;
+    if (!op->sor_ws && (rc = dalloc(&op->sor_ws, n * 5 / 2))) return rc;
     if constexpr (std::is_same_v<Tc, double>) {
         if (op->sorf64) return 0;
         if ((rc = dalloc(&op->sorf64, 3 * n)) || (rc = dalloc(&op->sora64, 4 * n))) return rc;
@@ -333,13 +339,19 @@ void enqueue_iteration(eg_operator *op, const OpView<Tc> &A, Work<Tv> &w, hipEve
     auto mark = [&](int i) {
         if (ev) (void)hipEventRecord(ev[i], s);
     };
+    const bool sor = op->sor_on;
+    Tv *xcm = sor ? op->sor_x<Tv>() : nullptr, *qcm = sor ? op->sor_q<Tv>() : nullptr;
+    Tv *wsc = sor ? op->sor_w<Tv>() : nullptr;
     mark(0);
-    launch_thomas<Tv>(T, nullptr, w.ph, TH_P, w.r, w.p, w.v, w.rh, op->partials, &nr, op->sc, s);
+    if (sor)
+        launch_thomas_cm<Tv>(T, op->nlon, nullptr, xcm, qcm, TH_P, w.r, w.p, w.v, w.rh, op->partials, &nr, op->sc, s);
+    else
+        launch_thomas<Tv>(T, nullptr, w.ph, TH_P, w.r, w.p, w.v, w.rh, op->partials, &nr, op->sc, s);
     mark(1);
-    if (op->sor_on) {   // t is free until the second product of the iteration
+    if (sor) {
         mark(12);
-        launch_sor<Tv, Tc>(A, op->sor_view<Tv, Tc>(), w.p, w.ph, w.t, op->sor_sweeps, op->sor_omega, op->sc, STOP_DONE,
-                           s);
+        launch_sor<Tv, Tc>(A, op->sor_view<Tv, Tc>(), qcm, xcm, wsc, w.ph, op->sor_sweeps, op->sor_omega, op->sc,
+                           STOP_DONE, s);
         mark(13);
     }
     mark(2);
@@ -347,12 +359,15 @@ void enqueue_iteration(eg_operator *op, const OpView<Tc> &A, Work<Tv> &w, hipEve
     mark(3);
     launch_finalize(FIN_SIGMA, op->partials, nr, op->sc, op->d_hist, nullptr, 0, 0, s);
     mark(4);
-    launch_thomas<Tv>(T, nullptr, w.sh, TH_S, w.r, w.s, w.v, nullptr, op->partials, &nr, op->sc, s);
+    if (sor)
+        launch_thomas_cm<Tv>(T, op->nlon, nullptr, xcm, qcm, TH_S, w.r, w.s, w.v, nullptr, op->partials, &nr, op->sc, s);
+    else
+        launch_thomas<Tv>(T, nullptr, w.sh, TH_S, w.r, w.s, w.v, nullptr, op->partials, &nr, op->sc, s);
     mark(5);
     launch_finalize(FIN_S, op->partials, nr, op->sc, op->d_hist, nullptr, 0, 0, s);
-    if (op->sor_on) {
+    if (sor) {
         mark(14);
-        launch_sor<Tv, Tc>(A, op->sor_view<Tv, Tc>(), w.s, w.sh, w.t, op->sor_sweeps, op->sor_omega, op->sc,
+        launch_sor<Tv, Tc>(A, op->sor_view<Tv, Tc>(), qcm, xcm, wsc, w.sh, op->sor_sweeps, op->sor_omega, op->sc,
                            STOP_DONE | STOP_SKIP | STOP_HALF, s);
         mark(15);
     }
@@ -602,10 +617,16 @@ int fgmres(eg_operator *op, const OpView<Tc> &A, Tv *d, double nb, double tol, i
         int jend = -1;
         for (int j = 0; j < m; ++j) {
             Tv *Vj = F.V + (size_t)j * n, *Zj = F.Z + (size_t)j * n;
-            launch_thomas<Tv>(T, Vj, Zj, TH_PLAIN, nullptr, nullptr, nullptr, nullptr, op->partials, nullptr, nullptr, s);
-            if (op->sor_on && !use_net)
-                launch_sor<Tv, Tc>(A, op->sor_view<Tv, Tc>(), Vj, Zj, F.tmp, op->sor_sweeps, op->sor_omega, nullptr, 0,
-                                   s);
+            if (op->sor_on && !use_net) {
+                Tv *xcm = op->sor_x<Tv>(), *qcm = op->sor_q<Tv>();
+                launch_thomas_cm<Tv>(T, op->nlon, Vj, xcm, qcm, TH_PLAIN, nullptr, nullptr, nullptr, nullptr,
+                                     op->partials, nullptr, nullptr, s);
+                launch_sor<Tv, Tc>(A, op->sor_view<Tv, Tc>(), qcm, xcm, op->sor_w<Tv>(), Zj, op->sor_sweeps,
+                                   op->sor_omega, nullptr, 0, s);
+            } else {
+                launch_thomas<Tv>(T, Vj, Zj, TH_PLAIN, nullptr, nullptr, nullptr, nullptr, op->partials, nullptr,
+                                  nullptr, s);
+            }
             if constexpr (std::is_same_v<Tc, float> || std::is_same_v<Tc, double>)
                 if (use_net) enqueue_net_stage<Tv, Tc>(op, net, coef, Vj, Zj, qp, nullptr, 0);
             launch_spmv<Tv, Tc>(A, Zj, F.W, nullptr, SP_PLAIN, op->partials, nullptr, nullptr, 0, s);
@@ -1100,7 +1121,7 @@ void eg_destroy_operator(eg_operator *op)
     dfree(op->harvest_x);
     for (Fgm<double> *F : {&op->f64}) { dfree(F->V); dfree(F->Z); dfree(F->W); dfree(F->R); dfree(F->tmp); }
     for (Fgm<float> *F : {&op->f32}) { dfree(F->V); dfree(F->Z); dfree(F->W); dfree(F->R); dfree(F->tmp); }
-    dfree(op->d_h); dfree(op->mpart); dfree(op->sor_scratch); dfree(op->mp_x); dfree(op->ir_backup);
+    dfree(op->d_h); dfree(op->mpart); dfree(op->sor_ws); dfree(op->mp_x); dfree(op->ir_backup);
     dfree(op->sorf64); dfree(op->sora64); dfree(op->sorf32); dfree(op->sora32); dfree(op->sorq[0]); dfree(op->sorq[1]);
     if (op->h_h) (void)hipHostFree(op->h_h);
     dfree(op->w64.qp);
@@ -1365,38 +1386,46 @@ int eg_apply_precond(eg_operator *op, const void *q, void *z, int prec)
     if (prec < EG_PREC_FP64 || prec > EG_PREC_FP16) return fail(EG_EINVAL, "unknown precision");
     int rc;
     const bool sor = op->precond == 1;
-    if (sor && !op->sor_scratch && (rc = dalloc(&op->sor_scratch, (size_t)op->n))) return rc;
+    hipStream_t s = op->stream;
     if (prec == EG_PREC_FP64) {
         const double *qd = static_cast<const double *>(q);
         double *zd = static_cast<double *>(z);
-        launch_thomas<double>(op->tri_view64(), qd, zd, TH_PLAIN, nullptr, nullptr, nullptr, nullptr, op->partials,
-                              nullptr, nullptr, op->stream);
         if (sor) {
             if ((rc = ensure_sor<double>(op))) return rc;
-            launch_sor<double, double>(op->view64(), op->sor_view<double, double>(), qd, zd, op->sor_scratch,
-                                       op->sor_sweeps, op->sor_omega, nullptr, 0, op->stream);
+            launch_thomas_cm<double>(op->tri_view64(), op->nlon, qd, op->sor_x<double>(), op->sor_q<double>(),
+                                     TH_PLAIN, nullptr, nullptr, nullptr, nullptr, op->partials, nullptr, nullptr, s);
+            launch_sor<double, double>(op->view64(), op->sor_view<double, double>(), op->sor_q<double>(),
+                                       op->sor_x<double>(), op->sor_w<double>(), zd, op->sor_sweeps, op->sor_omega,
+                                       nullptr, 0, s);
+        } else {
+            launch_thomas<double>(op->tri_view64(), qd, zd, TH_PLAIN, nullptr, nullptr, nullptr, nullptr,
+                                  op->partials, nullptr, nullptr, s);
         }
     } else {
         // every lower-precision set uses the FP32 rounding of the FP64 factors
         if ((rc = ensure_fp32(op))) return rc;
         const float *qf = static_cast<const float *>(q);
-        float *zf = static_cast<float *>(z), *wf = reinterpret_cast<float *>(op->sor_scratch);
-        launch_thomas<float>(op->tri_view32(), qf, zf, TH_PLAIN, nullptr, nullptr, nullptr, nullptr, op->partials,
-                             nullptr, nullptr, op->stream);
+        float *zf = static_cast<float *>(z);
         if (sor) {
-            if (prec == EG_PREC_FP32) {
-                if ((rc = ensure_sor<float>(op))) return rc;
-                launch_sor<float, float>(op->view32(), op->sor_view<float, float>(), qf, zf, wf, op->sor_sweeps,
-                                         op->sor_omega, nullptr, 0, op->stream);
-            } else if (prec == EG_PREC_BF16) {
-                if ((rc = ensure_sor<bf16_t>(op))) return rc;
-                launch_sor<float, bf16_t>(op->viewq<bf16_t>(0), op->sor_view<float, bf16_t>(), qf, zf, wf,
-                                          op->sor_sweeps, op->sor_omega, nullptr, 0, op->stream);
-            } else {
-                if ((rc = ensure_sor<fp16_t>(op))) return rc;
-                launch_sor<float, fp16_t>(op->viewq<fp16_t>(1), op->sor_view<float, fp16_t>(), qf, zf, wf,
-                                          op->sor_sweeps, op->sor_omega, nullptr, 0, op->stream);
-            }
+            if (prec == EG_PREC_FP32) rc = ensure_sor<float>(op);
+            else if (prec == EG_PREC_BF16) rc = ensure_sor<bf16_t>(op);
+            else rc = ensure_sor<fp16_t>(op);
+            if (rc) return rc;
+            float *xcm = op->sor_x<float>(), *qcm = op->sor_q<float>(), *wsc = op->sor_w<float>();
+            launch_thomas_cm<float>(op->tri_view32(), op->nlon, qf, xcm, qcm, TH_PLAIN, nullptr, nullptr, nullptr,
+                                    nullptr, op->partials, nullptr, nullptr, s);
+            if (prec == EG_PREC_FP32)
+                launch_sor<float, float>(op->view32(), op->sor_view<float, float>(), qcm, xcm, wsc, zf,
+                                         op->sor_sweeps, op->sor_omega, nullptr, 0, s);
+            else if (prec == EG_PREC_BF16)
+                launch_sor<float, bf16_t>(op->viewq<bf16_t>(0), op->sor_view<float, bf16_t>(), qcm, xcm, wsc, zf,
+                                          op->sor_sweeps, op->sor_omega, nullptr, 0, s);
+            else
+                launch_sor<float, fp16_t>(op->viewq<fp16_t>(1), op->sor_view<float, fp16_t>(), qcm, xcm, wsc, zf,
+                                          op->sor_sweeps, op->sor_omega, nullptr, 0, s);
+        } else {
+            launch_thomas<float>(op->tri_view32(), qf, zf, TH_PLAIN, nullptr, nullptr, nullptr, nullptr, op->partials,
+                                 nullptr, nullptr, s);
         }
     }
     EG_HIP(hipGetLastError());
