@@ -1,7 +1,8 @@
 """Parity at the benchmark's full sizes, in the launch configuration bench.py times.
 
 2560x1920x70 (344M unknowns): SpMV and Thomas outputs on sampled rows and columns against the
-oracle computed one row / one column at a time; every solver mode's true residual recomputed
+oracle computed one row / one column at a time; the line SOR on sampled columns against the
+oracle on a window around each; every solver mode's true residual recomputed
 by the oracle's full FP64 matrix-vector product on the host; the modes' solutions against each
 other.  640x480x70 with a manufactured solution: forward error against x*.
 """
@@ -104,6 +105,56 @@ def test_thomas_sampled_columns(eg, oracle_mod, c3):
             kappa = 2 * sub[6].reshape(p.nlev, -1).max(axis=0) / tmin
             err = np.abs(z - ref).reshape(p.nlev, -1).max(axis=0)
             assert np.all(err <= 32 * p.nlev * EPS64 * kappa * np.abs(ref).reshape(p.nlev, -1).max(axis=0))
+
+
+def _sor_window(coef, q, nlon, nlat, i0, j0, radius):
+    """The columns within `radius` of (i0, j0) as a sub-grid whose colouring matches the full
+    grid's ((i + j) parity) and whose longitude count is even; returns the sub-problem and the
+    position of (i0, j0) in it."""
+    j_lo, j_hi = max(0, j0 - radius), min(nlat, j0 + radius + 1)
+    i_lo = i0 - radius
+    if (i_lo + j_lo) % 2:
+        i_lo -= 1
+    ii = np.arange(i_lo, i_lo + 2 * radius + 2) % nlon
+    jj = np.arange(j_lo, j_hi)
+    sub = np.ascontiguousarray(coef[:, :, jj][:, :, :, ii])
+    qs = np.ascontiguousarray(q[:, jj][:, :, ii])
+    return sub, qs, j0 - j_lo, i0 - i_lo
+
+
+def test_line_sor_sampled_columns(eg, oracle_mod, c3):
+    """The red-black line SOR (3 sweeps, omega 1.5, the kernels and launch shape of the solver)
+    on sampled columns.  After the five half-sweeps that follow the tridiagonal solve, a column
+    depends only on the columns within 5 steps of it; the oracle runs on a window of radius 6
+    around each sample (its edges, where the window cuts couplings, are wrong but cannot reach
+    the centre) and its centre column is compared with the GPU's, all 70 levels."""
+    import torch
+    p, coef, _, op = c3
+    rng = np.random.default_rng(34)
+    q = rng.standard_normal(p.n)
+    qd = torch.from_numpy(q).cuda()
+    op.set_option("precond", 1)
+    try:
+        z64 = host(op.precond(qd)).reshape(p.nlev, p.nlat, p.nlon)
+        z32 = host(op.precond(qd.float(), prec=eg.PREC_FP32)).astype(np.float64).reshape(p.nlev, p.nlat, p.nlon)
+    finally:
+        op.set_option("precond", 0)
+    q3 = q.reshape(p.nlev, p.nlat, p.nlon)
+    q32 = q3.astype(np.float32).astype(np.float64)
+    samples = [(int(i), int(j)) for i, j in zip(rng.integers(0, p.nlon, 40), rng.integers(0, p.nlat, 40))]
+    samples += [(0, 0), (p.nlon - 1, 0), (0, p.nlat - 1), (p.nlon - 1, p.nlat - 1), (1, 1), (p.nlon - 2, 7)]
+    worst64 = worst32 = 0.0
+    for i0, j0 in samples:
+        sub, qs, jc, ic = _sor_window(coef, q3, p.nlon, p.nlat, i0, j0, 6)
+        ref = oracle_mod.rbsor(sub, qs.ravel(), sweeps=3, omega=1.5).reshape(sub.shape[1:])[:, jc, ic]
+        scale = np.max(np.abs(ref))
+        worst64 = max(worst64, np.max(np.abs(z64[:, j0, i0] - ref)) / scale)
+        # FP32: vectors and factors rounded to FP32; the oracle on the FP32 input vector
+        sub32, qs32, _, _ = _sor_window(coef, q32, p.nlon, p.nlat, i0, j0, 6)
+        ref32 = oracle_mod.rbsor(sub32, qs32.ravel(), sweeps=3, omega=1.5).reshape(sub.shape[1:])[:, jc, ic]
+        worst32 = max(worst32, np.max(np.abs(z32[:, j0, i0] - ref32)) / np.max(np.abs(ref32)))
+    print(f"line SOR at 2560x1920x70, {len(samples)} sampled columns: max rel diff FP64 {worst64:.2e}, FP32 {worst32:.2e}")
+    assert worst64 <= 1e-11 and worst32 <= 2e-5
 
 
 def test_all_modes_reach_1e8_true_residual(eg, oracle_mod, c3):
