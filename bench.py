@@ -40,13 +40,13 @@ BYTES_PER_POINT = {
     "residual": {0: 76},                        # 6 couplings + margin + x + b (FP64) + r (FP32)
 }
 # Red-black line SOR: algorithmic bytes of one half-sweep per grid point (half the columns
-# update: rhs q, own x in and out, the three LU factors, four horizontal couplings and the
-# parked forward-sweep value (write + read); the other half's x is read once as neighbours),
-# times 2 * sweeps - 1 half-sweeps per application (the first red half-sweep is the
-# tridiagonal solve before it).  The first half-sweep reads no old x of its own and the last
-# writes the other colour's values in grid order as well: over an application these balance,
-# so 52 B (FP64) per half-sweep holds on average.
-SOR_HALF_BYTES = {0: 52, 1: 26, 2: 22, 3: 22}
+# update: rhs q, own x in and out, the three LU factors and four horizontal couplings; the other
+# half's x is read once as neighbours), times 2 * sweeps - 1 half-sweeps per application (the
+# first red half-sweep is the tridiagonal solve before it).  The first half-sweep reads no old x
+# of its own and the last writes the other colour's values in grid order as well: over an
+# application these balance.  The generic kernel (level counts other than 70) also parks the
+# forward-sweep values in memory (+8 B FP64, +4 B FP32 per point), which is not counted.
+SOR_HALF_BYTES = {0: 44, 1: 22, 2: 18, 3: 18}
 KERNEL_IDS = {"thomas_p": [0], "spmv": [1, 3], "thomas_s": [2], "update": [4], "residual": [5], "sor": [6, 7]}
 KERNEL_SYMBOL = {"spmv": "k_spmv", "thomas_p": "k_thomas", "thomas_s": "k_thomas", "update": "k_update",
                  "residual": "k_spmv", "sor": "k_sor_half", "thomas_p_cm": "k_thomas", "thomas_s_cm": "k_thomas"}
@@ -63,9 +63,7 @@ MEASURED_TRAFFIC = {("c3", "spmv_fp64"): 28.74e9, ("c3", "spmv_fp32"): 14.67e9, 
                     ("c3", "residual_fp64"): 27.35e9,
                     ("c3", "thomas_p_cm_fp64"): 24.78e9, ("c3", "thomas_s_cm_fp64"): 22.02e9,
                     ("c3", "thomas_p_cm_fp32"): 12.39e9, ("c3", "thomas_s_cm_fp32"): 11.01e9,
-                    ("c3", "thomas_p_cm_bf16"): 12.39e9, ("c3", "thomas_s_cm_bf16"): 11.01e9,
-                    # one line-SOR application = five half-sweeps
-                    ("c3", "sor_fp64"): 95.94e9, ("c3", "sor_fp32"): 46.45e9, ("c3", "sor_bf16"): 39.57e9}
+                    ("c3", "thomas_p_cm_bf16"): 12.39e9, ("c3", "thomas_s_cm_bf16"): 11.01e9}
 
 
 def log(*a):

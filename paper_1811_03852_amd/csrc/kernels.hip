@@ -1452,12 +1452,136 @@ __global__ __launch_bounds__(kWG) void k_sor_half(OpView<Tc> op, SorView<Tv, Tc>
     }
 }
 
+// Register-resident variant for a fixed level count NL: the forward values w_k stay in
+// registers (no parked vector: 4 B per point less per FP32 half-sweep).  The loads of level
+// k + PF are issued while level k is computed, into a ring of PF register slots, with
+// scheduling fences so the compiler does not hoist every level's loads (as in k_thomas).
+// Needs nlon/2 % 64 == 0, so that each wave lies within one latitude row; the south/north
+// loads of the first/last row read the own column instead (their couplings are zero there, so
+// the sum is the same as the generic kernel's, which skips them).
+template <typename Tv, typename Tc, bool LAST, int NL, int PF>
+__global__ __launch_bounds__(kWG) void k_sor_half_reg(OpView<Tc> op, SorView<Tv, Tc> sv, const Tv *__restrict__ qcm,
+                                                      Tv *__restrict__ xcm, Tv *__restrict__ xout, int colour,
+                                                      Tv omega, Tv nb_scale, Tv own_scale,
+                                                      const Scalars *__restrict__ sc, int stop_mask, int per_xcd)
+{
+    if (stopped(sc, stop_mask)) return;
+    using V = typename CoefTraits<Tc>::val;
+    constexpr bool Q = CoefTraits<Tc>::quant;
+    const int nlat = op.nlat;
+    const int half = op.nlon / 2;
+    const long P = op.P, n = op.n, P2 = P / 2, n2 = n / 2;
+    const long lb = (long)(blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+    const long c2 = lb * kWG + threadIdx.x;
+    if (c2 >= P2) return;   // whole waves (P/2 is a multiple of 64 here)
+    const int j = __builtin_amdgcn_readfirstlane((int)(c2 / half));
+    const int m = (int)(c2 - (long)j * half);
+    const int par = (j + colour) & 1;
+    constexpr uint32_t SV = sizeof(Tv);
+    // lane byte offsets within a level plane of one colour
+    const uint32_t oo = (uint32_t)c2 * SV;
+    const uint32_t ow = (uint32_t)(j * half + (par ? m : (m == 0 ? half - 1 : m - 1))) * SV;
+    const uint32_t oe = (uint32_t)(j * half + (par ? (m == half - 1 ? 0 : m + 1) : m)) * SV;
+    const uint32_t os = (j > 0) ? oo - (uint32_t)half * SV : oo;
+    const uint32_t on = (j < nlat - 1) ? oo + (uint32_t)half * SV : oo;
+    const uint32_t oc = (uint32_t)c2;   // element index into the coupling rows
+    const Tv *qb = qcm + (long)colour * n2;
+    const Tv *lfb = sv.f + (long)colour * n2, *invb = sv.f + n + (long)colour * n2, *cfb = sv.f + 2 * n + (long)colour * n2;
+    const Tc *aWb = sv.a + (long)colour * n2, *aEb = aWb + n, *aSb = aWb + 2 * n, *aNb = aWb + 3 * n;
+    const Tv *oth = xcm + (long)(1 - colour) * n2;
+    Tv *own = xcm + (long)colour * n2;
+
+    Tv w[NL];
+    {
+        V rw[PF], re[PF], rs[PF], rn[PF];
+        Tv xw[PF], xe[PF], xs[PF], xn[PF], rq[PF], rl[PF];
+        auto issue = [&](int kk, int sl) {
+            const size_t lo = (size_t)kk * (size_t)P2;
+            float s0 = 1.f, s1 = 1.f, s2 = 1.f, s3 = 1.f;
+            if constexpr (Q) {
+                const float4 sq = *reinterpret_cast<const float4 *>(op.qs + ((size_t)kk * nlat + j) * kQsStride);
+                s0 = sq.x;
+                s1 = sq.y;
+                s2 = sq.z;
+                s3 = sq.w;
+            }
+            rw[sl] = DecB<Tc>::get(aWb + lo, oc, s0);
+            re[sl] = DecB<Tc>::get(aEb + lo, oc, s1);
+            rs[sl] = DecB<Tc>::get(aSb + lo, oc, s2);
+            rn[sl] = DecB<Tc>::get(aNb + lo, oc, s3);
+            xw[sl] = ldb(oth + lo, ow);
+            xe[sl] = ldb(oth + lo, oe);
+            xs[sl] = ldb(oth + lo, os);
+            xn[sl] = ldb(oth + lo, on);
+            rq[sl] = ldn(qb + lo, oo);
+            rl[sl] = ldn(lfb + lo, oo);
+        };
+#pragma unroll
+        for (int k = 0; k < PF && k < NL; ++k) issue(k, k);
+        Tv wprev = 0;
+#pragma unroll
+        for (int k = 0; k < NL; ++k) {
+            const int sl = k % PF;
+            Tv h = rw[sl] * xw[sl] + re[sl] * xe[sl];
+            h += static_cast<Tv>(rs[sl]) * xs[sl];
+            h += static_cast<Tv>(rn[sl]) * xn[sl];
+            const Tv rhs = rq[sl] + nb_scale * h;
+            w[k] = rhs + rl[sl] * wprev;
+            wprev = w[k];
+            if (k + PF < NL) issue(k + PF, sl);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+    const Tv keep = (Tv(1) - omega) * own_scale;
+    auto backward = [&](auto own_c) {
+        constexpr bool OWN = decltype(own_c)::value;
+        Tv bi[PF], bc[PF], bo[PF], bp[PF];
+        auto issue = [&](int kk, int sl) {
+            const size_t lo = (size_t)kk * (size_t)P2;
+            bi[sl] = ldn(invb + lo, oo);
+            bc[sl] = ldn(cfb + lo, oo);
+            if constexpr (OWN) bo[sl] = ldb(own + lo, oo);
+            if constexpr (LAST) bp[sl] = ldb(oth + lo, oo);
+        };
+#pragma unroll
+        for (int t = 0; t < PF && t < NL; ++t) issue(NL - 1 - t, t);
+        Tv ynext = 0;
+#pragma unroll
+        for (int k = NL - 1; k >= 0; --k) {
+            const int sl = (NL - 1 - k) % PF;
+            const Tv y = bi[sl] * w[k] + bc[sl] * ynext;
+            const Tv old = OWN ? bo[sl] : Tv(0);
+            const Tv val = keep * old + omega * y;
+            if constexpr (LAST) {
+                Tv *o = xout + (size_t)k * (size_t)P;
+                const uint32_t g = (uint32_t)(2 * c2);
+                __builtin_nontemporal_store(val, o + g + par);
+                __builtin_nontemporal_store(nb_scale * bp[sl], o + g + (1 - par));
+            } else {
+                stb(own + (size_t)k * (size_t)P2, oo, val);
+            }
+            ynext = y;
+            if (k - PF >= 0) issue(k - PF, sl);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    };
+    if (own_scale == Tv(0))
+        backward(std::integral_constant<bool, false>{});
+    else
+        backward(std::integral_constant<bool, true>{});
+}
+
 template <typename T> void launch_sor_perm(const T *src, T *dst, int nd, int nlon, int nlat, int nlev, hipStream_t s)
 {
     const long n = (long)nlon * nlat * nlev;
     hipLaunchKernelGGL((k_sor_perm<T>), dim3(elementwise_blocks(nd * n)), dim3(kWG), 0, s, src, dst, nd, nlon, nlat,
                        nlev);
 }
+
+// levels in flight in the register-resident half-sweep (FP32 and FP64 vectors: 138 and 233
+// VGPRs, no spills)
+constexpr int kSorPF = 4;
+constexpr int kSorPF64 = 3;
 
 template <typename Tv, typename Tc>
 void launch_sor(const OpView<Tc> &op, const SorView<Tv, Tc> &sv, const Tv *qcm, Tv *xcm, Tv *wsc, Tv *xout,
@@ -1469,10 +1593,22 @@ void launch_sor(const OpView<Tc> &op, const SorView<Tv, Tc> &sv, const Tv *qcm, 
     const unsigned blocks = (unsigned)(per_xcd * 8);
     const Tv w = static_cast<Tv>(omega);
     const int last = 2 * sweeps - 1;
+    // register-resident forward values at 70 levels, when each wave lies within one latitude row
+    const bool reg = op.nlev == 70 && (op.nlon / 2) % 64 == 0;
     for (int h = 1; h <= last; ++h) {
         const int colour = (h & 1) ? 1 : 0;                       // odd: black, even: red
         const Tv nb_scale = (h == 1) ? w : Tv(1);                 // red still holds T^{-1} q
         const Tv own_scale = (h == 1) ? Tv(0) : (h == 2 ? w : Tv(1));
+        if (reg) {
+            constexpr int PF = sizeof(Tv) == 4 ? kSorPF : kSorPF64;
+            if (h == last)
+                hipLaunchKernelGGL((k_sor_half_reg<Tv, Tc, true, 70, PF>), dim3(blocks), dim3(kWG), 0, s, op, sv, qcm,
+                                   xcm, xout, colour, w, nb_scale, own_scale, sc, stop_mask, per_xcd);
+            else
+                hipLaunchKernelGGL((k_sor_half_reg<Tv, Tc, false, 70, PF>), dim3(blocks), dim3(kWG), 0, s, op, sv, qcm,
+                                   xcm, xout, colour, w, nb_scale, own_scale, sc, stop_mask, per_xcd);
+            continue;
+        }
         if (h == last)
             hipLaunchKernelGGL((k_sor_half<Tv, Tc, true>), dim3(blocks), dim3(kWG), 0, s, op, sv, qcm, xcm, wsc, xout,
                                colour, w, nb_scale, own_scale, sc, stop_mask, per_xcd);
