@@ -63,7 +63,9 @@ MEASURED_TRAFFIC = {("c3", "spmv_fp64"): 28.74e9, ("c3", "spmv_fp32"): 14.67e9, 
                     ("c3", "residual_fp64"): 27.35e9,
                     ("c3", "thomas_p_cm_fp64"): 24.78e9, ("c3", "thomas_s_cm_fp64"): 22.02e9,
                     ("c3", "thomas_p_cm_fp32"): 12.39e9, ("c3", "thomas_s_cm_fp32"): 11.01e9,
-                    ("c3", "thomas_p_cm_bf16"): 12.39e9, ("c3", "thomas_s_cm_bf16"): 11.01e9}
+                    ("c3", "thomas_p_cm_bf16"): 12.39e9, ("c3", "thomas_s_cm_bf16"): 11.01e9,
+                    # one line-SOR application = five half-sweeps
+                    ("c3", "sor_fp64"): 80.85e9, ("c3", "sor_fp32"): 39.82e9, ("c3", "sor_bf16"): 32.78e9}
 
 
 def log(*a):
