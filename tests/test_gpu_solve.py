@@ -247,6 +247,33 @@ def test_paper_mixed_precision_mode(eg, oracle_mod, c1, tol):
     assert err <= 1e4 * tol
 
 
+@pytest.mark.parametrize("precond", [0, 1], ids=["tri", "line_sor"])
+@pytest.mark.parametrize("tol", [1e-4, 1e-6])
+def test_paper_mixed_precision_matches_the_mp_oracle(eg, oracle_mod, c1, precond, tol):
+    """EG_FP32_MP against the CPU emulation of the paper's mixed-precision BiCGStab (FP32
+    vectors, FP64 x and sums, restart every 150; oracle/mp.py): the first residual-history
+    entries agree to FP32 rounding, the iteration counts within 10 % (both sides round
+    differently, and BiCGStab amplifies it), and both true residuals are below tol."""
+    import torch
+    from oracle import mp
+    p, coef, b, x_ref, _ = c1
+    xo, ref = mp.bicgstab_mp(coef, b, tol=tol, precond="sor" if precond else "tri")
+    with eg.Operator(dev(coef)) as op:
+        op.set_option("precond", precond)
+        x = torch.zeros(p.n, dtype=torch.float64, device="cuda")
+        info = op.solve(dev(b), x, tol, 5000, eg.FP32_MP)
+        h = op.history()
+    xh = host(x)
+    print(f"MP {'line SOR' if precond else 'T^-1'} tol {tol:g}: GPU {info.iterations} its, oracle {ref.iterations}; "
+          f"history[:4] GPU {np.array2string(h[:4], precision=6)} oracle {np.array2string(ref.history[:4], precision=6)}")
+    assert info.status == eg.CONVERGED and ref.status == 0
+    assert _true_rel(oracle_mod, coef, b, xh) <= tol and ref.true_rel_residual <= tol
+    assert abs(info.iterations - ref.iterations) <= max(2, ref.iterations // 10)
+    k = min(4, len(h), len(ref.history))
+    assert np.allclose(h[:k], ref.history[:k], rtol=1e-4, atol=0)
+    assert np.linalg.norm(xh - xo) <= 1e4 * tol * np.linalg.norm(xo)
+
+
 def test_paper_mixed_precision_restarts_every_150(eg, oracle_mod):
     """Shift 1e-6 needs a few hundred iterations: the mode restarts from the true residual
     every 150 iterations and still converges."""

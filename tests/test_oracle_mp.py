@@ -1,0 +1,53 @@
+"""Pins for the emulation of the paper's mixed-precision BiCGStab (oracle/mp.py, Sec. 4)."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import mp
+
+
+def _problem(**kw):
+    p = synth.Problem(48, 36, 12, seed=kw.pop("seed", 3), **kw)
+    return p, synth.make_coeffs(p), synth.make_rhs(p).ravel()
+
+
+@pytest.mark.parametrize("precond,code", [("tri", 1), ("sor", 2)])
+@pytest.mark.parametrize("restart_every", [0, 7])
+def test_without_rounding_it_is_the_fp64_bicgstab(precond, code, restart_every):
+    """vec_dtype float64: step for step the FP64 BiCGStab of the C oracle (the same operations
+    in the same order: identical iteration count, status, residual history and x), periodic
+    restarts included."""
+    p, coef, b = _problem()
+    x, info = mp.bicgstab_mp(coef, b, tol=1e-9, restart_every=restart_every, precond=precond, vec_dtype=np.float64)
+    x_ref, ref = oracle.bicgstab(coef, b, tol=1e-9, restart_every=restart_every, precond=code)
+    assert info.status == ref.status == 0
+    assert info.iterations == ref.iterations
+    k = len(info.history)
+    assert np.array_equal(info.history, ref.history[:k])
+    assert np.array_equal(x, x_ref)
+    if restart_every:
+        assert info.restarts >= info.iterations // restart_every
+
+
+def test_fp32_vectors_round_and_still_converge():
+    """With float32 vectors the history leaves the FP64 one by about the FP32 rounding, and the
+    solve still reaches the paper's tolerances (1e-3, 1e-4) in about the FP64 iteration count."""
+    p, coef, b = _problem()
+    _, ref = oracle.bicgstab(coef, b, tol=1e-4, precond=1)
+    x, info = mp.bicgstab_mp(coef, b, tol=1e-4)
+    assert info.status == 0 and info.true_rel_residual <= 1e-4
+    assert abs(info.iterations - ref.iterations) <= max(2, ref.iterations // 5)
+    d = np.abs(info.history[:3] - ref.history[:3]) / ref.history[:3]
+    assert np.all(d < 1e-4) and np.any(d > 1e-9)      # rounded, but only at FP32 level
+    rel = np.linalg.norm(b - oracle.apply(coef, x)) / np.linalg.norm(b)
+    assert rel == pytest.approx(info.true_rel_residual, rel=1e-12)
+
+
+def test_restarts_every_150_from_the_true_residual():
+    """Shift 1e-6 needs a few hundred iterations: a restart every 150 iterations."""
+    p, coef, b = _problem(shift=1e-6, seed=5)
+    x, info = mp.bicgstab_mp(coef, b, tol=1e-5, maxit=3000)
+    assert info.status == 0 and info.iterations > 150
+    assert info.restarts >= info.iterations // 150
+    assert np.linalg.norm(b - oracle.apply(coef, x)) / np.linalg.norm(b) <= 1e-5
