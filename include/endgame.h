@@ -54,8 +54,11 @@ enum eg_mode {
     EG_LEARNED_FP32_IR = 5, /* FP64 refinement around flexible FP32 BiCGStab + learned precond.  */
     EG_FP32_MP = 6          /* the paper's mixed-precision BiCGStab (Sec. 3-4): FP32 vectors and
                                coefficients, FP64 solution updated every iteration, FP64 global
-                               sums, restart every restart_every iterations (150 if 0); no
-                               refinement, so it stalls below about 1e-6 (EG_STALLED)            */
+                               sums, restart from the FP64 true residual every restart_every
+                               iterations (150 if 0) and when the recursive residual has met
+                               tol but the true one has not; no refinement steps.  Where the
+                               FP32 recurrence cannot carry the solve below tol it ends with
+                               EG_STALLED after three such restarts                              */
 };
 
 /* Outcomes (>= 0) and errors (< 0). */
@@ -146,7 +149,10 @@ int eg_set_stream(eg_operator *op, void *hip_stream);
  *   "precond"        preconditioner of the plain modes: 0 the vertical tridiagonal solve
  *                    T^{-1}, 1 red-black vertical-line SOR (the tri_sor of Sec. 2, Eq. 7, with
  *                    the columns in red-black order; needs an even nlon) [0].  The learned modes
- *                    and the harvests always build on T^{-1}.
+ *                    and the harvests always build on T^{-1}.  The line SOR keeps the LU
+ *                    factors and the W, E, S, N couplings a second time in colour-major order
+ *                    (7n values in each precision used) and 5n/2 doubles of work space,
+ *                    allocated on first use and held until eg_destroy_operator.
  *   "sor_sweeps"     sweeps of the line SOR, 1..16 [3]
  *   "sor_omega"      its relaxation factor, 0 < omega < 2 [1.5]
  *   "method"         Krylov method of the plain modes: 0 BiCGStab, 1 restarted FGMRES [0]
