@@ -138,7 +138,7 @@ def rbsor(coef: np.ndarray, q: np.ndarray, sweeps: int = 3, omega: float = 1.5, 
 
 
 def lexsor(coef: np.ndarray, q: np.ndarray, sweeps: int = 3, omega: float = 1.5):
-    """The same line SOR in lexicographic column order (the paper's serial order)."""
+    """The same line SOR in the natural (lexicographic) column order of Eq. 7's L and U."""
     nlon, nlat, nlev = _check(coef)
     q = _vec(q, nlon * nlat * nlev)
     z = np.empty_like(q)

@@ -18,7 +18,7 @@
  *   orc_rbsor      Sec. 2, Eq. 6-7: the tri_sor preconditioner (a few over-relaxed sweeps of
  *                  vertical-line Gauss-Seidel in which T takes the place of the diagonal),
  *                  with the columns visited in red-black order instead of lexicographically.
- *   orc_lexsor     the same sweeps in lexicographic column order (the paper's serial order).
+ *   orc_lexsor     the same sweeps in the natural (lexicographic) column order of Eq. 7's L, U.
  *   orc_bicgstab   Sec. 2 (post-conditioned BiCGStab, Eq. 5; van der Vorst's method with the
  *                  preconditioner applied on the right) and Sec. 3 (halting on
  *                  R = ||r_i|| / ||b|| of the unpreconditioned residual, Eq. 8-9), with the
@@ -206,10 +206,11 @@ void orc_rbsor(int nlon, int nlat, int nlev, const double *coef, const double *q
 }
 
 /*
- * The same SOR in the serial order of the paper's CPU code (Sec. 2, Eq. 7): columns visited
- * lexicographically (i fastest, then j), each using the newest values of all its neighbours
- * (x_c <- (1 - omega) x_c + omega T_c^{-1}(q_c + sum_nb a_nb x_nb)); nsweeps sweeps from x = 0.
- * Kept for comparing the orderings; the GPU builds the red-black one.
+ * The same SOR in the natural column order of the splitting A = L + T + U of Sec. 2, Eq. 7
+ * (L, U the lower and upper triangles with i fastest, then j): columns visited in that order,
+ * each using the newest values of all its neighbours (x_c <- (1 - omega) x_c + omega
+ * T_c^{-1}(q_c + sum_nb a_nb x_nb)); nsweeps sweeps from x = 0.  Kept for comparing the
+ * orderings; the GPU builds the red-black one.
  */
 void orc_lexsor(int nlon, int nlat, int nlev, const double *coef, const double *q, double *z, int nsweeps,
                 double omega)

@@ -81,7 +81,7 @@ def test_bicgstab_with_sor_matches_dense_solve():
 
 
 def test_lexicographic_sor_matches_the_dense_gauss_seidel_splitting():
-    """The paper's serial order: (T + omega L) x_n = (1 - omega) T x_{n-1} + omega (q - U x_{n-1}),
+    """The paper's splitting in the natural column order: (T + omega L) x_n = (1 - omega) T x_{n-1} + omega (q - U x_{n-1}),
     with L / U the horizontal couplings to columns before / after in lexicographic order (Eq. 7),
     solved with the dense matrix."""
     p, coef, q = _problem(nlon=6, nlat=4, nlev=3)
@@ -102,7 +102,7 @@ def test_lexicographic_sor_matches_the_dense_gauss_seidel_splitting():
 
 def test_red_black_and_lexicographic_orders_precondition_alike():
     """BiCGStab iteration counts with the two column orders (3 sweeps, omega 1.5) on the
-    96x72x20 operator: the red-black order the GPU uses is as strong as the paper's serial one."""
+    96x72x20 operator: the red-black order the GPU uses is as strong as the natural one."""
     p = synth.CONFIGS["c1"]
     coef = synth.make_coeffs(p)
     b = synth.make_rhs(p).ravel()
