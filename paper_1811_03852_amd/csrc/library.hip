@@ -696,11 +696,6 @@ int fgmres(eg_operator *op, const OpView<Tc> &A, Tv *d, double nb, double tol, i
     return 0;
 }
 
-double fetch_out(eg_operator *op, int idx)
-{
-    return op->h_out[idx];
-}
-
 // rr64 = ||b - A x||^2, bb = ||b||^2 into h_out[0..1]; r (may be null) receives b - A x.
 template <typename Tout> int true_residual(eg_operator *op, const double *b, const double *x, Tout *r, int *nrows)
 {
