@@ -102,23 +102,28 @@ def _htap(t):
     return t % 3 - 1, t // 3 - 1
 
 
-def features(coef: np.ndarray, q: np.ndarray):
+def features(coef: np.ndarray, q: np.ndarray, scales=None):
+    """The four input channels; ``scales`` = (rms of q, rms of T^{-1} q) over the whole grid
+    when q is a window cut out of it (default: taken from q itself)."""
     nlev, nlat, nlon = coef.shape[1:]
     q = np.asarray(q, dtype=np.float64).ravel()
     z0 = oracle.thomas(coef, q)
-    rho = np.sqrt(np.mean(q * q))
-    rhoz = np.sqrt(np.mean(z0 * z0))
+    if scales is None:
+        rho = np.sqrt(np.mean(q * q))
+        rhoz = np.sqrt(np.mean(z0 * z0))
+    else:
+        rho, rhoz = scales
     x0 = np.stack([q / rho, z0 / rhoz, (coef[4] + coef[5]).ravel(), (coef[0] + coef[1] + coef[2] + coef[3]).ravel()],
                   axis=1)
     return x0.reshape(nlev, nlat, nlon, C_IN), rho
 
 
-def forward(theta: np.ndarray, coef: np.ndarray, q: np.ndarray, bf16_round: bool = True):
+def forward(theta: np.ndarray, coef: np.ndarray, q: np.ndarray, bf16_round: bool = True, scales=None):
     """delta(q) (flat) and the cache needed by ``backward``."""
     P = unpack(theta)
     rnd = bf16 if bf16_round else (lambda a: a)
     W1, W2, W3, W4 = (rnd(P[k]) for k in ("W1", "W2", "W3", "W4"))
-    x0, rho = features(coef, q)
+    x0, rho = features(coef, q, scales)
     x0 = rnd(x0)
     z1 = sum(_shift_v(x0, _vtap(t)) @ W1[t].T for t in range(TAPS_V)) + P["b1"]
     a1 = rnd(np.maximum(z1, 0.0))

@@ -2,7 +2,8 @@
 
 2560x1920x70 (344M unknowns): SpMV and Thomas outputs on sampled rows and columns against the
 oracle computed one row / one column at a time; the line SOR on sampled columns against the
-oracle on a window around each; every solver mode's true residual recomputed
+oracle on a window around each (and the network at 640x480x70 the same way); every solver
+mode's true residual recomputed
 by the oracle's full FP64 matrix-vector product on the host; the modes' solutions against each
 other.  640x480x70 with a manufactured solution: forward error against x*.
 """
@@ -229,6 +230,51 @@ def test_stress_case_1280x960x140(eg, oracle_mod):
         d = np.linalg.norm(sols[name] - ref) / np.linalg.norm(ref)
         print(f"{name} vs FP64+SOR: rel L2 {d:.2e}")
         assert d <= 1e-1   # shift 1e-6: cond(A) ~ 1e6, two solutions with R <= 1e-8 each
+
+
+def test_network_sampled_columns_640x480x70(eg, oracle_mod):
+    """The network's output delta(q) at the learned preconditioner's benchmark size, in the
+    launch configuration the solver uses, on sampled columns: a column's delta depends on the
+    3x3 columns around it (the horizontal layer; the others are vertical), so the oracle runs on
+    that window with the input scales of the whole grid, and its centre column (all 70 levels)
+    is compared with the GPU's (BF16 activations on both sides)."""
+    import torch
+    from oracle import net as onet
+    p = synth.CONFIGS["c4"]
+    coef = synth.make_coeffs(p, threads=16)
+    rng = np.random.default_rng(35)
+    d = onet.unpack(onet.init_theta(6))
+    d["W4"] = rng.standard_normal(d["W4"].shape) * 0.3
+    for k in ("b1", "b2", "b3"):
+        d[k] = rng.standard_normal(32) * 0.1
+    th = onet.pack(d).astype(np.float32).astype(np.float64)
+    q = rng.standard_normal(p.n).astype(np.float32)
+    net = eg.Net(0)
+    net.set_weights(th.astype(np.float32))
+    with eg.Operator(torch.from_numpy(coef).cuda()) as op:
+        delta = torch.empty(p.n, dtype=torch.float32, device="cuda")
+        net.apply(op, torch.from_numpy(q).cuda(), delta)
+        dg = host(delta).astype(np.float64).reshape(p.nlev, p.nlat, p.nlon)
+    net.close()
+    q64 = q.astype(np.float64)
+    z0 = oracle_mod.thomas(coef, q64)
+    scales = (np.sqrt(np.mean(q64 * q64)), np.sqrt(np.mean(z0 * z0)))
+    q3 = q64.reshape(p.nlev, p.nlat, p.nlon)
+    samples = [(int(i), int(j)) for i, j in zip(rng.integers(0, p.nlon, 40), rng.integers(0, p.nlat, 40))]
+    samples += [(0, 0), (p.nlon - 1, p.nlat - 1), (0, p.nlat - 1), (p.nlon - 1, 0), (5, 1)]
+    num = den = 0.0
+    for i0, j0 in samples:
+        ii = np.arange(i0 - 1, i0 + 2) % p.nlon
+        jj = np.arange(max(0, j0 - 1), min(p.nlat, j0 + 2))
+        sub = np.ascontiguousarray(coef[:, :, jj][:, :, :, ii])
+        qs = np.ascontiguousarray(q3[:, jj][:, :, ii])
+        dref, _ = onet.forward(th, sub, qs.ravel(), bf16_round=True, scales=scales)
+        col = dref.reshape(p.nlev, len(jj), 3)[:, j0 - jj[0], 1]
+        num += float(np.sum((dg[:, j0, i0] - col) ** 2))
+        den += float(np.sum(col ** 2))
+    err = np.sqrt(num / den)
+    print(f"network at 640x480x70, {len(samples)} sampled columns: delta rel L2 {err:.2e}")
+    assert err <= 1e-2
 
 
 def test_learned_preconditioner_640x480x70(eg, oracle_mod):
