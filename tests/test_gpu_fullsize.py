@@ -182,6 +182,52 @@ def test_all_modes_reach_1e8_true_residual(eg, oracle_mod, c3):
         assert d <= 1e-4   # two solutions with R <= 1e-8 each, cond(A) ~ 1e3 at shift 1e-3
 
 
+def _quick_net(eg):
+    """A network trained in seconds on the FGMRES bases of 8 small operators of the recipe."""
+    import torch
+    ops, rs, owner = [], [], []
+    for s in range(8):
+        q = synth.Problem(96, 72, 20, seed=1000 + s)
+        op = eg.Operator(torch.from_numpy(synth.make_coeffs(q)).cuda())
+        r, _ = op.harvest_krylov(torch.from_numpy(synth.make_rhs(q, seed=2000 + s).ravel()).cuda(), 20, errors=False)
+        ops.append(op)
+        rs.append(r)
+        owner += [s] * r.shape[0]
+    r = torch.cat(rs).contiguous()
+    net = eg.Net(11)
+    net.train(ops, r, r, owner, epochs=10, batch=16, lr=2e-3, seed=1)
+    for op in ops:
+        op.close()
+    return net
+
+
+def test_learned_modes_2560x1920x70(eg, oracle_mod, c3):
+    """Both learned modes on the 344M-unknown grid, in the method the benchmark configuration
+    names (flexible BiCGStab with the tridiagonal fallback): they reach 1e-8 (true residual by
+    the oracle's FP64 product on the host), whether the network carries the solve or the
+    fallback finishes it."""
+    import torch
+    p, coef, b, op = c3
+    net = _quick_net(eg)
+    bd = torch.from_numpy(b).cuda()
+    nb = np.linalg.norm(b)
+    op.attach(net)
+    op.set_option("learned_method", 0)
+    try:
+        for name in ("LEARNED_FP32_IR", "LEARNED_FP64"):
+            x = torch.zeros(p.n, dtype=torch.float64, device="cuda")
+            print(f"[fullsize] solving {name}", flush=True)
+            info = op.solve(bd, x, 1e-8, 20000, getattr(eg, name))
+            rel = np.linalg.norm(b - oracle_mod.apply(coef, host(x))) / nb
+            print(f"{name} (flexible BiCGStab): status {info.status}, {info.iterations} its, {info.outer_steps} outer, "
+                  f"{info.fallbacks} fallbacks, {info.seconds:.2f} s, true R (oracle) {rel:.3e}")
+            assert info.status == eg.CONVERGED and rel <= 1e-8 * (1 + 1e-6)
+    finally:
+        op.set_option("learned_method", 1)
+        op.attach(None)
+        net.close()
+
+
 def test_manufactured_solution_640x480x70(eg, oracle_mod):
     import torch
     p = synth.CONFIGS["c2"]
@@ -282,19 +328,7 @@ def test_learned_preconditioner_640x480x70(eg, oracle_mod):
     640x480x70 operator: FGMRES with the learned preconditioner reaches 1e-8 in FP64 and in
     FP32 with FP64 refinement (true residual by the oracle)."""
     import torch
-    ops, rs, owner = [], [], []
-    for s in range(8):
-        q = synth.Problem(96, 72, 20, seed=1000 + s)
-        op = eg.Operator(torch.from_numpy(synth.make_coeffs(q)).cuda())
-        r, _ = op.harvest_krylov(torch.from_numpy(synth.make_rhs(q, seed=2000 + s).ravel()).cuda(), 20, errors=False)
-        ops.append(op)
-        rs.append(r)
-        owner += [s] * r.shape[0]
-    r = torch.cat(rs).contiguous()
-    net = eg.Net(11)
-    net.train(ops, r, r, owner, epochs=10, batch=16, lr=2e-3, seed=1)
-    for op in ops:
-        op.close()
+    net = _quick_net(eg)
     p = synth.CONFIGS["c4"]
     coef = synth.make_coeffs(p, threads=16)
     b = synth.make_rhs(p).ravel()
