@@ -150,8 +150,9 @@ def train_network(eg, torch, shape, nops, nvec, epochs, seed=1):
 
 
 def learned_comparison(eg, torch, net, cfg_name, tol):
-    """FGMRES(30) with T^-1 vs with the learned M (both FP32 inner + FP64 refinement), and
-    BiCGStab, on one workload; one warm-up solve each, then one timed solve."""
+    """On one workload, in FP32 inner + FP64 refinement and in FP64: plain BiCGStab with T^-1
+    (the baseline), flexible BiCGStab with the learned M (and its tridiagonal fallback), and
+    FGMRES(30) with T^-1 and with the learned M; one warm-up solve each, then one timed solve."""
     import synth
     p = synth.CONFIGS[cfg_name]
     coef, b = generate_on_device(p, torch)
@@ -161,9 +162,11 @@ def learned_comparison(eg, torch, net, cfg_name, tol):
     op.attach(net)
     out = {"workload": f"{cfg_name}: {p.nlon}x{p.nlat}x{p.nlev}, b ~ N(0,1), tol {tol}"}
     x = torch.zeros(p.n, dtype=torch.float64, device="cuda")
-    for name, mode, method in (("fgmres_tri_fp32_ir", eg.FP32_IR, 1), ("fgmres_learned_fp32_ir", eg.LEARNED_FP32_IR, 1),
-                               ("bicgstab_tri_fp32_ir", eg.FP32_IR, 0), ("fgmres_tri_fp64", eg.FP64, 1),
-                               ("fgmres_learned_fp64", eg.LEARNED_FP64, 1)):
+    for name, mode, method in (("bicgstab_tri_fp32_ir", eg.FP32_IR, 0),
+                               ("bicgstab_learned_fp32_ir", eg.LEARNED_FP32_IR, 0),
+                               ("fgmres_tri_fp32_ir", eg.FP32_IR, 1), ("fgmres_learned_fp32_ir", eg.LEARNED_FP32_IR, 1),
+                               ("bicgstab_tri_fp64", eg.FP64, 0), ("bicgstab_learned_fp64", eg.LEARNED_FP64, 0),
+                               ("fgmres_tri_fp64", eg.FP64, 1), ("fgmres_learned_fp64", eg.LEARNED_FP64, 1)):
         op.set_option("method", method)
         op.set_option("learned_method", method)
         x.zero_()
