@@ -1254,6 +1254,11 @@ int eg_solve(eg_operator *op, const double *b, double *x, double tol, int maxit,
     op->hist_count = 0;
     op->hist_pending.clear();
     int rc;
+    // the line SOR is on for this solve only, whichever way it returns
+    struct SorScope {
+        eg_operator *op;
+        ~SorScope() { op->sor_on = false; }
+    } sor_scope{op};
     op->sor_on = (op->precond == 1) && !learned;
     if (op->sor_on) {
         if (mode == EG_FP64) rc = ensure_sor<double>(op);
@@ -1292,7 +1297,6 @@ int eg_solve(eg_operator *op, const double *b, double *x, double tol, int maxit,
         status = solve_ir<float>(op, op->view32(), b, x, tol, maxit, op->net);
         break;
     }
-    op->sor_on = false;
     if (status < 0) return status;
     // history to the host
     if (!op->hist_pending.empty()) {
