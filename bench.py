@@ -1,16 +1,17 @@
 """Benchmark: time-to-solve at ||b - A x|| / ||b|| <= 1e-8 on one MI355X, per solver mode, with
 the HBM roofline fraction of the dominant kernel and the CPU oracle as a reported baseline.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config c3] [--modes fp64,fp32_ir,...]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config n1280_2560x1920x70] [--modes fp64,fp32_ir,...]
 
 A step solves A x = b once in every listed mode (x0 = 0); a "_sor" suffix selects the red-black
-vertical-line SOR preconditioner (three sweeps, omega 1.5) instead of the tridiagonal solve.  Inputs (operator and right-hand
-side) are generated on the host from the seeded recipe, copied to HBM and the operator is built
+vertical-line SOR preconditioner (three sweeps, omega 1.5) instead of the tridiagonal solve.
+Inputs (operator and right-hand side) are generated on the host from the seeded recipe, copied to HBM and the operator is built
 before the timed region.  Learned modes first train the network (untimed, reported): FGMRES
 bases harvested from small operators of the same recipe, Adam on the residual-space loss.
 After the timed steps, the learned preconditioner is compared with the tridiagonal one on its
-own workload (640x480x70 by default), each with FGMRES(30) in FP32 with FP64 refinement, beside
-BiCGStab.  One JSON line is printed on stdout.
+own workload (640x480x70 by default): plain BiCGStab, flexible BiCGStab with the learned
+preconditioner and FGMRES(30) with either, in FP32 with FP64 refinement and in FP64.  One JSON
+line is printed on stdout.
 """
 from __future__ import annotations
 
@@ -56,16 +57,16 @@ PREC_NAME = {0: "fp64", 1: "fp32", 2: "bf16", 3: "fp16"}
 # grid (`python bench.py --traffic-probe` under `rocprofv3 --pmc`), scaled by the same counters
 # on a device copy of known size (FETCH_SIZE x 2, WRITE_SIZE x 1).  Valid while the kernels
 # are unchanged since that measurement; see profiles/hbm_traffic_2560x1920x70.txt.
-MEASURED_TRAFFIC = {("c3", "spmv_fp64"): 28.74e9, ("c3", "spmv_fp32"): 14.67e9, ("c3", "spmv_bf16"): 9.82e9,
-                    ("c3", "thomas_p_fp64"): 22.02e9, ("c3", "thomas_s_fp64"): 19.27e9, ("c3", "update_fp64"): 22.02e9,
-                    ("c3", "thomas_p_fp32"): 11.01e9, ("c3", "thomas_s_fp32"): 9.63e9, ("c3", "update_fp32"): 11.01e9,
-                    ("c3", "thomas_p_bf16"): 11.01e9, ("c3", "thomas_s_bf16"): 9.63e9, ("c3", "update_bf16"): 11.01e9,
-                    ("c3", "residual_fp64"): 27.35e9,
-                    ("c3", "thomas_p_cm_fp64"): 24.78e9, ("c3", "thomas_s_cm_fp64"): 22.02e9,
-                    ("c3", "thomas_p_cm_fp32"): 12.39e9, ("c3", "thomas_s_cm_fp32"): 11.01e9,
-                    ("c3", "thomas_p_cm_bf16"): 12.39e9, ("c3", "thomas_s_cm_bf16"): 11.01e9,
+MEASURED_TRAFFIC = {("n1280_2560x1920x70", "spmv_fp64"): 28.74e9, ("n1280_2560x1920x70", "spmv_fp32"): 14.67e9, ("n1280_2560x1920x70", "spmv_bf16"): 9.82e9,
+                    ("n1280_2560x1920x70", "thomas_p_fp64"): 22.02e9, ("n1280_2560x1920x70", "thomas_s_fp64"): 19.27e9, ("n1280_2560x1920x70", "update_fp64"): 22.02e9,
+                    ("n1280_2560x1920x70", "thomas_p_fp32"): 11.01e9, ("n1280_2560x1920x70", "thomas_s_fp32"): 9.63e9, ("n1280_2560x1920x70", "update_fp32"): 11.01e9,
+                    ("n1280_2560x1920x70", "thomas_p_bf16"): 11.01e9, ("n1280_2560x1920x70", "thomas_s_bf16"): 9.63e9, ("n1280_2560x1920x70", "update_bf16"): 11.01e9,
+                    ("n1280_2560x1920x70", "residual_fp64"): 27.35e9,
+                    ("n1280_2560x1920x70", "thomas_p_cm_fp64"): 24.78e9, ("n1280_2560x1920x70", "thomas_s_cm_fp64"): 22.02e9,
+                    ("n1280_2560x1920x70", "thomas_p_cm_fp32"): 12.39e9, ("n1280_2560x1920x70", "thomas_s_cm_fp32"): 11.01e9,
+                    ("n1280_2560x1920x70", "thomas_p_cm_bf16"): 12.39e9, ("n1280_2560x1920x70", "thomas_s_cm_bf16"): 11.01e9,
                     # one line-SOR application = five half-sweeps
-                    ("c3", "sor_fp64"): 80.85e9, ("c3", "sor_fp32"): 39.82e9, ("c3", "sor_bf16"): 32.78e9}
+                    ("n1280_2560x1920x70", "sor_fp64"): 80.85e9, ("n1280_2560x1920x70", "sor_fp32"): 39.82e9, ("n1280_2560x1920x70", "sor_bf16"): 32.78e9}
 
 
 def log(*a):
@@ -160,7 +161,7 @@ def learned_comparison(eg, torch, net, cfg_name, tol):
     del coef
     torch.cuda.empty_cache()
     op.attach(net)
-    out = {"workload": f"{cfg_name}: {p.nlon}x{p.nlat}x{p.nlev}, b ~ N(0,1), tol {tol}"}
+    out = {"workload": f"{p.nlon}x{p.nlat}x{p.nlev}, b ~ N(0,1), tol {tol}", "case": cfg_name}
     x = torch.zeros(p.n, dtype=torch.float64, device="cuda")
     for name, mode, method in (("bicgstab_tri_fp32_ir", eg.FP32_IR, 0),
                                ("bicgstab_learned_fp32_ir", eg.LEARNED_FP32_IR, 0),
@@ -228,11 +229,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", default="c3")
+    ap.add_argument("--config", default="n1280_2560x1920x70")
     ap.add_argument("--modes", default="fp64,fp32_ir,fp32_ir_bf16,fp64_sor,fp32_ir_sor,fp32_ir_bf16_sor")
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--learned-config", default="c4", help="workload of the learned-preconditioner comparison ('' skips it)")
+    ap.add_argument("--learned-config", default="learned_640x480x70", help="workload of the learned-preconditioner comparison ('' skips it)")
     ap.add_argument("--train-shape", default="160x120x70")
     ap.add_argument("--train-ops", type=int, default=16)
     ap.add_argument("--train-vecs", type=int, default=20)
@@ -274,7 +275,7 @@ def main():
         del x, b
         torch.cuda.empty_cache()
         # three network applications on the learned preconditioner's workload
-        p4 = synth.CONFIGS[args.learned_config or "c4"]
+        p4 = synth.CONFIGS[args.learned_config or "learned_640x480x70"]
         coef, _ = generate_on_device(p4, torch)
         op = eg.Operator(coef)
         del coef
@@ -284,7 +285,7 @@ def main():
             net.apply(op, q)
         torch.cuda.synchronize()
         print(json.dumps({"traffic_probe": args.config, "copy_bytes_read": p.n * 8, "copy_bytes_written": p.n * 8,
-                          "net_workload": args.learned_config or "c4"}))
+                          "net_workload": args.learned_config or "learned_640x480x70"}))
         return
     name2mode = {v: k for k, v in eg.MODE_NAMES.items()}
     # a "_sor" suffix runs the mode with the red-black line SOR preconditioner (option precond 1)
@@ -437,8 +438,8 @@ def main():
         "vs_baseline": None,
         "dtype": ",".join(dtypes),
         "data": "synthetic (seeded operator recipe and b ~ N(0,1); no UM data)",
-        "config": {"workload": f"{args.config}: {p.nlon}x{p.nlat}x{p.nlev} Helmholtz solve to 1e-8, one solve per mode "
-                               f"({','.join(name for name, _, _ in runs)})",
+        "config": {"workload": f"{p.nlon}x{p.nlat}x{p.nlev} Helmholtz solve to 1e-8, one solve per mode "
+                               f"({','.join(name for name, _, _ in runs)})", "case": args.config,
                    "grid": [p.nlon, p.nlat, p.nlev], "dof": p.n, "tol": args.tol, "parallelism": "1 GPU"},
         "modes": modes_out,
         "setup_seconds": {"generate_host": round(t_gen, 2), "operator_fp64": round(t_setup64, 3),

@@ -77,22 +77,22 @@ class Problem:
         return (self.nlev, self.nlat, self.nlon)
 
 
-def _c5_ratio() -> float:
+def _stress_ratio() -> float:
     # 140 levels with the same top/bottom thickness ratio as 70 levels at r = 1.1
     return 1.1 ** (69.0 / 139.0)
 
 
 CONFIGS: dict[str, Problem] = {
     # small correctness case (96 x 72 x 20, n = 138,240)
-    "c1": Problem(96, 72, 20, name="c1"),
+    "small_96x72x20": Problem(96, 72, 20, name="small_96x72x20"),
     # 640 x 480 x 70 (21.5M dof); right-hand side from a smooth manufactured solution
-    "c2": Problem(640, 480, 70, name="c2"),
+    "manufactured_640x480x70": Problem(640, 480, 70, name="manufactured_640x480x70"),
     # N1280-shaped grid 2560 x 1920 x 70 (344M dof)
-    "c3": Problem(2560, 1920, 70, name="c3"),
-    # learned-preconditioner case, same operator as c2
-    "c4": Problem(640, 480, 70, name="c4"),
+    "n1280_2560x1920x70": Problem(2560, 1920, 70, name="n1280_2560x1920x70"),
+    # learned-preconditioner case, same operator as the manufactured case
+    "learned_640x480x70": Problem(640, 480, 70, name="learned_640x480x70"),
     # stress case 1280 x 960 x 140, near-singular shift, 1e4 diffusivity contrast
-    "c5": Problem(1280, 960, 140, shift=1e-6, ratio=_c5_ratio(), bands=True, name="c5"),
+    "stress_1280x960x140": Problem(1280, 960, 140, shift=1e-6, ratio=_stress_ratio(), bands=True, name="stress_1280x960x140"),
 }
 
 

@@ -29,9 +29,9 @@ def eg():
 
 
 @pytest.fixture(scope="module")
-def c3(eg):
+def n1280(eg):
     import torch
-    p = synth.CONFIGS["c3"]
+    p = synth.CONFIGS["n1280_2560x1920x70"]
     coef = synth.make_coeffs(p, threads=16)
     b = synth.make_rhs(p).ravel()
     print(f"[fullsize] 2560x1920x70 generated", flush=True)
@@ -57,9 +57,9 @@ def _columns(coef, cols):
     return np.ascontiguousarray(coef[:, :, j, i][:, :, None, :])
 
 
-def test_spmv_sampled_rows(eg, oracle_mod, c3):
+def test_spmv_sampled_rows(eg, oracle_mod, n1280):
     import torch
-    p, coef, _, op = c3
+    p, coef, _, op = n1280
     rng = np.random.default_rng(31)
     x = rng.standard_normal(p.n)
     idx = _sample_points(p, rng, 20000)
@@ -78,9 +78,9 @@ def test_spmv_sampled_rows(eg, oracle_mod, c3):
         assert np.all(err <= (rel + 32 * EPS32) * scale)
 
 
-def test_thomas_sampled_columns(eg, oracle_mod, c3):
+def test_thomas_sampled_columns(eg, oracle_mod, n1280):
     import torch
-    p, coef, _, op = c3
+    p, coef, _, op = n1280
     rng = np.random.default_rng(32)
     P = p.nlon * p.nlat
     cols = np.unique(np.concatenate([rng.integers(0, P, 3000), [0, p.nlon - 1, P - p.nlon, P - 1]]))
@@ -123,14 +123,14 @@ def _sor_window(coef, q, nlon, nlat, i0, j0, radius):
     return sub, qs, j0 - j_lo, i0 - i_lo
 
 
-def test_line_sor_sampled_columns(eg, oracle_mod, c3):
+def test_line_sor_sampled_columns(eg, oracle_mod, n1280):
     """The red-black line SOR (3 sweeps, omega 1.5, the kernels and launch shape of the solver)
     on sampled columns.  After the five half-sweeps that follow the tridiagonal solve, a column
     depends only on the columns within 5 steps of it; the oracle runs on a window of radius 6
     around each sample (its edges, where the window cuts couplings, are wrong but cannot reach
     the centre) and its centre column is compared with the GPU's, all 70 levels."""
     import torch
-    p, coef, _, op = c3
+    p, coef, _, op = n1280
     rng = np.random.default_rng(34)
     q = rng.standard_normal(p.n)
     qd = torch.from_numpy(q).cuda()
@@ -158,9 +158,9 @@ def test_line_sor_sampled_columns(eg, oracle_mod, c3):
     assert worst64 <= 1e-11 and worst32 <= 2e-5
 
 
-def test_all_modes_reach_1e8_true_residual(eg, oracle_mod, c3):
+def test_all_modes_reach_1e8_true_residual(eg, oracle_mod, n1280):
     import torch
-    p, coef, b, op = c3
+    p, coef, b, op = n1280
     bd = torch.from_numpy(b).cuda()
     nb = np.linalg.norm(b)
     sols = {}
@@ -201,13 +201,13 @@ def _quick_net(eg):
     return net
 
 
-def test_learned_modes_2560x1920x70(eg, oracle_mod, c3):
+def test_learned_modes_2560x1920x70(eg, oracle_mod, n1280):
     """Both learned modes on the 344M-unknown grid, in the method the benchmark configuration
     names (flexible BiCGStab with the tridiagonal fallback): they reach 1e-8 (true residual by
     the oracle's FP64 product on the host), whether the network carries the solve or the
     fallback finishes it."""
     import torch
-    p, coef, b, op = c3
+    p, coef, b, op = n1280
     net = _quick_net(eg)
     bd = torch.from_numpy(b).cuda()
     nb = np.linalg.norm(b)
@@ -230,7 +230,7 @@ def test_learned_modes_2560x1920x70(eg, oracle_mod, c3):
 
 def test_manufactured_solution_640x480x70(eg, oracle_mod):
     import torch
-    p = synth.CONFIGS["c2"]
+    p = synth.CONFIGS["manufactured_640x480x70"]
     coef = synth.make_coeffs(p, threads=16)
     xs = synth.make_xstar(p).ravel()
     b = oracle_mod.apply(coef, xs)
@@ -252,7 +252,7 @@ def test_stress_case_1280x960x140(eg, oracle_mod):
     residual by the oracle's FP64 product on the host); the solutions agree within the
     conditioning of the problem."""
     import torch
-    p = synth.CONFIGS["c5"]
+    p = synth.CONFIGS["stress_1280x960x140"]
     coef = synth.make_coeffs(p, threads=16)
     b = synth.make_rhs(p).ravel()
     print("[fullsize] 1280x960x140 generated", flush=True)
@@ -286,7 +286,7 @@ def test_network_sampled_columns_640x480x70(eg, oracle_mod):
     is compared with the GPU's (BF16 activations on both sides)."""
     import torch
     from oracle import net as onet
-    p = synth.CONFIGS["c4"]
+    p = synth.CONFIGS["learned_640x480x70"]
     coef = synth.make_coeffs(p, threads=16)
     rng = np.random.default_rng(35)
     d = onet.unpack(onet.init_theta(6))
@@ -329,7 +329,7 @@ def test_learned_preconditioner_640x480x70(eg, oracle_mod):
     FP32 with FP64 refinement (true residual by the oracle)."""
     import torch
     net = _quick_net(eg)
-    p = synth.CONFIGS["c4"]
+    p = synth.CONFIGS["learned_640x480x70"]
     coef = synth.make_coeffs(p, threads=16)
     b = synth.make_rhs(p).ravel()
     with eg.Operator(torch.from_numpy(coef).cuda()) as op:

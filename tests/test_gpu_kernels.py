@@ -14,7 +14,7 @@ SHAPES = [
     synth.Problem(130, 37, 5, seed=2),              # more than two lon tiles, ragged
     synth.Problem(3, 1, 1, seed=3),                 # smallest legal grid
     synth.Problem(64, 16, 70, seed=4),              # exact tiles, 70 levels
-    synth.Problem(40, 30, 24, seed=5, shift=1e-6, bands=True, ratio=synth._c5_ratio()),
+    synth.Problem(40, 30, 24, seed=5, shift=1e-6, bands=True, ratio=synth._stress_ratio()),
     synth.Problem(8, 1, 33, seed=6),                # one latitude row
 ]
 

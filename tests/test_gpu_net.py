@@ -86,7 +86,7 @@ def test_zero_output_layer_reproduces_plain_solver_bitwise(eg):
     """Untrained net (zero output layer): delta = 0 exactly, so flexible BiCGStab with the
     learned M follows the tridiagonal-preconditioned trajectory bit for bit."""
     import torch
-    p = synth.CONFIGS["c1"]
+    p = synth.CONFIGS["small_96x72x20"]
     coef = synth.make_coeffs(p)
     b = dev(synth.make_rhs(p).ravel())
     net = eg.Net(3)
@@ -108,7 +108,7 @@ def test_zero_output_layer_reproduces_plain_solver_bitwise(eg):
 def test_zero_output_layer_fgmres_is_plain_fgmres_bitwise(eg):
     """Same identity for FGMRES: with delta = 0 the learned modes run plain FGMRES."""
     import torch
-    p = synth.CONFIGS["c1"]
+    p = synth.CONFIGS["small_96x72x20"]
     coef = synth.make_coeffs(p)
     b = dev(synth.make_rhs(p).ravel())
     net = eg.Net(3)

@@ -19,9 +19,9 @@ def eg():
 
 
 @pytest.fixture(scope="module")
-def c1(oracle_mod):
+def small(oracle_mod):
     """The small configuration and its oracle solution at tol 1e-12."""
-    p = synth.CONFIGS["c1"]
+    p = synth.CONFIGS["small_96x72x20"]
     coef = synth.make_coeffs(p)
     b = synth.make_rhs(p).ravel()
     x_ref, info = oracle_mod.bicgstab(coef, b, tol=1e-12)
@@ -33,10 +33,10 @@ def _true_rel(oracle_mod, coef, b, x):
     return np.linalg.norm(b - oracle_mod.apply(coef, x)) / np.linalg.norm(b)
 
 
-def test_fp64_parity_tight_tolerance(eg, oracle_mod, c1):
+def test_fp64_parity_tight_tolerance(eg, oracle_mod, small):
     """Both solvers at tol 1e-12: the GPU x matches the oracle x to 1e-10 relative L2."""
     import torch
-    p, coef, b, x_ref, info_ref = c1
+    p, coef, b, x_ref, info_ref = small
     with eg.Operator(dev(coef)) as op:
         x = torch.zeros(p.n, dtype=torch.float64, device="cuda")
         info = op.solve(dev(b), x, tol=1e-12, maxit=5000, mode=eg.FP64)
@@ -52,7 +52,7 @@ def test_fp64_parity_tight_tolerance(eg, oracle_mod, c1):
 
 
 @pytest.mark.parametrize("p", [synth.Problem(67, 13, 9, seed=1), synth.Problem(130, 37, 5, seed=2),
-                               synth.Problem(40, 30, 24, seed=5, shift=1e-6, bands=True, ratio=synth._c5_ratio()),
+                               synth.Problem(40, 30, 24, seed=5, shift=1e-6, bands=True, ratio=synth._stress_ratio()),
                                synth.Problem(64, 16, 70, seed=4)],
                          ids=lambda p: f"{p.nlon}x{p.nlat}x{p.nlev}")
 def test_fp64_parity_shapes(eg, oracle_mod, p):
@@ -72,11 +72,11 @@ def test_fp64_parity_shapes(eg, oracle_mod, p):
 
 
 @pytest.mark.parametrize("mode_name", ["FP64", "FP32_IR", "FP32_IR_BF16", "FP32_IR_FP16"])
-def test_modes_reach_1e8_true_residual(eg, oracle_mod, c1, mode_name):
+def test_modes_reach_1e8_true_residual(eg, oracle_mod, small, mode_name):
     """Every precision mode reaches ||b - A x|| / ||b|| <= 1e-8, checked by the oracle's FP64
     product on the returned x; the error against the FP64 oracle solution is reported."""
     import torch
-    p, coef, b, x_ref, _ = c1
+    p, coef, b, x_ref, _ = small
     with eg.Operator(dev(coef)) as op:
         x = torch.zeros(p.n, dtype=torch.float64, device="cuda")
         info = op.solve(dev(b), x, tol=1e-8, maxit=20000, mode=getattr(eg, mode_name))
@@ -92,10 +92,10 @@ def test_modes_reach_1e8_true_residual(eg, oracle_mod, c1, mode_name):
             assert info.outer_steps >= 1
 
 
-def test_refinement_outer_residuals_fall_by_eta(eg, oracle_mod, c1):
+def test_refinement_outer_residuals_fall_by_eta(eg, oracle_mod, small):
     """Each FP64 refinement step reduces the true residual by at least 10x."""
     import torch
-    p, coef, b, _, _ = c1
+    p, coef, b, _, _ = small
     with eg.Operator(dev(coef)) as op:
         op.set_option("eta", 1e-3)
         x = torch.zeros(p.n, dtype=torch.float64, device="cuda")
@@ -108,9 +108,9 @@ def test_refinement_outer_residuals_fall_by_eta(eg, oracle_mod, c1):
         assert rels[1] <= 0.1 * rels[0] and rels[2] <= 0.1 * rels[1], rels
 
 
-def test_special_cases(eg, oracle_mod, c1):
+def test_special_cases(eg, oracle_mod, small):
     import torch
-    p, coef, b, x_ref, _ = c1
+    p, coef, b, x_ref, _ = small
     with eg.Operator(dev(coef)) as op:
         # b = 0 -> x = 0
         x = torch.randn(p.n, dtype=torch.float64, device="cuda")
@@ -151,9 +151,9 @@ def test_decoupled_columns_converge_in_one_half_step(eg, oracle_mod):
         assert np.max(np.abs(host(x) - ref)) <= 1e-13 * np.abs(ref).max()
 
 
-def test_periodic_restart(eg, oracle_mod, c1):
+def test_periodic_restart(eg, oracle_mod, small):
     import torch
-    p, coef, b, x_ref, _ = c1
+    p, coef, b, x_ref, _ = small
     with eg.Operator(dev(coef)) as op:
         op.set_option("restart_every", 20)
         x = torch.zeros(p.n, dtype=torch.float64, device="cuda")
@@ -164,9 +164,9 @@ def test_periodic_restart(eg, oracle_mod, c1):
         assert abs(oi.iterations - info.iterations) <= max(3, oi.iterations // 10)
 
 
-def test_bitwise_deterministic(eg, c1):
+def test_bitwise_deterministic(eg, small):
     import torch
-    p, coef, b, _, _ = c1
+    p, coef, b, _, _ = small
     with eg.Operator(dev(coef)) as op:
         outs = []
         for _ in range(2):
@@ -178,13 +178,13 @@ def test_bitwise_deterministic(eg, c1):
             assert np.array_equal(a[0], b2[0]) and np.array_equal(a[1], b2[1])
 
 
-def test_fgmres_fp64_matches_oracle(eg, oracle_mod, c1):
+def test_fgmres_fp64_matches_oracle(eg, oracle_mod, small):
     """Restarted FGMRES(30) with T^{-1}: the same residual history as the FP64 oracle FGMRES
     (the same method; the GPU orthogonalises by classical Gram-Schmidt applied twice, the oracle
     by modified Gram-Schmidt, equal in exact arithmetic) and the same solution."""
     import torch
     from oracle import krylov
-    p, coef, b, x_ref, _ = c1
+    p, coef, b, x_ref, _ = small
     x_o, info_o = krylov.fgmres(coef, b, tol=1e-10, m=30, maxit=3000)
     assert info_o.status == 0
     with eg.Operator(dev(coef)) as op:
@@ -206,9 +206,9 @@ def test_fgmres_fp64_matches_oracle(eg, oracle_mod, c1):
 
 
 @pytest.mark.parametrize("mode_name", ["FP32_IR", "FP32_IR_BF16"])
-def test_fgmres_refinement_modes_reach_1e8(eg, oracle_mod, c1, mode_name):
+def test_fgmres_refinement_modes_reach_1e8(eg, oracle_mod, small, mode_name):
     import torch
-    p, coef, b, x_ref, _ = c1
+    p, coef, b, x_ref, _ = small
     with eg.Operator(dev(coef)) as op:
         op.set_option("method", 1)
         x = torch.zeros(p.n, dtype=torch.float64, device="cuda")
@@ -220,8 +220,8 @@ def test_fgmres_refinement_modes_reach_1e8(eg, oracle_mod, c1, mode_name):
     assert np.linalg.norm(xh - x_ref) <= 1e-5 * np.linalg.norm(x_ref)
 
 
-def test_fgmres_options_are_checked(eg, c1):
-    p, coef, b, _, _ = c1
+def test_fgmres_options_are_checked(eg, small):
+    p, coef, b, _, _ = small
     with eg.Operator(dev(coef)) as op:
         for key, bad in (("method", 2), ("learned_method", -1), ("gmres_m", 0), ("gmres_m", 65)):
             with pytest.raises(eg.EndgameError):
@@ -229,11 +229,11 @@ def test_fgmres_options_are_checked(eg, c1):
 
 
 @pytest.mark.parametrize("tol", [1e-4, 1e-6])
-def test_paper_mixed_precision_mode(eg, oracle_mod, c1, tol):
+def test_paper_mixed_precision_mode(eg, oracle_mod, small, tol):
     """The paper's MP BiCGStab (FP32 vectors, FP64 solution and sums, no refinement) at the
     tolerances the paper uses: converges with about the FP64 iteration count."""
     import torch
-    p, coef, b, x_ref, _ = c1
+    p, coef, b, x_ref, _ = small
     with eg.Operator(dev(coef)) as op:
         x = torch.zeros(p.n, dtype=torch.float64, device="cuda")
         info = op.solve(dev(b), x, tol, 5000, eg.FP32_MP)
@@ -249,14 +249,14 @@ def test_paper_mixed_precision_mode(eg, oracle_mod, c1, tol):
 
 @pytest.mark.parametrize("precond", [0, 1], ids=["tri", "line_sor"])
 @pytest.mark.parametrize("tol", [1e-4, 1e-6])
-def test_paper_mixed_precision_matches_the_mp_oracle(eg, oracle_mod, c1, precond, tol):
+def test_paper_mixed_precision_matches_the_mp_oracle(eg, oracle_mod, small, precond, tol):
     """EG_FP32_MP against the CPU emulation of the paper's mixed-precision BiCGStab (FP32
     vectors, FP64 x and sums, restart every 150; oracle/mp.py): the first residual-history
     entries agree to FP32 rounding, the iteration counts within 10 % (both sides round
     differently, and BiCGStab amplifies it), and both true residuals are below tol."""
     import torch
     from oracle import mp
-    p, coef, b, x_ref, _ = c1
+    p, coef, b, x_ref, _ = small
     xo, ref = mp.bicgstab_mp(coef, b, tol=tol, precond="sor" if precond else "tri")
     with eg.Operator(dev(coef)) as op:
         op.set_option("precond", precond)

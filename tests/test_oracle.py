@@ -221,7 +221,7 @@ def test_bicgstab_eigenmode_identity_preconditioner(oracle_mod):
 
 
 def test_bicgstab_history_and_special_cases(oracle_mod):
-    prob = synth.CONFIGS["c1"]
+    prob = synth.CONFIGS["small_96x72x20"]
     coef = synth.make_coeffs(prob)
     b = synth.make_rhs(prob).ravel()
     x, info = oracle_mod.bicgstab(coef, b, tol=1e-8)
@@ -244,7 +244,7 @@ def test_bicgstab_history_and_special_cases(oracle_mod):
 
 def test_bicgstab_periodic_restart(oracle_mod):
     """A mandatory restart every 20 iterations (Sec. 4 uses 150 operationally) still converges."""
-    prob = synth.CONFIGS["c1"]
+    prob = synth.CONFIGS["small_96x72x20"]
     coef = synth.make_coeffs(prob)
     b = synth.make_rhs(prob).ravel()
     x_ref, _ = oracle_mod.bicgstab(coef, b, tol=1e-11)

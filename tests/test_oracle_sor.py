@@ -103,7 +103,7 @@ def test_lexicographic_sor_matches_the_dense_gauss_seidel_splitting():
 def test_red_black_and_lexicographic_orders_precondition_alike():
     """BiCGStab iteration counts with the two column orders (3 sweeps, omega 1.5) on the
     96x72x20 operator: the red-black order the GPU uses is as strong as the natural one."""
-    p = synth.CONFIGS["c1"]
+    p = synth.CONFIGS["small_96x72x20"]
     coef = synth.make_coeffs(p)
     b = synth.make_rhs(p).ravel()
     _, i_rb = oracle.bicgstab(coef, b, tol=1e-8, precond=2)

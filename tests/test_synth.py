@@ -7,7 +7,7 @@ import synth
 
 
 def test_shapes_boundaries_margin():
-    for p in (synth.CONFIGS["c1"], synth.Problem(33, 17, 9, shift=1e-6, ratio=synth._c5_ratio(), bands=True)):
+    for p in (synth.CONFIGS["small_96x72x20"], synth.Problem(33, 17, 9, shift=1e-6, ratio=synth._stress_ratio(), bands=True)):
         c = synth.make_coeffs(p)
         assert c.shape == (7, p.nlev, p.nlat, p.nlon) and c.dtype == np.float64
         assert np.all(c[:6] >= 0)
@@ -34,10 +34,10 @@ def test_levels_and_aspect():
     dz = synth.level_thickness(70, 1.1)
     assert math.isclose(dz.sum(), 80_000.0, rel_tol=1e-12)
     assert math.isclose(dz[1] / dz[0], 1.1, rel_tol=1e-12)
-    dz5 = synth.level_thickness(140, synth._c5_ratio())
+    dz5 = synth.level_thickness(140, synth._stress_ratio())
     assert math.isclose(dz5[-1] / dz5[0], dz[-1] / dz[0], rel_tol=1e-9)
     # near-pole cell aspect ratio of the 2560 x 1920 grid: cos(phi_0) dlam / dphi ~ 1.23e-3
-    p = synth.CONFIGS["c3"]
+    p = synth.CONFIGS["n1280_2560x1920x70"]
     dphi = math.pi / p.nlat
     dlam = 2 * math.pi / p.nlon
     asp = math.cos(-math.pi / 2 + 0.5 * dphi) * dlam / dphi
@@ -45,7 +45,7 @@ def test_levels_and_aspect():
 
 
 def test_band_contrast():
-    k = synth.band_diffusivity(synth.CONFIGS["c5"])
+    k = synth.band_diffusivity(synth.CONFIGS["stress_1280x960x140"])
     assert k.min() == 1e-2 and k.max() == 1e2
     assert len(np.unique(k)) <= 8
     # contiguous bands
@@ -53,7 +53,7 @@ def test_band_contrast():
 
 
 def test_xstar_smooth_plus_noise():
-    p = synth.CONFIGS["c1"]
+    p = synth.CONFIGS["small_96x72x20"]
     x = synth.make_xstar(p)
     x0 = synth.make_xstar(p, noise=0.0)
     d = x - x0
