@@ -227,7 +227,7 @@ def paper_study(eg, torch, op, b):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="n1280_2560x1920x70")
     ap.add_argument("--modes", default="fp64,fp32_ir,fp32_ir_bf16,fp64_sor,fp32_ir_sor,fp32_ir_bf16_sor")
