@@ -7,6 +7,10 @@
 //   k_update    x += alpha phat + omega shat; r = s - omega t; <rhat, r>, <r, r> partials.
 //   k_finalize  fixed-order FP64 sum of the per-workgroup partials (Sec. 4: 64-bit global
 //               sums) and the scalar recurrences of BiCGStab, in one workgroup.
+//   k_sor_half_reg, k_sor_half
+//               one red-black half-sweep of the vertical-line SOR (Sec. 2, Eq. 7).
+//   k_mdot, k_maxpy, k_msum, k_vscale
+//               Gram-Schmidt building blocks of FGMRES.
 //
 // Every floating-point sum that leaves a workgroup is FP64 and is reduced in a fixed order, so
 // results are bitwise reproducible for a given grid.
@@ -1347,7 +1351,8 @@ void launch_quantize(int kind, int nlon, int nlat, int nlev, const double *a64, 
 //     x_c <- (1 - omega) x_c + omega T_c^{-1} (q_c + sum of its horizontal couplings times x)
 // With nlon even every horizontal neighbour has the other colour, so the columns of one colour
 // are independent: one lane per column, the rhs gathered level by level on the way up, w_k of
-// the Thomas forward sweep parked in a scratch vector, the blend done on the way down.
+// the Thomas forward sweep kept (in registers at 70 levels, k_sor_half_reg; otherwise parked
+// in a scratch vector, k_sor_half), the blend done on the way down.
 //
 // Layout: everything a half-sweep touches is in colour-major order,
 // index = colour * n/2 + k * P/2 + c2 with c2 = j * nlon/2 + i/2: the operator constants (the
