@@ -142,6 +142,8 @@ int eg_set_stream(eg_operator *op, void *hip_stream);
  *   "restart_every"  mandatory restart period in iterations, 0 = off [0]
  *                    (Sec. 4 uses 150 operationally)
  *   "max_outer"      limit on refinement steps [30]
+ *   "inner_maxit"    limit on the iterations of one inner FP32 solve [1000]; the correction of
+ *                    a capped inner solve is kept only if it lowers the FP64 true residual
  *   "poll"           iterations enqueued between host checks of the device flags [8]
  *   "stall_window"   learned modes: iterations without a 2x gain that trigger fallback [20]
  *                    (FGMRES: at least one restart cycle, max(stall_window, gmres_m))

@@ -127,6 +127,7 @@ struct eg_operator {
     double eta = 1e-4;
     int restart_every = 0;
     int max_outer = 30;
+    int inner_maxit = 1000;     // iterations of one inner FP32 solve of the refinement
     int poll = 8;
     int stall_window = 20;
     int precond = 0;            // plain modes: 0 T^{-1}, 1 red-black vertical-line SOR
@@ -869,7 +870,10 @@ int solve_ir(eg_operator *op, const OpView<Tc> &A32, const double *b, double *x,
         rel_prev = rel;
         // inner solve  A32 d = r32  to relative tolerance eta (no tighter than this step needs)
         const double eta = std::max(op->eta, 0.25 * tol / rel);
-        if ((rc = put_run_params(op, eta, maxit - total, total, op->restart_every))) return rc;
+        // a capped inner solve still hands over its correction; the check of the true residual
+        // above undoes it if it did not help
+        const int inner_cap = std::min(maxit - total, op->inner_maxit);
+        if ((rc = put_run_params(op, eta, inner_cap, total, op->restart_every))) return rc;
         launch_finalize(FIN_INIT, op->partials, nr, op->sc, op->d_hist, nullptr, 2, 2, s);
         launch_fill<float>(w.x, op->n, 0.0f, s);
         EG_HIP(hipGetLastError());
@@ -886,7 +890,7 @@ int solve_ir(eg_operator *op, const OpView<Tc> &A32, const double *b, double *x,
             int its = 0, st = 1, fb = 0;
             const Tc *coef = nullptr;
             if constexpr (std::is_same_v<Tc, float>) coef = op->a32;
-            if ((rc = fgmres<float, Tc>(op, A32, w.x, nb_in, eta, maxit - total, use_net ? net : nullptr, coef, resid,
+            if ((rc = fgmres<float, Tc>(op, A32, w.x, nb_in, eta, inner_cap, use_net ? net : nullptr, coef, resid,
                                         &its, &st, &fb)))
                 return rc;
             if (fb) {
@@ -1199,6 +1203,9 @@ int eg_set_option(eg_operator *op, const char *key, double value)
     } else if (k == "max_outer") {
         if (value < 1) return fail(EG_EINVAL, "max_outer must be >= 1");
         op->max_outer = (int)value;
+    } else if (k == "inner_maxit") {
+        if (value < 1 || value != std::floor(value)) return fail(EG_EINVAL, "inner_maxit must be an integer >= 1");
+        op->inner_maxit = (int)std::min(value, 1e9);
     } else if (k == "poll") {
         if (value < 1 || value > 4096) return fail(EG_EINVAL, "poll must be in [1, 4096]");
         op->poll = (int)value;

@@ -245,37 +245,64 @@ def test_manufactured_solution_640x480x70(eg, oracle_mod):
             assert info.status == eg.CONVERGED and rel <= 1e-8 * (1 + 1e-6) and fwd <= 1e-5
 
 
-def test_stress_case_1280x960x140(eg, oracle_mod):
+@pytest.fixture(scope="module")
+def stress():
+    """The stress case on the host: 1280x960x140, shift 1e-6, vertical diffusivity contrast 1e4."""
+    p = synth.CONFIGS["stress_1280x960x140"]
+    coef = synth.make_coeffs(p, threads=16)
+    b = synth.make_rhs(p).ravel()
+    print("[fullsize] 1280x960x140 generated", flush=True)
+    return p, coef, b
+
+
+def _stress_solve(eg, oracle_mod, op, stress, name, mode):
+    import torch
+    p, coef, b = stress
+    x = torch.zeros(p.n, dtype=torch.float64, device="cuda")
+    print(f"[fullsize] 1280x960x140 {name}", flush=True)
+    info = op.solve(torch.from_numpy(b).cuda(), x, 1e-8, 20000, mode)
+    xh = host(x)
+    rel = np.linalg.norm(b - oracle_mod.apply(coef, xh)) / np.linalg.norm(b)
+    print(f"1280x960x140 {name}: status {info.status}, {info.iterations} its, {info.outer_steps} outer, "
+          f"{info.fallbacks} fallbacks, {info.seconds:.2f} s, true R {rel:.2e}", flush=True)
+    assert info.status == eg.CONVERGED and rel <= 1e-8 * (1 + 1e-6)
+    return xh
+
+
+def test_stress_case_1280x960x140(eg, oracle_mod, stress):
     """Coefficient contrast 1e4 in vertical bands, shift 1e-6 (near-singular), 140 levels: FP64
     (line SOR), FP32 inner + FP64 refinement with T^{-1} (whose FP32 inner solve fails here: the
     safeguard undoes it and the FP64 solver finishes) and with line SOR reach 1e-8 (true
     residual by the oracle's FP64 product on the host); the solutions agree within the
     conditioning of the problem."""
     import torch
-    p = synth.CONFIGS["stress_1280x960x140"]
-    coef = synth.make_coeffs(p, threads=16)
-    b = synth.make_rhs(p).ravel()
-    print("[fullsize] 1280x960x140 generated", flush=True)
-    nb = np.linalg.norm(b)
+    p, coef, b = stress
     sols = {}
     with eg.Operator(torch.from_numpy(coef).cuda()) as op:
-        bd = torch.from_numpy(b).cuda()
         for name, mode, pc in (("FP64+SOR", eg.FP64, 1), ("FP32_IR", eg.FP32_IR, 0), ("FP32_IR+SOR", eg.FP32_IR, 1)):
             op.set_option("precond", pc)
-            x = torch.zeros(p.n, dtype=torch.float64, device="cuda")
-            print(f"[fullsize] 1280x960x140 {name}", flush=True)
-            info = op.solve(bd, x, 1e-8, 20000, mode)
-            xh = host(x)
-            rel = np.linalg.norm(b - oracle_mod.apply(coef, xh)) / nb
-            print(f"1280x960x140 {name}: status {info.status}, {info.iterations} its, {info.outer_steps} outer, "
-                  f"{info.fallbacks} fallbacks to FP64, {info.seconds:.2f} s, true R {rel:.2e}")
-            assert info.status == eg.CONVERGED and rel <= 1e-8 * (1 + 1e-6)
-            sols[name] = xh
+            sols[name] = _stress_solve(eg, oracle_mod, op, stress, name, mode)
     ref = sols["FP64+SOR"]
     for name in ("FP32_IR", "FP32_IR+SOR"):
         d = np.linalg.norm(sols[name] - ref) / np.linalg.norm(ref)
         print(f"{name} vs FP64+SOR: rel L2 {d:.2e}")
         assert d <= 1e-1   # shift 1e-6: cond(A) ~ 1e6, two solutions with R <= 1e-8 each
+
+
+def test_stress_case_learned_1280x960x140(eg, oracle_mod, stress):
+    """The learned preconditioner with FP32 inner iterations and FP64 refinement on the stress
+    case, in flexible BiCGStab with the tridiagonal fallback (the benchmark configuration's
+    method): it reaches 1e-8, by whichever path the safeguards leave it."""
+    import torch
+    p, coef, b = stress
+    net = _quick_net(eg)
+    try:
+        with eg.Operator(torch.from_numpy(coef).cuda()) as op:
+            op.attach(net)
+            op.set_option("learned_method", 0)
+            _stress_solve(eg, oracle_mod, op, stress, "LEARNED_FP32_IR", eg.LEARNED_FP32_IR)
+    finally:
+        net.close()
 
 
 def test_network_sampled_columns_640x480x70(eg, oracle_mod):

@@ -108,6 +108,30 @@ def test_refinement_outer_residuals_fall_by_eta(eg, oracle_mod, small):
         assert rels[1] <= 0.1 * rels[0] and rels[2] <= 0.1 * rels[1], rels
 
 
+@pytest.mark.parametrize("method", [0, 1], ids=["bicgstab", "fgmres"])
+def test_capped_inner_solves_still_refine(eg, oracle_mod, small, method):
+    """Option inner_maxit: every inner FP32 solve stops after 10 iterations, far from eta; the
+    refinement keeps each correction that lowers the FP64 true residual and still reaches 1e-8,
+    in more outer steps."""
+    import torch
+    p, coef, b, _, _ = small
+    with eg.Operator(dev(coef)) as op:
+        op.set_option("method", method)
+        x = torch.zeros(p.n, dtype=torch.float64, device="cuda")
+        free = op.solve(dev(b), x, 1e-8, 20000, eg.FP32_IR)
+        op.set_option("inner_maxit", 10)
+        x.zero_()
+        info = op.solve(dev(b), x, 1e-8, 20000, eg.FP32_IR)
+        for bad in (0, 2.5):
+            with pytest.raises(eg.EndgameError):
+                op.set_option("inner_maxit", bad)
+    rel = _true_rel(oracle_mod, coef, b, host(x))
+    print(f"inner_maxit 10: {info.outer_steps} outer steps, {info.iterations} its (uncapped: {free.outer_steps} "
+          f"outer, {free.iterations} its), {info.fallbacks} fallbacks, true R {rel:.2e}")
+    assert info.status == eg.CONVERGED and rel <= 1e-8 and info.fallbacks == 0
+    assert info.outer_steps > free.outer_steps and info.iterations <= 10 * info.outer_steps
+
+
 def test_special_cases(eg, oracle_mod, small):
     import torch
     p, coef, b, x_ref, _ = small
