@@ -85,6 +85,26 @@ def generate_on_device(p, torch):
     return coef, b
 
 
+def copy_rate(torch, n: int) -> float:
+    """GB/s of a device-to-device copy of n doubles (read + write), median of 5, HIP events."""
+    a = torch.empty(n, dtype=torch.float64, device="cuda")
+    a.fill_(1.0)
+    c = torch.empty_like(a)
+    c.copy_(a)
+    times = []
+    for _ in range(5):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        c.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+    del a, c
+    torch.cuda.empty_cache()
+    times.sort()
+    return round(2 * 8 * n / (times[2] * 1e-3) / 1e9, 1)
+
+
 def cpu_baseline(n_target: int, iterations: int, sample_iters: int = 20):
     """Single-thread oracle BiCGStab on a 640x480x70 grid of the same recipe for a fixed number
     of iterations; scaled per point and iteration to the benchmark grid."""
@@ -399,7 +419,10 @@ def main():
     roofline = {"bound": "hbm", "kernel": dom_name, "achieved": dom["gbs"], "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": round(dom["gbs"] / PEAK_HBM_GBS, 4), "traffic": traffic,
                 "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-                "bytes_per_launch": dom["bytes_per_launch"], "avg_ms": dom["avg_ms"]}
+                "bytes_per_launch": dom["bytes_per_launch"], "avg_ms": dom["avg_ms"],
+                "copy_gbs": copy_rate(torch, p.n),
+                "copy_note": "device-to-device copy of one FP64 grid vector on the same GPU, read + write bytes / "
+                             "time (median of 5): the attainable streaming rate, context for frac, not its denominator"}
 
     modes_out = {}
     for k, d in per_mode.items():
