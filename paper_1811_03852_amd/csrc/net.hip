@@ -328,6 +328,102 @@ __global__ __launch_bounds__(256) void k_conv_fwd(NetGeo g, const uint16_t *__re
 }
 
 // ------------------------------------------------------------------------------------------
+// The 3x3 layer when every tile of 16 positions lies in one latitude row (nlon % 16 == 0): a
+// lane loads its own position in the three rows j - 1, j, j + 1, and takes its west and east
+// neighbours from the lanes beside it (a DPP shift within the row of 16 lanes that holds one
+// channel group); only the tile's two edge columns are loaded separately, as one shared address
+// per row.  The taps are multiplied in the order of k_conv_fwd<2>, so the results are the same.
+// ------------------------------------------------------------------------------------------
+template <int CTRL> __device__ __forceinline__ bf16x8 dpp8(bf16x8 v)
+{
+    uint4 u = __builtin_bit_cast(uint4, v);
+    u.x = (uint32_t)__builtin_amdgcn_update_dpp((int)u.x, (int)u.x, CTRL, 0xf, 0xf, false);
+    u.y = (uint32_t)__builtin_amdgcn_update_dpp((int)u.y, (int)u.y, CTRL, 0xf, 0xf, false);
+    u.z = (uint32_t)__builtin_amdgcn_update_dpp((int)u.z, (int)u.z, CTRL, 0xf, 0xf, false);
+    u.w = (uint32_t)__builtin_amdgcn_update_dpp((int)u.w, (int)u.w, CTRL, 0xf, 0xf, false);
+    return __builtin_bit_cast(bf16x8, u);
+}
+constexpr int kDppRowShl1 = 0x101;   // lane m receives lane m + 1 of its row of 16
+constexpr int kDppRowShr1 = 0x111;   // lane m receives lane m - 1
+
+__global__ __launch_bounds__(256) void k_conv3x3_rows(NetGeo g, const uint16_t *__restrict__ in,
+                                                      const uint16_t *__restrict__ wf, const float *__restrict__ bias,
+                                                      uint16_t *__restrict__ out, const Scalars *__restrict__ sc,
+                                                      int stop_mask, int tiles, int kchunk, long units, int per_xcd)
+{
+    if (stop_now(sc, stop_mask)) return;
+    const int lane = threadIdx.x & 63, m = lane & 15, grp = lane >> 4;
+    __shared__ uint4 wsh[18 * 64];
+    for (int e = threadIdx.x; e < 18 * 64; e += 256) {
+        const int tn = e / 64, l = e % 64;   // tn = 2 t + nt
+        wsh[e] = *reinterpret_cast<const uint4 *>(wf + (long)(tn / 2) * 1024 + (16 * (tn % 2) + (l & 15)) * 32 +
+                                                  8 * (l >> 4));
+    }
+    __syncthreads();
+    const long unit = col_unit(per_xcd);
+    if (unit >= units) return;
+    float bs[2][4];
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) bs[nt][jj] = bias[16 * nt + 4 * grp + jj];
+    const int tile = (int)(unit % tiles);
+    const int k0 = (int)(unit / tiles) * kchunk;
+    const int k1 = min(g.nlev, k0 + kchunk);
+    const long t0 = (long)tile * 16, p2 = t0 + m;
+    const int nlon = g.nlon;
+    const int j = (int)(t0 / nlon), i0 = (int)(t0 % nlon);
+    const int il = (i0 == 0) ? nlon - 1 : i0 - 1;        // west of the tile's first column
+    const int ir = (i0 + 16 == nlon) ? 0 : i0 + 16;       // east of its last
+    const bool rv[3] = {j > 0, true, j < g.nlat - 1};     // rows j - 1, j, j + 1 exist
+    long own[3], wl[3], er[3];                             // positions in the level plane
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        const int jr = rv[r] ? j + r - 1 : j;              // a missing row reads row j, masked below
+        own[r] = (long)jr * nlon + (i0 + m);
+        wl[r] = (long)jr * nlon + il;
+        er[r] = (long)jr * nlon + ir;
+    }
+    auto load = [&](int k, bf16x8 *a) {
+        const uint16_t *base = in + (long)k * g.P * 32 + 8 * grp;
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+            a[r] = ld8(base + own[r] * 32);
+            a[3 + r] = ld8(base + wl[r] * 32);
+            a[6 + r] = ld8(base + er[r] * 32);
+        }
+    };
+    bf16x8 cur[9], nxt[9];
+    load(k0, cur);
+    for (int k = k0; k < k1; ++k) {
+        asm volatile("" ::: "memory");
+        load(min(k + 1, k1 - 1), nxt);   // the last level re-reads itself (in bounds, unused)
+        f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+            const bf16x8 o = cur[r];
+            bf16x8 w = dpp8<kDppRowShr1>(o);
+            bf16x8 e = dpp8<kDppRowShl1>(o);
+            w = keep8(m == 0 ? cur[3 + r] : w, rv[r]);
+            e = keep8(m == 15 ? cur[6 + r] : e, rv[r]);
+            const bf16x8 c = keep8(o, rv[r]);
+            const int t = 3 * r;   // taps (di, dj) = (-1, r - 1), (0, r - 1), (1, r - 1)
+            acc0 = mfma(__builtin_bit_cast(bf16x8, wsh[(2 * t) * 64 + lane]), w, acc0);
+            acc1 = mfma(__builtin_bit_cast(bf16x8, wsh[(2 * t + 1) * 64 + lane]), w, acc1);
+            acc0 = mfma(__builtin_bit_cast(bf16x8, wsh[(2 * t + 2) * 64 + lane]), c, acc0);
+            acc1 = mfma(__builtin_bit_cast(bf16x8, wsh[(2 * t + 3) * 64 + lane]), c, acc1);
+            acc0 = mfma(__builtin_bit_cast(bf16x8, wsh[(2 * t + 4) * 64 + lane]), e, acc0);
+            acc1 = mfma(__builtin_bit_cast(bf16x8, wsh[(2 * t + 5) * 64 + lane]), e, acc1);
+        }
+        uint16_t *dst = out + ((long)k * g.P + p2) * 32 + 4 * grp;
+        store4(dst, acc0, bs[0]);
+        store4(dst + 16, acc1, bs[1]);
+#pragma unroll
+        for (int t = 0; t < 9; ++t) cur[t] = nxt[t];
+    }
+}
+
+// ------------------------------------------------------------------------------------------
 // conv layer, backward data:  din[p][ci] = [aprev[p][ci] > 0] sum_{t, co} W[t][co][ci] dout[nb(p, -t)][co]
 // (the transposed convolution, masked by the derivative of the ReLU that produced aprev)
 // ------------------------------------------------------------------------------------------
@@ -875,8 +971,12 @@ void launch_net_forward_layers(const NetGeo &g, const NetDev &d, const NetActs &
     const ColGrid c = col_grid(g, 16);
     hipLaunchKernelGGL((k_conv_fwd<1>), dim3(c.blocks), dim3(256), 0, s, g, act.x0, d.w1f, d.theta + kNetOffB1, act.a1,
                        sc, stop_mask, c.tiles, c.kchunk, c.units, c.per_xcd);
-    hipLaunchKernelGGL((k_conv_fwd<2>), dim3(c.blocks), dim3(256), 0, s, g, act.a1, d.w2f, d.theta + kNetOffB2, act.a2,
-                       sc, stop_mask, c.tiles, c.kchunk, c.units, c.per_xcd);
+    if (g.nlon % 16 == 0)
+        hipLaunchKernelGGL(k_conv3x3_rows, dim3(c.blocks), dim3(256), 0, s, g, act.a1, d.w2f, d.theta + kNetOffB2,
+                           act.a2, sc, stop_mask, c.tiles, c.kchunk, c.units, c.per_xcd);
+    else
+        hipLaunchKernelGGL((k_conv_fwd<2>), dim3(c.blocks), dim3(256), 0, s, g, act.a1, d.w2f, d.theta + kNetOffB2,
+                           act.a2, sc, stop_mask, c.tiles, c.kchunk, c.units, c.per_xcd);
     hipLaunchKernelGGL((k_conv_fwd<3>), dim3(c.blocks), dim3(256), 0, s, g, act.a2, d.w3f, d.theta + kNetOffB3, act.a3,
                        sc, stop_mask, c.tiles, c.kchunk, c.units, c.per_xcd);
 }
