@@ -734,15 +734,24 @@ __global__ __launch_bounds__(256) void k_net_out(NetGeo g, const uint16_t *__res
     if (p2 >= g.P) return;
     // r[d] accumulates the output of level kk - 2 + d
     float r[5] = {b4, b4, b4, b4, b4};
+    // input rows are loaded one level ahead (clamped to the grid; a clamped row is not used)
+    auto ldrow = [&](int kk, uint4 *u) {
+        const int kc = min(max(kk, 0), g.nlev - 1);
+        const uint4 *row = reinterpret_cast<const uint4 *>(a3 + ((long)kc * g.P + p2) * 32);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) u[v] = row[v];
+    };
+    uint4 cur[4], nxt[4];
+    ldrow(k0 - 2, cur);
     for (int kk = k0 - 2; kk < k1 + 2; ++kk) {
         // keeps the weights in LDS (read as broadcasts every level) instead of 160 registers
         asm volatile("" ::: "memory");
+        ldrow(kk + 1, nxt);
         if (kk >= 0 && kk < g.nlev) {
-            const uint4 *row = reinterpret_cast<const uint4 *>(a3 + ((long)kk * g.P + p2) * 32);
             float s[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const uint4 u = row[v];
+                const uint4 u = cur[v];
                 const uint32_t wd[4] = {u.x, u.y, u.z, u.w};
 #pragma unroll
                 for (int h = 0; h < 4; ++h) {
@@ -766,6 +775,8 @@ __global__ __launch_bounds__(256) void k_net_out(NetGeo g, const uint16_t *__res
         r[2] = r[3];
         r[3] = r[4];
         r[4] = b4;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) cur[v] = nxt[v];
     }
 }
 
