@@ -423,6 +423,109 @@ __global__ __launch_bounds__(256) void k_conv3x3_rows(NetGeo g, const uint16_t *
     }
 }
 
+// The same layer for strips of 64 positions (nlon % 64 == 0): a wave holds four tiles of 16
+// consecutive positions, so a tile's first and last lanes take their west / east neighbours
+// from the adjacent tile of the same wave (a DPP rotation within the row of 16 lanes); only the
+// strip's two edge columns are loaded separately.  Each weight operand is read from LDS once per
+// level for the four tiles.  Taps are accumulated in the order of k_conv_fwd<2>.
+constexpr int kDppRowRor1 = 0x121;    // lane m receives lane (m - 1) mod 16
+constexpr int kDppRowRor15 = 0x12f;   // lane m receives lane (m + 1) mod 16
+
+__global__ __launch_bounds__(256) void k_conv3x3_strip(NetGeo g, const uint16_t *__restrict__ in,
+                                                       const uint16_t *__restrict__ wf,
+                                                       const float *__restrict__ bias, uint16_t *__restrict__ out,
+                                                       const Scalars *__restrict__ sc, int stop_mask, int tiles,
+                                                       int kchunk, long units, int per_xcd)
+{
+    constexpr int NT = 4;   // tiles of 16 positions per wave
+    if (stop_now(sc, stop_mask)) return;
+    const int lane = threadIdx.x & 63, m = lane & 15, grp = lane >> 4;
+    __shared__ uint4 wsh[18 * 64];
+    for (int e = threadIdx.x; e < 18 * 64; e += 256) {
+        const int tn = e / 64, l = e % 64;   // tn = 2 t + nt
+        wsh[e] = *reinterpret_cast<const uint4 *>(wf + (long)(tn / 2) * 1024 + (16 * (tn % 2) + (l & 15)) * 32 +
+                                                  8 * (l >> 4));
+    }
+    __syncthreads();
+    const long unit = col_unit(per_xcd);
+    if (unit >= units) return;
+    float bs[2][4];
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) bs[nt][jj] = bias[16 * nt + 4 * grp + jj];
+    const int strip = (int)(unit % tiles);   // `tiles` counts strips of 64 positions here
+    const int k0 = (int)(unit / tiles) * kchunk;
+    const int k1 = min(g.nlev, k0 + kchunk);
+    const int nlon = g.nlon;
+    const long t0 = (long)strip * 64;
+    const int j = (int)(t0 / nlon), i0 = (int)(t0 % nlon);
+    const int il = (i0 == 0) ? nlon - 1 : i0 - 1;          // west of the strip's first column
+    const int ir = (i0 + 64 == nlon) ? 0 : i0 + 64;        // east of its last
+    const bool rv[3] = {j > 0, true, j < g.nlat - 1};       // rows j - 1, j, j + 1 exist
+    int rb[3];                                              // first position of each row used
+#pragma unroll
+    for (int r = 0; r < 3; ++r) rb[r] = (rv[r] ? j + r - 1 : j) * nlon;   // a missing row reads row j, masked
+    // per level: own positions of the four tiles in three rows, then the strip's edges
+    auto load = [&](int k, bf16x8 *a) {
+        const uint16_t *base = in + (long)k * g.P * 32 + 8 * grp;
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+#pragma unroll
+            for (int s = 0; s < NT; ++s) a[r * NT + s] = ld8(base + ((long)rb[r] + i0 + 16 * s + m) * 32);
+            a[3 * NT + r] = ld8(base + ((long)rb[r] + il) * 32);
+            a[3 * NT + 3 + r] = ld8(base + ((long)rb[r] + ir) * 32);
+        }
+    };
+    constexpr int NL = 3 * NT + 6;
+    bf16x8 cur[NL], nxt[NL];
+    load(k0, cur);
+    for (int k = k0; k < k1; ++k) {
+        asm volatile("" ::: "memory");
+        load(min(k + 1, k1 - 1), nxt);   // the last level re-reads itself (in bounds, unused)
+        f32x4 acc[NT][2];
+#pragma unroll
+        for (int s = 0; s < NT; ++s) acc[s][0] = acc[s][1] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {   // di = c - 1
+                const int t = 3 * r + c;
+                const bf16x8 w0 = __builtin_bit_cast(bf16x8, wsh[(2 * t) * 64 + lane]);
+                const bf16x8 w1 = __builtin_bit_cast(bf16x8, wsh[(2 * t + 1) * 64 + lane]);
+#pragma unroll
+                for (int s = 0; s < NT; ++s) {
+                    bf16x8 v;
+                    if (c == 1) {
+                        v = cur[r * NT + s];
+                    } else if (c == 0) {
+                        const bf16x8 in_tile = dpp8<kDppRowShr1>(cur[r * NT + s]);
+                        const bf16x8 before = (s > 0) ? dpp8<kDppRowRor1>(cur[r * NT + (s > 0 ? s - 1 : 0)])
+                                                      : cur[3 * NT + r];
+                        v = (m == 0) ? before : in_tile;
+                    } else {
+                        const bf16x8 in_tile = dpp8<kDppRowShl1>(cur[r * NT + s]);
+                        const bf16x8 after = (s < NT - 1) ? dpp8<kDppRowRor15>(cur[r * NT + (s < NT - 1 ? s + 1 : 0)])
+                                                          : cur[3 * NT + 3 + r];
+                        v = (m == 15) ? after : in_tile;
+                    }
+                    v = keep8(v, rv[r]);
+                    acc[s][0] = mfma(w0, v, acc[s][0]);
+                    acc[s][1] = mfma(w1, v, acc[s][1]);
+                }
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < NT; ++s) {
+            uint16_t *dst = out + ((long)k * g.P + t0 + 16 * s + m) * 32 + 4 * grp;
+            store4(dst, acc[s][0], bs[0]);
+            store4(dst + 16, acc[s][1], bs[1]);
+        }
+#pragma unroll
+        for (int t = 0; t < NL; ++t) cur[t] = nxt[t];
+    }
+}
+
 // ------------------------------------------------------------------------------------------
 // conv layer, backward data:  din[p][ci] = [aprev[p][ci] > 0] sum_{t, co} W[t][co][ci] dout[nb(p, -t)][co]
 // (the transposed convolution, masked by the derivative of the ReLU that produced aprev)
@@ -982,7 +1085,11 @@ void launch_net_forward_layers(const NetGeo &g, const NetDev &d, const NetActs &
     const ColGrid c = col_grid(g, 16);
     hipLaunchKernelGGL((k_conv_fwd<1>), dim3(c.blocks), dim3(256), 0, s, g, act.x0, d.w1f, d.theta + kNetOffB1, act.a1,
                        sc, stop_mask, c.tiles, c.kchunk, c.units, c.per_xcd);
-    if (g.nlon % 16 == 0)
+    if (g.nlon % 64 == 0) {
+        const ColGrid c4 = col_grid(g, 64);
+        hipLaunchKernelGGL(k_conv3x3_strip, dim3(c4.blocks), dim3(256), 0, s, g, act.a1, d.w2f, d.theta + kNetOffB2,
+                           act.a2, sc, stop_mask, c4.tiles, c4.kchunk, c4.units, c4.per_xcd);
+    } else if (g.nlon % 16 == 0)
         hipLaunchKernelGGL(k_conv3x3_rows, dim3(c.blocks), dim3(256), 0, s, g, act.a1, d.w2f, d.theta + kNetOffB2,
                            act.a2, sc, stop_mask, c.tiles, c.kchunk, c.units, c.per_xcd);
     else

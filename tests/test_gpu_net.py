@@ -36,9 +36,11 @@ def _rel(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
-# 32x6x9 and 48x7x20 take the 3x3 kernel for rows of whole 16-position tiles (nlon % 16 == 0)
+# 32x6x9 and 48x7x20 take the 3x3 kernel for rows of whole 16-position tiles (nlon % 16 == 0),
+# 64x6x9 and 128x5x12 the one for strips of 64 positions (nlon % 64 == 0)
 @pytest.mark.parametrize("p", [synth.Problem(24, 12, 9, seed=2), synth.Problem(37, 9, 20, seed=3),
-                               synth.Problem(32, 6, 9, seed=4), synth.Problem(48, 7, 20, seed=5)],
+                               synth.Problem(32, 6, 9, seed=4), synth.Problem(48, 7, 20, seed=5),
+                               synth.Problem(64, 6, 9, seed=6), synth.Problem(128, 5, 12, seed=7)],
                          ids=lambda p: f"{p.nlon}x{p.nlat}x{p.nlev}")
 def test_forward_matches_oracle(eg, p):
     import torch
