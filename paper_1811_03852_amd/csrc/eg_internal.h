@@ -174,7 +174,7 @@ void launch_check_finite(long n, const double *v, int *bad, hipStream_t s);
 constexpr int kNetParams = 15233;
 constexpr int kNetOffW1 = 0, kNetOffB1 = 640, kNetOffW2 = 672, kNetOffB2 = 9888, kNetOffW3 = 9920,
               kNetOffB3 = 15040, kNetOffW4 = 15072, kNetOffB4 = 15232;
-constexpr int kNetPartRows = 512;   // rows of per-wave partial weight gradients
+constexpr int kNetPartRows = 768;   // rows of per-workgroup partial weight gradients (3 per CU)
 
 struct NetGeo {
     int nlon, nlat, nlev;

@@ -53,13 +53,24 @@ struct Pos {
     int i, j, k;
 };
 
+// (i, j, k) of position 0 <= p < n; 32-bit divisions when every position fits in 31 bits (a
+// test on a kernel argument, so the branch is uniform)
 __device__ __forceinline__ Pos decompose(const NetGeo &g, long p)
 {
     Pos r;
-    r.i = (int)(p % g.nlon);
-    const long q = p / g.nlon;
-    r.j = (int)(q % g.nlat);
-    r.k = (int)(q / g.nlat);
+    if (g.n <= 0x7fffffffL) {
+        const uint32_t u = static_cast<uint32_t>(p), nlon = static_cast<uint32_t>(g.nlon);
+        const uint32_t nlat = static_cast<uint32_t>(g.nlat);
+        const uint32_t q = u / nlon, k = q / nlat;
+        r.i = static_cast<int>(u - q * nlon);
+        r.j = static_cast<int>(q - k * nlat);
+        r.k = static_cast<int>(k);
+    } else {
+        r.i = (int)(p % g.nlon);
+        const long q = p / g.nlon;
+        r.j = (int)(q % g.nlat);
+        r.k = (int)(q / g.nlat);
+    }
     return r;
 }
 
@@ -549,11 +560,28 @@ __global__ __launch_bounds__(256) void k_conv_bwd(NetGeo g, const uint16_t *__re
         const bool pv = p < g.n;
         const long pc = pv ? p : g.n - 1;
         const Pos x = decompose(g, pc);
-        f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+        // every load is issued before the first multiply (unconditional, at a valid address;
+        // a neighbour outside the grid is zeroed afterwards)
+        bf16x8 av[T];
+        bool ok[T];
 #pragma unroll
         for (int t = 0; t < T; ++t) {
             const long q = LayerGeo<L>::nb(g, pc, x, t, true);
-            const bf16x8 a = (pv && q >= 0) ? ld8(dout + q * 32 + 8 * grp) : zero8();
+            ok[t] = pv && q >= 0;
+            av[t] = ld8(dout + (q >= 0 ? q : pc) * 32 + 8 * grp);
+        }
+        uint16_t mk0[4], mk1[4];
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) {
+            const long q = tile * 16 + 4 * grp + jj;
+            const long qc = q < g.n ? q : g.n - 1;
+            mk0[jj] = aprev[qc * 32 + m];
+            mk1[jj] = aprev[qc * 32 + 16 + m];
+        }
+        f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int t = 0; t < T; ++t) {
+            const bf16x8 a = keep8(av[t], ok[t]);
             acc0 = mfma(a, wb[t][0], acc0);
             acc1 = mfma(a, wb[t][1], acc1);
         }
@@ -561,8 +589,8 @@ __global__ __launch_bounds__(256) void k_conv_bwd(NetGeo g, const uint16_t *__re
         for (int jj = 0; jj < 4; ++jj) {
             const long q = tile * 16 + 4 * grp + jj;
             if (q < g.n) {
-                const float m0 = bf2f(aprev[q * 32 + m]) > 0.f ? 1.f : 0.f;
-                const float m1 = bf2f(aprev[q * 32 + 16 + m]) > 0.f ? 1.f : 0.f;
+                const float m0 = bf2f(mk0[jj]) > 0.f ? 1.f : 0.f;
+                const float m1 = bf2f(mk1[jj]) > 0.f ? 1.f : 0.f;
                 din[q * 32 + m] = f2bf(acc0[jj] * m0);
                 din[q * 32 + 16 + m] = f2bf(acc1[jj] * m1);
             }
@@ -574,12 +602,47 @@ __global__ __launch_bounds__(256) void k_conv_bwd(NetGeo g, const uint16_t *__re
 // ------------------------------------------------------------------------------------------
 // Weight gradient of the 32 -> 32 layers through LDS (layers 2 and 3):
 //   dW[t][co][ci] = sum_p dout[p][co] in[nb(p, t)][ci],   db[co] = sum_p dout[p][co]
-// One workgroup (one partial row) walks chunks of 32 consecutive positions.  The chunk's dout
-// tile and, per tap, the neighbours' input tile are loaded with 32-byte vector loads and
-// written to LDS transposed ([channel][position]), so each MFMA operand (8 consecutive
-// positions of one channel) is a single 16-byte LDS read; K = 32 positions per MFMA.  Wave w
-// owns taps w, w + 4, w + 8 (its accumulators: 16 floats per tap).
+// One workgroup (one partial row) walks chunks of 32 consecutive positions.  A chunk needs
+// T + 1 tiles of 32 positions x 32 channels: dout, and the input at each tap's neighbours.
+// Wave w loads tiles w, w + 4, w + 8 with 16-byte loads, a lane taking 8 channels of two
+// adjacent positions, and writes them to LDS transposed ([channel][position]) as packed
+// position pairs, so each MFMA operand (8 consecutive positions of one channel) is a single
+// 16-byte LDS read; K = 32 positions per MFMA.  Wave w multiplies taps w, w + 4, w + 8 (its
+// accumulators: 16 floats per tap).  Two chunks are in flight in registers: the loads of
+// chunk c + 2 (in grid-stride steps) are issued before the multiplications of chunk c, so
+// their latency is hidden behind two chunks of work, and each chunk costs two barriers.
 // ------------------------------------------------------------------------------------------
+template <int NTPW> struct DwBuf {
+    uint4 v[NTPW][2];   // [tile of this wave][even, odd position]
+    bool ok[NTPW][2];   // false: the value is outside the grid and counts as zero
+};
+
+// wave wv's tiles of chunk ch.  The loads are unconditional (an address outside the grid is
+// replaced by the position itself and flagged), so the compiler can count them and a put
+// waits only for its own chunk.
+template <int L, int NTPW>
+__device__ __forceinline__ DwBuf<NTPW> dw_fetch(const NetGeo g, const uint16_t *dout, const uint16_t *in, long ch,
+                                                int wv, int pp, int cq)
+{
+    constexpr int NT = LayerGeo<L>::T + 1;
+    DwBuf<NTPW> r;
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+        const long p = ch * 32 + 2 * pp + e;
+        const bool pv = p < g.n;
+        const long pc = pv ? p : g.n - 1;
+        const Pos x = decompose(g, pc);
+#pragma unroll
+        for (int a = 0; a < NTPW; ++a) {
+            const int tile = wv + 4 * a < NT ? wv + 4 * a : 0;
+            const long q = (tile == 0) ? pc : LayerGeo<L>::nb(g, pc, x, tile - 1, false);
+            r.ok[a][e] = pv && q >= 0;
+            r.v[a][e] = *reinterpret_cast<const uint4 *>(((tile == 0) ? dout : in) + (q >= 0 ? q : pc) * 32 + 8 * cq);
+        }
+    }
+    return r;
+}
+
 template <int L>
 __global__ __launch_bounds__(256) void k_conv_dw_lds(NetGeo g, const uint16_t *__restrict__ dout,
                                                      const uint16_t *__restrict__ in, float *__restrict__ part,
@@ -587,12 +650,14 @@ __global__ __launch_bounds__(256) void k_conv_dw_lds(NetGeo g, const uint16_t *_
 {
     static_assert(L == 2 || L == 3, "32 -> 32 layers only");
     constexpr int T = LayerGeo<L>::T;
-    constexpr int TW = (T + 3) / 4;   // taps per wave
-    constexpr int PITCH = 40;         // bf16 per LDS row (80 bytes: 16-byte aligned rows)
-    __shared__ __align__(16) uint16_t dT[32 * PITCH];
-    __shared__ __align__(16) uint16_t iT[4][32 * PITCH];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, m = lane & 15, grp = lane >> 4;
-    const int lp = lane >> 1, lh = lane & 1;   // loader lane: position lp, channels 16 lh .. 16 lh + 15
+    constexpr int NT = T + 1;           // tile 0: dout; tile 1 + t: input at tap t
+    constexpr int TPW = (NT + 3) / 4;   // tiles loaded per wave
+    constexpr int TW = (T + 3) / 4;     // taps multiplied per wave
+    constexpr int PITCH = 40;           // bf16 per LDS row (80 bytes: 16-byte aligned rows)
+    __shared__ __align__(16) uint16_t tl[NT][32 * PITCH];
+    const int lane = threadIdx.x & 63, m = lane & 15, grp = lane >> 4;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
+    const int pp = lane >> 2, cq = lane & 3;   // loader lane: positions 2 pp, 2 pp + 1; channels 8 cq .. 8 cq + 7
     f32x4 acc[TW][2][2];
 #pragma unroll
     for (int a = 0; a < TW; ++a)
@@ -600,106 +665,122 @@ __global__ __launch_bounds__(256) void k_conv_dw_lds(NetGeo g, const uint16_t *_
         for (int b = 0; b < 2; ++b)
 #pragma unroll
             for (int c = 0; c < 2; ++c) acc[a][b][c] = f32x4{0.f, 0.f, 0.f, 0.f};
-    float bsum[16];
+    float bsum[8];
 #pragma unroll
-    for (int c = 0; c < 16; ++c) bsum[c] = 0.f;
-    // write 16 channels of one position into a transposed tile
-    auto put = [&](uint16_t *tile, uint4 u0, uint4 u1) {
-        const uint32_t w[8] = {u0.x, u0.y, u0.z, u0.w, u1.x, u1.y, u1.z, u1.w};
+    for (int c = 0; c < 8; ++c) bsum[c] = 0.f;
+    const long nchunks = (g.n + 31) / 32;
+    const long G = gridDim.x;
+
+    auto fetch = [&](long ch) { return dw_fetch<L, TPW>(g, dout, in, ch, wv, pp, cq); };
+    // channel c = 8 cq + h of the two positions as one dword: (even | odd << 16)
+    auto put = [&](const DwBuf<TPW> &r) {
 #pragma unroll
-        for (int h = 0; h < 8; ++h) {
-            tile[(16 * lh + 2 * h) * PITCH + lp] = static_cast<uint16_t>(w[h] & 0xffffu);
-            tile[(16 * lh + 2 * h + 1) * PITCH + lp] = static_cast<uint16_t>(w[h] >> 16);
+        for (int a = 0; a < TPW; ++a) {
+            const int tile = wv + 4 * a;
+            if (tile >= NT) break;
+            const uint32_t ke = r.ok[a][0] ? 0xffffffffu : 0u, ko = r.ok[a][1] ? 0xffffffffu : 0u;
+            const uint32_t ev[4] = {r.v[a][0].x & ke, r.v[a][0].y & ke, r.v[a][0].z & ke, r.v[a][0].w & ke};
+            const uint32_t od[4] = {r.v[a][1].x & ko, r.v[a][1].y & ko, r.v[a][1].z & ko, r.v[a][1].w & ko};
+            uint32_t *dst = reinterpret_cast<uint32_t *>(tl[tile]);
+#pragma unroll
+            for (int h = 0; h < 4; ++h) {
+                dst[((8 * cq + 2 * h) * PITCH + 2 * pp) / 2] = (ev[h] & 0xffffu) | (od[h] << 16);
+                dst[((8 * cq + 2 * h + 1) * PITCH + 2 * pp) / 2] = (ev[h] >> 16) | (od[h] & 0xffff0000u);
+            }
+            if (tile == 0) {
+#pragma unroll
+                for (int h = 0; h < 4; ++h) {
+                    bsum[2 * h] += bf2f(static_cast<uint16_t>(ev[h] & 0xffffu)) + bf2f(static_cast<uint16_t>(od[h] & 0xffffu));
+                    bsum[2 * h + 1] += bf2f(static_cast<uint16_t>(ev[h] >> 16)) + bf2f(static_cast<uint16_t>(od[h] >> 16));
+                }
+            }
         }
     };
-    const long nchunks = (g.n + 31) / 32;
-    for (long ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
-        const long p = ch * 32 + lp;
-        const bool pv = p < g.n;
-        const long pc = pv ? p : g.n - 1;
-        __syncthreads();   // the previous chunk's tiles are no longer read
-        if (wv == 0) {
-            uint4 u0 = make_uint4(0, 0, 0, 0), u1 = u0;
-            if (pv) {
-                const uint4 *src = reinterpret_cast<const uint4 *>(dout + pc * 32 + 16 * lh);
-                u0 = src[0];
-                u1 = src[1];
-            }
-            const uint32_t w[8] = {u0.x, u0.y, u0.z, u0.w, u1.x, u1.y, u1.z, u1.w};
+    auto multiply = [&]() {
+        bf16x8 A[2];
 #pragma unroll
-            for (int h = 0; h < 8; ++h) {
-                bsum[2 * h] += bf2f(static_cast<uint16_t>(w[h] & 0xffffu));
-                bsum[2 * h + 1] += bf2f(static_cast<uint16_t>(w[h] >> 16));
-            }
-            put(dT, u0, u1);
-        }
-        __syncthreads();
-        const Pos x = decompose(g, pc);
-        // every wave runs TW rounds (a wave with fewer taps idles in its last round) so that
-        // all of them meet the workgroup barriers
+        for (int mt = 0; mt < 2; ++mt)
+            A[mt] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(tl[0] + (16 * mt + m) * PITCH + 8 * grp));
 #pragma unroll
         for (int a = 0; a < TW; ++a) {
             const int t = wv + 4 * a;
-            const bool tv = t < T;
-            const long q = tv ? LayerGeo<L>::nb(g, pc, x, t, false) : -1;
-            uint4 u0 = make_uint4(0, 0, 0, 0), u1 = u0;
-            if (pv && q >= 0) {
-                const uint4 *src = reinterpret_cast<const uint4 *>(in + q * 32 + 16 * lh);
-                u0 = src[0];
-                u1 = src[1];
-            }
-            if (a > 0) __syncthreads();   // the previous round's tile has been read
-            put(iT[wv], u0, u1);
-            __syncthreads();
-            if (!tv) continue;
-            bf16x8 A[2], B[2];
-#pragma unroll
-            for (int mt = 0; mt < 2; ++mt)
-                A[mt] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(dT + (16 * mt + m) * PITCH + 8 * grp));
+            if (t >= T) break;
+            bf16x8 B[2];
 #pragma unroll
             for (int nt = 0; nt < 2; ++nt)
                 B[nt] = __builtin_bit_cast(bf16x8,
-                                           *reinterpret_cast<const uint4 *>(iT[wv] + (16 * nt + m) * PITCH + 8 * grp));
+                                           *reinterpret_cast<const uint4 *>(tl[1 + t] + (16 * nt + m) * PITCH + 8 * grp));
 #pragma unroll
             for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
                 for (int nt = 0; nt < 2; ++nt) acc[a][mt][nt] = mfma(A[mt], B[nt], acc[a][mt][nt]);
         }
+    };
+
+    // chunks ch (from b0) and ch + G (from b1) per trip; every wave meets every barrier.  A
+    // fetch past the last chunk re-reads the last one (valid addresses, never used; operator
+    // grids have n >= 3, so there is a last chunk).
+    const long last = nchunks - 1;
+    long ch = blockIdx.x;
+    DwBuf<TPW> b0 = fetch(ch < last ? ch : last);
+    DwBuf<TPW> b1 = fetch(ch + G < last ? ch + G : last);
+    for (; ch < nchunks; ch += 2 * G) {
+        __syncthreads();   // the previous chunk's tiles are no longer read
+        put(b0);
+        b0 = fetch(ch + 2 * G < last ? ch + 2 * G : last);
+        __syncthreads();
+        multiply();
+        if (ch + G >= nchunks) break;
+        __syncthreads();
+        put(b1);
+        b1 = fetch(ch + 3 * G < last ? ch + 3 * G : last);
+        __syncthreads();
+        multiply();
     }
+
     float *dst = part + (long)blockIdx.x * kNetParams;
     const int off = (L == 2) ? kNetOffW2 : kNetOffW3;
-    // result lane l: co = 16 mt + 4 grp + jj, ci = 16 nt + m
+    // result lane l: co = 16 mt + 4 grp + jj, ci = 16 nt + m.  The previous values are read
+    // unconditionally (all of them before the first add) and used only when adding.
 #pragma unroll
     for (int a = 0; a < TW; ++a) {
         const int t = wv + 4 * a;
         if (t >= T) break;
+        float prev[2][2][4];
 #pragma unroll
         for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
             for (int nt = 0; nt < 2; ++nt)
 #pragma unroll
-                for (int jj = 0; jj < 4; ++jj) {
-                    float &o = dst[off + t * 1024 + (16 * mt + 4 * grp + jj) * 32 + 16 * nt + m];
-                    o = add ? o + acc[a][mt][nt][jj] : acc[a][mt][nt][jj];
-                }
+                for (int jj = 0; jj < 4; ++jj)
+                    prev[mt][nt][jj] = dst[off + t * 1024 + (16 * mt + 4 * grp + jj) * 32 + 16 * nt + m];
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+            for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+                for (int jj = 0; jj < 4; ++jj)
+                    dst[off + t * 1024 + (16 * mt + 4 * grp + jj) * 32 + 16 * nt + m] =
+                        add ? prev[mt][nt][jj] + acc[a][mt][nt][jj] : acc[a][mt][nt][jj];
     }
     if (wv == 0) {
-        // bias: lanes with the same lh hold the same channels for different positions
+        // bias: lanes with the same cq hold the same channels for different positions
 #pragma unroll
-        for (int c = 0; c < 16; ++c) {
+        for (int c = 0; c < 8; ++c) {
             float v = bsum[c];
-            v += __shfl_xor(v, 2);
             v += __shfl_xor(v, 4);
             v += __shfl_xor(v, 8);
             v += __shfl_xor(v, 16);
             v += __shfl_xor(v, 32);
-            if (lane < 2 && lane == lh) {
-                float &o = dst[((L == 2) ? kNetOffB2 : kNetOffB3) + 16 * lh + c];
+            if (lane < 4) {
+                float &o = dst[((L == 2) ? kNetOffB2 : kNetOffB3) + 8 * cq + c];
                 o = add ? o + v : v;
             }
         }
     }
 }
+
+constexpr int kLevelBatch = 8;   // levels whose loads a column march issues together
 
 // ------------------------------------------------------------------------------------------
 // Weight gradients of the two layers with few weights, as column marches on the vector ALU.
@@ -720,23 +801,43 @@ __global__ __launch_bounds__(256) void k_net_out_dw_col(NetGeo g, const float *_
     const long nst = (long)gridDim.x * 8;
     float acc[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
     float bacc = 0.f;
-    auto dr = [&](long col, int k) -> float { return (k >= 0 && k < g.nlev) ? rho * u[col + (long)k * g.P] : 0.f; };
+    // loads at a clamped level, zeroed outside the column afterwards (no branch around a load)
+    auto dr = [&](long col, int k) -> float {
+        const int kc = k < 0 ? 0 : (k < g.nlev ? k : g.nlev - 1);
+        const float v = rho * u[col + (long)kc * g.P];
+        return (k >= 0 && k < g.nlev) ? v : 0.f;
+    };
     for (long col = (long)blockIdx.x * 8 + st; col < g.P; col += nst) {
         // d[t] = drho at level kk + 2 - t
         float d0 = dr(col, 2), d1 = dr(col, 1), d2 = dr(col, 0), d3 = 0.f, d4 = 0.f;
-        for (int kk = 0; kk < g.nlev; ++kk) {
-            const float a = bf2f(a3[(col + (long)kk * g.P) * 32 + c]);
-            acc[0] += d0 * a;
-            acc[1] += d1 * a;
-            acc[2] += d2 * a;
-            acc[3] += d3 * a;
-            acc[4] += d4 * a;
-            bacc += d2;
-            d4 = d3;
-            d3 = d2;
-            d2 = d1;
-            d1 = d0;
-            d0 = dr(col, kk + 3);
+        // levels in batches, each batch's loads issued together; past the top the
+        // activation and drho are zero, so the extra steps add exact zeros
+        for (int k0 = 0; k0 < g.nlev; k0 += kLevelBatch) {
+            uint16_t araw[kLevelBatch];
+            float uraw[kLevelBatch];
+#pragma unroll
+            for (int j = 0; j < kLevelBatch; ++j) {   // raw loads only: scaling and masking come at use
+                const int kk = k0 + j;
+                const int kc = kk < g.nlev ? kk : g.nlev - 1;
+                const int ku = kk + 3 < g.nlev ? kk + 3 : g.nlev - 1;
+                araw[j] = a3[(col + (long)kc * g.P) * 32 + c];
+                uraw[j] = u[col + (long)ku * g.P];
+            }
+#pragma unroll
+            for (int j = 0; j < kLevelBatch; ++j) {
+                const float a = (k0 + j < g.nlev) ? bf2f(araw[j]) : 0.f;
+                acc[0] += d0 * a;
+                acc[1] += d1 * a;
+                acc[2] += d2 * a;
+                acc[3] += d3 * a;
+                acc[4] += d4 * a;
+                bacc += d2;
+                d4 = d3;
+                d3 = d2;
+                d2 = d1;
+                d1 = d0;
+                d0 = (k0 + j + 3 < g.nlev) ? rho * uraw[j] : 0.f;
+            }
         }
     }
     __shared__ float red[8][161];
@@ -765,8 +866,12 @@ __global__ __launch_bounds__(256) void k_conv_dw1_col(NetGeo g, const uint16_t *
 #pragma unroll
         for (int ci = 0; ci < 4; ++ci) acc[t][ci] = 0.f;
     float bacc = 0.f;
+    // loads at a clamped level, zeroed outside the column afterwards (no branch around a load)
     auto xin = [&](long col, int k) -> uint2 {
-        return (k >= 0 && k < g.nlev) ? reinterpret_cast<const uint2 *>(x0)[col + (long)k * g.P] : make_uint2(0, 0);
+        const int kc = k < 0 ? 0 : (k < g.nlev ? k : g.nlev - 1);
+        const uint2 v = reinterpret_cast<const uint2 *>(x0)[col + (long)kc * g.P];
+        const bool in = k >= 0 && k < g.nlev;
+        return make_uint2(in ? v.x : 0u, in ? v.y : 0u);
     };
     auto ch = [](uint2 v, int ci) -> float {
         const uint32_t w = (ci < 2) ? v.x : v.y;
@@ -775,22 +880,38 @@ __global__ __launch_bounds__(256) void k_conv_dw1_col(NetGeo g, const uint16_t *
     for (long col = (long)blockIdx.x * 8 + st; col < g.P; col += nst) {
         // w[t] = x0 at level k + t - 2
         uint2 w0 = xin(col, -2), w1 = xin(col, -1), w2 = xin(col, 0), w3 = xin(col, 1), w4 = xin(col, 2);
-        for (int k = 0; k < g.nlev; ++k) {
-            const float dv = bf2f(dout[(col + (long)k * g.P) * 32 + co]);
-            bacc += dv;
+        // levels in batches, each batch's loads issued together; past the top dout and x0
+        // are zero, so the extra steps add exact zeros
+        for (int k0 = 0; k0 < g.nlev; k0 += kLevelBatch) {
+            uint16_t draw[kLevelBatch];
+            uint2 nx[kLevelBatch];
 #pragma unroll
-            for (int ci = 0; ci < 4; ++ci) {
-                acc[0][ci] += dv * ch(w0, ci);
-                acc[1][ci] += dv * ch(w1, ci);
-                acc[2][ci] += dv * ch(w2, ci);
-                acc[3][ci] += dv * ch(w3, ci);
-                acc[4][ci] += dv * ch(w4, ci);
+            for (int j = 0; j < kLevelBatch; ++j) {   // raw loads only: masking comes at use
+                const int k = k0 + j;
+                const int kc = k < g.nlev ? k : g.nlev - 1;
+                const int kx = k + 3 < g.nlev ? k + 3 : g.nlev - 1;
+                draw[j] = dout[(col + (long)kc * g.P) * 32 + co];
+                nx[j] = reinterpret_cast<const uint2 *>(x0)[col + (long)kx * g.P];
             }
-            w0 = w1;
-            w1 = w2;
-            w2 = w3;
-            w3 = w4;
-            w4 = xin(col, k + 3);
+#pragma unroll
+            for (int j = 0; j < kLevelBatch; ++j) {
+                const float dv = (k0 + j < g.nlev) ? bf2f(draw[j]) : 0.f;
+                bacc += dv;
+#pragma unroll
+                for (int ci = 0; ci < 4; ++ci) {
+                    acc[0][ci] += dv * ch(w0, ci);
+                    acc[1][ci] += dv * ch(w1, ci);
+                    acc[2][ci] += dv * ch(w2, ci);
+                    acc[3][ci] += dv * ch(w3, ci);
+                    acc[4][ci] += dv * ch(w4, ci);
+                }
+                w0 = w1;
+                w1 = w2;
+                w2 = w3;
+                w3 = w4;
+                const bool top = k0 + j + 3 < g.nlev;
+                w4 = make_uint2(top ? nx[j].x : 0u, top ? nx[j].y : 0u);
+            }
         }
     }
     __shared__ float red[8][5 * 128 + 32];
@@ -951,27 +1072,55 @@ __global__ __launch_bounds__(256) void k_net_diff(long n, const float *__restric
 // z = T^{-T} y per column from the LU factors (l, inv, c) of T = L U:
 //   U^T u = y :  ~u_k = y_k + c_{k-1} ~u_{k-1},  u_k = inv_k ~u_k
 //   L^T z = u :  z_k = u_k + l_{k+1} z_{k+1}
+// One lane per column.  The columns are few next to the lanes of the chip (one per horizontal
+// point), so the level walks load eight levels at a time (at clamped levels, all issued
+// before the first use) to keep more loads in flight than the recurrence alone would.
 // ------------------------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_thomas_t(TriView<float> tv, const float *__restrict__ y,
                                                   float *__restrict__ z)
 {
+    constexpr int B = 8;
     const long col = (long)blockIdx.x * 256 + threadIdx.x;
     if (col >= tv.P) return;
     const long P = tv.P, n = tv.n;
+    const int nlev = tv.nlev;
     const float *lf = tv.f, *invf = tv.f + n, *cf = tv.f + 2 * n;
     float ut = 0.f, cprev = 0.f;
-    for (int k = 0; k < tv.nlev; ++k) {
-        const long c = col + (long)k * P;
-        ut = y[c] + cprev * ut;
-        z[c] = invf[c] * ut;
-        cprev = cf[c];
+    for (int k0 = 0; k0 < nlev; k0 += B) {
+        float yv[B], iv[B], cv[B];
+#pragma unroll
+        for (int j = 0; j < B; ++j) {
+            const long c = col + (long)(k0 + j < nlev ? k0 + j : nlev - 1) * P;
+            yv[j] = y[c];
+            iv[j] = invf[c];
+            cv[j] = cf[c];
+        }
+#pragma unroll
+        for (int j = 0; j < B; ++j) {
+            if (k0 + j < nlev) {
+                ut = yv[j] + cprev * ut;
+                z[col + (long)(k0 + j) * P] = iv[j] * ut;
+                cprev = cv[j];
+            }
+        }
     }
     float zz = 0.f, lnext = 0.f;
-    for (int k = tv.nlev - 1; k >= 0; --k) {
-        const long c = col + (long)k * P;
-        zz = z[c] + lnext * zz;
-        z[c] = zz;
-        lnext = lf[c];
+    for (int k1 = nlev - 1; k1 >= 0; k1 -= B) {
+        float zv[B], lv[B];
+#pragma unroll
+        for (int j = 0; j < B; ++j) {
+            const long c = col + (long)(k1 - j >= 0 ? k1 - j : 0) * P;
+            zv[j] = z[c];
+            lv[j] = lf[c];
+        }
+#pragma unroll
+        for (int j = 0; j < B; ++j) {
+            if (k1 - j >= 0) {
+                zz = zv[j] + lnext * zz;
+                z[col + (long)(k1 - j) * P] = zz;
+                lnext = lv[j];
+            }
+        }
     }
 }
 

@@ -60,9 +60,13 @@ def test_forward_matches_oracle(eg, p):
     net.close()
 
 
+# the second shape gives every gradient workgroup two or three chunks of 32 positions (the
+# chunk pipeline's both halves and its early exit), a ragged last chunk and a ragged last batch
+# of levels in the column kernels
+@pytest.mark.parametrize("shape", [(24, 12, 9), (47, 31, 30)], ids=lambda s: "x".join(map(str, s)))
 @pytest.mark.parametrize("kind", [onet.LOSS_ERROR, onet.LOSS_RESIDUAL])
-def test_gradients_match_oracle(eg, kind):
-    p = synth.Problem(24, 12, 9, seed=6)
+def test_gradients_match_oracle(eg, kind, shape):
+    p = synth.Problem(*shape, seed=6)
     coef = synth.make_coeffs(p)
     th = _theta(7)
     net = eg.Net(0)
