@@ -548,11 +548,15 @@ __global__ __launch_bounds__(256) void k_conv_bwd(NetGeo g, const uint16_t *__re
 {
     constexpr int T = LayerGeo<L>::T;
     const int lane = threadIdx.x & 63, m = lane & 15, grp = lane >> 4;
-    bf16x8 wb[T][2];
-#pragma unroll
-    for (int t = 0; t < T; ++t)
-#pragma unroll
-        for (int nt = 0; nt < 2; ++nt) wb[t][nt] = ld8(wt + (long)t * 1024 + (16 * nt + m) * 32 + 8 * grp);
+    // the weights in MFMA operand order, one 16-byte slot per (tap, output half, lane): held in
+    // LDS rather than registers, so more waves fit on a SIMD to hide the loads' latency
+    __shared__ uint4 wsh[T * 2 * 64];
+    __shared__ __align__(16) uint16_t otile[4][16 * 32];   // per wave: 16 positions x 32 channels
+    for (int e = threadIdx.x; e < T * 2 * 64; e += 256) {
+        const int t = e >> 7, nt = (e >> 6) & 1, l = e & 63;
+        wsh[e] = *reinterpret_cast<const uint4 *>(wt + (long)t * 1024 + (16 * nt + (l & 15)) * 32 + 8 * (l >> 4));
+    }
+    __syncthreads();
     const long ntiles = (g.n + 15) / 16;
     const long nw = (long)gridDim.x * 4;
     for (long tile = (long)blockIdx.x * 4 + (threadIdx.x >> 6); tile < ntiles; tile += nw) {
@@ -570,31 +574,43 @@ __global__ __launch_bounds__(256) void k_conv_bwd(NetGeo g, const uint16_t *__re
             ok[t] = pv && q >= 0;
             av[t] = ld8(dout + (q >= 0 ? q : pc) * 32 + 8 * grp);
         }
-        uint16_t mk0[4], mk1[4];
-#pragma unroll
-        for (int jj = 0; jj < 4; ++jj) {
-            const long q = tile * 16 + 4 * grp + jj;
-            const long qc = q < g.n ? q : g.n - 1;
-            mk0[jj] = aprev[qc * 32 + m];
-            mk1[jj] = aprev[qc * 32 + 16 + m];
-        }
+        // the tile's result is turned around through LDS so that lane l stores channels
+        // 8 (l % 4) .. 8 (l % 4) + 7 of position l / 4 with one 16-byte store; its 8 mask values
+        // come with one 16-byte load, issued here with the others
+        const long qo = tile * 16 + (lane >> 2);
+        const int co = 8 * (lane & 3);
+        const uint4 mk = *reinterpret_cast<const uint4 *>(aprev + (qo < g.n ? qo : g.n - 1) * 32 + co);
         f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+        // an opaque copy of the lane index keeps the compiler from hoisting the weight reads
+        // out of the loop (which would bring the registers back)
+        int wl = lane;
+        asm volatile("" : "+v"(wl));
 #pragma unroll
         for (int t = 0; t < T; ++t) {
             const bf16x8 a = keep8(av[t], ok[t]);
-            acc0 = mfma(a, wb[t][0], acc0);
-            acc1 = mfma(a, wb[t][1], acc1);
+            acc0 = mfma(a, __builtin_bit_cast(bf16x8, wsh[(2 * t) * 64 + wl]), acc0);
+            acc1 = mfma(a, __builtin_bit_cast(bf16x8, wsh[(2 * t + 1) * 64 + wl]), acc1);
         }
+        // result lane l: channel m (acc0) and 16 + m (acc1) of positions 4 grp + jj.  The tile
+        // is wave-private and LDS serves one wave's accesses in order, so no barrier is needed.
+        uint16_t *ot = otile[threadIdx.x >> 6];
 #pragma unroll
         for (int jj = 0; jj < 4; ++jj) {
-            const long q = tile * 16 + 4 * grp + jj;
-            if (q < g.n) {
-                const float m0 = bf2f(mk0[jj]) > 0.f ? 1.f : 0.f;
-                const float m1 = bf2f(mk1[jj]) > 0.f ? 1.f : 0.f;
-                din[q * 32 + m] = f2bf(acc0[jj] * m0);
-                din[q * 32 + 16 + m] = f2bf(acc1[jj] * m1);
-            }
+            ot[(4 * grp + jj) * 32 + m] = f2bf(acc0[jj]);
+            ot[(4 * grp + jj) * 32 + 16 + m] = f2bf(acc1[jj]);
         }
+        const uint4 r = *reinterpret_cast<const uint4 *>(ot + (lane >> 2) * 32 + co);
+        const uint32_t rv[4] = {r.x, r.y, r.z, r.w}, mv[4] = {mk.x, mk.y, mk.z, mk.w};
+        uint32_t ov[4];
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+            // f2bf(v * [aprev > 0]): the same bits as masking the FP32 result (a zero keeps v's sign)
+            const float lo = bf2f(static_cast<uint16_t>(rv[h] & 0xffffu)), hi = bf2f(static_cast<uint16_t>(rv[h] >> 16));
+            const float mlo = bf2f(static_cast<uint16_t>(mv[h] & 0xffffu)) > 0.f ? 1.f : 0.f;
+            const float mhi = bf2f(static_cast<uint16_t>(mv[h] >> 16)) > 0.f ? 1.f : 0.f;
+            ov[h] = static_cast<uint32_t>(f2bf(lo * mlo)) | (static_cast<uint32_t>(f2bf(hi * mhi)) << 16);
+        }
+        if (qo < g.n) *reinterpret_cast<uint4 *>(din + qo * 32 + co) = make_uint4(ov[0], ov[1], ov[2], ov[3]);
     }
 }
 
