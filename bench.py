@@ -105,6 +105,18 @@ def copy_rate(torch, n: int) -> float:
     return round(2 * 8 * n / (times[2] * 1e-3) / 1e9, 1)
 
 
+def _cpu_model() -> str:
+    """The host CPU's model name (from /proc/cpuinfo), for the record beside the CPU timing."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(n_target: int, iterations: int, sample_iters: int = 20):
     """Single-thread oracle BiCGStab on a 640x480x70 grid of the same recipe for a fixed number
     of iterations; scaled per point and iteration to the benchmark grid."""
@@ -128,6 +140,8 @@ def cpu_baseline(n_target: int, iterations: int, sample_iters: int = 20):
         "unit": "s",
         "cores": 1,
         "kind": "oracle",
+        "cpu_model": _cpu_model(),
+        "host_threads": os.cpu_count(),
         "sample": (f"oracle FP64 BiCGStab + T^-1, {sample_iters} iterations (difference of a {1 + sample_iters}- and a 1-iteration "
                    f"run) on the 640x480x70 grid of the same recipe ({dt:.1f} s, 1 thread); scaled by grid size to {n_target} points and by this run's FP64 "
                    f"iteration count ({iterations}); extrapolated, not a full CPU solve"),
