@@ -1032,12 +1032,19 @@ __global__ __launch_bounds__(256) void k_net_out_bwd(NetGeo g, const float *__re
     const long stride = (long)gridDim.x * 256;
     for (long p = (long)blockIdx.x * 256 + threadIdx.x; p < g.n; p += stride) {
         const Pos x = decompose(g, p);
-        float dd[5];
+        // the five loads at valid addresses first (a level outside the column reads p and is
+        // zeroed afterwards), so they are in flight together
+        float ur[5];
+        bool in[5];
 #pragma unroll
         for (int t = 0; t < 5; ++t) {
             const long nb = nb_v(g, p, x, -(t - 2));
-            dd[t] = nb < 0 ? 0.f : rho * u[nb];
+            in[t] = nb >= 0;
+            ur[t] = u[nb >= 0 ? nb : p];
         }
+        float dd[5];
+#pragma unroll
+        for (int t = 0; t < 5; ++t) dd[t] = in[t] ? rho * ur[t] : 0.f;
         const uint4 *row = reinterpret_cast<const uint4 *>(a3 + p * 32);
         uint4 *orow = reinterpret_cast<uint4 *>(dh3 + p * 32);
 #pragma unroll
@@ -1158,13 +1165,20 @@ __global__ __launch_bounds__(256) void k_spmv_t(NetGeo g, const float *__restric
         float diag = mg[c];
 #pragma unroll
         for (int d = 0; d < 6; ++d) diag += a[d * n + c];
+        // the four conditional neighbours load at a valid index (c itself when absent) and are
+        // zeroed afterwards, so no load waits behind a branch
+        const bool hn = p.j < g.nlat - 1, hs = p.j > 0, hu = p.k < g.nlev - 1, hd = p.k > 0;
+        const long cn = hn ? c + g.nlon : c, cs = hs ? c - g.nlon : c;
+        const long cu = hu ? c + g.P : c, cd = hd ? c - g.P : c;
+        const float tn = a[2 * n + cn] * x[cn], ts = a[3 * n + cs] * x[cs];
+        const float tu = a[4 * n + cu] * x[cu], td = a[5 * n + cd] * x[cd];
         float s = diag * x[c];
         s -= a[ce] * x[ce];              // row c+1 couples to c through its W coupling
         s -= a[n + cw] * x[cw];          // row c-1 through its E coupling
-        if (p.j < g.nlat - 1) s -= a[2 * n + c + g.nlon] * x[c + g.nlon];
-        if (p.j > 0) s -= a[3 * n + c - g.nlon] * x[c - g.nlon];
-        if (p.k < g.nlev - 1) s -= a[4 * n + c + g.P] * x[c + g.P];
-        if (p.k > 0) s -= a[5 * n + c - g.P] * x[c - g.P];
+        if (hn) s -= tn;
+        if (hs) s -= ts;
+        if (hu) s -= tu;
+        if (hd) s -= td;
         y[c] = s;
     }
 }
