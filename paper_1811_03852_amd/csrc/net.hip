@@ -616,6 +616,74 @@ __global__ __launch_bounds__(256) void k_conv_bwd(NetGeo g, const uint16_t *__re
 
 
 // ------------------------------------------------------------------------------------------
+// Backward data of the vertical 32 -> 32 layer (layer 3) as a column march, the structure of
+// the forward kernel: each dout row is loaded once and the five taps come from a rolling
+// window of levels.  The MFMA forms D[ci][position] = Wt[t][ci][co] dout[position][co]^T
+// (Wt the transposed weights [tap][ci][co]); tap t pairs with level k + 2 - t, and the taps
+// are accumulated in the order t = 0 .. 4.  Lane l ends with input channels 16 nt + 4 (l / 16)
+// .. + 3 of position l % 16, masked by [aprev > 0] (8-byte loads and stores).
+// ------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_conv_bwd_col(NetGeo g, const uint16_t *__restrict__ dout,
+                                                      const uint16_t *__restrict__ wt,
+                                                      const uint16_t *__restrict__ aprev, uint16_t *__restrict__ din,
+                                                      int tiles, int kchunk, long units, int per_xcd)
+{
+    const int lane = threadIdx.x & 63, m = lane & 15, grp = lane >> 4;
+    const long unit = col_unit(per_xcd);
+    if (unit >= units) return;
+    bf16x8 wa[5][2];
+#pragma unroll
+    for (int t = 0; t < 5; ++t)
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt) wa[t][nt] = ld8(wt + (long)t * 1024 + (16 * nt + m) * 32 + 8 * grp);
+    const int tile = (int)(unit % tiles);
+    const int k0 = (int)(unit / tiles) * kchunk;
+    const int k1 = min(g.nlev, k0 + kchunk);
+    const long p2 = (long)tile * 16 + m;
+    const bool pv = p2 < g.P;
+    const long p2s = pv ? p2 : g.P - 1;   // an in-bounds address for the lanes past the plane
+    auto row = [&](int kk) -> bf16x8 {
+        const int kc = min(max(kk, 0), g.nlev - 1);
+        return keep8(ld8(dout + ((long)kc * g.P + p2s) * 32 + 8 * grp), pv && kk >= 0 && kk < g.nlev);
+    };
+    // f2bf(v * [a > 0]) for four channels: v FP32 results, a the BF16 activations
+    auto masked = [](f32x4 v, uint2 a) -> uint2 {
+        const float m0 = bf2f(static_cast<uint16_t>(a.x & 0xffffu)) > 0.f ? 1.f : 0.f;
+        const float m1 = bf2f(static_cast<uint16_t>(a.x >> 16)) > 0.f ? 1.f : 0.f;
+        const float m2 = bf2f(static_cast<uint16_t>(a.y & 0xffffu)) > 0.f ? 1.f : 0.f;
+        const float m3 = bf2f(static_cast<uint16_t>(a.y >> 16)) > 0.f ? 1.f : 0.f;
+        return make_uint2(static_cast<uint32_t>(f2bf(v[0] * m0)) | (static_cast<uint32_t>(f2bf(v[1] * m1)) << 16),
+                          static_cast<uint32_t>(f2bf(v[2] * m2)) | (static_cast<uint32_t>(f2bf(v[3] * m3)) << 16));
+    };
+    bf16x8 w0 = row(k0 - 2), w1 = row(k0 - 1), w2 = row(k0), w3 = row(k0 + 1), w4 = row(k0 + 2);
+    for (int k = k0; k < k1; ++k) {
+        const bf16x8 nx = row(k + 3);   // one level ahead
+        const long ob = ((long)k * g.P + p2s) * 32 + 4 * grp;
+        const uint2 a0 = *reinterpret_cast<const uint2 *>(aprev + ob);
+        const uint2 a1 = *reinterpret_cast<const uint2 *>(aprev + ob + 16);
+        f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+        acc0 = mfma(wa[0][0], w4, acc0);
+        acc1 = mfma(wa[0][1], w4, acc1);
+        acc0 = mfma(wa[1][0], w3, acc0);
+        acc1 = mfma(wa[1][1], w3, acc1);
+        acc0 = mfma(wa[2][0], w2, acc0);
+        acc1 = mfma(wa[2][1], w2, acc1);
+        acc0 = mfma(wa[3][0], w1, acc0);
+        acc1 = mfma(wa[3][1], w1, acc1);
+        acc0 = mfma(wa[4][0], w0, acc0);
+        acc1 = mfma(wa[4][1], w0, acc1);
+        if (pv) {
+            *reinterpret_cast<uint2 *>(din + ob) = masked(acc0, a0);
+            *reinterpret_cast<uint2 *>(din + ob + 16) = masked(acc1, a1);
+        }
+        w0 = w1;
+        w1 = w2;
+        w2 = w3;
+        w3 = w4;
+        w4 = nx;
+    }
+}
+// ------------------------------------------------------------------------------------------
 // Weight gradient of the 32 -> 32 layers through LDS (layers 2 and 3):
 //   dW[t][co][ci] = sum_p dout[p][co] in[nb(p, t)][ci],   db[co] = sum_p dout[p][co]
 // One workgroup (one partial row) walks chunks of 32 consecutive positions.  A chunk needs
@@ -1317,7 +1385,9 @@ void launch_net_backward(const NetGeo &g, const NetDev &d, const NetActs &act, c
     const int nb = net_blocks((g.n + 15) / 16, 4 * 8, 4096);
     // layer 3: dW3 from (dh3, a2); dh2 = bwd(dh3) masked by a2
     hipLaunchKernelGGL((k_conv_dw_lds<3>), dim3(rows), dim3(256), 0, s, g, act.d1, act.a2, d.part, add);
-    hipLaunchKernelGGL((k_conv_bwd<3>), dim3(nb), dim3(256), 0, s, g, act.d1, d.w3b, act.a2, act.d2);
+    const ColGrid c = col_grid(g, 16);
+    hipLaunchKernelGGL(k_conv_bwd_col, dim3(c.blocks), dim3(256), 0, s, g, act.d1, d.w3b, act.a2, act.d2, c.tiles,
+                       c.kchunk, c.units, c.per_xcd);
     // layer 2: dW2 from (dh2, a1); dh1 = bwd(dh2) masked by a1
     hipLaunchKernelGGL((k_conv_dw_lds<2>), dim3(rows), dim3(256), 0, s, g, act.d2, act.a1, d.part, add);
     hipLaunchKernelGGL((k_conv_bwd<2>), dim3(nb), dim3(256), 0, s, g, act.d2, d.w2b, act.a1, act.d1);
