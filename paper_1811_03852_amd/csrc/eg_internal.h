@@ -201,6 +201,10 @@ void launch_net_features(const NetGeo &g, const Tv *q, const Tv *z0, const Tc *a
                          int stop_mask, hipStream_t s);
 void launch_net_forward_layers(const NetGeo &g, const NetDev &d, const NetActs &act, const Scalars *sc, int stop_mask,
                                hipStream_t s);
+// inference: layers 1-2, then layer 3 fused with the output layer (a3 is not stored)
+template <typename Tv>
+void launch_net_forward_fused(const NetGeo &g, const NetDev &d, const NetActs &act, const Tv *q, Tv *qout,
+                              float *delta, const Scalars *sc, int stop_mask, hipStream_t s);
 template <typename Tv>
 void launch_net_out(const NetGeo &g, const NetDev &d, const NetActs &act, const Tv *q, Tv *qout, float *delta,
                     const Scalars *sc, int stop_mask, hipStream_t s);

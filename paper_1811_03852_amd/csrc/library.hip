@@ -475,8 +475,7 @@ void enqueue_net_stage(eg_operator *op, eg_net *net, const Tc *coef, const Tv *q
     launch_dot2<Tv>(op->n, q, q, z, z, op->partials, &nr, op->sc, stop_mask, s);
     launch_finalize(FIN_NET, op->partials, nr, op->sc, nullptr, nullptr, 0, 0, s);
     launch_net_features<Tv, Tc>(g, q, z, coef, net->act.x0, op->sc, stop_mask, s);
-    launch_net_forward_layers(g, net->d, net->act, op->sc, stop_mask, s);
-    launch_net_out<Tv>(g, net->d, net->act, q, qp, delta, op->sc, stop_mask, s);
+    launch_net_forward_fused<Tv>(g, net->d, net->act, q, qp, delta, op->sc, stop_mask, s);
     launch_thomas<Tv>(op->tri_view<Tv>(), qp, z, TH_PLAIN, nullptr, nullptr, nullptr, nullptr, op->partials, nullptr,
                       op->sc, s, stop_mask);
 }

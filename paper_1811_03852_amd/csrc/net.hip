@@ -1088,6 +1088,119 @@ __global__ __launch_bounds__(256) void k_net_out(NetGeo g, const uint16_t *__res
     }
 }
 
+// ------------------------------------------------------------------------------------------
+// Inference: layer 3 (conv1d 32 -> 32, 5 taps) and the output layer (conv1d 32 -> 1, 5 taps)
+// in one column march, so the layer-3 activations never go to HBM.  Per level kk the MFMA
+// forms the 16 positions' a3(kk) (bias, ReLU and BF16 rounding as the two-kernel path stores
+// them); each lane takes the five tap sums over its 8 channels, the four lanes of a position
+// add theirs (cross-lane), and the sums join the pending outputs of levels kk + 2 - t as in
+// k_net_out.  Output level k needs a3 at k - 2 .. k + 2, which needs a2 at k - 4 .. k + 4:
+// a level chunk recomputes the a3 levels it shares with its neighbours.
+// ------------------------------------------------------------------------------------------
+template <typename Tv>
+__global__ __launch_bounds__(256) void k_conv3_out(NetGeo g, const uint16_t *__restrict__ a2,
+                                                   const uint16_t *__restrict__ w3f, const float *__restrict__ w4,
+                                                   const float *__restrict__ theta, const Tv *__restrict__ q,
+                                                   Tv *__restrict__ qout, float *__restrict__ delta,
+                                                   const Scalars *__restrict__ sc, int stop_mask, int tiles,
+                                                   int kchunk, long units, int per_xcd)
+{
+    if (stop_now(sc, stop_mask)) return;
+    const int lane = threadIdx.x & 63, m = lane & 15, grp = lane >> 4;
+    bf16x8 wa[5][2];
+#pragma unroll
+    for (int c = 0; c < 5; ++c)
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt) wa[c][nt] = ld8(w3f + (long)c * 1024 + (16 * nt + m) * 32 + 8 * grp);
+    // this lane's channels 16 nt + 4 grp + jj: layer-3 bias in registers; the output layer's
+    // weights in LDS (four consecutive channels per 16-byte read), re-read every level rather
+    // than held in 40 registers, so more waves fit on a SIMD
+    __shared__ __align__(16) float w4s[160];
+    if (threadIdx.x < 160) w4s[threadIdx.x] = w4[threadIdx.x];
+    __syncthreads();
+    float bs[2][4];
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) bs[nt][jj] = theta[kNetOffB3 + 16 * nt + 4 * grp + jj];
+    const long unit = col_unit(per_xcd);
+    if (unit >= units) return;
+    const float b4 = theta[kNetOffB4];
+    const double rho = sqrt(sc->net_q2 / (double)g.n);
+    const int tile = (int)(unit % tiles);
+    const int k0 = (int)(unit / tiles) * kchunk;
+    const int k1 = min(g.nlev, k0 + kchunk);
+    const long p2 = (long)tile * 16 + m;
+    const bool pv = p2 < g.P;
+    const long p2s = pv ? p2 : g.P - 1;   // an in-bounds address for the lanes past the plane
+    auto row = [&](int kk) -> bf16x8 {
+        const int kc = min(max(kk, 0), g.nlev - 1);
+        return keep8(ld8(a2 + ((long)kc * g.P + p2s) * 32 + 8 * grp), pv && kk >= 0 && kk < g.nlev);
+    };
+    // a2 window of the first a3 level computed (it moves one level per computed a3 level) and
+    // the next two rows in flight
+    const int ka = max(k0 - 2, 0);
+    bf16x8 v0 = row(ka - 2), v1 = row(ka - 1), v2 = row(ka), v3 = row(ka + 1), v4 = row(ka + 2);
+    bf16x8 n0 = row(ka + 3), n1 = row(ka + 4);
+    // r[d] accumulates the output of level kk - 2 + d
+    float r[5] = {b4, b4, b4, b4, b4};
+    for (int kk = k0 - 2; kk < k1 + 2; ++kk) {
+        if (kk >= 0 && kk < g.nlev) {
+            asm volatile("" ::: "memory");   // keeps the LDS weight reads inside the loop
+            const bf16x8 nx = row(kk + 5);   // three levels ahead
+            f32x4 acc[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
+#pragma unroll
+            for (int nt = 0; nt < 2; ++nt) {
+                acc[nt] = mfma(wa[0][nt], v0, acc[nt]);
+                acc[nt] = mfma(wa[1][nt], v1, acc[nt]);
+                acc[nt] = mfma(wa[2][nt], v2, acc[nt]);
+                acc[nt] = mfma(wa[3][nt], v3, acc[nt]);
+                acc[nt] = mfma(wa[4][nt], v4, acc[nt]);
+            }
+            float st[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int nt = 0; nt < 2; ++nt) {
+                float a[4];
+#pragma unroll
+                for (int jj = 0; jj < 4; ++jj) a[jj] = bf2f(f2bf(fmaxf(acc[nt][jj] + bs[nt][jj], 0.f)));
+#pragma unroll
+                for (int t = 0; t < 5; ++t) {
+                    const float4 wv = *reinterpret_cast<const float4 *>(w4s + t * 32 + 16 * nt + 4 * grp);
+                    st[t] += wv.x * a[0];
+                    st[t] += wv.y * a[1];
+                    st[t] += wv.z * a[2];
+                    st[t] += wv.w * a[3];
+                }
+            }
+#pragma unroll
+            for (int t = 0; t < 5; ++t) {
+                st[t] += __shfl_xor(st[t], 16);
+                st[t] += __shfl_xor(st[t], 32);
+            }
+#pragma unroll
+            for (int d = 0; d < 5; ++d) r[d] += st[4 - d];
+            v0 = v1;
+            v1 = v2;
+            v2 = v3;
+            v3 = v4;
+            v4 = n0;
+            n0 = n1;
+            n1 = nx;
+        }
+        const int k = kk - 2;
+        if (k >= k0 && k < k1 && grp == 0 && pv) {
+            const long p = (long)k * g.P + p2;
+            if (delta) delta[p] = r[0];
+            qout[p] = static_cast<Tv>(static_cast<double>(q[p]) + rho * static_cast<double>(r[0]));
+        }
+        r[0] = r[1];
+        r[1] = r[2];
+        r[2] = r[3];
+        r[3] = r[4];
+        r[4] = b4;
+    }
+}
+
 // Backward of the output layer:  dδ = rho u;  dh3[p][c] = [a3 > 0] sum_t W4[t][c] dδ[p - (t - 2) P]
 __global__ __launch_bounds__(256) void k_net_out_bwd(NetGeo g, const float *__restrict__ u,
                                                      const uint16_t *__restrict__ a3, const float *__restrict__ w4,
@@ -1326,8 +1439,9 @@ void launch_net_features(const NetGeo &g, const Tv *q, const Tv *z0, const Tc *a
                        sc, stop_mask);
 }
 
-void launch_net_forward_layers(const NetGeo &g, const NetDev &d, const NetActs &act, const Scalars *sc, int stop_mask,
-                               hipStream_t s)
+// layers 1 and 2 (x0 -> a1 -> a2)
+static void launch_net_layers12(const NetGeo &g, const NetDev &d, const NetActs &act, const Scalars *sc, int stop_mask,
+                                hipStream_t s)
 {
     const ColGrid c = col_grid(g, 16);
     hipLaunchKernelGGL((k_conv_fwd<1>), dim3(c.blocks), dim3(256), 0, s, g, act.x0, d.w1f, d.theta + kNetOffB1, act.a1,
@@ -1342,8 +1456,25 @@ void launch_net_forward_layers(const NetGeo &g, const NetDev &d, const NetActs &
     else
         hipLaunchKernelGGL((k_conv_fwd<2>), dim3(c.blocks), dim3(256), 0, s, g, act.a1, d.w2f, d.theta + kNetOffB2,
                            act.a2, sc, stop_mask, c.tiles, c.kchunk, c.units, c.per_xcd);
+}
+
+void launch_net_forward_layers(const NetGeo &g, const NetDev &d, const NetActs &act, const Scalars *sc, int stop_mask,
+                               hipStream_t s)
+{
+    launch_net_layers12(g, d, act, sc, stop_mask, s);
+    const ColGrid c = col_grid(g, 16);
     hipLaunchKernelGGL((k_conv_fwd<3>), dim3(c.blocks), dim3(256), 0, s, g, act.a2, d.w3f, d.theta + kNetOffB3, act.a3,
                        sc, stop_mask, c.tiles, c.kchunk, c.units, c.per_xcd);
+}
+
+template <typename Tv>
+void launch_net_forward_fused(const NetGeo &g, const NetDev &d, const NetActs &act, const Tv *q, Tv *qout,
+                              float *delta, const Scalars *sc, int stop_mask, hipStream_t s)
+{
+    launch_net_layers12(g, d, act, sc, stop_mask, s);
+    const ColGrid c = col_grid(g, 16);
+    hipLaunchKernelGGL((k_conv3_out<Tv>), dim3(c.blocks), dim3(256), 0, s, g, act.a2, d.w3f, d.w4, d.theta, q, qout,
+                       delta, sc, stop_mask, c.tiles, c.kchunk, c.units, c.per_xcd);
 }
 
 template <typename Tv>
@@ -1420,6 +1551,10 @@ template void launch_net_features<float, double>(const NetGeo &, const float *, 
                                                  uint16_t *, const Scalars *, int, hipStream_t);
 template void launch_net_features<float, float>(const NetGeo &, const float *, const float *, const float *,
                                                 uint16_t *, const Scalars *, int, hipStream_t);
+template void launch_net_forward_fused<double>(const NetGeo &, const NetDev &, const NetActs &, const double *,
+                                               double *, float *, const Scalars *, int, hipStream_t);
+template void launch_net_forward_fused<float>(const NetGeo &, const NetDev &, const NetActs &, const float *, float *,
+                                              float *, const Scalars *, int, hipStream_t);
 template void launch_net_out<double>(const NetGeo &, const NetDev &, const NetActs &, const double *, double *,
                                      float *, const Scalars *, int, hipStream_t);
 template void launch_net_out<float>(const NetGeo &, const NetDev &, const NetActs &, const float *, float *, float *,
