@@ -61,12 +61,12 @@ MEASURED_TRAFFIC = {("n1280_2560x1920x70", "spmv_fp64"): 28.74e9, ("n1280_2560x1
                     ("n1280_2560x1920x70", "thomas_p_fp64"): 22.02e9, ("n1280_2560x1920x70", "thomas_s_fp64"): 19.27e9, ("n1280_2560x1920x70", "update_fp64"): 22.02e9,
                     ("n1280_2560x1920x70", "thomas_p_fp32"): 11.01e9, ("n1280_2560x1920x70", "thomas_s_fp32"): 9.63e9, ("n1280_2560x1920x70", "update_fp32"): 11.01e9,
                     ("n1280_2560x1920x70", "thomas_p_bf16"): 11.01e9, ("n1280_2560x1920x70", "thomas_s_bf16"): 9.63e9, ("n1280_2560x1920x70", "update_bf16"): 11.01e9,
-                    ("n1280_2560x1920x70", "residual_fp64"): 27.44e9,
+                    ("n1280_2560x1920x70", "residual_fp64"): 27.42e9,
                     ("n1280_2560x1920x70", "thomas_p_cm_fp64"): 24.77e9, ("n1280_2560x1920x70", "thomas_s_cm_fp64"): 22.02e9,
                     ("n1280_2560x1920x70", "thomas_p_cm_fp32"): 12.39e9, ("n1280_2560x1920x70", "thomas_s_cm_fp32"): 11.01e9,
                     ("n1280_2560x1920x70", "thomas_p_cm_bf16"): 12.39e9, ("n1280_2560x1920x70", "thomas_s_cm_bf16"): 11.01e9,
                     # one line-SOR application = five half-sweeps
-                    ("n1280_2560x1920x70", "sor_fp64"): 80.82e9, ("n1280_2560x1920x70", "sor_fp32"): 39.61e9, ("n1280_2560x1920x70", "sor_bf16"): 32.77e9}
+                    ("n1280_2560x1920x70", "sor_fp64"): 80.83e9, ("n1280_2560x1920x70", "sor_fp32"): 39.62e9, ("n1280_2560x1920x70", "sor_bf16"): 32.77e9}
 
 
 def log(*a):

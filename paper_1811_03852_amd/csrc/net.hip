@@ -1092,9 +1092,8 @@ __global__ __launch_bounds__(256) void k_net_out(NetGeo g, const uint16_t *__res
 // Inference: layer 3 (conv1d 32 -> 32, 5 taps) and the output layer (conv1d 32 -> 1, 5 taps)
 // in one column march, so the layer-3 activations never go to HBM.  Per level kk the MFMA
 // forms the 16 positions' a3(kk) (bias, ReLU and BF16 rounding as the two-kernel path stores
-// them); each lane takes the five tap sums over its 8 channels, the four lanes of a position
-// add theirs (cross-lane), and the sums join the pending outputs of levels kk + 2 - t as in
-// k_net_out.  Output level k needs a3 at k - 2 .. k + 2, which needs a2 at k - 4 .. k + 4:
+// them), a second MFMA the five tap sums of each position, and the sums join the pending
+// outputs of levels kk + 2 - t as in k_net_out.  Output level k needs a3 at k - 2 .. k + 2, which needs a2 at k - 4 .. k + 4:
 // a level chunk recomputes the a3 levels it shares with its neighbours.
 // ------------------------------------------------------------------------------------------
 template <typename Tv>
@@ -1112,17 +1111,24 @@ __global__ __launch_bounds__(256) void k_conv3_out(NetGeo g, const uint16_t *__r
     for (int c = 0; c < 5; ++c)
 #pragma unroll
         for (int nt = 0; nt < 2; ++nt) wa[c][nt] = ld8(w3f + (long)c * 1024 + (16 * nt + m) * 32 + 8 * grp);
-    // this lane's channels 16 nt + 4 grp + jj: layer-3 bias in registers; the output layer's
-    // weights in LDS (four consecutive channels per 16-byte read), re-read every level rather
-    // than held in 40 registers, so more waves fit on a SIMD
-    __shared__ __align__(16) float w4s[160];
-    if (threadIdx.x < 160) w4s[threadIdx.x] = w4[threadIdx.x];
-    __syncthreads();
+    // this lane's channels 16 nt + 4 grp + jj: layer-3 bias
     float bs[2][4];
 #pragma unroll
     for (int nt = 0; nt < 2; ++nt)
 #pragma unroll
         for (int jj = 0; jj < 4; ++jj) bs[nt][jj] = theta[kNetOffB3 + 16 * nt + 4 * grp + jj];
+    // The output layer is one more MFMA per level, D[t][position] = W4[t][K] a3[position][K]:
+    // with the K index 8 grp + 4 nt + jj standing for channel 16 nt + 4 grp + jj, the B operand
+    // is this lane's own eight a3 values, and A is row t = m of W4 (taps 0..4; rows 5..15 zero)
+    // in the same channel order.  W4 is held BF16-exact, so the products are exact.
+    uint32_t wd[4];
+#pragma unroll
+    for (int i = 0; i < 8; i += 2) {
+        const int c = 16 * (i / 4) + 4 * grp + (i % 4);   // channel of K element 8 grp + i
+        const uint32_t lo = m < 5 ? f2bf(w4[m * 32 + c]) : 0u, hi = m < 5 ? f2bf(w4[m * 32 + c + 1]) : 0u;
+        wd[i / 2] = lo | (hi << 16);
+    }
+    const bf16x8 w4a = __builtin_bit_cast(bf16x8, make_uint4(wd[0], wd[1], wd[2], wd[3]));
     const long unit = col_unit(per_xcd);
     if (unit >= units) return;
     const float b4 = theta[kNetOffB4];
@@ -1146,7 +1152,6 @@ __global__ __launch_bounds__(256) void k_conv3_out(NetGeo g, const uint16_t *__r
     float r[5] = {b4, b4, b4, b4, b4};
     for (int kk = k0 - 2; kk < k1 + 2; ++kk) {
         if (kk >= 0 && kk < g.nlev) {
-            asm volatile("" ::: "memory");   // keeps the LDS weight reads inside the loop
             const bf16x8 nx = row(kk + 5);   // three levels ahead
             f32x4 acc[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
 #pragma unroll
@@ -1157,26 +1162,19 @@ __global__ __launch_bounds__(256) void k_conv3_out(NetGeo g, const uint16_t *__r
                 acc[nt] = mfma(wa[3][nt], v3, acc[nt]);
                 acc[nt] = mfma(wa[4][nt], v4, acc[nt]);
             }
-            float st[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+            // a3 as the two-kernel path stores it (bias, ReLU, BF16), packed in K order
+            uint32_t ad[4];
 #pragma unroll
-            for (int nt = 0; nt < 2; ++nt) {
-                float a[4];
-#pragma unroll
-                for (int jj = 0; jj < 4; ++jj) a[jj] = bf2f(f2bf(fmaxf(acc[nt][jj] + bs[nt][jj], 0.f)));
-#pragma unroll
-                for (int t = 0; t < 5; ++t) {
-                    const float4 wv = *reinterpret_cast<const float4 *>(w4s + t * 32 + 16 * nt + 4 * grp);
-                    st[t] += wv.x * a[0];
-                    st[t] += wv.y * a[1];
-                    st[t] += wv.z * a[2];
-                    st[t] += wv.w * a[3];
-                }
+            for (int i = 0; i < 8; i += 2) {
+                const uint32_t lo = f2bf(fmaxf(acc[i / 4][i % 4] + bs[i / 4][i % 4], 0.f));
+                const uint32_t hi = f2bf(fmaxf(acc[i / 4][i % 4 + 1] + bs[i / 4][i % 4 + 1], 0.f));
+                ad[i / 2] = lo | (hi << 16);
             }
-#pragma unroll
-            for (int t = 0; t < 5; ++t) {
-                st[t] += __shfl_xor(st[t], 16);
-                st[t] += __shfl_xor(st[t], 32);
-            }
+            const f32x4 so = mfma(w4a, __builtin_bit_cast(bf16x8, make_uint4(ad[0], ad[1], ad[2], ad[3])),
+                                  f32x4{0.f, 0.f, 0.f, 0.f});
+            // lane (m, 0) holds the tap sums t = 0..3 of position m, lane (m, 1) holds t = 4
+            const float s4 = __shfl_down(so[0], 16);
+            const float st[5] = {so[0], so[1], so[2], so[3], s4};
 #pragma unroll
             for (int d = 0; d < 5; ++d) r[d] += st[4 - d];
             v0 = v1;
