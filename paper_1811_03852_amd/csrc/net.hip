@@ -1093,8 +1093,9 @@ __global__ __launch_bounds__(256) void k_net_out(NetGeo g, const uint16_t *__res
 // in one column march, so the layer-3 activations never go to HBM.  Per level kk the MFMA
 // forms the 16 positions' a3(kk) (bias, ReLU and BF16 rounding as the two-kernel path stores
 // them), a second MFMA the five tap sums of each position, and the sums join the pending
-// outputs of levels kk + 2 - t as in k_net_out.  Output level k needs a3 at k - 2 .. k + 2, which needs a2 at k - 4 .. k + 4:
-// a level chunk recomputes the a3 levels it shares with its neighbours.
+// outputs of levels kk + 2 - t as in k_net_out.  Output level k needs a3 at k - 2 .. k + 2,
+// which needs a2 at k - 4 .. k + 4: a level chunk recomputes the a3 levels it shares with its
+// neighbours.
 // ------------------------------------------------------------------------------------------
 template <typename Tv>
 __global__ __launch_bounds__(256) void k_conv3_out(NetGeo g, const uint16_t *__restrict__ a2,
@@ -1105,6 +1106,8 @@ __global__ __launch_bounds__(256) void k_conv3_out(NetGeo g, const uint16_t *__r
                                                    int kchunk, long units, int per_xcd)
 {
     if (stop_now(sc, stop_mask)) return;
+    const long unit = col_unit(per_xcd);
+    if (unit >= units) return;
     const int lane = threadIdx.x & 63, m = lane & 15, grp = lane >> 4;
     bf16x8 wa[5][2];
 #pragma unroll
@@ -1129,8 +1132,6 @@ __global__ __launch_bounds__(256) void k_conv3_out(NetGeo g, const uint16_t *__r
         wd[i / 2] = lo | (hi << 16);
     }
     const bf16x8 w4a = __builtin_bit_cast(bf16x8, make_uint4(wd[0], wd[1], wd[2], wd[3]));
-    const long unit = col_unit(per_xcd);
-    if (unit >= units) return;
     const float b4 = theta[kNetOffB4];
     const double rho = sqrt(sc->net_q2 / (double)g.n);
     const int tile = (int)(unit % tiles);
