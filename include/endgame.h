@@ -145,6 +145,9 @@ int eg_set_stream(eg_operator *op, void *hip_stream);
  *   "inner_maxit"    limit on the iterations of one inner FP32 solve [1000]; the correction of
  *                    a capped inner solve is kept only if it lowers the FP64 true residual
  *   "poll"           iterations enqueued between host checks of the device flags [8]
+ *   "eps_bd"         BiCGStab breakdown threshold, 0 <= eps_bd < 1 [2^-52]: the iteration
+ *                    restarts (rhat = p = r) when |<rhat, r>| <= eps_bd ||rhat|| ||r|| or
+ *                    |<rhat, v>| <= eps_bd ||rhat|| ||v|| (Sec. 4: near-zero scalar weights)
  *   "stall_window"   learned modes: iterations without a 2x gain that trigger fallback [20]
  *                    (FGMRES: at least one restart cycle, max(stall_window, gmres_m))
  *   "profile"        1 = time every streaming kernel launch (see eg_kernel_stats) [0]

@@ -22,6 +22,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liboracle.so")
 _SRC = os.path.join(_HERE, "oracle.c")
 _lib = None
+EPS_BD = 2.0 ** -52   # default breakdown threshold of BiCGStab (relative cosine)
 
 
 def build(force: bool = True) -> str:
@@ -37,7 +38,8 @@ def build(force: bool = True) -> str:
 class _Info(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int), ("restarts", ctypes.c_int), ("status", ctypes.c_int),
                 ("half_step_exit", ctypes.c_int), ("rel_residual", ctypes.c_double),
-                ("true_rel_residual", ctypes.c_double)]
+                ("true_rel_residual", ctypes.c_double), ("sigma_restarts", ctypes.c_int),
+                ("rho_restarts", ctypes.c_int)]
 
 
 @dataclass
@@ -49,6 +51,8 @@ class SolveInfo:
     rel_residual: float
     true_rel_residual: float
     history: np.ndarray
+    sigma_restarts: int = 0
+    rho_restarts: int = 0
 
 
 def _load():
@@ -72,6 +76,7 @@ def _load():
                                                              ctypes.c_int, ctypes.c_int, ctypes.c_double, dp,
                                                              ctypes.c_int, ctypes.POINTER(_Info)]
         lib.orc_bicgstab_sor.restype = ctypes.c_int
+        lib.orc_set_eps_bd.argtypes = [ctypes.c_double]
         _lib = lib
     return _lib
 
@@ -148,10 +153,11 @@ def lexsor(coef: np.ndarray, q: np.ndarray, sweeps: int = 3, omega: float = 1.5)
 
 def bicgstab(coef: np.ndarray, b: np.ndarray, x0: np.ndarray | None = None, tol: float = 1e-8,
              maxit: int = 20000, restart_every: int = 0, precond: int = 1,
-             hist_cap: int | None = None, sor_sweeps: int = 3, sor_omega: float = 1.5) -> tuple[np.ndarray, SolveInfo]:
+             hist_cap: int | None = None, sor_sweeps: int = 3, sor_omega: float = 1.5,
+             eps_bd: float = EPS_BD) -> tuple[np.ndarray, SolveInfo]:
     """Right-preconditioned BiCGStab; precond 1 = vertical tridiagonal, 0 = identity,
     2 = red-black line SOR, 3 = lexicographic line SOR, with ``sor_sweeps`` sweeps and
-    relaxation ``sor_omega``."""
+    relaxation ``sor_omega``; ``eps_bd`` is the breakdown threshold (relative cosine)."""
     nlon, nlat, nlev = _check(coef)
     n = nlon * nlat * nlev
     b = _vec(b, n)
@@ -159,15 +165,17 @@ def bicgstab(coef: np.ndarray, b: np.ndarray, x0: np.ndarray | None = None, tol:
     cap = maxit if hist_cap is None else hist_cap
     hist = np.full(max(cap, 1), np.nan)
     info = _Info()
+    _load().orc_set_eps_bd(float(eps_bd))
     if precond in (2, 3):
         _load().orc_bicgstab_sor(nlon, nlat, nlev, _dp(coef), _dp(b), _dp(x), tol, maxit, restart_every, precond,
                                  int(sor_sweeps), float(sor_omega), _dp(hist), cap, ctypes.byref(info))
     else:
         _load().orc_bicgstab(nlon, nlat, nlev, _dp(coef), _dp(b), _dp(x), tol, maxit, restart_every, precond,
                              _dp(hist), cap, ctypes.byref(info))
+    _load().orc_set_eps_bd(EPS_BD)
     h = hist[:min(info.iterations, cap)].copy()
     return x, SolveInfo(info.iterations, info.restarts, info.status, info.half_step_exit, info.rel_residual,
-                        info.true_rel_residual, h)
+                        info.true_rel_residual, h, info.sigma_restarts, info.rho_restarts)
 
 
 def dense_matrix(coef: np.ndarray) -> np.ndarray:

@@ -55,6 +55,8 @@ typedef struct {
     int half_step_exit;      /* 1 if the final exit happened at the half step                 */
     double rel_residual;     /* recursive ||r|| / ||b|| at exit                               */
     double true_rel_residual;/* ||b - A x|| / ||b|| at exit                                   */
+    int sigma_restarts;      /* restarts taken because <rhat, v> was near zero                 */
+    int rho_restarts;        /* restarts taken because <rhat, r> was near zero                 */
 } orc_info;
 
 /* y = A x, plain row definition (Sec. 2: 7-band operator). */
@@ -272,6 +274,11 @@ static double nrm2(long n, const double *a) { return sqrt(orc_dot(n, a, a)); }
 /* preconditioner choice of orc_bicgstab: 0 = identity, 1 = vertical tridiagonal (T^{-1}),
  * 2 = red-black line SOR (orc_rbsor), 3 = lexicographic line SOR (orc_lexsor), both with
  * sor_sweeps sweeps and relaxation sor_omega (orc_bicgstab_sor) */
+/* Breakdown threshold of BiCGStab (relative cosine), 2^-52 unless a test sets another to force
+ * the restart paths. */
+static double g_eps_bd = 2.220446049250313e-16;
+void orc_set_eps_bd(double eps) { g_eps_bd = eps; }
+
 static int g_sor_sweeps = 3;
 static double g_sor_omega = 1.5;
 
@@ -315,7 +322,7 @@ int orc_bicgstab(int nlon, int nlat, int nlev, const double *coef, const double 
                  int hist_cap, orc_info *info)
 {
     const long n = (long)nlon * nlat * nlev;
-    const double eps_bd = 2.220446049250313e-16; /* 2^-52 */
+    const double eps_bd = g_eps_bd;
     orc_info loc;
     if (!info) info = &loc;
     memset(info, 0, sizeof(*info));
@@ -372,6 +379,7 @@ int orc_bicgstab(int nlon, int nlat, int nlev, const double *coef, const double 
             rhnorm = rnorm;
             rho = orc_dot(n, rh, r);
             info->restarts++;
+            info->rho_restarts++;
         }
         double beta = (rho / rho_prev) * (alpha / omega);
         for (long i = 0; i < n; ++i) p[i] = r[i] + beta * (p[i] - omega * v[i]);
@@ -380,6 +388,7 @@ int orc_bicgstab(int nlon, int nlat, int nlev, const double *coef, const double 
         double sigma = orc_dot(n, rh, v);
         if (fabs(sigma) <= eps_bd * rhnorm * nrm2(n, v)) {
             info->restarts++;
+            info->sigma_restarts++;
             fresh = 1;
             if (hist && it <= hist_cap) hist[it - 1] = rnorm / nb;
             continue;

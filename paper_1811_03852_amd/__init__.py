@@ -121,6 +121,40 @@ def _ptr(t) -> int:
     return t.data_ptr()
 
 
+def _args(*specs):
+    """Device pointers of tensor arguments after checking what the C ABI assumes of each: a
+    contiguous tensor of ``numel`` elements of ``dtype`` on ``device``.  ``specs`` are tuples
+    (tensor, name, dtype, numel, device); None tensors pass through as None.  The shapes and
+    types of all arguments are checked before their placement.  Raises before any library call."""
+    import torch
+    for t, name, dtype, numel, _ in specs:
+        if t is None:
+            continue
+        if not isinstance(t, torch.Tensor):
+            raise TypeError(f"{name}: expected a torch.Tensor")
+        if t.dtype != dtype:
+            raise ValueError(f"{name}: expected {dtype}, got {t.dtype}")
+        if t.numel() != numel:
+            raise ValueError(f"{name}: expected {numel} elements, got {t.numel()}")
+        if not t.is_contiguous():
+            raise ValueError(f"{name}: tensor must be contiguous")
+    out = []
+    for t, name, _, _, device in specs:
+        if t is None:
+            out.append(None)
+            continue
+        if not t.is_cuda:
+            raise TypeError(f"{name}: expected a CUDA/HIP tensor")
+        if device is not None and t.device != device:
+            raise ValueError(f"{name}: on {t.device}, the operator lives on {device}")
+        out.append(t.data_ptr())
+    return out
+
+
+def _arg(t, name: str, dtype, numel: int, device=None) -> int:
+    return _args((t, name, dtype, numel, device))[0]
+
+
 def _vec_dtype(prec: int):
     import torch
     return torch.float64 if prec == PREC_FP64 else torch.float32
@@ -177,8 +211,10 @@ class Operator:
 
     def solve(self, b, x, tol: float = 1e-8, maxit: int = 20000, mode: int = FP64) -> SolveInfo:
         """Solve in place: ``x`` holds the initial guess and receives the solution."""
+        import torch
+        pb, px = _args((b, "b", torch.float64, self.n, self.device), (x, "x", torch.float64, self.n, self.device))
         self._bind_stream()
-        status = _check(_lib.eg_solve(self._h, _ptr(b), _ptr(x), float(tol), int(maxit), int(mode)))
+        status = _check(_lib.eg_solve(self._h, pb, px, float(tol), int(maxit), int(mode)))
         info = _Info()
         _check(_lib.eg_get_info(self._h, ctypes.byref(info)))
         return SolveInfo(status, info.iterations, info.outer_steps, info.restarts, info.fallbacks,
@@ -191,26 +227,46 @@ class Operator:
         _lib.eg_residual_history(self._h, buf.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), cnt)
         return buf[:cnt]
 
+    def _prec_arg(self, prec: int):
+        if prec not in (PREC_FP64, PREC_FP32, PREC_BF16, PREC_FP16):
+            raise ValueError(f"unknown precision {prec}")
+        return _vec_dtype(prec)
+
     def apply(self, x, y=None, prec: int = PREC_FP64):
         import torch
-        self._bind_stream()
+        dt = self._prec_arg(prec)
+        _args((x, "x", dt, self.n, None), (y, "y", dt, self.n, None))
+        px = _arg(x, "x", dt, self.n, self.device)
         if y is None:
             y = torch.empty_like(x)
-        _check(_lib.eg_apply(self._h, _ptr(x), _ptr(y), int(prec)))
+        py = _arg(y, "y", dt, self.n, self.device)
+        if py == px:
+            raise ValueError("x and y must not overlap")
+        self._bind_stream()
+        _check(_lib.eg_apply(self._h, px, py, int(prec)))
         return y
 
     def precond(self, q, z=None, prec: int = PREC_FP64):
         import torch
-        self._bind_stream()
+        dt = self._prec_arg(prec)
+        _args((q, "q", dt, self.n, None), (z, "z", dt, self.n, None))
+        pq = _arg(q, "q", dt, self.n, self.device)
         if z is None:
             z = torch.empty_like(q)
-        _check(_lib.eg_apply_precond(self._h, _ptr(q), _ptr(z), int(prec)))
+        pz = _arg(z, "z", dt, self.n, self.device)
+        if pz == pq:
+            raise ValueError("q and z must not overlap")
+        self._bind_stream()
+        _check(_lib.eg_apply_precond(self._h, pq, pz, int(prec)))
         return z
 
     def residual(self, b, x, r=None) -> float:
+        import torch
+        pb, px, pr = _args((b, "b", torch.float64, self.n, self.device), (x, "x", torch.float64, self.n, self.device),
+                           (r, "r", torch.float64, self.n, self.device))
         self._bind_stream()
         rel = ctypes.c_double()
-        _check(_lib.eg_residual(self._h, _ptr(b), _ptr(x), None if r is None else _ptr(r), ctypes.byref(rel)))
+        _check(_lib.eg_residual(self._h, pb, px, pr, ctypes.byref(rel)))
         return rel.value
 
     def kernel_stats(self, kernel: int, prec: int) -> tuple[int, float]:
@@ -231,28 +287,39 @@ class Operator:
     def harvest(self, b, nsnap: int):
         """(r, e) float tensors of shape (count, n) from the solver's own FP64 iterates."""
         import torch
+        if nsnap < 1:
+            raise ValueError("nsnap must be >= 1")
+        pb = _arg(b, "b", torch.float64, self.n, self.device)
         self._bind_stream()
         r = torch.empty((nsnap, self.n), dtype=torch.float32, device=b.device)
         e = torch.empty_like(r)
-        cnt = _check(_lib.eg_harvest(self._h, _ptr(b), int(nsnap), _ptr(r), _ptr(e)))
+        cnt = _check(_lib.eg_harvest(self._h, pb, int(nsnap), _ptr(r), _ptr(e)))
         return r[:cnt].contiguous(), e[:cnt].contiguous()
 
     def harvest_krylov(self, b, nvec: int, errors: bool = True):
         """(r, e) float tensors of shape (count, n): the FGMRES basis vectors of b and A^{-1} of
         each (e is None when ``errors`` is False)."""
         import torch
+        if not 1 <= nvec <= 64:
+            raise ValueError("nvec must be in 1..64")
+        pb = _arg(b, "b", torch.float64, self.n, self.device)
         self._bind_stream()
         r = torch.empty((nvec, self.n), dtype=torch.float32, device=b.device)
         e = torch.empty_like(r) if errors else None
-        cnt = _check(_lib.eg_harvest_krylov(self._h, _ptr(b), int(nvec), _ptr(r), _ptr(e) if errors else None))
+        cnt = _check(_lib.eg_harvest_krylov(self._h, pb, int(nvec), _ptr(r), _ptr(e) if errors else None))
         return r[:cnt].contiguous(), (e[:cnt].contiguous() if errors else None)
 
     def dot(self, a, b) -> float:
+        """<a, b> with FP64 products and sums; a and b: float64 or float32 tensors of equal
+        length and dtype (any length) on the operator's device."""
         import torch
-        self._bind_stream()
+        if not isinstance(a, torch.Tensor) or a.dtype not in (torch.float64, torch.float32):
+            raise ValueError("a: expected a float64 or float32 tensor")
+        pa, pb = _args((a, "a", a.dtype, a.numel(), self.device), (b, "b", a.dtype, a.numel(), self.device))
         prec = PREC_FP64 if a.dtype == torch.float64 else PREC_FP32
+        self._bind_stream()
         out = ctypes.c_double()
-        _check(_lib.eg_dot(self._h, _ptr(a), _ptr(b), a.numel(), prec, ctypes.byref(out)))
+        _check(_lib.eg_dot(self._h, pa, pb, a.numel(), prec, ctypes.byref(out)))
         return out.value
 
 
@@ -295,42 +362,62 @@ class Net:
     def apply(self, op: Operator, q, delta=None):
         """M(q) in FP32 (q: float tensor of n); returns z (and fills ``delta`` if given)."""
         import torch
+        pq, pd = _args((q, "q", torch.float32, op.n, op.device), (delta, "delta", torch.float32, op.n, op.device))
         op._bind_stream()
         z = torch.empty_like(q)
-        _check(_lib.eg_net_apply(op._h, self._h, _ptr(q), _ptr(z), None if delta is None else _ptr(delta)))
+        _check(_lib.eg_net_apply(op._h, self._h, pq, _ptr(z), pd))
         return z
 
     def loss_grad(self, op: Operator, r, e):
         import numpy as np
+        import torch
+        pr, pe = _args((r, "r", torch.float32, op.n, op.device), (e, "e", torch.float32, op.n, op.device))
         op._bind_stream()
         loss = ctypes.c_double()
         g = np.zeros(N_NET_PARAMS, dtype=np.float32)
-        _check(_lib.eg_net_loss_grad(op._h, self._h, _ptr(r), _ptr(e), ctypes.byref(loss),
-                                     g.ctypes.data_as(ctypes.c_void_p)))
+        _check(_lib.eg_net_loss_grad(op._h, self._h, pr, pe, ctypes.byref(loss), g.ctypes.data_as(ctypes.c_void_p)))
         return loss.value, g
 
     @staticmethod
-    def _pairs(ops, pair_op):
+    def _pairs(ops, r, e, pair_op):
+        """Checked marshalling of a training set: r and e float32 of shape (len(pair_op), n) on
+        the operators' device, every operator of the same grid, every pair_op index valid."""
         import numpy as np
+        import torch
+        if not ops:
+            raise ValueError("need at least one operator")
+        n, device = ops[0].n, ops[0].device
+        for o in ops:
+            if (o.nlon, o.nlat, o.nlev) != (ops[0].nlon, ops[0].nlat, ops[0].nlev) or o.device != device:
+                raise ValueError("all training operators must have the same grid and device")
+        po = np.ascontiguousarray(pair_op, dtype=np.int32).ravel()
+        if po.size < 1 or po.min() < 0 or po.max() >= len(ops):
+            raise ValueError("pair_op must hold operator indices in [0, len(ops))")
+        for name, t in (("r", r), ("e", e)):
+            if not isinstance(t, torch.Tensor) or tuple(t.shape) != (po.size, n):
+                raise ValueError(f"{name}: expected shape ({po.size}, {n}), got "
+                                 f"{tuple(t.shape) if isinstance(t, torch.Tensor) else type(t)}")
+        pr, pe = _args((r, "r", torch.float32, po.size * n, device), (e, "e", torch.float32, po.size * n, device))
         arr = (ctypes.c_void_p * len(ops))(*[o._h.value for o in ops])
-        po = np.ascontiguousarray(pair_op, dtype=np.int32)
-        return arr, po
+        return arr, po, pr, pe
 
     def train(self, ops, r, e, pair_op, epochs: int, batch: int = 16, lr: float = 1e-3, seed: int = 0):
         """Adam training; returns the per-epoch mean training loss (numpy array)."""
         import numpy as np
+        arr, po, pr, pe = self._pairs(ops, r, e, pair_op)
+        if epochs < 0 or batch < 1 or not lr > 0:
+            raise ValueError("need epochs >= 0, batch >= 1, lr > 0")
         ops[0]._bind_stream()
-        arr, po = self._pairs(ops, pair_op)
         hist = np.zeros(max(epochs, 1))
-        _check(_lib.eg_net_train(self._h, arr, len(ops), _ptr(r), _ptr(e), po.ctypes.data_as(ctypes.c_void_p),
+        _check(_lib.eg_net_train(self._h, arr, len(ops), pr, pe, po.ctypes.data_as(ctypes.c_void_p),
                                  po.size, int(epochs), int(batch), float(lr), int(seed),
                                  hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
         return hist[:epochs]
 
     def eval(self, ops, r, e, pair_op) -> float:
+        arr, po, pr, pe = self._pairs(ops, r, e, pair_op)
         ops[0]._bind_stream()
-        arr, po = self._pairs(ops, pair_op)
         out = ctypes.c_double()
-        _check(_lib.eg_net_eval(self._h, arr, len(ops), _ptr(r), _ptr(e), po.ctypes.data_as(ctypes.c_void_p),
+        _check(_lib.eg_net_eval(self._h, arr, len(ops), pr, pe, po.ctypes.data_as(ctypes.c_void_p),
                                 po.size, ctypes.byref(out)))
         return out.value

@@ -1060,8 +1060,14 @@ __global__ __launch_bounds__(kWG) void k_finalize(int stage, const double *__res
         const int slot = sc->hist_base + it - 1;
         sc->work_mask = sc->skip ? 0x3 : (sc->half ? 0x17 : 0x1f);
         if (sc->skip) {
+            // sigma breakdown: r is unchanged, the next iteration starts afresh from it
+            // (rhat = p = r), so the recurrence restarts from rho = ||r||^2 as after FIN_TRUE
             sc->skip = 0;
             sc->fresh = 1;
+            sc->rho = sc->rr;
+            sc->rhat2 = sc->rr;
+            sc->rho_prev = sc->alpha = sc->omega = 1.0;
+            sc->beta = 0.0;
             if (hist && slot < sc->hist_cap) hist[slot] = sc->last_rel;
             if (it >= sc->maxit) {
                 sc->done = 1;

@@ -130,6 +130,7 @@ struct eg_operator {
     int inner_maxit = 1000;     // iterations of one inner FP32 solve of the refinement
     int poll = 8;
     int stall_window = 20;
+    double eps_bd = 2.220446049250313e-16;   // breakdown threshold (relative cosine), 2^-52
     int precond = 0;            // plain modes: 0 T^{-1}, 1 red-black vertical-line SOR
     int sor_sweeps = 3;
     double sor_omega = 1.5;
@@ -295,7 +296,7 @@ int put_run_params(eg_operator *op, double tol, int maxit, int hist_base, int re
     Scalars h{};
     h.aux0 = tol;
     h.maxit = maxit;
-    h.eps_bd = 2.220446049250313e-16;
+    h.eps_bd = op->eps_bd;
     h.hist_base = hist_base;
     h.hist_cap = op->hist_cap;
     h.restart_every = restart_every;
@@ -1229,6 +1230,9 @@ int eg_set_option(eg_operator *op, const char *key, double value)
         op->gm_m = (int)value;
     } else if (k == "profile") {
         op->profile = value != 0.0;
+    } else if (k == "eps_bd") {
+        if (!(value >= 0.0 && value < 1.0)) return fail(EG_EINVAL, "eps_bd must be in [0, 1)");
+        op->eps_bd = value;
     } else if (k == "stall_window") {
         if (value < 1) return fail(EG_EINVAL, "stall_window must be >= 1");
         op->stall_window = (int)value;

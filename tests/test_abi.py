@@ -59,3 +59,66 @@ def test_modes_and_status_codes_match_header():
                       ("EG_ENONFINITE", eg.ENONFINITE), ("EG_ENOPC", eg.ENOPC)]:
         m = re.search(rf"\b{name}\s*=\s*(-?\d+)", src)
         assert m and int(m.group(1)) == val, name
+
+
+def _fake_operator(n_shape=(8, 6, 5)):
+    """An Operator object with its shape fields set and no library handle: enough to reach the
+    binding's argument checks, which must raise before any library call."""
+    import torch
+    import paper_1811_03852_amd as eg
+    op = eg.Operator.__new__(eg.Operator)
+    op.nlon, op.nlat, op.nlev = n_shape
+    op.n = n_shape[0] * n_shape[1] * n_shape[2]
+    op.device = torch.device("cuda", 0)
+    op._h = None
+    return op
+
+
+def test_binding_rejects_wrong_dtype_size_and_host_tensors():
+    """A float32 or short vector handed to a call that reads n doubles would make the library
+    read past the buffer: the binding checks dtype, length and placement first."""
+    import torch
+    import paper_1811_03852_amd as eg
+    op = _fake_operator()
+    n = op.n
+    good = torch.zeros(n, dtype=torch.float64)
+    with pytest.raises(ValueError, match="float64"):
+        op.solve(torch.zeros(n, dtype=torch.float32), good)
+    with pytest.raises(ValueError, match="elements"):
+        op.solve(good, torch.zeros(n - 1, dtype=torch.float64))
+    with pytest.raises(TypeError, match="CUDA"):
+        op.solve(good, good.clone())
+    with pytest.raises(ValueError, match="float32"):
+        op.apply(good, prec=eg.PREC_FP32)
+    with pytest.raises(ValueError, match="elements"):
+        op.precond(torch.zeros(2 * n, dtype=torch.float64))
+    with pytest.raises(ValueError, match="precision"):
+        op.apply(good, prec=7)
+    with pytest.raises(ValueError, match="contiguous"):
+        op.residual(torch.zeros(2 * n, dtype=torch.float64)[::2], good)
+    with pytest.raises(ValueError):
+        op.dot(torch.zeros(n, dtype=torch.float64), torch.zeros(n, dtype=torch.float32))
+    with pytest.raises(ValueError, match="nvec"):
+        op.harvest_krylov(good, 65)
+
+
+def test_binding_rejects_bad_training_sets():
+    """Training pairs must be float32 of shape (len(pair_op), n), every pair_op index must name
+    an operator, and all operators must share a grid."""
+    import torch
+    import paper_1811_03852_amd as eg
+    ops = [_fake_operator(), _fake_operator()]
+    n = ops[0].n
+    net = eg.Net.__new__(eg.Net)
+    net._h = None
+    r = torch.zeros((3, n), dtype=torch.float32)
+    with pytest.raises(ValueError, match="shape"):
+        net.train(ops, r, torch.zeros((2, n), dtype=torch.float32), [0, 1, 1], epochs=1)
+    with pytest.raises(ValueError, match="pair_op"):
+        net.train(ops, r, r, [0, 1, 2], epochs=1)
+    with pytest.raises(ValueError, match="float32"):
+        net.eval(ops, r.double(), r, [0, 0, 1])
+    with pytest.raises(ValueError, match="same grid"):
+        net.eval([ops[0], _fake_operator((8, 6, 4))], r, r, [0, 0, 1])
+    with pytest.raises(ValueError, match="elements"):
+        net.loss_grad(ops[0], torch.zeros(n + 1, dtype=torch.float32), torch.zeros(n, dtype=torch.float32))

@@ -71,6 +71,33 @@ def test_fp64_parity_shapes(eg, oracle_mod, p):
         assert err <= (1e-10 if p.shift >= 1e-3 else 1e-7), err
 
 
+@pytest.mark.parametrize("p", [synth.Problem(48, 24, 10, seed=7), synth.Problem(64, 32, 16, seed=3)],
+                         ids=lambda p: f"{p.nlon}x{p.nlat}x{p.nlev}")
+def test_breakdown_restarts_follow_oracle(eg, oracle_mod, p):
+    """A breakdown threshold of 1e-2 (option eps_bd; the cosine guards of Sec. 4) forces both
+    kinds of restart: after <rhat, r> and after <rhat, v> fall below it.  The GPU takes the same
+    restarts at the same iterations as the oracle, its residual history follows the oracle's and
+    x agrees (the restart after a <rhat, v> breakdown restarts the recurrence from ||r||^2)."""
+    import torch
+    coef = synth.make_coeffs(p)
+    b = synth.make_rhs(p).ravel()
+    x_ref, info_ref = oracle_mod.bicgstab(coef, b, tol=1e-10, eps_bd=1e-2)
+    assert info_ref.status == 0 and info_ref.sigma_restarts >= 1 and info_ref.rho_restarts >= 1
+    with eg.Operator(dev(coef)) as op:
+        op.set_option("eps_bd", 1e-2)
+        x = torch.zeros(p.n, dtype=torch.float64, device="cuda")
+        info = op.solve(dev(b), x, tol=1e-10, maxit=2000, mode=eg.FP64)
+        hist = op.history()
+    print(f"{p.nlon}x{p.nlat}x{p.nlev}: GPU {info.iterations} its {info.restarts} restarts, oracle "
+          f"{info_ref.iterations} its {info_ref.restarts} restarts ({info_ref.sigma_restarts} after <rhat, v>)")
+    assert info.status == eg.CONVERGED
+    assert info.iterations == info_ref.iterations and info.restarts == info_ref.restarts
+    dh = np.max(np.abs(hist - info_ref.history) / info_ref.history)
+    assert dh <= 1e-6, dh
+    err = np.linalg.norm(host(x) - x_ref) / np.linalg.norm(x_ref)
+    assert err <= 1e-8, err
+
+
 @pytest.mark.parametrize("mode_name", ["FP64", "FP32_IR", "FP32_IR_BF16", "FP32_IR_FP16"])
 def test_modes_reach_1e8_true_residual(eg, oracle_mod, small, mode_name):
     """Every precision mode reaches ||b - A x|| / ||b|| <= 1e-8, checked by the oracle's FP64

@@ -259,3 +259,24 @@ def test_dot_exact_on_integers(oracle_mod):
     a = rng.integers(-1000, 1000, 100000).astype(np.float64)
     b = rng.integers(-1000, 1000, 100000).astype(np.float64)
     assert oracle_mod.dot(a, b) == float(np.dot(a.astype(np.int64), b.astype(np.int64)))
+
+
+def test_bicgstab_breakdown_restarts_reach_dense_solution(oracle_mod):
+    """Breakdown guards of Sec. 4 forced with a threshold of 1e-2 on the relative cosines: the
+    iteration restarts once after <rhat, v> and once after <rhat, r> fell below it, and still
+    converges to the dense LU solution; up to the first restart it is bitwise the run with the
+    default threshold (the guard changes nothing until it fires)."""
+    prob = synth.Problem(24, 16, 10, seed=1)
+    coef = synth.make_coeffs(prob)
+    b = synth.make_rhs(prob).ravel()
+    x_ref = oracle_mod.dense_solve(coef, b)
+    x, info = oracle_mod.bicgstab(coef, b, tol=1e-12, eps_bd=1e-2)
+    assert info.status == 0 and info.sigma_restarts == 1 and info.rho_restarts == 1
+    assert info.restarts == 2
+    assert np.linalg.norm(x - x_ref) / np.linalg.norm(x_ref) <= 1e-10
+    _, plain = oracle_mod.bicgstab(coef, b, tol=1e-12)
+    assert plain.restarts == 0
+    h, hp = info.history, plain.history
+    m = min(h.size, hp.size)
+    first = int(np.argmax(h[:m] != hp[:m]))
+    assert first >= 1 and np.array_equal(h[:first], hp[:first])
