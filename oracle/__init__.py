@@ -20,18 +20,23 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liboracle.so")
+LIB_OMP_PATH = os.path.join(_HERE, "liboracle_omp.so")
 _SRC = os.path.join(_HERE, "oracle.c")
 _lib = None
+_lib_omp = None
 EPS_BD = 2.0 ** -52   # default breakdown threshold of BiCGStab (relative cosine)
 
 
 def build(force: bool = True) -> str:
-    """Compile ``oracle.c`` into ``liboracle.so`` (gcc, -O2, no FMA contraction)."""
-    if force or not os.path.exists(LIB_PATH):
-        tmp = LIB_PATH + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
-                               "-Wall", "-o", tmp, _SRC, "-lm"])
-        os.replace(tmp, LIB_PATH)
+    """Compile ``oracle.c`` into ``liboracle.so`` (gcc, -O2, no FMA contraction, one thread) and
+    into ``liboracle_omp.so`` (the same source with OpenMP: grid loops shared among threads,
+    inner products over a fixed partition, see the source's header)."""
+    for path, extra in ((LIB_PATH, []), (LIB_OMP_PATH, ["-fopenmp", "-DORC_OPENMP"])):
+        if force or not os.path.exists(path):
+            tmp = path + ".tmp"
+            subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
+                                   "-Wall", *extra, "-o", tmp, _SRC, "-lm"])
+            os.replace(tmp, path)
     return LIB_PATH
 
 
@@ -55,12 +60,14 @@ class SolveInfo:
     rho_restarts: int = 0
 
 
-def _load():
-    global _lib
-    if _lib is None:
-        if not os.path.exists(LIB_PATH) or os.path.getmtime(LIB_PATH) < os.path.getmtime(_SRC):
+def _load(parallel: bool = False):
+    """The single-threaded oracle library, or (``parallel``) its OpenMP build."""
+    global _lib, _lib_omp
+    if (_lib_omp if parallel else _lib) is None:
+        path = LIB_OMP_PATH if parallel else LIB_PATH
+        if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_SRC):
             build()
-        lib = ctypes.CDLL(LIB_PATH)
+        lib = ctypes.CDLL(path)
         dp = ctypes.POINTER(ctypes.c_double)
         lib.orc_apply.argtypes = [ctypes.c_int] * 3 + [dp, dp, dp]
         lib.orc_apply_points.argtypes = [ctypes.c_int] * 3 + [dp, dp, ctypes.POINTER(ctypes.c_long), ctypes.c_long, dp]
@@ -77,8 +84,11 @@ def _load():
                                                              ctypes.c_int, ctypes.POINTER(_Info)]
         lib.orc_bicgstab_sor.restype = ctypes.c_int
         lib.orc_set_eps_bd.argtypes = [ctypes.c_double]
-        _lib = lib
-    return _lib
+        if parallel:
+            _lib_omp = lib
+        else:
+            _lib = lib
+    return _lib_omp if parallel else _lib
 
 
 def _dp(a: np.ndarray):
@@ -96,12 +106,12 @@ def _vec(v: np.ndarray, n: int) -> np.ndarray:
     return v
 
 
-def apply(coef: np.ndarray, x: np.ndarray) -> np.ndarray:
-    """y = A x (plain row definition)."""
+def apply(coef: np.ndarray, x: np.ndarray, parallel: bool = False) -> np.ndarray:
+    """y = A x (plain row definition); ``parallel``: the OpenMP build (bitwise the same)."""
     nlon, nlat, nlev = _check(coef)
     x = _vec(x, nlon * nlat * nlev)
     y = np.empty_like(x)
-    _load().orc_apply(nlon, nlat, nlev, _dp(coef), _dp(x), _dp(y))
+    _load(parallel).orc_apply(nlon, nlat, nlev, _dp(coef), _dp(x), _dp(y))
     return y
 
 
@@ -116,19 +126,21 @@ def apply_points(coef: np.ndarray, x: np.ndarray, idx: np.ndarray) -> np.ndarray
     return y
 
 
-def thomas(coef: np.ndarray, q: np.ndarray) -> np.ndarray:
-    """z = T^{-1} q, T = tridiag(-aD, C, -aU) per column."""
+def thomas(coef: np.ndarray, q: np.ndarray, parallel: bool = False) -> np.ndarray:
+    """z = T^{-1} q, T = tridiag(-aD, C, -aU) per column; ``parallel``: the OpenMP build
+    (bitwise the same)."""
     nlon, nlat, nlev = _check(coef)
     q = _vec(q, nlon * nlat * nlev)
     z = np.empty_like(q)
-    _load().orc_thomas(nlon, nlat, nlev, _dp(coef), _dp(q), _dp(z))
+    _load(parallel).orc_thomas(nlon, nlat, nlev, _dp(coef), _dp(q), _dp(z))
     return z
 
 
-def dot(a: np.ndarray, b: np.ndarray) -> float:
+def dot(a: np.ndarray, b: np.ndarray, parallel: bool = False) -> float:
+    """<a, b>, summed left to right (``parallel``: over the fixed partition of the OpenMP build)."""
     a = np.ascontiguousarray(a, dtype=np.float64).ravel()
     b = np.ascontiguousarray(b, dtype=np.float64).ravel()
-    return _load().orc_dot(a.size, _dp(a), _dp(b))
+    return _load(parallel).orc_dot(a.size, _dp(a), _dp(b))
 
 
 def rbsor(coef: np.ndarray, q: np.ndarray, sweeps: int = 3, omega: float = 1.5, half_sweeps: int | None = None):
@@ -154,10 +166,12 @@ def lexsor(coef: np.ndarray, q: np.ndarray, sweeps: int = 3, omega: float = 1.5)
 def bicgstab(coef: np.ndarray, b: np.ndarray, x0: np.ndarray | None = None, tol: float = 1e-8,
              maxit: int = 20000, restart_every: int = 0, precond: int = 1,
              hist_cap: int | None = None, sor_sweeps: int = 3, sor_omega: float = 1.5,
-             eps_bd: float = EPS_BD) -> tuple[np.ndarray, SolveInfo]:
+             eps_bd: float = EPS_BD, parallel: bool = False) -> tuple[np.ndarray, SolveInfo]:
     """Right-preconditioned BiCGStab; precond 1 = vertical tridiagonal, 0 = identity,
     2 = red-black line SOR, 3 = lexicographic line SOR, with ``sor_sweeps`` sweeps and
-    relaxation ``sor_omega``; ``eps_bd`` is the breakdown threshold (relative cosine)."""
+    relaxation ``sor_omega``; ``eps_bd`` is the breakdown threshold (relative cosine).
+    ``parallel`` runs the OpenMP build (all host threads; fixed-partition inner products)."""
+    lib = _load(parallel)
     nlon, nlat, nlev = _check(coef)
     n = nlon * nlat * nlev
     b = _vec(b, n)
@@ -165,14 +179,14 @@ def bicgstab(coef: np.ndarray, b: np.ndarray, x0: np.ndarray | None = None, tol:
     cap = maxit if hist_cap is None else hist_cap
     hist = np.full(max(cap, 1), np.nan)
     info = _Info()
-    _load().orc_set_eps_bd(float(eps_bd))
+    lib.orc_set_eps_bd(float(eps_bd))
     if precond in (2, 3):
-        _load().orc_bicgstab_sor(nlon, nlat, nlev, _dp(coef), _dp(b), _dp(x), tol, maxit, restart_every, precond,
-                                 int(sor_sweeps), float(sor_omega), _dp(hist), cap, ctypes.byref(info))
+        lib.orc_bicgstab_sor(nlon, nlat, nlev, _dp(coef), _dp(b), _dp(x), tol, maxit, restart_every, precond,
+                             int(sor_sweeps), float(sor_omega), _dp(hist), cap, ctypes.byref(info))
     else:
-        _load().orc_bicgstab(nlon, nlat, nlev, _dp(coef), _dp(b), _dp(x), tol, maxit, restart_every, precond,
-                             _dp(hist), cap, ctypes.byref(info))
-    _load().orc_set_eps_bd(EPS_BD)
+        lib.orc_bicgstab(nlon, nlat, nlev, _dp(coef), _dp(b), _dp(x), tol, maxit, restart_every, precond,
+                         _dp(hist), cap, ctypes.byref(info))
+    lib.orc_set_eps_bd(EPS_BD)
     h = hist[:min(info.iterations, cap)].copy()
     return x, SolveInfo(info.iterations, info.restarts, info.status, info.half_step_exit, info.rel_residual,
                         info.true_rel_residual, h, info.sigma_restarts, info.rho_restarts)

@@ -23,6 +23,9 @@ With ``bf16=True`` the weights, the input channels, the hidden activations and t
 gradients are rounded to BF16 (round to nearest even) at the points where the GPU kernels
 store them in BF16; all arithmetic is FP64.  With ``bf16=False`` the function is plain FP64
 and is pinned by central finite differences in the tests.
+
+``adam_step`` is the optimiser the training uses (Kingma & Ba 2015, Algorithm 1) in FP64, pinned
+by a hand-worked two-step example and by its closed form under a constant gradient.
 """
 from __future__ import annotations
 
@@ -209,6 +212,31 @@ def loss_and_grad(theta, coef, r, e, bf16_round: bool = True, kind: int = LOSS_E
     G["b1"] = g_z1.sum(axis=(0, 1, 2))
     G["W1"] = np.stack([np.einsum("kjio,kjic->oc", g_z1, _shift_v(c["x0"], _vtap(t))) for t in range(TAPS_V)])
     return L, pack(G)
+
+
+class AdamState:
+    """Optimiser state of ``adam_step``: first and second moment estimates and the step count."""
+
+    def __init__(self, size: int):
+        self.m = np.zeros(size)
+        self.v = np.zeros(size)
+        self.t = 0
+
+
+def adam_step(theta: np.ndarray, grad: np.ndarray, state: AdamState, lr: float, beta1: float = 0.9,
+              beta2: float = 0.999, eps: float = 1e-8) -> np.ndarray:
+    """One Adam update in FP64 (Kingma & Ba, ICLR 2015, Algorithm 1): exponential moving
+    averages of the gradient and of its square, each divided by one minus its decay rate to
+    the power t (the bias correction of the zero start), then a step of lr along the ratio of
+    the corrected first moment to the square root of the corrected second moment plus eps.
+    Updates ``state`` in place and returns the new parameters."""
+    g = np.asarray(grad, dtype=np.float64)
+    state.t += 1
+    state.m = beta1 * state.m + (1.0 - beta1) * g
+    state.v = beta2 * state.v + (1.0 - beta2) * (g * g)
+    m_hat = state.m / (1.0 - beta1 ** state.t)
+    v_hat = state.v / (1.0 - beta2 ** state.t)
+    return np.asarray(theta, dtype=np.float64) - lr * m_hat / (np.sqrt(v_hat) + eps)
 
 
 def init_theta(seed: int) -> np.ndarray:

@@ -40,6 +40,26 @@
 #include <stdlib.h>
 #include <string.h>
 
+/* Multi-threaded build (-fopenmp -DORC_OPENMP, liboracle_omp.so): the same arithmetic with the
+ * grid loops shared among threads.  Every loop writes disjoint elements, so each result is
+ * bitwise the single-threaded one, except the inner products, which add the partial sums of a
+ * fixed partition into ORC_DOT_BLOCKS contiguous blocks (each left to right, then the block
+ * sums left to right): deterministic for any thread count, but summed in another order than
+ * the single-threaded build. */
+#ifdef ORC_OPENMP
+#include <omp.h>
+#define ORC_PARFOR _Pragma("omp parallel for schedule(static)")
+#define ORC_PARFOR2 _Pragma("omp parallel for collapse(2) schedule(static)")
+#define ORC_PARALLEL _Pragma("omp parallel")
+#define ORC_FOR _Pragma("omp for schedule(static)")
+#else
+#define ORC_PARFOR
+#define ORC_PARFOR2
+#define ORC_PARALLEL
+#define ORC_FOR
+#endif
+#define ORC_DOT_BLOCKS 256
+
 #define ORC_W 0
 #define ORC_E 1
 #define ORC_S 2
@@ -67,6 +87,7 @@ void orc_apply(int nlon, int nlat, int nlev, const double *coef, const double *x
     const double *aW = coef + ORC_W * n, *aE = coef + ORC_E * n, *aS = coef + ORC_S * n;
     const double *aN = coef + ORC_N * n, *aD = coef + ORC_D * n, *aU = coef + ORC_U * n;
     const double *C = coef + ORC_C * n;
+    ORC_PARFOR2
     for (int k = 0; k < nlev; ++k)
         for (int j = 0; j < nlat; ++j)
             for (int i = 0; i < nlon; ++i) {
@@ -119,25 +140,62 @@ void orc_thomas(int nlon, int nlat, int nlev, const double *coef, const double *
     const long P = (long)nlon * nlat;
     const long n = P * nlev;
     const double *aD = coef + ORC_D * n, *aU = coef + ORC_U * n, *C = coef + ORC_C * n;
-    double *cp = (double *)malloc(sizeof(double) * (size_t)nlev);
-    double *yy = (double *)malloc(sizeof(double) * (size_t)nlev);
-    for (long col = 0; col < P; ++col) {
-        /* forward elimination: T = L U with unit-upper U having superdiagonal cp */
-        cp[0] = -aU[col] / C[col];
-        yy[0] = q[col] / C[col];
-        for (int k = 1; k < nlev; ++k) {
-            long c = col + k * P;
-            double den = C[c] - (-aD[c]) * cp[k - 1];
-            cp[k] = -aU[c] / den;
-            yy[k] = (q[c] - (-aD[c]) * yy[k - 1]) / den;
+#ifdef ORC_OPENMP
+    /* the same recurrences for blocks of ORC_TB adjacent columns at a time, level by level,
+     * so that each level of a block is one contiguous run of memory */
+#define ORC_TB 64
+#pragma omp parallel
+    {
+        double *cp = (double *)malloc(sizeof(double) * (size_t)nlev * ORC_TB);
+        double *yy = (double *)malloc(sizeof(double) * (size_t)nlev * ORC_TB);
+#pragma omp for schedule(static)
+        for (long c0 = 0; c0 < P; c0 += ORC_TB) {
+            const int nb = (int)(P - c0 < ORC_TB ? P - c0 : ORC_TB);
+            for (int m = 0; m < nb; ++m) {
+                const long col = c0 + m;
+                cp[m] = -aU[col] / C[col];
+                yy[m] = q[col] / C[col];
+            }
+            for (int k = 1; k < nlev; ++k)
+                for (int m = 0; m < nb; ++m) {
+                    const long c = c0 + m + k * P;
+                    const double den = C[c] - (-aD[c]) * cp[(k - 1) * ORC_TB + m];
+                    cp[k * ORC_TB + m] = -aU[c] / den;
+                    yy[k * ORC_TB + m] = (q[c] - (-aD[c]) * yy[(k - 1) * ORC_TB + m]) / den;
+                }
+            for (int m = 0; m < nb; ++m) z[c0 + m + (long)(nlev - 1) * P] = yy[(nlev - 1) * ORC_TB + m];
+            for (int k = nlev - 2; k >= 0; --k)
+                for (int m = 0; m < nb; ++m)
+                    z[c0 + m + k * P] = yy[k * ORC_TB + m] - cp[k * ORC_TB + m] * z[c0 + m + (k + 1) * P];
         }
-        /* back substitution */
-        z[col + (long)(nlev - 1) * P] = yy[nlev - 1];
-        for (int k = nlev - 2; k >= 0; --k)
-            z[col + k * P] = yy[k] - cp[k] * z[col + (k + 1) * P];
+        free(cp);
+        free(yy);
     }
-    free(cp);
-    free(yy);
+    return;
+#endif
+    ORC_PARALLEL
+    {
+        double *cp = (double *)malloc(sizeof(double) * (size_t)nlev);
+        double *yy = (double *)malloc(sizeof(double) * (size_t)nlev);
+        ORC_FOR
+        for (long col = 0; col < P; ++col) {
+            /* forward elimination: T = L U with unit-upper U having superdiagonal cp */
+            cp[0] = -aU[col] / C[col];
+            yy[0] = q[col] / C[col];
+            for (int k = 1; k < nlev; ++k) {
+                long c = col + k * P;
+                double den = C[c] - (-aD[c]) * cp[k - 1];
+                cp[k] = -aU[c] / den;
+                yy[k] = (q[c] - (-aD[c]) * yy[k - 1]) / den;
+            }
+            /* back substitution */
+            z[col + (long)(nlev - 1) * P] = yy[nlev - 1];
+            for (int k = nlev - 2; k >= 0; --k)
+                z[col + k * P] = yy[k] - cp[k] * z[col + (k + 1) * P];
+        }
+        free(cp);
+        free(yy);
+    }
 }
 
 /*
@@ -264,21 +322,35 @@ void orc_lexsor(int nlon, int nlat, int nlev, const double *coef, const double *
 
 double orc_dot(long n, const double *a, const double *b)
 {
+#ifdef ORC_OPENMP
+    double part[ORC_DOT_BLOCKS];
+    ORC_PARFOR
+    for (int blk = 0; blk < ORC_DOT_BLOCKS; ++blk) {
+        const long lo = n * blk / ORC_DOT_BLOCKS, hi = n * (blk + 1) / ORC_DOT_BLOCKS;
+        double s = 0.0;
+        for (long i = lo; i < hi; ++i) s = s + a[i] * b[i];
+        part[blk] = s;
+    }
+    double s = 0.0;
+    for (int blk = 0; blk < ORC_DOT_BLOCKS; ++blk) s = s + part[blk];
+    return s;
+#else
     double s = 0.0;
     for (long i = 0; i < n; ++i) s = s + a[i] * b[i];
     return s;
+#endif
 }
 
 static double nrm2(long n, const double *a) { return sqrt(orc_dot(n, a, a)); }
 
-/* preconditioner choice of orc_bicgstab: 0 = identity, 1 = vertical tridiagonal (T^{-1}),
- * 2 = red-black line SOR (orc_rbsor), 3 = lexicographic line SOR (orc_lexsor), both with
- * sor_sweeps sweeps and relaxation sor_omega (orc_bicgstab_sor) */
 /* Breakdown threshold of BiCGStab (relative cosine), 2^-52 unless a test sets another to force
  * the restart paths. */
 static double g_eps_bd = 2.220446049250313e-16;
 void orc_set_eps_bd(double eps) { g_eps_bd = eps; }
 
+/* preconditioner choice of orc_bicgstab: 0 = identity, 1 = vertical tridiagonal (T^{-1}),
+ * 2 = red-black line SOR (orc_rbsor), 3 = lexicographic line SOR (orc_lexsor), both with
+ * sor_sweeps sweeps and relaxation sor_omega (orc_bicgstab_sor) */
 static int g_sor_sweeps = 3;
 static double g_sor_omega = 1.5;
 
@@ -346,6 +418,7 @@ int orc_bicgstab(int nlon, int nlat, int nlev, const double *coef, const double 
 
     /* r = b - A x */
     orc_apply(nlon, nlat, nlev, coef, x, r);
+    ORC_PARFOR
     for (long i = 0; i < n; ++i) r[i] = b[i] - r[i];
     double rnorm = nrm2(n, r);
     info->rel_residual = rnorm / nb;
@@ -382,6 +455,7 @@ int orc_bicgstab(int nlon, int nlat, int nlev, const double *coef, const double 
             info->rho_restarts++;
         }
         double beta = (rho / rho_prev) * (alpha / omega);
+        ORC_PARFOR
         for (long i = 0; i < n; ++i) p[i] = r[i] + beta * (p[i] - omega * v[i]);
         apply_m(precond, nlon, nlat, nlev, coef, p, ph, n);
         orc_apply(nlon, nlat, nlev, coef, ph, v);
@@ -394,9 +468,11 @@ int orc_bicgstab(int nlon, int nlat, int nlev, const double *coef, const double 
             continue;
         }
         alpha = rho / sigma;
+        ORC_PARFOR
         for (long i = 0; i < n; ++i) s[i] = r[i] - alpha * v[i];
         double snorm = nrm2(n, s);
         if (snorm / nb <= tol) {
+            ORC_PARFOR
             for (long i = 0; i < n; ++i) x[i] = x[i] + alpha * ph[i];
             info->rel_residual = snorm / nb;
             if (hist && it <= hist_cap) hist[it - 1] = snorm / nb;
@@ -409,6 +485,7 @@ int orc_bicgstab(int nlon, int nlat, int nlev, const double *coef, const double 
             double ts = orc_dot(n, t, s);
             if (tt == 0.0 || ts == 0.0) {
                 /* omega would be zero or undefined: keep the half step and restart */
+                ORC_PARFOR
                 for (long i = 0; i < n; ++i) x[i] = x[i] + alpha * ph[i];
                 memcpy(r, s, sizeof(double) * (size_t)n);
                 rnorm = snorm;
@@ -418,7 +495,9 @@ int orc_bicgstab(int nlon, int nlat, int nlev, const double *coef, const double 
                 continue;
             }
             omega = ts / tt;
+            ORC_PARFOR
             for (long i = 0; i < n; ++i) x[i] = x[i] + alpha * ph[i] + omega * sh[i];
+            ORC_PARFOR
             for (long i = 0; i < n; ++i) r[i] = s[i] - omega * t[i];
             rho_prev = rho;
             rnorm = nrm2(n, r);
@@ -430,6 +509,7 @@ int orc_bicgstab(int nlon, int nlat, int nlev, const double *coef, const double 
         if (info->status == 0) {
             /* residual-gap check on the true residual */
             orc_apply(nlon, nlat, nlev, coef, x, t);
+            ORC_PARFOR
             for (long i = 0; i < n; ++i) r[i] = b[i] - t[i];
             rnorm = nrm2(n, r);
             info->true_rel_residual = rnorm / nb;
@@ -447,6 +527,7 @@ int orc_bicgstab(int nlon, int nlat, int nlev, const double *coef, const double 
         }
         if (restart_every > 0 && it % restart_every == 0) {
             orc_apply(nlon, nlat, nlev, coef, x, t);
+            ORC_PARFOR
             for (long i = 0; i < n; ++i) r[i] = b[i] - t[i];
             rnorm = nrm2(n, r);
             info->restarts++;
@@ -456,6 +537,7 @@ int orc_bicgstab(int nlon, int nlat, int nlev, const double *coef, const double 
     if (info->status != 0) {
         /* iteration limit: report the true residual of the returned x */
         orc_apply(nlon, nlat, nlev, coef, x, t);
+        ORC_PARFOR
         for (long i = 0; i < n; ++i) r[i] = b[i] - t[i];
         info->true_rel_residual = nrm2(n, r) / nb;
     }

@@ -164,7 +164,7 @@ def test_all_modes_reach_1e8_true_residual(eg, oracle_mod, n1280):
     bd = torch.from_numpy(b).cuda()
     nb = np.linalg.norm(b)
     sols = {}
-    for name in ("FP64", "FP32_IR", "FP32_IR_BF16"):
+    for name in ("FP64", "FP32_IR", "FP32_IR_BF16", "FP32_IR_FP16"):
         x = torch.zeros(p.n, dtype=torch.float64, device="cuda")
         print(f"[fullsize] solving {name}", flush=True)
         info = op.solve(bd, x, 1e-8, 20000, getattr(eg, name))
@@ -176,10 +176,12 @@ def test_all_modes_reach_1e8_true_residual(eg, oracle_mod, n1280):
         assert abs(rel - info.true_rel_residual) <= 1e-6 * rel
         sols[name] = xh
     ref = sols["FP64"]
-    for name in ("FP32_IR", "FP32_IR_BF16"):
+    for name in ("FP32_IR", "FP32_IR_BF16", "FP32_IR_FP16"):
         d = np.linalg.norm(sols[name] - ref) / np.linalg.norm(ref)
         print(f"{name} vs FP64: rel L2 {d:.2e}")
-        assert d <= 1e-4   # two solutions with R <= 1e-8 each, cond(A) ~ 1e3 at shift 1e-3
+        # two solutions with R <= 1e-8 each could differ by up to cond(A) 1e-8 ~ 1e-5 at shift
+        # 1e-3; they agree to about 1e-7
+        assert d <= 1e-6
 
 
 def _quick_net(eg):
@@ -245,6 +247,45 @@ def test_manufactured_solution_640x480x70(eg, oracle_mod):
             assert info.status == eg.CONVERGED and rel <= 1e-8 * (1 + 1e-6) and fwd <= 1e-5
 
 
+def test_fp64_parity_and_mode_errors_640x480x70(eg, oracle_mod):
+    """The 640x480x70 manufactured problem (b = A x*): the oracle (its OpenMP build, fixed
+    partition sums) and the GPU both solve in FP64 to tol 1e-12 and x agrees to 1e-10; then
+    every mode solves to tol 1e-8 and reports its error against that oracle solution (the
+    forward error expected of R <= 1e-8 at cond(A) ~ 1e3 is at most about 1e-5)."""
+    import time
+    import torch
+    p = synth.CONFIGS["manufactured_640x480x70"]
+    coef = synth.make_coeffs(p, threads=16)
+    xs = synth.make_xstar(p).ravel()
+    b = oracle_mod.apply(coef, xs, parallel=True)
+    t0 = time.perf_counter()
+    print("[fullsize] 640x480x70 oracle solve to 1e-12 (OpenMP)", flush=True)
+    x_or, info_or = oracle_mod.bicgstab(coef, b, tol=1e-12, parallel=True)
+    print(f"oracle: {info_or.iterations} its, true R {info_or.true_rel_residual:.2e}, "
+          f"{time.perf_counter() - t0:.1f} s", flush=True)
+    assert info_or.status == 0
+    nx = np.linalg.norm(x_or)
+    with eg.Operator(torch.from_numpy(coef).cuda()) as op:
+        bd = torch.from_numpy(b).cuda()
+        x = torch.zeros(p.n, dtype=torch.float64, device="cuda")
+        info = op.solve(bd, x, 1e-12, 20000, eg.FP64)
+        err = np.linalg.norm(host(x) - x_or) / nx
+        print(f"FP64 tol 1e-12: {info.iterations} its (oracle {info_or.iterations}), error vs oracle {err:.2e}")
+        assert info.status == eg.CONVERGED and err <= 1e-10
+        for name in ("FP64", "FP32_IR", "FP32_IR_BF16", "FP32_IR_FP16"):
+            for pc in (0, 1):
+                op.set_option("precond", pc)
+                x.zero_()
+                info = op.solve(bd, x, 1e-8, 20000, getattr(eg, name))
+                xh = host(x)
+                rel = np.linalg.norm(b - oracle_mod.apply(coef, xh, parallel=True)) / np.linalg.norm(b)
+                err = np.linalg.norm(xh - x_or) / nx
+                print(f"{name}{' + line SOR' if pc else ''} tol 1e-8: {info.iterations} its, {info.outer_steps} outer, "
+                      f"true R {rel:.2e}, error vs FP64 oracle {err:.2e}")
+                assert info.status == eg.CONVERGED and rel <= 1e-8 * (1 + 1e-6) and err <= 1e-5
+        op.set_option("precond", 0)
+
+
 @pytest.fixture(scope="module")
 def stress():
     """The stress case on the host: 1280x960x140, shift 1e-6, vertical diffusivity contrast 1e4."""
@@ -286,7 +327,9 @@ def test_stress_case_1280x960x140(eg, oracle_mod, stress):
     for name in ("FP32_IR", "FP32_IR+SOR"):
         d = np.linalg.norm(sols[name] - ref) / np.linalg.norm(ref)
         print(f"{name} vs FP64+SOR: rel L2 {d:.2e}")
-        assert d <= 1e-1   # shift 1e-6: cond(A) ~ 1e6, two solutions with R <= 1e-8 each
+        # shift 1e-6: cond(A) ~ 1e6 would allow 1e-2 between two solutions with R <= 1e-8 each;
+        # they agree to about 1e-7
+        assert d <= 1e-6
 
 
 def test_stress_case_learned_1280x960x140(eg, oracle_mod, stress):
@@ -347,7 +390,7 @@ def test_network_sampled_columns_640x480x70(eg, oracle_mod):
         den += float(np.sum(col ** 2))
     err = np.sqrt(num / den)
     print(f"network at 640x480x70, {len(samples)} sampled columns: delta rel L2 {err:.2e}")
-    assert err <= 1e-2
+    assert err <= 2e-3
 
 
 def test_learned_preconditioner_640x480x70(eg, oracle_mod):

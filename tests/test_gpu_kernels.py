@@ -4,7 +4,8 @@ import numpy as np
 import pytest
 
 import synth
-from tests.helpers import EPS32, EPS64, abs_bound, dev, host, quantized_coeffs
+from oracle.quant import quantized_coeffs
+from tests.helpers import EPS32, EPS64, abs_bound, dev, host
 
 pytestmark = pytest.mark.gpu
 

@@ -54,9 +54,13 @@ def test_forward_matches_oracle(eg, p):
         z = host(net.apply(op, dev(q), delta)).astype(np.float64)
     d_ref, _ = onet.forward(th, coef, q.astype(np.float64), bf16_round=True)
     z_ref = onet.apply(th, coef, q.astype(np.float64), bf16_round=True)
-    e_d, e_z = _rel(host(delta).astype(np.float64), d_ref), _rel(z, z_ref)
-    print(f"forward parity: delta rel L2 {e_d:.2e}, M(q) rel L2 {e_z:.2e}")
-    assert e_d <= 1e-2 and e_z <= 1e-3
+    dg = host(delta).astype(np.float64)
+    e_d, e_z = _rel(dg, d_ref), _rel(z, z_ref)
+    # per level, against the level-average size of delta: an error confined to a few levels
+    # (a column chunk's boundary levels, say) shows here even when the total is small
+    per_level = np.linalg.norm((dg - d_ref).reshape(p.nlev, -1), axis=1) / (np.linalg.norm(d_ref) / np.sqrt(p.nlev))
+    print(f"forward parity: delta rel L2 {e_d:.2e} (worst level {per_level.max():.2e}), M(q) rel L2 {e_z:.2e}")
+    assert e_d <= 2e-3 and per_level.max() <= 5e-3 and e_z <= 1e-3
     net.close()
 
 
@@ -86,8 +90,100 @@ def test_gradients_match_oracle(eg, kind, shape):
         err = _rel(G[name].ravel(), Gr[name].ravel())
         print(f"grad {name}: rel L2 {err:.2e}")
         worst = max(worst, err)
-    assert worst <= 2e-2
+    assert worst <= 5e-3
     net.close()
+
+
+@pytest.mark.parametrize("kind", [onet.LOSS_ERROR, onet.LOSS_RESIDUAL])
+def test_training_steps_match_oracle_adam(eg, kind):
+    """eg_net_train from known weights: two pairs in one batch of two, two epochs, so two Adam
+    steps on the mean gradient of the pairs.  The oracle takes the same two steps with its FP64
+    gradient (loss_and_grad) and its Adam (adam_step, Kingma & Ba's Algorithm 1); the updates
+    theta_2 - theta_0 agree element by element wherever the gradient is well above the BF16
+    gradient error, and are bounded by the Adam step size everywhere else."""
+    import torch
+    p = synth.Problem(24, 12, 9, seed=6)
+    coef = synth.make_coeffs(p)
+    th0 = _theta(7)
+    rng = np.random.default_rng(12)
+    r = rng.standard_normal((2, p.n)).astype(np.float32)
+    e = rng.standard_normal((2, p.n)).astype(np.float32)
+    lr = 1e-2
+    net = eg.Net(0)
+    net.set_weights(th0.astype(np.float32))
+    net.set_loss(kind)
+    with eg.Operator(dev(coef)) as op:
+        net.train([op], dev(r), dev(e), [0, 0], epochs=2, batch=2, lr=lr, seed=0)
+        th2_gpu = net.get_weights().astype(np.float64)
+    net.close()
+    st = onet.AdamState(th0.size)
+    th, grads = th0, []
+    for _ in range(2):
+        gs = [onet.loss_and_grad(th, coef, r[i].astype(np.float64), e[i].astype(np.float64), bf16_round=True,
+                                 kind=kind)[1] for i in range(2)]
+        g = 0.5 * (gs[0] + gs[1])
+        grads.append(g)
+        th = onet.adam_step(th, g, st, lr)
+    u_ref, u_gpu = th - th0, th2_gpu - th0
+    # a parameter is well determined when both of its gradients stand 25x above the noise of the
+    # BF16 gradient (relative L2 error per tensor about 2e-4, so 2e-4 of the tensor's rms)
+    ok = np.ones(th0.size, dtype=bool)
+    o = 0
+    for _, shape in onet.SHAPES:
+        size = int(np.prod(shape))
+        for g in grads:
+            seg = g[o:o + size]
+            ok[o:o + size] &= np.abs(seg) > 5e-3 * np.sqrt(np.mean(seg * seg))
+        o += size
+    dev_ok = np.max(np.abs(u_gpu[ok] - u_ref[ok]))
+    rel_ok = np.linalg.norm(u_gpu[ok] - u_ref[ok]) / np.linalg.norm(u_ref[ok])
+    print(f"Adam steps: {ok.mean():.1%} of parameters well determined, there max |du| {dev_ok / lr:.2e} lr, "
+          f"rel L2 {rel_ok:.2e}; max |u| {np.max(np.abs(u_gpu)) / lr:.3f} lr")
+    assert ok.mean() >= 0.65
+    # a wrong bias correction, swapped decay rates or a wrong batch mean move these by O(lr)
+    assert dev_ok <= 5e-2 * lr and rel_ok <= 1e-2, (dev_ok, rel_ok)
+    # two Adam steps move no parameter by more than about 2 lr
+    assert np.max(np.abs(u_gpu)) <= 2.05 * lr
+
+
+def test_flexible_bicgstab_follows_oracle(eg, oracle_mod):
+    """EG_LEARNED_FP64 with flexible BiCGStab (learned_method 0) against the oracle's flexible
+    BiCGStab (oracle/krylov.bicgstab_flex) driven by the oracle's network (oracle/net.apply,
+    BF16 rounding where the GPU stores BF16) with the same stall fallback to T^{-1}.  This random
+    network makes both stall and fall back once; until then the residual histories agree to the
+    network's BF16 rounding, the iteration counts agree closely, x agrees to the tolerance's
+    conditioning, and the GPU's recursive residual is its true one (x advanced along exactly the
+    preconditioned vectors that entered A)."""
+    import torch
+    from oracle import krylov
+    p = synth.Problem(48, 24, 10, seed=7)
+    coef = synth.make_coeffs(p)
+    b = synth.make_rhs(p).ravel()
+    th = _theta(4, 0.3)
+    x_or, ref = krylov.bicgstab_flex(coef, b, lambda q: onet.apply(th, coef, q, bf16_round=True), tol=1e-10,
+                                     fallback=lambda q: oracle_mod.thomas(coef, q), stall_window=20)
+    assert ref.status == 0
+    net = eg.Net(0)
+    net.set_weights(th.astype(np.float32))
+    with eg.Operator(dev(coef)) as op:
+        op.attach(net)
+        op.set_option("learned_method", 0)
+        op.set_option("stall_window", 20)
+        x = torch.zeros(p.n, dtype=torch.float64, device="cuda")
+        info = op.solve(dev(b), x, 1e-10, 5000, eg.LEARNED_FP64)
+        h = op.history()
+    net.close()
+    xh = host(x)
+    k = min(10, len(h), len(ref.history))
+    dh = np.abs(h[:k] - ref.history[:k]) / ref.history[:k]
+    err = np.linalg.norm(xh - x_or) / np.linalg.norm(x_or)
+    print(f"flexible BiCGStab: GPU {info.iterations} its {info.fallbacks} fallbacks, oracle {ref.iterations} its "
+          f"{ref.fallbacks} fallbacks; first {k} history entries agree to {dh.max():.2e}; x error {err:.2e}")
+    assert info.status == eg.CONVERGED and info.fallbacks == ref.fallbacks
+    assert abs(info.iterations - ref.iterations) <= max(3, ref.iterations // 10)
+    assert dh.max() <= 1e-2
+    assert err <= 1e-8
+    assert abs(info.true_rel_residual - h[-1]) <= 1e-12
 
 
 def test_zero_output_layer_reproduces_plain_solver_bitwise(eg):

@@ -5,7 +5,8 @@ import numpy as np
 import pytest
 
 import synth
-from tests.helpers import dev, host, quantized_coeffs
+from oracle.quant import quantized_coeffs
+from tests.helpers import dev, host
 
 pytestmark = pytest.mark.gpu
 

@@ -280,3 +280,23 @@ def test_bicgstab_breakdown_restarts_reach_dense_solution(oracle_mod):
     m = min(h.size, hp.size)
     first = int(np.argmax(h[:m] != hp[:m]))
     assert first >= 1 and np.array_equal(h[:first], hp[:first])
+
+
+def test_openmp_build_agrees_with_single_thread(oracle_mod):
+    """The OpenMP build of the same source: SpMV and tridiagonal solve bitwise equal to the
+    single-threaded build, inner products equal up to summation order, and the whole solve at
+    tol 1e-12 within 1e-11 of the single-threaded oracle."""
+    prob = synth.CONFIGS["small_96x72x20"]
+    coef = synth.make_coeffs(prob)
+    b = synth.make_rhs(prob).ravel()
+    assert np.array_equal(oracle_mod.apply(coef, b), oracle_mod.apply(coef, b, parallel=True))
+    assert np.array_equal(oracle_mod.thomas(coef, b), oracle_mod.thomas(coef, b, parallel=True))
+    d1, d2 = oracle_mod.dot(b, b), oracle_mod.dot(b, b, parallel=True)
+    assert abs(d1 - d2) <= 1e-14 * d1
+    rng = np.random.default_rng(1)
+    ia = rng.integers(-1000, 1000, 100003).astype(np.float64)
+    assert oracle_mod.dot(ia, ia, parallel=True) == float(np.dot(ia.astype(np.int64), ia.astype(np.int64)))
+    x1, i1 = oracle_mod.bicgstab(coef, b, tol=1e-12)
+    x2, i2 = oracle_mod.bicgstab(coef, b, tol=1e-12, parallel=True)
+    assert i1.status == i2.status == 0 and abs(i1.iterations - i2.iterations) <= 2
+    assert np.linalg.norm(x1 - x2) / np.linalg.norm(x1) <= 1e-11

@@ -1,4 +1,5 @@
-"""Pins for the FP64 restarted flexible GMRES reference (oracle/krylov.py)."""
+"""Pins for the FP64 Krylov references with a changing preconditioner (oracle/krylov.py):
+restarted flexible GMRES and flexible BiCGStab with the stall fallback."""
 import numpy as np
 import pytest
 
@@ -77,3 +78,64 @@ def test_identity_preconditioner_on_diagonal_system():
     x, info = krylov.fgmres(coef, b, tol=1e-13, m=10, precond=lambda j, v: v)
     assert info.status == 0 and info.iterations == 3
     assert np.allclose(x, b / coef[6].ravel(), rtol=1e-12)
+
+
+@pytest.mark.parametrize("eps_bd", [2.0 ** -52, 1e-2])
+@pytest.mark.parametrize("code", [1, 0], ids=["tri", "identity"])
+def test_flexible_bicgstab_with_fixed_m_is_the_c_oracle(code, eps_bd):
+    """With the same M at every call the flexible BiCGStab is, bit for bit, the C oracle's
+    BiCGStab (same iterations, restarts, residual history and x), breakdown restarts included."""
+    p = synth.Problem(48, 24, 10, seed=7)
+    coef = synth.make_coeffs(p)
+    b = synth.make_rhs(p).ravel()
+    M = (lambda q: oracle.thomas(coef, q)) if code == 1 else (lambda q: q.copy())
+    x_ref, ref = oracle.bicgstab(coef, b, tol=1e-10, precond=code, eps_bd=eps_bd)
+    x, info = krylov.bicgstab_flex(coef, b, M, tol=1e-10, eps_bd=eps_bd)
+    assert info.status == ref.status == 0 and info.iterations == ref.iterations
+    assert info.restarts == ref.restarts and info.fallbacks == 0
+    assert np.array_equal(info.history, ref.history) and np.array_equal(x, x_ref)
+    if eps_bd > 1e-10 and code == 1:
+        assert ref.sigma_restarts >= 1 and ref.rho_restarts >= 1
+
+
+def test_flexible_bicgstab_with_changing_m():
+    """M alternates between the tridiagonal solve and two line-SOR sweeps from call to call:
+    the iteration converges to the dense LU solution and, because x moves along exactly the
+    preconditioned vectors that entered A, its recursive residual is the true one."""
+    p = synth.Problem(16, 12, 8, seed=4)
+    coef = synth.make_coeffs(p)
+    b = synth.make_rhs(p).ravel()
+    calls = [0]
+
+    def M(q):
+        calls[0] += 1
+        return oracle.thomas(coef, q) if calls[0] % 2 else oracle.rbsor(coef, q, sweeps=2)
+
+    x, info = krylov.bicgstab_flex(coef, b, M, tol=1e-12)
+    x_ref = oracle.dense_solve(coef, b)
+    assert info.status == 0 and calls[0] >= 2 * info.iterations - 1
+    assert np.linalg.norm(x - x_ref) / np.linalg.norm(x_ref) <= 1e-10
+    assert abs(info.true_rel_residual - info.history[-1]) <= 1e-13
+
+
+def test_flexible_bicgstab_stall_falls_back():
+    """A preconditioner that cannot carry the solve (T^{-1} of the wrong columns: the input
+    rolled by one longitude) stalls; after stall_window iterations without halving the residual
+    M becomes the tridiagonal solve, the iteration restarts from the true residual and converges
+    to the dense LU solution."""
+    p = synth.Problem(16, 12, 8, seed=4)
+    coef = synth.make_coeffs(p)
+    b = synth.make_rhs(p).ravel()
+    nlev, nlat, nlon = coef.shape[1:]
+
+    def bad(q):
+        return np.roll(oracle.thomas(coef, q).reshape(nlev, nlat, nlon), 5, axis=2).ravel()
+
+    tri = lambda q: oracle.thomas(coef, q)   # noqa: E731
+    x, info = krylov.bicgstab_flex(coef, b, bad, tol=1e-12, fallback=tri, stall_window=20)
+    assert info.fallbacks == 1 and info.status == 0
+    x_ref = oracle.dense_solve(coef, b)
+    assert np.linalg.norm(x - x_ref) / np.linalg.norm(x_ref) <= 1e-10
+    # without the fallback the same preconditioner does not reach the tolerance in that many steps
+    _, stuck = krylov.bicgstab_flex(coef, b, bad, tol=1e-12, maxit=info.iterations)
+    assert stuck.status != 0

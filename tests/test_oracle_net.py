@@ -105,3 +105,39 @@ def test_transpose_coefficients_give_the_adjoint():
     assert abs(lhs - rhs) <= 1e-12 * np.linalg.norm(x) * np.linalg.norm(y) * 10
     A = oracle.dense_matrix(coef)
     assert np.allclose(oracle.dense_matrix(net.transpose_coeffs(coef)), A.T, rtol=0, atol=1e-15)
+
+
+def _golden_adam():
+    path = __import__("os").path.join(__import__("os").path.dirname(__file__), "golden", "adam_two_steps.txt")
+    rows = [list(map(float, ln.split())) for ln in open(path) if ln.strip() and not ln.startswith("#")]
+    return np.array(rows)
+
+
+def test_adam_two_steps_match_hand_worked_example():
+    """Two Adam steps on three parameters (one of them with a zero first gradient) against the
+    values worked out by hand in decimal arithmetic (tests/golden/adam_two_steps.txt)."""
+    g = _golden_adam()
+    st = net.AdamState(3)
+    th1 = net.adam_step(g[:, 0], g[:, 1], st, lr=0.1)
+    assert np.allclose(st.m, g[:, 3], rtol=1e-14, atol=1e-18) and np.allclose(st.v, g[:, 4], rtol=1e-14, atol=1e-22)
+    assert np.allclose(th1, g[:, 5], rtol=1e-15, atol=0)
+    th2 = net.adam_step(th1, g[:, 2], st, lr=0.1)
+    assert np.allclose(st.m, g[:, 6], rtol=1e-14, atol=0) and np.allclose(st.v, g[:, 7], rtol=1e-14, atol=0)
+    # 1 - b2^2 = 0.001999 cancels three digits: a few units in the last place
+    assert np.allclose(th2, g[:, 8], rtol=5e-15, atol=0)
+    assert st.t == 2
+
+
+def test_adam_constant_gradient_closed_form():
+    """Under a constant gradient g the bias-corrected moments are exactly g and g^2 at every
+    step, so each step moves every parameter by lr g / (|g| + eps): a step of lr against the
+    gradient's sign whatever its scale (a missing correction or swapped decay rates would give
+    steps that grow or shrink with t)."""
+    rng = np.random.default_rng(3)
+    g = rng.standard_normal(50) * np.logspace(-6, 3, 50)
+    th0 = rng.standard_normal(50)
+    st = net.AdamState(50)
+    th = th0
+    for t in range(1, 6):
+        th = net.adam_step(th, g, st, lr=1e-2)
+        assert np.allclose(th, th0 - t * 1e-2 * g / (np.abs(g) + 1e-8), rtol=0, atol=1e-14)

@@ -1,0 +1,76 @@
+"""Pins for the 16-bit coefficient reference (oracle/quant.py): its rounding against torch's
+and numpy's correctly rounded conversions and against hand-made ties, its scales, and the
+row sums of the operator it rebuilds."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import net as onet
+from oracle import quant
+
+
+def _float32_values(rng, count):
+    """Positive float32 values over BF16's whole range, subnormals included."""
+    mant = rng.integers(1 << 23, 1 << 24, count).astype(np.float64)
+    exp = rng.integers(-149 - 23, 128 - 23, count)
+    v = np.ldexp(mant, exp)
+    v = v[(v > 0) & (v < 3.0e38)]
+    return v.astype(np.float32).astype(np.float64)
+
+
+def test_bf16_rounding_matches_torch():
+    """round_sig(., 8, -126) is torch's float32 -> bfloat16 conversion (round to nearest even)
+    on float32 inputs, over the normal and the subnormal range."""
+    torch = pytest.importorskip("torch")
+    rng = np.random.default_rng(0)
+    v = _float32_values(rng, 200000)
+    ref = torch.from_numpy(v.astype(np.float32)).to(torch.bfloat16).to(torch.float64).numpy()
+    ours = quant.round_sig(v, 8, -126)
+    finite = np.isfinite(ref)
+    assert np.array_equal(ours[finite], ref[finite])
+    # the network oracle's own BF16 rounding (pinned against torch elsewhere) agrees
+    assert np.array_equal(ours, onet.bf16(v))
+
+
+def test_fp16_rounding_matches_numpy():
+    """round_sig(., 11, -14) is numpy's correctly rounded float64 -> float16 conversion,
+    subnormals (down to 2^-24) included."""
+    rng = np.random.default_rng(1)
+    v = np.ldexp(rng.uniform(1.0, 2.0, 200000), rng.integers(-26, 15, 200000))   # below FP16's overflow
+    ref = v.astype(np.float16).astype(np.float64)
+    assert np.array_equal(quant.round_sig(v, 11, -14), ref)
+
+
+def test_rounding_ties_go_to_even():
+    """Exact halfway cases: 1 + k/2^8 + 1/2^9 lies halfway between two BF16 values and goes to
+    the one with an even last bit; below the normal range the spacing stays 2^-133."""
+    k = np.arange(0, 128)
+    u = 1.0 + k / 256.0 + 1.0 / 512.0
+    r = quant.round_sig(u, 8, -126)
+    lo, hi = 1.0 + k / 256.0, 1.0 + (k + 1) / 256.0
+    expect = np.where(k % 2 == 0, lo, hi)
+    assert np.array_equal(r, expect)
+    sub = np.ldexp(np.array([1.5, 2.5, 3.5, 0.5, 0.49]), -133)
+    assert np.array_equal(quant.round_sig(sub, 8, -126), np.ldexp(np.array([2.0, 2.0, 4.0, 0.0, 0.0]), -133))
+
+
+@pytest.mark.parametrize("kind,rel", [("bf16", 2.0 ** -8), ("fp16", 2.0 ** -11)])
+def test_quantized_operator(kind, rel):
+    """Scales are powers of two with the row maximum in (1/2, 1] after scaling; each coupling
+    is within half a unit in its last place (the unit roundoff 2^-8 for BF16 and 2^-11 for FP16,
+    relative; these magnitudes are far from underflow); zero couplings stay zero; the rebuilt
+    operator's row sums are the FP32 margin."""
+    p = synth.Problem(40, 30, 12, seed=3)
+    coef = synth.make_coeffs(p)
+    s = quant.scales(coef)
+    assert np.array_equal(s, np.ldexp(1.0, np.frexp(s)[1] - 1))
+    mx = coef[:6].max(axis=3, keepdims=True)
+    ratio = mx[mx > 0] / np.broadcast_to(s, mx.shape)[mx > 0]
+    assert np.all((ratio > 0.5) & (ratio <= 1.0))
+    cq = quant.quantized_coeffs(coef, kind)
+    a, aq = coef[:6], cq[:6]
+    assert np.array_equal(aq == 0, a == 0) and np.all(aq >= 0)
+    assert np.all(np.abs(aq - a) <= rel * a)
+    m32 = quant.margin(coef).astype(np.float32).astype(np.float64)
+    rows = cq[6] - aq.sum(axis=0)
+    assert np.allclose(rows, m32, rtol=0, atol=1e-15 * np.abs(cq[6]).max())
