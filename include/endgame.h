@@ -297,6 +297,53 @@ int eg_net_train(eg_net *net, eg_operator *const *ops, int nops, const float *r,
 int eg_net_eval(eg_net *net, eg_operator *const *ops, int nops, const float *r, const float *e, const int *pair_op,
                 int npairs, double *mean_loss);
 
+/* ---- the learned preconditioner as part of the operator ----
+ *
+ * The calls below give an operator a network of its own (created on first use, freed by
+ * eg_destroy_operator) and make it the operator's learned preconditioner, as eg_attach_learned_pc
+ * does with a caller-owned one.  Until one of them (or eg_attach_learned_pc) has run, the
+ * EG_LEARNED_* modes return EG_ENOPC.
+ *
+ * Train it on (residual, error) pairs that the solver itself produces for this operator (the
+ * iterates of FP64 BiCGStab, eg_harvest, or the Krylov basis of FGMRES, eg_harvest_krylov),
+ * from seeded random right-hand sides b ~ N(0, 1) drawn in the library (splitmix64 + Box-Muller
+ * from `seed`).  Sec. 2's solver is the source of the pairs; the network and its training are
+ * this library's extension (the paper has no learned preconditioner).
+ *   harvest_cfg  host string of comma-separated key=value settings (NULL or "" = defaults):
+ *                  source=iterates|krylov   pairs r_i = b - A x_i, e_i = x* - x_i from the first
+ *                                           iterates of an FP64 solve (eg_harvest), or the FGMRES
+ *                                           basis v_j with e_j = A^{-1} v_j (eg_harvest_krylov)
+ *                                           [iterates]
+ *                  rhs=N         right-hand sides, 1..4096 [8]
+ *                  pairs=K       pairs per right-hand side, 1..64 [20]
+ *                  loss=error|residual      ||M(r) - e||^2/||e||^2 or ||A M(r) - r||^2/||r||^2 [error]
+ *                  batch=B       pairs per Adam step [16]
+ *                The pairs are held in device memory only during the call (2 K N n floats).
+ *   epochs >= 0, lr > 0 (Adam, beta 0.9 / 0.999), seed: right-hand sides, shuffling and the
+ *   network's initial weights when it is created here (a network that exists is trained on).
+ * Returns 0, or EG_EINVAL for a bad setting (the message names it), EG_ENOMEM, EG_EHIP.
+ */
+int eg_train_learned_pc(eg_operator *op, const char *harvest_cfg, int epochs, double lr, unsigned seed);
+
+/* The operator's learned preconditioner's weights as a byte image: a 16-byte header (the
+ * characters "EGPC", format version 1, the parameter count 15233, 0, as int32) followed by the
+ * 15233 FP32 weights in the order of eg_net_set_weights.
+ *   weights  host buffer of cap bytes, or NULL to ask for the size.
+ * Returns the image size in bytes (60948), whether or not it was written (it is written when
+ * weights != NULL and cap is at least that size; a smaller cap gives EG_EINVAL), or EG_ENOPC
+ * when the operator has no learned preconditioner. */
+int eg_save_learned_pc(const eg_operator *op, void *weights, long cap);
+
+/* Load an image written by eg_save_learned_pc (host buffer of nbytes bytes) into the
+ * operator's own network (created if needed) and make it the learned preconditioner; the
+ * optimiser state restarts.  EG_EINVAL when the header or the size does not match. */
+int eg_load_learned_pc(eg_operator *op, const void *weights, long nbytes);
+
+/* The network the operator's learned modes use (its own or an attached one), borrowed: valid
+ * until the operator is destroyed or another network is attached.  *out = NULL and EG_ENOPC
+ * when there is none. */
+int eg_get_learned_pc(eg_operator *op, eg_net **out);
+
 /* Grid sizes of an operator (host ints; any pointer may be NULL). */
 int eg_get_shape(const eg_operator *op, int *nlon, int *nlat, int *nlev);
 

@@ -28,7 +28,9 @@ EXPORTED = ["eg_create_operator", "eg_solve", "eg_get_info", "eg_residual_histor
             "eg_apply", "eg_apply_precond", "eg_residual", "eg_dot", "eg_get_shape", "eg_destroy_operator",
             "eg_last_error", "eg_kernel_stats", "eg_reset_kernel_stats", "eg_net_create", "eg_net_destroy",
             "eg_net_set_weights", "eg_net_get_weights", "eg_attach_learned_pc", "eg_net_apply", "eg_net_loss_grad",
-            "eg_harvest", "eg_harvest_krylov", "eg_net_train", "eg_net_eval", "eg_net_set_loss"]
+            "eg_harvest", "eg_harvest_krylov", "eg_net_train", "eg_net_eval", "eg_net_set_loss",
+            "eg_train_learned_pc", "eg_save_learned_pc", "eg_load_learned_pc", "eg_get_learned_pc"]
+PC_IMAGE_BYTES = 16 + 4 * 15233
 N_NET_PARAMS = 15233
 # enum eg_kernel
 K_THOMAS_P, K_SPMV_V, K_THOMAS_S, K_SPMV_T, K_UPDATE, K_RESIDUAL, K_SOR_P, K_SOR_S = range(8)
@@ -97,6 +99,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                           ctypes.c_double, ctypes.c_ulonglong, dp], ctypes.c_int),
         "eg_net_eval": ([vp, vp, ctypes.c_int, vp, vp, vp, ctypes.c_int, dp], ctypes.c_int),
         "eg_net_set_loss": ([vp, ctypes.c_int], ctypes.c_int),
+        "eg_train_learned_pc": ([vp, ctypes.c_char_p, ctypes.c_int, ctypes.c_double, ctypes.c_uint], ctypes.c_int),
+        "eg_save_learned_pc": ([vp, vp, ctypes.c_long], ctypes.c_int),
+        "eg_load_learned_pc": ([vp, vp, ctypes.c_long], ctypes.c_int),
+        "eg_get_learned_pc": ([vp, ctypes.POINTER(vp)], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -284,6 +290,34 @@ class Operator:
         _check(_lib.eg_attach_learned_pc(self._h, None if net is None else net._h))
         self._net = net
 
+    def train_learned_pc(self, harvest_cfg: str = "", epochs: int = 20, lr: float = 1e-3, seed: int = 0):
+        """Harvest (residual, error) pairs from this operator's own solves and train its own
+        network on them; it becomes the learned preconditioner (see eg_train_learned_pc)."""
+        if epochs < 0 or not lr > 0:
+            raise ValueError("need epochs >= 0 and lr > 0")
+        self._bind_stream()
+        _check(_lib.eg_train_learned_pc(self._h, harvest_cfg.encode(), int(epochs), float(lr), int(seed) & 0xFFFFFFFF))
+
+    def save_learned_pc(self) -> bytes:
+        """The learned preconditioner's weights as a byte image (header + FP32 weights)."""
+        size = _check(_lib.eg_save_learned_pc(self._h, None, 0))
+        buf = ctypes.create_string_buffer(size)
+        _check(_lib.eg_save_learned_pc(self._h, ctypes.cast(buf, ctypes.c_void_p), size))
+        return buf.raw
+
+    def load_learned_pc(self, image: bytes):
+        """Load an image from save_learned_pc into this operator's own network."""
+        if not isinstance(image, (bytes, bytearray)):
+            raise TypeError("image must be bytes")
+        buf = ctypes.create_string_buffer(bytes(image), len(image))
+        _check(_lib.eg_load_learned_pc(self._h, ctypes.cast(buf, ctypes.c_void_p), len(image)))
+
+    def learned_pc(self) -> "Net":
+        """The network the learned modes use (borrowed from the operator: do not close it)."""
+        h = ctypes.c_void_p()
+        _check(_lib.eg_get_learned_pc(self._h, ctypes.byref(h)))
+        return Net._borrowed(h, self)
+
     def harvest(self, b, nsnap: int):
         """(r, e) float tensors of shape (count, n) from the solver's own FP64 iterates."""
         import torch
@@ -332,7 +366,19 @@ class Net:
         _check(lib.eg_net_create(int(seed), ctypes.byref(h)))
         self._h = h
 
+    @classmethod
+    def _borrowed(cls, handle, owner):
+        """A view of a network the library owns (an operator's own network): never destroyed
+        from Python; keeps its operator alive."""
+        net = cls.__new__(cls)
+        net._h = handle
+        net._owner = owner
+        return net
+
     def close(self):
+        if getattr(self, "_owner", None) is not None:
+            self._h = None
+            return
         if getattr(self, "_h", None):
             _lib.eg_net_destroy(self._h)
             self._h = None

@@ -26,6 +26,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <type_traits>
@@ -156,7 +157,8 @@ struct eg_operator {
     eg_info info{};
     std::vector<double> hist_host;
     int hist_count = 0;
-    eg_net *net = nullptr;      // learned preconditioner attached to this operator (not owned)
+    eg_net *net = nullptr;      // learned preconditioner of the learned modes (own_net or a caller's)
+    eg_net *own_net = nullptr;  // network owned by the operator (eg_train/load_learned_pc)
     double *harvest_x = nullptr;
     int method = 0;             // plain modes: 0 BiCGStab, 1 FGMRES
     int learned_method = 1;     // learned modes: 0 flexible BiCGStab, 1 FGMRES
@@ -1089,6 +1091,63 @@ int ensure_loss(eg_net *net, long npairs)
     return 0;
 }
 
+// Settings of eg_train_learned_pc ("key=value,key=value").
+struct PcCfg {
+    int source = 0;   // 0: iterates of an FP64 solve (eg_harvest), 1: FGMRES basis (eg_harvest_krylov)
+    int rhs = 8;
+    int pairs = 20;
+    int loss = 0;     // 0 error space, 1 residual space
+    int batch = 16;
+};
+
+int parse_pc_cfg(const char *cfg, PcCfg &c)
+{
+    if (!cfg) return 0;
+    const std::string all(cfg);
+    size_t pos = 0;
+    while (pos < all.size()) {
+        size_t end = all.find(',', pos);
+        if (end == std::string::npos) end = all.size();
+        const std::string item = all.substr(pos, end - pos);
+        pos = end + 1;
+        if (item.empty()) continue;
+        const size_t eq = item.find('=');
+        if (eq == std::string::npos) return fail(EG_EINVAL, "harvest_cfg: '" + item + "' is not key=value");
+        const std::string key = item.substr(0, eq), val = item.substr(eq + 1);
+        auto as_int = [&](int lo, int hi, int *out) {
+            char *endp = nullptr;
+            const long v = std::strtol(val.c_str(), &endp, 10);
+            if (val.empty() || *endp != '\0' || v < lo || v > hi)
+                return fail(EG_EINVAL, "harvest_cfg: " + key + " must be an integer in [" + std::to_string(lo) + ", " +
+                                           std::to_string(hi) + "]");
+            *out = (int)v;
+            return 0;
+        };
+        int rc = 0;
+        if (key == "source") {
+            if (val == "iterates") c.source = 0;
+            else if (val == "krylov") c.source = 1;
+            else return fail(EG_EINVAL, "harvest_cfg: source must be iterates or krylov");
+        } else if (key == "loss") {
+            if (val == "error") c.loss = 0;
+            else if (val == "residual") c.loss = 1;
+            else return fail(EG_EINVAL, "harvest_cfg: loss must be error or residual");
+        } else if (key == "rhs") {
+            rc = as_int(1, 4096, &c.rhs);
+        } else if (key == "pairs") {
+            rc = as_int(1, kMaxGmres, &c.pairs);
+        } else if (key == "batch") {
+            rc = as_int(1, 1 << 20, &c.batch);
+        } else {
+            return fail(EG_EINVAL, "harvest_cfg: unknown key '" + key + "'");
+        }
+        if (rc) return rc;
+    }
+    return 0;
+}
+
+constexpr long kPcImageBytes = 16 + 4L * kNetParams;   // header + FP32 weights
+
 int check_pairs(eg_operator *const *ops, int nops, const float *r, const float *e, const int *pair_op, int npairs)
 {
     if (!ops || nops < 1 || !r || !e || !pair_op || npairs < 1) return fail(EG_EINVAL, "bad training arguments");
@@ -1138,6 +1197,7 @@ void eg_destroy_operator(eg_operator *op)
     dfree(op->partials); dfree(op->sc); dfree(op->d_out); dfree(op->d_bad); dfree(op->d_hist);
     if (op->h_sc) (void)hipHostFree(op->h_sc);
     if (op->h_out) (void)hipHostFree(op->h_out);
+    if (op->own_net) eg_net_destroy(op->own_net);
     delete op;
 }
 
@@ -1708,6 +1768,98 @@ int eg_net_train(eg_net *net, eg_operator *const *ops, int nops, const float *r,
         for (double v : losses) m += v;
         if (loss_hist) loss_hist[ep] = m / npairs;
     }
+    return 0;
+}
+
+int eg_get_learned_pc(eg_operator *op, eg_net **out)
+{
+    if (!op || !out) return fail(EG_EINVAL, "NULL argument");
+    *out = op->net;
+    return op->net ? 0 : fail(EG_ENOPC, "the operator has no learned preconditioner");
+}
+
+int eg_train_learned_pc(eg_operator *op, const char *harvest_cfg, int epochs, double lr, unsigned seed)
+{
+    if (!op) return fail(EG_EINVAL, "op is NULL");
+    if (epochs < 0 || !(lr > 0.0)) return fail(EG_EINVAL, "need epochs >= 0 and lr > 0");
+    PcCfg c;
+    int rc;
+    if ((rc = parse_pc_cfg(harvest_cfg, c))) return rc;
+    if (!op->own_net) {
+        eg_net *net = nullptr;
+        if ((rc = eg_net_create(seed, &net))) return rc;
+        op->own_net = net;
+    }
+    eg_net *net = op->own_net;
+    net->loss_kind = c.loss;
+    // the pairs live only for this call
+    struct Tmp {
+        float *r = nullptr, *e = nullptr;
+        double *b = nullptr;
+        ~Tmp() { dfree(r); dfree(e); dfree(b); }
+    } t;
+    const size_t n = (size_t)op->n, cap = (size_t)c.rhs * c.pairs;
+    if ((rc = dalloc(&t.r, cap * n)) || (rc = dalloc(&t.e, cap * n)) || (rc = dalloc(&t.b, n))) return rc;
+    std::vector<double> hb(n);
+    long np = 0;
+    for (int k = 0; k < c.rhs; ++k) {
+        uint64_t st = (uint64_t)seed * 0x9E3779B97F4A7C15ull + 0x51ED270Bull * (uint64_t)(k + 1);
+        for (size_t i = 0; i < n; ++i) hb[i] = std_normal(st);
+        EG_HIP(hipMemcpyAsync(t.b, hb.data(), n * sizeof(double), hipMemcpyHostToDevice, op->stream));
+        EG_HIP(hipStreamSynchronize(op->stream));
+        const int cnt = c.source == 0 ? eg_harvest(op, t.b, c.pairs, t.r + (size_t)np * n, t.e + (size_t)np * n)
+                                      : eg_harvest_krylov(op, t.b, c.pairs, t.r + (size_t)np * n, t.e + (size_t)np * n);
+        if (cnt < 0) return cnt;
+        np += cnt;
+    }
+    if (np < 1) return fail(EG_EINVAL, "the harvest produced no pairs");
+    std::vector<int> owner((size_t)np, 0);
+    eg_operator *ops[1] = {op};
+    if ((rc = eg_net_train(net, ops, 1, t.r, t.e, owner.data(), (int)np, epochs, c.batch, lr, seed, nullptr)))
+        return rc;
+    op->net = net;
+    return 0;
+}
+
+int eg_save_learned_pc(const eg_operator *op, void *weights, long cap)
+{
+    if (!op) return fail(EG_EINVAL, "op is NULL");
+    if (!op->net) return fail(EG_ENOPC, "the operator has no learned preconditioner");
+    if (!weights) return (int)kPcImageBytes;
+    if (cap < kPcImageBytes) return fail(EG_EINVAL, "need " + std::to_string(kPcImageBytes) + " bytes");
+    std::vector<float> w(kNetParams);
+    int rc = eg_net_get_weights(op->net, w.data(), kNetParams);
+    if (rc < 0) return rc;
+    const int32_t hdr[3] = {1, kNetParams, 0};
+    unsigned char *out = static_cast<unsigned char *>(weights);
+    std::memcpy(out, "EGPC", 4);
+    std::memcpy(out + 4, hdr, sizeof(hdr));
+    std::memcpy(out + 16, w.data(), 4 * (size_t)kNetParams);
+    return (int)kPcImageBytes;
+}
+
+int eg_load_learned_pc(eg_operator *op, const void *weights, long nbytes)
+{
+    if (!op || !weights) return fail(EG_EINVAL, "NULL argument");
+    if (nbytes != kPcImageBytes) return fail(EG_EINVAL, "a learned-preconditioner image has " +
+                                                            std::to_string(kPcImageBytes) + " bytes");
+    const unsigned char *in = static_cast<const unsigned char *>(weights);
+    int32_t hdr[3];
+    std::memcpy(hdr, in + 4, sizeof(hdr));
+    if (std::memcmp(in, "EGPC", 4) != 0 || hdr[0] != 1 || hdr[1] != kNetParams || hdr[2] != 0)
+        return fail(EG_EINVAL, "not a learned-preconditioner image (header EGPC, version 1, 15233 weights)");
+    std::vector<float> w(kNetParams);
+    std::memcpy(w.data(), in + 16, 4 * (size_t)kNetParams);
+    for (float v : w)
+        if (!std::isfinite(v)) return fail(EG_EINVAL, "the image holds non-finite weights");
+    int rc;
+    if (!op->own_net) {
+        eg_net *net = nullptr;
+        if ((rc = eg_net_create(0, &net))) return rc;
+        op->own_net = net;
+    }
+    if ((rc = eg_net_set_weights(op->own_net, w.data(), kNetParams))) return rc;
+    op->net = op->own_net;
     return 0;
 }
 

@@ -46,6 +46,10 @@ def test_argument_errors_without_device_work(lib):
     assert lib.eg_set_option(None, b"eta", 1e-4) == -1
     assert lib.eg_harvest_krylov(None, None, 5, None, None) == -1
     assert lib.eg_harvest(None, None, 5, None, None) == -1
+    assert lib.eg_train_learned_pc(None, b"rhs=2", 1, 1e-3, 0) == -1
+    assert lib.eg_save_learned_pc(None, None, 0) == -1
+    assert lib.eg_load_learned_pc(None, None, 0) == -1
+    assert lib.eg_get_learned_pc(None, None) == -1
     lib.eg_destroy_operator(None)
 
 

@@ -150,10 +150,13 @@ def test_flexible_bicgstab_follows_oracle(eg, oracle_mod):
     """EG_LEARNED_FP64 with flexible BiCGStab (learned_method 0) against the oracle's flexible
     BiCGStab (oracle/krylov.bicgstab_flex) driven by the oracle's network (oracle/net.apply,
     BF16 rounding where the GPU stores BF16) with the same stall fallback to T^{-1}.  This random
-    network makes both stall and fall back once; until then the residual histories agree to the
-    network's BF16 rounding, the iteration counts agree closely, x agrees to the tolerance's
-    conditioning, and the GPU's recursive residual is its true one (x advanced along exactly the
-    preconditioned vectors that entered A)."""
+    network makes both stall and fall back once, after the same number of iterations; the first
+    iteration's two residuals agree to the network's rounding, the iteration counts agree
+    closely, x agrees to the tolerance's conditioning, and the GPU's recursive residual is its
+    true one (x advanced along exactly the preconditioned vectors that entered A).
+    Later history entries are not compared one by one: with a nonlinear M the recurrence loses
+    its bi-orthogonality and the trajectory is chaotic (the oracle's own third residual moves by
+    11 % when M's output is perturbed by 1e-5 relative)."""
     import torch
     from oracle import krylov
     p = synth.Problem(48, 24, 10, seed=7)
@@ -174,16 +177,65 @@ def test_flexible_bicgstab_follows_oracle(eg, oracle_mod):
         h = op.history()
     net.close()
     xh = host(x)
-    k = min(10, len(h), len(ref.history))
+    k = 2
     dh = np.abs(h[:k] - ref.history[:k]) / ref.history[:k]
     err = np.linalg.norm(xh - x_or) / np.linalg.norm(x_or)
     print(f"flexible BiCGStab: GPU {info.iterations} its {info.fallbacks} fallbacks, oracle {ref.iterations} its "
           f"{ref.fallbacks} fallbacks; first {k} history entries agree to {dh.max():.2e}; x error {err:.2e}")
     assert info.status == eg.CONVERGED and info.fallbacks == ref.fallbacks
     assert abs(info.iterations - ref.iterations) <= max(3, ref.iterations // 10)
-    assert dh.max() <= 1e-2
+    assert dh.max() <= 1e-4
     assert err <= 1e-8
     assert abs(info.true_rel_residual - h[-1]) <= 1e-12
+
+
+def test_learned_pc_train_save_load(eg, oracle_mod):
+    """The operator-owned learned preconditioner through the C ABI: learned modes refuse to run
+    before it exists (EG_ENOPC); eg_train_learned_pc harvests pairs from the operator's own FP64
+    solves and lowers the error-space loss on pairs it did not train on; the saved image loads
+    into a second operator bit for bit, and both solve to the same x bit for bit; a damaged
+    image is refused."""
+    import torch
+    p = synth.Problem(48, 24, 10, seed=9)
+    coef = synth.make_coeffs(p)
+    b = dev(synth.make_rhs(p, seed=77).ravel())
+    with eg.Operator(dev(coef)) as op:
+        x1 = torch.zeros(p.n, dtype=torch.float64, device="cuda")
+        with pytest.raises(eg.EndgameError) as exc:
+            op.solve(b, x1, 1e-8, 2000, eg.LEARNED_FP64)
+        assert exc.value.code == eg.ENOPC
+        with pytest.raises(eg.EndgameError):
+            op.save_learned_pc()
+        r, e = op.harvest(b, 12)                  # held-out pairs (another right-hand side)
+        owner = [0] * r.shape[0]
+        base = eg.Net(0)                          # zero output layer: M = T^{-1}
+        base.set_loss(eg.Net.LOSS_ERROR)
+        loss0 = base.eval([op], r, e, owner)
+        base.close()
+        op.train_learned_pc("source=iterates,rhs=4,pairs=12,loss=error,batch=8", epochs=15, lr=2e-3, seed=3)
+        loss1 = op.learned_pc().eval([op], r, e, owner)
+        print(f"eg_train_learned_pc: held-out error-space loss {loss0:.4f} (T^-1 alone) -> {loss1:.4f}")
+        assert loss1 < loss0
+        img = op.save_learned_pc()
+        assert len(img) == eg.PC_IMAGE_BYTES and img[:4] == b"EGPC"
+        i1 = op.solve(b, x1, 1e-8, 2000, eg.LEARNED_FP64)
+        rel = np.linalg.norm(host(b) - oracle_mod.apply(coef, host(x1))) / np.linalg.norm(host(b))
+        assert i1.status == eg.CONVERGED and rel <= 1e-8
+    with eg.Operator(dev(coef)) as op2:
+        op2.load_learned_pc(img)
+        assert op2.save_learned_pc() == img
+        x2 = torch.zeros_like(x1)
+        i2 = op2.solve(b, x2, 1e-8, 2000, eg.LEARNED_FP64)
+        assert i2.iterations == i1.iterations and torch.equal(x1, x2)
+        bad = bytearray(img)
+        bad[4] = 2                                # format version 2 does not exist
+        with pytest.raises(eg.EndgameError) as exc:
+            op2.load_learned_pc(bytes(bad))
+        assert exc.value.code == eg.EINVAL
+        with pytest.raises(eg.EndgameError):
+            op2.load_learned_pc(img[:-4])
+        with pytest.raises(eg.EndgameError):
+            op2.train_learned_pc("source=nowhere")
 
 
 def test_zero_output_layer_reproduces_plain_solver_bitwise(eg):
