@@ -203,6 +203,22 @@ int eg_residual(eg_operator *op, const double *b, const double *x, double *r, do
 int eg_dot(eg_operator *op, const void *a, const void *b, long n, int prec, double *out_host);
 
 /*
+ * eg_dot for callers that cannot allocate device memory (code under stream capture, serving
+ * loops that must not call hipMalloc): the same inner product with no operator and no
+ * allocation of any kind.  Its partial sums and result live in a static device array of the
+ * library, 8192 x 4 + 4 doubles (256 KiB + 32 B) per GPU, held from the first call on that GPU
+ * until the process ends.
+ *   a, b       device arrays of n elements, double (prec = EG_PREC_FP64) or float (other).
+ *   n          0 .. 2^40 (EG_EINVAL beyond).
+ *   hip_stream hipStream_t the work is ordered on (NULL = null stream); the call waits for it.
+ *   out_host   host double.
+ * Every call on one GPU uses that GPU's one array, which keeps the last call's contents: calls
+ * that overlap on one GPU (from several threads or streams) race and must be serialised by the
+ * caller.  Bitwise equal to eg_dot for the same n and inputs.
+ */
+int eg_dot_noalloc(const void *a, const void *b, long n, int prec, void *hip_stream, double *out_host);
+
+/*
  * Kernel timing (tracing).  With the option "profile" set to 1, every streaming kernel launch
  * of eg_solve that does work is bracketed by HIP events on the operator's stream and its
  * device time is accumulated per (kernel, precision); the host then checks the device flags

@@ -29,7 +29,8 @@ EXPORTED = ["eg_create_operator", "eg_solve", "eg_get_info", "eg_residual_histor
             "eg_last_error", "eg_kernel_stats", "eg_reset_kernel_stats", "eg_net_create", "eg_net_destroy",
             "eg_net_set_weights", "eg_net_get_weights", "eg_attach_learned_pc", "eg_net_apply", "eg_net_loss_grad",
             "eg_harvest", "eg_harvest_krylov", "eg_net_train", "eg_net_eval", "eg_net_set_loss",
-            "eg_train_learned_pc", "eg_save_learned_pc", "eg_load_learned_pc", "eg_get_learned_pc"]
+            "eg_train_learned_pc", "eg_save_learned_pc", "eg_load_learned_pc", "eg_get_learned_pc",
+            "eg_dot_noalloc"]
 PC_IMAGE_BYTES = 16 + 4 * 15233
 N_NET_PARAMS = 15233
 # enum eg_kernel
@@ -103,6 +104,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "eg_save_learned_pc": ([vp, vp, ctypes.c_long], ctypes.c_int),
         "eg_load_learned_pc": ([vp, vp, ctypes.c_long], ctypes.c_int),
         "eg_get_learned_pc": ([vp, ctypes.POINTER(vp)], ctypes.c_int),
+        "eg_dot_noalloc": ([vp, vp, ctypes.c_long, ctypes.c_int, vp, dp], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -164,6 +166,23 @@ def _arg(t, name: str, dtype, numel: int, device=None) -> int:
 def _vec_dtype(prec: int):
     import torch
     return torch.float64 if prec == PREC_FP64 else torch.float32
+
+
+def dot_noalloc(a, b) -> float:
+    """<a, b> with FP64 products and sums, allocating nothing (eg_dot_noalloc): a and b are
+    float64 or float32 device tensors of equal length and dtype; ordered on torch's current
+    stream of their device."""
+    import torch
+    lib = load_library()
+    if not isinstance(a, torch.Tensor) or a.dtype not in (torch.float64, torch.float32):
+        raise ValueError("a: expected a float64 or float32 tensor")
+    pa, pb = _args((a, "a", a.dtype, a.numel(), None), (b, "b", a.dtype, a.numel(), a.device))
+    prec = PREC_FP64 if a.dtype == torch.float64 else PREC_FP32
+    s = torch.cuda.current_stream(a.device).cuda_stream
+    out = ctypes.c_double()
+    with torch.cuda.device(a.device):
+        _check(lib.eg_dot_noalloc(pa, pb, a.numel(), prec, ctypes.c_void_p(s), ctypes.byref(out)))
+    return out.value
 
 
 class Operator:

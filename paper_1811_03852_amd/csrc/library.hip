@@ -28,6 +28,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -85,6 +86,37 @@ template <typename Tv> struct Work {
     Tv *qp = nullptr;   // learned modes: q + rho * delta before the final tridiagonal solve
     bool ready = false;
 };
+
+// ---- allocation-free inner product (eg_dot_noalloc) ----------------------------------------
+// Its per-workgroup partial sums (at most kNoAllocRows rows, the row count of the elementwise
+// kernels) and its result live in this file-scope device array: one copy per GPU, held until
+// the process ends.  Host code must not pass the array's name to a kernel (on the host it is a
+// stand-in, not a device address): it uses the address hipGetSymbolAddress returns for the
+// current device, looked up once per device.
+constexpr int kNoAllocRows = 8192;
+constexpr int kNoAllocDoubles = kNoAllocRows * kPartialCols + kPartialCols;
+constexpr long kNoAllocMaxN = 1L << 40;
+static __device__ __align__(256) double scratch[kNoAllocDoubles];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (looked up on the first call per device).
+int scratch_ptr(double **out)
+{
+    int dev = 0;
+    EG_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(EG_EINVAL, "device index out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        EG_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        g_scratch_ptr[dev] = static_cast<double *>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return 0;
+}
 
 }  // namespace
 
@@ -1526,6 +1558,31 @@ int eg_dot(eg_operator *op, const void *a, const void *b, long n, int prec, doub
     EG_HIP(hipMemcpyAsync(op->h_out, op->d_out, 4 * sizeof(double), hipMemcpyDeviceToHost, op->stream));
     EG_HIP(hipStreamSynchronize(op->stream));
     *out_host = op->h_out[0];
+    return 0;
+}
+
+int eg_dot_noalloc(const void *a, const void *b, long n, int prec, void *hip_stream, double *out_host)
+{
+    if (!a || !b || !out_host) return fail(EG_EINVAL, "NULL argument");
+    if (n < 0 || n > kNoAllocMaxN) return fail(EG_EINVAL, "n must be in [0, 2^40]");
+    if (prec < EG_PREC_FP64 || prec > EG_PREC_FP16) return fail(EG_EINVAL, "unknown precision");
+    double *ws = nullptr;
+    int rc;
+    if ((rc = scratch_ptr(&ws))) return rc;
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    int nr = 0;
+    // the same kernels as eg_dot: partial rows (every row the sum reads is written first), then
+    // the fixed-order sum into the four doubles after them
+    if (prec == EG_PREC_FP64)
+        launch_dot<double, double>(n, static_cast<const double *>(a), static_cast<const double *>(b), ws, &nr, s);
+    else
+        launch_dot<float, float>(n, static_cast<const float *>(a), static_cast<const float *>(b), ws, &nr, s);
+    if (nr > kNoAllocRows) return fail(EG_EINVAL, "internal: more partial rows than the static array holds");
+    double *res = ws + (size_t)kNoAllocRows * kPartialCols;
+    launch_finalize(FIN_SUM, ws, nr, nullptr, nullptr, res, 0, 0, s);
+    EG_HIP(hipGetLastError());
+    EG_HIP(hipMemcpyAsync(out_host, res, sizeof(double), hipMemcpyDeviceToHost, s));
+    EG_HIP(hipStreamSynchronize(s));
     return 0;
 }
 
