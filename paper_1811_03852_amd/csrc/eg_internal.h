@@ -97,7 +97,10 @@ template <typename Tout>
 void launch_residual(const OpView<double> &op, const double *b, const double *x, Tout *r, double *partials,
                      int *nrows, hipStream_t s);
 
-enum ThomasMode { TH_PLAIN = 0, TH_P = 1, TH_S = 2 };
+// TH_PF: the TH_P step of an iteration that starts afresh (rhat = p = r), a kernel of its own on
+// the register path (launched beside TH_P; each returns at once unless the device's restart
+// flag says it is the one)
+enum ThomasMode { TH_PLAIN = 0, TH_P = 1, TH_S = 2, TH_PF = 3 };
 // stop_mask: flags that make a TH_PLAIN launch return at once (TH_P / TH_S use their own)
 template <typename Tv>
 void launch_thomas(const TriView<Tv> &tv, const Tv *q, Tv *z, int mode, const Tv *r, Tv *p, const Tv *v, Tv *rhat,

@@ -80,6 +80,22 @@ __device__ __forceinline__ void block_sum_store(double (&v)[NV], double *row)
     }
 }
 
+// Sum NV doubles over one wave in a fixed order (butterfly); lane 0 writes `row`.
+template <int NV>
+__device__ __forceinline__ void wave_sum_store(double (&v)[NV], double *row)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+        for (int c = 0; c < NV; ++c) v[c] += __shfl_xor(v[c], off);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int c = 0; c < NV; ++c) row[c] = v[c];
+#pragma unroll
+        for (int c = NV; c < kPartialCols; ++c) row[c] = 0.0;
+    }
+}
+
 // ------------------------------------------------------------------------------------------
 // k_spmv: 7-point stencil, difference form  y = m x + sum_d a_d (x - x_d)
 //
@@ -286,12 +302,14 @@ static SpmvGrid spmv_grid(int nlon, int nlat, int nlev)
 
 constexpr int kSpmvRows = 2;   // latitude rows per thread
 
+constexpr int kUpdateMaxBlocks = 32768;   // most workgroups of the vector-update kernels
+
 int partial_rows_needed(int nlon, int nlat, int nlev)
 {
     const long P = (long)nlon * nlat;
     long rows = spmv_grid<kSpmvRows>(nlon, nlat, nlev).nblocks;
-    rows = std::max(rows, (P + kWG - 1) / kWG);   // thomas(S): one row per workgroup of columns
-    rows = std::max(rows, 8192L);                 // elementwise kernels
+    rows = std::max(rows, (P + 63) / 64);         // thomas(S): one row per wave of columns
+    rows = std::max(rows, (long)kUpdateMaxBlocks);   // elementwise kernels (the update the most)
     return (int)rows;
 }
 
@@ -385,17 +403,23 @@ void launch_tri_factor(const double *a64, const double *m64, int nlon, int nlat,
 // colour * n/2 + k * P/2 + j * nlon/2 + i/2, colour = (i + j) & 1, nlon even) and q is also
 // stored there, to qcm: the start of a line-SOR application (both in one pass).
 // ------------------------------------------------------------------------------------------
-template <typename Tv, int NL, int MODE, bool CM, int PF = 8>
-__global__ __launch_bounds__(kWG) void k_thomas(TriView<Tv> tv, const Tv *__restrict__ q, Tv *__restrict__ z,
-                                                const Tv *__restrict__ r, Tv *__restrict__ p,
-                                                const Tv *__restrict__ v, Tv *__restrict__ rhat,
-                                                double *__restrict__ partials, const Scalars *__restrict__ sc,
-                                                int stop_mask, Tv *__restrict__ qcm, int nlon)
+// One wave per workgroup: with the register-resident columns (up to 199 VGPRs in FP64, two
+// waves per SIMD) a finished wave is replaced at once on its own SIMD instead of waiting for
+// the other waves of a four-wave workgroup; 5.66 instead of 5.26 TB/s for TH_P at
+// 2560x1920x70 in FP64.
+constexpr int kTriWG = 64;
+
+template <typename Tv, int NL, int MODE, bool CM, int PF>
+__device__ __forceinline__ void thomas_body(TriView<Tv> tv, const Tv *__restrict__ q, Tv *__restrict__ z,
+                                            const Tv *__restrict__ r, Tv *__restrict__ p, const Tv *__restrict__ v,
+                                            Tv *__restrict__ rhat, double *__restrict__ partials,
+                                            const Scalars *__restrict__ sc, int stop_mask, Tv *__restrict__ qcm,
+                                            int nlon)
 {
     if (stopped(sc, stop_mask)) return;
     const long P = tv.P, n = tv.n;
     const int nlev = (NL > 0) ? NL : tv.nlev;
-    const long col = (long)blockIdx.x * kWG + threadIdx.x;
+    const long col = (long)blockIdx.x * kTriWG + threadIdx.x;
     const bool act = col < P;
     // 32-bit lane offset within a level plane; per-level bases below are wave-uniform
     const unsigned cu = static_cast<unsigned>(act ? col : P - 1);
@@ -413,15 +437,21 @@ __global__ __launch_bounds__(kWG) void k_thomas(TriView<Tv> tv, const Tv *__rest
     int fresh = 0;
     if constexpr (MODE == TH_P) {
         fresh = sc->fresh;
+        // on the register path a restart iteration is TH_PF's (a separate kernel keeps this
+        // one's forward sweep free of the restart variant: 3.9 instead of 4.2 ms at 2560x1920x70)
+        if constexpr (NL > 0)
+            if (fresh) return;
         beta = static_cast<Tv>(sc->beta);
         omega = static_cast<Tv>(sc->omega);
     }
+    if constexpr (MODE == TH_PF)
+        if (!sc->fresh) return;
     if constexpr (MODE == TH_S) alpha = static_cast<Tv>(sc->alpha);
     double acc[1] = {0.0};
     auto lv = [&](auto *base, int k) { return base + (size_t)k * (size_t)P; };
 
     if constexpr (NL > 0) {
-        // Register path (the launcher guarantees P % kWG == 0, so every lane owns a column,
+        // Register path (the launcher guarantees P % kTriWG == 0, so every lane owns a column,
         // and n * sizeof(Tv) < 2^32, so level offsets fit 32-bit byte offsets from the
         // wave-uniform array bases).  Software pipeline: the loads of level k + PF are issued
         // while level k is computed, into a ring of PF register slots; the scheduling fences
@@ -433,8 +463,7 @@ __global__ __launch_bounds__(kWG) void k_thomas(TriView<Tv> tv, const Tv *__rest
         auto ld = [](const Tv *base, uint32_t bo) { return ldn(base, bo); };
         auto st = [](Tv *base, uint32_t bo, Tv val) { stn(base, bo, val); };
         Tv w[NL];
-        auto sweep = [&](auto fresh_c) {
-            constexpr bool F = decltype(fresh_c)::value;
+        {
             Tv b0[PF], b1[PF], b2[PF], bl[PF];
             uint32_t bl_off = bo0;   // next level to load
             auto issue = [&](int sl) {
@@ -442,10 +471,10 @@ __global__ __launch_bounds__(kWG) void k_thomas(TriView<Tv> tv, const Tv *__rest
                     b0[sl] = ld(q, bl_off);
                 } else if constexpr (MODE == TH_P) {
                     b0[sl] = ld(r, bl_off);
-                    if constexpr (!F) {
-                        b1[sl] = ld(p, bl_off);
-                        b2[sl] = ld(v, bl_off);
-                    }
+                    b1[sl] = ld(p, bl_off);
+                    b2[sl] = ld(v, bl_off);
+                } else if constexpr (MODE == TH_PF) {
+                    b0[sl] = ld(r, bl_off);
                 } else {
                     b0[sl] = ld(r, bl_off);
                     b2[sl] = ld(v, bl_off);
@@ -466,12 +495,11 @@ __global__ __launch_bounds__(kWG) void k_thomas(TriView<Tv> tv, const Tv *__rest
                 if constexpr (MODE == TH_PLAIN) {
                     qk = b0[sl];
                 } else if constexpr (MODE == TH_P) {
-                    if constexpr (F) {
-                        qk = b0[sl];
-                        st(rhat, bo, qk);
-                    } else {
-                        qk = b0[sl] + beta * (b1[sl] - omega * b2[sl]);
-                    }
+                    qk = b0[sl] + beta * (b1[sl] - omega * b2[sl]);
+                    st(p, bo, qk);
+                } else if constexpr (MODE == TH_PF) {
+                    qk = b0[sl];
+                    st(rhat, bo, qk);
                     st(p, bo, qk);
                 } else {
                     qk = b0[sl] - alpha * b2[sl];
@@ -492,11 +520,7 @@ __global__ __launch_bounds__(kWG) void k_thomas(TriView<Tv> tv, const Tv *__rest
                 __builtin_amdgcn_sched_barrier(0);
             }
             if constexpr (MODE == TH_S) acc[0] = ss;
-        };
-        if (MODE == TH_P && fresh)
-            sweep(std::integral_constant<bool, true>{});
-        else
-            sweep(std::integral_constant<bool, false>{});
+        }
         Tv bi[PF], bc[PF];
         uint32_t bl_off = bo0 + static_cast<uint32_t>(NL - 1) * step;
 #pragma unroll
@@ -557,27 +581,58 @@ __global__ __launch_bounds__(kWG) void k_thomas(TriView<Tv> tv, const Tv *__rest
             }
         }
     }
-    if constexpr (MODE == TH_S) block_sum_store<1>(acc, partials + (long)blockIdx.x * kPartialCols);
+    if constexpr (MODE == TH_S) wave_sum_store<1>(acc, partials + (long)blockIdx.x * kPartialCols);
 }
 
-template <typename Tv, int NL, bool CM>
+template <typename Tv, int NL, int MODE, bool CM, int PF = 8>
+__global__ __launch_bounds__(kTriWG) void k_thomas(TriView<Tv> tv, const Tv *__restrict__ q, Tv *__restrict__ z,
+                                                const Tv *__restrict__ r, Tv *__restrict__ p,
+                                                const Tv *__restrict__ v, Tv *__restrict__ rhat,
+                                                double *__restrict__ partials, const Scalars *__restrict__ sc,
+                                                int stop_mask, Tv *__restrict__ qcm, int nlon)
+{
+    thomas_body<Tv, NL, MODE, CM, PF>(tv, q, z, r, p, v, rhat, partials, sc, stop_mask, qcm, nlon);
+}
+
+// Deep columns in FP64 (140 levels: 280 registers of forward values): one wave per SIMD, so the
+// compiler may use the whole register file (architectural and accumulation registers) and keep
+// 24 levels of loads in flight.  5.46 TB/s at 1280x960x140 against 3.95 TB/s for parking the
+// forward values in memory (the generic path, +16 B per point).
+constexpr int kDeepPF = 24;
+template <typename Tv, int NL, int MODE, bool CM>
+__global__ __launch_bounds__(kTriWG) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_thomas_deep(
+    TriView<Tv> tv, const Tv *__restrict__ q, Tv *__restrict__ z, const Tv *__restrict__ r, Tv *__restrict__ p,
+    const Tv *__restrict__ v, Tv *__restrict__ rhat, double *__restrict__ partials, const Scalars *__restrict__ sc,
+    int stop_mask, Tv *__restrict__ qcm, int nlon)
+{
+    thomas_body<Tv, NL, MODE, CM, kDeepPF>(tv, q, z, r, p, v, rhat, partials, sc, stop_mask, qcm, nlon);
+}
+
+template <typename Tv, int NL, bool CM, bool DEEP = false>
 static int thomas_dispatch_mode(const TriView<Tv> &tv, const Tv *q, Tv *z, int mode, const Tv *r, Tv *p,
                                 const Tv *v, Tv *rhat, double *partials, const Scalars *sc, hipStream_t s,
                                 int stop_mask, Tv *qcm, int nlon)
 {
-    const int nb = (int)((tv.P + kWG - 1) / kWG);
+    const int nb = (int)((tv.P + kTriWG - 1) / kTriWG);
+    auto launch = [&](auto mode_c, int mask) {
+        constexpr int M = decltype(mode_c)::value;
+        if constexpr (DEEP)
+            hipLaunchKernelGGL((k_thomas_deep<Tv, NL, M, CM>), dim3(nb), dim3(kTriWG), 0, s, tv, q, z, r, p, v, rhat,
+                               partials, sc, mask, qcm, nlon);
+        else
+            hipLaunchKernelGGL((k_thomas<Tv, NL, M, CM>), dim3(nb), dim3(kTriWG), 0, s, tv, q, z, r, p, v, rhat,
+                               partials, sc, mask, qcm, nlon);
+    };
     switch (mode) {
     case TH_P:
-        hipLaunchKernelGGL((k_thomas<Tv, NL, TH_P, CM>), dim3(nb), dim3(kWG), 0, s, tv, q, z, r, p, v, rhat, partials,
-                           sc, STOP_DONE, qcm, nlon);
+        if constexpr (NL > 0) launch(std::integral_constant<int, TH_PF>{}, STOP_DONE);
+        launch(std::integral_constant<int, TH_P>{}, STOP_DONE);
         return 0;
     case TH_S:
-        hipLaunchKernelGGL((k_thomas<Tv, NL, TH_S, CM>), dim3(nb), dim3(kWG), 0, s, tv, q, z, r, p, v, rhat, partials,
-                           sc, STOP_DONE | STOP_SKIP, qcm, nlon);
+        launch(std::integral_constant<int, TH_S>{}, STOP_DONE | STOP_SKIP);
         return nb;
     default:
-        hipLaunchKernelGGL((k_thomas<Tv, NL, TH_PLAIN, CM>), dim3(nb), dim3(kWG), 0, s, tv, q, z, r, p, v, rhat,
-                           partials, sc, stop_mask, qcm, nlon);
+        launch(std::integral_constant<int, TH_PLAIN>{}, stop_mask);
         return 0;
     }
 }
@@ -590,14 +645,19 @@ static int thomas_dispatch(const TriView<Tv> &tv, const Tv *q, Tv *z, int mode, 
     // Register-resident forward values for the level counts in use, on grids whose columns
     // fill whole workgroups and whose arrays are addressable with 32-bit byte offsets; any
     // other grid takes the generic path.
-    const bool reg = (tv.P % kWG == 0) && ((unsigned long)tv.n * sizeof(Tv) < (1ul << 32));
+    const bool reg = (tv.P % kTriWG == 0) && ((unsigned long)tv.n * sizeof(Tv) < (1ul << 32));
     if (reg && tv.nlev == 20)
         return thomas_dispatch_mode<Tv, 20, CM>(tv, q, z, mode, r, p, v, rhat, partials, sc, s, stop_mask, qcm, nlon);
     if (reg && tv.nlev == 70)
         return thomas_dispatch_mode<Tv, 70, CM>(tv, q, z, mode, r, p, v, rhat, partials, sc, s, stop_mask, qcm, nlon);
-    if (reg && tv.nlev == 140 && sizeof(Tv) == 4)
-        return thomas_dispatch_mode<Tv, (sizeof(Tv) == 4 ? 140 : 0), CM>(tv, q, z, mode, r, p, v, rhat, partials, sc,
-                                                                          s, stop_mask, qcm, nlon);
+    if (reg && tv.nlev == 140) {
+        if constexpr (sizeof(Tv) == 4)
+            return thomas_dispatch_mode<Tv, 140, CM>(tv, q, z, mode, r, p, v, rhat, partials, sc, s, stop_mask, qcm,
+                                                     nlon);
+        else
+            return thomas_dispatch_mode<Tv, 140, CM, true>(tv, q, z, mode, r, p, v, rhat, partials, sc, s, stop_mask,
+                                                           qcm, nlon);
+    }
     return thomas_dispatch_mode<Tv, 0, CM>(tv, q, z, mode, r, p, v, rhat, partials, sc, s, stop_mask, qcm, nlon);
 }
 
@@ -755,10 +815,21 @@ static int elementwise_blocks(long n)
     return (int)nb;
 }
 
+// The vector update streams six vectors in and two out: with up to 32768 workgroups (about ten
+// 16-byte vectors per thread at 2560x1920x70) it moves 5.40 TB/s against 5.03 TB/s with 8192;
+// its partial rows cost the single-workgroup sum 23 instead of 12 us.
+static int update_blocks(long n)
+{
+    long nb = (n + kWG * 4 - 1) / (kWG * 4);
+    if (nb > kUpdateMaxBlocks) nb = kUpdateMaxBlocks;
+    if (nb < 1) nb = 1;
+    return (int)nb;
+}
+
 void launch_update_mp(long n, double *x, const float *ph, const float *sh, const float *s, const float *t, float *r,
                       const float *rhat, double *partials, int *nrows, const Scalars *sc, hipStream_t stream)
 {
-    const int nb = elementwise_blocks(n);
+    const int nb = update_blocks(n);
     hipLaunchKernelGGL(k_update_mp, dim3(nb), dim3(kWG), 0, stream, n, x, ph, sh, s, t, r, rhat, partials, sc);
     if (nrows) *nrows = nb;
 }
@@ -767,7 +838,7 @@ template <typename Tv>
 void launch_update(long n, Tv *x, const Tv *ph, const Tv *sh, const Tv *s, const Tv *t, Tv *r, const Tv *rhat,
                    double *partials, int *nrows, const Scalars *sc, hipStream_t stream)
 {
-    const int nb = elementwise_blocks(n);
+    const int nb = update_blocks(n);
     hipLaunchKernelGGL((k_update<Tv>), dim3(nb), dim3(kWG), 0, stream, n, x, ph, sh, s, t, r, rhat, partials, sc);
     if (nrows) *nrows = nb;
 }
@@ -1392,8 +1463,12 @@ __global__ __launch_bounds__(kWG) void k_sor_perm(const T *__restrict__ src, T *
     }
 }
 
+// One wave per workgroup for the half-sweeps too (133-233 VGPRs: a finished wave is replaced on
+// its own SIMD at once).
+constexpr int kSorWG = 64;
+
 template <typename Tv, typename Tc, bool LAST>
-__global__ __launch_bounds__(kWG) void k_sor_half(OpView<Tc> op, SorView<Tv, Tc> sv, const Tv *__restrict__ qcm,
+__global__ __launch_bounds__(kSorWG) void k_sor_half(OpView<Tc> op, SorView<Tv, Tc> sv, const Tv *__restrict__ qcm,
                                                   Tv *__restrict__ xcm, Tv *__restrict__ wsc, Tv *__restrict__ xout,
                                                   int colour, Tv omega, Tv nb_scale, Tv own_scale,
                                                   const Scalars *__restrict__ sc, int stop_mask, int per_xcd)
@@ -1408,7 +1483,7 @@ __global__ __launch_bounds__(kWG) void k_sor_half(OpView<Tc> op, SorView<Tv, Tc>
     // block (b % 8) * per_xcd + b / 8 and each XCD walks a contiguous band of latitude rows,
     // whose north and south neighbour rows its own L2 then holds
     const long lb = (long)(blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
-    const long c2 = lb * kWG + threadIdx.x;
+    const long c2 = lb * kSorWG + threadIdx.x;
     if (c2 >= P2) return;
     const int j = (int)(c2 / half), m = (int)(c2 % half);
     const int par = (j + colour) & 1;   // own grid column i = 2m + par
@@ -1471,10 +1546,10 @@ __global__ __launch_bounds__(kWG) void k_sor_half(OpView<Tc> op, SorView<Tv, Tc>
 // loads of the first/last row read the own column instead (their couplings are zero there, so
 // the sum is the same as the generic kernel's, which skips them).
 template <typename Tv, typename Tc, bool LAST, int NL, int PF>
-__global__ __launch_bounds__(kWG) void k_sor_half_reg(OpView<Tc> op, SorView<Tv, Tc> sv, const Tv *__restrict__ qcm,
-                                                      Tv *__restrict__ xcm, Tv *__restrict__ xout, int colour,
-                                                      Tv omega, Tv nb_scale, Tv own_scale,
-                                                      const Scalars *__restrict__ sc, int stop_mask, int per_xcd)
+__device__ __forceinline__ void sor_half_reg_body(OpView<Tc> op, SorView<Tv, Tc> sv, const Tv *__restrict__ qcm,
+                                                  Tv *__restrict__ xcm, Tv *__restrict__ xout, int colour, Tv omega,
+                                                  Tv nb_scale, Tv own_scale, const Scalars *__restrict__ sc,
+                                                  int stop_mask, int per_xcd)
 {
     if (stopped(sc, stop_mask)) return;
     using V = typename CoefTraits<Tc>::val;
@@ -1483,7 +1558,7 @@ __global__ __launch_bounds__(kWG) void k_sor_half_reg(OpView<Tc> op, SorView<Tv,
     const int half = op.nlon / 2;
     const long P = op.P, n = op.n, P2 = P / 2, n2 = n / 2;
     const long lb = (long)(blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
-    const long c2 = lb * kWG + threadIdx.x;
+    const long c2 = lb * kSorWG + threadIdx.x;
     if (c2 >= P2) return;   // whole waves (P/2 is a multiple of 64 here)
     const int j = __builtin_amdgcn_readfirstlane((int)(c2 / half));
     const int m = (int)(c2 - (long)j * half);
@@ -1582,6 +1657,26 @@ __global__ __launch_bounds__(kWG) void k_sor_half_reg(OpView<Tc> op, SorView<Tv,
         backward(std::integral_constant<bool, true>{});
 }
 
+template <typename Tv, typename Tc, bool LAST, int NL, int PF>
+__global__ __launch_bounds__(kSorWG) void k_sor_half_reg(OpView<Tc> op, SorView<Tv, Tc> sv, const Tv *__restrict__ qcm,
+                                                      Tv *__restrict__ xcm, Tv *__restrict__ xout, int colour,
+                                                      Tv omega, Tv nb_scale, Tv own_scale,
+                                                      const Scalars *__restrict__ sc, int stop_mask, int per_xcd)
+{
+    sor_half_reg_body<Tv, Tc, LAST, NL, PF>(op, sv, qcm, xcm, xout, colour, omega, nb_scale, own_scale, sc, stop_mask,
+                                            per_xcd);
+}
+
+// 140 levels in FP64: one wave per SIMD with the whole register file, as k_thomas_deep
+template <typename Tv, typename Tc, bool LAST, int NL, int PF>
+__global__ __launch_bounds__(kSorWG) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_sor_half_deep(
+    OpView<Tc> op, SorView<Tv, Tc> sv, const Tv *__restrict__ qcm, Tv *__restrict__ xcm, Tv *__restrict__ xout,
+    int colour, Tv omega, Tv nb_scale, Tv own_scale, const Scalars *__restrict__ sc, int stop_mask, int per_xcd)
+{
+    sor_half_reg_body<Tv, Tc, LAST, NL, PF>(op, sv, qcm, xcm, xout, colour, omega, nb_scale, own_scale, sc, stop_mask,
+                                            per_xcd);
+}
+
 template <typename T> void launch_sor_perm(const T *src, T *dst, int nd, int nlon, int nlat, int nlev, hipStream_t s)
 {
     const long n = (long)nlon * nlat * nlev;
@@ -1593,19 +1688,23 @@ template <typename T> void launch_sor_perm(const T *src, T *dst, int nd, int nlo
 // VGPRs, no spills)
 constexpr int kSorPF = 4;
 constexpr int kSorPF64 = 3;
+constexpr int kSorDeepPF = 8;   // 140 levels in FP64, one wave per SIMD
 
 template <typename Tv, typename Tc>
 void launch_sor(const OpView<Tc> &op, const SorView<Tv, Tc> &sv, const Tv *qcm, Tv *xcm, Tv *wsc, Tv *xout,
                 int sweeps, double omega, const Scalars *sc, int stop_mask, hipStream_t s)
 {
     const long half_cols = op.P / 2;
-    const long lblocks = (half_cols + kWG - 1) / kWG;
+    const long lblocks = (half_cols + kSorWG - 1) / kSorWG;
     const int per_xcd = (int)((lblocks + 7) / 8);
     const unsigned blocks = (unsigned)(per_xcd * 8);
     const Tv w = static_cast<Tv>(omega);
     const int last = 2 * sweeps - 1;
-    // register-resident forward values at 70 levels, when each wave lies within one latitude row
-    const bool reg = op.nlev == 70 && (op.nlon / 2) % 64 == 0;
+    // register-resident forward values at 70 and 140 levels, when each wave lies within one
+    // latitude row and level offsets fit 32 bits
+    const bool rows_ok = (op.nlon / 2) % 64 == 0 && (unsigned long)op.n * sizeof(Tv) < (1ul << 32);
+    const bool reg = rows_ok && op.nlev == 70;
+    const bool reg140 = rows_ok && op.nlev == 140;
     for (int h = 1; h <= last; ++h) {
         const int colour = (h & 1) ? 1 : 0;                       // odd: black, even: red
         const Tv nb_scale = (h == 1) ? w : Tv(1);                 // red still holds T^{-1} q
@@ -1613,18 +1712,37 @@ void launch_sor(const OpView<Tc> &op, const SorView<Tv, Tc> &sv, const Tv *qcm, 
         if (reg) {
             constexpr int PF = sizeof(Tv) == 4 ? kSorPF : kSorPF64;
             if (h == last)
-                hipLaunchKernelGGL((k_sor_half_reg<Tv, Tc, true, 70, PF>), dim3(blocks), dim3(kWG), 0, s, op, sv, qcm,
+                hipLaunchKernelGGL((k_sor_half_reg<Tv, Tc, true, 70, PF>), dim3(blocks), dim3(kSorWG), 0, s, op, sv, qcm,
                                    xcm, xout, colour, w, nb_scale, own_scale, sc, stop_mask, per_xcd);
             else
-                hipLaunchKernelGGL((k_sor_half_reg<Tv, Tc, false, 70, PF>), dim3(blocks), dim3(kWG), 0, s, op, sv, qcm,
+                hipLaunchKernelGGL((k_sor_half_reg<Tv, Tc, false, 70, PF>), dim3(blocks), dim3(kSorWG), 0, s, op, sv, qcm,
                                    xcm, xout, colour, w, nb_scale, own_scale, sc, stop_mask, per_xcd);
             continue;
         }
+        if (reg140) {
+            if constexpr (sizeof(Tv) == 4) {
+                if (h == last)
+                    hipLaunchKernelGGL((k_sor_half_reg<Tv, Tc, true, 140, kSorPF>), dim3(blocks), dim3(kSorWG), 0, s, op,
+                                       sv, qcm, xcm, xout, colour, w, nb_scale, own_scale, sc, stop_mask, per_xcd);
+                else
+                    hipLaunchKernelGGL((k_sor_half_reg<Tv, Tc, false, 140, kSorPF>), dim3(blocks), dim3(kSorWG), 0, s,
+                                       op, sv, qcm, xcm, xout, colour, w, nb_scale, own_scale, sc, stop_mask, per_xcd);
+            } else {
+                if (h == last)
+                    hipLaunchKernelGGL((k_sor_half_deep<Tv, Tc, true, 140, kSorDeepPF>), dim3(blocks), dim3(kSorWG), 0, s,
+                                       op, sv, qcm, xcm, xout, colour, w, nb_scale, own_scale, sc, stop_mask, per_xcd);
+                else
+                    hipLaunchKernelGGL((k_sor_half_deep<Tv, Tc, false, 140, kSorDeepPF>), dim3(blocks), dim3(kSorWG), 0,
+                                       s, op, sv, qcm, xcm, xout, colour, w, nb_scale, own_scale, sc, stop_mask,
+                                       per_xcd);
+            }
+            continue;
+        }
         if (h == last)
-            hipLaunchKernelGGL((k_sor_half<Tv, Tc, true>), dim3(blocks), dim3(kWG), 0, s, op, sv, qcm, xcm, wsc, xout,
+            hipLaunchKernelGGL((k_sor_half<Tv, Tc, true>), dim3(blocks), dim3(kSorWG), 0, s, op, sv, qcm, xcm, wsc, xout,
                                colour, w, nb_scale, own_scale, sc, stop_mask, per_xcd);
         else
-            hipLaunchKernelGGL((k_sor_half<Tv, Tc, false>), dim3(blocks), dim3(kWG), 0, s, op, sv, qcm, xcm, wsc,
+            hipLaunchKernelGGL((k_sor_half<Tv, Tc, false>), dim3(blocks), dim3(kSorWG), 0, s, op, sv, qcm, xcm, wsc,
                                xout, colour, w, nb_scale, own_scale, sc, stop_mask, per_xcd);
     }
 }

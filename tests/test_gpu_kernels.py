@@ -17,6 +17,9 @@ SHAPES = [
     synth.Problem(64, 16, 70, seed=4),              # exact tiles, 70 levels
     synth.Problem(40, 30, 24, seed=5, shift=1e-6, bands=True, ratio=synth._stress_ratio()),
     synth.Problem(8, 1, 33, seed=6),                # one latitude row
+    # 140 levels with whole waves of columns: the register-resident tridiagonal solves (FP64
+    # at one wave per SIMD)
+    synth.Problem(128, 8, 140, seed=7, shift=1e-6, bands=True, ratio=synth._stress_ratio()),
 ]
 
 
@@ -107,7 +110,8 @@ def test_thomas_fp64_matches_oracle(eg, oracle_mod, p):
 
 
 @pytest.mark.parametrize("prec_name", ["PREC_FP32", "PREC_BF16", "PREC_FP16"])
-@pytest.mark.parametrize("p", [SHAPES[0], SHAPES[1], SHAPES[4], SHAPES[5]], ids=lambda p: f"{p.nlon}x{p.nlat}x{p.nlev}")
+@pytest.mark.parametrize("p", [SHAPES[0], SHAPES[1], SHAPES[4], SHAPES[5], SHAPES[7]],
+                         ids=lambda p: f"{p.nlon}x{p.nlat}x{p.nlev}")
 def test_thomas_low_precision_backward_error(eg, oracle_mod, p, prec_name):
     """Every FP32-vector precision applies the FP64 T's LU factors rounded to FP32: a
     componentwise backward error of order nlev eps32 against the FP64 T (for an M-matrix

@@ -390,9 +390,11 @@ def test_learned_modes_reach_1e8(eg, oracle_mod, trained, mode_name, method):
 
 
 def test_trained_network_gain(eg, oracle_mod, trained):
-    """What the trained network gains over the same Krylov method without it, on operators it
-    never saw: FGMRES(30) with M = T^{-1}(q + rho delta(q)) against FGMRES(30) with T^{-1}
-    (and, reported beside them, flexible BiCGStab against plain BiCGStab)."""
+    """What the trained network gains over the method without it, on operators it never saw:
+    FGMRES(30) with M = T^{-1}(q + rho delta(q)) against FGMRES(30) with T^{-1} (asserted: at
+    least 10 % fewer iterations), and the time-to-solve of every combination against BiCGStab
+    with T^{-1}, the solver the network is meant to beat (reported: on these grids the network's
+    cost per application outweighs the iterations it saves)."""
     import time
     import torch
     rows = []
@@ -409,9 +411,12 @@ def test_trained_network_gain(eg, oracle_mod, trained):
                 op.set_option("learned_method", method)
                 for mode, tag in ((eg.FP64, "tri"), (eg.LEARNED_FP64, "learned")):
                     x = torch.zeros(p.n, dtype=torch.float64, device="cuda")
+                    op.solve(dev(b), x, 1e-8, 5000, mode)          # untimed: buffers
+                    x.zero_()
                     torch.cuda.synchronize()
                     t0 = time.perf_counter()
                     info = op.solve(dev(b), x, 1e-8, 5000, mode)
+                    torch.cuda.synchronize()
                     dt = time.perf_counter() - t0
                     rel = np.linalg.norm(b - oracle_mod.apply(coef, host(x))) / np.linalg.norm(b)
                     assert info.status == eg.CONVERGED and rel <= 1e-8
@@ -421,6 +426,10 @@ def test_trained_network_gain(eg, oracle_mod, trained):
     tri = np.mean([r["fgmres_tri"][0] for r in rows])
     learned = np.mean([r["fgmres_learned"][0] for r in rows])
     print(f"FGMRES iterations: T^-1 {tri:.1f}, learned {learned:.1f} ({100 * (1 - learned / tri):.0f}% fewer)")
+    base = np.mean([r["bicgstab_tri"][2] for r in rows])
+    for key in ("fgmres_tri", "fgmres_learned", "bicgstab_learned"):
+        print(f"time-to-solve {key}: {np.mean([r[key][2] for r in rows]) / base:.2f} x BiCGStab with T^-1 "
+              f"({1e3 * base:.2f} ms)")
     assert learned <= 0.9 * tri and all(r["fgmres_learned"][1] == 0 for r in rows)
 
 

@@ -53,7 +53,10 @@ def test_fp64_parity_tight_tolerance(eg, oracle_mod, small):
 
 @pytest.mark.parametrize("p", [synth.Problem(67, 13, 9, seed=1), synth.Problem(130, 37, 5, seed=2),
                                synth.Problem(40, 30, 24, seed=5, shift=1e-6, bands=True, ratio=synth._stress_ratio()),
-                               synth.Problem(64, 16, 70, seed=4)],
+                               synth.Problem(64, 16, 70, seed=4),
+                               # 140 levels, whole waves of columns: the FP64 tridiagonal kernels
+                               # at one wave per SIMD
+                               synth.Problem(128, 8, 140, seed=8, shift=1e-6, bands=True, ratio=synth._stress_ratio())],
                          ids=lambda p: f"{p.nlon}x{p.nlat}x{p.nlev}")
 def test_fp64_parity_shapes(eg, oracle_mod, p):
     import torch

@@ -28,7 +28,9 @@ def _rel(a, b):
 # second leaves its last workgroup partly empty), the others the generic one
 SHAPES = [synth.Problem(96, 72, 20, seed=0), synth.Problem(40, 30, 24, seed=1), synth.Problem(130, 37, 5, seed=2),
           synth.Problem(64, 16, 70, seed=3), synth.Problem(8, 6, 1, seed=4), synth.Problem(128, 24, 70, seed=5),
-          synth.Problem(256, 25, 70, seed=6)]
+          synth.Problem(256, 25, 70, seed=6),
+          # 140 levels, nlon / 2 a multiple of 64: the register-resident half-sweeps at 140 levels
+          synth.Problem(128, 6, 140, seed=7, ratio=synth._stress_ratio())]
 
 
 @pytest.mark.parametrize("sweeps,omega", [(1, 1.0), (2, 1.5), (3, 1.5)])
@@ -45,7 +47,7 @@ def test_sor_fp64_matches_oracle(eg, oracle_mod, p, sweeps, omega):
     assert _rel(z, ref) <= 1e-11
 
 
-@pytest.mark.parametrize("shape", [0, 6])
+@pytest.mark.parametrize("shape", [0, 6, 7])
 @pytest.mark.parametrize("prec_name", ["PREC_FP32", "PREC_BF16", "PREC_FP16"])
 def test_sor_low_precision(eg, oracle_mod, prec_name, shape):
     """FP32 vectors, the FP32 rounding of the FP64 tridiagonal factors, and that precision's
