@@ -3,15 +3,16 @@ the HBM roofline fraction of the dominant kernel and the CPU oracle as a reporte
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--config n1280_2560x1920x70] [--modes fp64,fp32_ir,...]
 
-A step solves A x = b once in every listed mode (x0 = 0); a "_sor" suffix selects the red-black
-vertical-line SOR preconditioner (three sweeps, omega 1.5) instead of the tridiagonal solve.
-Inputs (operator and right-hand side) are generated on the host from the seeded recipe, copied to HBM and the operator is built
-before the timed region.  Learned modes first train the network (untimed, reported): FGMRES
-bases harvested from small operators of the same recipe, Adam on the residual-space loss.
-After the timed steps, the learned preconditioner is compared with the tridiagonal one on its
-own workload (640x480x70 by default): plain BiCGStab, flexible BiCGStab with the learned
-preconditioner and FGMRES(30) with either, in FP32 with FP64 refinement and in FP64.  One JSON
-line is printed on stdout.
+A step solves A x = b once in every listed mode (x0 = 0) on the 2560x1920x70 grid: FP64, FP32
+inner iterations with FP64 refinement, and the same with BF16 couplings, all with the vertical
+tridiagonal preconditioner; `value` is the sum of these times-to-solve.  Inputs are generated
+on the host from the seeded recipe, copied to HBM and the operator is built before the timed
+region.  After the timed steps, each once (after one untimed solve): the same modes with the
+red-black line-SOR preconditioner ("_sor" suffix: three sweeps, omega 1.5) and the learned
+preconditioner's modes on the same grid; the paper's Table 1 comparison (DP against its MP
+BiCGStab); the learned preconditioner against the tridiagonal one on its own workload
+(640x480x70) for two training recipes; the stress case (1280x960x140); and the CPU oracle,
+timed on the host while those legs run.  One JSON line is printed on stdout.
 """
 from __future__ import annotations
 
@@ -69,8 +70,11 @@ MEASURED_TRAFFIC = {("n1280_2560x1920x70", "spmv_fp64"): 28.74e9, ("n1280_2560x1
                     ("n1280_2560x1920x70", "sor_fp64"): 80.83e9, ("n1280_2560x1920x70", "sor_fp32"): 39.62e9, ("n1280_2560x1920x70", "sor_bf16"): 32.77e9}
 
 
+_T_START = time.perf_counter()
+
+
 def log(*a):
-    print(*a, file=sys.stderr, flush=True)
+    print(f"[{time.perf_counter() - _T_START:7.1f} s]", *a, file=sys.stderr, flush=True)
 
 
 def generate_on_device(p, torch):
@@ -117,41 +121,101 @@ def _cpu_model() -> str:
     return "unknown"
 
 
-def cpu_baseline(n_target: int, iterations: int, sample_iters: int = 20):
-    """Single-thread oracle BiCGStab on a 640x480x70 grid of the same recipe for a fixed number
-    of iterations; scaled per point and iteration to the benchmark grid."""
+def cpu_baseline(gpu_fp64_iterations: int, sample_iters: int = 5):
+    """The oracle (single-threaded C, -O2, no FMA contraction) on the host: a full FP64 solve of
+    the 96x72x20 problem, and a timed sample of `sample_iters` iterations on the benchmark's
+    own 2560x1920x70 grid, scaled to the GPU's FP64 iteration count (extrapolated); the
+    640x480x70 figure of the same kind is kept as context.  Per-iteration time = (time of a
+    `sample_iters`-iteration run - 2 x one matrix-vector product) / `sample_iters` (the run
+    forms the initial and the final true residual besides its iterations)."""
     import numpy as np
 
     import oracle
     import synth
-    sp = synth.Problem(640, 480, 70, seed=0)
-    coef = synth.make_coeffs(sp, threads=8)
-    b = synth.make_rhs(sp).ravel()
-    # difference of two runs removes the set-up and final true-residual products
+
+    def per_iteration(p, threads):
+        coef = synth.make_coeffs(p, threads=threads)
+        b = synth.make_rhs(p).ravel()
+        t0 = time.perf_counter()
+        oracle.apply(coef, b)
+        t_apply = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        _, info = oracle.bicgstab(coef, b, tol=1e-30, maxit=sample_iters)
+        t_run = time.perf_counter() - t0
+        del coef, b
+        return (t_run - 2 * t_apply) / sample_iters, t_run, info.iterations
+
+    out = {"unit": "s", "cores": 1, "kind": "oracle", "cpu_model": _cpu_model(), "host_threads": os.cpu_count()}
+    p1 = synth.CONFIGS["small_96x72x20"]
+    c1 = synth.make_coeffs(p1)
+    b1 = synth.make_rhs(p1).ravel()
     t0 = time.perf_counter()
-    oracle.bicgstab(coef, b, tol=1e-30, maxit=1)
-    t1 = time.perf_counter()
-    _, info = oracle.bicgstab(coef, b, tol=1e-30, maxit=1 + sample_iters)
-    t2 = time.perf_counter()
-    dt = (t2 - t1) - (t1 - t0)
-    per_pt_iter = dt / (sample_iters * sp.n)
-    return {
-        "value": per_pt_iter * n_target * iterations,
-        "unit": "s",
-        "cores": 1,
-        "kind": "oracle",
-        "cpu_model": _cpu_model(),
-        "host_threads": os.cpu_count(),
-        "sample": (f"oracle FP64 BiCGStab + T^-1, {sample_iters} iterations (difference of a {1 + sample_iters}- and a 1-iteration "
-                   f"run) on the 640x480x70 grid of the same recipe ({dt:.1f} s, 1 thread); scaled by grid size to {n_target} points and by this run's FP64 "
-                   f"iteration count ({iterations}); extrapolated, not a full CPU solve"),
-    }
+    _, i1 = oracle.bicgstab(c1, b1, tol=1e-8)
+    out["small_96x72x20_full_solve"] = {"seconds": round(time.perf_counter() - t0, 3), "iterations": i1.iterations,
+                                        "true_rel_residual": i1.true_rel_residual}
+    del c1, b1
+    it2, _, _ = per_iteration(synth.CONFIGS["manufactured_640x480x70"], 16)
+    out["context_640x480x70_seconds_per_iteration"] = round(it2, 3)
+    it3, t_run, nits = per_iteration(synth.CONFIGS["n1280_2560x1920x70"], 8)
+    out["n1280_seconds_per_iteration"] = round(it3, 2)
+    out["value"] = round(it3 * gpu_fp64_iterations, 1)
+    out["sample"] = (f"oracle FP64 BiCGStab + T^-1 on the 2560x1920x70 grid itself: a {nits}-iteration run took "
+                     f"{t_run:.1f} s (1 thread), {it3:.2f} s per iteration after the two true-residual products; "
+                     f"value = that x the GPU's FP64 iteration count ({gpu_fp64_iterations}): extrapolated, not a full "
+                     f"CPU solve; timed on the host while the GPU legs after the timed steps ran")
+    return out
 
 
-def train_network(eg, torch, shape, nops, nvec, epochs, seed=1):
-    """Harvest FGMRES bases from `nops` operators of the recipe at `shape` and train a network."""
-    import numpy as np
+def train_error_recipe(eg, torch, nops=100, nsnap=20, nval=10, epochs=20, lr=1e-3, batch=16, seed=1):
+    """The learned preconditioner's configured recipe: (r_i, e_i = x* - x_i) pairs from the
+    first nsnap iterates of FP64 BiCGStab solves (eg_harvest) on nops operators of the
+    96x72x20 recipe with fresh perturbation seeds (1000 + s) and right-hand sides (seed 2000 + s);
+    the last nval operators' pairs are held out for validation; Adam on the error-space loss
+    ||M(r) - e||^2 / ||e||^2."""
+    import synth
+    t0 = time.perf_counter()
+    ops, rs, es, owner = [], [], [], []
+    for s in range(nops):
+        p = synth.Problem(96, 72, 20, seed=1000 + s)
+        op = eg.Operator(torch.from_numpy(synth.make_coeffs(p, threads=16)).cuda())
+        r, e = op.harvest(torch.from_numpy(synth.make_rhs(p, seed=2000 + s).ravel()).cuda(), nsnap)
+        ops.append(op)
+        rs.append(r)
+        es.append(e)
+        owner += [s] * r.shape[0]
+    ntrain_ops = nops - nval
+    ntr = sum(int(r.shape[0]) for r in rs[:ntrain_ops])
+    r = torch.cat(rs).contiguous()
+    e = torch.cat(es).contiguous()
+    del rs, es
+    torch.cuda.synchronize()
+    t_harvest = time.perf_counter() - t0
+    net = eg.Net(11)
+    net.set_loss(eg.Net.LOSS_ERROR)
+    rv, ev, ov = r[ntr:].contiguous(), e[ntr:].contiguous(), [o - ntrain_ops for o in owner[ntr:]]
+    val0 = net.eval(ops[ntrain_ops:], rv, ev, ov)
+    t0 = time.perf_counter()
+    hist = net.train(ops[:ntrain_ops], r[:ntr].contiguous(), e[:ntr].contiguous(), owner[:ntr], epochs=epochs,
+                     batch=batch, lr=lr, seed=seed)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    val1 = net.eval(ops[ntrain_ops:], rv, ev, ov)
+    for op in ops:
+        op.close()
+    info = {"recipe": "error", "shape": [96, 72, 20], "operators": nops, "iterates_per_solve": nsnap,
+            "pairs_train": ntr, "pairs_validation": int(rv.shape[0]), "epochs": epochs, "batch": batch, "lr": lr,
+            "loss": "||M(r) - e||^2 / ||e||^2",
+            "loss_train_first_epoch": round(float(hist[0]), 4), "loss_train_last_epoch": round(float(hist[-1]), 4),
+            "loss_validation_untrained": round(val0, 4), "loss_validation_trained": round(val1, 4),
+            "harvest_seconds": round(t_harvest, 2), "train_seconds": round(t_train, 2)}
+    del r, e, rv, ev
+    torch.cuda.empty_cache()
+    return net, info
 
+
+def train_krylov_recipe(eg, torch, shape, nops, nvec, epochs, seed=1):
+    """Second recipe: the FGMRES basis vectors (the vectors a Krylov method applies the
+    preconditioner to) of `nops` operators of the recipe at `shape`, residual-space loss."""
     import synth
     t0 = time.perf_counter()
     ops, rs, owner = [], [], []
@@ -175,48 +239,134 @@ def train_network(eg, torch, shape, nops, nvec, epochs, seed=1):
     t_train = time.perf_counter() - t0
     for op in ops:
         op.close()
-    info = {"shape": list(shape), "operators": nops, "vectors_per_operator": nvec, "pairs": int(r.shape[0]),
-            "epochs": epochs, "loss": "||A M(r) - r||^2 / ||r||^2", "loss_untrained": round(loss0, 4),
-            "loss_last_epoch": round(float(hist[-1]), 4), "harvest_seconds": round(t_harvest, 2),
-            "train_seconds": round(t_train, 2)}
+    info = {"recipe": "krylov", "shape": list(shape), "operators": nops, "vectors_per_operator": nvec,
+            "pairs": int(r.shape[0]), "epochs": epochs, "loss": "||A M(r) - r||^2 / ||r||^2",
+            "loss_untrained": round(loss0, 4), "loss_last_epoch": round(float(hist[-1]), 4),
+            "harvest_seconds": round(t_harvest, 2), "train_seconds": round(t_train, 2)}
     del r
     torch.cuda.empty_cache()
     return net, info
 
 
-def learned_comparison(eg, torch, net, cfg_name, tol):
-    """On one workload, in FP32 inner + FP64 refinement and in FP64: plain BiCGStab with T^-1
-    (the baseline), flexible BiCGStab with the learned M (and its tridiagonal fallback), and
-    FGMRES(30) with T^-1 and with the learned M; one warm-up solve each, then one timed solve."""
+def _timed_solve(op, torch, b, x, tol, mode, reps):
+    """One untimed solve, then `reps` timed ones (median); returns (seconds, info)."""
+    x.zero_()
+    op.solve(b, x, tol, 20000, mode)
+    times, info = [], None
+    for _ in range(reps):
+        x.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        info = op.solve(b, x, tol, 20000, mode)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    times.sort()
+    return times[len(times) // 2], info
+
+
+def learned_comparison(eg, torch, nets, cfg_name, tol, reps=3):
+    """On the learned preconditioner's workload, in FP32 inner + FP64 refinement and in FP64:
+    BiCGStab with T^-1 (the method without the network), flexible BiCGStab with each trained
+    network (and the tridiagonal fallback), FGMRES(30) with T^-1 and with each network.  The
+    BiCGStab rows are the median of `reps` timed solves after one untimed solve, the slower
+    FGMRES rows one timed solve after one untimed solve."""
     import synth
     p = synth.CONFIGS[cfg_name]
     coef, b = generate_on_device(p, torch)
     op = eg.Operator(coef)
     del coef
     torch.cuda.empty_cache()
-    op.attach(net)
-    out = {"workload": f"{p.nlon}x{p.nlat}x{p.nlev}, b ~ N(0,1), tol {tol}", "case": cfg_name}
+    out = {"workload": f"{p.nlon}x{p.nlat}x{p.nlev}, b ~ N(0,1), tol {tol}", "case": cfg_name,
+           "timing": f"BiCGStab rows: median of {reps}; FGMRES rows: one solve"}
     x = torch.zeros(p.n, dtype=torch.float64, device="cuda")
-    for name, mode, method in (("bicgstab_tri_fp32_ir", eg.FP32_IR, 0),
-                               ("bicgstab_learned_fp32_ir", eg.LEARNED_FP32_IR, 0),
-                               ("fgmres_tri_fp32_ir", eg.FP32_IR, 1), ("fgmres_learned_fp32_ir", eg.LEARNED_FP32_IR, 1),
-                               ("bicgstab_tri_fp64", eg.FP64, 0), ("bicgstab_learned_fp64", eg.LEARNED_FP64, 0),
-                               ("fgmres_tri_fp64", eg.FP64, 1), ("fgmres_learned_fp64", eg.LEARNED_FP64, 1)):
-        op.set_option("method", method)
-        op.set_option("learned_method", method)
-        x.zero_()
-        op.solve(b, x, tol, 20000, mode)
-        x.zero_()
+    runs = [("bicgstab_tri", None, 0), ("fgmres_tri", None, 1)]
+    for name in nets:
+        runs += [(f"bicgstab_learned_{name}", name, 0), (f"fgmres_learned_{name}", name, 1)]
+    for prec, plain, learned in (("fp32_ir", eg.FP32_IR, eg.LEARNED_FP32_IR), ("fp64", eg.FP64, eg.LEARNED_FP64)):
+        for label, net_name, method in runs:
+            op.attach(nets[net_name] if net_name else None)
+            op.set_option("method", method)
+            op.set_option("learned_method", method)
+            sec, info = _timed_solve(op, torch, b, x, tol, learned if net_name else plain, reps if method == 0 else 1)
+            key = f"{label}_{prec}"
+            out[key] = {"seconds": round(sec, 4), "iterations": info.iterations, "outer_steps": info.outer_steps,
+                        "fallbacks": info.fallbacks, "status": info.status, "true_rel_residual": info.true_rel_residual}
+            log(f"learned comparison {key}: {out[key]}")
+    for prec in ("fp32_ir", "fp64"):
+        base = out[f"bicgstab_tri_{prec}"]["seconds"]
+        for name in nets:
+            for m in ("bicgstab", "fgmres"):
+                e = out[f"{m}_learned_{name}_{prec}"]
+                e["time_vs_bicgstab_tri"] = round(e["seconds"] / base, 3)
+    op.attach(None)
+    op.close()
+    return out
+
+
+def stress_leg(eg, torch, net, cfg_name, tol):
+    """The stress case (1280x960x140, shift 1e-6, vertical diffusivity contrast 1e4): plain FP64
+    BiCGStab with T^-1, FP64 with the line SOR, FP32 inner + FP64 refinement with the line SOR
+    and the learned preconditioner in FP32 + refinement (flexible BiCGStab with its fallback);
+    one timed solve each after the operator's copies are built; every mode's difference from
+    the FP64 + line-SOR solution."""
+    import synth
+    p = synth.CONFIGS[cfg_name]
+    t0 = time.perf_counter()
+    coef, b = generate_on_device(p, torch)
+    op = eg.Operator(coef)
+    del coef
+    torch.cuda.empty_cache()
+    t_gen = time.perf_counter() - t0
+    op.attach(net)
+    op.set_option("learned_method", 0)
+    # build the FP32 and line-SOR copies outside the timed solves
+    q = torch.zeros(p.n, dtype=torch.float32, device="cuda")
+    op.apply(q, torch.empty_like(q), eg.PREC_FP32)
+    op.set_option("precond", 1)
+    op.precond(q, torch.empty_like(q), eg.PREC_FP32)
+    q64 = torch.zeros(p.n, dtype=torch.float64, device="cuda")
+    op.precond(q64, torch.empty_like(q64), eg.PREC_FP64)
+    del q, q64
+    out = {"workload": f"{p.nlon}x{p.nlat}x{p.nlev}, shift {p.shift:g}, vertical diffusivity contrast 1e4, b ~ N(0,1), "
+                       f"tol {tol}", "case": cfg_name, "generate_seconds": round(t_gen, 2), "timing": "one solve each"}
+    sols = {}
+    for name, mode, pc in (("fp64_sor", eg.FP64, 1), ("fp64", eg.FP64, 0), ("fp32_ir_sor", eg.FP32_IR, 1),
+                           ("learned_fp32_ir", eg.LEARNED_FP32_IR, 0)):
+        op.set_option("precond", pc)
+        x = torch.zeros(p.n, dtype=torch.float64, device="cuda")
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         info = op.solve(b, x, tol, 20000, mode)
         torch.cuda.synchronize()
-        out[name] = {"seconds": round(time.perf_counter() - t0, 4), "iterations": info.iterations,
+        out[name] = {"seconds": round(time.perf_counter() - t0, 3), "iterations": info.iterations,
                      "outer_steps": info.outer_steps, "fallbacks": info.fallbacks, "status": info.status,
                      "true_rel_residual": info.true_rel_residual}
-        log(f"learned comparison {name}: {out[name]}")
+        sols[name] = x
+        log(f"stress {name}: {out[name]}")
+    ref = sols["fp64_sor"]
+    nref = torch.linalg.vector_norm(ref).item()
+    for name, x in sols.items():
+        if name != "fp64_sor":
+            out[name]["rel_diff_vs_fp64_sor"] = torch.linalg.vector_norm(x - ref).item() / nref
+    op.attach(None)
     op.close()
+    del sols, ref, x, b
+    torch.cuda.empty_cache()
     return out
+
+
+def gpu_small_fp64(eg, torch, reps=5):
+    """FP64 time-to-solve on the 96x72x20 correctness grid (launch-bound; beside the CPU oracle's
+    full solve of the same problem)."""
+    import synth
+    p = synth.CONFIGS["small_96x72x20"]
+    coef = torch.from_numpy(synth.make_coeffs(p)).cuda()
+    b = torch.from_numpy(synth.make_rhs(p).ravel()).cuda()
+    op = eg.Operator(coef)
+    x = torch.zeros(p.n, dtype=torch.float64, device="cuda")
+    sec, info = _timed_solve(op, torch, b, x, 1e-8, eg.FP64, reps)
+    op.close()
+    return {"seconds": round(sec, 5), "iterations": info.iterations, "true_rel_residual": info.true_rel_residual}
 
 
 def paper_study(eg, torch, op, b):
@@ -230,11 +380,9 @@ def paper_study(eg, torch, op, b):
     op.set_option("sor_omega", 1.5)
     x = torch.zeros_like(b)
     sweep = {}
-    for tol in (1e-3, 1e-4, 1e-5, 1e-6, 1e-7, 1e-8):
+    for tol in (1e-3, 1e-4, 1e-6, 1e-8):
         row = {}
         for name, mode in (("dp", eg.FP64), ("mp", eg.FP32_MP)):
-            x.zero_()
-            op.solve(b, x, tol, 2000, mode)
             x.zero_()
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -264,10 +412,17 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="n1280_2560x1920x70")
-    ap.add_argument("--modes", default="fp64,fp32_ir,fp32_ir_bf16,fp64_sor,fp32_ir_sor,fp32_ir_bf16_sor")
+    ap.add_argument("--modes", default="fp64,fp32_ir,fp32_ir_bf16")
+    ap.add_argument("--extra-modes", default="fp64_sor,fp32_ir_sor,fp32_ir_bf16_sor,learned_fp32_ir",
+                    help="modes timed once each after the timed steps ('' skips them)")
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--learned-config", default="learned_640x480x70", help="workload of the learned-preconditioner comparison ('' skips it)")
+    ap.add_argument("--learned-config", default="learned_640x480x70",
+                    help="workload of the learned-preconditioner comparison ('' skips it)")
+    ap.add_argument("--learned-reps", type=int, default=3)
+    ap.add_argument("--stress-config", default="stress_1280x960x140", help="stress case ('' skips it)")
+    ap.add_argument("--error-ops", type=int, default=100, help="96x72x20 operators of the error-loss recipe")
+    ap.add_argument("--error-epochs", type=int, default=20)
     ap.add_argument("--train-shape", default="160x120x70")
     ap.add_argument("--train-ops", type=int, default=16)
     ap.add_argument("--train-vecs", type=int, default=20)
@@ -281,6 +436,8 @@ def main():
               f"is not built in this framework", file=sys.stderr)
         sys.exit(2)
 
+    import threading
+
     import numpy as np
     import torch
 
@@ -290,52 +447,34 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     p = synth.CONFIGS[args.config]
     if args.traffic_probe:
-        coef, b = generate_on_device(p, torch)
-        op = eg.Operator(coef)
-        del coef
-        x = torch.zeros(p.n, dtype=torch.float64, device="cuda")
-        for m in (eg.FP64, eg.FP32_IR, eg.FP32_IR_BF16):
-            x.zero_()
-            op.solve(b, x, args.tol, 4, m)
-        op.set_option("precond", 1)   # the line-SOR half-sweeps
-        for m in (eg.FP64, eg.FP32_IR, eg.FP32_IR_BF16):
-            x.zero_()
-            op.solve(b, x, args.tol, 2, m)
-        op.set_option("precond", 0)
-        for _ in range(3):
-            x.copy_(b)
-        torch.cuda.synchronize()
-        op.close()
-        del x, b
-        torch.cuda.empty_cache()
-        # three network applications on the learned preconditioner's workload
-        p4 = synth.CONFIGS[args.learned_config or "learned_640x480x70"]
-        coef, _ = generate_on_device(p4, torch)
-        op = eg.Operator(coef)
-        del coef
-        net = eg.Net(11)
-        q = torch.randn(p4.n, dtype=torch.float32, device="cuda", generator=torch.Generator("cuda").manual_seed(5))
-        for _ in range(3):
-            net.apply(op, q)
-        torch.cuda.synchronize()
-        print(json.dumps({"traffic_probe": args.config, "copy_bytes_read": p.n * 8, "copy_bytes_written": p.n * 8,
-                          "net_workload": args.learned_config or "learned_640x480x70"}))
+        traffic_probe(eg, torch, p, args)
         return
     name2mode = {v: k for k, v in eg.MODE_NAMES.items()}
-    # a "_sor" suffix runs the mode with the red-black line SOR preconditioner (option precond 1)
-    runs = []
-    for m in args.modes.split(","):
-        if not m:
-            continue
-        sor = m.endswith("_sor")
-        runs.append((m, name2mode[m[:-4] if sor else m], sor))
-    modes = [mode for _, mode, _ in runs]
 
-    net, training = None, None
-    if args.learned_config or any(m in (eg.LEARNED_FP64, eg.LEARNED_FP32_IR) for m in modes):
-        shape = tuple(int(v) for v in args.train_shape.split("x"))
-        net, training = train_network(eg, torch, shape, args.train_ops, args.train_vecs, args.train_epochs)
-        log(f"trained the network: {training}")
+    def parse_modes(text):
+        # a "_sor" suffix runs the mode with the red-black line SOR preconditioner (option precond 1)
+        out = []
+        for m in text.split(","):
+            if m:
+                sor = m.endswith("_sor")
+                out.append((m, name2mode[m[:-4] if sor else m], sor))
+        return out
+
+    runs = parse_modes(args.modes)
+    extra = parse_modes(args.extra_modes)
+    learned_modes = (eg.LEARNED_FP64, eg.LEARNED_FP32_IR)
+    need_net = bool(args.learned_config or args.stress_config) or any(m in learned_modes for _, m, _ in runs + extra)
+
+    nets, training = {}, {}
+    if need_net:
+        nets["error"], training["error"] = train_error_recipe(eg, torch, nops=args.error_ops,
+                                                              epochs=args.error_epochs)
+        log(f"trained the network (error recipe): {training['error']}")
+        if args.learned_config:
+            shape = tuple(int(v) for v in args.train_shape.split("x"))
+            nets["krylov"], training["krylov"] = train_krylov_recipe(eg, torch, shape, args.train_ops, args.train_vecs,
+                                                                     args.train_epochs)
+            log(f"trained the network (Krylov recipe): {training['krylov']}")
 
     t0 = time.perf_counter()
     coef, b = generate_on_device(p, torch)
@@ -354,8 +493,9 @@ def main():
     scratch = torch.zeros(p.n, dtype=torch.float32, device="cuda")
     out = torch.empty_like(scratch)
     t_setup_low = {}
-    for m in modes:
-        prec = {eg.FP32_IR: eg.PREC_FP32, eg.FP32_IR_BF16: eg.PREC_BF16, eg.FP32_IR_FP16: eg.PREC_FP16}.get(m)
+    for _, m, _ in runs + extra:
+        prec = {eg.FP32_IR: eg.PREC_FP32, eg.FP32_IR_BF16: eg.PREC_BF16, eg.FP32_IR_FP16: eg.PREC_FP16,
+                eg.LEARNED_FP32_IR: eg.PREC_FP32}.get(m)
         if prec is not None and PREC_NAME[prec] not in t_setup_low:
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -364,8 +504,9 @@ def main():
             t_setup_low[PREC_NAME[prec]] = time.perf_counter() - t0
     del scratch, out
 
-    if net is not None:
-        op.attach(net)
+    if "error" in nets:
+        op.attach(nets["error"])
+    op.set_option("learned_method", 0)   # flexible BiCGStab, the method the configuration names
     x = torch.zeros(p.n, dtype=torch.float64, device="cuda")
     for _ in range(args.warmup):
         for name, m, sor in runs:
@@ -396,7 +537,7 @@ def main():
                        "true_rel_residual": None} for name, _, _ in runs}
     torch.cuda.synchronize()
     t_start = time.perf_counter()
-    for _ in range(args.steps):
+    for step in range(args.steps):
         for name, m, sor in runs:
             op.set_option("precond", 1 if sor else 0)
             x.zero_()
@@ -408,10 +549,12 @@ def main():
             d["seconds"].append(time.perf_counter() - ts)
             collect(sor)
             d.update(iterations=info.iterations, outer_steps=info.outer_steps, status=info.status,
-                     true_rel_residual=info.true_rel_residual)
+                     true_rel_residual=info.true_rel_residual, fallbacks=info.fallbacks)
+        log(f"timed step {step + 1}/{args.steps}: " + ", ".join(f"{k} {v['seconds'][-1]:.3f} s" for k, v in per_mode.items()))
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
     ms_per_step = 1000.0 * elapsed / args.steps
+    op.set_option("profile", 0)
 
     # per-kernel achieved bandwidth from the library's HIP-event timing over the timed region
     kernels = {}
@@ -444,24 +587,56 @@ def main():
                         "outer_steps": d["outer_steps"], "status": d["status"],
                         "true_rel_residual": d["true_rel_residual"]}
     fp64_iters = per_mode.get("fp64", {}).get("iterations")
+
+    # the CPU oracle runs on the host while the GPU legs below keep the GPU busy
+    cpu = None
+    cpu_thread = None
+    if not args.no_cpu_baseline:
+        box = {}
+
+        def run_cpu():
+            try:
+                box["result"] = cpu_baseline(fp64_iters or 1)
+            except Exception as exc:   # reported, not fatal to the GPU measurement
+                box["result"] = {"error": repr(exc)}
+
+        log("timing the CPU oracle on the host (background) ...")
+        cpu_thread = threading.Thread(target=run_cpu, daemon=True)
+        cpu_thread.start()
+
+    # the other modes on the same grid, once each after an untimed solve
+    extra_out = {}
+    for name, m, sor in extra:
+        op.set_option("precond", 1 if sor else 0)
+        sec, info = _timed_solve(op, torch, b, x, args.tol, m, 1)
+        extra_out[name] = {"seconds": round(sec, 4), "iterations": info.iterations, "outer_steps": info.outer_steps,
+                           "fallbacks": info.fallbacks, "status": info.status,
+                           "true_rel_residual": info.true_rel_residual}
+        log(f"{args.config} {name}: {extra_out[name]}")
+    op.set_option("precond", 0)
     paper = None if args.no_paper_study else paper_study(eg, torch, op, b)
+    op.attach(None)
     op.close()
     del x, b
     torch.cuda.empty_cache()
 
+    small = gpu_small_fp64(eg, torch)
     learned = None
     if args.learned_config:
-        learned = learned_comparison(eg, torch, net, args.learned_config, args.tol)
+        learned = learned_comparison(eg, torch, nets, args.learned_config, args.tol, args.learned_reps)
         learned["training"] = training
-
-    cpu = None
-    if not args.no_cpu_baseline:
-        log("timing the CPU oracle on a sample ...")
-        cpu = cpu_baseline(p.n, fp64_iters or 1)
+    stress = None
+    if args.stress_config:
+        stress = stress_leg(eg, torch, nets.get("error"), args.stress_config, args.tol)
+    if cpu_thread is not None:
+        cpu_thread.join()
+        cpu = box["result"]
+        if "small_96x72x20_full_solve" in cpu:
+            cpu["small_96x72x20_gpu_fp64"] = small
 
     dtypes = sorted({{eg.FP64: "f64", eg.FP32_IR: "f64+f32", eg.FP32_IR_BF16: "f64+f32+bf16",
                       eg.FP32_IR_FP16: "f64+f32+f16", eg.LEARNED_FP64: "f64+bf16mfma",
-                      eg.LEARNED_FP32_IR: "f64+f32+bf16mfma"}[m] for m in modes})
+                      eg.LEARNED_FP32_IR: "f64+f32+bf16mfma", eg.FP32_MP: "f64+f32"}[m] for _, m, _ in runs})
     result = {
         "metric": "time-to-solve at ||r||/||b||<=1e-8, FP64 vs mixed vs learned-PC; HBM GB/s",
         "value": round(ms_per_step / 1000.0, 4),
@@ -476,18 +651,61 @@ def main():
         "dtype": ",".join(dtypes),
         "data": "synthetic (seeded operator recipe and b ~ N(0,1); no UM data)",
         "config": {"workload": f"{p.nlon}x{p.nlat}x{p.nlev} Helmholtz solve to 1e-8, one solve per mode "
-                               f"({','.join(name for name, _, _ in runs)})", "case": args.config,
-                   "grid": [p.nlon, p.nlat, p.nlev], "dof": p.n, "tol": args.tol, "parallelism": "1 GPU"},
+                               f"({','.join(name for name, _, _ in runs)}); value = the sum of these times-to-solve",
+                   "case": args.config, "grid": [p.nlon, p.nlat, p.nlev], "dof": p.n, "tol": args.tol,
+                   "parallelism": "1 GPU"},
+        "value_is": "sum over the step's modes of the time-to-solve (see modes for each)",
         "modes": modes_out,
+        "other_modes": extra_out,
         "setup_seconds": {"generate_host": round(t_gen, 2), "operator_fp64": round(t_setup64, 3),
                           **{f"operator_{k}": round(v, 3) for k, v in t_setup_low.items()}},
         "roofline": roofline,
         "kernels": kernels,
         "cpu_baseline": cpu,
         "learned": learned,
+        "stress": stress,
         "paper_study": paper,
     }
     print(json.dumps(result), flush=True)
+
+
+def traffic_probe(eg, torch, p, args):
+    """Four iterations of each mode, two line-SOR iterations of each, a device copy of known
+    size, and three network applications on the learned preconditioner's workload in each of
+    its two inference paths, for counter runs."""
+    import synth
+    coef, b = generate_on_device(p, torch)
+    op = eg.Operator(coef)
+    del coef
+    x = torch.zeros(p.n, dtype=torch.float64, device="cuda")
+    for m in (eg.FP64, eg.FP32_IR, eg.FP32_IR_BF16):
+        x.zero_()
+        op.solve(b, x, args.tol, 4, m)
+    op.set_option("precond", 1)   # the line-SOR half-sweeps
+    for m in (eg.FP64, eg.FP32_IR, eg.FP32_IR_BF16):
+        x.zero_()
+        op.solve(b, x, args.tol, 2, m)
+    op.set_option("precond", 0)
+    for _ in range(3):
+        x.copy_(b)
+    torch.cuda.synchronize()
+    op.close()
+    del x, b
+    torch.cuda.empty_cache()
+    # three network applications on the learned preconditioner's workload
+    p4 = synth.CONFIGS[args.learned_config or "learned_640x480x70"]
+    coef, _ = generate_on_device(p4, torch)
+    op = eg.Operator(coef)
+    del coef
+    net = eg.Net(11)
+    q = torch.randn(p4.n, dtype=torch.float32, device="cuda", generator=torch.Generator("cuda").manual_seed(5))
+    for fused in (1, 0):   # the one-launch inference, then the layer-by-layer kernels
+        op.set_option("net_fused", fused)
+        for _ in range(3):
+            net.apply(op, q)
+    torch.cuda.synchronize()
+    print(json.dumps({"traffic_probe": args.config, "copy_bytes_read": p.n * 8, "copy_bytes_written": p.n * 8,
+                      "net_workload": args.learned_config or "learned_640x480x70"}))
 
 
 if __name__ == "__main__":

@@ -163,6 +163,12 @@ int eg_set_stream(eg_operator *op, void *hip_stream);
  *   "method"         Krylov method of the plain modes: 0 BiCGStab, 1 restarted FGMRES [0]
  *   "learned_method" Krylov method of the learned modes: 0 flexible BiCGStab, 1 FGMRES [1]
  *   "gmres_m"        FGMRES restart length, 1..64 [30]
+ *   "net_fused"      learned modes on grids with nlon a multiple of 64: 1 runs the network's
+ *                    inference as one launch (input channels, all layers and q + rho delta,
+ *                    activations kept on chip; a BF16 pair of static input channels per grid
+ *                    point is built on first use and held until eg_destroy_operator), 0 as one
+ *                    launch per layer with the activations in HBM [1]; the results are bitwise
+ *                    the same
  * Returns EG_EINVAL for an unknown key or out-of-range value.
  */
 int eg_set_option(eg_operator *op, const char *key, double value);

@@ -208,6 +208,14 @@ void launch_net_forward_layers(const NetGeo &g, const NetDev &d, const NetActs &
 template <typename Tv>
 void launch_net_forward_fused(const NetGeo &g, const NetDev &d, const NetActs &act, const Tv *q, Tv *qout,
                               float *delta, const Scalars *sc, int stop_mask, hipStream_t s);
+// inference in one launch (grids with nlon a multiple of 64, net_fused_ok): input channels
+// from q, z0 = T^{-1} q and the operator's static channels (launch_net_static, one BF16 pair
+// per point), every layer, and q' = q + rho delta; bitwise the layered path's result
+bool net_fused_ok(const NetGeo &g);
+void launch_net_static(long n, const double *a64, uint32_t *fs, hipStream_t s);
+template <typename Tv>
+void launch_net_infer(const NetGeo &g, const NetDev &d, const Tv *q, const Tv *z0, const uint32_t *fstat, Tv *qout,
+                      float *delta, const Scalars *sc, int stop_mask, hipStream_t s);
 template <typename Tv>
 void launch_net_out(const NetGeo &g, const NetDev &d, const NetActs &act, const Tv *q, Tv *qout, float *delta,
                     const Scalars *sc, int stop_mask, hipStream_t s);

@@ -191,6 +191,8 @@ struct eg_operator {
     int hist_count = 0;
     eg_net *net = nullptr;      // learned preconditioner of the learned modes (own_net or a caller's)
     eg_net *own_net = nullptr;  // network owned by the operator (eg_train/load_learned_pc)
+    uint32_t *net_fs = nullptr; // static input channels of the one-launch inference (BF16 pairs)
+    int net_fused = 1;          // 0: the layered inference (kept for comparison)
     double *harvest_x = nullptr;
     int method = 0;             // plain modes: 0 BiCGStab, 1 FGMRES
     int learned_method = 1;     // learned modes: 0 flexible BiCGStab, 1 FGMRES
@@ -496,6 +498,20 @@ template <typename Tv> int ensure_qp(eg_operator *op, Work<Tv> &w)
     return w.qp ? 0 : dalloc(&w.qp, (size_t)op->n);
 }
 
+NetGeo geo_of(const eg_operator *op);
+
+// the static input channels of the one-launch inference, built once per operator from the
+// FP64 couplings (their FP32 roundings give the same channels)
+int ensure_net_static(eg_operator *op)
+{
+    if (op->net_fs || !net_fused_ok(geo_of(op))) return 0;
+    int rc = dalloc(&op->net_fs, (size_t)op->n);
+    if (rc) return rc;
+    launch_net_static(op->n, op->a64, op->net_fs, op->stream);
+    EG_HIP(hipGetLastError());
+    return 0;
+}
+
 NetGeo geo_of(const eg_operator *op) { return {op->nlon, op->nlat, op->nlev, op->P, op->n}; }
 
 // z (holding T^{-1} q on entry) <- M(q) = T^{-1} (q + rho delta(q)).  Tc: coefficient set the
@@ -509,8 +525,12 @@ void enqueue_net_stage(eg_operator *op, eg_net *net, const Tc *coef, const Tv *q
     int nr = 0;
     launch_dot2<Tv>(op->n, q, q, z, z, op->partials, &nr, op->sc, stop_mask, s);
     launch_finalize(FIN_NET, op->partials, nr, op->sc, nullptr, nullptr, 0, 0, s);
-    launch_net_features<Tv, Tc>(g, q, z, coef, net->act.x0, op->sc, stop_mask, s);
-    launch_net_forward_fused<Tv>(g, net->d, net->act, q, qp, delta, op->sc, stop_mask, s);
+    if (op->net_fs && op->net_fused) {
+        launch_net_infer<Tv>(g, net->d, q, z, op->net_fs, qp, delta, op->sc, stop_mask, s);
+    } else {
+        launch_net_features<Tv, Tc>(g, q, z, coef, net->act.x0, op->sc, stop_mask, s);
+        launch_net_forward_fused<Tv>(g, net->d, net->act, q, qp, delta, op->sc, stop_mask, s);
+    }
     launch_thomas<Tv>(op->tri_view<Tv>(), qp, z, TH_PLAIN, nullptr, nullptr, nullptr, nullptr, op->partials, nullptr,
                       op->sc, s, stop_mask);
 }
@@ -761,7 +781,8 @@ int solve_fp64(eg_operator *op, const double *b, double *x, double tol, int maxi
 {
     int rc;
     if ((rc = ensure_work(op, op->w64))) return rc;
-    if (net && ((rc = ensure_qp(op, op->w64)) || (rc = ensure_acts(net, op->n, false)))) return rc;
+    if (net && ((rc = ensure_qp(op, op->w64)) || (rc = ensure_acts(net, op->n, false)) || (rc = ensure_net_static(op))))
+        return rc;
     Work<double> &w = op->w64;
     hipStream_t s = op->stream;
     const OpView<double> A = op->view64();
@@ -855,7 +876,8 @@ int solve_ir(eg_operator *op, const OpView<Tc> &A32, const double *b, double *x,
 {
     int rc;
     if ((rc = ensure_work(op, op->w32))) return rc;
-    if (net && ((rc = ensure_qp(op, op->w32)) || (rc = ensure_acts(net, op->n, false)))) return rc;
+    if (net && ((rc = ensure_qp(op, op->w32)) || (rc = ensure_acts(net, op->n, false)) || (rc = ensure_net_static(op))))
+        return rc;
     bool use_net = net != nullptr;
     Work<float> &w = op->w32;
     hipStream_t s = op->stream;
@@ -1230,6 +1252,7 @@ void eg_destroy_operator(eg_operator *op)
     if (op->h_sc) (void)hipHostFree(op->h_sc);
     if (op->h_out) (void)hipHostFree(op->h_out);
     if (op->own_net) eg_net_destroy(op->own_net);
+    dfree(op->net_fs);
     delete op;
 }
 
@@ -1325,6 +1348,9 @@ int eg_set_option(eg_operator *op, const char *key, double value)
     } else if (k == "eps_bd") {
         if (!(value >= 0.0 && value < 1.0)) return fail(EG_EINVAL, "eps_bd must be in [0, 1)");
         op->eps_bd = value;
+    } else if (k == "net_fused") {
+        if (value != 0.0 && value != 1.0) return fail(EG_EINVAL, "net_fused must be 0 or 1");
+        op->net_fused = (int)value;
     } else if (k == "stall_window") {
         if (value < 1) return fail(EG_EINVAL, "stall_window must be >= 1");
         op->stall_window = (int)value;
@@ -1681,7 +1707,8 @@ int eg_net_apply(eg_operator *op, eg_net *net, const float *q, float *z, float *
 {
     if (!op || !net || !q || !z) return fail(EG_EINVAL, "NULL argument");
     int rc;
-    if ((rc = ensure_fp32(op)) || (rc = ensure_acts(net, op->n, false)) || (rc = ensure_train_tmp(net, op->n)))
+    if ((rc = ensure_fp32(op)) || (rc = ensure_acts(net, op->n, false)) || (rc = ensure_train_tmp(net, op->n)) ||
+        (rc = ensure_net_static(op)))
         return rc;
     hipStream_t s = op->stream;
     launch_thomas<float>(op->tri_view32(), q, z, TH_PLAIN, nullptr, nullptr, nullptr, nullptr, op->partials, nullptr,

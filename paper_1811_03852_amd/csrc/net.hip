@@ -36,6 +36,25 @@ __device__ __forceinline__ bf16x8 ld8(const uint16_t *row)
 
 __device__ __forceinline__ bf16x8 zero8() { return __builtin_bit_cast(bf16x8, make_uint4(0, 0, 0, 0)); }
 
+// two floats rounded to BF16 (ties to even) in one 32-bit word, a in the low half
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t pack_bf16x2(float a, float b)
+{
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2_t{a, b}, bf16x2_t));
+}
+
+// the network's two vector input channels at one point, BF16: q / rho and z / rho_z (z = T^{-1} q,
+// rho, rho_z their root-mean-square values), multiplied in the vectors' precision
+template <typename Tv>
+__device__ __forceinline__ uint32_t vec_channels(Tv q, Tv z, double inv_rho, double inv_rhoz)
+{
+    if constexpr (sizeof(Tv) == 4)
+        return pack_bf16x2(q * static_cast<float>(inv_rho), z * static_cast<float>(inv_rhoz));
+    else
+        return pack_bf16x2(static_cast<float>(q * inv_rho), static_cast<float>(z * inv_rhoz));
+}
+
 // v if keep, else zero, without a branch (loads stay unconditional, so the compiler can count
 // them and wait only for the ones a multiply needs)
 __device__ __forceinline__ bf16x8 keep8(bf16x8 v, bool keep)
@@ -131,15 +150,10 @@ __global__ __launch_bounds__(256) void k_net_features(NetGeo g, const Tv *__rest
     const double inv_rhoz = sc->net_z2 > 0.0 ? 1.0 / sqrt(sc->net_z2 / (double)g.n) : 0.0;
     const long stride = (long)gridDim.x * 256;
     for (long p = (long)blockIdx.x * 256 + threadIdx.x; p < g.n; p += stride) {
-        const float c0 = static_cast<float>(static_cast<double>(q[p]) * inv_rho);
-        const float c1 = static_cast<float>(static_cast<double>(z0[p]) * inv_rhoz);
         const float c2 = static_cast<float>(a[4 * g.n + p]) + static_cast<float>(a[5 * g.n + p]);
         const float c3 = (static_cast<float>(a[p]) + static_cast<float>(a[g.n + p])) +
                          (static_cast<float>(a[2 * g.n + p]) + static_cast<float>(a[3 * g.n + p]));
-        uint2 v;
-        v.x = static_cast<uint32_t>(f2bf(c0)) | (static_cast<uint32_t>(f2bf(c1)) << 16);
-        v.y = static_cast<uint32_t>(f2bf(c2)) | (static_cast<uint32_t>(f2bf(c3)) << 16);
-        reinterpret_cast<uint2 *>(x0)[p] = v;
+        reinterpret_cast<uint2 *>(x0)[p] = make_uint2(vec_channels(q[p], z0[p], inv_rho, inv_rhoz), pack_bf16x2(c2, c3));
     }
 }
 
@@ -179,15 +193,29 @@ __device__ __forceinline__ long col_unit(int per_xcd)
     return ((long)(b & 7) * per_xcd + (b >> 3)) * 4 + (threadIdx.x >> 6);
 }
 
-// four consecutive output channels of one position: bias, ReLU, BF16, one 8-byte store
-__device__ __forceinline__ void store4(uint16_t *dst, f32x4 acc, const float *b)
+// Four consecutive output channels of one position (the accumulator started from the bias):
+// BF16, then ReLU on the BF16 pairs.  A BF16 number is negative exactly when its 16-bit pattern
+// is a negative int16, so a packed int16 max with 0 is the ReLU; rounding is monotone and keeps
+// the sign, so this equals rounding max(v, 0) (a negative zero becomes +0).
+typedef short s16x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t relu_bf16x2(uint32_t v)
 {
-    uint2 v;
-    v.x = static_cast<uint32_t>(f2bf(fmaxf(acc[0] + b[0], 0.f))) |
-          (static_cast<uint32_t>(f2bf(fmaxf(acc[1] + b[1], 0.f))) << 16);
-    v.y = static_cast<uint32_t>(f2bf(fmaxf(acc[2] + b[2], 0.f))) |
-          (static_cast<uint32_t>(f2bf(fmaxf(acc[3] + b[3], 0.f))) << 16);
-    *reinterpret_cast<uint2 *>(dst) = v;
+    const s16x2 r = __builtin_elementwise_max(__builtin_bit_cast(s16x2, v), s16x2{0, 0});
+    return __builtin_bit_cast(uint32_t, r);
+}
+__device__ __forceinline__ uint2 relu_pack4(f32x4 acc)
+{
+    return make_uint2(relu_bf16x2(pack_bf16x2(acc[0], acc[1])), relu_bf16x2(pack_bf16x2(acc[2], acc[3])));
+}
+__device__ __forceinline__ void store4(uint16_t *dst, f32x4 acc)
+{
+    *reinterpret_cast<uint2 *>(dst) = relu_pack4(acc);
+}
+// the bias of output channels 16 nt + 4 grp .. + 3, the accumulator's initial value
+__device__ __forceinline__ f32x4 bias4(const float *b, int nt, int grp)
+{
+    const float *p = b + 16 * nt + 4 * grp;
+    return f32x4{p[0], p[1], p[2], p[3]};
 }
 
 // ------------------------------------------------------------------------------------------
@@ -227,11 +255,7 @@ __global__ __launch_bounds__(256) void k_conv_fwd(NetGeo g, const uint16_t *__re
 #pragma unroll
             for (int nt = 0; nt < 2; ++nt) wa[c][nt] = ld8(wf + (long)c * 1024 + (16 * nt + m) * 32 + 8 * grp);
     }
-    float bs[2][4];
-#pragma unroll
-    for (int nt = 0; nt < 2; ++nt)
-#pragma unroll
-        for (int jj = 0; jj < 4; ++jj) bs[nt][jj] = bias[16 * nt + 4 * grp + jj];
+    const f32x4 bv0 = bias4(bias, 0, grp), bv1 = bias4(bias, 1, grp);
     const int tile = (int)(unit % tiles);
     const int k0 = (int)(unit / tiles) * kchunk;
     const int k1 = min(g.nlev, k0 + kchunk);
@@ -241,8 +265,8 @@ __global__ __launch_bounds__(256) void k_conv_fwd(NetGeo g, const uint16_t *__re
     auto emit = [&](int k, f32x4 acc0, f32x4 acc1) {
         if (!pv) return;
         uint16_t *dst = out + ((long)k * g.P + p2) * 32 + 4 * grp;
-        store4(dst, acc0, bs[0]);
-        store4(dst + 16, acc1, bs[1]);
+        store4(dst, acc0);
+        store4(dst + 16, acc1);
     };
     if constexpr (L == 2) {
         // the nine horizontal neighbours in the level plane (periodic in longitude, none
@@ -274,7 +298,7 @@ __global__ __launch_bounds__(256) void k_conv_fwd(NetGeo g, const uint16_t *__re
             load9(min(k + 1, k1 - 1), nxt);   // the last level re-reads itself (in bounds, unused)
 #pragma unroll
             for (int t = 0; t < 9; ++t) cur[t] = keep8(cur[t], (ok >> t) & 1);
-            f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+            f32x4 acc0 = bv0, acc1 = bv1;
 #pragma unroll
             for (int t = 0; t < 9; ++t) {
                 acc0 = mfma(__builtin_bit_cast(bf16x8, wsh[(2 * t) * 64 + lane]), cur[t], acc0);
@@ -292,7 +316,7 @@ __global__ __launch_bounds__(256) void k_conv_fwd(NetGeo g, const uint16_t *__re
         bf16x8 w0 = row(k0 - 2), w1 = row(k0 - 1), w2 = row(k0), w3 = row(k0 + 1), w4 = row(k0 + 2);
         for (int k = k0; k < k1; ++k) {
             const bf16x8 nx = row(k + 3);   // one level ahead
-            f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+            f32x4 acc0 = bv0, acc1 = bv1;
             acc0 = mfma(wa[0][0], w0, acc0);
             acc1 = mfma(wa[0][1], w0, acc1);
             acc0 = mfma(wa[1][0], w1, acc0);
@@ -325,7 +349,7 @@ __global__ __launch_bounds__(256) void k_conv_fwd(NetGeo g, const uint16_t *__re
             const uint2 lo = grp == 0 ? x0 : (grp == 1 ? x2 : (grp == 2 ? x4 : zz));
             const uint2 hi = grp == 0 ? x1 : (grp == 1 ? x3 : zz);
             const bf16x8 a = __builtin_bit_cast(bf16x8, make_uint4(lo.x, lo.y, hi.x, hi.y));
-            f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+            f32x4 acc0 = bv0, acc1 = bv1;
             acc0 = mfma(wa[0][0], a, acc0);
             acc1 = mfma(wa[0][1], a, acc1);
             emit(k, acc0, acc1);
@@ -373,11 +397,7 @@ __global__ __launch_bounds__(256) void k_conv3x3_rows(NetGeo g, const uint16_t *
     __syncthreads();
     const long unit = col_unit(per_xcd);
     if (unit >= units) return;
-    float bs[2][4];
-#pragma unroll
-    for (int nt = 0; nt < 2; ++nt)
-#pragma unroll
-        for (int jj = 0; jj < 4; ++jj) bs[nt][jj] = bias[16 * nt + 4 * grp + jj];
+    const f32x4 bv0 = bias4(bias, 0, grp), bv1 = bias4(bias, 1, grp);
     const int tile = (int)(unit % tiles);
     const int k0 = (int)(unit / tiles) * kchunk;
     const int k1 = min(g.nlev, k0 + kchunk);
@@ -409,7 +429,7 @@ __global__ __launch_bounds__(256) void k_conv3x3_rows(NetGeo g, const uint16_t *
     for (int k = k0; k < k1; ++k) {
         asm volatile("" ::: "memory");
         load(min(k + 1, k1 - 1), nxt);   // the last level re-reads itself (in bounds, unused)
-        f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+        f32x4 acc0 = bv0, acc1 = bv1;
 #pragma unroll
         for (int r = 0; r < 3; ++r) {
             const bf16x8 o = cur[r];
@@ -427,8 +447,8 @@ __global__ __launch_bounds__(256) void k_conv3x3_rows(NetGeo g, const uint16_t *
             acc1 = mfma(__builtin_bit_cast(bf16x8, wsh[(2 * t + 5) * 64 + lane]), e, acc1);
         }
         uint16_t *dst = out + ((long)k * g.P + p2) * 32 + 4 * grp;
-        store4(dst, acc0, bs[0]);
-        store4(dst + 16, acc1, bs[1]);
+        store4(dst, acc0);
+        store4(dst + 16, acc1);
 #pragma unroll
         for (int t = 0; t < 9; ++t) cur[t] = nxt[t];
     }
@@ -460,11 +480,7 @@ __global__ __launch_bounds__(256) void k_conv3x3_strip(NetGeo g, const uint16_t 
     __syncthreads();
     const long unit = col_unit(per_xcd);
     if (unit >= units) return;
-    float bs[2][4];
-#pragma unroll
-    for (int nt = 0; nt < 2; ++nt)
-#pragma unroll
-        for (int jj = 0; jj < 4; ++jj) bs[nt][jj] = bias[16 * nt + 4 * grp + jj];
+    const f32x4 bv0 = bias4(bias, 0, grp), bv1 = bias4(bias, 1, grp);
     const int strip = (int)(unit % tiles);   // `tiles` counts strips of 64 positions here
     const int k0 = (int)(unit / tiles) * kchunk;
     const int k1 = min(g.nlev, k0 + kchunk);
@@ -496,7 +512,10 @@ __global__ __launch_bounds__(256) void k_conv3x3_strip(NetGeo g, const uint16_t 
         load(min(k + 1, k1 - 1), nxt);   // the last level re-reads itself (in bounds, unused)
         f32x4 acc[NT][2];
 #pragma unroll
-        for (int s = 0; s < NT; ++s) acc[s][0] = acc[s][1] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int s = 0; s < NT; ++s) {
+            acc[s][0] = bv0;
+            acc[s][1] = bv1;
+        }
 #pragma unroll
         for (int r = 0; r < 3; ++r) {
 #pragma unroll
@@ -529,8 +548,8 @@ __global__ __launch_bounds__(256) void k_conv3x3_strip(NetGeo g, const uint16_t 
 #pragma unroll
         for (int s = 0; s < NT; ++s) {
             uint16_t *dst = out + ((long)k * g.P + t0 + 16 * s + m) * 32 + 4 * grp;
-            store4(dst, acc[s][0], bs[0]);
-            store4(dst + 16, acc[s][1], bs[1]);
+            store4(dst, acc[s][0]);
+            store4(dst + 16, acc[s][1]);
         }
 #pragma unroll
         for (int t = 0; t < NL; ++t) cur[t] = nxt[t];
@@ -1115,11 +1134,7 @@ __global__ __launch_bounds__(256) void k_conv3_out(NetGeo g, const uint16_t *__r
 #pragma unroll
         for (int nt = 0; nt < 2; ++nt) wa[c][nt] = ld8(w3f + (long)c * 1024 + (16 * nt + m) * 32 + 8 * grp);
     // this lane's channels 16 nt + 4 grp + jj: layer-3 bias
-    float bs[2][4];
-#pragma unroll
-    for (int nt = 0; nt < 2; ++nt)
-#pragma unroll
-        for (int jj = 0; jj < 4; ++jj) bs[nt][jj] = theta[kNetOffB3 + 16 * nt + 4 * grp + jj];
+    const f32x4 bv0 = bias4(theta + kNetOffB3, 0, grp), bv1 = bias4(theta + kNetOffB3, 1, grp);
     // The output layer is one more MFMA per level, D[t][position] = W4[t][K] a3[position][K]:
     // with the K index 8 grp + 4 nt + jj standing for channel 16 nt + 4 grp + jj, the B operand
     // is this lane's own eight a3 values, and A is row t = m of W4 (taps 0..4; rows 5..15 zero)
@@ -1154,7 +1169,7 @@ __global__ __launch_bounds__(256) void k_conv3_out(NetGeo g, const uint16_t *__r
     for (int kk = k0 - 2; kk < k1 + 2; ++kk) {
         if (kk >= 0 && kk < g.nlev) {
             const bf16x8 nx = row(kk + 5);   // three levels ahead
-            f32x4 acc[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
+            f32x4 acc[2] = {bv0, bv1};
 #pragma unroll
             for (int nt = 0; nt < 2; ++nt) {
                 acc[nt] = mfma(wa[0][nt], v0, acc[nt]);
@@ -1163,15 +1178,9 @@ __global__ __launch_bounds__(256) void k_conv3_out(NetGeo g, const uint16_t *__r
                 acc[nt] = mfma(wa[3][nt], v3, acc[nt]);
                 acc[nt] = mfma(wa[4][nt], v4, acc[nt]);
             }
-            // a3 as the two-kernel path stores it (bias, ReLU, BF16), packed in K order
-            uint32_t ad[4];
-#pragma unroll
-            for (int i = 0; i < 8; i += 2) {
-                const uint32_t lo = f2bf(fmaxf(acc[i / 4][i % 4] + bs[i / 4][i % 4], 0.f));
-                const uint32_t hi = f2bf(fmaxf(acc[i / 4][i % 4 + 1] + bs[i / 4][i % 4 + 1], 0.f));
-                ad[i / 2] = lo | (hi << 16);
-            }
-            const f32x4 so = mfma(w4a, __builtin_bit_cast(bf16x8, make_uint4(ad[0], ad[1], ad[2], ad[3])),
+            // a3 as the two-kernel path stores it (BF16, ReLU), packed in K order
+            const uint2 a0 = relu_pack4(acc[0]), a1 = relu_pack4(acc[1]);
+            const f32x4 so = mfma(w4a, __builtin_bit_cast(bf16x8, make_uint4(a0.x, a0.y, a1.x, a1.y)),
                                   f32x4{0.f, 0.f, 0.f, 0.f});
             // lane (m, 0) holds the tap sums t = 0..3 of position m, lane (m, 1) holds t = 4
             const float s4 = __shfl_down(so[0], 16);
@@ -1197,6 +1206,346 @@ __global__ __launch_bounds__(256) void k_conv3_out(NetGeo g, const uint16_t *__r
         r[2] = r[3];
         r[3] = r[4];
         r[4] = b4;
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// The operator's static input channels (D + U, W + E + S + N as BF16, one 32-bit word per
+// grid point), formed as k_net_features forms them; the FP32 coefficients are the FP32
+// roundings of the FP64 ones, so one array serves both precisions.
+// ------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_net_static(long n, const double *__restrict__ a, uint32_t *__restrict__ fs)
+{
+    const long stride = (long)gridDim.x * 256;
+    for (long p = (long)blockIdx.x * 256 + threadIdx.x; p < n; p += stride) {
+        const float c2 = static_cast<float>(a[4 * n + p]) + static_cast<float>(a[5 * n + p]);
+        const float c3 = (static_cast<float>(a[p]) + static_cast<float>(a[n + p])) +
+                         (static_cast<float>(a[2 * n + p]) + static_cast<float>(a[3 * n + p]));
+        fs[p] = pack_bf16x2(c2, c3);
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// The whole inference in one launch (nlon a multiple of 64): input channels, layer 1, the 3x3
+// layer, layer 3 and the output layer, with a1 and a2 handed on in LDS and registers instead
+// of HBM.  A workgroup of eight waves (two per SIMD) owns 4 latitude rows x 64 longitudes and
+// marches up the levels; wave w owns tiles 2 (w % 2) and 2 (w % 2) + 1 of 16 positions in row
+// w / 2.  Step s does
+//   * layer 1 at level s on the block's rows, the row on each side, and one more tile holding
+//     the west and east halo columns of those six rows (25 tiles, spread over the waves).  Its
+//     input channels are formed on the fly from q, T^{-1} q and the static channels as
+//     k_net_features forms them, in a window of five levels per tile (the loads of level
+//     s + 3 are issued at the start of the step and consumed at its end); the result goes to
+//     an LDS plane [row][8-channel block][column], double-buffered by level, zero on rows
+//     outside the grid (the poles);
+//   * a workgroup barrier;
+//   * a2 of level s - 1 (written by this wave at step s - 1) read back from a wave-private LDS
+//     tile in the operand layout of layer 3 (channels 8 grp .. 8 grp + 7 of its position),
+//     joining a window of five levels; the 3x3 layer at level s for the wave's two tiles,
+//     operands from the LDS plane, weights from LDS, the result written to the other half of
+//     the wave's LDS tile (read back after the next barrier);
+//   * layer 3 at level s - 3 from the window and its output-layer tap sums (as k_conv3_out),
+//     and the output of level s - 5:  q' = q + rho delta.
+// Every product and sum is taken in the order of the layered kernels (k_net_features,
+// k_conv_fwd<1>, k_conv3x3_strip, k_conv3_out), so the result is bitwise theirs.  Offsets are
+// 32-bit byte offsets from the arrays' bases (the launcher checks n * sizeof(Tv) < 2^32).
+// ------------------------------------------------------------------------------------------
+constexpr int kFuRows = 4;                // latitude rows per workgroup
+constexpr int kFuCols = 64;               // longitudes per workgroup
+constexpr int kFuWaves = 8;               // two per row, two per SIMD
+constexpr int kFuA1Rows = kFuRows + 2;    // layer-1 rows: the block's and one on each side
+constexpr int kFuA1Cols = kFuCols + 2;    // with the west and east halo columns
+constexpr int kFuA1Elems = kFuA1Rows * 4 * kFuA1Cols;   // 16-byte elements of one plane
+constexpr int kFuL1Tiles = 4 * kFuA1Rows + 1;
+constexpr int kFuL1PerWave = (kFuL1Tiles + kFuWaves - 1) / kFuWaves;
+
+template <typename T> __device__ __forceinline__ T ld_off(const T *base, uint32_t off)
+{
+    return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + off);
+}
+template <typename T> __device__ __forceinline__ void st_off(T *base, uint32_t off, T v)
+{
+    *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + off) = v;
+}
+
+// a wave-uniform double held in scalar registers
+__device__ __forceinline__ double uniform_f64(double v)
+{
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(u));
+    const uint32_t hi = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(u >> 32));
+    return __builtin_bit_cast(double, (static_cast<uint64_t>(hi) << 32) | lo);
+}
+
+template <typename Tv>
+__global__ __launch_bounds__(64 * kFuWaves) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_net_fused(
+    NetGeo g, const Tv *__restrict__ q, const Tv *__restrict__ z0, const uint32_t *__restrict__ fstat,
+    const uint16_t *__restrict__ w1f, const uint16_t *__restrict__ w2f, const uint16_t *__restrict__ w3f,
+    const float *__restrict__ w4, const float *__restrict__ theta, Tv *__restrict__ qout, float *__restrict__ delta,
+    const Scalars *__restrict__ sc, int stop_mask, int nstrips, int nblocks, int per_xcd)
+{
+    if (stop_now(sc, stop_mask)) return;
+    const int blk = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);   // XCD-aware, as the SpMV tiles
+    if (blk >= nblocks) return;                                        // whole workgroup
+    __shared__ uint4 w2s[18 * 64];                     // 3x3 weights in each lane's operand order
+    __shared__ uint4 a1s[2][kFuA1Elems];               // layer-1 plane, [row][block][column]
+    __shared__ uint4 a2s[2][kFuWaves][2 * 4 * 16];     // per wave: [tile][block][position]
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, m = lane & 15, grp = lane >> 4;
+    const int nlon = g.nlon, nlat = g.nlat, nlev = g.nlev;
+    const long P = g.P;
+    const int j0 = (blk / nstrips) * kFuRows, i0 = (blk % nstrips) * kFuCols;
+    for (int e = threadIdx.x; e < 18 * 64; e += 64 * kFuWaves) {
+        const int tn = e / 64, l = e % 64;   // tn = 2 t + nt
+        w2s[e] = *reinterpret_cast<const uint4 *>(w2f + (long)(tn / 2) * 1024 + (16 * (tn % 2) + (l & 15)) * 32 +
+                                                  8 * (l >> 4));
+    }
+
+    bf16x8 w1a[2], w3a[5][2];
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt) w1a[nt] = ld8(w1f + (16 * nt + m) * 32 + 8 * grp);
+#pragma unroll
+    for (int c = 0; c < 5; ++c)
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt) w3a[c][nt] = ld8(w3f + (long)c * 1024 + (16 * nt + m) * 32 + 8 * grp);
+    // biases of layers 1-3 as accumulator initial values, [layer][nt][grp], read from LDS at
+    // each use (registers are the scarce resource here)
+    __shared__ f32x4 bias_s[3][2][4];
+    if (threadIdx.x < 24) {
+        const int ly = threadIdx.x / 8, nt = (threadIdx.x / 4) % 2, gq = threadIdx.x % 4;
+        bias_s[ly][nt][gq] = bias4(theta + (ly == 0 ? kNetOffB1 : (ly == 1 ? kNetOffB2 : kNetOffB3)), nt, gq);
+    }
+    __syncthreads();   // the 3x3 weights and the biases, before layer 1 of the first step
+    uint32_t wd[4];
+#pragma unroll
+    for (int i = 0; i < 8; i += 2) {
+        const int c = 16 * (i / 4) + 4 * grp + (i % 4);
+        const uint32_t lo = m < 5 ? f2bf(w4[m * 32 + c]) : 0u, hi = m < 5 ? f2bf(w4[m * 32 + c + 1]) : 0u;
+        wd[i / 2] = lo | (hi << 16);
+    }
+    const bf16x8 w4a = __builtin_bit_cast(bf16x8, make_uint4(wd[0], wd[1], wd[2], wd[3]));
+    const float b4 = theta[kNetOffB4];
+    const double inv_rho = uniform_f64(1.0 / sqrt(sc->net_q2 / (double)g.n));
+    const double inv_rhoz = uniform_f64(sc->net_z2 > 0.0 ? 1.0 / sqrt(sc->net_z2 / (double)g.n) : 0.0);
+    const double rho = uniform_f64(sqrt(sc->net_q2 / (double)g.n));
+    // lane group grp supplies layer 1's taps 2 grp and 2 grp + 1: masks that pick them from the
+    // window without indexing it by grp (an indexed window would be placed in scratch memory)
+    const uint32_t g0 = grp == 0 ? ~0u : 0u, g1 = grp == 1 ? ~0u : 0u, g2 = grp == 2 ? ~0u : 0u;
+    const uint32_t step_v = static_cast<uint32_t>(P * (long)sizeof(Tv)), step_f = static_cast<uint32_t>(P * 4);
+
+    // layer-1 tiles of this wave: u = wv + 8 t.  Tile u < 24 is row u / 4 of the layer-1 rows
+    // (grid row j0 - 1 + u / 4), columns 16 (u % 4) + m of the block; tile 24 holds the west
+    // (lanes 0..5) and east (lanes 6..11) halo columns of the six rows, lanes 12..15 unused.
+    uint32_t pos1[kFuL1PerWave];   // plane position (in bounds)
+    int dst1[kFuL1PerWave];        // LDS element (8-byte units) of this lane's channel group, -1: none
+    bool val1[kFuL1PerWave];       // the position lies inside the grid
+#pragma unroll
+    for (int t = 0; t < kFuL1PerWave; ++t) {
+        const int u = wv + kFuWaves * t;
+        int rr = -1, col = 0, i = i0;
+        if (u < 4 * kFuA1Rows) {
+            rr = u >> 2;
+            col = 1 + 16 * (u & 3) + m;
+            i = i0 + 16 * (u & 3) + m;
+        } else if (u == 4 * kFuA1Rows && m < 2 * kFuA1Rows) {
+            const bool east = m >= kFuA1Rows;
+            rr = east ? m - kFuA1Rows : m;
+            col = east ? kFuA1Cols - 1 : 0;
+            i = east ? (i0 + kFuCols == nlon ? 0 : i0 + kFuCols) : (i0 == 0 ? nlon - 1 : i0 - 1);
+        }
+        const int j = j0 - 1 + rr;
+        val1[t] = rr >= 0 && j >= 0 && j < nlat;
+        pos1[t] = val1[t] ? static_cast<uint32_t>(j * nlon + i) : 0u;
+        dst1[t] = rr < 0 ? -1 : ((rr * 4 + (grp >> 1)) * kFuA1Cols + col) * 2 + (grp & 1);
+    }
+    struct Raw {
+        Tv q, z;
+        uint32_t f;
+    };
+    auto load_raw = [&](int t, int L) -> Raw {
+        const uint32_t lc = static_cast<uint32_t>(min(max(L, 0), nlev - 1));
+        return Raw{ld_off(q, pos1[t] * (uint32_t)sizeof(Tv) + lc * step_v),
+                   ld_off(z0, pos1[t] * (uint32_t)sizeof(Tv) + lc * step_v), ld_off(fstat, pos1[t] * 4u + lc * step_f)};
+    };
+    // input channels of tile t at level L (zero outside the column or the grid)
+    auto channels = [&](int t, int L, const Raw &v) -> uint2 {
+        const bool keep = val1[t] && L >= 0 && L < nlev;
+        return make_uint2(keep ? vec_channels(v.q, v.z, inv_rho, inv_rhoz) : 0u, keep ? v.f : 0u);
+    };
+    // Rolling windows are rings indexed by level mod 5 (the loop below is unrolled by five, so
+    // every index is a constant and nothing is copied from slot to slot):
+    //   xw   input channels of levels st - 2 .. st + 2,
+    //   vw   a2 of levels st - 5 .. st - 1,
+    //   racc pending outputs of levels st - 5 .. st - 1 (started from the output bias).
+    uint2 xw[kFuL1PerWave][5];
+    Raw nxt[kFuL1PerWave];       // level st + 3, in flight during step st
+#pragma unroll
+    for (int t = 0; t < kFuL1PerWave; ++t)
+        if (wv + kFuWaves * t < kFuL1Tiles)
+#pragma unroll
+            for (int L = -2; L <= 2; ++L) xw[t][(L + 5) % 5] = channels(t, L, load_raw(t, L));
+
+    // this wave's output row and the positions of its two tiles
+    const int lr = wv >> 1, hc = kFuCols / 2 * (wv & 1);
+    const int jo = j0 + lr;
+    const bool row_ok = jo < nlat;
+    const uint32_t po = static_cast<uint32_t>((row_ok ? jo : 0) * nlon + i0 + hc + m);   // + 16 s for tile s
+    bf16x8 vw[2][5];
+    float racc[2][5];
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int d = 0; d < 5; ++d) {
+            vw[s][d] = zero8();
+            racc[s][d] = b4;
+        }
+
+    uint2 *a1w = reinterpret_cast<uint2 *>(&a1s[0][0]);
+    // one step; PH = st mod 5
+    auto step = [&](auto ph_c, int st) {
+        constexpr int PH = decltype(ph_c)::value;
+        const int buf = st & 1;
+        const int k = st - 5;   // output level of this step
+        // loads consumed at the end of the step: layer-1 inputs of level st + 3, q of level k
+        if (st < nlev) {
+#pragma unroll
+            for (int t = 0; t < kFuL1PerWave; ++t)
+                if (wv + kFuWaves * t < kFuL1Tiles) nxt[t] = load_raw(t, st + 3);
+        }
+        const uint32_t ko = static_cast<uint32_t>(min(max(k, 0), nlev - 1));
+        Tv qo[2];
+#pragma unroll
+        for (int s = 0; s < 2; ++s) qo[s] = ld_off(q, (po + 16 * s) * (uint32_t)sizeof(Tv) + ko * step_v);
+        // ---- layer 1 at level st: taps 2 grp, 2 grp + 1 are levels st - 2 + 2 grp, st - 1 + 2 grp
+        if (st < nlev) {
+            uint2 *pl = a1w + buf * (kFuA1Elems * 2);
+#pragma unroll
+            for (int t = 0; t < kFuL1PerWave; ++t) {
+                if (wv + kFuWaves * t >= kFuL1Tiles) continue;   // wave-uniform
+                const uint2 x0 = xw[t][(PH + 3) % 5], x1 = xw[t][(PH + 4) % 5], x2 = xw[t][PH % 5],
+                            x3 = xw[t][(PH + 1) % 5], x4 = xw[t][(PH + 2) % 5];
+                const uint2 lo = make_uint2((x0.x & g0) | (x2.x & g1) | (x4.x & g2), (x0.y & g0) | (x2.y & g1) | (x4.y & g2));
+                const uint2 hi = make_uint2((x1.x & g0) | (x3.x & g1), (x1.y & g0) | (x3.y & g1));
+                const bf16x8 a = __builtin_bit_cast(bf16x8, make_uint4(lo.x, lo.y, hi.x, hi.y));
+                const f32x4 acc0 = mfma(w1a[0], a, bias_s[0][0][grp]);
+                const f32x4 acc1 = mfma(w1a[1], a, bias_s[0][1][grp]);
+                if (dst1[t] >= 0) {
+                    const uint2 zz = make_uint2(0, 0);
+                    const uint2 v0 = relu_pack4(acc0), v1 = relu_pack4(acc1);
+                    pl[dst1[t]] = val1[t] ? v0 : zz;                       // channels 4 grp .. + 3
+                    pl[dst1[t] + 2 * 2 * kFuA1Cols] = val1[t] ? v1 : zz;   // channels 16 + 4 grp .. + 3
+                }
+            }
+        }
+        __syncthreads();
+        // ---- a2 of level st - 1 joins the window ----
+        if (st >= 1 && st - 1 < nlev) {
+#pragma unroll
+            for (int s = 0; s < 2; ++s)
+                vw[s][(PH + 4) % 5] = __builtin_bit_cast(bf16x8, a2s[buf ^ 1][wv][(s * 4 + grp) * 16 + m]);
+        } else {
+#pragma unroll
+            for (int s = 0; s < 2; ++s) vw[s][(PH + 4) % 5] = zero8();
+        }
+        // ---- the 3x3 layer at level st for this wave's two tiles ----
+        if (st < nlev) {
+            const uint4 *pl = &a1s[buf][0];
+            const f32x4 b20 = bias_s[1][0][grp], b21 = bias_s[1][1][grp];
+            f32x4 acc[2][2] = {{b20, b21}, {b20, b21}};
+#pragma unroll
+            for (int r = 0; r < 3; ++r) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {   // tap t = 3 r + c: (di, dj) = (c - 1, r - 1)
+                    const int t = 3 * r + c;
+                    const bf16x8 wa0 = __builtin_bit_cast(bf16x8, w2s[(2 * t) * 64 + lane]);
+                    const bf16x8 wa1 = __builtin_bit_cast(bf16x8, w2s[(2 * t + 1) * 64 + lane]);
+                    const uint4 *rowp = pl + ((lr + r) * 4 + grp) * kFuA1Cols + hc + c + m;   // column 1 + hc + m + c - 1
+#pragma unroll
+                    for (int s = 0; s < 2; ++s) {
+                        const bf16x8 v = __builtin_bit_cast(bf16x8, rowp[16 * s]);
+                        acc[s][0] = mfma(wa0, v, acc[s][0]);
+                        acc[s][1] = mfma(wa1, v, acc[s][1]);
+                    }
+                }
+            }
+            uint2 *tw = reinterpret_cast<uint2 *>(&a2s[buf][wv][0]);
+#pragma unroll
+            for (int s = 0; s < 2; ++s)
+#pragma unroll
+                for (int nt = 0; nt < 2; ++nt)
+                    tw[((s * 4 + 2 * nt + (grp >> 1)) * 16 + m) * 2 + (grp & 1)] = relu_pack4(acc[s][nt]);
+        }
+        // ---- layer 3 at level kk = st - 3 (a2 of levels st - 5 .. st - 1), output of level k ----
+        const int kk = st - 3;
+        if (kk >= 0 && kk < nlev) {
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+                f32x4 acc[2] = {bias_s[2][0][grp], bias_s[2][1][grp]};
+#pragma unroll
+                for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+                    for (int c = 0; c < 5; ++c) acc[nt] = mfma(w3a[c][nt], vw[s][(PH + c) % 5], acc[nt]);
+                const uint2 a0 = relu_pack4(acc[0]), a1 = relu_pack4(acc[1]);
+                const f32x4 so = mfma(w4a, __builtin_bit_cast(bf16x8, make_uint4(a0.x, a0.y, a1.x, a1.y)),
+                                      f32x4{0.f, 0.f, 0.f, 0.f});
+                const float s4 = __shfl_down(so[0], 16);
+                const float stp[5] = {so[0], so[1], so[2], so[3], s4};
+                // output level st - 5 + d (slot (PH + d) % 5) takes tap 4 - d of this a3 level
+#pragma unroll
+                for (int d = 0; d < 5; ++d) racc[s][(PH + d) % 5] += stp[4 - d];
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            if (k >= 0 && k < nlev && grp == 0 && row_ok) {
+                const uint32_t e = po + 16 * s + static_cast<uint32_t>(k) * static_cast<uint32_t>(P);   // element
+                if (delta) st_off(delta, e * 4u, racc[s][PH]);
+                st_off(qout, e * (uint32_t)sizeof(Tv),
+                       static_cast<Tv>(static_cast<double>(qo[s]) + rho * static_cast<double>(racc[s][PH])));
+            }
+            racc[s][PH] = b4;   // the slot's next level is st
+        }
+        // level st + 3 enters the layer-1 window (in the slot of level st - 2)
+        if (st < nlev) {
+#pragma unroll
+            for (int t = 0; t < kFuL1PerWave; ++t)
+                if (wv + kFuWaves * t < kFuL1Tiles) xw[t][(PH + 3) % 5] = channels(t, st + 3, nxt[t]);
+        }
+    };
+    if constexpr (sizeof(Tv) == 4) {
+        // nlev + 5 steps, padded to a multiple of five with steps that do nothing but the barrier
+        const int nsteps = (nlev + 5 + 4) / 5 * 5;
+        for (int st = 0; st < nsteps; st += 5) {
+            step(std::integral_constant<int, 0>{}, st);
+            step(std::integral_constant<int, 1>{}, st + 1);
+            step(std::integral_constant<int, 2>{}, st + 2);
+            step(std::integral_constant<int, 3>{}, st + 3);
+            step(std::integral_constant<int, 4>{}, st + 4);
+        }
+    } else {
+        // FP64 vectors: unrolled by five the kernel would not fit two waves per SIMD; every
+        // step takes phase 0 and the rings are turned by one slot after it
+        for (int st = 0; st < nlev + 5; ++st) {
+            step(std::integral_constant<int, 0>{}, st);
+#pragma unroll
+            for (int t = 0; t < kFuL1PerWave; ++t) {
+                const uint2 x = xw[t][0];
+#pragma unroll
+                for (int d = 0; d < 4; ++d) xw[t][d] = xw[t][d + 1];
+                xw[t][4] = x;
+            }
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+                const bf16x8 v = vw[s][0];
+                const float r = racc[s][0];
+#pragma unroll
+                for (int d = 0; d < 4; ++d) {
+                    vw[s][d] = vw[s][d + 1];
+                    racc[s][d] = racc[s][d + 1];
+                }
+                vw[s][4] = v;
+                racc[s][4] = r;
+            }
+        }
     }
 }
 
@@ -1485,6 +1834,25 @@ void launch_net_out(const NetGeo &g, const NetDev &d, const NetActs &act, const 
                        stop_mask, c.tiles, c.kchunk, c.units, c.per_xcd);
 }
 
+// the one-launch inference takes blocks of 64 longitudes and 32-bit byte offsets (FP64 vectors)
+bool net_fused_ok(const NetGeo &g) { return g.nlon % kFuCols == 0 && (unsigned long)g.n * 8 < (1ul << 32); }
+
+void launch_net_static(long n, const double *a64, uint32_t *fs, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_net_static, dim3(net_blocks(n, 1024, 8192)), dim3(256), 0, s, n, a64, fs);
+}
+
+template <typename Tv>
+void launch_net_infer(const NetGeo &g, const NetDev &d, const Tv *q, const Tv *z0, const uint32_t *fstat, Tv *qout,
+                      float *delta, const Scalars *sc, int stop_mask, hipStream_t s)
+{
+    const int nstrips = g.nlon / kFuCols;
+    const long nb = (long)nstrips * ((g.nlat + kFuRows - 1) / kFuRows);
+    const int per_xcd = (int)((nb + 7) / 8);
+    hipLaunchKernelGGL((k_net_fused<Tv>), dim3(per_xcd * 8), dim3(64 * kFuWaves), 0, s, g, q, z0, fstat, d.w1f, d.w2f, d.w3f,
+                       d.w4, d.theta, qout, delta, sc, stop_mask, nstrips, (int)nb, per_xcd);
+}
+
 void launch_thomas_t(const TriView<float> &tv, const float *y, float *z, hipStream_t s)
 {
     hipLaunchKernelGGL(k_thomas_t, dim3((unsigned)((tv.P + 255) / 256)), dim3(256), 0, s, tv, y, z);
@@ -1554,6 +1922,10 @@ template void launch_net_forward_fused<double>(const NetGeo &, const NetDev &, c
                                                double *, float *, const Scalars *, int, hipStream_t);
 template void launch_net_forward_fused<float>(const NetGeo &, const NetDev &, const NetActs &, const float *, float *,
                                               float *, const Scalars *, int, hipStream_t);
+template void launch_net_infer<double>(const NetGeo &, const NetDev &, const double *, const double *,
+                                       const uint32_t *, double *, float *, const Scalars *, int, hipStream_t);
+template void launch_net_infer<float>(const NetGeo &, const NetDev &, const float *, const float *, const uint32_t *,
+                                      float *, float *, const Scalars *, int, hipStream_t);
 template void launch_net_out<double>(const NetGeo &, const NetDev &, const NetActs &, const double *, double *,
                                      float *, const Scalars *, int, hipStream_t);
 template void launch_net_out<float>(const NetGeo &, const NetDev &, const NetActs &, const float *, float *, float *,

@@ -36,11 +36,13 @@ def _rel(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
-# 32x6x9 and 48x7x20 take the 3x3 kernel for rows of whole 16-position tiles (nlon % 16 == 0),
-# 64x6x9 and 128x5x12 the one for strips of 64 positions (nlon % 64 == 0)
+# 32x6x9 and 48x7x20 take the layered inference with the 3x3 kernel for rows of whole
+# 16-position tiles (nlon % 16 == 0); 64x6x9, 128x5x12 and 192x9x70 (nlon % 64 == 0) the
+# one-launch inference, whose last block of four rows is partly outside the grid
 @pytest.mark.parametrize("p", [synth.Problem(24, 12, 9, seed=2), synth.Problem(37, 9, 20, seed=3),
                                synth.Problem(32, 6, 9, seed=4), synth.Problem(48, 7, 20, seed=5),
-                               synth.Problem(64, 6, 9, seed=6), synth.Problem(128, 5, 12, seed=7)],
+                               synth.Problem(64, 6, 9, seed=6), synth.Problem(128, 5, 12, seed=7),
+                               synth.Problem(192, 9, 70, seed=8)],
                          ids=lambda p: f"{p.nlon}x{p.nlat}x{p.nlev}")
 def test_forward_matches_oracle(eg, p):
     import torch
@@ -61,6 +63,46 @@ def test_forward_matches_oracle(eg, p):
     per_level = np.linalg.norm((dg - d_ref).reshape(p.nlev, -1), axis=1) / (np.linalg.norm(d_ref) / np.sqrt(p.nlev))
     print(f"forward parity: delta rel L2 {e_d:.2e} (worst level {per_level.max():.2e}), M(q) rel L2 {e_z:.2e}")
     assert e_d <= 2e-3 and per_level.max() <= 5e-3 and e_z <= 1e-3
+    net.close()
+
+
+# nlon a multiple of 64: 64x6x9 and 192x9x70 leave the last four-row block partly outside the
+# grid, 128x1x3 has one row (both neighbours are poles) and fewer levels than taps, 256x8x20
+# spans several blocks in both directions
+@pytest.mark.parametrize("shape", [(64, 6, 9), (128, 1, 3), (192, 9, 70), (256, 8, 20)],
+                         ids=lambda s: "x".join(map(str, s)))
+def test_fused_inference_is_the_layered_one_bitwise(eg, shape):
+    """The one-launch inference (option net_fused 1) against the layer-by-layer kernels
+    (net_fused 0): the same delta and M(q) bit for bit, and learned solves in FP64 and in FP32
+    with refinement that follow the same trajectory bit for bit."""
+    import torch
+    p = synth.Problem(*shape, seed=11)
+    coef = synth.make_coeffs(p)
+    net = eg.Net(0)
+    net.set_weights(_theta(5).astype(np.float32))
+    q = dev(np.random.default_rng(6).standard_normal(p.n).astype(np.float32))
+    b = dev(synth.make_rhs(p).ravel())
+    with eg.Operator(dev(coef)) as op:
+        out = {}
+        for fused in (1, 0):
+            op.set_option("net_fused", fused)
+            delta = torch.empty(p.n, dtype=torch.float32, device="cuda")
+            z = net.apply(op, q, delta)
+            op.attach(net)
+            op.set_option("learned_method", 0)
+            sols = []
+            for mode in (eg.LEARNED_FP64, eg.LEARNED_FP32_IR):
+                x = torch.zeros(p.n, dtype=torch.float64, device="cuda")
+                info = op.solve(b, x, 1e-10, 12, mode)
+                sols.append((x, op.history(), info.iterations))
+            op.attach(None)
+            out[fused] = (z, delta, sols)
+        z1, d1, s1 = out[1]
+        z0, d0, s0 = out[0]
+        assert torch.equal(d1, d0) and torch.equal(z1, z0)
+        assert float(torch.linalg.vector_norm(d1)) > 0.0
+        for (x1, h1, i1), (x0, h0, i0) in zip(s1, s0):
+            assert i1 == i0 and torch.equal(x1, x0) and np.array_equal(h1, h0)
     net.close()
 
 
