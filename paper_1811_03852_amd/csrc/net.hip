@@ -1314,7 +1314,9 @@ __global__ __launch_bounds__(64 * kFuWaves) __attribute__((amdgpu_waves_per_eu(2
         const int ly = threadIdx.x / 8, nt = (threadIdx.x / 4) % 2, gq = threadIdx.x % 4;
         bias_s[ly][nt][gq] = bias4(theta + (ly == 0 ? kNetOffB1 : (ly == 1 ? kNetOffB2 : kNetOffB3)), nt, gq);
     }
-    __syncthreads();   // the 3x3 weights and the biases, before layer 1 of the first step
+    // both layer-1 planes start at zero: rows outside the grid (the poles) are never written
+    for (int e = threadIdx.x; e < 2 * kFuA1Elems; e += 64 * kFuWaves) (&a1s[0][0])[e] = make_uint4(0, 0, 0, 0);
+    __syncthreads();   // the 3x3 weights, the biases and the zeroed planes, before layer 1
     uint32_t wd[4];
 #pragma unroll
     for (int i = 0; i < 8; i += 2) {
@@ -1366,23 +1368,51 @@ __global__ __launch_bounds__(64 * kFuWaves) __attribute__((amdgpu_waves_per_eu(2
         return Raw{ld_off(q, pos1[t] * (uint32_t)sizeof(Tv) + lc * step_v),
                    ld_off(z0, pos1[t] * (uint32_t)sizeof(Tv) + lc * step_v), ld_off(fstat, pos1[t] * 4u + lc * step_f)};
     };
-    // input channels of tile t at level L (zero outside the column or the grid)
-    auto channels = [&](int t, int L, const Raw &v) -> uint2 {
-        const bool keep = val1[t] && L >= 0 && L < nlev;
-        return make_uint2(keep ? vec_channels(v.q, v.z, inv_rho, inv_rhoz) : 0u, keep ? v.f : 0u);
+    // input channels at level L (zero outside the column; positions outside the grid compute
+    // values that are never stored)
+    auto channels = [&](int L, const Raw &v) -> uint2 {
+        const bool keep = L >= 0 && L < nlev;   // uniform
+        return keep ? make_uint2(vec_channels(v.q, v.z, inv_rho, inv_rhoz), v.f) : make_uint2(0u, 0u);
     };
     // Rolling windows are rings indexed by level mod 5 (the loop below is unrolled by five, so
     // every index is a constant and nothing is copied from slot to slot):
-    //   xw   input channels of levels st - 2 .. st + 2,
+    //   xw   input channels of levels st - 1 .. st + 3 (layer 1 runs one level ahead),
     //   vw   a2 of levels st - 5 .. st - 1,
     //   racc pending outputs of levels st - 5 .. st - 1 (started from the output bias).
     uint2 xw[kFuL1PerWave][5];
-    Raw nxt[kFuL1PerWave];       // level st + 3, in flight during step st
+    Raw nxt[kFuL1PerWave];       // level st + 4, in flight during step st
+    // layer 1 at level L from the window (taps 2 grp, 2 grp + 1 are levels L - 2 + 2 grp,
+    // L - 1 + 2 grp, in slots (L - 2 + tap) mod 5), into LDS plane L & 1
+    uint2 *a1w = reinterpret_cast<uint2 *>(&a1s[0][0]);
+    auto layer1 = [&](auto l_c, int L) {
+        constexpr int LM = decltype(l_c)::value;   // L mod 5
+        uint2 *pl = a1w + (L & 1) * (kFuA1Elems * 2);
+#pragma unroll
+        for (int t = 0; t < kFuL1PerWave; ++t) {
+            if (wv + kFuWaves * t >= kFuL1Tiles) continue;   // wave-uniform
+            const uint2 x0 = xw[t][(LM + 3) % 5], x1 = xw[t][(LM + 4) % 5], x2 = xw[t][LM % 5],
+                        x3 = xw[t][(LM + 1) % 5], x4 = xw[t][(LM + 2) % 5];
+            const uint2 lo = make_uint2((x0.x & g0) | (x2.x & g1) | (x4.x & g2), (x0.y & g0) | (x2.y & g1) | (x4.y & g2));
+            const uint2 hi = make_uint2((x1.x & g0) | (x3.x & g1), (x1.y & g0) | (x3.y & g1));
+            const bf16x8 a = __builtin_bit_cast(bf16x8, make_uint4(lo.x, lo.y, hi.x, hi.y));
+            const f32x4 acc0 = mfma(w1a[0], a, bias_s[0][0][grp]);
+            const f32x4 acc1 = mfma(w1a[1], a, bias_s[0][1][grp]);
+            if (val1[t]) {
+                pl[dst1[t]] = relu_pack4(acc0);                        // channels 4 grp .. + 3
+                pl[dst1[t] + 2 * 2 * kFuA1Cols] = relu_pack4(acc1);    // channels 16 + 4 grp .. + 3
+            }
+        }
+    };
 #pragma unroll
     for (int t = 0; t < kFuL1PerWave; ++t)
         if (wv + kFuWaves * t < kFuL1Tiles)
 #pragma unroll
-            for (int L = -2; L <= 2; ++L) xw[t][(L + 5) % 5] = channels(t, L, load_raw(t, L));
+            for (int L = -2; L <= 2; ++L) xw[t][(L + 5) % 5] = channels(L, load_raw(t, L));
+    layer1(std::integral_constant<int, 0>{}, 0);
+#pragma unroll
+    for (int t = 0; t < kFuL1PerWave; ++t)   // level 3 replaces level -2
+        if (wv + kFuWaves * t < kFuL1Tiles) xw[t][3] = channels(3, load_raw(t, 3));
+    __syncthreads();   // layer 1 of level 0
 
     // this wave's output row and the positions of its two tiles
     const int lr = wv >> 1, hc = kFuCols / 2 * (wv & 1);
@@ -1399,44 +1429,23 @@ __global__ __launch_bounds__(64 * kFuWaves) __attribute__((amdgpu_waves_per_eu(2
             racc[s][d] = b4;
         }
 
-    uint2 *a1w = reinterpret_cast<uint2 *>(&a1s[0][0]);
     // one step; PH = st mod 5
     auto step = [&](auto ph_c, int st) {
         constexpr int PH = decltype(ph_c)::value;
         const int buf = st & 1;
         const int k = st - 5;   // output level of this step
-        // loads consumed at the end of the step: layer-1 inputs of level st + 3, q of level k
-        if (st < nlev) {
+        // loads consumed at the end of the step: layer-1 inputs of level st + 4, q of level k
+        if (st + 1 < nlev) {
 #pragma unroll
             for (int t = 0; t < kFuL1PerWave; ++t)
-                if (wv + kFuWaves * t < kFuL1Tiles) nxt[t] = load_raw(t, st + 3);
+                if (wv + kFuWaves * t < kFuL1Tiles) nxt[t] = load_raw(t, st + 4);
         }
         const uint32_t ko = static_cast<uint32_t>(min(max(k, 0), nlev - 1));
         Tv qo[2];
 #pragma unroll
         for (int s = 0; s < 2; ++s) qo[s] = ld_off(q, (po + 16 * s) * (uint32_t)sizeof(Tv) + ko * step_v);
-        // ---- layer 1 at level st: taps 2 grp, 2 grp + 1 are levels st - 2 + 2 grp, st - 1 + 2 grp
-        if (st < nlev) {
-            uint2 *pl = a1w + buf * (kFuA1Elems * 2);
-#pragma unroll
-            for (int t = 0; t < kFuL1PerWave; ++t) {
-                if (wv + kFuWaves * t >= kFuL1Tiles) continue;   // wave-uniform
-                const uint2 x0 = xw[t][(PH + 3) % 5], x1 = xw[t][(PH + 4) % 5], x2 = xw[t][PH % 5],
-                            x3 = xw[t][(PH + 1) % 5], x4 = xw[t][(PH + 2) % 5];
-                const uint2 lo = make_uint2((x0.x & g0) | (x2.x & g1) | (x4.x & g2), (x0.y & g0) | (x2.y & g1) | (x4.y & g2));
-                const uint2 hi = make_uint2((x1.x & g0) | (x3.x & g1), (x1.y & g0) | (x3.y & g1));
-                const bf16x8 a = __builtin_bit_cast(bf16x8, make_uint4(lo.x, lo.y, hi.x, hi.y));
-                const f32x4 acc0 = mfma(w1a[0], a, bias_s[0][0][grp]);
-                const f32x4 acc1 = mfma(w1a[1], a, bias_s[0][1][grp]);
-                if (dst1[t] >= 0) {
-                    const uint2 zz = make_uint2(0, 0);
-                    const uint2 v0 = relu_pack4(acc0), v1 = relu_pack4(acc1);
-                    pl[dst1[t]] = val1[t] ? v0 : zz;                       // channels 4 grp .. + 3
-                    pl[dst1[t] + 2 * 2 * kFuA1Cols] = val1[t] ? v1 : zz;   // channels 16 + 4 grp .. + 3
-                }
-            }
-        }
-        __syncthreads();
+        // ---- layer 1 at level st + 1, into the plane the 3x3 layer reads next step ----
+        if (st + 1 < nlev) layer1(std::integral_constant<int, (PH + 1) % 5>{}, st + 1);
         // ---- a2 of level st - 1 joins the window ----
         if (st >= 1 && st - 1 < nlev) {
 #pragma unroll
@@ -1504,12 +1513,15 @@ __global__ __launch_bounds__(64 * kFuWaves) __attribute__((amdgpu_waves_per_eu(2
             }
             racc[s][PH] = b4;   // the slot's next level is st
         }
-        // level st + 3 enters the layer-1 window (in the slot of level st - 2)
-        if (st < nlev) {
+        // level st + 4 enters the layer-1 window (in the slot of level st - 1)
+        if (st + 1 < nlev) {
 #pragma unroll
             for (int t = 0; t < kFuL1PerWave; ++t)
-                if (wv + kFuWaves * t < kFuL1Tiles) xw[t][(PH + 3) % 5] = channels(t, st + 3, nxt[t]);
+                if (wv + kFuWaves * t < kFuL1Tiles) xw[t][(PH + 4) % 5] = channels(st + 4, nxt[t]);
         }
+        // layer 1 of level st + 1 and the a2 tile of level st are complete; the plane and the
+        // tile read this step may be written again
+        __syncthreads();
     };
     if constexpr (sizeof(Tv) == 4) {
         // nlev + 5 steps, padded to a multiple of five with steps that do nothing but the barrier
