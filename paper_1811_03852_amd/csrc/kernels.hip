@@ -594,6 +594,156 @@ __global__ __launch_bounds__(kTriWG) void k_thomas(TriView<Tv> tv, const Tv *__r
     thomas_body<Tv, NL, MODE, CM, PF>(tv, q, z, r, p, v, rhat, partials, sc, stop_mask, qcm, nlon);
 }
 
+// FP32 vectors, two adjacent columns per lane: every load and store moves 8 bytes per lane (512
+// per wave, as in FP64); the same arithmetic per column, so z is bitwise the one-column
+// kernel's (TH_S sums ||s||^2 over the lane's two columns).  Register path only; the launcher
+// guarantees P % (2 kTriWG) == 0, an even nlon and n * 4 < 2^32.  TH_P at 2560x1920x70:
+// 5.50 against 5.14 TB/s with one column per lane (isolated kernels).
+typedef float f2v __attribute__((ext_vector_type(2)));
+template <int NL, int MODE, bool CM, int PF>
+__device__ __forceinline__ void thomas_body_pair(TriView<float> tv, const float *__restrict__ q,
+                                                 float *__restrict__ z, const float *__restrict__ r,
+                                                 float *__restrict__ p, const float *__restrict__ v,
+                                                 float *__restrict__ rhat, double *__restrict__ partials,
+                                                 const Scalars *__restrict__ sc, int stop_mask,
+                                                 float *__restrict__ qcm, int nlon)
+{
+    if (stopped(sc, stop_mask)) return;
+    const long P = tv.P, n = tv.n;
+    const uint32_t u = blockIdx.x * kTriWG + threadIdx.x;   // columns 2u and 2u + 1 of the plane
+    float beta = 0, omega = 0, alpha = 0;
+    if constexpr (MODE == TH_P) {
+        if (sc->fresh) return;   // a restart iteration is TH_PF's
+        beta = static_cast<float>(sc->beta);
+        omega = static_cast<float>(sc->omega);
+    }
+    if constexpr (MODE == TH_PF)
+        if (!sc->fresh) return;
+    if constexpr (MODE == TH_S) alpha = static_cast<float>(sc->alpha);
+    const uint32_t step = static_cast<uint32_t>(P * 4);
+    const uint32_t bo0 = u * 8u;
+    // colour-major element offsets of the two columns (same row, i even, so opposite colours
+    // and the same index within the colour)
+    uint32_t ca0 = 0, cb0 = 0;
+    const uint32_t cstep = static_cast<uint32_t>(P / 2 * 4);
+    if constexpr (CM) {
+        const uint32_t c0 = 2 * u;
+        const int i = (int)(c0 % (uint32_t)nlon), j = (int)(c0 / (uint32_t)nlon);
+        const long within = (long)j * (nlon / 2) + i / 2;
+        const long colour = (i + j) & 1;
+        ca0 = static_cast<uint32_t>((colour * (n / 2) + within) * 4);
+        cb0 = static_cast<uint32_t>(((colour ^ 1) * (n / 2) + within) * 4);
+    }
+    const float *lf = tv.f;
+    const float *invf = tv.f + n;
+    const float *cf = tv.f + 2 * n;
+    auto ld = [](const float *base, uint32_t bo) { return ldn(reinterpret_cast<const f2v *>(base), bo); };
+    auto st = [](float *base, uint32_t bo, f2v val) { stn(reinterpret_cast<f2v *>(base), bo, val); };
+    double acc[1] = {0.0};
+    f2v w[NL];
+    {
+        f2v b0[PF], b1[PF], b2[PF], bl[PF];
+        uint32_t bl_off = bo0;
+        auto issue = [&](int sl) {
+            if constexpr (MODE == TH_PLAIN) {
+                b0[sl] = ld(q, bl_off);
+            } else if constexpr (MODE == TH_P) {
+                b0[sl] = ld(r, bl_off);
+                b1[sl] = ld(p, bl_off);
+                b2[sl] = ld(v, bl_off);
+            } else if constexpr (MODE == TH_PF) {
+                b0[sl] = ld(r, bl_off);
+            } else {
+                b0[sl] = ld(r, bl_off);
+                b2[sl] = ld(v, bl_off);
+            }
+            bl[sl] = ld(lf, bl_off);
+            bl_off += step;
+        };
+#pragma unroll
+        for (int k = 0; k < PF && k < NL; ++k) issue(k);
+        uint32_t bo = bo0, ca = ca0, cb = cb0;
+        f2v wprev = {0.f, 0.f};
+        double ss = 0.0;
+#pragma unroll
+        for (int k = 0; k < NL; ++k) {
+            const int sl = k % PF;
+            f2v qk;
+            if constexpr (MODE == TH_PLAIN) {
+                qk = b0[sl];
+            } else if constexpr (MODE == TH_P) {
+                qk = b0[sl] + beta * (b1[sl] - omega * b2[sl]);
+                st(p, bo, qk);
+            } else if constexpr (MODE == TH_PF) {
+                qk = b0[sl];
+                st(rhat, bo, qk);
+                st(p, bo, qk);
+            } else {
+                qk = b0[sl] - alpha * b2[sl];
+                st(p, bo, qk);
+                ss = fma(static_cast<double>(qk.x), static_cast<double>(qk.x), ss);
+                ss = fma(static_cast<double>(qk.y), static_cast<double>(qk.y), ss);
+                asm volatile("" : "+v"(ss));
+            }
+            if constexpr (CM) {
+                stn(qcm, ca, qk.x);
+                stn(qcm, cb, qk.y);
+                ca += cstep;
+                cb += cstep;
+            }
+            w[k] = qk + bl[sl] * wprev;
+            wprev = w[k];
+            bo += step;
+            if (k + PF < NL) issue(sl);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        if constexpr (MODE == TH_S) acc[0] = ss;
+    }
+    f2v bi[PF], bc[PF];
+    uint32_t bl_off = bo0 + static_cast<uint32_t>(NL - 1) * step;
+#pragma unroll
+    for (int j = 0; j < PF && j < NL; ++j) {
+        bi[j] = ld(invf, bl_off);
+        bc[j] = ld(cf, bl_off);
+        bl_off -= step;
+    }
+    uint32_t bo = bo0 + static_cast<uint32_t>(NL - 1) * step;
+    uint32_t ca = ca0 + static_cast<uint32_t>(NL - 1) * cstep, cb = cb0 + static_cast<uint32_t>(NL - 1) * cstep;
+    f2v zz = {0.f, 0.f};
+#pragma unroll
+    for (int k = NL - 1; k >= 0; --k) {
+        const int sl = (NL - 1 - k) % PF;
+        zz = bi[sl] * w[k] + bc[sl] * zz;
+        if constexpr (CM) {
+            stn(z, ca, zz.x);
+            stn(z, cb, zz.y);
+            ca -= cstep;
+            cb -= cstep;
+        } else {
+            st(z, bo, zz);
+            bo -= step;
+        }
+        if (k - PF >= 0) {
+            bi[sl] = ld(invf, bl_off);
+            bc[sl] = ld(cf, bl_off);
+            bl_off -= step;
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    if constexpr (MODE == TH_S) wave_sum_store<1>(acc, partials + (long)blockIdx.x * kPartialCols);
+}
+
+template <int NL, int MODE, bool CM, int PF = 8>
+__global__ __launch_bounds__(kTriWG) void k_thomas_pair(TriView<float> tv, const float *__restrict__ q,
+                                                     float *__restrict__ z, const float *__restrict__ r,
+                                                     float *__restrict__ p, const float *__restrict__ v,
+                                                     float *__restrict__ rhat, double *__restrict__ partials,
+                                                     const Scalars *__restrict__ sc, int stop_mask,
+                                                     float *__restrict__ qcm, int nlon)
+{
+    thomas_body_pair<NL, MODE, CM, PF>(tv, q, z, r, p, v, rhat, partials, sc, stop_mask, qcm, nlon);
+}
+
 // Deep columns in FP64 (140 levels: 280 registers of forward values): one wave per SIMD, so the
 // compiler may use the whole register file (architectural and accumulation registers) and keep
 // 24 levels of loads in flight.  5.46 TB/s at 1280x960x140 against 3.95 TB/s for parking the
@@ -608,15 +758,18 @@ __global__ __launch_bounds__(kTriWG) __attribute__((amdgpu_waves_per_eu(1, 1))) 
     thomas_body<Tv, NL, MODE, CM, kDeepPF>(tv, q, z, r, p, v, rhat, partials, sc, stop_mask, qcm, nlon);
 }
 
-template <typename Tv, int NL, bool CM, bool DEEP = false>
+template <typename Tv, int NL, bool CM, bool DEEP = false, bool PAIR = false>
 static int thomas_dispatch_mode(const TriView<Tv> &tv, const Tv *q, Tv *z, int mode, const Tv *r, Tv *p,
                                 const Tv *v, Tv *rhat, double *partials, const Scalars *sc, hipStream_t s,
                                 int stop_mask, Tv *qcm, int nlon)
 {
-    const int nb = (int)((tv.P + kTriWG - 1) / kTriWG);
+    const int nb = (int)((tv.P / (PAIR ? 2 : 1) + kTriWG - 1) / kTriWG);
     auto launch = [&](auto mode_c, int mask) {
         constexpr int M = decltype(mode_c)::value;
-        if constexpr (DEEP)
+        if constexpr (PAIR)
+            hipLaunchKernelGGL((k_thomas_pair<NL, M, CM>), dim3(nb), dim3(kTriWG), 0, s, tv, q, z, r, p, v, rhat,
+                               partials, sc, mask, qcm, nlon);
+        else if constexpr (DEEP)
             hipLaunchKernelGGL((k_thomas_deep<Tv, NL, M, CM>), dim3(nb), dim3(kTriWG), 0, s, tv, q, z, r, p, v, rhat,
                                partials, sc, mask, qcm, nlon);
         else
@@ -646,6 +799,17 @@ static int thomas_dispatch(const TriView<Tv> &tv, const Tv *q, Tv *z, int mode, 
     // fill whole workgroups and whose arrays are addressable with 32-bit byte offsets; any
     // other grid takes the generic path.
     const bool reg = (tv.P % kTriWG == 0) && ((unsigned long)tv.n * sizeof(Tv) < (1ul << 32));
+    if constexpr (sizeof(Tv) == 4) {
+        // FP32: two columns per lane where the plane fills whole waves of column pairs (and, for
+        // the colour-major output, the pairs lie within a latitude row)
+        const bool pair = reg && tv.P % (2 * kTriWG) == 0 && (!CM || nlon % 2 == 0);
+        if (pair && tv.nlev == 20)
+            return thomas_dispatch_mode<Tv, 20, CM, false, true>(tv, q, z, mode, r, p, v, rhat, partials, sc, s,
+                                                                  stop_mask, qcm, nlon);
+        if (pair && tv.nlev == 70)
+            return thomas_dispatch_mode<Tv, 70, CM, false, true>(tv, q, z, mode, r, p, v, rhat, partials, sc, s,
+                                                                  stop_mask, qcm, nlon);
+    }
     if (reg && tv.nlev == 20)
         return thomas_dispatch_mode<Tv, 20, CM>(tv, q, z, mode, r, p, v, rhat, partials, sc, s, stop_mask, qcm, nlon);
     if (reg && tv.nlev == 70)
