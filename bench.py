@@ -57,17 +57,19 @@ PREC_NAME = {0: "fp64", 1: "fp32", 2: "bf16", 3: "fp16"}
 # HBM bytes per launch measured with rocprofv3 FETCH_SIZE and WRITE_SIZE on the 2560x1920x70
 # grid (`python bench.py --traffic-probe` under `rocprofv3 --pmc`), scaled by the same counters
 # on a device copy of known size (FETCH_SIZE x 2, WRITE_SIZE x 1).  Valid while the kernels
-# are unchanged since that measurement; see profiles/hbm_traffic_2560x1920x70.txt.
-MEASURED_TRAFFIC = {("n1280_2560x1920x70", "spmv_fp64"): 28.74e9, ("n1280_2560x1920x70", "spmv_fp32"): 14.67e9, ("n1280_2560x1920x70", "spmv_bf16"): 9.87e9,
-                    ("n1280_2560x1920x70", "thomas_p_fp64"): 22.02e9, ("n1280_2560x1920x70", "thomas_s_fp64"): 19.27e9, ("n1280_2560x1920x70", "update_fp64"): 22.02e9,
-                    ("n1280_2560x1920x70", "thomas_p_fp32"): 11.01e9, ("n1280_2560x1920x70", "thomas_s_fp32"): 9.63e9, ("n1280_2560x1920x70", "update_fp32"): 11.01e9,
-                    ("n1280_2560x1920x70", "thomas_p_bf16"): 11.01e9, ("n1280_2560x1920x70", "thomas_s_bf16"): 9.63e9, ("n1280_2560x1920x70", "update_bf16"): 11.01e9,
-                    ("n1280_2560x1920x70", "residual_fp64"): 27.42e9,
-                    ("n1280_2560x1920x70", "thomas_p_cm_fp64"): 24.77e9, ("n1280_2560x1920x70", "thomas_s_cm_fp64"): 22.02e9,
-                    ("n1280_2560x1920x70", "thomas_p_cm_fp32"): 12.39e9, ("n1280_2560x1920x70", "thomas_s_cm_fp32"): 11.01e9,
-                    ("n1280_2560x1920x70", "thomas_p_cm_bf16"): 12.39e9, ("n1280_2560x1920x70", "thomas_s_cm_bf16"): 11.01e9,
+# are unchanged since that measurement; see profiles/hbm_traffic_2560x1920x70.txt.  The 16-bit
+# modes run the FP32 tridiagonal and update kernels.
+_C = "n1280_2560x1920x70"
+MEASURED_TRAFFIC = {(_C, "spmv_fp64"): 28.74e9, (_C, "spmv_fp32"): 14.67e9, (_C, "spmv_bf16"): 9.82e9,
+                    (_C, "residual_fp64"): 27.35e9,
+                    (_C, "thomas_p_fp64"): 22.02e9, (_C, "thomas_s_fp64"): 19.27e9, (_C, "update_fp64"): 22.02e9,
+                    (_C, "thomas_p_fp32"): 11.01e9, (_C, "thomas_s_fp32"): 9.63e9, (_C, "update_fp32"): 11.01e9,
+                    (_C, "thomas_p_bf16"): 11.01e9, (_C, "thomas_s_bf16"): 9.63e9, (_C, "update_bf16"): 11.01e9,
+                    (_C, "thomas_p_cm_fp64"): 24.77e9, (_C, "thomas_s_cm_fp64"): 22.02e9,
+                    (_C, "thomas_p_cm_fp32"): 12.39e9, (_C, "thomas_s_cm_fp32"): 11.01e9,
+                    (_C, "thomas_p_cm_bf16"): 12.39e9, (_C, "thomas_s_cm_bf16"): 11.01e9,
                     # one line-SOR application = five half-sweeps
-                    ("n1280_2560x1920x70", "sor_fp64"): 80.83e9, ("n1280_2560x1920x70", "sor_fp32"): 39.62e9, ("n1280_2560x1920x70", "sor_bf16"): 32.77e9}
+                    (_C, "sor_fp64"): 81.75e9, (_C, "sor_fp32"): 40.24e9, (_C, "sor_bf16"): 32.78e9}
 
 
 _T_START = time.perf_counter()
