@@ -269,9 +269,9 @@ def _timed_solve(op, torch, b, x, tol, mode, reps):
 def learned_comparison(eg, torch, nets, cfg_name, tol, reps=3):
     """On the learned preconditioner's workload, in FP32 inner + FP64 refinement and in FP64:
     BiCGStab with T^-1 (the method without the network), flexible BiCGStab with each trained
-    network (and the tridiagonal fallback), FGMRES(30) with T^-1 and with each network.  The
-    BiCGStab rows are the median of `reps` timed solves after one untimed solve, the slower
-    FGMRES rows one timed solve after one untimed solve."""
+    network (and the tridiagonal fallback), FGMRES(30) with T^-1 and with each network.  After
+    one untimed solve, the BiCGStab rows are the median of `reps` timed solves, the slower FGMRES
+    rows the median of three."""
     import synth
     p = synth.CONFIGS[cfg_name]
     coef, b = generate_on_device(p, torch)
@@ -279,7 +279,7 @@ def learned_comparison(eg, torch, nets, cfg_name, tol, reps=3):
     del coef
     torch.cuda.empty_cache()
     out = {"workload": f"{p.nlon}x{p.nlat}x{p.nlev}, b ~ N(0,1), tol {tol}", "case": cfg_name,
-           "timing": f"BiCGStab rows: median of {reps}; FGMRES rows: one solve"}
+           "timing": f"after one untimed solve, BiCGStab rows: median of {reps} timed solves; FGMRES rows: median of 3"}
     x = torch.zeros(p.n, dtype=torch.float64, device="cuda")
     runs = [("bicgstab_tri", None, 0), ("fgmres_tri", None, 1)]
     for name in nets:
@@ -289,7 +289,7 @@ def learned_comparison(eg, torch, nets, cfg_name, tol, reps=3):
             op.attach(nets[net_name] if net_name else None)
             op.set_option("method", method)
             op.set_option("learned_method", method)
-            sec, info = _timed_solve(op, torch, b, x, tol, learned if net_name else plain, reps if method == 0 else 1)
+            sec, info = _timed_solve(op, torch, b, x, tol, learned if net_name else plain, reps if method == 0 else 3)
             key = f"{label}_{prec}"
             out[key] = {"seconds": round(sec, 4), "iterations": info.iterations, "outer_steps": info.outer_steps,
                         "fallbacks": info.fallbacks, "status": info.status, "true_rel_residual": info.true_rel_residual}
@@ -408,6 +408,66 @@ def paper_study(eg, torch, op, b):
             "tolerance_sweep": sweep}
 
 
+def fig1_study(eg, torch, configs=("small_96x72x20", "manufactured_640x480x70"), tol=1e-10):
+    """The paper's toy-model comparison (Sec. 4, Fig. 1): the all-32-bit BiCGStab (FP32 vectors,
+    coefficients and solution, FP64 sums; EG_FP32_MP with option mp_x32, no periodic restarts)
+    against the FP64 one, both with T^-1, R (the solver's recursive relative residual) against
+    iteration.  For R_c = 1e-1 .. 1e-8: the first iteration at which each solver's R reaches R_c,
+    their ratio, and the time to get there (iterations x that solver's time per iteration)."""
+    import numpy as np
+    import synth
+    out = {}
+    for name in configs:
+        p = synth.CONFIGS[name]
+        coef, b = generate_on_device(p, torch)
+        op = eg.Operator(coef)
+        del coef
+        op.set_option("restart_every", 10 ** 9)
+        rows, hist = {}, {}
+        maxit = 20000
+        x = torch.zeros(p.n, dtype=torch.float64, device="cuda")
+        for label, mode, x32 in (("dp", eg.FP64, 0), ("sp", eg.FP32_MP, 1)):
+            op.set_option("mp_x32", x32)
+            x.zero_()
+            op.solve(b, x, 1e-3, 50, mode)   # untimed: work vectors and coefficient copies
+            x.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            info = op.solve(b, x, tol, maxit, mode)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            h = np.asarray(op.history())
+            hist[label] = h
+            rows[label] = {"iterations": info.iterations, "status": info.status, "seconds": round(dt, 4),
+                           "ms_per_iteration": round(1e3 * dt / max(info.iterations, 1), 4),
+                           "true_rel_residual": info.true_rel_residual,
+                           "min_recursive_R": float(h.min()) if h.size else None,
+                           "R_every_5th_iteration": [float(f"{v:.3g}") for v in h[4::5]]}
+            if label == "dp":
+                maxit = 3 * info.iterations + 50
+        op.set_option("mp_x32", 0)
+        cross = {}
+        for k in range(1, 9):
+            e = {}
+            for label in ("dp", "sp"):
+                hit = np.nonzero(hist[label] <= 10.0 ** -k)[0]
+                its = int(hit[0]) + 1 if hit.size else None
+                e[f"{label}_iterations"] = its
+                e[f"{label}_ms"] = round(its * rows[label]["ms_per_iteration"], 3) if its else None
+            if e["dp_iterations"] and e["sp_iterations"]:
+                e["sp_over_dp_iterations"] = round(e["sp_iterations"] / e["dp_iterations"], 3)
+                e["sp_over_dp_time"] = round(e["sp_ms"] / e["dp_ms"], 3)
+            cross[f"1e-{k}"] = e
+        rows["by_R"] = cross
+        rows["time_per_iteration_sp_over_dp"] = round(rows["sp"]["ms_per_iteration"] / rows["dp"]["ms_per_iteration"], 3)
+        out[name] = rows
+        log(f"fig1 study {name}: " + ", ".join(f"{rc}: {e.get('sp_over_dp_iterations')}" for rc, e in cross.items()))
+        op.close()
+        del b, x
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -421,7 +481,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--learned-config", default="learned_640x480x70",
                     help="workload of the learned-preconditioner comparison ('' skips it)")
-    ap.add_argument("--learned-reps", type=int, default=3)
+    ap.add_argument("--learned-reps", type=int, default=5,
+                    help="timed solves per BiCGStab row of the learned comparison (median; FGMRES rows: 3)")
     ap.add_argument("--stress-config", default="stress_1280x960x140", help="stress case ('' skips it)")
     ap.add_argument("--error-ops", type=int, default=100, help="96x72x20 operators of the error-loss recipe")
     ap.add_argument("--error-epochs", type=int, default=20)
@@ -429,7 +490,8 @@ def main():
     ap.add_argument("--train-ops", type=int, default=16)
     ap.add_argument("--train-vecs", type=int, default=20)
     ap.add_argument("--train-epochs", type=int, default=20)
-    ap.add_argument("--no-paper-study", action="store_true", help="skip the DP vs MP comparison of the paper's Table 1")
+    ap.add_argument("--no-paper-study", action="store_true",
+                    help="skip the paper's comparisons (DP vs MP of its Table 1, 32- vs 64-bit of its Fig. 1)")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="run four iterations of each mode and a device copy of known size (for counter runs) and exit")
     args = ap.parse_args()
@@ -623,6 +685,7 @@ def main():
     torch.cuda.empty_cache()
 
     small = gpu_small_fp64(eg, torch)
+    fig1 = None if args.no_paper_study else fig1_study(eg, torch)
     learned = None
     if args.learned_config:
         learned = learned_comparison(eg, torch, nets, args.learned_config, args.tol, args.learned_reps)
@@ -667,6 +730,7 @@ def main():
         "learned": learned,
         "stress": stress,
         "paper_study": paper,
+        "fig1_study": fig1,
     }
     print(json.dumps(result), flush=True)
 

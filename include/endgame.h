@@ -163,6 +163,9 @@ int eg_set_stream(eg_operator *op, void *hip_stream);
  *   "method"         Krylov method of the plain modes: 0 BiCGStab, 1 restarted FGMRES [0]
  *   "learned_method" Krylov method of the learned modes: 0 flexible BiCGStab, 1 FGMRES [1]
  *   "gmres_m"        FGMRES restart length, 1..64 [30]
+ *   "mp_x32"         EG_FP32_MP only: 1 rounds the solution to FP32 after every update as well,
+ *                    giving the all-32-bit BiCGStab of the paper's toy-model comparison (Sec. 4,
+ *                    Fig. 1); with restart_every set beyond maxit it runs without restarts [0]
  *   "net_fused"      learned modes on grids with nlon a multiple of 64: 1 runs the network's
  *                    inference as one launch (input channels, all layers and q + rho delta,
  *                    activations kept on chip; a BF16 pair of static input channels per grid

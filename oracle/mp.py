@@ -13,7 +13,10 @@ true residual use the float64 operator.
 
 ``vec_dtype=np.float64`` turns every rounding off: the iteration is then the FP64 BiCGStab of
 ``oracle.bicgstab`` step for step (the same breakdown restarts, half-step exit, true-residual
-check and periodic restart), which is how this emulation is pinned.
+check and periodic restart), which is how this emulation is pinned.  ``x_dtype=np.float32``
+also rounds the solution to 32 bits after every update: the all-32-bit solver the paper
+compares with the 64-bit one in its toy model (Sec. 4, Fig. 1), pinned by its representation
+floor (its true residual stalls at that of the exact solution rounded to float32).
 """
 from __future__ import annotations
 
@@ -36,9 +39,16 @@ class MpInfo:
 
 
 def bicgstab_mp(coef: np.ndarray, b: np.ndarray, tol: float = 1e-4, maxit: int = 5000, restart_every: int = 150,
-                precond: str = "tri", sor_sweeps: int = 3, sor_omega: float = 1.5, vec_dtype=np.float32):
-    """Solve A x = b from x = 0; returns (x (float64), MpInfo)."""
+                precond: str = "tri", sor_sweeps: int = 3, sor_omega: float = 1.5, vec_dtype=np.float32,
+                x_dtype=np.float64):
+    """Solve A x = b from x = 0; returns (x (float64), MpInfo).  ``x_dtype=np.float32`` rounds
+    the solution to float32 after every update as well: the all-32-bit solver of the paper's
+    toy-model comparison (Sec. 4, Fig. 1; pass restart_every=0 for no periodic restarts)."""
     vd = np.dtype(vec_dtype)
+    xd = np.dtype(x_dtype)
+
+    def xr(v):                        # the solution's storage precision
+        return v if xd == np.float64 else v.astype(xd).astype(np.float64)
     b = np.asarray(b, dtype=np.float64).ravel()
     n = b.size
     coef_lo = coef.astype(vd).astype(np.float64) if vd != np.float64 else coef
@@ -112,7 +122,7 @@ def bicgstab_mp(coef: np.ndarray, b: np.ndarray, tol: float = 1e-4, maxit: int =
         s = lo(hi(r) - alpha * hi(v))
         snorm = nrm(s)
         if snorm / nb <= tol:                              # converged at the half step
-            x = x + alpha * hi(ph)
+            x = xr(x + alpha * hi(ph))
             hist.append(snorm / nb)
             status = 0
         else:
@@ -120,7 +130,7 @@ def bicgstab_mp(coef: np.ndarray, b: np.ndarray, tol: float = 1e-4, maxit: int =
             t = op_lo(sh)
             tt, ts = dot(t, t), dot(t, s)
             if tt == 0.0 or ts == 0.0:
-                x = x + alpha * hi(ph)
+                x = xr(x + alpha * hi(ph))
                 r = s
                 rnorm = snorm
                 restarts += 1
@@ -128,7 +138,7 @@ def bicgstab_mp(coef: np.ndarray, b: np.ndarray, tol: float = 1e-4, maxit: int =
                 hist.append(rnorm / nb)
                 continue
             omega = ts / tt
-            x = x + alpha * hi(ph) + omega * hi(sh)
+            x = xr(x + alpha * hi(ph) + omega * hi(sh))
             r = lo(hi(s) - omega * hi(t))
             rho_prev = rho
             rnorm = nrm(r)

@@ -129,8 +129,9 @@ template <typename Tf>
 void launch_tri_factor(const double *a64, const double *m64, int nlon, int nlat, int nlev, Tf *f, hipStream_t s);
 
 // x (FP64) += alpha phat + omega shat; r = s - omega t (FP32): the paper's mixed-precision update
+// (x32: x rounded to FP32 after every update, the all-32-bit solver)
 void launch_update_mp(long n, double *x, const float *ph, const float *sh, const float *s, const float *t, float *r,
-                      const float *rhat, double *partials, int *nrows, const Scalars *sc, hipStream_t stream);
+                      const float *rhat, double *partials, int *nrows, const Scalars *sc, bool x32, hipStream_t stream);
 template <typename Tv>
 void launch_update(long n, Tv *x, const Tv *ph, const Tv *sh, const Tv *s, const Tv *t, Tv *r, const Tv *rhat,
                    double *partials, int *nrows, const Scalars *sc, hipStream_t stream);

@@ -941,6 +941,9 @@ __global__ __launch_bounds__(kWG) void k_update(long n, Tv *__restrict__ x, cons
 // updated every iteration from the FP32 search directions with the FP64 scalars; the
 // residual recurrence stays FP32.  Same modes as k_update (full step, half step, half step
 // after a t = 0 breakdown).
+// X32: the solution is held in 32 bits as well (rounded after every update): the all-32-bit
+// solver the paper compares with the 64-bit one in its toy model (Sec. 4, Fig. 1)
+template <bool X32>
 __global__ __launch_bounds__(kWG) void k_update_mp(long n, double *__restrict__ x, const float *__restrict__ ph,
                                                    const float *__restrict__ sh, const float *__restrict__ s,
                                                    const float *__restrict__ t, float *__restrict__ r,
@@ -966,6 +969,7 @@ __global__ __launch_bounds__(kWG) void k_update_mp(long n, double *__restrict__ 
             acc[0] += static_cast<double>(rhat[i]) * static_cast<double>(ri);
             acc[1] += static_cast<double>(ri) * static_cast<double>(ri);
         }
+        if constexpr (X32) xi = static_cast<double>(static_cast<float>(xi));
         x[i] = xi;
     }
     block_sum_store<2>(acc, partials + (long)blockIdx.x * kPartialCols);
@@ -991,10 +995,13 @@ static int update_blocks(long n)
 }
 
 void launch_update_mp(long n, double *x, const float *ph, const float *sh, const float *s, const float *t, float *r,
-                      const float *rhat, double *partials, int *nrows, const Scalars *sc, hipStream_t stream)
+                      const float *rhat, double *partials, int *nrows, const Scalars *sc, bool x32, hipStream_t stream)
 {
     const int nb = update_blocks(n);
-    hipLaunchKernelGGL(k_update_mp, dim3(nb), dim3(kWG), 0, stream, n, x, ph, sh, s, t, r, rhat, partials, sc);
+    if (x32)
+        hipLaunchKernelGGL(k_update_mp<true>, dim3(nb), dim3(kWG), 0, stream, n, x, ph, sh, s, t, r, rhat, partials, sc);
+    else
+        hipLaunchKernelGGL(k_update_mp<false>, dim3(nb), dim3(kWG), 0, stream, n, x, ph, sh, s, t, r, rhat, partials, sc);
     if (nrows) *nrows = nb;
 }
 

@@ -174,6 +174,7 @@ struct eg_operator {
     double *mp_x = nullptr;     // EG_FP32_MP: the FP64 solution the FP32 iteration updates
     double *ir_backup = nullptr;   // refinement: x before the last correction
     bool mp_active = false;
+    bool mp_x32 = false;        // EG_FP32_MP with the solution held in 32 bits too (option mp_x32)
     // colour-major copies of the LU factors and the W, E, S, N couplings the SOR reads
     double *sorf64 = nullptr, *sora64 = nullptr;
     float *sorf32 = nullptr, *sora32 = nullptr;
@@ -416,7 +417,8 @@ void enqueue_iteration(eg_operator *op, const OpView<Tc> &A, Work<Tv> &w, hipEve
     mark(8);
     if constexpr (std::is_same_v<Tv, float>) {
         if (op->mp_active)
-            launch_update_mp(op->n, op->mp_x, w.ph, w.sh, w.s, w.t, w.r, w.rh, op->partials, &nr, op->sc, s);
+            launch_update_mp(op->n, op->mp_x, w.ph, w.sh, w.s, w.t, w.r, w.rh, op->partials, &nr, op->sc, op->mp_x32,
+                             s);
         else
             launch_update<Tv>(op->n, w.x, w.ph, w.sh, w.s, w.t, w.r, w.rh, op->partials, &nr, op->sc, s);
     } else {
@@ -1348,6 +1350,9 @@ int eg_set_option(eg_operator *op, const char *key, double value)
     } else if (k == "eps_bd") {
         if (!(value >= 0.0 && value < 1.0)) return fail(EG_EINVAL, "eps_bd must be in [0, 1)");
         op->eps_bd = value;
+    } else if (k == "mp_x32") {
+        if (value != 0.0 && value != 1.0) return fail(EG_EINVAL, "mp_x32 must be 0 or 1");
+        op->mp_x32 = value != 0.0;
     } else if (k == "net_fused") {
         if (value != 0.0 && value != 1.0) return fail(EG_EINVAL, "net_fused must be 0 or 1");
         op->net_fused = (int)value;

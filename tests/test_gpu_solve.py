@@ -342,3 +342,43 @@ def test_paper_mixed_precision_restarts_every_150(eg, oracle_mod):
     print(f"MP shift 1e-6: {info.iterations} its, {info.restarts} restarts, true R {rel:.2e}")
     assert info.status == eg.CONVERGED and rel <= 1e-5
     assert info.iterations > 150 and info.restarts >= info.iterations // 150
+
+
+def test_all_32_bit_solver_matches_the_oracle(eg, oracle_mod, small):
+    """Option mp_x32: EG_FP32_MP with the solution held in 32 bits too, the all-32-bit solver of
+    the paper's toy-model comparison (Sec. 4, Fig. 1), without periodic restarts.  Against the
+    oracle's emulation (oracle/mp.py, x_dtype float32): every entry of x is a float32, the first
+    residual-history entries agree to FP32 rounding and the iteration counts within 10 %; run
+    to 1e-12 its true residual stalls at the floor a float32 solution implies (the exact
+    solution rounded to float32), while the 64-bit-solution mode goes below that floor."""
+    import torch
+    from oracle import mp
+    p, coef, b, x_ref, _ = small
+    xo, ref = mp.bicgstab_mp(coef, b, tol=1e-4, restart_every=0, x_dtype=np.float32)
+    nb = np.linalg.norm(b)
+    floor = np.linalg.norm(b - oracle_mod.apply(coef, x_ref.astype(np.float32).astype(np.float64))) / nb
+    with eg.Operator(dev(coef)) as op:
+        op.set_option("restart_every", 10 ** 9)
+        op.set_option("mp_x32", 1)
+        x = torch.zeros(p.n, dtype=torch.float64, device="cuda")
+        info = op.solve(dev(b), x, 1e-4, 5000, eg.FP32_MP)
+        h = op.history()
+        xt = torch.zeros_like(x)
+        it = op.solve(dev(b), xt, 1e-12, 3000, eg.FP32_MP)
+        op.set_option("mp_x32", 0)
+        x64 = torch.zeros_like(x)
+        i64 = op.solve(dev(b), x64, 1e-12, 3000, eg.FP32_MP)
+    xh, xth = host(x), host(xt)
+    r_tight = _true_rel(oracle_mod, coef, b, xth)
+    r64 = _true_rel(oracle_mod, coef, b, host(x64))
+    print(f"all-32-bit: {info.iterations} its (oracle {ref.iterations}); to 1e-12: status {it.status}, true R "
+          f"{r_tight:.2e} (float32 floor {floor:.2e}); 64-bit x: status {i64.status}, true R {r64:.2e}")
+    assert info.status == eg.CONVERGED and ref.status == 0
+    assert np.array_equal(xh, xh.astype(np.float32).astype(np.float64))
+    assert np.array_equal(xth, xth.astype(np.float32).astype(np.float64))
+    assert abs(info.iterations - ref.iterations) <= max(2, ref.iterations // 10)
+    k = min(4, len(h), len(ref.history))
+    assert np.allclose(h[:k], ref.history[:k], rtol=1e-4, atol=0)
+    assert _true_rel(oracle_mod, coef, b, xh) <= 1e-4
+    assert 0.3 * floor <= r_tight <= 30 * floor and it.status != eg.CONVERGED
+    assert r64 <= 0.1 * floor

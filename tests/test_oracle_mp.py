@@ -51,3 +51,35 @@ def test_restarts_every_150_from_the_true_residual():
     assert info.status == 0 and info.iterations > 150
     assert info.restarts >= info.iterations // 150
     assert np.linalg.norm(b - oracle.apply(coef, x)) / np.linalg.norm(b) <= 1e-5
+
+
+def test_32_bit_solution_stalls_at_its_representation_floor():
+    """x_dtype float32 (the all-32-bit solver of the paper's toy model, Sec. 4 / Fig. 1): the
+    solution is held in 32 bits, so its true residual cannot fall below that of the exact
+    solution rounded to float32 (from a dense LU solve, independent of the iteration); the same
+    iteration with a 64-bit solution goes well below that floor."""
+    p = synth.Problem(12, 8, 6, seed=4)
+    coef, b = synth.make_coeffs(p), synth.make_rhs(p).ravel()
+    x_star = oracle.dense_solve(coef, b)
+    nb = np.linalg.norm(b)
+    floor = np.linalg.norm(b - oracle.apply(coef, x_star.astype(np.float32).astype(np.float64))) / nb
+    assert floor > 1e-9   # float32 rounding of x is visible in the residual at this conditioning
+    x32, i32 = mp.bicgstab_mp(coef, b, tol=1e-14, maxit=300, restart_every=0, x_dtype=np.float32)
+    x64, i64 = mp.bicgstab_mp(coef, b, tol=1e-14, maxit=300, restart_every=0)
+    assert np.array_equal(x32, x32.astype(np.float32).astype(np.float64))
+    r32 = np.linalg.norm(b - oracle.apply(coef, x32)) / nb
+    r64 = np.linalg.norm(b - oracle.apply(coef, x64)) / nb
+    print(f"floor {floor:.2e}, 32-bit x {r32:.2e}, 64-bit x {r64:.2e}")
+    assert 0.3 * floor <= r32 <= 30 * floor
+    assert r64 <= 0.1 * floor
+
+
+def test_32_bit_solution_follows_the_64_bit_one_early():
+    """Fig. 1's first observation: the two solvers' residual histories agree at first (here to
+    FP32 level over the first iterations) and part later."""
+    p, coef, b = _problem()
+    _, i32 = mp.bicgstab_mp(coef, b, tol=1e-10, maxit=400, restart_every=0, x_dtype=np.float32)
+    _, i64 = mp.bicgstab_mp(coef, b, tol=1e-10, maxit=400, restart_every=0)
+    k = min(len(i32.history), len(i64.history), 4)
+    d = np.abs(i32.history[:k] - i64.history[:k]) / i64.history[:k]
+    assert np.all(d < 1e-4)
