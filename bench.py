@@ -125,7 +125,8 @@ def _cpu_model() -> str:
 
 def cpu_baseline(gpu_fp64_iterations: int, sample_iters: int = 5):
     """The oracle (single-threaded C, -O2, no FMA contraction) on the host: a full FP64 solve of
-    the 96x72x20 problem, and a timed sample of `sample_iters` iterations on the benchmark's
+    the 96x72x20 problem, a full solve of the 640x480x70 problem with the OpenMP build of the
+    same source (thread count recorded), and a timed sample of `sample_iters` iterations on the benchmark's
     own 2560x1920x70 grid, scaled to the GPU's FP64 iteration count (extrapolated); the
     640x480x70 figure of the same kind is kept as context.  Per-iteration time = (time of a
     `sample_iters`-iteration run - 2 x one matrix-vector product) / `sample_iters` (the run
@@ -156,6 +157,17 @@ def cpu_baseline(gpu_fp64_iterations: int, sample_iters: int = 5):
     out["small_96x72x20_full_solve"] = {"seconds": round(time.perf_counter() - t0, 3), "iterations": i1.iterations,
                                         "true_rel_residual": i1.true_rel_residual}
     del c1, b1
+    # 640x480x70: a full solve with the OpenMP build of the same oracle source (fixed-partition
+    # sums, so the same result for any thread count); one thread would take minutes
+    p2 = synth.CONFIGS["manufactured_640x480x70"]
+    c2 = synth.make_coeffs(p2, threads=16)
+    b2 = synth.make_rhs(p2).ravel()
+    t0 = time.perf_counter()
+    _, i2 = oracle.bicgstab(c2, b2, tol=1e-8, parallel=True)
+    out["c2_640x480x70_full_solve_openmp"] = {"seconds": round(time.perf_counter() - t0, 2), "iterations": i2.iterations,
+                                              "true_rel_residual": i2.true_rel_residual,
+                                              "threads": int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count())}
+    del c2, b2
     it2, _, _ = per_iteration(synth.CONFIGS["manufactured_640x480x70"], 16)
     out["context_640x480x70_seconds_per_iteration"] = round(it2, 3)
     it3, t_run, nits = per_iteration(synth.CONFIGS["n1280_2560x1920x70"], 8)
