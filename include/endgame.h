@@ -137,7 +137,7 @@ int eg_set_stream(eg_operator *op, void *hip_stream);
 
 /*
  * Solver options (defaults in brackets):
- *   "eta"            inner relative tolerance of the FP32 refinement solves [1e-4]
+ *   "eta"            inner relative tolerance of the FP32 refinement solves [1e-2]
  *                    (Sec. 3, Eq. 10: keep the 32-bit target well above eps_32)
  *   "restart_every"  mandatory restart period in iterations, 0 = off [0]
  *                    (Sec. 4 uses 150 operationally)

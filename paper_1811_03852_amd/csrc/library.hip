@@ -157,7 +157,7 @@ struct eg_operator {
     double *d_hist = nullptr;
     int hist_cap = 0;
 
-    double eta = 1e-4;
+    double eta = 1e-2;          // inner relative tolerance of one refinement step
     int restart_every = 0;
     int max_outer = 30;
     int inner_maxit = 1000;     // iterations of one inner FP32 solve of the refinement

@@ -1456,7 +1456,8 @@ __global__ __launch_bounds__(64 * kFuWaves) __attribute__((amdgpu_waves_per_eu(2
             for (int s = 0; s < 2; ++s) vw[s][(PH + 4) % 5] = zero8();
         }
         // ---- the 3x3 layer at level st for this wave's two tiles ----
-        if (st < nlev) {
+        auto conv3 = [&]() {
+            if (st >= nlev) return;
             const uint4 *pl = &a1s[buf][0];
             const f32x4 b20 = bias_s[1][0][grp], b21 = bias_s[1][1][grp];
             f32x4 acc[2][2] = {{b20, b21}, {b20, b21}};
@@ -1482,10 +1483,11 @@ __global__ __launch_bounds__(64 * kFuWaves) __attribute__((amdgpu_waves_per_eu(2
 #pragma unroll
                 for (int nt = 0; nt < 2; ++nt)
                     tw[((s * 4 + 2 * nt + (grp >> 1)) * 16 + m) * 2 + (grp & 1)] = relu_pack4(acc[s][nt]);
-        }
+        };
         // ---- layer 3 at level kk = st - 3 (a2 of levels st - 5 .. st - 1), output of level k ----
-        const int kk = st - 3;
-        if (kk >= 0 && kk < nlev) {
+        auto layer3 = [&]() {
+            const int kk = st - 3;
+            if (kk < 0 || kk >= nlev) return;
 #pragma unroll
             for (int s = 0; s < 2; ++s) {
                 f32x4 acc[2] = {bias_s[2][0][grp], bias_s[2][1][grp]};
@@ -1502,6 +1504,16 @@ __global__ __launch_bounds__(64 * kFuWaves) __attribute__((amdgpu_waves_per_eu(2
 #pragma unroll
                 for (int d = 0; d < 5; ++d) racc[s][(PH + d) % 5] += stp[4 - d];
             }
+        };
+        // the two are independent within a step; the two waves of a SIMD (w and w + 4) take
+        // them in opposite order, so one streams LDS operands while the other multiplies
+        // register operands
+        if (wv < 4) {
+            conv3();
+            layer3();
+        } else {
+            layer3();
+            conv3();
         }
 #pragma unroll
         for (int s = 0; s < 2; ++s) {
