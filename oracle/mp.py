@@ -40,10 +40,12 @@ class MpInfo:
 
 def bicgstab_mp(coef: np.ndarray, b: np.ndarray, tol: float = 1e-4, maxit: int = 5000, restart_every: int = 150,
                 precond: str = "tri", sor_sweeps: int = 3, sor_omega: float = 1.5, vec_dtype=np.float32,
-                x_dtype=np.float64):
+                x_dtype=np.float64, trace=None):
     """Solve A x = b from x = 0; returns (x (float64), MpInfo).  ``x_dtype=np.float32`` rounds
     the solution to float32 after every update as well: the all-32-bit solver of the paper's
-    toy-model comparison (Sec. 4, Fig. 1; pass restart_every=0 for no periodic restarts)."""
+    toy-model comparison (Sec. 4, Fig. 1; pass restart_every=0 for no periodic restarts).
+    ``trace(it, state)``, if given, sees the iteration's vectors (r, rh, p, ph, v, s, sh, t, x)
+    after every full iteration."""
     vd = np.dtype(vec_dtype)
     xd = np.dtype(x_dtype)
 
@@ -143,6 +145,8 @@ def bicgstab_mp(coef: np.ndarray, b: np.ndarray, tol: float = 1e-4, maxit: int =
             rho_prev = rho
             rnorm = nrm(r)
             hist.append(rnorm / nb)
+            if trace is not None:
+                trace(it, dict(r=r, rh=rh, p=p, ph=ph, v=v, s=s, sh=sh, t=t, x=x))
             if rnorm / nb <= tol:
                 status = 0
         if status == 0:                                    # check the 64-bit true residual

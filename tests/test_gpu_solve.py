@@ -306,8 +306,10 @@ def test_paper_mixed_precision_mode(eg, oracle_mod, small, tol):
 def test_paper_mixed_precision_matches_the_mp_oracle(eg, oracle_mod, small, precond, tol):
     """EG_FP32_MP against the CPU emulation of the paper's mixed-precision BiCGStab (FP32
     vectors, FP64 x and sums, restart every 150; oracle/mp.py): the first residual-history
-    entries agree to FP32 rounding, the iteration counts within 10 % (both sides round
-    differently, and BiCGStab amplifies it), and both true residuals are below tol."""
+    entries agree to FP32 rounding (eight with T^-1 within 2e-5, measured 5e-6; four with the
+    line SOR within 5e-5, measured 9e-6; later entries part as BiCGStab amplifies the two
+    sides' different rounding orders), the iteration counts within 10 %, and both true
+    residuals are below tol."""
     import torch
     from oracle import mp
     p, coef, b, x_ref, _ = small
@@ -323,8 +325,8 @@ def test_paper_mixed_precision_matches_the_mp_oracle(eg, oracle_mod, small, prec
     assert info.status == eg.CONVERGED and ref.status == 0
     assert _true_rel(oracle_mod, coef, b, xh) <= tol and ref.true_rel_residual <= tol
     assert abs(info.iterations - ref.iterations) <= max(2, ref.iterations // 10)
-    k = min(4, len(h), len(ref.history))
-    assert np.allclose(h[:k], ref.history[:k], rtol=1e-4, atol=0)
+    k = min(4 if precond else 8, len(h), len(ref.history))
+    assert np.allclose(h[:k], ref.history[:k], rtol=5e-5 if precond else 2e-5, atol=0)
     assert np.linalg.norm(xh - xo) <= 1e4 * tol * np.linalg.norm(xo)
 
 

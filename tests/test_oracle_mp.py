@@ -83,3 +83,24 @@ def test_32_bit_solution_follows_the_64_bit_one_early():
     k = min(len(i32.history), len(i64.history), 4)
     d = np.abs(i32.history[:k] - i64.history[:k]) / i64.history[:k]
     assert np.all(d < 1e-4)
+
+
+@pytest.mark.parametrize("precond", ["tri", "sor"])
+def test_every_32_bit_vector_is_rounded_and_x_is_not(precond):
+    """Sec. 4's split, checked on the emulation's state after every iteration: each of r, r^, p,
+    p^ = M p, v = A p^, s, s^ = M s and t = A s^ holds float32 values only (a rounding dropped
+    anywhere leaves float64 values in that vector), while the 64-bit solution x does not."""
+    p, coef, b = _problem(seed=7)
+    names = ("r", "rh", "p", "ph", "v", "s", "sh", "t")
+    seen = []
+
+    def check(it, st):
+        for name in names:
+            v = np.asarray(st[name], dtype=np.float64)
+            assert np.array_equal(v, v.astype(np.float32).astype(np.float64)), (it, name)
+        x = np.asarray(st["x"], dtype=np.float64)
+        seen.append(not np.array_equal(x, x.astype(np.float32).astype(np.float64)))
+
+    _, info = mp.bicgstab_mp(coef, b, tol=1e-6, precond=precond, trace=check)
+    assert info.status == 0 and len(seen) >= 5
+    assert all(seen)
