@@ -145,6 +145,13 @@ int eg_set_stream(eg_operator *op, void *hip_stream);
  *   "inner_maxit"    limit on the iterations of one inner FP32 solve [1000]; the correction of
  *                    a capped inner solve is kept only if it lowers the FP64 true residual
  *   "poll"           iterations enqueued between host checks of the device flags [8]
+ *   "graph"          1 = the BiCGStab iterations between two host checks are captured once
+ *                    (per precision, preconditioner and work buffers) as a HIP graph and
+ *                    replayed: one launch call per batch instead of ten per iteration, for
+ *                    grids small enough to be bound by launch overhead.  The graphs live on
+ *                    a private stream created on first use and are freed by
+ *                    eg_destroy_operator; 0 = launch every kernel (also whenever "profile"
+ *                    is 1) [1]
  *   "eps_bd"         BiCGStab breakdown threshold, 0 <= eps_bd < 1 [2^-52]: the iteration
  *                    restarts (rhat = p = r) when |<rhat, r>| <= eps_bd ||rhat|| ||r|| or
  *                    |<rhat, v>| <= eps_bd ||rhat|| ||v|| (Sec. 4: near-zero scalar weights)

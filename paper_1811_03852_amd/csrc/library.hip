@@ -135,6 +135,19 @@ struct eg_net {
     int loss_kind = 1;          // 0: ||M(r) - e||^2 / ||e||^2,  1: ||A M(r) - r||^2 / ||r||^2
 };
 
+// A batch of plain iterations captured as a HIP graph, with everything its kernels were
+// launched with: the same key means the same launches, so the graph can be replayed.
+struct IterKey {
+    const void *a, *m, *qs, *tri, *sor_ws, *sorf, *sora, *mp_x, *partials, *sc, *hist;
+    const void *w[9];
+    int tv, tc, sor_on, sweeps, mp_active, mp_x32, batch;
+    double omega;
+};
+struct IterGraph {
+    IterKey key;
+    hipGraphExec_t exec;
+};
+
 struct eg_operator {
     int nlon = 0, nlat = 0, nlev = 0;
     long P = 0, n = 0;
@@ -180,6 +193,9 @@ struct eg_operator {
     float *sorf32 = nullptr, *sora32 = nullptr;
     uint16_t *sorq[2] = {nullptr, nullptr};
     int profile = 0;
+    int use_graph = 1;          // replay the batched iteration as a HIP graph (option graph)
+    hipStream_t cap_stream = nullptr;   // private stream the graphs are captured on
+    std::vector<IterGraph> graphs;      // instantiated iteration batches, newest last
 
     // kernel timing: events around the streaming kernels of one iteration + the residual
     hipEvent_t ev[16] = {};
@@ -428,6 +444,72 @@ void enqueue_iteration(eg_operator *op, const OpView<Tc> &A, Work<Tv> &w, hipEve
     launch_finalize(FIN_END, op->partials, nr, op->sc, op->d_hist, nullptr, 0, 0, s);
 }
 
+// `batch` plain iterations as one HIP graph: found among the operator's graphs by what its
+// launches read, else captured on the private stream and instantiated.  The iteration is
+// kernel launches only (no memset or copy nodes), and every kernel takes its per-iteration
+// decisions from the device scalar block, so a replay does what eager launches would.
+template <typename Tv, typename Tc>
+int iteration_graph(eg_operator *op, const OpView<Tc> &A, Work<Tv> &w, int batch, hipGraphExec_t *out)
+{
+    IterKey key;
+    std::memset(&key, 0, sizeof key);
+    key.a = A.a;
+    key.m = A.m;
+    key.qs = A.qs;
+    key.tri = op->tri_view<Tv>().f;
+    key.sor_on = op->sor_on;
+    if (op->sor_on) {
+        const SorView<Tv, Tc> sv = op->sor_view<Tv, Tc>();
+        key.sor_ws = op->sor_ws;
+        key.sorf = sv.f;
+        key.sora = sv.a;
+        key.sweeps = op->sor_sweeps;
+        key.omega = op->sor_omega;
+    }
+    key.mp_active = op->mp_active;
+    key.mp_x32 = op->mp_x32;
+    key.mp_x = op->mp_active ? op->mp_x : nullptr;
+    key.partials = op->partials;
+    key.sc = op->sc;
+    key.hist = op->d_hist;
+    const void *wv[9] = {w.r, w.rh, w.p, w.ph, w.v, w.s, w.sh, w.t, w.x};
+    for (int i = 0; i < 9; ++i) key.w[i] = wv[i];
+    key.tv = sizeof(Tv);
+    key.tc = prec_of<Tc>();
+    key.batch = batch;
+    for (const IterGraph &g : op->graphs)
+        if (std::memcmp(&g.key, &key, sizeof key) == 0) {
+            *out = g.exec;
+            return 0;
+        }
+    if (!op->cap_stream) EG_HIP(hipStreamCreateWithFlags(&op->cap_stream, hipStreamNonBlocking));
+    EG_HIP(hipGetLastError());
+    EG_HIP(hipStreamBeginCapture(op->cap_stream, hipStreamCaptureModeThreadLocal));
+    const hipStream_t user = op->stream;
+    op->stream = op->cap_stream;
+    for (int b = 0; b < batch; ++b) enqueue_iteration<Tv, Tc>(op, A, w, nullptr);
+    op->stream = user;
+    hipGraph_t graph = nullptr;
+    const hipError_t launched = hipGetLastError();
+    const hipError_t ended = hipStreamEndCapture(op->cap_stream, &graph);
+    if (launched != hipSuccess || ended != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return fail(EG_EHIP, std::string("capture of the iteration failed: ") +
+                                 hipGetErrorString(launched != hipSuccess ? launched : ended));
+    }
+    hipGraphExec_t exec = nullptr;
+    const hipError_t inst = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (inst != hipSuccess) return fail(EG_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(inst));
+    if (op->graphs.size() >= 8) {   // a few modes per operator; drop the oldest
+        (void)hipGraphExecDestroy(op->graphs.front().exec);
+        op->graphs.erase(op->graphs.begin());
+    }
+    op->graphs.push_back({key, exec});
+    *out = exec;
+    return 0;
+}
+
 // Run Krylov iterations until the device says done.  Precondition: FIN_INIT (or FIN_TRUE) has
 // been enqueued for this run; w.r holds the residual and w.x the iterate.
 template <typename Tv, typename Tc> int krylov_run(eg_operator *op, const OpView<Tc> &A, Work<Tv> &w)
@@ -454,6 +536,15 @@ template <typename Tv, typename Tc> int krylov_run(eg_operator *op, const OpView
         return 0;
     }
     int batch = std::max(1, op->poll);
+    if (op->use_graph) {
+        hipGraphExec_t exec = nullptr;
+        if ((rc = iteration_graph<Tv, Tc>(op, A, w, batch, &exec))) return rc;
+        while (!op->h_sc->done) {
+            EG_HIP(hipGraphLaunch(exec, op->stream));
+            if ((rc = sync_scalars(op))) return rc;
+        }
+        return 0;
+    }
     while (!op->h_sc->done) {
         for (int b = 0; b < batch; ++b) enqueue_iteration<Tv, Tc>(op, A, w, nullptr);
         EG_HIP(hipGetLastError());
@@ -1250,6 +1341,8 @@ void eg_destroy_operator(eg_operator *op)
     }
     if (op->ev_ready)
         for (hipEvent_t e : op->ev) (void)hipEventDestroy(e);
+    for (const IterGraph &g : op->graphs) (void)hipGraphExecDestroy(g.exec);
+    if (op->cap_stream) (void)hipStreamDestroy(op->cap_stream);
     dfree(op->partials); dfree(op->sc); dfree(op->d_out); dfree(op->d_bad); dfree(op->d_hist);
     if (op->h_sc) (void)hipHostFree(op->h_sc);
     if (op->h_out) (void)hipHostFree(op->h_out);
@@ -1347,6 +1440,9 @@ int eg_set_option(eg_operator *op, const char *key, double value)
         op->gm_m = (int)value;
     } else if (k == "profile") {
         op->profile = value != 0.0;
+    } else if (k == "graph") {
+        if (value != 0.0 && value != 1.0) return fail(EG_EINVAL, "graph must be 0 or 1");
+        op->use_graph = (int)value;
     } else if (k == "eps_bd") {
         if (!(value >= 0.0 && value < 1.0)) return fail(EG_EINVAL, "eps_bd must be in [0, 1)");
         op->eps_bd = value;
