@@ -1130,8 +1130,19 @@ __global__ __launch_bounds__(kWG) void k_msum(const double *__restrict__ part, i
     __shared__ double sm[kWG];
     const int c = threadIdx.x % kMBlk, g = threadIdx.x / kMBlk;
     double s = 0.0;
-    if (c < ncols)
-        for (int r = g; r < rows; r += kGroups) s += part[(long)r * kMBlk + c];
+    if (c < ncols) {
+        // rows g, g + kGroups, ... added in that order, loaded eight at a time ahead
+        constexpr int U = 8;
+        int r = g;
+        for (; r + (U - 1) * kGroups < rows; r += U * kGroups) {
+            double v[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) v[u] = part[(long)(r + u * kGroups) * kMBlk + c];
+#pragma unroll
+            for (int u = 0; u < U; ++u) s += v[u];
+        }
+        for (; r < rows; r += kGroups) s += part[(long)r * kMBlk + c];
+    }
     sm[threadIdx.x] = s;
     __syncthreads();
     if (threadIdx.x < ncols) {
@@ -1187,7 +1198,23 @@ __global__ __launch_bounds__(kWG) void k_finalize(int stage, const double *__res
     double a[kPartialCols];
 #pragma unroll
     for (int c = 0; c < kPartialCols; ++c) a[c] = 0.0;
-    for (int r = threadIdx.x; r < nrows; r += kWG)
+    // thread t adds rows t, t + kWG, t + 2 kWG, ... in that order; the rows are loaded eight
+    // at a time ahead of the additions (up to 32,768 rows: one load chain per row would leave
+    // the single workgroup waiting on memory latency)
+    constexpr int U = 8;
+    int r = threadIdx.x;
+    for (; r + (U - 1) * kWG < nrows; r += U * kWG) {
+        double v[U][kPartialCols];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int c = 0; c < kPartialCols; ++c) v[u][c] = partials[(long)(r + u * kWG) * kPartialCols + c];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int c = 0; c < kPartialCols; ++c) a[c] += v[u][c];
+    }
+    for (; r < nrows; r += kWG)
 #pragma unroll
         for (int c = 0; c < kPartialCols; ++c) a[c] += partials[(long)r * kPartialCols + c];
     __shared__ double tot[kPartialCols];
