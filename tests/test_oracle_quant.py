@@ -59,7 +59,8 @@ def test_quantized_operator(kind, rel):
     """Scales are powers of two with the row maximum in (1/2, 1] after scaling; each coupling
     is within half a unit in its last place (the unit roundoff 2^-8 for BF16 and 2^-11 for FP16,
     relative; these magnitudes are far from underflow); zero couplings stay zero; the rebuilt
-    operator's row sums are the FP32 margin."""
+    operator's row sums are the FP32 margin, and its diagonal differs from C by no more than
+    the FP32 rounding of the true margin plus the couplings' roundings."""
     p = synth.Problem(40, 30, 12, seed=3)
     coef = synth.make_coeffs(p)
     s = quant.scales(coef)
@@ -74,3 +75,6 @@ def test_quantized_operator(kind, rel):
     m32 = quant.margin(coef).astype(np.float32).astype(np.float64)
     rows = cq[6] - aq.sum(axis=0)
     assert np.allclose(rows, m32, rtol=0, atol=1e-15 * np.abs(cq[6]).max())
+    m_true = coef[6] - coef[:6].sum(axis=0)
+    bound = 2.0 ** -24 * np.abs(m_true) + np.abs(aq - a).sum(axis=0) + 1e-14 * np.abs(coef[6])
+    assert np.all(np.abs(cq[6] - coef[6]) <= bound)
