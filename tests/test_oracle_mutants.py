@@ -228,6 +228,7 @@ def test_python_pins_pass_on_the_real_modules(tag):
     assert total > 0 and failed == []
 
 
+@pytest.mark.filterwarnings("ignore::RuntimeWarning")   # a mutant may produce NaN on purpose
 @pytest.mark.parametrize("idx", range(len(PY_MUTANTS)), ids=[m[3] for m in PY_MUTANTS])
 def test_python_planted_mistake_fails_a_pin(idx):
     modname, pinname, attr, label, subs = PY_MUTANTS[idx]
