@@ -105,3 +105,13 @@ def test_graph_cuts_launch_overhead_on_a_small_grid(eg, small):
     print(f"96x72x20 FP64: launches {times[0][0] * 1e3:.2f} ms, graph {times[1][0] * 1e3:.2f} ms "
           f"({times[1][1]} iterations, {times[1][0] / times[1][1] * 1e6:.1f} us per iteration)")
     assert times[0][1] == times[1][1]
+
+
+def test_graph_option_is_checked(eg, small):
+    p, coef, _ = small
+    with eg.Operator(dev(coef)) as op:
+        for bad in (2, 0.5, -1):
+            with pytest.raises(eg.EndgameError):
+                op.set_option("graph", bad)
+        op.set_option("graph", 0)
+        op.set_option("graph", 1)
