@@ -49,7 +49,9 @@ enum eg_mode {
                             /* undone, and so is the refinement when it stagnates: the solve     */
                             /* then continues from x with the EG_FP64 solver (info.fallbacks).   */
     EG_FP32_IR_BF16 = 2,    /* as EG_FP32_IR, inner off-diagonal couplings stored as BF16        */
-    EG_FP32_IR_FP16 = 3,    /* as EG_FP32_IR, inner off-diagonal couplings stored as FP16        */
+                            /* remainders: coupling = offset + q * scale, one offset and one     */
+                            /* power-of-two scale per direction, level and latitude row          */
+    EG_FP32_IR_FP16 = 3,    /* as EG_FP32_IR_BF16 with FP16 remainders                           */
     EG_LEARNED_FP64 = 4,    /* flexible BiCGStab in FP64 with the learned preconditioner         */
     EG_LEARNED_FP32_IR = 5, /* FP64 refinement around flexible FP32 BiCGStab + learned precond.  */
     EG_FP32_MP = 6          /* the paper's mixed-precision BiCGStab (Sec. 3-4): FP32 vectors and

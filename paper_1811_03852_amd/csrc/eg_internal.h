@@ -63,13 +63,16 @@ struct fp16_t { uint16_t bits; };
 template <> struct CoefTraits<bf16_t> { using val = float; static constexpr bool quant = true; };
 template <> struct CoefTraits<fp16_t> { using val = float; static constexpr bool quant = true; };
 
-constexpr int kQsStride = 8;   // floats per (level, latitude row) record of 16-bit scales
+// floats per (level, latitude row) record of a 16-bit coefficient set: the six directions'
+// power-of-two scales at 0..5 and their offsets at 8..13 (a coupling is offset + q * scale)
+constexpr int kQsStride = 16;
+constexpr int kQsOff = 8;
 
 template <typename Tc> struct OpView {
     using V = typename CoefTraits<Tc>::val;
     const Tc *a;        // [6][n]
     const V *m;         // [n]
-    const float *qs;    // [nlev][nlat][kQsStride] power-of-two scales (16-bit sets only)
+    const float *qs;    // [nlev][nlat][kQsStride] scales and offsets (16-bit sets only)
     int nlon, nlat, nlev;
     long P, n;
 };

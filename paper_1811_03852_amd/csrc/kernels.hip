@@ -29,20 +29,6 @@ namespace eg {
 __device__ __forceinline__ float bf16_to_f(uint16_t b) { return __uint_as_float(static_cast<uint32_t>(b) << 16); }
 __device__ __forceinline__ float fp16_to_f(uint16_t b) { return static_cast<float>(__builtin_bit_cast(_Float16, b)); }
 
-template <typename Tc> struct Dec;
-template <> struct Dec<double> {
-    __device__ static __forceinline__ double get(const double *a, long i, float) { return a[i]; }
-};
-template <> struct Dec<float> {
-    __device__ static __forceinline__ float get(const float *a, long i, float) { return a[i]; }
-};
-template <> struct Dec<bf16_t> {
-    __device__ static __forceinline__ float get(const bf16_t *a, long i, float s) { return bf16_to_f(a[i].bits) * s; }
-};
-template <> struct Dec<fp16_t> {
-    __device__ static __forceinline__ float get(const fp16_t *a, long i, float s) { return fp16_to_f(a[i].bits) * s; }
-};
-
 __device__ __forceinline__ bool stopped(const Scalars *sc, int mask)
 {
     if (!sc || !mask) return false;
@@ -131,23 +117,29 @@ template <typename T> __device__ __forceinline__ void stn(T *base, uint32_t boff
     __builtin_nontemporal_store(v, reinterpret_cast<T *>(reinterpret_cast<char *>(base) + boff));
 }
 
+// A coupling of row i: FP64 and FP32 sets hold it; a 16-bit set holds q with
+// coupling = offset + q * scale (one offset and one power-of-two scale per direction, level and
+// latitude row), rounded once to FP32 (q * scale is exact, so the fma rounds only the sum).
 template <typename Tc> struct DecB;
 template <> struct DecB<double> {
-    __device__ static __forceinline__ double get(const double *row, uint32_t i, float) { return ldn(row, i * 8u); }
+    __device__ static __forceinline__ double get(const double *row, uint32_t i, float, float)
+    {
+        return ldn(row, i * 8u);
+    }
 };
 template <> struct DecB<float> {
-    __device__ static __forceinline__ float get(const float *row, uint32_t i, float) { return ldn(row, i * 4u); }
+    __device__ static __forceinline__ float get(const float *row, uint32_t i, float, float) { return ldn(row, i * 4u); }
 };
 template <> struct DecB<bf16_t> {
-    __device__ static __forceinline__ float get(const bf16_t *row, uint32_t i, float s)
+    __device__ static __forceinline__ float get(const bf16_t *row, uint32_t i, float s, float off)
     {
-        return bf16_to_f(ldn(reinterpret_cast<const uint16_t *>(row), i * 2u)) * s;
+        return __builtin_fmaf(bf16_to_f(ldn(reinterpret_cast<const uint16_t *>(row), i * 2u)), s, off);
     }
 };
 template <> struct DecB<fp16_t> {
-    __device__ static __forceinline__ float get(const fp16_t *row, uint32_t i, float s)
+    __device__ static __forceinline__ float get(const fp16_t *row, uint32_t i, float s, float off)
     {
-        return fp16_to_f(ldn(reinterpret_cast<const uint16_t *>(row), i * 2u)) * s;
+        return __builtin_fmaf(fp16_to_f(ldn(reinterpret_cast<const uint16_t *>(row), i * 2u)), s, off);
     }
 };
 
@@ -223,24 +215,31 @@ __global__ __launch_bounds__(kWG) void k_spmv(OpView<Tc> op, const Tv *__restric
                 const Tv xs = (r == 0) ? hs : xc[r - 1];
                 const Tv xnn = (r == R - 1) ? hn : xc[r + 1];
                 float s0 = 1.f, s1 = 1.f, s2 = 1.f, s3 = 1.f, s4 = 1.f, s5 = 1.f;
+                float f0 = 0.f, f1 = 0.f, f2 = 0.f, f3 = 0.f, f4 = 0.f, f5 = 0.f;
                 if constexpr (Q) {
-                    // the row's six scales: one wave-uniform 32-byte record
+                    // the row's six scales and six offsets: one wave-uniform 64-byte record
                     const float4 *qr = reinterpret_cast<const float4 *>(op.qs + ((size_t)k * nlat + jc[r]) * kQsStride);
-                    const float4 q0 = qr[0], q1 = qr[1];
+                    const float4 q0 = qr[0], q1 = qr[1], o0 = qr[2], o1 = qr[3];
                     s0 = q0.x;
                     s1 = q0.y;
                     s2 = q0.z;
                     s3 = q0.w;
                     s4 = q1.x;
                     s5 = q1.y;
+                    f0 = o0.x;
+                    f1 = o0.y;
+                    f2 = o0.z;
+                    f3 = o0.w;
+                    f4 = o1.x;
+                    f5 = o1.y;
                 }
                 const Tc *arow = op.a + rowoff;
-                const V aW = DecB<Tc>::get(arow, ic, s0);
-                const V aE = DecB<Tc>::get(arow + n, ic, s1);
-                const V aS = DecB<Tc>::get(arow + 2 * n, ic, s2);
-                const V aN = DecB<Tc>::get(arow + 3 * n, ic, s3);
-                const V aD = DecB<Tc>::get(arow + 4 * n, ic, s4);
-                const V aU = DecB<Tc>::get(arow + 5 * n, ic, s5);
+                const V aW = DecB<Tc>::get(arow, ic, s0, f0);
+                const V aE = DecB<Tc>::get(arow + n, ic, s1, f1);
+                const V aS = DecB<Tc>::get(arow + 2 * n, ic, s2, f2);
+                const V aN = DecB<Tc>::get(arow + 3 * n, ic, s3, f3);
+                const V aD = DecB<Tc>::get(arow + 4 * n, ic, s4, f4);
+                const V aU = DecB<Tc>::get(arow + 5 * n, ic, s5, f5);
                 const V mm = ldn(op.m + rowoff, ic * (uint32_t)sizeof(V));
                 Tv yv = mm * xr;
                 yv += aW * (xr - xw);
@@ -1542,21 +1541,23 @@ void launch_to_fp32(long n, const double *a64, const double *m64, float *a32, fl
     hipLaunchKernelGGL(k_to_fp32, dim3(elementwise_blocks(n)), dim3(kWG), 0, s, n, a64, m64, a32, m32);
 }
 
-// Round a non-negative double to p significant bits, ties to even, with exponents below emin
-// held at emin (gradual underflow).  Every step is exact except the single rint.
+// Round a double to p significant bits, ties to even, with exponents below emin held at emin
+// (gradual underflow); the sign is kept.  Every step is exact except the single rint.
 __device__ double round_sig(double u, int p, int emin)
 {
     if (u == 0.0) return 0.0;
     int e;
-    (void)frexp(u, &e);         // u = f 2^e, f in [1/2, 1): leading bit has weight 2^(e-1)
+    (void)frexp(u, &e);         // |u| = f 2^e, f in [1/2, 1): leading bit has weight 2^(e-1)
     int lead = e - 1;
     if (lead < emin) lead = emin;
     const double ulp = ldexp(1.0, lead - (p - 1));
     return rint(u / ulp) * ulp;
 }
 
-// One wave per (direction, level, latitude row): power-of-two scale 2^ceil(log2 max a), stored
-// at qs[(k * nlat + j) * 8 + d] so that one row's six scales are one 32-byte record.
+// One wave per (direction, level, latitude row).  Offset: the FP32 rounding of the midpoint of
+// the row's smallest and largest coupling when every coupling of the row is positive, else 0
+// (so zero couplings stay zero); scale: the power of two 2^ceil(log2 max |a - offset|).  Stored
+// at qs[(k * nlat + j) * kQsStride + d] and + kQsOff + d, so one row's record is one 64-byte line.
 __global__ __launch_bounds__(64) void k_qscale(int nlon, int nlat, int nlev, const double *__restrict__ a64,
                                                float *__restrict__ qs)
 {
@@ -1565,8 +1566,18 @@ __global__ __launch_bounds__(64) void k_qscale(int nlon, int nlat, int nlev, con
     const long kj = row % ((long)nlev * nlat);
     const long n = (long)nlon * nlat * nlev;
     const double *src = a64 + (long)d * n + kj * nlon;
+    double lo = INFINITY, hi = 0.0;
+    for (int i = threadIdx.x; i < nlon; i += 64) {
+        lo = fmin(lo, src[i]);
+        hi = fmax(hi, src[i]);
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        lo = fmin(lo, __shfl_xor(lo, off));
+        hi = fmax(hi, __shfl_xor(hi, off));
+    }
+    const float offv = (lo > 0.0) ? static_cast<float>(0.5 * (lo + hi)) : 0.f;
     double mx = 0.0;
-    for (int i = threadIdx.x; i < nlon; i += 64) mx = fmax(mx, src[i]);
+    for (int i = threadIdx.x; i < nlon; i += 64) mx = fmax(mx, fabs(src[i] - static_cast<double>(offv)));
     for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off));
     if (threadIdx.x == 0) {
         float s = 1.f;
@@ -1576,12 +1587,16 @@ __global__ __launch_bounds__(64) void k_qscale(int nlon, int nlat, int nlev, con
             s = ldexpf(1.f, (f == 0.5) ? e - 1 : e);
         }
         qs[kj * kQsStride + d] = s;
+        qs[kj * kQsStride + kQsOff + d] = offv;
         if (d == 0)
-            for (int pad = 6; pad < kQsStride; ++pad) qs[kj * kQsStride + pad] = 1.f;
+            for (int pad = 6; pad < kQsOff; ++pad) {
+                qs[kj * kQsStride + pad] = 1.f;
+                qs[kj * kQsStride + kQsOff + pad] = 0.f;
+            }
     }
 }
 
-// a_q = RNE(a / scale) in BF16 (kind 2) or FP16 (kind 3)
+// q = RNE((a - offset) / scale) in BF16 (kind 2) or FP16 (kind 3)
 __global__ __launch_bounds__(kWG) void k_quantize(int kind, int nlon, int nlat, int nlev,
                                                   const double *__restrict__ a64, const float *__restrict__ qs,
                                                   uint16_t *__restrict__ aq)
@@ -1594,7 +1609,8 @@ __global__ __launch_bounds__(kWG) void k_quantize(int kind, int nlon, int nlat, 
 #pragma unroll
         for (int d = 0; d < 6; ++d) {
             const double s = qs[kj * kQsStride + d];
-            const double u = a64[d * n + c] / s;
+            const double off = qs[kj * kQsStride + kQsOff + d];
+            const double u = (a64[d * n + c] - off) / s;
             uint16_t bits;
             if (kind == PBF16) {
                 const double r = round_sig(u, 8, -126);
@@ -1697,19 +1713,23 @@ __global__ __launch_bounds__(kSorWG) void k_sor_half(OpView<Tc> op, SorView<Tv, 
     for (int k = 0; k < nlev; ++k) {
         const long pi = own + (long)k * P2;
         const Tv *ok = oth + (long)k * P2;
-        float s0 = 1.f, s1 = 1.f, s2 = 1.f, s3 = 1.f;
+        float s0 = 1.f, s1 = 1.f, s2 = 1.f, s3 = 1.f, f0 = 0.f, f1 = 0.f, f2 = 0.f, f3 = 0.f;
         if constexpr (Q) {
             const float *qr = op.qs + ((size_t)k * nlat + j) * kQsStride;
             s0 = qr[0];
             s1 = qr[1];
             s2 = qr[2];
             s3 = qr[3];
+            f0 = qr[kQsOff];
+            f1 = qr[kQsOff + 1];
+            f2 = qr[kQsOff + 2];
+            f3 = qr[kQsOff + 3];
         }
-        const V aW = DecB<Tc>::get(aWp + pi, 0, s0);
-        const V aE = DecB<Tc>::get(aEp + pi, 0, s1);
+        const V aW = DecB<Tc>::get(aWp + pi, 0, s0, f0);
+        const V aE = DecB<Tc>::get(aEp + pi, 0, s1, f1);
         Tv h = aW * ok[cw] + aE * ok[ce];
-        if (hs) h += static_cast<Tv>(DecB<Tc>::get(aSp + pi, 0, s2)) * ok[c2 - half];
-        if (hn) h += static_cast<Tv>(DecB<Tc>::get(aNp + pi, 0, s3)) * ok[c2 + half];
+        if (hs) h += static_cast<Tv>(DecB<Tc>::get(aSp + pi, 0, s2, f2)) * ok[c2 - half];
+        if (hn) h += static_cast<Tv>(DecB<Tc>::get(aNp + pi, 0, s3, f3)) * ok[c2 + half];
         const Tv rhs = __builtin_nontemporal_load(qcm + pi) + nb_scale * h;
         const Tv w = rhs + __builtin_nontemporal_load(lf + pi) * wprev;
         __builtin_nontemporal_store(w, wsc + c2 + (long)k * P2);
@@ -1781,18 +1801,24 @@ __device__ __forceinline__ void sor_half_reg_body(OpView<Tc> op, SorView<Tv, Tc>
         Tv xw[PF], xe[PF], xs[PF], xn[PF], rq[PF], rl[PF];
         auto issue = [&](int kk, int sl) {
             const size_t lo = (size_t)kk * (size_t)P2;
-            float s0 = 1.f, s1 = 1.f, s2 = 1.f, s3 = 1.f;
+            float s0 = 1.f, s1 = 1.f, s2 = 1.f, s3 = 1.f, f0 = 0.f, f1 = 0.f, f2 = 0.f, f3 = 0.f;
             if constexpr (Q) {
-                const float4 sq = *reinterpret_cast<const float4 *>(op.qs + ((size_t)kk * nlat + j) * kQsStride);
+                const float *rec = op.qs + ((size_t)kk * nlat + j) * kQsStride;
+                const float4 sq = *reinterpret_cast<const float4 *>(rec);
+                const float4 oq = *reinterpret_cast<const float4 *>(rec + kQsOff);
                 s0 = sq.x;
                 s1 = sq.y;
                 s2 = sq.z;
                 s3 = sq.w;
+                f0 = oq.x;
+                f1 = oq.y;
+                f2 = oq.z;
+                f3 = oq.w;
             }
-            rw[sl] = DecB<Tc>::get(aWb + lo, oc, s0);
-            re[sl] = DecB<Tc>::get(aEb + lo, oc, s1);
-            rs[sl] = DecB<Tc>::get(aSb + lo, oc, s2);
-            rn[sl] = DecB<Tc>::get(aNb + lo, oc, s3);
+            rw[sl] = DecB<Tc>::get(aWb + lo, oc, s0, f0);
+            re[sl] = DecB<Tc>::get(aEb + lo, oc, s1, f1);
+            rs[sl] = DecB<Tc>::get(aSb + lo, oc, s2, f2);
+            rn[sl] = DecB<Tc>::get(aNb + lo, oc, s3, f3);
             xw[sl] = ldb(oth + lo, ow);
             xe[sl] = ldb(oth + lo, oe);
             xs[sl] = ldb(oth + lo, os);

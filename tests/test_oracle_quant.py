@@ -56,22 +56,38 @@ def test_rounding_ties_go_to_even():
 
 @pytest.mark.parametrize("kind,rel", [("bf16", 2.0 ** -8), ("fp16", 2.0 ** -11)])
 def test_quantized_operator(kind, rel):
-    """Scales are powers of two with the row maximum in (1/2, 1] after scaling; each coupling
-    is within half a unit in its last place (the unit roundoff 2^-8 for BF16 and 2^-11 for FP16,
-    relative; these magnitudes are far from underflow); zero couplings stay zero; the rebuilt
-    operator's row sums are the FP32 margin, and its diagonal differs from C by no more than
-    the FP32 rounding of the true margin plus the couplings' roundings."""
+    """Offsets: 0 on rows holding a zero coupling, else an FP32 value no farther than half the
+    row's spread (plus its own rounding) from every coupling of the row; scales are powers of
+    two with the row's largest |a - offset| in (1/2, 1] after scaling; each coupling is within
+    half a unit in the last place of its remainder a - offset (the unit roundoff 2^-8 for BF16
+    and 2^-11 for FP16, relative; these magnitudes are far from underflow) plus the FP32
+    rounding of offset + remainder; zero couplings stay zero; the rebuilt operator's row sums
+    are the FP32 margin, and its diagonal differs from C by no more than the FP32 rounding of
+    the true margin plus the couplings' roundings."""
     p = synth.Problem(40, 30, 12, seed=3)
     coef = synth.make_coeffs(p)
+    a = coef[:6]
+    lo, hi = a.min(axis=3, keepdims=True), a.max(axis=3, keepdims=True)
+    o = quant.offsets(coef)
+    assert np.all(o[lo == 0] == 0) and np.all(o[lo > 0] > 0)
+    assert np.array_equal(o, o.astype(np.float32).astype(np.float64))
+    assert np.all(np.abs(a - o) <= 0.5 * (hi - lo) + 2.0 ** -24 * o)
     s = quant.scales(coef)
     assert np.array_equal(s, np.ldexp(1.0, np.frexp(s)[1] - 1))
-    mx = coef[:6].max(axis=3, keepdims=True)
+    mx = np.abs(a - o).max(axis=3, keepdims=True)
     ratio = mx[mx > 0] / np.broadcast_to(s, mx.shape)[mx > 0]
     assert np.all((ratio > 0.5) & (ratio <= 1.0))
     cq = quant.quantized_coeffs(coef, kind)
-    a, aq = coef[:6], cq[:6]
+    aq = cq[:6]
     assert np.array_equal(aq == 0, a == 0) and np.all(aq >= 0)
-    assert np.all(np.abs(aq - a) <= rel * a)
+    assert np.array_equal(aq, aq.astype(np.float32).astype(np.float64))
+    assert np.all(np.abs(aq - a) <= rel * np.abs(a - o) + 2.0 ** -24 * aq)
+    # the offsets pay: on these operators the coupling error is far below the plain format's
+    assert np.max(np.abs(aq - a) / np.where(a > 0, a, 1.0)) < 0.25 * rel
+    # a zero among positive couplings: its row keeps offset 0, so the zero stays zero
+    c2 = coef.copy()
+    c2[0, 3, 5, 7] = 0.0
+    assert quant.offsets(c2)[0, 3, 5, 0] == 0 and quant.quantized_coeffs(c2, kind)[0, 3, 5, 7] == 0
     m32 = quant.margin(coef).astype(np.float32).astype(np.float64)
     rows = cq[6] - aq.sum(axis=0)
     assert np.allclose(rows, m32, rtol=0, atol=1e-15 * np.abs(cq[6]).max())
