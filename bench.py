@@ -487,7 +487,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="n1280_2560x1920x70")
     ap.add_argument("--modes", default="fp64,fp32_ir,fp32_ir_bf16")
-    ap.add_argument("--extra-modes", default="fp32_ir_fp16,fp64_sor,fp32_ir_sor,fp32_ir_bf16_sor,learned_fp32_ir",
+    ap.add_argument("--extra-modes", default="fp32_ir_fp16,fp64_sor,fp32_ir_sor,fp32_ir_bf16_sor,fp32_ir_fp16_sor,"
+                                             "learned_fp32_ir",
                     help="modes timed once each after the timed steps ('' skips them)")
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
