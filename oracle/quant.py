@@ -6,8 +6,9 @@ project's extension of its mixed-precision idea.  Its definition, written out pl
 
 * each of the six off-diagonal coupling planes (W, E, S, N, D, U) is stored per level and
   latitude row as an offset o plus a scaled remainder: o is the FP32 rounding of the midpoint
-  of the row's smallest and largest coupling when all of them are positive, else 0 (zero
-  couplings stay zero), and the remainder a - o is divided by the power of two
+  of the row's smallest and largest coupling when all of them are positive and the largest is
+  at most twice the smallest, else 0 (zero couplings stay zero, and no coupling's relative
+  error exceeds the plain format's), and the remainder a - o is divided by the power of two
   s = 2^ceil(log2 max |a - o|) of the row, so that every scaled value lies in [-1, 1] and the
   scaling itself is exact;
 * the scaled value is rounded to nearest, ties to even, to 8 significant bits with the
@@ -50,7 +51,7 @@ def offsets(coef: np.ndarray) -> np.ndarray:
     lo = coef[:6].min(axis=3, keepdims=True)
     hi = coef[:6].max(axis=3, keepdims=True)
     mid = (0.5 * (lo + hi)).astype(np.float32).astype(np.float64)
-    return np.where(lo > 0, mid, 0.0)
+    return np.where((lo > 0) & (hi <= 2.0 * lo), mid, 0.0)
 
 
 def scales(coef: np.ndarray) -> np.ndarray:

@@ -1555,9 +1555,11 @@ __device__ double round_sig(double u, int p, int emin)
 }
 
 // One wave per (direction, level, latitude row).  Offset: the FP32 rounding of the midpoint of
-// the row's smallest and largest coupling when every coupling of the row is positive, else 0
-// (so zero couplings stay zero); scale: the power of two 2^ceil(log2 max |a - offset|).  Stored
-// at qs[(k * nlat + j) * kQsStride + d] and + kQsOff + d, so one row's record is one 64-byte line.
+// the row's smallest and largest coupling when every coupling of the row is positive and the
+// largest is at most twice the smallest, else 0 (zero couplings stay zero, and no coupling's
+// relative error exceeds the plain format's); scale: the power of two 2^ceil(log2 max
+// |a - offset|).  Stored at qs[(k * nlat + j) * kQsStride + d] and + kQsOff + d, so one row's
+// record is one 64-byte line.
 __global__ __launch_bounds__(64) void k_qscale(int nlon, int nlat, int nlev, const double *__restrict__ a64,
                                                float *__restrict__ qs)
 {
@@ -1575,7 +1577,7 @@ __global__ __launch_bounds__(64) void k_qscale(int nlon, int nlat, int nlev, con
         lo = fmin(lo, __shfl_xor(lo, off));
         hi = fmax(hi, __shfl_xor(hi, off));
     }
-    const float offv = (lo > 0.0) ? static_cast<float>(0.5 * (lo + hi)) : 0.f;
+    const float offv = (lo > 0.0 && hi <= 2.0 * lo) ? static_cast<float>(0.5 * (lo + hi)) : 0.f;
     double mx = 0.0;
     for (int i = threadIdx.x; i < nlon; i += 64) mx = fmax(mx, fabs(src[i] - static_cast<double>(offv)));
     for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off));

@@ -166,7 +166,9 @@ PY_MUTANTS = [
     ("oracle.quant", "tests.test_oracle_quant", "quant", "16-bit: the row's minimum as offset",
      [("mid = (0.5 * (lo + hi)).astype(np.float32).astype(np.float64)", "mid = lo")]),
     ("oracle.quant", "tests.test_oracle_quant", "quant", "16-bit: offsets also on rows holding a zero",
-     [("return np.where(lo > 0, mid, 0.0)", "return np.where(hi > 0, mid, 0.0)")]),
+     [("return np.where((lo > 0) & (hi <= 2.0 * lo), mid, 0.0)", "return np.where(hi > 0, mid, 0.0)")]),
+    ("oracle.quant", "tests.test_oracle_quant", "quant", "16-bit: offsets also on widely spread rows",
+     [("return np.where((lo > 0) & (hi <= 2.0 * lo), mid, 0.0)", "return np.where(lo > 0, mid, 0.0)")]),
     ("oracle.quant", "tests.test_oracle_quant", "quant", "16-bit: rounding truncates",
      [("out[nz] = np.rint(u[nz] / ulp) * ulp", "out[nz] = np.floor(u[nz] / ulp) * ulp")]),
     ("oracle.krylov", "tests.test_oracle_krylov", "krylov", "FGMRES: Givens rotation with the wrong sign",

@@ -56,8 +56,9 @@ def test_rounding_ties_go_to_even():
 
 @pytest.mark.parametrize("kind,rel", [("bf16", 2.0 ** -8), ("fp16", 2.0 ** -11)])
 def test_quantized_operator(kind, rel):
-    """Offsets: 0 on rows holding a zero coupling, else an FP32 value no farther than half the
-    row's spread (plus its own rounding) from every coupling of the row; scales are powers of
+    """Offsets: 0 on rows holding a zero coupling or spread over more than a factor 2, else an
+    FP32 value no farther than half the row's spread (plus its own rounding) from every
+    coupling of the row; scales are powers of
     two with the row's largest |a - offset| in (1/2, 1] after scaling; each coupling is within
     half a unit in the last place of its remainder a - offset (the unit roundoff 2^-8 for BF16
     and 2^-11 for FP16, relative; these magnitudes are far from underflow) plus the FP32
@@ -69,7 +70,8 @@ def test_quantized_operator(kind, rel):
     a = coef[:6]
     lo, hi = a.min(axis=3, keepdims=True), a.max(axis=3, keepdims=True)
     o = quant.offsets(coef)
-    assert np.all(o[lo == 0] == 0) and np.all(o[lo > 0] > 0)
+    narrow = (lo > 0) & (hi <= 2 * lo)
+    assert np.all(o[~narrow] == 0) and np.all(o[narrow] > 0)
     assert np.array_equal(o, o.astype(np.float32).astype(np.float64))
     assert np.all(np.abs(a - o) <= 0.5 * (hi - lo) + 2.0 ** -24 * o)
     s = quant.scales(coef)
@@ -82,12 +84,20 @@ def test_quantized_operator(kind, rel):
     assert np.array_equal(aq == 0, a == 0) and np.all(aq >= 0)
     assert np.array_equal(aq, aq.astype(np.float32).astype(np.float64))
     assert np.all(np.abs(aq - a) <= rel * np.abs(a - o) + 2.0 ** -24 * aq)
+    assert np.all(np.abs(aq - a) <= rel * a + 2.0 ** -24 * aq)      # never worse than the plain format
     # the offsets pay: on these operators the coupling error is far below the plain format's
     assert np.max(np.abs(aq - a) / np.where(a > 0, a, 1.0)) < 0.25 * rel
     # a zero among positive couplings: its row keeps offset 0, so the zero stays zero
     c2 = coef.copy()
     c2[0, 3, 5, 7] = 0.0
     assert quant.offsets(c2)[0, 3, 5, 0] == 0 and quant.quantized_coeffs(c2, kind)[0, 3, 5, 7] == 0
+    # a row spread over more than a factor 2 keeps offset 0: its smallest coupling keeps the
+    # format's relative precision
+    c3 = coef.copy()
+    c3[1, 4, 6, 9] *= 100.0
+    aq3 = quant.quantized_coeffs(c3, kind)[1, 4, 6]
+    assert quant.offsets(c3)[1, 4, 6, 0] == 0
+    assert np.all(np.abs(aq3 - c3[1, 4, 6]) <= rel * c3[1, 4, 6] + 2.0 ** -24 * aq3)
     m32 = quant.margin(coef).astype(np.float32).astype(np.float64)
     rows = cq[6] - aq.sum(axis=0)
     assert np.allclose(rows, m32, rtol=0, atol=1e-15 * np.abs(cq[6]).max())
