@@ -1198,8 +1198,8 @@ __global__ __launch_bounds__(kWG) void k_finalize(int stage, const double *__res
 #pragma unroll
     for (int c = 0; c < kPartialCols; ++c) a[c] = 0.0;
     // thread t adds rows t, t + kWG, t + 2 kWG, ... in that order; the rows are loaded eight
-    // at a time ahead of the additions (up to 32,768 rows: one load chain per row would leave
-    // the single workgroup waiting on memory latency)
+    // at a time ahead of the additions (tens of thousands of rows on large grids: one load chain
+    // per row would leave the single workgroup waiting on memory latency)
     constexpr int U = 8;
     int r = threadIdx.x;
     for (; r + (U - 1) * kWG < nrows; r += U * kWG) {
