@@ -4,6 +4,8 @@ device work."""
 import ctypes
 import os
 import re
+import shutil
+import subprocess
 
 import pytest
 
@@ -126,3 +128,29 @@ def test_binding_rejects_bad_training_sets():
         net.eval([ops[0], _fake_operator((8, 6, 4))], r, r, [0, 0, 1])
     with pytest.raises(ValueError, match="elements"):
         net.loss_grad(ops[0], torch.zeros(n + 1, dtype=torch.float32), torch.zeros(n, dtype=torch.float32))
+
+
+@pytest.mark.skipif(shutil.which("gcc") is None, reason="needs gcc")
+def test_header_compiles_as_c_and_every_entry_point_links(lib, tmp_path):
+    """A plain C99 caller: the header compiles warning-free under -pedantic, a program that takes
+    the address of every declared entry point links against libendgame.so, and it runs on the
+    host as far as an argument check (no device work)."""
+    import paper_1811_03852_amd as eg
+    names = _declared()
+    refs = ",\n".join(f"        (void (*)(void)){n}" for n in names)
+    prog = tmp_path / "caller.c"
+    prog.write_text('#include "endgame.h"\n#include <stdio.h>\nint main(void)\n{\n'
+                    f"    void (*fns[])(void) = {{\n{refs}\n    }};\n"
+                    "    int i, k = 0;\n"
+                    "    for (i = 0; i < (int)(sizeof fns / sizeof fns[0]); ++i) k += fns[i] != 0;\n"
+                    '    printf("%d\\n", k);\n'
+                    "    return eg_create_operator(0, 10, 10, 10, 0) == EG_EINVAL ? 0 : 1;\n}\n")
+    libdir = os.path.dirname(eg.LIB_PATH)
+    exe = tmp_path / "caller"
+    r = subprocess.run(["gcc", "-std=c99", "-Wall", "-Wextra", "-pedantic", "-Werror", "-I", os.path.dirname(HEADER),
+                        str(prog), "-L", libdir, "-lendgame", f"-Wl,-rpath,{libdir}", "-o", str(exe)],
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stderr
+    assert int(r.stdout.strip()) == len(names)
