@@ -1,7 +1,8 @@
 """Parity at the benchmark's full sizes, in the launch configuration bench.py times.
 
 2560x1920x70 (344M unknowns): SpMV and Thomas outputs on sampled rows and columns against the
-oracle computed one row / one column at a time; the line SOR on sampled columns against the
+oracle computed one row / one column at a time (the 16-bit products against the oracle's
+quantised operator, built for the sampled rows); the line SOR on sampled columns against the
 oracle on a window around each (and the network at 640x480x70 the same way); every solver
 mode's true residual recomputed
 by the oracle's full FP64 matrix-vector product on the host; the modes' solutions against each
@@ -11,6 +12,7 @@ import numpy as np
 import pytest
 
 import synth
+from oracle.quant import quantized_coeffs
 from tests.helpers import host
 
 pytestmark = pytest.mark.gpu
@@ -76,6 +78,38 @@ def test_spmv_sampled_rows(eg, oracle_mod, n1280):
         err = np.abs(y - ref32)
         print(f"SpMV prec {prec}: max |y - oracle| / scale = {np.max(err / scale):.2e}")
         assert np.all(err <= (rel + 32 * EPS32) * scale)
+
+
+def test_spmv_16bit_sampled_rows_match_quantized_operator(eg, oracle_mod, n1280):
+    """The BF16 and FP16 products on sampled rows against the oracle's quantised operator,
+    element by element.  The quantised couplings of a row depend only on its own latitude row
+    (offset and scale per direction, level and row) and its rebuilt diagonal only on its own
+    margin, so the oracle quantises just the sampled rows; they are written into the host copy
+    of the coefficients for the row-by-row product and put back afterwards."""
+    import torch
+    p, coef, _, op = n1280
+    rng = np.random.default_rng(33)
+    idx = _sample_points(p, rng, 2000)
+    rows = np.unique(idx // p.nlon)                  # k * nlat + j
+    kk, jj = rows // p.nlat, rows % p.nlat
+    saved = coef[:, kk, jj, :]                       # (7, rows, nlon), a copy
+    x32 = torch.from_numpy(rng.standard_normal(p.n)).cuda().float()
+    xh = x32.double().cpu().numpy()
+    for kind, prec in (("bf16", eg.PREC_BF16), ("fp16", eg.PREC_FP16)):
+        y = host(op.apply(x32, prec=prec)).astype(np.float64)[idx]
+        q = quantized_coeffs(saved[:, :, None, :], kind)[:, :, 0, :]
+        try:
+            coef[:, kk, jj, :] = q
+            ref = oracle_mod.apply_points(coef, xh, idx)
+            cq = coef[6].reshape(-1)[idx]
+        finally:
+            coef[:, kk, jj, :] = saved
+        # the quantised diagonal is its FP32 margin plus the couplings, so C |x_p| + sum a |x_d|
+        # <= 2 C max |x| bounds every term of the product
+        scale = 2.0 * cq * np.max(np.abs(xh))
+        err = np.abs(y - ref)
+        print(f"16-bit SpMV {kind}: {idx.size} rows, max |y - oracle| / scale = {np.max(err / scale):.2e}")
+        assert np.all(err <= 32 * EPS32 * scale)
 
 
 def test_thomas_sampled_columns(eg, oracle_mod, n1280):
