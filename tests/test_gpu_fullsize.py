@@ -464,7 +464,7 @@ def test_network_sampled_columns_640x480x70(eg, oracle_mod):
         den += float(np.sum(col ** 2))
     err = np.sqrt(num / den)
     print(f"network at 640x480x70, {len(samples)} sampled columns: delta rel L2 {err:.2e}")
-    assert err <= 2e-3
+    assert err <= 1e-3   # measured 2.05e-4
 
 
 def test_learned_preconditioner_640x480x70(eg, oracle_mod):
