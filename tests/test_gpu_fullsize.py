@@ -258,6 +258,33 @@ def test_all_modes_reach_1e8_true_residual(eg, oracle_mod, n1280):
         assert d <= 1e-6
 
 
+def test_paper_mp_mode_2560x1920x70(eg, oracle_mod, n1280):
+    """The paper's mixed-precision BiCGStab (FP64 solution, FP32 vectors and couplings, FP64
+    sums, restart every 150 iterations; Sec. 4) with the line SOR on the 344M-unknown grid, at
+    tol 1e-6 as in the benchmark's tolerance sweep: it converges (true residual by the oracle's
+    FP64 product on the host) in about the iterations of the 64-bit solve."""
+    import torch
+    p, coef, b, op = n1280
+    bd = torch.from_numpy(b).cuda()
+    nb = np.linalg.norm(b)
+    op.set_option("precond", 1)   # the MP mode restarts every 150 iterations by default
+    try:
+        res = {}
+        for name in ("FP64", "FP32_MP"):
+            x = torch.zeros(p.n, dtype=torch.float64, device="cuda")
+            print(f"[fullsize] solving {name} with the line SOR", flush=True)
+            info = op.solve(bd, x, 1e-6, 5000, getattr(eg, name))
+            rel = np.linalg.norm(b - oracle_mod.apply(coef, host(x))) / nb
+            print(f"{name} + line SOR: status {info.status}, {info.iterations} its, {info.seconds:.2f} s, "
+                  f"true R (oracle) {rel:.3e}, library {info.true_rel_residual:.3e}")
+            assert info.status == eg.CONVERGED and rel <= 1e-6 * (1 + 1e-6)
+            assert abs(rel - info.true_rel_residual) <= 1e-6 * rel
+            res[name] = info
+    finally:
+        op.set_option("precond", 0)
+    assert abs(res["FP32_MP"].iterations - res["FP64"].iterations) <= max(3, res["FP64"].iterations // 4)
+
+
 def _quick_net(eg):
     """A network trained in seconds on the FGMRES bases of 8 small operators of the recipe."""
     import torch
